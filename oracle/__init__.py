@@ -65,10 +65,11 @@ def _load():
         lib.or_set_sphere_reject.argtypes = [P, i32]
         lib.or_set_materials.argtypes = [P, P, i32]
         lib.or_trace.restype = i64
-        lib.or_trace.argtypes = [P, P, i64, i32, i32, P, P, P, P, P, P, P, P, P, P, P, i32]
+        lib.or_trace.argtypes = [P, P, i64, i32, i32, P, P, P, P, P, P, P, P, P, P, P, P, i32]
         lib.or_camera_rays.argtypes = [P, i32, i32, P, i64, P]
         lib.or_ao_uniforms.argtypes = [u64, u64, P, P]
         lib.or_ao_direction.argtypes = [P, ctypes.c_double, ctypes.c_double, P]
+        lib.or_ao_rays.argtypes = [P, P, i64, u64, i32, P, P, P]
         lib.or_render.restype = i64
         lib.or_render.argtypes = [P, P, P, i32, i32, i32, i32, u64, P, i64, i32, P, P, P]
         _lib = lib
@@ -134,10 +135,11 @@ class Scene:
 
     def trace(self, rays: np.ndarray, any_hit: bool = False, threads: int = 0) -> dict:
         """rays f32[N,8].  Returns dict of per-ray arrays (t, u, v, inst,
-        prim, hit, amb, beta, nties, ties[N,16,2], ties_tuv[N,16,3], tests)."""
+        prim, hit, amb, beta, delta, nties, ties[N,16,2], ties_tuv[N,16,3], tests);
+        beta / delta are the float32 error bands of the hit's barycentrics / t."""
         rays = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
         n = rays.shape[0]
-        out = dict(t=np.empty(n), u=np.empty(n), v=np.empty(n), beta=np.empty(n),
+        out = dict(t=np.empty(n), u=np.empty(n), v=np.empty(n), beta=np.empty(n), delta=np.empty(n),
                    inst=np.empty(n, np.uint32), prim=np.empty(n, np.uint32),
                    hit=np.empty(n, np.uint8), amb=np.empty(n, np.uint8),
                    nties=np.empty(n, np.int32), ties=np.zeros((n, MAX_TIES, 2), np.uint32),
@@ -145,11 +147,24 @@ class Scene:
         tests = self._lib.or_trace(self.h, _ptr(rays), n, 1 if any_hit else 0,
                                    threads or default_threads(),
                                    _ptr(out["t"]), _ptr(out["u"]), _ptr(out["v"]), _ptr(out["beta"]),
+                                   _ptr(out["delta"]),
                                    _ptr(out["inst"]), _ptr(out["prim"]), _ptr(out["hit"]),
                                    _ptr(out["amb"]), _ptr(out["nties"]), _ptr(out["ties"]),
                                    _ptr(out["ties_tuv"]), MAX_TIES)
         out["tests"] = int(tests)
         return out
+
+    def ao_rays(self, rays: np.ndarray, seed: int, threads: int = 0) -> dict:
+        """The 8 ambient-occlusion rays spawned at each input ray's closest hit:
+        rays [n,8,6] (origin, direction; undefined where hit == 0), hit, amb."""
+        rays = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
+        n = rays.shape[0]
+        out = np.zeros((n, 8, 6))
+        hit = np.empty(n, np.uint8)
+        amb = np.empty(n, np.uint8)
+        self._lib.or_ao_rays(self.h, _ptr(rays), n, seed, threads or default_threads(), _ptr(out),
+                             _ptr(hit), _ptr(amb))
+        return dict(rays=out, hit=hit, amb=amb)
 
     def render(self, pixels=None, threads: int = 0, width=None, height=None, max_depth=None,
                mode=None, seed=None) -> dict:

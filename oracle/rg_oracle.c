@@ -33,9 +33,10 @@
  *   beta_j  = (K*2^-24*R_j + sigma_obj(t_j)) * P_j * |d| / |S_j|   (barycentric)
  *   delta_j = (K*2^-24*R_j + sigma_obj(t_j)) * |n_j| / |S_j| + K*2^-24*|t_j|  (t units)
  * with R_j the largest distance from the origin point used by a float32
- * traversal (the ray moved to its entry into the instance's world box) to
- * the triangle's vertices, P_j its perimeter, n_j = e1 x e2, S_j = d.n_j,
- * all in object space, K = 16, and sigma_obj the propagated uncertainty of a
+ * traversal (the object-space ray moved to where it enters the mesh's box,
+ * not before tmin) to the triangle's vertices plus that point's own distance
+ * from the object-space origin, P_j the perimeter, n_j = e1 x e2, S_j = d.n_j,
+ * all in object space, K = 4, and sigma_obj the propagated uncertainty of a
  * secondary ray's origin and direction (zero for rays given as input).
  */
 #include <math.h>
@@ -44,7 +45,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define OR_K 16.0
+#define OR_K 4.0
 #define OR_EPS32 (1.0 / 16777216.0) /* 2^-24 */
 #define OR_MISS 0xFFFFFFFFu
 
@@ -52,6 +53,9 @@ typedef struct {
     double *tri;        /* [T][9]: a, e1 = b-a, e2 = c-a */
     int64_t n;
     const uint16_t *prim_mat; /* borrowed, may be NULL */
+    const uint32_t *idx;      /* borrowed vertex indices [T][3] */
+    int32_t *nbr;             /* [T][3] triangle across edge s (s=0: bc, 1: ca, 2: ab), -1 if none */
+    int8_t *nslot;            /* [T][3] that edge's slot in the neighbour */
     double lo[3], hi[3];      /* object-space box of the vertices */
     double sc[3], sr;         /* bounding sphere */
 } or_blas;
@@ -81,6 +85,8 @@ typedef struct {
     or_mat *mats;
     int32_t nm;
     int64_t tests; /* running count of ray-triangle tests (approximate under threads) */
+    int adj_built;
+    pthread_mutex_t adj_lock;
 } or_scene;
 
 /* ---------------------------------------------------------------- vectors */
@@ -156,6 +162,7 @@ or_scene *or_scene_new(int32_t n_blas, const int64_t *vert_off, const int64_t *t
         B->n = t1 - t0;
         B->tri = (double *)malloc(sizeof(double) * 9 * (size_t)(B->n > 0 ? B->n : 1));
         B->prim_mat = prim_mat ? prim_mat + t0 : NULL;
+        B->idx = idx + 3 * t0;
         for (int k = 0; k < 3; ++k) { B->lo[k] = INFINITY; B->hi[k] = -INFINITY; }
         for (int64_t v = 0; v < nv; ++v)
             for (int k = 0; k < 3; ++k) {
@@ -207,12 +214,76 @@ or_scene *or_scene_new(int32_t n_blas, const int64_t *vert_off, const int64_t *t
         }
     }
     s->sphere_reject = 0;
+    s->adj_built = 0;
+    pthread_mutex_init(&s->adj_lock, NULL);
     return s;
+}
+
+/* Edge adjacency of each mesh (by vertex index): an edge shared by exactly
+ * two triangles links them; boundary and non-manifold edges link nothing. */
+typedef struct {
+    uint64_t key;
+    uint32_t tri;
+    uint32_t slot;
+} or_edge;
+
+static int edge_cmp(const void *x, const void *y) {
+    const or_edge *a = (const or_edge *)x, *b = (const or_edge *)y;
+    if (a->key != b->key) return a->key < b->key ? -1 : 1;
+    if (a->tri != b->tri) return a->tri < b->tri ? -1 : 1;
+    return (int)a->slot - (int)b->slot;
+}
+
+static void build_adjacency(or_blas *B) {
+    int64_t m = 3 * B->n;
+    B->nbr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    B->nslot = (int8_t *)malloc((size_t)(m > 0 ? m : 1));
+    or_edge *e = (or_edge *)malloc(sizeof(or_edge) * (size_t)(m > 0 ? m : 1));
+    for (int64_t t = 0; t < B->n; ++t) {
+        const uint32_t *I = B->idx + 3 * t;
+        for (int sl = 0; sl < 3; ++sl) {
+            /* slot 0: edge (b,c); 1: (c,a); 2: (a,b) */
+            uint32_t p = I[(sl + 1) % 3], q = I[(sl + 2) % 3];
+            uint32_t lo = p < q ? p : q, hi = p < q ? q : p;
+            e[3 * t + sl].key = ((uint64_t)lo << 32) | hi;
+            e[3 * t + sl].tri = (uint32_t)t;
+            e[3 * t + sl].slot = (uint32_t)sl;
+            B->nbr[3 * t + sl] = -1;
+            B->nslot[3 * t + sl] = -1;
+        }
+    }
+    qsort(e, (size_t)m, sizeof(or_edge), edge_cmp);
+    for (int64_t i = 0; i < m;) {
+        int64_t j = i;
+        while (j < m && e[j].key == e[i].key) ++j;
+        if (j - i == 2 && e[i].tri != e[i + 1].tri) {
+            B->nbr[3 * (int64_t)e[i].tri + e[i].slot] = (int32_t)e[i + 1].tri;
+            B->nslot[3 * (int64_t)e[i].tri + e[i].slot] = (int8_t)e[i + 1].slot;
+            B->nbr[3 * (int64_t)e[i + 1].tri + e[i + 1].slot] = (int32_t)e[i].tri;
+            B->nslot[3 * (int64_t)e[i + 1].tri + e[i + 1].slot] = (int8_t)e[i].slot;
+        }
+        i = j;
+    }
+    free(e);
+}
+
+static void ensure_adjacency(or_scene *s) {
+    pthread_mutex_lock(&s->adj_lock);
+    if (!s->adj_built) {
+        for (int32_t b = 0; b < s->nb; ++b) build_adjacency(&s->blas[b]);
+        s->adj_built = 1;
+    }
+    pthread_mutex_unlock(&s->adj_lock);
 }
 
 void or_scene_free(or_scene *s) {
     if (!s) return;
-    for (int32_t b = 0; b < s->nb; ++b) free(s->blas[b].tri);
+    for (int32_t b = 0; b < s->nb; ++b) {
+        free(s->blas[b].tri);
+        free(s->blas[b].nbr);
+        free(s->blas[b].nslot);
+    }
+    pthread_mutex_destroy(&s->adj_lock);
     free(s->blas);
     free(s->inst);
     free(s->mats);
@@ -256,7 +327,8 @@ typedef struct {
     int nties;
     uint32_t tie_inst[OR_MAX_TIES], tie_prim[OR_MAX_TIES];
     double tie_t[OR_MAX_TIES], tie_u[OR_MAX_TIES], tie_v[OR_MAX_TIES];
-    double beta;   /* band of the reported hit */
+    double beta;   /* band of the reported hit (barycentric units) */
+    double delta;  /* float32 error band of the reported hit's t (t units) */
     double nobj[3]; /* object-space geometric normal of the hit triangle (e1 x e2) */
     int64_t tests;
 } or_result;
@@ -319,9 +391,128 @@ static int sphere_skip(const or_blas *B, const double o[3], const double d[3], d
     return 0;
 }
 
+static void tri_vertex(const double *T, int slot, double out[3]) {
+    for (int k = 0; k < 3; ++k) out[k] = T[k] + (slot == 1 ? T[3 + k] : (slot == 2 ? T[6 + k] : 0.0));
+}
+
+/* One triangle against one object-space ray, with its float32 error bands. */
+typedef struct {
+    double t, u, v, w, m, beta, delta, cosg;
+    int near; /* the ray passes within float32 error of the triangle's bounding sphere */
+} tri_eval_t;
+
+typedef struct {
+    const double *o, *d, *o0;  /* object-space ray and the float32 origin point */
+    double o0len, dl, dlen;    /* |o0|, |d| (object), |d| (world) */
+    double inv_fro;
+    const or_ray *R;
+} ray_frame;
+
+static int tri_eval(const double *T, const ray_frame *F, tri_eval_t *e) {
+    double det;
+    if (!mt64(T, F->o, F->d, &e->t, &e->u, &e->v, &det)) return 0;
+    e->w = 1.0 - e->u - e->v;
+    e->m = tri_min3(e->w, e->u, e->v);
+    double n[3], e3[3], va[3], vb[3], vc[3];
+    v_cross(n, T + 3, T + 6);
+    double Sabs = fabs(v_dot(F->d, n));
+    double nlen = v_len(n);
+    v_sub(va, T, F->o0);
+    for (int k = 0; k < 3; ++k) { vb[k] = va[k] + T[3 + k]; vc[k] = va[k] + T[6 + k]; }
+    double Rj = v_len(va);
+    if (v_len(vb) > Rj) Rj = v_len(vb);
+    if (v_len(vc) > Rj) Rj = v_len(vc);
+    Rj += F->o0len; /* float32 coordinates carry error relative to their magnitude */
+    v_sub(e3, T + 6, T + 3);
+    double P = v_len(T + 3) + v_len(T + 6) + v_len(e3);
+    /* where along the ray the triangle lies: its bounding sphere's closest
+     * approach (not the plane crossing, which runs off for grazing planes) */
+    double cen[3], rc = 0.0, oc[3], cr[3];
+    for (int k = 0; k < 3; ++k) cen[k] = T[k] + (T[3 + k] + T[6 + k]) / 3.0;
+    for (int q = 0; q < 3; ++q) {
+        double vq[3], dv[3];
+        tri_vertex(T, q, vq);
+        v_sub(dv, vq, cen);
+        double l = v_len(dv);
+        if (l > rc) rc = l;
+    }
+    v_sub(oc, cen, F->o);
+    v_cross(cr, oc, F->d);
+    double dist = v_len(cr) / F->dl;
+    double tc = v_dot(oc, F->d) / (F->dl * F->dl);
+    /* the drift of a secondary ray grows with t: take the plane crossing,
+     * clamped to the triangle's extent along the ray */
+    double ext = rc / F->dl;
+    double talong = fabs(fmin(fmax(e->t, tc - ext), tc + ext));
+    double sig = (F->R->sig_pos + F->R->sig_dir * talong * F->dlen) * F->inv_fro;
+    double pos_err = OR_K * OR_EPS32 * Rj + sig;
+    e->beta = pos_err * P * F->dl / Sabs;
+    e->delta = pos_err * nlen / Sabs + OR_K * OR_EPS32 * fabs(e->t);
+    e->cosg = Sabs / (nlen * F->dl);
+    /* A triangle the ray passes farther from than the position error can
+     * only be missed, however grazing (its bands grow as 1/cos). */
+    double reach = rc + 2.0 * pos_err;
+    double tr = reach / F->dl;
+    e->near = dist <= reach && tc >= F->R->tmin - tr && tc <= F->R->tmax + tr;
+    return 1;
+}
+
+/* A crossing of triangle j within the error band of exactly one of its edges
+ * (and robustly inside the other two) is covered when the edge is shared with
+ * one neighbour that lies on the other side of the edge as seen along the ray
+ * (not a silhouette) and is itself robustly inside its other two edges: a
+ * perturbed ray that leaves j enters the neighbour.  Returns the neighbour's
+ * index (its evaluation in *ek) or -1. */
+static int64_t covering(const or_blas *B, int64_t j, const tri_eval_t *ej, const ray_frame *F, tri_eval_t *ek) {
+    if (!B->nbr) return -1;
+    double c[3] = {ej->w, ej->u, ej->v};
+    int near = -1, cnt = 0;
+    for (int sl = 0; sl < 3; ++sl) {
+        if (fabs(c[sl]) <= ej->beta) { near = sl; ++cnt; }
+        else if (c[sl] < 0.0) return -1;
+    }
+    if (cnt != 1) return -1;
+    int64_t k = B->nbr[3 * j + near];
+    if (k < 0) return -1;
+    int sk = B->nslot[3 * j + near];
+    const double *Tj = B->tri + 9 * j, *Tk = B->tri + 9 * k;
+    if (!tri_eval(Tk, F, ek)) return -1;
+    double ck[3] = {ek->w, ek->u, ek->v};
+    for (int sl = 0; sl < 3; ++sl)
+        if (sl != sk && ck[sl] <= ek->beta) return -1;
+    double pp[3], qq[3], rj[3], rk[3], eq[3], ej3[3], ek3[3], cj[3], ckx[3];
+    tri_vertex(Tj, (near + 1) % 3, pp);
+    tri_vertex(Tj, (near + 2) % 3, qq);
+    tri_vertex(Tj, near, rj);
+    tri_vertex(Tk, sk, rk);
+    v_sub(eq, qq, pp);
+    v_sub(ej3, rj, pp);
+    v_sub(ek3, rk, pp);
+    v_cross(cj, eq, ej3);
+    v_cross(ckx, eq, ek3);
+    if (!(v_dot(cj, F->d) * v_dot(ckx, F->d) < 0.0)) return -1;
+    return k;
+}
+
+static void add_tie(or_result *res, uint32_t i, uint32_t j, const tri_eval_t *e) {
+    for (int q = 0; q < res->nties; ++q)
+        if (res->tie_inst[q] == i && res->tie_prim[q] == j) return;
+    if (res->nties >= OR_MAX_TIES) {
+        res->amb = 1; /* tie set overflow: membership cannot be checked */
+        return;
+    }
+    int q = res->nties++;
+    res->tie_inst[q] = i; res->tie_prim[q] = j;
+    res->tie_t[q] = e->t; res->tie_u[q] = e->u; res->tie_v[q] = e->v;
+}
+
 /* Per-ray evaluation.  any = 0: closest hit with ties and ambiguity;
- * any = 1: occlusion (hit = any genuine hit exists) with ambiguity. */
-static void or_trace_one(const or_scene *S, const or_ray *R, int any, or_result *res) {
+ * any = 1: occlusion (hit = some genuine hit exists) with ambiguity.
+ * cover = 1 lets a covered edge crossing (see covering()) count as
+ * unambiguous; any-hit always allows it, closest hit only where either of
+ * the two triangles is an acceptable answer (not when flat shading depends
+ * on which one is hit). */
+static void or_trace_one(const or_scene *S, const or_ray *R, int any, int cover, or_result *res) {
     memset(res, 0, sizeof(*res));
     res->t = INFINITY;
     res->inst = res->prim = OR_MISS;
@@ -360,64 +551,57 @@ static void or_trace_one(const or_scene *S, const or_ray *R, int any, or_result 
         xf_point(I->inv, R->o, o);
         xf_vec(I->inv, R->d, d);
         if (S->sphere_reject && sphere_skip(B, o, d, R->tmin, R->tmax)) continue;
-        /* origin a float32 traversal would use: moved to the world-box entry */
+        /* origin a float32 traversal would use: moved to where the ray enters
+         * the mesh's box (object space), never before tmin */
         double te0, te1, ts = R->tmin;
-        if (box_enter(I->wlo, I->whi, R->o, R->d, &te0, &te1) && te0 > ts) ts = te0;
+        if (box_enter(B->lo, B->hi, o, d, &te0, &te1) && te0 > ts) ts = te0;
+        if (ts > R->tmax) ts = R->tmax;
         double o0[3] = {o[0] + ts * d[0], o[1] + ts * d[1], o[2] + ts * d[2]};
-        double dl = v_len(d);
+        ray_frame F = {o, d, o0, v_len(o0), v_len(d), dlen, I->inv_fro, R};
         for (int64_t j = 0; j < B->n; ++j) {
-            double t, u, v, det;
+            tri_eval_t e, ek;
             ++tests;
-            const double *T = B->tri + 9 * j;
-            if (!mt64(T, o, d, &t, &u, &v, &det)) continue;
-            double w = 1.0 - u - v;
-            double m = tri_min3(w, u, v);
-            double n[3], e3[3];
-            v_cross(n, T + 3, T + 6);
-            double Sabs = fabs(v_dot(d, n));
-            double nlen = v_len(n);
-            /* vertex distances from o0 */
-            double va[3], vb[3], vc[3];
-            v_sub(va, T, o0);
-            for (int k = 0; k < 3; ++k) { vb[k] = va[k] + T[3 + k]; vc[k] = va[k] + T[6 + k]; }
-            double Rj = v_len(va);
-            if (v_len(vb) > Rj) Rj = v_len(vb);
-            if (v_len(vc) > Rj) Rj = v_len(vc);
-            v_sub(e3, T + 6, T + 3);
-            double P = v_len(T + 3) + v_len(T + 6) + v_len(e3);
-            double sig = (R->sig_pos + R->sig_dir * fabs(t) * dlen) * I->inv_fro;
-            double pos_err = OR_K * OR_EPS32 * Rj + sig;
-            double beta = pos_err * P * dl / Sabs;
-            double delta = pos_err * nlen / Sabs + OR_K * OR_EPS32 * fabs(t);
+            if (!tri_eval(B->tri + 9 * j, &F, &e)) continue;
+            if (!e.near) continue; /* robustly missed: no band can reach it */
+            double t = e.t, m = e.m, beta = e.beta, delta = e.delta;
             double tmax_band = fin_tmax ? fmax(1e-5 * R->tmax, delta) : 0.0;
             if (!any) {
                 int in_range = (t >= R->tmin - delta) && (t <= tlim * (1.0 + 1e-5) + delta);
-                if (in_range && fabs(m) <= beta) res->amb = 1;
+                if (in_range && fabs(m) <= beta) {
+                    int64_t k = cover ? covering(B, j, &e, &F, &ek) : -1;
+                    double ttol = res->hit ? fmax(1e-5 * res->t, fmin(e.delta, k >= 0 ? ek.delta : e.delta)) : 0.0;
+                    if (k >= 0 && res->hit && fabs(t - res->t) <= ttol && fabs(ek.t - res->t) <= ttol &&
+                        t >= R->tmin + delta && ek.t >= R->tmin + ek.delta &&
+                        (!fin_tmax || (t <= R->tmax - tmax_band && ek.t <= R->tmax - tmax_band))) {
+                        add_tie(res, (uint32_t)i, (uint32_t)j, &e);
+                        add_tie(res, (uint32_t)i, (uint32_t)k, &ek);
+                    } else {
+                        res->amb = 1;
+                    }
+                }
                 if (m >= -beta && fabs(t - R->tmin) <= delta && t <= tlim * (1.0 + 1e-5) + delta) res->amb = 1;
                 if (m >= -beta && fin_tmax && fabs(t - R->tmax) <= tmax_band &&
                     (!res->hit || t <= tlim * (1.0 + 1e-5) + delta))
                     res->amb = 1;
-                if (res->hit && m >= -beta && t >= R->tmin && t <= R->tmax &&
-                    fabs(t - res->t) <= 1e-6 * res->t) {
-                    if (res->nties < OR_MAX_TIES) {
-                        int q = res->nties++;
-                        res->tie_inst[q] = (uint32_t)i; res->tie_prim[q] = (uint32_t)j;
-                        res->tie_t[q] = t; res->tie_u[q] = u; res->tie_v[q] = v;
-                    } else {
-                        res->amb = 1; /* tie set overflow: cannot check membership */
-                    }
-                }
+                if (res->hit && m >= -beta && t >= R->tmin && t <= R->tmax && fabs(t - res->t) <= 1e-6 * res->t)
+                    add_tie(res, (uint32_t)i, (uint32_t)j, &e);
                 if (res->hit && (uint32_t)i == res->inst && (uint32_t)j == res->prim) {
                     res->beta = beta;
-                    double cosg = Sabs / (nlen * dl);
-                    if (cosg < 1e-3) res->amb = 1;
+                    res->delta = delta;
+                    if (e.cosg < 1e-3) res->amb = 1;
                     if (fin_tmax && fabs(res->t - R->tmax) <= tmax_band) res->amb = 1;
                 }
             } else {
-                if (m >= beta && t >= R->tmin + delta && (!fin_tmax || t <= R->tmax - tmax_band))
-                    robust_hit = 1;
+                int robust_t = t >= R->tmin + delta && (!fin_tmax || t <= R->tmax - tmax_band);
+                if (m >= beta && robust_t) robust_hit = 1;
                 int in_range = (t >= R->tmin - delta) && (!fin_tmax || t <= R->tmax + tmax_band);
-                if (in_range && fabs(m) <= beta) near_band = 1;
+                if (in_range && fabs(m) <= beta) {
+                    int64_t k = covering(B, j, &e, &F, &ek);
+                    int robust_k = k >= 0 && ek.t >= R->tmin + ek.delta &&
+                                   (!fin_tmax || ek.t <= R->tmax - fmax(1e-5 * R->tmax, ek.delta));
+                    if (k >= 0 && robust_t && robust_k) robust_hit = 1;
+                    else near_band = 1;
+                }
                 if (m >= -beta && fabs(t - R->tmin) <= delta) near_band = 1;
                 if (m >= -beta && fin_tmax && fabs(t - R->tmax) <= tmax_band) near_band = 1;
             }
@@ -463,7 +647,7 @@ typedef struct {
     const or_scene *S;
     const float *rays;
     int any;
-    double *t, *u, *v, *beta;
+    double *t, *u, *v, *beta, *delta;
     uint32_t *inst, *prim;
     uint8_t *hit, *amb;
     int32_t *nties;
@@ -481,8 +665,8 @@ static void trace_task(void *vctx, int64_t r) {
     R.tmin = q[6]; R.tmax = q[7];
     R.sig_pos = R.sig_dir = 0.0;
     or_result res;
-    or_trace_one(c->S, &R, c->any, &res);
-    c->t[r] = res.t; c->u[r] = res.u; c->v[r] = res.v; c->beta[r] = res.beta;
+    or_trace_one(c->S, &R, c->any, 1, &res);
+    c->t[r] = res.t; c->u[r] = res.u; c->v[r] = res.v; c->beta[r] = res.beta; c->delta[r] = res.delta;
     c->inst[r] = res.inst; c->prim[r] = res.prim;
     c->hit[r] = (uint8_t)res.hit; c->amb[r] = (uint8_t)res.amb;
     int nt = res.nties < c->max_ties ? res.nties : c->max_ties;
@@ -501,10 +685,11 @@ static void trace_task(void *vctx, int64_t r) {
 /* rays: f32[N][8] = ox oy oz dx dy dz tmin tmax.  Returns the number of
  * ray-triangle tests performed. */
 int64_t or_trace(or_scene *S, const float *rays, int64_t n, int32_t any, int32_t nthreads,
-                 double *t, double *u, double *v, double *beta, uint32_t *inst, uint32_t *prim,
-                 uint8_t *hit, uint8_t *amb, int32_t *nties, uint32_t *ties, double *ties_tuv,
-                 int32_t max_ties) {
-    trace_ctx c = {S, rays, any, t, u, v, beta, inst, prim, hit, amb, nties, ties, ties_tuv,
+                 double *t, double *u, double *v, double *beta, double *delta, uint32_t *inst,
+                 uint32_t *prim, uint8_t *hit, uint8_t *amb, int32_t *nties, uint32_t *ties,
+                 double *ties_tuv, int32_t max_ties) {
+    ensure_adjacency(S);
+    trace_ctx c = {S, rays, any, t, u, v, beta, delta, inst, prim, hit, amb, nties, ties, ties_tuv,
                    max_ties, 0};
     pool_run(trace_task, &c, n, nthreads);
     S->tests += c.tests;
@@ -641,7 +826,7 @@ static void radiance(render_ctx *C, const or_ray *R, int k, double out[3], int *
                      int64_t *tests) {
     const or_scene *S = C->S;
     or_result h;
-    or_trace_one(S, R, 0, &h);
+    or_trace_one(S, R, 0, 0, &h);
     ++*nrays;
     *tests += h.tests;
     if (h.amb) *amb = 1;
@@ -671,7 +856,7 @@ static void radiance(render_ctx *C, const or_ray *R, int k, double out[3], int *
             sr.tmax = 1.0 - 1e-4;
             child_sigma(R, &h, &g, 1.0, 1.0, &sr);
             or_result sh;
-            or_trace_one(S, &sr, 1, &sh);
+            or_trace_one(S, &sr, 1, 1, &sh);
             ++*nrays;
             *tests += sh.tests;
             if (sh.amb) *amb = 1;
@@ -733,7 +918,7 @@ static void ao_pixel(render_ctx *C, const or_ray *R, int64_t pixel, double out[3
                      int64_t *nrays, int64_t *tests) {
     const or_scene *S = C->S;
     or_result h;
-    or_trace_one(S, R, 0, &h);
+    or_trace_one(S, R, 0, 0, &h);
     ++*nrays;
     *tests += h.tests;
     if (h.amb) *amb = 1;
@@ -756,7 +941,7 @@ static void ao_pixel(render_ctx *C, const or_ray *R, int64_t pixel, double out[3
         child_sigma(R, &h, &g, 0.0, 1.0, &ar);
         ar.sig_dir += 8.0 * OR_K * OR_EPS32; /* float32 sin/cos/sqrt of the sample */
         or_result sh;
-        or_trace_one(S, &ar, 1, &sh);
+        or_trace_one(S, &ar, 1, 1, &sh);
         ++*nrays;
         *tests += sh.tests;
         if (sh.amb) *amb = 1;
@@ -793,8 +978,51 @@ static void render_task(void *vctx, int64_t i) {
 int64_t or_render(or_scene *S, const float *cam, const float *light, int32_t W, int32_t H,
                   int32_t max_depth, int32_t mode, uint64_t seed, const int64_t *pixels, int64_t n,
                   int32_t nthreads, double *rgb, uint8_t *amb, int64_t *nrays) {
+    ensure_adjacency(S);
     render_ctx C = {S, cam, light, W, H, max_depth, mode, seed, pixels, rgb, amb, nrays, 0};
     pool_run(render_task, &C, n, nthreads);
     S->tests += C.tests;
     return C.tests;
+}
+
+/* Ambient-occlusion rays of input rays: for each ray with a closest hit, the
+ * 8 rays (origin, direction) the incoherent workload spawns there; out is
+ * [n][8][6] (undefined for misses), hit/amb per input ray. */
+typedef struct {
+    const or_scene *S;
+    const float *rays;
+    uint64_t seed;
+    double *out;
+    uint8_t *hit, *amb;
+} aorays_ctx;
+
+static void aorays_task(void *vctx, int64_t r) {
+    aorays_ctx *c = (aorays_ctx *)vctx;
+    const float *q = c->rays + 8 * r;
+    or_ray R;
+    for (int k = 0; k < 3; ++k) { R.o[k] = q[k]; R.d[k] = q[3 + k]; }
+    R.tmin = q[6]; R.tmax = q[7];
+    R.sig_pos = R.sig_dir = 0.0;
+    or_result h;
+    or_trace_one(c->S, &R, 0, 0, &h);
+    c->hit[r] = (uint8_t)h.hit;
+    c->amb[r] = (uint8_t)h.amb;
+    if (!h.hit) return;
+    hit_geom g;
+    hit_geometry(c->S, &R, &h, &g);
+    double eps = offset_eps(g.p);
+    for (int k = 0; k < 8; ++k) {
+        double u1, u2, dir[3];
+        or_ao_uniforms(c->seed, (uint64_t)r * 8ull + (uint64_t)k, &u1, &u2);
+        ao_direction(g.nf, u1, u2, dir);
+        double *o = c->out + ((size_t)r * 8 + k) * 6;
+        for (int m = 0; m < 3; ++m) { o[m] = g.p[m] + eps * g.nf[m]; o[3 + m] = dir[m]; }
+    }
+}
+
+void or_ao_rays(or_scene *S, const float *rays, int64_t n, uint64_t seed, int32_t nthreads, double *out,
+                uint8_t *hit, uint8_t *amb) {
+    ensure_adjacency(S);
+    aorays_ctx c = {S, rays, seed, out, hit, amb};
+    pool_run(aorays_task, &c, n, nthreads);
 }

@@ -189,7 +189,7 @@ def test_small_config_frame_properties():
     b = orc.render(threads=3)
     assert np.array_equal(a["rgb"], b["rgb"]) and np.array_equal(a["amb"], b["amb"])
     assert np.isfinite(a["rgb"]).all() and (a["rgb"] >= 0).all()
-    assert a["amb"].mean() < 0.02
+    assert a["amb"].mean() < 0.005
     assert a["nrays"].min() >= 1 and a["nrays"].max() <= 4
 
 
