@@ -1,0 +1,269 @@
+/*
+ * rg.h -- C ABI of the MI355X ray-tracing library (librg.so).
+ *
+ * The paper describes ray tracing on RTX as two steps (section 1): first a
+ * two-layered structure is built from the vertex data of the scene's models
+ * and their transformation matrices; then a dispatch runs a ray-generation
+ * shader, and for each ray a closest-hit, any-hit or miss shader runs, which
+ * may spawn further rays up to a recursion limit (footnote), each ray carrying
+ * a small payload.  Section 2.1 adds multiple objects, reflection, refraction
+ * and shadow casting.  This header turns those steps into calls:
+ *
+ *   bottom level from vertex data            rg_build_blas   (+ rg_blas_sizes)
+ *   top level from instances and matrices    rg_build_tlas   (+ rg_tlas_sizes)
+ *   ray generation                           rg_camera_rays, rg_ao_rays
+ *   closest hit / miss per ray               rg_trace_closest
+ *   any hit per ray                          rg_trace_any
+ *   dispatch with capped recursion/payload   rg_render       (+ rg_render_sizes)
+ *
+ * Conventions (all entry points):
+ *   - Pointers are DEVICE pointers unless the comment says "host".
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it; calls documented as "synchronous" also wait for
+ *     it before returning.
+ *   - The library never allocates device memory: the caller allocates every
+ *     buffer, sized with the *_sizes calls.  Buffers must be 256-byte aligned
+ *     (any torch CUDA tensor's storage is).
+ *   - Return value: RG_OK or a negative rg_status.  Argument validation is
+ *     done on the host before anything is enqueued; a failed validation
+ *     enqueues nothing.  Device faults surface at the caller's next sync.
+ *   - Nothing throws across the ABI.  The library is thread-safe for calls on
+ *     different buffers; concurrent calls that share a scratch buffer race.
+ *
+ * Ray semantics: a ray is o + t d with t in the closed interval [tmin, tmax];
+ * t is measured in units of |d| (directions need not be unit length).
+ * Triangles are two-sided, their edges and vertices count as inside, and a
+ * ray parallel to a triangle's plane misses it.  Closest hit returns the least
+ * t; exact ties go to the lowest (instance, primitive).  Barycentrics follow
+ * p = (1-u-v) v0 + u v1 + v v2.  A miss is reported as t = +inf and
+ * inst = prim = RG_MISS.
+ */
+#ifndef RG_H
+#define RG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rg_status;
+#define RG_OK 0
+#define RG_ERR_INVALID_ARG (-1)   /* bad pointer, size, value or option */
+#define RG_ERR_OUT_OF_MEMORY (-2) /* a caller buffer is smaller than *_sizes reported */
+#define RG_ERR_HIP (-3)           /* a HIP runtime call or kernel launch failed */
+#define RG_ERR_UNSUPPORTED (-4)   /* valid request outside what this build handles */
+#define RG_ERR_UNIMPLEMENTED (-5)
+
+#define RG_MISS 0xFFFFFFFFu
+#define RG_PER_PRIM 0xFFFFFFFFu   /* instance material: use the mesh's per-primitive ids */
+#define RG_MAX_DEPTH 8
+
+/* Hierarchy options.  width = children per node (2, 4 or 8); leaf_max =
+ * most triangles per leaf (1..8).  NULL means {4, 4}. */
+typedef struct {
+    int32_t width;
+    int32_t leaf_max;
+} rg_build_opts;
+
+typedef struct {
+    uint64_t bytes;         /* size of the output buffer */
+    uint64_t scratch_bytes; /* size of the scratch buffer */
+} rg_sizes;
+
+/* Bottom-level structure: a POD descriptor of the caller's output buffer.
+ * Layout of `buf` (all offsets in bytes from buf):
+ *   0:         header of four uint64 device addresses: nodes, tris, mats,
+ *              slots (the arrays below).
+ *   nodes_off: n_nodes nodes of 32*width bytes (width 4: 128 B):
+ *              float lo_x[w], lo_y[w], lo_z[w], hi_x[w], hi_y[w], hi_z[w];
+ *              uint32 child[w]; padding to 32*width bytes.
+ *              child = RG_MISS: empty slot (its box is lo=+inf, hi=-inf);
+ *              bit 31 clear: index of an inner node; bit 31 set: a leaf of
+ *              bits 28..30 + 1 primitives starting at bits 0..27.
+ *              Node 0 is the root.
+ *   tris_off:  n_tris triangles in leaf order, 40 B each:
+ *              float v0[3], v1[3], v2[3]; uint32 prim (index in the input).
+ *   mats_off:  uint16 material per triangle in leaf order (0 if none given).
+ *   slots_off: uint32 per input triangle: its position in leaf order.
+ * The build reads the vertex and index arrays only during the call; the
+ * descriptor refers to `buf`, which must outlive every top level using it. */
+typedef struct {
+    void *buf;
+    uint64_t nodes_off, tris_off, mats_off, slots_off;
+    int64_t n_tris, n_nodes;
+    int32_t width, leaf_max, depth, has_mats;
+    float lo[3], hi[3]; /* root box (object space) */
+} rg_blas;
+
+/* Top-level structure.  Layout of `buf`:
+ *   nodes_off: nodes as above; leaves hold one instance each.
+ *   inst_off:  n_inst 80-byte records in leaf order:
+ *              float inv[9] (world->object linear part, row-major),
+ *              float p[3] (object->world translation),
+ *              uint64 blas_nodes, blas_tris, blas_header (device addresses),
+ *              uint32 material (RG_PER_PRIM = per primitive), uint32 inst
+ *              (index in the input).
+ *   rec_off:   uint32 per input instance: its record's position.
+ * It refers to the bottom levels' buffers, which must outlive it. */
+typedef struct {
+    void *buf;
+    uint64_t nodes_off, inst_off, rec_off;
+    int64_t n_inst, n_nodes;
+    int32_t width, depth, max_blas_depth, reserved;
+    float lo[3], hi[3]; /* world box */
+} rg_tlas;
+
+/* Rays in structure-of-arrays form, n entries each (device). */
+typedef struct {
+    const float *ox, *oy, *oz, *dx, *dy, *dz, *tmin, *tmax;
+} rg_rays;
+
+/* Hit records in structure-of-arrays form (device).  Any pointer may be
+ * NULL to skip that field.  Miss: t = +inf, inst = prim = RG_MISS, u = v = 0. */
+typedef struct {
+    float *t;
+    uint32_t *inst, *prim;
+    float *u, *v;
+} rg_hits;
+
+typedef struct {
+    int32_t type; /* 0 diffuse, 1 mirror, 2 glass */
+    float rgb[3]; /* diffuse albedo or mirror reflectance; unused by glass */
+    float ior;    /* glass index of refraction */
+} rg_material;
+
+typedef struct {
+    float eye[3], target[3], up[3], vfov_deg; /* vertical field of view */
+} rg_camera;
+
+typedef struct {
+    float pos[3], intensity[3], ambient;
+} rg_light;
+
+typedef struct {
+    uint64_t rays_traced;  /* closest-hit rays of all depths */
+    uint64_t shadow_rays;  /* any-hit rays (shadow or occlusion) */
+    float ms_total;        /* GPU time of the whole call */
+} rg_render_stats;
+
+/* ---------------------------------------------------------------- errors */
+const char *rg_status_string(rg_status s);
+/* The last HIP failure of the calling thread as "file:line: hipErrorName"
+ * (empty if none).  The pointer stays valid until the thread's next call. */
+const char *rg_last_error(void);
+
+/* ------------------------------------------------------- bottom level */
+/* Sizes for a bottom level of n_tris triangles (host call, no GPU work).
+ * Errors: RG_ERR_INVALID_ARG for n_tris < 1 or > 2^28, bad opts, NULL out. */
+rg_status rg_blas_sizes(int64_t n_tris, const rg_build_opts *opts, rg_sizes *out /*host*/);
+
+/* Builds a linear BVH (Morton codes of triangle-box centres, LSD radix sort
+ * with LDS ranking, Karras's radix-tree hierarchy, bottom-up box refit) and
+ * collapses it into `width`-wide nodes with leaves of at most leaf_max
+ * triangles; writes nodes, triangles in leaf order and per-triangle
+ * materials into out_buf.  verts: float[n_verts][3]; idx: uint32[n_tris][3];
+ * prim_material: uint16[n_tris] or NULL.  Synchronous (waits for `stream`).
+ * Errors: RG_ERR_INVALID_ARG for NULL pointers, sizes out of range, an index
+ * >= n_verts or a non-finite vertex (checked on the device, reported after the
+ * sync); RG_ERR_OUT_OF_MEMORY if out_bytes / scratch_bytes are too small. */
+rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx, int64_t n_tris,
+                        const uint16_t *prim_material, const rg_build_opts *opts,
+                        void *out_buf, uint64_t out_bytes, void *scratch, uint64_t scratch_bytes,
+                        void *stream, rg_blas *out /*host*/);
+
+/* --------------------------------------------------------- top level */
+rg_status rg_tlas_sizes(int64_t n_inst, const rg_build_opts *opts, rg_sizes *out /*host*/);
+
+/* Builds the top level over n_inst instances.  blas: host array of n_blas
+ * descriptors (all of the same width as opts); xform: host float[n_inst][3][4]
+ * object->world; blas_id, inst_material: host uint32[n_inst].  Instance boxes
+ * are the 8 transformed corners of the bottom level's root box, computed in
+ * double and rounded outward to float; the world->object inverse is computed
+ * in double and stored as float.  Synchronous.
+ * Errors: RG_ERR_INVALID_ARG for NULL pointers, blas_id out of range, a
+ * non-finite or singular matrix, mixed widths. */
+rg_status rg_build_tlas(const rg_blas *blas, int32_t n_blas, const float *xform,
+                        const uint32_t *blas_id, const uint32_t *inst_material, int64_t n_inst,
+                        const rg_build_opts *opts, void *out_buf, uint64_t out_bytes,
+                        void *scratch, uint64_t scratch_bytes, void *stream, rg_tlas *out /*host*/);
+
+/* ---------------------------------------------------------- tracing */
+/* Closest hit for n rays.  Asynchronous.
+ * Errors: RG_ERR_INVALID_ARG for NULL tlas/ray pointers or n < 0 (n == 0 is
+ * a no-op); RG_ERR_UNSUPPORTED if the hierarchy is deeper than the traversal
+ * stack holds (never for the configurations built here). */
+rg_status rg_trace_closest(const rg_tlas *tlas, rg_rays rays, int64_t n, rg_hits out, void *stream);
+
+/* Any hit: occluded[i] = 1 if some triangle is hit in [tmin, tmax], else 0.
+ * `found` (nullable) receives one such hit (not necessarily the closest).
+ * Asynchronous.  Errors as rg_trace_closest. */
+rg_status rg_trace_any(const rg_tlas *tlas, rg_rays rays, int64_t n, uint8_t *occluded,
+                       const rg_hits *found /*host struct, nullable*/, void *stream);
+
+/* Visit counts per ray of the same traversal (closest if any_hit == 0):
+ * counts uint32[n][3] = inner nodes, triangles, instances visited.  Used to
+ * compute the bytes a traversal must move.  Asynchronous. */
+rg_status rg_trace_counts(const rg_tlas *tlas, rg_rays rays, int64_t n, int32_t any_hit,
+                          uint32_t *counts, void *stream);
+
+/* ---------------------------------------------------- ray generation */
+/* Pinhole camera rays, one per pixel centre, y = 0 the top row, vertical
+ * field of view: f = normalize(target-eye), r = normalize(f x up), u = r x f,
+ * d = normalize(f + sx r + sy u), tmin = 0, tmax = +inf.  Ray i is pixel i
+ * (row-major).  `rays` points to 8 float arrays of width*height entries.
+ * Asynchronous. */
+rg_status rg_camera_rays(const rg_camera *cam /*host*/, int32_t width, int32_t height,
+                         float *const rays[8], void *stream);
+
+/* Ambient-occlusion rays: for each input ray i (n of them) whose hit is not a
+ * miss, 8 cosine-weighted directions around the faced normal (Malley's
+ * method in the Duff et al. 2017 basis), uniforms from SplitMix64 keyed by
+ * (seed, i*8+k), origin offset 1e-4*max(1,|p|inf) along the faced normal,
+ * tmin 0, tmax `ao_tmax`.  Output is compacted in input order: out_rays
+ * (8 float arrays of capacity 8n), out_src uint32[8n] = (i*8 + k), and the
+ * count in *out_count (device uint32).  Asynchronous. */
+rg_status rg_ao_rays(const rg_tlas *tlas, rg_rays rays, int64_t n, const uint32_t *hit_inst,
+                     const uint32_t *hit_prim, const float *hit_t, uint64_t seed, float ao_tmax,
+                     float *const out_rays[8], uint32_t *out_src, uint32_t *out_count,
+                     void *scratch, uint64_t scratch_bytes, void *stream);
+rg_status rg_ao_rays_scratch(int64_t n, uint64_t *scratch_bytes /*host*/);
+
+/* ------------------------------------------------------------ render */
+/* Scratch bytes for rg_render at this size (host call). */
+rg_status rg_render_sizes(int32_t width, int32_t height, int32_t max_depth, int32_t mode,
+                          uint64_t *scratch_bytes /*host*/);
+
+/* Renders one frame: camera rays, then for depth 0..max_depth a closest-hit
+ * pass, shading (sky on a miss; ambient term, a shadow ray towards the point
+ * light for diffuse hits; a mirror child; reflection and refraction children
+ * for glass with Schlick's Fresnel term, both spawned, none past max_depth),
+ * an any-hit pass for the shadow rays and the direct term for unoccluded
+ * ones.  mode 1 renders ambient occlusion instead (8 rays per primary hit,
+ * tmax 5, pixel = 1 - occluded/8).  Contributions are summed per pixel in
+ * 64-bit fixed point (scale 2^32), so the image does not depend on execution
+ * order.  image: float[height][width][3], linear.  Asynchronous unless
+ * `stats` is non-NULL (then it waits to fill it).
+ * Errors: RG_ERR_INVALID_ARG (NULL pointers, sizes, max_depth > RG_MAX_DEPTH,
+ * a material index out of range is not checked on the device: ids >= n_mats
+ * are clamped), RG_ERR_OUT_OF_MEMORY (scratch too small). */
+rg_status rg_render(const rg_tlas *tlas, const rg_material *mats /*host*/, int32_t n_mats,
+                    const rg_camera *cam /*host*/, const rg_light *light /*host*/, int32_t width,
+                    int32_t height, int32_t max_depth, int32_t mode, uint64_t seed, float *image,
+                    void *scratch, uint64_t scratch_bytes, void *stream,
+                    rg_render_stats *stats /*host, nullable*/);
+
+/* ------------------------------------------------ build verification */
+/* Runs the first build stages of rg_build_blas and copies their results out
+ * for verification: keys uint64[n] and ids uint32[n] after the sort,
+ * left/right int32[n-1] of the radix tree (>= 0 inner node, < 0 leaf -(i+1)),
+ * boxes float[2n-1][6] (inner nodes 0..n-2, then leaves in sorted order).
+ * scratch as for rg_build_blas.  Synchronous. */
+rg_status rg_lbvh_stages(const float *verts, int64_t n_verts, const uint32_t *idx, int64_t n_tris,
+                         uint64_t *keys, uint32_t *ids, int32_t *left, int32_t *right, float *boxes,
+                         void *scratch, uint64_t scratch_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RG_H */

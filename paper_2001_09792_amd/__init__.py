@@ -1,0 +1,420 @@
+"""Python binding of librg.so (include/rg.h): argument marshalling only.
+
+Every step of the ray-tracing path runs in the HIP kernels of librg.so;
+this module only turns torch CUDA tensors into device pointers, owns the
+caller-allocated buffers that the C ABI asks for, and maps status codes to
+exceptions.  Importing it loads the library and fails loudly if it has not
+been built (`python -m paper_2001_09792_amd._build`).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+# torch first: it ships its own HIP runtime (soname libamdhip64.so.7); loading
+# torch before librg.so makes the dynamic loader bind librg.so to that same
+# runtime instead of a second copy from /opt/rocm, which would not see the
+# device torch has opened.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librg.so")
+
+RG_OK = 0
+MISS = 0xFFFFFFFF
+PER_PRIM = 0xFFFFFFFF
+MAX_DEPTH = 8
+
+c_f = ctypes.c_float
+c_i32 = ctypes.c_int32
+c_i64 = ctypes.c_int64
+c_u64 = ctypes.c_uint64
+c_p = ctypes.c_void_p
+
+
+class BuildOpts(ctypes.Structure):
+    _fields_ = [("width", c_i32), ("leaf_max", c_i32)]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [("bytes", c_u64), ("scratch_bytes", c_u64)]
+
+
+class BlasDesc(ctypes.Structure):
+    _fields_ = [("buf", c_p), ("nodes_off", c_u64), ("tris_off", c_u64), ("mats_off", c_u64),
+                ("slots_off", c_u64), ("n_tris", c_i64), ("n_nodes", c_i64), ("width", c_i32),
+                ("leaf_max", c_i32), ("depth", c_i32), ("has_mats", c_i32), ("lo", c_f * 3),
+                ("hi", c_f * 3)]
+
+
+class TlasDesc(ctypes.Structure):
+    _fields_ = [("buf", c_p), ("nodes_off", c_u64), ("inst_off", c_u64), ("rec_off", c_u64),
+                ("n_inst", c_i64), ("n_nodes", c_i64), ("width", c_i32), ("depth", c_i32),
+                ("max_blas_depth", c_i32), ("reserved", c_i32), ("lo", c_f * 3), ("hi", c_f * 3)]
+
+
+class Rays(ctypes.Structure):
+    _fields_ = [(k, c_p) for k in ("ox", "oy", "oz", "dx", "dy", "dz", "tmin", "tmax")]
+
+
+class Hits(ctypes.Structure):
+    _fields_ = [("t", c_p), ("inst", c_p), ("prim", c_p), ("u", c_p), ("v", c_p)]
+
+
+class Material(ctypes.Structure):
+    _fields_ = [("type", c_i32), ("rgb", c_f * 3), ("ior", c_f)]
+
+
+class CameraDesc(ctypes.Structure):
+    _fields_ = [("eye", c_f * 3), ("target", c_f * 3), ("up", c_f * 3), ("vfov_deg", c_f)]
+
+
+class LightDesc(ctypes.Structure):
+    _fields_ = [("pos", c_f * 3), ("intensity", c_f * 3), ("ambient", c_f)]
+
+
+class RenderStats(ctypes.Structure):
+    _fields_ = [("rays_traced", c_u64), ("shadow_rays", c_u64), ("ms_total", c_f)]
+
+
+# name -> (restype, argtypes); every function of include/rg.h
+SIGNATURES = {
+    "rg_status_string": (ctypes.c_char_p, [c_i32]),
+    "rg_last_error": (ctypes.c_char_p, []),
+    "rg_blas_sizes": (c_i32, [c_i64, c_p, c_p]),
+    "rg_build_blas": (c_i32, [c_p, c_i64, c_p, c_i64, c_p, c_p, c_p, c_u64, c_p, c_u64, c_p, c_p]),
+    "rg_tlas_sizes": (c_i32, [c_i64, c_p, c_p]),
+    "rg_build_tlas": (c_i32, [c_p, c_i32, c_p, c_p, c_p, c_i64, c_p, c_p, c_u64, c_p, c_u64, c_p, c_p]),
+    "rg_trace_closest": (c_i32, [c_p, Rays, c_i64, Hits, c_p]),
+    "rg_trace_any": (c_i32, [c_p, Rays, c_i64, c_p, c_p, c_p]),
+    "rg_trace_counts": (c_i32, [c_p, Rays, c_i64, c_i32, c_p, c_p]),
+    "rg_camera_rays": (c_i32, [c_p, c_i32, c_i32, c_p, c_p]),
+    "rg_ao_rays": (c_i32, [c_p, Rays, c_i64, c_p, c_p, c_p, c_u64, c_f, c_p, c_p, c_p, c_p, c_u64, c_p]),
+    "rg_ao_rays_scratch": (c_i32, [c_i64, c_p]),
+    "rg_render_sizes": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_p]),
+    "rg_render": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_u64, c_p, c_p, c_u64,
+                          c_p, c_p]),
+    "rg_lbvh_stages": (c_i32, [c_p, c_i64, c_p, c_i64, c_p, c_p, c_p, c_p, c_p, c_p, c_u64, c_p]),
+}
+
+
+class RgError(RuntimeError):
+    def __init__(self, fn: str, status: int, text: str):
+        super().__init__(f"{fn} failed: {text} ({status})")
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2001_09792_amd._build` "
+                          "(there is no fallback implementation)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = load_library()
+
+
+def _check(fn: str, status: int):
+    if status != RG_OK:
+        text = _lib.rg_status_string(status).decode()
+        if status == -3:
+            text += " at " + _lib.rg_last_error().decode()
+        raise RgError(fn, status, text)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _bytes(n: int, device):
+    torch = _torch()
+    return torch.empty(max(int(n), 256), dtype=torch.uint8, device=device)
+
+
+def _opts(width: int, leaf_max: int) -> BuildOpts:
+    return BuildOpts(width, leaf_max)
+
+
+# -------------------------------------------------------------- bottom level
+class Blas:
+    """A bottom-level structure: the caller-owned buffer and its descriptor."""
+
+    def __init__(self, buf, desc: BlasDesc):
+        self.buf = buf
+        self.desc = desc
+
+    @property
+    def n_tris(self) -> int:
+        return int(self.desc.n_tris)
+
+    @property
+    def depth(self) -> int:
+        return int(self.desc.depth)
+
+
+def blas_sizes(n_tris: int, width: int = 4, leaf_max: int = 4):
+    s = Sizes()
+    o = _opts(width, leaf_max)
+    _check("rg_blas_sizes", _lib.rg_blas_sizes(n_tris, ctypes.byref(o), ctypes.byref(s)))
+    return int(s.bytes), int(s.scratch_bytes)
+
+
+def build_blas(verts, idx, prim_mat=None, width: int = 4, leaf_max: int = 4, scratch=None,
+               stream=None) -> Blas:
+    """verts: CUDA float32 [V,3]; idx: CUDA int32/uint32 [T,3]; prim_mat: CUDA
+    int16 [T] or None."""
+    n_tris = int(idx.shape[0])
+    nb, ns = blas_sizes(n_tris, width, leaf_max)
+    buf = _bytes(nb, verts.device)
+    if scratch is None or scratch.numel() < ns:
+        scratch = _bytes(ns, verts.device)
+    d = BlasDesc()
+    o = _opts(width, leaf_max)
+    _check("rg_build_blas", _lib.rg_build_blas(
+        _ptr(verts), int(verts.shape[0]), _ptr(idx), n_tris, _ptr(prim_mat), ctypes.byref(o),
+        _ptr(buf), buf.numel(), _ptr(scratch), scratch.numel(), _stream(stream), ctypes.byref(d)))
+    return Blas(buf, d)
+
+
+# ----------------------------------------------------------------- top level
+class Tlas:
+    def __init__(self, buf, desc: TlasDesc, blas: Sequence[Blas]):
+        self.buf = buf
+        self.desc = desc
+        self.blas = list(blas)   # keeps the bottom levels alive
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.desc)
+
+
+def build_tlas(blas: Sequence[Blas], xform, blas_id, inst_mat, width: int = 4, stream=None,
+               scratch=None) -> Tlas:
+    """xform: host float32 [I,3,4]; blas_id, inst_mat: host uint32 [I]."""
+    torch = _torch()
+    xform = np.ascontiguousarray(xform, np.float32).reshape(-1, 12)
+    blas_id = np.ascontiguousarray(blas_id, np.uint32)
+    inst_mat = np.ascontiguousarray(inst_mat, np.uint32)
+    n = xform.shape[0]
+    s = Sizes()
+    o = _opts(width, 1)
+    _check("rg_tlas_sizes", _lib.rg_tlas_sizes(n, ctypes.byref(o), ctypes.byref(s)))
+    dev = blas[0].buf.device
+    buf = _bytes(s.bytes, dev)
+    if scratch is None or scratch.numel() < s.scratch_bytes:
+        scratch = _bytes(s.scratch_bytes, dev)
+    arr = (BlasDesc * len(blas))(*[b.desc for b in blas])
+    d = TlasDesc()
+    _check("rg_build_tlas", _lib.rg_build_tlas(
+        arr, len(blas), xform.ctypes.data, blas_id.ctypes.data, inst_mat.ctypes.data, n,
+        ctypes.byref(o), _ptr(buf), buf.numel(), _ptr(scratch), scratch.numel(), _stream(stream),
+        ctypes.byref(d)))
+    del torch
+    return Tlas(buf, d, blas)
+
+
+def upload_scene(scene, width: int = 4, leaf_max: int = 4, device="cuda") -> Tlas:
+    """Builds every mesh and the instance level of a scene object with
+    attributes blas (meshes with verts/idx/prim_mat), xform, blas_id, inst_mat."""
+    torch = _torch()
+    built: List[Blas] = []
+    for m in scene.blas:
+        v = torch.from_numpy(np.ascontiguousarray(m.verts, np.float32)).to(device)
+        i = torch.from_numpy(np.ascontiguousarray(m.idx, np.uint32).view(np.int32)).to(device)
+        pm = None
+        if m.prim_mat is not None:
+            pm = torch.from_numpy(np.ascontiguousarray(m.prim_mat, np.uint16).view(np.int16)).to(device)
+        built.append(build_blas(v, i, pm, width, leaf_max))
+        del v, i, pm
+    return build_tlas(built, scene.xform, scene.blas_id, scene.inst_mat, width)
+
+
+# ------------------------------------------------------------------- rays
+def rays_struct(r) -> Rays:
+    """r: CUDA float32 [8, N] (ox oy oz dx dy dz tmin tmax rows)."""
+    if r.dim() != 2 or r.shape[0] != 8:
+        raise ValueError("rays must be [8, N]")
+    base = _ptr(r)
+    n = r.shape[1]
+    return Rays(*[base + 4 * n * k for k in range(8)])
+
+
+def rays_to_device(rays_np, device="cuda"):
+    """Host float32 [N,8] -> CUDA [8,N]."""
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(rays_np, np.float32).T)).to(device)
+
+
+def alloc_hits(n: int, device="cuda"):
+    torch = _torch()
+    return dict(t=torch.empty(n, dtype=torch.float32, device=device),
+                inst=torch.empty(n, dtype=torch.int32, device=device),
+                prim=torch.empty(n, dtype=torch.int32, device=device),
+                u=torch.empty(n, dtype=torch.float32, device=device),
+                v=torch.empty(n, dtype=torch.float32, device=device))
+
+
+def _hits_struct(h) -> Hits:
+    return Hits(_ptr(h["t"]), _ptr(h["inst"]), _ptr(h["prim"]), _ptr(h["u"]), _ptr(h["v"]))
+
+
+def trace_closest(tlas: Tlas, rays, out=None, stream=None):
+    n = rays.shape[1]
+    if out is None:
+        out = alloc_hits(n, rays.device)
+    _check("rg_trace_closest", _lib.rg_trace_closest(tlas.ref, rays_struct(rays), n, _hits_struct(out),
+                                                     _stream(stream)))
+    return out
+
+
+def trace_any(tlas: Tlas, rays, occluded=None, found=None, stream=None):
+    torch = _torch()
+    n = rays.shape[1]
+    if occluded is None:
+        occluded = torch.empty(n, dtype=torch.uint8, device=rays.device)
+    fh = ctypes.byref(_hits_struct(found)) if found is not None else None
+    _check("rg_trace_any", _lib.rg_trace_any(tlas.ref, rays_struct(rays), n, _ptr(occluded), fh,
+                                             _stream(stream)))
+    return occluded
+
+
+def trace_counts(tlas: Tlas, rays, any_hit: bool = False, counts=None, stream=None):
+    torch = _torch()
+    n = rays.shape[1]
+    if counts is None:
+        counts = torch.empty((n, 3), dtype=torch.int32, device=rays.device)
+    _check("rg_trace_counts", _lib.rg_trace_counts(tlas.ref, rays_struct(rays), n, 1 if any_hit else 0,
+                                                   _ptr(counts), _stream(stream)))
+    return counts
+
+
+def camera_desc(cam) -> CameraDesc:
+    return CameraDesc((c_f * 3)(*cam.eye), (c_f * 3)(*cam.target), (c_f * 3)(*cam.up), cam.vfov_deg)
+
+
+def light_desc(light) -> LightDesc:
+    return LightDesc((c_f * 3)(*light.pos), (c_f * 3)(*light.intensity), light.ambient)
+
+
+def camera_rays(cam, width: int, height: int, out=None, stream=None):
+    torch = _torch()
+    n = width * height
+    if out is None:
+        out = torch.empty((8, n), dtype=torch.float32, device="cuda")
+    ptrs = (c_p * 8)(*[out.data_ptr() + 4 * n * k for k in range(8)])
+    cd = camera_desc(cam)
+    _check("rg_camera_rays", _lib.rg_camera_rays(ctypes.byref(cd), width, height, ptrs, _stream(stream)))
+    return out
+
+
+def ao_rays(tlas: Tlas, rays, hits, seed: int, tmax: float = 5.0, out=None, src=None, count=None,
+            scratch=None, stream=None):
+    """AO rays for every hit ray; returns (rays [8, 8N] (first `count` valid),
+    src [8N], count tensor [1])."""
+    torch = _torch()
+    n = rays.shape[1]
+    dev = rays.device
+    if out is None:
+        out = torch.empty((8, 8 * n), dtype=torch.float32, device=dev)
+    if src is None:
+        src = torch.empty(8 * n, dtype=torch.int32, device=dev)
+    if count is None:
+        count = torch.zeros(1, dtype=torch.int32, device=dev)
+    need = ctypes.c_uint64()
+    _check("rg_ao_rays_scratch", _lib.rg_ao_rays_scratch(n, ctypes.byref(need)))
+    if scratch is None or scratch.numel() < need.value:
+        scratch = _bytes(need.value, dev)
+    cap = out.shape[1]
+    ptrs = (c_p * 8)(*[out.data_ptr() + 4 * cap * k for k in range(8)])
+    _check("rg_ao_rays", _lib.rg_ao_rays(tlas.ref, rays_struct(rays), n, _ptr(hits["inst"]), _ptr(hits["prim"]),
+                                         _ptr(hits["t"]), seed, tmax, ptrs, _ptr(src), _ptr(count),
+                                         _ptr(scratch), scratch.numel(), _stream(stream)))
+    return out, src, count
+
+
+def materials_array(mats) -> ctypes.Array:
+    """Structured numpy (type, rgb[3], ior) -> rg_material[]."""
+    arr = (Material * len(mats))()
+    for i, m in enumerate(mats):
+        arr[i].type = int(m["type"])
+        for k in range(3):
+            arr[i].rgb[k] = float(m["rgb"][k])
+        arr[i].ior = float(m["ior"])
+    return arr
+
+
+def render_sizes(width: int, height: int, max_depth: int, mode: int) -> int:
+    s = ctypes.c_uint64()
+    _check("rg_render_sizes", _lib.rg_render_sizes(width, height, max_depth, mode, ctypes.byref(s)))
+    return int(s.value)
+
+
+class Renderer:
+    """Owns the scratch buffer of rg_render for one image size / depth / mode."""
+
+    def __init__(self, width: int, height: int, max_depth: int, mode: int = 0, device="cuda"):
+        torch = _torch()
+        self.width, self.height, self.max_depth, self.mode = width, height, max_depth, mode
+        self.scratch = _bytes(render_sizes(width, height, max_depth, mode), device)
+        self.image = torch.empty((height, width, 3), dtype=torch.float32, device=device)
+
+    def render(self, tlas: Tlas, mats, camera, light, seed: int = 0, stats: bool = False, stream=None):
+        ma = materials_array(mats)
+        cd, ld = camera_desc(camera), light_desc(light)
+        st = RenderStats()
+        _check("rg_render", _lib.rg_render(tlas.ref, ma, len(mats), ctypes.byref(cd), ctypes.byref(ld),
+                                           self.width, self.height, self.max_depth, self.mode, seed,
+                                           _ptr(self.image), _ptr(self.scratch), self.scratch.numel(),
+                                           _stream(stream), ctypes.byref(st) if stats else None))
+        if stats:
+            return self.image, dict(rays_traced=int(st.rays_traced), shadow_rays=int(st.shadow_rays),
+                                    ms_total=float(st.ms_total))
+        return self.image
+
+
+def render(tlas: Tlas, mats, camera, light, width: int, height: int, max_depth: int, mode: int = 0,
+           seed: int = 0, stream=None):
+    r = Renderer(width, height, max_depth, mode)
+    return r.render(tlas, mats, camera, light, seed, stream=stream).clone()
+
+
+def lbvh_stages(verts, idx, stream=None) -> dict:
+    """Intermediate results of the bottom-level build (keys, ids, tree, boxes)."""
+    torch = _torch()
+    n = int(idx.shape[0])
+    _, ns = blas_sizes(n)
+    scratch = _bytes(ns, verts.device)
+    dev = verts.device
+    keys = torch.empty(n, dtype=torch.int64, device=dev)
+    ids = torch.empty(n, dtype=torch.int32, device=dev)
+    left = torch.empty(max(n - 1, 1), dtype=torch.int32, device=dev)
+    right = torch.empty(max(n - 1, 1), dtype=torch.int32, device=dev)
+    boxes = torch.empty((2 * n - 1, 6), dtype=torch.float32, device=dev)
+    _check("rg_lbvh_stages", _lib.rg_lbvh_stages(_ptr(verts), int(verts.shape[0]), _ptr(idx), n, _ptr(keys),
+                                                 _ptr(ids), _ptr(left), _ptr(right), _ptr(boxes),
+                                                 _ptr(scratch), scratch.numel(), _stream(stream)))
+    return dict(keys=keys, ids=ids, left=left[:n - 1], right=right[:n - 1], boxes=boxes)

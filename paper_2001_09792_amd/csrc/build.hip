@@ -1,0 +1,941 @@
+// build.hip -- linear BVH construction for gfx950 and the bottom/top-level
+// entry points.
+//
+// The paper builds its two-layered structure from the models' vertex data
+// (bottom level) and from instances with transformation matrices (top level)
+// inside the RTX driver (section 1).  Here both levels use one pipeline:
+//   1. primitive boxes and the bounds of their centres,
+//   2. 63-bit Morton codes of the quantised centres,
+//   3. a stable LSD radix sort of (key, id), 8-bit digits, ranked in LDS,
+//   4. Karras's parallel radix-tree construction (HPG 2012),
+//   5. bottom-up box refit with arrival counters,
+//   6. top-down collapse into W-wide nodes (repeatedly opening the inner
+//      child with the largest surface area), leaves of <= leaf_max prims,
+// followed by reordering the primitives into leaf order.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "rg_internal.h"
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kThreads * kSortItems;
+constexpr int kScanThreads = 1024;
+
+// --------------------------------------------------------------- helpers
+
+__device__ inline float wave_min(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ inline float wave_max(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// ------------------------------------------------- 1. primitive boxes
+// flags bit 0: an index out of range; bit 1: a non-finite coordinate.
+__global__ void k_tri_boxes(const float *__restrict__ verts, int64_t n_verts,
+                            const uint32_t *__restrict__ idx, int64_t n, float *__restrict__ box,
+                            uint32_t *__restrict__ flags) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t a = idx[3 * i], b = idx[3 * i + 1], c = idx[3 * i + 2];
+    uint32_t bad = 0;
+    if ((int64_t)a >= n_verts || (int64_t)b >= n_verts || (int64_t)c >= n_verts) {
+        bad |= 1u;
+        a = b = c = 0;
+    }
+    float v[9];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        v[k] = verts[3 * (int64_t)a + k];
+        v[3 + k] = verts[3 * (int64_t)b + k];
+        v[6 + k] = verts[3 * (int64_t)c + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+        if (!isfinite(v[k])) bad |= 2u;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        box[6 * i + k] = fminf(fminf(v[k], v[3 + k]), v[6 + k]);
+        box[6 * i + 3 + k] = fmaxf(fmaxf(v[k], v[3 + k]), v[6 + k]);
+    }
+    if (bad) atomicOr(flags, bad);
+}
+
+// Bounds of the box centres c = 0.5 (lo + hi) as order-preserving uints:
+// bounds[0..2] = min, bounds[3..5] = max.
+__global__ void k_centre_bounds(const float *__restrict__ box, int64_t n, uint32_t *__restrict__ bounds) {
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float c = (box[6 * i + k] + box[6 * i + 3 + k]) * 0.5f;
+            mn[k] = fminf(mn[k], c);
+            mx[k] = fmaxf(mx[k], c);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        mn[k] = wave_min(mn[k]);
+        mx[k] = wave_max(mx[k]);
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            atomicMin(&bounds[k], rg_f2ord(mn[k]));
+            atomicMax(&bounds[3 + k], rg_f2ord(mx[k]));
+        }
+    }
+}
+
+// ------------------------------------------------------ 2. Morton codes
+__device__ inline uint64_t spread21(uint64_t x) {
+    x &= 0x1FFFFFull;
+    x = (x | (x << 32)) & 0x001F00000000FFFFull;
+    x = (x | (x << 16)) & 0x001F0000FF0000FFull;
+    x = (x | (x << 8)) & 0x100F00F00F00F00Full;
+    x = (x | (x << 4)) & 0x10C30C30C30C30C3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__global__ void k_morton(const float *__restrict__ box, int64_t n, const uint32_t *__restrict__ bounds,
+                         uint64_t *__restrict__ keys, uint32_t *__restrict__ ids) {
+#pragma clang fp contract(off)
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t q[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float lo = rg_ord2f(bounds[k]), hi = rg_ord2f(bounds[3 + k]);
+        float ext = hi - lo;
+        float s = ext > 0.0f ? 2097152.0f / ext : 0.0f;
+        float c = (box[6 * i + k] + box[6 * i + 3 + k]) * 0.5f;
+        float x = (c - lo) * s;
+        x = floorf(x);
+        uint64_t v = (x > 0.0f) ? (uint64_t)x : 0ull;  // NaN -> 0
+        q[k] = v > 2097151ull ? 2097151ull : v;
+    }
+    keys[i] = (spread21(q[0]) << 2) | (spread21(q[1]) << 1) | spread21(q[2]);
+    ids[i] = (uint32_t)i;
+}
+
+// -------------------------------------------------- 3. LSD radix sort
+__global__ void k_sort_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
+                            uint32_t *__restrict__ ghist, int nblocks) {
+    __shared__ uint32_t h[256];
+    int t = threadIdx.x;
+    h[t] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        int64_t i = base + it * kThreads + t;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    ghist[(int64_t)t * nblocks + blockIdx.x] = h[t];
+}
+
+// In-place exclusive prefix sum of m entries with one workgroup.
+__global__ void __launch_bounds__(kScanThreads) k_scan_excl(uint32_t *data, int64_t m) {
+    __shared__ uint32_t wsum[kScanThreads / 64];
+    __shared__ uint32_t carry;
+    int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < m; base += kScanThreads) {
+        uint32_t v = (base + t < m) ? data[base + t] : 0u;
+        uint32_t x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        if (w == 0) {
+            uint32_t s = lane < kScanThreads / 64 ? wsum[lane] : 0u;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                uint32_t y = __shfl_up(s, o, 64);
+                if (lane >= o) s += y;
+            }
+            if (lane < kScanThreads / 64) wsum[lane] = s;  // inclusive wave totals
+        }
+        __syncthreads();
+        uint32_t before = (w > 0 ? wsum[w - 1] : 0u) + x - v;
+        uint32_t c = carry;
+        if (base + t < m) data[base + t] = c + before;
+        __syncthreads();
+        if (t == kScanThreads - 1) carry = c + wsum[kScanThreads / 64 - 1];
+        __syncthreads();
+    }
+}
+
+// Stable scatter: within each 256-element chunk, lanes with equal digits are
+// matched with 8 ballots, ranked by lane order, and offset by the counts of
+// earlier waves (LDS) and of earlier chunks and blocks.
+__global__ void __launch_bounds__(kThreads) k_sort_scatter(
+    const uint64_t *__restrict__ keys_in, const uint32_t *__restrict__ ids_in,
+    uint64_t *__restrict__ keys_out, uint32_t *__restrict__ ids_out, int64_t n, int shift,
+    const uint32_t *__restrict__ goff, int nblocks) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcount[kThreads / 64][256];
+    int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    run[t] = goff[(int64_t)t * nblocks + blockIdx.x];
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    for (int it = 0; it < kSortItems; ++it) {
+        int64_t i = (int64_t)blockIdx.x * kSortTile + it * kThreads + t;
+        bool valid = i < n;
+        uint64_t key = valid ? keys_in[i] : 0ull;
+        uint32_t id = valid ? ids_in[i] : 0u;
+        uint32_t digit = (uint32_t)(key >> shift) & 255u;
+#pragma unroll
+        for (int q = 0; q < kThreads / 64; ++q) wcount[q][t] = 0u;
+        __syncthreads();
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            bool bit = (digit >> b) & 1u;
+            uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        uint32_t rank = (uint32_t)__popcll(peers & lt);
+        if (valid && rank == 0) wcount[w][digit] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        uint32_t total = 0;
+#pragma unroll
+        for (int q = 0; q < kThreads / 64; ++q) {
+            uint32_t c = wcount[q][t];
+            wcount[q][t] = total;
+            total += c;
+        }
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = run[digit] + wcount[w][digit] + rank;
+            if (pos < (uint64_t)n) {  // always true for a consistent histogram
+                keys_out[pos] = key;
+                ids_out[pos] = id;
+            }
+        }
+        __syncthreads();
+        run[t] += total;
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------- 4. Karras hierarchy
+__device__ inline int k_delta(const uint64_t *__restrict__ k, int64_t n, int64_t i, int64_t j) {
+    if (j < 0 || j >= n) return -1;
+    uint64_t a = k[i], b = k[j];
+    if (a == b) return 64 + __clz((int)((uint32_t)i ^ (uint32_t)j));
+    return __clzll((long long)(a ^ b));
+}
+
+__global__ void k_karras(const uint64_t *__restrict__ keys, int64_t n, int32_t *__restrict__ left,
+                         int32_t *__restrict__ right, int32_t *__restrict__ parent_int,
+                         int32_t *__restrict__ parent_leaf, int32_t *__restrict__ first,
+                         int32_t *__restrict__ last) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    int d = (k_delta(keys, n, i, i + 1) - k_delta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
+    int dmin = k_delta(keys, n, i, i - d);
+    int64_t lmax = 2;
+    while (k_delta(keys, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int64_t l = 0;
+    for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
+        if (k_delta(keys, n, i, i + (l + t) * d) > dmin) l += t;
+    int64_t j = i + l * d;
+    int dnode = k_delta(keys, n, i, j);
+    int64_t s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (k_delta(keys, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    int64_t g = i + s * d + (d < 0 ? -1 : 0);
+    int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+    if (g < 0 || g + 1 > n - 1 || lo < 0 || hi > n - 1) return;  // unreachable for sorted keys
+    if (lo == g) {
+        left[i] = -(int32_t)(g + 1);
+        parent_leaf[g] = (int32_t)i;
+    } else {
+        left[i] = (int32_t)g;
+        parent_int[g] = (int32_t)i;
+    }
+    if (hi == g + 1) {
+        right[i] = -(int32_t)(g + 2);
+        parent_leaf[g + 1] = (int32_t)i;
+    } else {
+        right[i] = (int32_t)(g + 1);
+        parent_int[g + 1] = (int32_t)i;
+    }
+    first[i] = (int32_t)lo;
+    last[i] = (int32_t)hi;
+    if (i == 0) parent_int[0] = -1;
+}
+
+// -------------------------------------------------------- 5. box refit
+__global__ void k_refit(const float *__restrict__ prim_box, const uint32_t *__restrict__ ids, int64_t n,
+                        const int32_t *__restrict__ left, const int32_t *__restrict__ right,
+                        const int32_t *__restrict__ parent_int, const int32_t *__restrict__ parent_leaf,
+                        uint32_t *counter, float *int_box, float *leaf_box) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t src = ids[i];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) leaf_box[6 * i + k] = prim_box[6 * (int64_t)src + k];
+    if (n < 2) return;
+    int32_t p = parent_leaf[i];
+    while (p >= 0 && p < n - 1) {
+        uint32_t old = __hip_atomic_fetch_add(&counter[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == 0u) return;  // the sibling's subtree is still being built
+        int32_t c[2] = {left[p], right[p]};
+        float b[12];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const float *src_box = c[s] < 0 ? leaf_box + 6 * (int64_t)(-c[s] - 1) : int_box + 6 * (int64_t)c[s];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) b[6 * s + k] = src_box[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            int_box[6 * (int64_t)p + k] = fminf(b[k], b[6 + k]);
+            int_box[6 * (int64_t)p + 3 + k] = fmaxf(b[3 + k], b[9 + k]);
+        }
+        p = parent_int[p];
+    }
+}
+
+// --------------------------------------------------- 6. wide collapse
+__device__ inline float surface_area(const float *b) {
+    float dx = b[3] - b[0], dy = b[4] - b[1], dz = b[5] - b[2];
+    return 2.0f * (dx * dy + dy * dz + dz * dx);
+}
+
+template <int W>
+__global__ void k_collapse(const int32_t *__restrict__ left, const int32_t *__restrict__ right,
+                           const int32_t *__restrict__ first, const int32_t *__restrict__ last,
+                           const float *__restrict__ int_box, const float *__restrict__ leaf_box,
+                           int leaf_max, const uint2 *__restrict__ q_in, const uint32_t *__restrict__ q_in_count,
+                           uint2 *__restrict__ q_out, uint32_t *q_out_count, uint32_t *node_count,
+                           RgNode<W> *__restrict__ nodes, uint32_t cap, uint32_t *err) {
+    uint32_t cnt = *q_in_count;
+    if (cnt > cap) cnt = cap;
+    for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < cnt; qi += gridDim.x * blockDim.x) {
+        uint2 item = q_in[qi];
+        int32_t C[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) C[k] = 0;
+        C[0] = left[item.y];
+        C[1] = right[item.y];
+        int m = 2;
+        while (m < W) {
+            int best = -1;
+            float bsa = -1.0f;
+            for (int k = 0; k < m; ++k) {
+                if (C[k] >= 0) {
+                    float sa = surface_area(int_box + 6 * (int64_t)C[k]);
+                    if (sa > bsa) {
+                        bsa = sa;
+                        best = k;
+                    }
+                }
+            }
+            if (best < 0) break;
+            int32_t c = C[best];
+            C[best] = left[c];
+            C[m++] = right[c];
+        }
+        RgNode<W> *nd = nodes + item.x;
+        for (int k = 0; k < W; ++k) {
+            if (k >= m) {
+                nd->lo_x[k] = INFINITY; nd->lo_y[k] = INFINITY; nd->lo_z[k] = INFINITY;
+                nd->hi_x[k] = -INFINITY; nd->hi_y[k] = -INFINITY; nd->hi_z[k] = -INFINITY;
+                nd->child[k] = RG_EMPTY;
+                nd->pad[k] = 0u;
+                continue;
+            }
+            int32_t c = C[k];
+            const float *b;
+            uint32_t link;
+            if (c < 0) {
+                int32_t leaf = -c - 1;
+                b = leaf_box + 6 * (int64_t)leaf;
+                link = rg_leaf((uint32_t)leaf, 1u);
+            } else {
+                b = int_box + 6 * (int64_t)c;
+                int32_t size = last[c] - first[c] + 1;
+                if (size <= leaf_max) {
+                    link = rg_leaf((uint32_t)first[c], (uint32_t)size);
+                } else {
+                    uint32_t nn = atomicAdd(node_count, 1u);
+                    uint32_t slot = atomicAdd(q_out_count, 1u);
+                    if (nn < cap && slot < cap) {  // a BVH2 has n-1 inner nodes: never exceeded
+                        q_out[slot] = make_uint2(nn, (uint32_t)c);
+                        link = nn;
+                    } else {
+                        atomicOr(err, 4u);
+                        link = RG_EMPTY;
+                    }
+                }
+            }
+            nd->lo_x[k] = b[0]; nd->lo_y[k] = b[1]; nd->lo_z[k] = b[2];
+            nd->hi_x[k] = b[3]; nd->hi_y[k] = b[4]; nd->hi_z[k] = b[5];
+            nd->child[k] = link;
+            nd->pad[k] = 0u;
+        }
+    }
+}
+
+// Single-primitive structure: one root node with one leaf child.
+template <int W>
+__global__ void k_single_root(const float *__restrict__ leaf_box, RgNode<W> *nodes) {
+    int k = threadIdx.x;
+    if (k >= W) return;
+    RgNode<W> *nd = nodes;
+    if (k == 0) {
+        nd->lo_x[0] = leaf_box[0]; nd->lo_y[0] = leaf_box[1]; nd->lo_z[0] = leaf_box[2];
+        nd->hi_x[0] = leaf_box[3]; nd->hi_y[0] = leaf_box[4]; nd->hi_z[0] = leaf_box[5];
+        nd->child[0] = rg_leaf(0u, 1u);
+    } else {
+        nd->lo_x[k] = INFINITY; nd->lo_y[k] = INFINITY; nd->lo_z[k] = INFINITY;
+        nd->hi_x[k] = -INFINITY; nd->hi_y[k] = -INFINITY; nd->hi_z[k] = -INFINITY;
+        nd->child[k] = RG_EMPTY;
+    }
+    nd->pad[k] = 0u;
+}
+
+__global__ void k_collapse_init(uint2 *q, uint32_t *q_count, uint32_t *node_count) {
+    q[0] = make_uint2(0u, 0u);
+    *q_count = 1u;
+    *node_count = 1u;
+}
+
+// ------------------------------------------------------ reordering
+__global__ void k_reorder_tris(const float *__restrict__ verts, const uint32_t *__restrict__ idx,
+                               const uint32_t *__restrict__ ids, int64_t n, const uint16_t *__restrict__ pm,
+                               RgTri *__restrict__ tris, uint16_t *__restrict__ mats, uint32_t *__restrict__ slots) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t s = ids[i];
+    RgTri t;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        uint32_t vi = idx[3 * (int64_t)s + v];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) t.v[3 * v + k] = verts[3 * (int64_t)vi + k];
+    }
+    t.prim = s;
+    tris[i] = t;
+    mats[i] = pm ? pm[s] : (uint16_t)0;
+    slots[s] = (uint32_t)i;
+}
+
+__global__ void k_blas_header(RgBlasHdr *h, uint64_t nodes, uint64_t tris, uint64_t mats, uint64_t slots) {
+    h->nodes = nodes;
+    h->tris = tris;
+    h->mats = mats;
+    h->slots = slots;
+}
+
+// ----------------------------------------------------------- top level
+struct BlasInfo {
+    float lo[3], hi[3];
+    uint64_t nodes, tris, hdr;
+};
+
+__device__ inline float round_down(double x) {
+    float f = (float)x;
+    if ((double)f > x) f = nextafterf(f, -INFINITY);
+    return f;
+}
+__device__ inline float round_up(double x) {
+    float f = (float)x;
+    if ((double)f < x) f = nextafterf(f, INFINITY);
+    return f;
+}
+
+__global__ void k_inst_setup(const float *__restrict__ xform, const uint32_t *__restrict__ blas_id,
+                             const uint32_t *__restrict__ inst_mat, const BlasInfo *__restrict__ blas,
+                             int64_t n, float *__restrict__ box, RgInst *__restrict__ recs) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double m[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) m[k] = (double)xform[12 * i + k];
+    const BlasInfo &B = blas[blas_id[i]];
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int c = 0; c < 8; ++c) {
+        double p[3] = {(double)((c & 1) ? B.hi[0] : B.lo[0]), (double)((c & 2) ? B.hi[1] : B.lo[1]),
+                       (double)((c & 4) ? B.hi[2] : B.lo[2])};
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            double w = m[4 * r] * p[0] + m[4 * r + 1] * p[1] + m[4 * r + 2] * p[2] + m[4 * r + 3];
+            mn[r] = fmin(mn[r], w);
+            mx[r] = fmax(mx[r], w);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        box[6 * i + r] = round_down(mn[r]);
+        box[6 * i + 3 + r] = round_up(mx[r]);
+    }
+    // inverse of the linear part (adjugate over determinant), in double
+    double a = m[0], b = m[1], c = m[2], d = m[4], e = m[5], f = m[6], g = m[8], h = m[9], k = m[10];
+    double A = e * k - f * h, Bc = -(d * k - f * g), Cc = d * h - e * g;
+    double det = a * A + b * Bc + c * Cc;
+    double inv[9] = {A / det, -(b * k - c * h) / det, (b * f - c * e) / det,
+                     Bc / det, (a * k - c * g) / det, -(a * f - c * d) / det,
+                     Cc / det, -(a * h - b * g) / det, (a * e - b * d) / det};
+    RgInst r;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) r.inv[q] = (float)inv[q];
+    r.p[0] = xform[12 * i + 3];
+    r.p[1] = xform[12 * i + 7];
+    r.p[2] = xform[12 * i + 11];
+    r.nodes = B.nodes;
+    r.tris = B.tris;
+    r.hdr = B.hdr;
+    r.mat = inst_mat[i];
+    r.inst = (uint32_t)i;
+    recs[i] = r;
+}
+
+__global__ void k_reorder_inst(const RgInst *__restrict__ in, const uint32_t *__restrict__ ids, int64_t n,
+                               RgInst *__restrict__ out, uint32_t *__restrict__ rec_of) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = in[ids[i]];
+    rec_of[ids[i]] = (uint32_t)i;
+}
+
+int node_bytes(int w) { return 32 * w; }
+
+bool opts_ok(const rg_build_opts *o, int32_t *w, int32_t *leaf) {
+    int32_t W = o ? o->width : 4, L = o ? o->leaf_max : 4;
+    if (!(W == 2 || W == 4 || W == 8)) return false;
+    if (L < 1 || L > 8) return false;
+    *w = W;
+    *leaf = L;
+    return true;
+}
+
+uint64_t align256(uint64_t x) { return (x + 255u) & ~uint64_t(255); }
+
+struct LbvhScratch {
+    float *leaf_box, *int_box;
+    uint64_t *keys, *keys2;
+    uint32_t *ids, *ids2, *hist, *bounds, *counter, *qcount, *flags;
+    int32_t *left, *right, *pint, *pleaf, *first, *last;
+    uint2 *q0, *q1;
+};
+
+bool carve(RgArena &a, int64_t n, LbvhScratch &s) {
+    int64_t nb = (n + kSortTile - 1) / kSortTile;
+    int64_t ni = n > 1 ? n - 1 : 1;
+    s.leaf_box = a.take<float>(6 * n);
+    s.int_box = a.take<float>(6 * ni);
+    s.keys = a.take<uint64_t>(n);
+    s.keys2 = a.take<uint64_t>(n);
+    s.ids = a.take<uint32_t>(n);
+    s.ids2 = a.take<uint32_t>(n);
+    s.hist = a.take<uint32_t>(256 * nb);
+    s.bounds = a.take<uint32_t>(8);
+    s.counter = a.take<uint32_t>(ni);
+    s.qcount = a.take<uint32_t>(8);
+    s.flags = a.take<uint32_t>(8);
+    s.left = a.take<int32_t>(ni);
+    s.right = a.take<int32_t>(ni);
+    s.pint = a.take<int32_t>(ni);
+    s.pleaf = a.take<int32_t>(n);
+    s.first = a.take<int32_t>(ni);
+    s.last = a.take<int32_t>(ni);
+    s.q0 = a.take<uint2>(ni);
+    s.q1 = a.take<uint2>(ni);
+    return !a.overflow();
+}
+
+template <int W>
+rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes_v, hipStream_t st,
+                   int32_t *depth, int64_t *n_nodes) {
+    RgNode<W> *nodes = reinterpret_cast<RgNode<W> *>(nodes_v);
+    if (n == 1) {
+        k_single_root<W><<<1, 64, 0, st>>>(s.leaf_box, nodes);
+        RG_LAUNCH_CHECK();
+        *depth = 1;
+        *n_nodes = 1;
+        return RG_OK;
+    }
+    uint32_t *qc = s.qcount;  // [0], [1] queue counts, [2] node count, [3] error flags
+    const uint32_t cap = (uint32_t)(n - 1);
+    k_fill_u32<<<1, 64, 0, st>>>(qc, 0u, 4);
+    k_collapse_init<<<1, 1, 0, st>>>(s.q0, qc, qc + 2);
+    RG_LAUNCH_CHECK();
+    uint2 *qin = s.q0, *qout = s.q1;
+    uint32_t *cin = qc, *cout = qc + 1;
+    uint32_t count = 1, host_count = 0;
+    int32_t d = 0;
+    while (count > 0) {
+        ++d;
+        k_fill_u32<<<1, 64, 0, st>>>(cout, 0u, 1);
+        unsigned blocks = rg_blocks(count, kThreads);
+        if (blocks > 4096) blocks = 4096;
+        k_collapse<W><<<blocks, kThreads, 0, st>>>(s.left, s.right, s.first, s.last, s.int_box, s.leaf_box,
+                                                    leaf_max, qin, cin, qout, cout, qc + 2, nodes, cap, qc + 3);
+        RG_LAUNCH_CHECK();
+        uint32_t hq[4];
+        RG_HIP(hipMemcpyAsync(hq, qc, 16, hipMemcpyDeviceToHost, st));
+        RG_HIP(hipStreamSynchronize(st));
+        host_count = hq[cout - qc];
+        if (hq[3] != 0u || d > 4096) return RG_ERR_HIP;  // inconsistent hierarchy: never expected
+        count = host_count;
+        uint2 *tq = qin;
+        qin = qout;
+        qout = tq;
+        uint32_t *tc = cin;
+        cin = cout;
+        cout = tc;
+    }
+    uint32_t nn = 0;
+    RG_HIP(hipMemcpyAsync(&nn, qc + 2, 4, hipMemcpyDeviceToHost, st));
+    RG_HIP(hipStreamSynchronize(st));
+    *depth = d;
+    *n_nodes = nn;
+    return RG_OK;
+}
+
+}  // namespace
+
+uint64_t rg_lbvh_scratch_bytes(int64_t n) {
+    RgArena a{nullptr, 0, 0};
+    LbvhScratch s;
+    carve(a, n, s);
+    return a.used;
+}
+
+rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t leaf_max, void *nodes,
+                        RgArena &arena, hipStream_t st, RgLbvhOut *out, bool keep_stages, uint64_t *keys_out,
+                        int32_t *left_out, int32_t *right_out, float *boxes_out) {
+    LbvhScratch s;
+    if (!carve(arena, n, s)) return RG_ERR_OUT_OF_MEMORY;
+    int nblocks = (int)((n + kSortTile - 1) / kSortTile);
+    // bounds of the centres
+    k_fill_u32<<<1, 64, 0, st>>>(s.bounds, 0xFFFFFFFFu, 3);
+    k_fill_u32<<<1, 64, 0, st>>>(s.bounds + 3, 0u, 3);
+    unsigned bb = rg_blocks(n, kThreads);
+    if (bb > 1024) bb = 1024;
+    k_centre_bounds<<<bb, kThreads, 0, st>>>(prim_box, n, s.bounds);
+    RG_LAUNCH_CHECK();
+    k_morton<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(prim_box, n, s.bounds, s.keys, s.ids);
+    RG_LAUNCH_CHECK();
+    // 8 passes of 8 bits; the result lands back in keys/ids
+    uint64_t *ka = s.keys, *kb = s.keys2;
+    uint32_t *ia = s.ids, *ib = s.ids2;
+    for (int shift = 0; shift < 64; shift += 8) {
+        k_sort_hist<<<nblocks, kThreads, 0, st>>>(ka, n, shift, s.hist, nblocks);
+        k_scan_excl<<<1, kScanThreads, 0, st>>>(s.hist, (int64_t)256 * nblocks);
+        k_sort_scatter<<<nblocks, kThreads, 0, st>>>(ka, ia, kb, ib, n, shift, s.hist, nblocks);
+        RG_LAUNCH_CHECK();
+        uint64_t *tk = ka; ka = kb; kb = tk;
+        uint32_t *ti = ia; ia = ib; ib = ti;
+    }
+    if (n > 1) {
+        k_karras<<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>(ka, n, s.left, s.right, s.pint, s.pleaf, s.first,
+                                                                  s.last);
+        k_fill_u32<<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>(s.counter, 0u, n - 1);
+        RG_LAUNCH_CHECK();
+    }
+    k_refit<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(prim_box, ia, n, s.left, s.right, s.pint, s.pleaf, s.counter,
+                                                         s.int_box, s.leaf_box);
+    RG_LAUNCH_CHECK();
+    if (keep_stages) {
+        RG_HIP(hipMemcpyAsync(keys_out, ka, 8 * n, hipMemcpyDeviceToDevice, st));
+        if (n > 1) {
+            RG_HIP(hipMemcpyAsync(left_out, s.left, 4 * (n - 1), hipMemcpyDeviceToDevice, st));
+            RG_HIP(hipMemcpyAsync(right_out, s.right, 4 * (n - 1), hipMemcpyDeviceToDevice, st));
+            RG_HIP(hipMemcpyAsync(boxes_out, s.int_box, 24 * (n - 1), hipMemcpyDeviceToDevice, st));
+        }
+        RG_HIP(hipMemcpyAsync(boxes_out + 6 * (n - 1), s.leaf_box, 24 * n, hipMemcpyDeviceToDevice, st));
+    }
+    out->ids = ia;
+    rg_status r = RG_OK;
+    if (nodes) {
+        if (width == 2) r = collapse<2>(s, n, leaf_max, nodes, st, &out->depth, &out->n_nodes);
+        else if (width == 4) r = collapse<4>(s, n, leaf_max, nodes, st, &out->depth, &out->n_nodes);
+        else r = collapse<8>(s, n, leaf_max, nodes, st, &out->depth, &out->n_nodes);
+        if (r != RG_OK) return r;
+    }
+    float rb[6];
+    RG_HIP(hipMemcpyAsync(rb, n > 1 ? s.int_box : s.leaf_box, 24, hipMemcpyDeviceToHost, st));
+    RG_HIP(hipStreamSynchronize(st));
+    for (int k = 0; k < 3; ++k) {
+        out->lo[k] = rb[k];
+        out->hi[k] = rb[3 + k];
+    }
+    return RG_OK;
+}
+
+rg_status rg_scan_excl_u32(uint32_t *data, int64_t m, hipStream_t st) {
+    k_scan_excl<<<1, kScanThreads, 0, st>>>(data, m);
+    RG_LAUNCH_CHECK();
+    return RG_OK;
+}
+
+// ================================================================ ABI
+namespace {
+
+uint64_t blas_out_bytes(int64_t n, int w, uint64_t *nodes_off, uint64_t *tris_off, uint64_t *mats_off,
+                        uint64_t *slots_off) {
+    int64_t max_nodes = n > 1 ? n - 1 : 1;
+    uint64_t off = 256;  // header
+    *nodes_off = off;
+    off = align256(off + (uint64_t)max_nodes * node_bytes(w));
+    *tris_off = off;
+    off = align256(off + (uint64_t)n * sizeof(RgTri));
+    *mats_off = off;
+    off = align256(off + (uint64_t)n * 2u);
+    *slots_off = off;
+    off = align256(off + (uint64_t)n * 4u);
+    return off;
+}
+
+uint64_t blas_scratch_bytes(int64_t n) {
+    RgArena a{nullptr, 0, 0};
+    a.take<float>(6 * n);  // primitive boxes
+    a.take<uint32_t>(8);   // flags
+    return a.used + rg_lbvh_scratch_bytes(n);
+}
+
+uint64_t tlas_out_bytes(int64_t n, int w, uint64_t *nodes_off, uint64_t *inst_off, uint64_t *rec_off) {
+    int64_t max_nodes = n > 1 ? n - 1 : 1;
+    uint64_t off = 0;
+    *nodes_off = off;
+    off = align256(off + (uint64_t)max_nodes * node_bytes(w));
+    *inst_off = off;
+    off = align256(off + (uint64_t)n * sizeof(RgInst));
+    *rec_off = off;
+    off = align256(off + (uint64_t)n * 4u);
+    return off;
+}
+
+uint64_t tlas_scratch_bytes(int64_t n, int32_t n_blas) {
+    RgArena a{nullptr, 0, 0};
+    a.take<float>(12 * n);      // matrices
+    a.take<uint32_t>(n);        // blas ids
+    a.take<uint32_t>(n);        // materials
+    a.take<BlasInfo>(n_blas > 0 ? n_blas : 1);
+    a.take<float>(6 * n);       // instance boxes
+    a.take<RgInst>(n);          // unsorted records
+    return a.used + rg_lbvh_scratch_bytes(n);
+}
+
+}  // namespace
+
+namespace {
+thread_local char g_last_error[256] = "";
+}
+
+void rg_set_error(const char *file, int line, const char *what) {
+    const char *base = file;
+    for (const char *p = file; *p; ++p)
+        if (*p == '/') base = p + 1;
+    snprintf(g_last_error, sizeof(g_last_error), "%s:%d: %s", base, line, what);
+}
+
+extern "C" {
+
+const char *rg_last_error(void) { return g_last_error; }
+
+const char *rg_status_string(rg_status s) {
+    switch (s) {
+        case RG_OK: return "ok";
+        case RG_ERR_INVALID_ARG: return "invalid argument";
+        case RG_ERR_OUT_OF_MEMORY: return "buffer too small";
+        case RG_ERR_HIP: return "HIP runtime error";
+        case RG_ERR_UNSUPPORTED: return "unsupported";
+        case RG_ERR_UNIMPLEMENTED: return "unimplemented";
+        default: return "unknown status";
+    }
+}
+
+rg_status rg_blas_sizes(int64_t n_tris, const rg_build_opts *opts, rg_sizes *out) {
+    int32_t w, l;
+    if (!out || n_tris < 1 || n_tris > RG_MAX_TRIS || !opts_ok(opts, &w, &l)) return RG_ERR_INVALID_ARG;
+    uint64_t a, b, c, d;
+    out->bytes = blas_out_bytes(n_tris, w, &a, &b, &c, &d);
+    out->scratch_bytes = blas_scratch_bytes(n_tris);
+    return RG_OK;
+}
+
+rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx, int64_t n_tris,
+                        const uint16_t *prim_material, const rg_build_opts *opts, void *out_buf,
+                        uint64_t out_bytes, void *scratch, uint64_t scratch_bytes, void *stream, rg_blas *out) {
+    int32_t w, l;
+    if (!verts || !idx || !out_buf || !scratch || !out) return RG_ERR_INVALID_ARG;
+    if (n_verts < 1 || n_verts > (1ll << 32) || n_tris < 1 || n_tris > RG_MAX_TRIS) return RG_ERR_INVALID_ARG;
+    if (!opts_ok(opts, &w, &l)) return RG_ERR_INVALID_ARG;
+    uint64_t no, to, mo, so;
+    uint64_t need = blas_out_bytes(n_tris, w, &no, &to, &mo, &so);
+    if (out_bytes < need || scratch_bytes < blas_scratch_bytes(n_tris)) return RG_ERR_OUT_OF_MEMORY;
+    hipStream_t st = (hipStream_t)stream;
+    RgArena arena{(char *)scratch, scratch_bytes, 0};
+    float *pbox = arena.take<float>(6 * n_tris);
+    uint32_t *flags = arena.take<uint32_t>(8);
+    k_fill_u32<<<1, 64, 0, st>>>(flags, 0u, 1);
+    k_tri_boxes<<<rg_blocks(n_tris, kThreads), kThreads, 0, st>>>(verts, n_verts, idx, n_tris, pbox, flags);
+    RG_LAUNCH_CHECK();
+    uint32_t hflags = 0;
+    RG_HIP(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, st));
+    RG_HIP(hipStreamSynchronize(st));
+    if (hflags) return RG_ERR_INVALID_ARG;
+    char *base = (char *)out_buf;
+    RgLbvhOut lo;
+    rg_status r = rg_lbvh_build(pbox, n_tris, w, l, base + no, arena, st, &lo, false, nullptr, nullptr, nullptr,
+                                nullptr);
+    if (r != RG_OK) return r;
+    k_reorder_tris<<<rg_blocks(n_tris, kThreads), kThreads, 0, st>>>(
+        verts, idx, lo.ids, n_tris, prim_material, (RgTri *)(base + to), (uint16_t *)(base + mo),
+        (uint32_t *)(base + so));
+    k_blas_header<<<1, 1, 0, st>>>((RgBlasHdr *)base, (uint64_t)(base + no), (uint64_t)(base + to),
+                                   (uint64_t)(base + mo), (uint64_t)(base + so));
+    RG_LAUNCH_CHECK();
+    RG_HIP(hipStreamSynchronize(st));
+    out->buf = out_buf;
+    out->nodes_off = no;
+    out->tris_off = to;
+    out->mats_off = mo;
+    out->slots_off = so;
+    out->n_tris = n_tris;
+    out->n_nodes = lo.n_nodes;
+    out->width = w;
+    out->leaf_max = l;
+    out->depth = lo.depth;
+    out->has_mats = prim_material ? 1 : 0;
+    for (int k = 0; k < 3; ++k) {
+        out->lo[k] = lo.lo[k];
+        out->hi[k] = lo.hi[k];
+    }
+    return RG_OK;
+}
+
+rg_status rg_tlas_sizes(int64_t n_inst, const rg_build_opts *opts, rg_sizes *out) {
+    int32_t w, l;
+    if (!out || n_inst < 1 || n_inst > RG_MAX_TRIS || !opts_ok(opts, &w, &l)) return RG_ERR_INVALID_ARG;
+    uint64_t a, b, c;
+    out->bytes = tlas_out_bytes(n_inst, w, &a, &b, &c);
+    out->scratch_bytes = tlas_scratch_bytes(n_inst, 4096);
+    return RG_OK;
+}
+
+rg_status rg_build_tlas(const rg_blas *blas, int32_t n_blas, const float *xform, const uint32_t *blas_id,
+                        const uint32_t *inst_material, int64_t n_inst, const rg_build_opts *opts, void *out_buf,
+                        uint64_t out_bytes, void *scratch, uint64_t scratch_bytes, void *stream, rg_tlas *out) {
+    int32_t w, l;
+    if (!blas || !xform || !blas_id || !inst_material || !out_buf || !scratch || !out) return RG_ERR_INVALID_ARG;
+    if (n_blas < 1 || n_blas > 4096 || n_inst < 1 || n_inst > RG_MAX_TRIS) return RG_ERR_INVALID_ARG;
+    if (!opts_ok(opts, &w, &l)) return RG_ERR_INVALID_ARG;
+    int32_t max_depth = 0;
+    std::vector<BlasInfo> info((size_t)n_blas);
+    for (int32_t b = 0; b < n_blas; ++b) {
+        if (!blas[b].buf || blas[b].width != w) return RG_ERR_INVALID_ARG;
+        if (blas[b].depth > max_depth) max_depth = blas[b].depth;
+        for (int k = 0; k < 3; ++k) {
+            info[b].lo[k] = blas[b].lo[k];
+            info[b].hi[k] = blas[b].hi[k];
+        }
+        info[b].nodes = (uint64_t)((char *)blas[b].buf + blas[b].nodes_off);
+        info[b].tris = (uint64_t)((char *)blas[b].buf + blas[b].tris_off);
+        info[b].hdr = (uint64_t)blas[b].buf;
+    }
+    for (int64_t i = 0; i < n_inst; ++i) {
+        if (blas_id[i] >= (uint32_t)n_blas) return RG_ERR_INVALID_ARG;
+        const float *m = xform + 12 * i;
+        for (int k = 0; k < 12; ++k)
+            if (!std::isfinite(m[k])) return RG_ERR_INVALID_ARG;
+        double a = m[0], b = m[1], c = m[2], d = m[4], e = m[5], f = m[6], g = m[8], h = m[9], k = m[10];
+        double det = a * (e * k - f * h) - b * (d * k - f * g) + c * (d * h - e * g);
+        if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return RG_ERR_INVALID_ARG;
+    }
+    uint64_t no, io, ro;
+    uint64_t need = tlas_out_bytes(n_inst, w, &no, &io, &ro);
+    if (out_bytes < need || scratch_bytes < tlas_scratch_bytes(n_inst, n_blas)) return RG_ERR_OUT_OF_MEMORY;
+    hipStream_t st = (hipStream_t)stream;
+    RgArena arena{(char *)scratch, scratch_bytes, 0};
+    float *d_xf = arena.take<float>(12 * n_inst);
+    uint32_t *d_bid = arena.take<uint32_t>(n_inst);
+    uint32_t *d_mat = arena.take<uint32_t>(n_inst);
+    BlasInfo *d_info = arena.take<BlasInfo>(n_blas);
+    float *d_box = arena.take<float>(6 * n_inst);
+    RgInst *d_rec = arena.take<RgInst>(n_inst);
+    RG_HIP(hipMemcpyAsync(d_xf, xform, 48 * n_inst, hipMemcpyHostToDevice, st));
+    RG_HIP(hipMemcpyAsync(d_bid, blas_id, 4 * n_inst, hipMemcpyHostToDevice, st));
+    RG_HIP(hipMemcpyAsync(d_mat, inst_material, 4 * n_inst, hipMemcpyHostToDevice, st));
+    RG_HIP(hipMemcpyAsync(d_info, info.data(), sizeof(BlasInfo) * n_blas, hipMemcpyHostToDevice, st));
+    k_inst_setup<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(d_xf, d_bid, d_mat, d_info, n_inst, d_box, d_rec);
+    RG_LAUNCH_CHECK();
+    char *base = (char *)out_buf;
+    RgLbvhOut lo;
+    rg_status r = rg_lbvh_build(d_box, n_inst, w, 1, base + no, arena, st, &lo, false, nullptr, nullptr, nullptr,
+                                nullptr);
+    if (r != RG_OK) return r;
+    k_reorder_inst<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(d_rec, lo.ids, n_inst, (RgInst *)(base + io),
+                                                                      (uint32_t *)(base + ro));
+    RG_LAUNCH_CHECK();
+    RG_HIP(hipStreamSynchronize(st));
+    out->buf = out_buf;
+    out->nodes_off = no;
+    out->inst_off = io;
+    out->rec_off = ro;
+    out->n_inst = n_inst;
+    out->n_nodes = lo.n_nodes;
+    out->width = w;
+    out->depth = lo.depth;
+    out->max_blas_depth = max_depth;
+    out->reserved = 0;
+    for (int k = 0; k < 3; ++k) {
+        out->lo[k] = lo.lo[k];
+        out->hi[k] = lo.hi[k];
+    }
+    return RG_OK;
+}
+
+rg_status rg_lbvh_stages(const float *verts, int64_t n_verts, const uint32_t *idx, int64_t n_tris, uint64_t *keys,
+                         uint32_t *ids, int32_t *left, int32_t *right, float *boxes, void *scratch,
+                         uint64_t scratch_bytes, void *stream) {
+    if (!verts || !idx || !keys || !ids || !boxes || !scratch) return RG_ERR_INVALID_ARG;
+    if (n_tris > 1 && (!left || !right)) return RG_ERR_INVALID_ARG;
+    if (n_verts < 1 || n_tris < 1 || n_tris > RG_MAX_TRIS) return RG_ERR_INVALID_ARG;
+    if (scratch_bytes < blas_scratch_bytes(n_tris)) return RG_ERR_OUT_OF_MEMORY;
+    hipStream_t st = (hipStream_t)stream;
+    RgArena arena{(char *)scratch, scratch_bytes, 0};
+    float *pbox = arena.take<float>(6 * n_tris);
+    uint32_t *flags = arena.take<uint32_t>(8);
+    k_fill_u32<<<1, 64, 0, st>>>(flags, 0u, 1);
+    k_tri_boxes<<<rg_blocks(n_tris, kThreads), kThreads, 0, st>>>(verts, n_verts, idx, n_tris, pbox, flags);
+    RG_LAUNCH_CHECK();
+    uint32_t hflags = 0;
+    RG_HIP(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, st));
+    RG_HIP(hipStreamSynchronize(st));
+    if (hflags) return RG_ERR_INVALID_ARG;
+    RgLbvhOut lo;
+    rg_status r = rg_lbvh_build(pbox, n_tris, 4, 4, nullptr, arena, st, &lo, true, keys, left, right, boxes);
+    if (r != RG_OK) return r;
+    RG_HIP(hipMemcpyAsync(ids, lo.ids, 4 * n_tris, hipMemcpyDeviceToDevice, st));
+    RG_HIP(hipStreamSynchronize(st));
+    return RG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,689 @@
+// render.hip -- ray generation and the wavefront render loop.
+//
+// The paper's dispatch starts a ray-generation shader that casts the first
+// rays; closest-hit / miss shaders then may spawn further rays, each carrying
+// a payload, up to a recursion limit (section 1 and its footnote), and the
+// render system adds reflection, refraction and shadow casting for multiple
+// objects with material properties (section 2.1).  On gfx950 the recursion
+// runs breadth-first: one pass per depth over a queue of rays whose payload
+// is (pixel, throughput).  Shading adds the sky on a miss and the ambient
+// term on a diffuse hit to the pixel, queues a shadow ray carrying the
+// pending direct term, and queues mirror / glass children.  Children and
+// shadow rays are appended with one atomic per wave (ballot + popcount
+// ranks).  Pixel sums are 64-bit fixed point (2^32 per unit), so the image
+// is independent of the order in which waves append and add.
+#include <cmath>
+
+#include "trace_core.h"
+
+namespace {
+
+constexpr int kT = 256;
+constexpr float kPi = 3.14159265358979323846f;
+
+struct CamF {
+    float eye[3], f[3], r[3], u[3], th;
+};
+
+__device__ inline void normalize3(float v[3]) {
+    float l = sqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    v[0] = v[0] / l;
+    v[1] = v[1] / l;
+    v[2] = v[2] / l;
+}
+__device__ inline float dot3(const float a[3], const float b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+__device__ inline void cross3(float r[3], const float a[3], const float b[3]) {
+    float x = a[1] * b[2] - a[2] * b[1], y = a[2] * b[0] - a[0] * b[2], z = a[0] * b[1] - a[1] * b[0];
+    r[0] = x; r[1] = y; r[2] = z;
+}
+
+// Camera basis: f = normalize(target - eye), r = normalize(f x up), u = r x f.
+__device__ inline CamF camera_basis(const rg_camera &c) {
+    CamF k;
+    float f[3] = {c.target[0] - c.eye[0], c.target[1] - c.eye[1], c.target[2] - c.eye[2]};
+    normalize3(f);
+    float r[3];
+    cross3(r, f, c.up);
+    normalize3(r);
+    float u[3];
+    cross3(u, r, f);
+    for (int q = 0; q < 3; ++q) {
+        k.eye[q] = c.eye[q]; k.f[q] = f[q]; k.r[q] = r[q]; k.u[q] = u[q];
+    }
+    k.th = tanf(0.5f * c.vfov_deg * (kPi / 180.0f));
+    return k;
+}
+
+__device__ inline void camera_dir(const CamF &k, int W, int H, int64_t pixel, float d[3]) {
+    int64_t x = pixel % W, y = pixel / W;
+    float sx = (2.0f * ((float)x + 0.5f) / (float)W - 1.0f) * k.th * ((float)W / (float)H);
+    float sy = (1.0f - 2.0f * ((float)y + 0.5f) / (float)H) * k.th;
+    for (int q = 0; q < 3; ++q) d[q] = k.f[q] + sx * k.r[q] + sy * k.u[q];
+    normalize3(d);
+}
+
+__global__ void k_camera_rays(rg_camera cam, int W, int H, float *o0, float *o1, float *o2, float *d0, float *d1,
+                              float *d2, float *tmin, float *tmax, uint32_t *pix, float *b0, float *b1, float *b2,
+                              uint32_t *count) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int64_t n = (int64_t)W * H;
+    if (i == 0 && count) *count = (uint32_t)n;
+    if (i >= n) return;
+    CamF k = camera_basis(cam);
+    float d[3];
+    camera_dir(k, W, H, i, d);
+    o0[i] = k.eye[0]; o1[i] = k.eye[1]; o2[i] = k.eye[2];
+    d0[i] = d[0]; d1[i] = d[1]; d2[i] = d[2];
+    tmin[i] = 0.0f;
+    tmax[i] = INFINITY;
+    if (pix) {
+        pix[i] = (uint32_t)i;
+        b0[i] = 1.0f; b1[i] = 1.0f; b2[i] = 1.0f;
+    }
+}
+
+// ------------------------------------------------------ hit geometry
+struct HitGeom {
+    float p[3], ng[3], nf[3], dn[3];
+    uint32_t mat;
+};
+
+__device__ inline void hit_geometry(const RgInst *recs, uint32_t rec_idx, uint32_t slot, const float o[3],
+                                    const float d[3], float t, HitGeom &g) {
+    const RgInst &R = recs[rec_idx];
+    const RgTri tri = reinterpret_cast<const RgTri *>(R.tris)[slot];
+    for (int q = 0; q < 3; ++q) g.p[q] = o[q] + t * d[q];
+    float e1[3] = {tri.v[3] - tri.v[0], tri.v[4] - tri.v[1], tri.v[5] - tri.v[2]};
+    float e2[3] = {tri.v[6] - tri.v[0], tri.v[7] - tri.v[1], tri.v[8] - tri.v[2]};
+    float no[3];
+    cross3(no, e1, e2);
+    // normals map with the transpose of the world->object matrix
+    float n[3];
+    for (int c = 0; c < 3; ++c) n[c] = R.inv[c] * no[0] + R.inv[3 + c] * no[1] + R.inv[6 + c] * no[2];
+    normalize3(n);
+    for (int q = 0; q < 3; ++q) {
+        g.ng[q] = n[q];
+        g.dn[q] = d[q];
+    }
+    normalize3(g.dn);
+    float s = dot3(g.ng, g.dn) < 0.0f ? 1.0f : -1.0f;
+    for (int q = 0; q < 3; ++q) g.nf[q] = s * g.ng[q];
+    if (R.mat != RG_PER_PRIM) {
+        g.mat = R.mat;
+    } else {
+        const RgBlasHdr *h = reinterpret_cast<const RgBlasHdr *>(R.hdr);
+        g.mat = reinterpret_cast<const uint16_t *>(h->mats)[slot];
+    }
+}
+
+__device__ inline float offset_eps(const float p[3]) {
+    float m = fmaxf(fmaxf(fabsf(p[0]), fabsf(p[1])), fabsf(p[2]));
+    return 1e-4f * fmaxf(1.0f, m);
+}
+
+// ------------------------------------------------------ fixed point
+__device__ inline void accum_add(unsigned long long *acc, uint32_t pixel, const float v[3]) {
+    for (int q = 0; q < 3; ++q) {
+        if (!(v[q] > 0.0f)) continue;
+        unsigned long long x = (unsigned long long)llrint((double)v[q] * 4294967296.0);
+        atomicAdd(acc + 3 * (uint64_t)pixel + q, x);
+    }
+}
+
+// --------------------------------------------------------- queues
+struct Queue {
+    float *ray[8];
+    uint32_t *pix;
+    float *beta[3];
+};
+struct ShadowQ {
+    float *ray[8];
+    uint32_t *pix;
+    float *pend[3];
+    uint8_t *occ;
+};
+
+__device__ inline void put_ray(float *const ray[8], uint32_t j, const float o[3], const float d[3], float tmin,
+                               float tmax) {
+    ray[0][j] = o[0]; ray[1][j] = o[1]; ray[2][j] = o[2];
+    ray[3][j] = d[0]; ray[4][j] = d[1]; ray[5][j] = d[2];
+    ray[6][j] = tmin; ray[7][j] = tmax;
+}
+
+// Appends `cnt` (0..2) entries per lane with one atomic per wave; returns
+// this lane's first slot.
+__device__ inline uint32_t wave_append(uint32_t *counter, uint32_t cnt) {
+    uint64_t b1 = __ballot(cnt >= 1u), b2 = __ballot(cnt >= 2u);
+    int lane = threadIdx.x & 63;
+    uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    uint32_t before = (uint32_t)(__popcll(b1 & lt) + __popcll(b2 & lt));
+    uint32_t total = (uint32_t)(__popcll(b1) + __popcll(b2));
+    uint64_t active = __ballot(1);
+    int leader = __ffsll((long long)active) - 1;
+    uint32_t base = 0;
+    if (lane == leader && total > 0) base = atomicAdd(counter, total);
+    base = __shfl(base, leader, 64);
+    return base + before;
+}
+
+struct ShadeArgs {
+    Queue in;
+    const uint32_t *count_in;
+    const float *hit_t;
+    const uint32_t *hit_rec, *hit_slot;
+    const RgInst *recs;
+    const RgMat *mats;
+    int32_t n_mats;
+    rg_light light;
+    int32_t depth, max_depth;
+    unsigned long long *acc;
+    Queue out;
+    uint32_t *count_out;
+    ShadowQ sq;
+    uint32_t *count_sq;
+    int64_t cap;
+};
+
+__global__ void __launch_bounds__(kT) k_shade(ShadeArgs a) {
+    int64_t i = blockIdx.x * (int64_t)kT + threadIdx.x;
+    int64_t n = *a.count_in;
+    bool active = i < n;
+    uint32_t n_child = 0, n_shadow = 0;
+    float co[2][3], cd[2][3], cb[2][3];
+    float so[3], sd[3], sp[3];
+    uint32_t pixel = 0;
+    if (active) {
+        pixel = a.in.pix[i];
+        float beta[3] = {a.in.beta[0][i], a.in.beta[1][i], a.in.beta[2][i]};
+        float o[3] = {a.in.ray[0][i], a.in.ray[1][i], a.in.ray[2][i]};
+        float d[3] = {a.in.ray[3][i], a.in.ray[4][i], a.in.ray[5][i]};
+        uint32_t rec = a.hit_rec[i];
+        if (rec == RG_MISS) {
+            float dn[3] = {d[0], d[1], d[2]};
+            normalize3(dn);
+            float s = 0.5f * (dn[1] + 1.0f);
+            float sky[3] = {(1.0f - s) + s * 0.5f, (1.0f - s) + s * 0.7f, (1.0f - s) + s * 1.0f};
+            float v[3] = {beta[0] * sky[0], beta[1] * sky[1], beta[2] * sky[2]};
+            accum_add(a.acc, pixel, v);
+        } else {
+            HitGeom g;
+            hit_geometry(a.recs, rec, a.hit_slot[i], o, d, a.hit_t[i], g);
+            uint32_t mid = g.mat < (uint32_t)a.n_mats ? g.mat : (uint32_t)(a.n_mats - 1);
+            const RgMat M = a.mats[mid];
+            float eps = offset_eps(g.p);
+            if (M.type == 0) {
+                float amb[3] = {beta[0] * M.rgb[0] * a.light.ambient, beta[1] * M.rgb[1] * a.light.ambient,
+                                beta[2] * M.rgb[2] * a.light.ambient};
+                accum_add(a.acc, pixel, amb);
+                float l[3] = {a.light.pos[0] - g.p[0], a.light.pos[1] - g.p[1], a.light.pos[2] - g.p[2]};
+                normalize3(l);
+                float c = dot3(g.nf, l);
+                if (c > 0.0f) {
+                    n_shadow = 1;
+                    for (int q = 0; q < 3; ++q) {
+                        so[q] = g.p[q] + eps * g.nf[q];
+                        sd[q] = a.light.pos[q] - so[q];
+                        sp[q] = beta[q] * M.rgb[q] * a.light.intensity[q] * c;
+                    }
+                }
+            } else if (a.depth < a.max_depth) {
+                float dnf = dot3(g.dn, g.nf);
+                for (int q = 0; q < 3; ++q) {
+                    co[0][q] = g.p[q] + eps * g.nf[q];
+                    cd[0][q] = g.dn[q] - 2.0f * dnf * g.nf[q];
+                }
+                if (M.type == 1) {
+                    n_child = 1;
+                    for (int q = 0; q < 3; ++q) cb[0][q] = beta[q] * M.rgb[q];
+                } else {
+                    bool entering = dot3(g.dn, g.ng) < 0.0f;
+                    float ior = M.ior;
+                    float eta = entering ? 1.0f / ior : ior;
+                    float cosi = -dnf;
+                    float kappa = 1.0f - eta * eta * (1.0f - cosi * cosi);
+                    if (kappa < 0.0f) {
+                        n_child = 1;
+                        for (int q = 0; q < 3; ++q) cb[0][q] = beta[q];
+                    } else {
+                        float sk = sqrtf(kappa);
+                        float r0 = (ior - 1.0f) / (ior + 1.0f);
+                        r0 = r0 * r0;
+                        float cc = entering ? cosi : sk;
+                        float om = 1.0f - cc;
+                        float F = r0 + (1.0f - r0) * om * om * om * om * om;
+                        n_child = 2;
+                        for (int q = 0; q < 3; ++q) {
+                            cb[0][q] = beta[q] * F;
+                            co[1][q] = g.p[q] - eps * g.nf[q];
+                            cd[1][q] = eta * g.dn[q] + (eta * cosi - sk) * g.nf[q];
+                            cb[1][q] = beta[q] * (1.0f - F);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    uint32_t cs = wave_append(a.count_out, n_child);
+    uint32_t ss = wave_append(a.count_sq, n_shadow);
+    for (uint32_t c = 0; c < n_child; ++c) {
+        uint32_t j = cs + c;
+        if ((int64_t)j >= a.cap) break;  // the queue holds n 2^D entries: never reached
+        put_ray(a.out.ray, j, co[c], cd[c], 0.0f, INFINITY);
+        a.out.pix[j] = pixel;
+        a.out.beta[0][j] = cb[c][0];
+        a.out.beta[1][j] = cb[c][1];
+        a.out.beta[2][j] = cb[c][2];
+    }
+    if (n_shadow && (int64_t)ss < a.cap) {
+        put_ray(a.sq.ray, ss, so, sd, 0.0f, 1.0f - 1e-4f);
+        a.sq.pix[ss] = pixel;
+        a.sq.pend[0][ss] = sp[0];
+        a.sq.pend[1][ss] = sp[1];
+        a.sq.pend[2][ss] = sp[2];
+    }
+}
+
+__global__ void k_shadow_resolve(ShadowQ sq, const uint32_t *count, unsigned long long *acc) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)*count) return;
+    if (sq.occ[i]) return;
+    float v[3] = {sq.pend[0][i], sq.pend[1][i], sq.pend[2][i]};
+    accum_add(acc, sq.pix[i], v);
+}
+
+__global__ void k_resolve(const unsigned long long *acc, int64_t n, float *image) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= 3 * n) return;
+    image[i] = (float)((double)acc[i] * (1.0 / 4294967296.0));
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+__global__ void k_stat_add(unsigned long long *stat, const uint32_t *count) { *stat += *count; }
+
+// -------------------------------------------------- ambient occlusion
+__device__ inline uint64_t splitmix_out(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Cosine-weighted direction around unit n (Malley's method) in the basis of
+// Duff et al. 2017; uniforms from SplitMix64 started at seed + 2 key gamma.
+__device__ inline void ao_dir(const float n[3], uint64_t seed, uint64_t key, float out[3]) {
+    const uint64_t g = 0x9E3779B97F4A7C15ull;
+    uint64_t s = seed + 2ull * key * g;
+    float u1 = (float)(splitmix_out(s + g) >> 40) * (1.0f / 16777216.0f);
+    float u2 = (float)(splitmix_out(s + 2ull * g) >> 40) * (1.0f / 16777216.0f);
+    float sgn = n[2] >= 0.0f ? 1.0f : -1.0f;
+    float a = -1.0f / (sgn + n[2]);
+    float b = n[0] * n[1] * a;
+    float b1[3] = {1.0f + sgn * n[0] * n[0] * a, sgn * b, -sgn * n[0]};
+    float b2[3] = {b, sgn + n[1] * n[1] * a, -n[1]};
+    float r = sqrtf(u1);
+    float sp, cp;
+    sincospif(2.0f * u2, &sp, &cp);
+    float x = r * cp, y = r * sp, z = sqrtf(1.0f - u1);
+    for (int q = 0; q < 3; ++q) out[q] = x * b1[q] + y * b2[q] + z * n[q];
+}
+
+struct AoArgs {
+    const float *ray[8];
+    int64_t n;
+    const uint32_t *hit_a, *hit_b;  // (rec, slot), or (inst, prim) input ids if map
+    const float *hit_t;
+    const uint32_t *rec_of;         // tlas: record of an input instance (map only)
+    const RgInst *recs;
+    uint64_t seed;
+    float tmax;
+    float *out[8];
+    uint32_t *src;
+    uint32_t *count;
+    uint32_t *block_off;            // per-block offsets (scanned)
+    bool map;
+};
+
+__device__ inline bool ao_hit(const AoArgs &a, int64_t i) { return i < a.n && a.hit_a[i] != RG_MISS; }
+
+__global__ void k_ao_count(AoArgs a) {
+    int64_t i = blockIdx.x * (int64_t)kT + threadIdx.x;
+    uint64_t b = __ballot(ao_hit(a, i));
+    __shared__ uint32_t wc[kT / 64];
+    if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = (uint32_t)__popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int w = 0; w < kT / 64; ++w) s += wc[w];
+        a.block_off[blockIdx.x] = 8u * s;
+    }
+}
+
+__global__ void k_ao_emit(AoArgs a, int nblocks, const uint32_t *block_cnt_last) {
+    int64_t i = blockIdx.x * (int64_t)kT + threadIdx.x;
+    bool h = ao_hit(a, i);
+    uint64_t b = __ballot(h);
+    __shared__ uint32_t wc[kT / 64];
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) wc[w] = (uint32_t)__popcll(b);
+    __syncthreads();
+    uint32_t before = 0, tot = 0;
+    for (int q = 0; q < kT / 64; ++q) {
+        if (q < w) before += wc[q];
+        tot += wc[q];
+    }
+    uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    before += (uint32_t)__popcll(b & lt);
+    uint32_t base = a.block_off[blockIdx.x];
+    if (blockIdx.x == (unsigned)(nblocks - 1) && threadIdx.x == 0) *a.count = base + 8u * tot;
+    if (!h) return;
+    uint32_t rec = a.hit_a[i], slot = a.hit_b[i];
+    if (a.map) {
+        rec = a.rec_of[rec];
+        const RgBlasHdr *hd = reinterpret_cast<const RgBlasHdr *>(a.recs[rec].hdr);
+        slot = reinterpret_cast<const uint32_t *>(hd->slots)[slot];
+    }
+    float o[3] = {a.ray[0][i], a.ray[1][i], a.ray[2][i]};
+    float d[3] = {a.ray[3][i], a.ray[4][i], a.ray[5][i]};
+    HitGeom g;
+    hit_geometry(a.recs, rec, slot, o, d, a.hit_t[i], g);
+    float eps = offset_eps(g.p);
+    float org[3] = {g.p[0] + eps * g.nf[0], g.p[1] + eps * g.nf[1], g.p[2] + eps * g.nf[2]};
+    uint32_t j0 = base + 8u * before;
+    for (int k = 0; k < 8; ++k) {
+        float dir[3];
+        ao_dir(g.nf, a.seed, (uint64_t)i * 8ull + (uint64_t)k, dir);
+        put_ray(a.out, j0 + k, org, dir, 0.0f, a.tmax);
+        a.src[j0 + k] = (uint32_t)(i * 8 + k);
+    }
+}
+
+__global__ void k_ao_accum(const uint8_t *occ, const uint32_t *src, const uint32_t *count,
+                           unsigned long long *acc) {
+    int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= (int64_t)*count) return;
+    if (occ[j]) atomicAdd(acc + 3 * (uint64_t)(src[j] >> 3), 1ull);
+}
+
+__global__ void k_ao_resolve(const unsigned long long *acc, const uint32_t *hit_rec, int64_t n, float *image) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float v = 1.0f;
+    if (hit_rec[i] != RG_MISS) v = 1.0f - (float)acc[3 * i] * 0.125f;
+    image[3 * i] = v;
+    image[3 * i + 1] = v;
+    image[3 * i + 2] = v;
+}
+
+rg_status ao_generate(AoArgs a, hipStream_t st) {
+    int nb = (int)rg_blocks(a.n, kT);
+    k_ao_count<<<nb, kT, 0, st>>>(a);
+    RG_LAUNCH_CHECK();
+    rg_status r = rg_scan_excl_u32(a.block_off, nb, st);
+    if (r != RG_OK) return r;
+    k_ao_emit<<<nb, kT, 0, st>>>(a, nb, nullptr);
+    RG_LAUNCH_CHECK();
+    return RG_OK;
+}
+
+// ------------------------------------------------------ scratch layout
+struct RenderBufs {
+    unsigned long long *acc, *stat;
+    Queue q[2];
+    ShadowQ sq;
+    float *hit_t;
+    uint32_t *hit_rec, *hit_slot, *counts;
+    RgMat *mats;
+    // ambient occlusion
+    float *ao_ray[8];
+    uint32_t *ao_src, *ao_blk;
+    uint8_t *ao_occ;
+};
+
+int64_t queue_cap(int64_t n, int32_t D, int32_t mode) { return mode == 1 ? n : n << D; }
+
+bool carve(RgArena &A, int64_t n, int32_t D, int32_t mode, RenderBufs &b) {
+    int64_t cap = queue_cap(n, D, mode);
+    b.acc = A.take<unsigned long long>(3 * n);
+    b.stat = A.take<unsigned long long>(4);
+    b.counts = A.take<uint32_t>(8);
+    b.mats = A.take<RgMat>(256);
+    b.hit_t = A.take<float>(cap);
+    b.hit_rec = A.take<uint32_t>(cap);
+    b.hit_slot = A.take<uint32_t>(cap);
+    int nq = mode == 1 ? 1 : 2;
+    for (int k = 0; k < nq; ++k) {
+        for (int c = 0; c < 8; ++c) b.q[k].ray[c] = A.take<float>(cap);
+        b.q[k].pix = A.take<uint32_t>(cap);
+        for (int c = 0; c < 3; ++c) b.q[k].beta[c] = A.take<float>(cap);
+    }
+    if (mode == 1) {
+        b.q[1] = b.q[0];
+        for (int c = 0; c < 8; ++c) b.ao_ray[c] = A.take<float>(8 * n);
+        b.ao_src = A.take<uint32_t>(8 * n);
+        b.ao_blk = A.take<uint32_t>(rg_blocks(n, kT));
+        b.ao_occ = A.take<uint8_t>(8 * n);
+    } else {
+        for (int c = 0; c < 8; ++c) b.sq.ray[c] = A.take<float>(cap);
+        b.sq.pix = A.take<uint32_t>(cap);
+        for (int c = 0; c < 3; ++c) b.sq.pend[c] = A.take<float>(cap);
+        b.sq.occ = A.take<uint8_t>(cap);
+    }
+    return !A.overflow();
+}
+
+bool tlas_valid(const rg_tlas *t) {
+    return t && t->buf && t->n_inst >= 1 && (t->width == 2 || t->width == 4 || t->width == 8);
+}
+
+RgTraceArgs trace_args(const rg_tlas *t) {
+    RgTraceArgs a = {};
+    a.nodes = (const char *)t->buf + t->nodes_off;
+    a.recs = (const RgInst *)((const char *)t->buf + t->inst_off);
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+rg_status rg_camera_rays(const rg_camera *cam, int32_t width, int32_t height, float *const rays[8], void *stream) {
+    if (!cam || !rays || width < 1 || height < 1 || (int64_t)width * height > (1ll << 31)) return RG_ERR_INVALID_ARG;
+    for (int k = 0; k < 8; ++k)
+        if (!rays[k]) return RG_ERR_INVALID_ARG;
+    int64_t n = (int64_t)width * height;
+    k_camera_rays<<<rg_blocks(n, kT), kT, 0, (hipStream_t)stream>>>(
+        *cam, width, height, rays[0], rays[1], rays[2], rays[3], rays[4], rays[5], rays[6], rays[7], nullptr, nullptr,
+        nullptr, nullptr, nullptr);
+    RG_LAUNCH_CHECK();
+    return RG_OK;
+}
+
+rg_status rg_ao_rays_scratch(int64_t n, uint64_t *scratch_bytes) {
+    if (n < 0 || !scratch_bytes) return RG_ERR_INVALID_ARG;
+    *scratch_bytes = ((uint64_t)rg_blocks(n, kT) * 4u + 255u) & ~uint64_t(255);
+    return RG_OK;
+}
+
+rg_status rg_ao_rays(const rg_tlas *tlas, rg_rays rays, int64_t n, const uint32_t *hit_inst, const uint32_t *hit_prim,
+                     const float *hit_t, uint64_t seed, float ao_tmax, float *const out_rays[8], uint32_t *out_src,
+                     uint32_t *out_count, void *scratch, uint64_t scratch_bytes, void *stream) {
+    if (!tlas_valid(tlas) || n < 1 || n > (1ll << 28) || !hit_inst || !hit_prim || !hit_t || !out_rays || !out_src ||
+        !out_count || !scratch)
+        return RG_ERR_INVALID_ARG;
+    if (!rays.ox || !rays.oy || !rays.oz || !rays.dx || !rays.dy || !rays.dz) return RG_ERR_INVALID_ARG;
+    for (int k = 0; k < 8; ++k)
+        if (!out_rays[k]) return RG_ERR_INVALID_ARG;
+    uint64_t need;
+    rg_ao_rays_scratch(n, &need);
+    if (scratch_bytes < need) return RG_ERR_OUT_OF_MEMORY;
+    AoArgs a = {};
+    a.ray[0] = rays.ox; a.ray[1] = rays.oy; a.ray[2] = rays.oz;
+    a.ray[3] = rays.dx; a.ray[4] = rays.dy; a.ray[5] = rays.dz;
+    a.n = n;
+    a.hit_a = hit_inst;
+    a.hit_b = hit_prim;
+    a.hit_t = hit_t;
+    a.rec_of = (const uint32_t *)((const char *)tlas->buf + tlas->rec_off);
+    a.recs = (const RgInst *)((const char *)tlas->buf + tlas->inst_off);
+    a.seed = seed;
+    a.tmax = ao_tmax;
+    for (int k = 0; k < 8; ++k) a.out[k] = out_rays[k];
+    a.src = out_src;
+    a.count = out_count;
+    a.block_off = (uint32_t *)scratch;
+    a.map = true;
+    return ao_generate(a, (hipStream_t)stream);
+}
+
+rg_status rg_render_sizes(int32_t width, int32_t height, int32_t max_depth, int32_t mode, uint64_t *scratch_bytes) {
+    if (!scratch_bytes || width < 1 || height < 1 || max_depth < 0 || max_depth > RG_MAX_DEPTH ||
+        (mode != 0 && mode != 1))
+        return RG_ERR_INVALID_ARG;
+    int64_t n = (int64_t)width * height;
+    if (queue_cap(n, max_depth, mode) > (1ll << 31)) return RG_ERR_UNSUPPORTED;
+    RgArena A{nullptr, 0, 0};
+    RenderBufs b;
+    carve(A, n, max_depth, mode, b);
+    *scratch_bytes = A.used;
+    return RG_OK;
+}
+
+rg_status rg_render(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats, const rg_camera *cam,
+                    const rg_light *light, int32_t width, int32_t height, int32_t max_depth, int32_t mode,
+                    uint64_t seed, float *image, void *scratch, uint64_t scratch_bytes, void *stream,
+                    rg_render_stats *stats) {
+    if (!tlas_valid(tlas) || !mats || n_mats < 1 || n_mats > 256 || !cam || !light || !image || !scratch)
+        return RG_ERR_INVALID_ARG;
+    uint64_t need = 0;
+    rg_status r = rg_render_sizes(width, height, max_depth, mode, &need);
+    if (r != RG_OK) return r;
+    if (scratch_bytes < need) return RG_ERR_OUT_OF_MEMORY;
+    if (!rg_trace_depth_ok(tlas)) return RG_ERR_UNSUPPORTED;
+    hipStream_t st = (hipStream_t)stream;
+    int64_t n = (int64_t)width * height;
+    RgArena A{(char *)scratch, scratch_bytes, 0};
+    RenderBufs b;
+    if (!carve(A, n, max_depth, mode, b)) return RG_ERR_OUT_OF_MEMORY;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (stats) {
+        RG_HIP(hipEventCreate(&e0));
+        RG_HIP(hipEventCreate(&e1));
+        RG_HIP(hipEventRecord(e0, st));
+    }
+    RG_HIP(hipMemcpyAsync(b.mats, mats, sizeof(RgMat) * n_mats, hipMemcpyHostToDevice, st));
+    k_zero_u64<<<rg_blocks(3 * n, kT), kT, 0, st>>>(b.acc, 3 * n);
+    k_zero_u64<<<1, kT, 0, st>>>(b.stat, 4);
+    k_fill_u32<<<1, kT, 0, st>>>(b.counts, 0u, 8);
+    Queue &q0 = b.q[0];
+    k_camera_rays<<<rg_blocks(n, kT), kT, 0, st>>>(*cam, width, height, q0.ray[0], q0.ray[1], q0.ray[2], q0.ray[3],
+                                                   q0.ray[4], q0.ray[5], q0.ray[6], q0.ray[7], q0.pix, q0.beta[0],
+                                                   q0.beta[1], q0.beta[2], b.counts + 0);
+    RG_LAUNCH_CHECK();
+    RgTraceArgs ta = trace_args(tlas);
+    if (mode == 1) {
+        for (int c = 0; c < 8; ++c) ta.ray[c] = q0.ray[c];
+        ta.n = n;
+        ta.t = b.hit_t;
+        ta.inst = b.hit_rec;
+        ta.prim = b.hit_slot;
+        r = rg_trace_launch(tlas->width, false, rgt::kRender, ta, st);
+        if (r != RG_OK) return r;
+        AoArgs a = {};
+        for (int c = 0; c < 6; ++c) a.ray[c] = q0.ray[c];
+        a.n = n;
+        a.hit_a = b.hit_rec;
+        a.hit_b = b.hit_slot;
+        a.hit_t = b.hit_t;
+        a.recs = ta.recs;
+        a.seed = seed;
+        a.tmax = 5.0f;
+        for (int c = 0; c < 8; ++c) a.out[c] = b.ao_ray[c];
+        a.src = b.ao_src;
+        a.count = b.counts + 2;
+        a.block_off = b.ao_blk;
+        a.map = false;
+        r = ao_generate(a, st);
+        if (r != RG_OK) return r;
+        RgTraceArgs tb = trace_args(tlas);
+        for (int c = 0; c < 8; ++c) tb.ray[c] = b.ao_ray[c];
+        tb.n = 8 * n;
+        tb.count = b.counts + 2;
+        tb.occluded = b.ao_occ;
+        r = rg_trace_launch(tlas->width, true, rgt::kRender, tb, st);
+        if (r != RG_OK) return r;
+        k_ao_accum<<<rg_blocks(8 * n, kT), kT, 0, st>>>(b.ao_occ, b.ao_src, b.counts + 2, b.acc);
+        k_ao_resolve<<<rg_blocks(n, kT), kT, 0, st>>>(b.acc, b.hit_rec, n, image);
+        RG_LAUNCH_CHECK();
+        k_stat_add<<<1, 1, 0, st>>>(b.stat, b.counts + 0);
+        k_stat_add<<<1, 1, 0, st>>>(b.stat + 1, b.counts + 2);
+    } else {
+        for (int k = 0; k <= max_depth; ++k) {
+            Queue &qin = b.q[k & 1], &qout = b.q[(k + 1) & 1];
+            uint32_t *cin = b.counts + (k & 1), *cout = b.counts + ((k + 1) & 1), *csq = b.counts + 2;
+            int64_t cap_k = n << k;
+            RgTraceArgs tc = ta;
+            for (int c = 0; c < 8; ++c) tc.ray[c] = qin.ray[c];
+            tc.n = cap_k;
+            tc.count = cin;
+            tc.t = b.hit_t;
+            tc.inst = b.hit_rec;
+            tc.prim = b.hit_slot;
+            r = rg_trace_launch(tlas->width, false, rgt::kRender, tc, st);
+            if (r != RG_OK) return r;
+            k_stat_add<<<1, 1, 0, st>>>(b.stat, cin);
+            k_fill_u32<<<1, 64, 0, st>>>(cout, 0u, 1);
+            k_fill_u32<<<1, 64, 0, st>>>(csq, 0u, 1);
+            ShadeArgs sa;
+            sa.in = qin;
+            sa.count_in = cin;
+            sa.hit_t = b.hit_t;
+            sa.hit_rec = b.hit_rec;
+            sa.hit_slot = b.hit_slot;
+            sa.recs = ta.recs;
+            sa.mats = b.mats;
+            sa.n_mats = n_mats;
+            sa.light = *light;
+            sa.depth = k;
+            sa.max_depth = max_depth;
+            sa.acc = b.acc;
+            sa.out = qout;
+            sa.count_out = cout;
+            sa.sq = b.sq;
+            sa.count_sq = csq;
+            sa.cap = queue_cap(n, max_depth, mode);
+            k_shade<<<rg_blocks(cap_k, kT), kT, 0, st>>>(sa);
+            RG_LAUNCH_CHECK();
+            RgTraceArgs ts = ta;
+            for (int c = 0; c < 8; ++c) ts.ray[c] = b.sq.ray[c];
+            ts.n = cap_k;
+            ts.count = csq;
+            ts.occluded = b.sq.occ;
+            r = rg_trace_launch(tlas->width, true, rgt::kRender, ts, st);
+            if (r != RG_OK) return r;
+            k_stat_add<<<1, 1, 0, st>>>(b.stat + 1, csq);
+            k_shadow_resolve<<<rg_blocks(cap_k, kT), kT, 0, st>>>(b.sq, csq, b.acc);
+            RG_LAUNCH_CHECK();
+        }
+        k_resolve<<<rg_blocks(3 * n, kT), kT, 0, st>>>(b.acc, n, image);
+        RG_LAUNCH_CHECK();
+    }
+    if (stats) {
+        RG_HIP(hipEventRecord(e1, st));
+        unsigned long long hs[2] = {0, 0};
+        RG_HIP(hipMemcpyAsync(hs, b.stat, 16, hipMemcpyDeviceToHost, st));
+        RG_HIP(hipStreamSynchronize(st));
+        float ms = 0.0f;
+        RG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        stats->rays_traced = hs[0];
+        stats->shadow_rays = hs[1];
+        stats->ms_total = ms;
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+    }
+    return RG_OK;
+}
+
+}  // extern "C"

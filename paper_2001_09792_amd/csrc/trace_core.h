@@ -1,0 +1,353 @@
+// trace_core.h -- the per-ray traversal of the two-level hierarchy, shared by
+// the trace entry points and the render passes (both in trace.hip / render.hip).
+//
+// Per ray: test the W child boxes of the current node (robust slab test: the
+// far distance is widened by 2*gamma_3, after Ize 2013, so rounding never
+// drops a box the ray touches), continue with the nearest hit child and push
+// the others far-to-near.  At a top-level leaf the ray is moved into the
+// instance's object space: the ray is mapped with the world->object
+// matrix in double (t is unchanged by the map), and its origin is slid to
+// where it enters the bottom level's root box, so float32 coordinates stay
+// box-sized; the slide t0 is added back to every t.  At a bottom-level leaf each
+// triangle is tested with the watertight ray/triangle test of Woop, Benthin &
+// Wald (JCGT 2013): vertices are sheared into ray space and three 2-D edge
+// functions decide inside/outside; evaluated without fused multiply-add, a
+// shared edge gives exactly negated values in its two triangles, so no ray
+// passes between them.  Edges and vertices count as inside (two-sided,
+// closed), a zero determinant (ray parallel to the plane) is a miss.
+// Closest hit keeps the least t (ties: lowest instance, then primitive);
+// any hit stops at the first triangle in [tmin, tmax].
+#pragma once
+
+#include "rg_internal.h"
+
+namespace rgt {
+
+constexpr int kThreads = 256;   // threads per workgroup of the trace kernels
+constexpr int kLdsStack = 16;   // stack entries per lane kept in LDS
+constexpr int kPrivStack = 96;  // further entries per lane in private memory
+constexpr int kStackCap = kLdsStack + kPrivStack;
+constexpr uint32_t kSentinel = 0xFFFFFFFEu;
+constexpr uint32_t kMaxSteps = 1u << 22;  // loop bound: far above any traversal of a valid hierarchy
+constexpr float kFarWiden = 2.0f * (3.0f * 5.9604645e-8f) / (1.0f - 3.0f * 5.9604645e-8f);  // 2 gamma_3
+
+enum Mode { kClosest = 0, kCounts = 1, kRender = 2 };
+
+struct Ray {
+    float o[3], d[3], tmin, tmax;
+};
+
+// Result of one traversal.  For kRender `inst` is the top-level record index
+// and `prim` the bottom-level triangle slot (leaf order); otherwise they are
+// the input indices.
+struct Hit {
+    float t, u, v;
+    uint32_t inst, prim;
+    uint32_t n_nodes, n_tris, n_inst;  // visit counts (kCounts)
+};
+
+__device__ inline float safe_rcp(float x) {
+    // zero components get a huge finite reciprocal of the same sign, so that
+    // (lo - o) * inv never evaluates 0 * inf
+    const float tiny = 1e-30f;
+    float y = fabsf(x) < tiny ? copysignf(tiny, x) : x;
+    return 1.0f / y;
+}
+
+// Ray-space shear constants (Woop, Benthin & Wald 2013).
+struct Shear {
+    int kx, ky, kz;
+    float sx, sy, sz;
+};
+
+__device__ inline Shear make_shear(const float d[3]) {
+    Shear s;
+    float ax = fabsf(d[0]), ay = fabsf(d[1]), az = fabsf(d[2]);
+    s.kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+    s.kx = s.kz == 2 ? 0 : s.kz + 1;
+    s.ky = s.kx == 2 ? 0 : s.kx + 1;
+    if (d[s.kz] < 0.0f) {
+        int t = s.kx;
+        s.kx = s.ky;
+        s.ky = t;
+    }
+    float dz = d[s.kz];
+    s.sx = d[s.kx] / dz;
+    s.sy = d[s.ky] / dz;
+    s.sz = 1.0f / dz;
+    return s;
+}
+
+__device__ inline float comp(const float v[3], int k) { return k == 0 ? v[0] : (k == 1 ? v[1] : v[2]); }
+
+// Watertight ray/triangle test in ray space.  Returns true on a hit and writes
+// t (in the ray's own frame), u (weight of v1), v (weight of v2).
+__device__ inline bool tri_test(const float *__restrict__ tv, const float o[3], const Shear &s, float *t_out,
+                                float *u_out, float *v_out) {
+#pragma clang fp contract(off)
+    float a[3] = {tv[0] - o[0], tv[1] - o[1], tv[2] - o[2]};
+    float b[3] = {tv[3] - o[0], tv[4] - o[1], tv[5] - o[2]};
+    float c[3] = {tv[6] - o[0], tv[7] - o[1], tv[8] - o[2]};
+    float az = comp(a, s.kz), bz = comp(b, s.kz), cz = comp(c, s.kz);
+    float Ax = comp(a, s.kx) - s.sx * az, Ay = comp(a, s.ky) - s.sy * az;
+    float Bx = comp(b, s.kx) - s.sx * bz, By = comp(b, s.ky) - s.sy * bz;
+    float Cx = comp(c, s.kx) - s.sx * cz, Cy = comp(c, s.ky) - s.sy * cz;
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    bool neg = (U < 0.0f) || (V < 0.0f) || (W < 0.0f);
+    bool pos = (U > 0.0f) || (V > 0.0f) || (W > 0.0f);
+    if (neg && pos) return false;
+    float det = U + V + W;
+    if (det == 0.0f) return false;
+    float T = U * (s.sz * az) + V * (s.sz * bz) + W * (s.sz * cz);
+    *t_out = T / det;
+    *u_out = V / det;
+    *v_out = W / det;
+    return true;
+}
+
+// Stack with the first kLdsStack entries in LDS (lane-interleaved, so the
+// 64 lanes of a wave hit 64 different banks) and the rest in private memory.
+struct Stack {
+    uint32_t *lds;  // base of this lane's column: lds[e * kThreads]
+    uint32_t priv[kPrivStack];
+    int sp;
+    __device__ inline void push(uint32_t v) {
+        if (sp < kLdsStack) lds[sp * kThreads] = v;
+        else priv[sp - kLdsStack] = v;
+        ++sp;
+    }
+    __device__ inline uint32_t pop() {
+        --sp;
+        return sp < kLdsStack ? lds[sp * kThreads] : priv[sp - kLdsStack];
+    }
+};
+
+template <int W>
+__device__ inline void sort_children(float tn[W], uint32_t ch[W]) {
+#define RG_CSWAP(i, j)                                  \
+    if (tn[j] < tn[i]) {                                \
+        float tf_ = tn[i]; tn[i] = tn[j]; tn[j] = tf_;  \
+        uint32_t tc_ = ch[i]; ch[i] = ch[j]; ch[j] = tc_; \
+    }
+    if constexpr (W == 2) {
+        RG_CSWAP(0, 1)
+    } else if constexpr (W == 4) {
+        RG_CSWAP(0, 1) RG_CSWAP(2, 3) RG_CSWAP(0, 2) RG_CSWAP(1, 3) RG_CSWAP(1, 2)
+    } else {
+        RG_CSWAP(0, 1) RG_CSWAP(2, 3) RG_CSWAP(4, 5) RG_CSWAP(6, 7)
+        RG_CSWAP(0, 2) RG_CSWAP(1, 3) RG_CSWAP(4, 6) RG_CSWAP(5, 7)
+        RG_CSWAP(1, 2) RG_CSWAP(5, 6) RG_CSWAP(0, 4) RG_CSWAP(3, 7)
+        RG_CSWAP(1, 5) RG_CSWAP(2, 6)
+        RG_CSWAP(1, 4) RG_CSWAP(3, 6)
+        RG_CSWAP(2, 4) RG_CSWAP(3, 5)
+        RG_CSWAP(3, 4)
+    }
+#undef RG_CSWAP
+}
+
+// Closest (ANY = false) or any (ANY = true) hit of one ray.  `lds_col` is this
+// lane's LDS stack column.
+template <int W, bool ANY, int MODE>
+__device__ inline bool trace_ray(const RgNode<W> *__restrict__ tlas_nodes, const RgInst *__restrict__ recs,
+                                 const Ray &R, uint32_t *lds_col, Hit &h) {
+    h.t = INFINITY;
+    h.u = h.v = 0.0f;
+    h.inst = h.prim = RG_MISS;
+    h.n_nodes = h.n_tris = h.n_inst = 0;
+    const float tmin = R.tmin;
+    float best = R.tmax;  // closest: shrinks to the best hit; the interval stays closed
+    if (!(tmin <= best)) return false;
+    float widx = safe_rcp(R.d[0]), widy = safe_rcp(R.d[1]), widz = safe_rcp(R.d[2]);
+    // current frame
+    float ox = R.o[0], oy = R.o[1], oz = R.o[2];
+    float ix = widx, iy = widy, iz = widz;
+    float t0 = 0.0f;        // slide of the current frame's origin
+    float tlo = tmin;       // interval in the current frame
+    float thi = best;
+    const RgNode<W> *nodes = tlas_nodes;
+    const RgTri *tris = nullptr;
+    uint32_t rec_idx = 0, inst_id = 0;
+    float lo3[3] = {0, 0, 0};
+    Shear sh;
+    sh.kx = 0; sh.ky = 1; sh.kz = 2; sh.sx = sh.sy = 0.0f; sh.sz = 1.0f;
+    bool in_blas = false;
+    bool found = false;
+    Stack st;
+    st.lds = lds_col;
+    st.sp = 0;
+    uint32_t cur = 0;  // root inner node of the top level
+    uint32_t steps = 0;
+    while (true) {
+        if (++steps > kMaxSteps) return found;
+        if (!rg_is_leaf(cur)) {
+            if (MODE == kCounts) ++h.n_nodes;
+            const RgNode<W> nd = nodes[cur];
+            float tn[W];
+            uint32_t ch[W];
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                float x0 = (nd.lo_x[k] - ox) * ix, x1 = (nd.hi_x[k] - ox) * ix;
+                float y0 = (nd.lo_y[k] - oy) * iy, y1 = (nd.hi_y[k] - oy) * iy;
+                float z0 = (nd.lo_z[k] - oz) * iz, z1 = (nd.hi_z[k] - oz) * iz;
+                float n_ = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), tlo));
+                float f_ = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fmaxf(z0, z1));
+                f_ = f_ + fabsf(f_) * kFarWiden;
+                f_ = fminf(f_, thi);
+                bool hit = (n_ <= f_) && (nd.child[k] != RG_EMPTY);
+                tn[k] = hit ? n_ : INFINITY;
+                ch[k] = nd.child[k];
+            }
+            if (!ANY) sort_children<W>(tn, ch);
+            // the nearest hit child continues; the others are pushed far first
+            uint32_t next = RG_EMPTY;
+            if (ANY) {
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    if (tn[k] != INFINITY) {
+                        if (next == RG_EMPTY) next = ch[k];
+                        else st.push(ch[k]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = W - 1; k >= 1; --k)
+                    if (tn[k] != INFINITY) st.push(ch[k]);
+                if (tn[0] != INFINITY) next = ch[0];
+            }
+            if (next != RG_EMPTY) {
+                cur = next;
+                continue;
+            }
+        } else if (!in_blas) {
+            // top-level leaf: one instance
+            rec_idx = rg_leaf_first(cur);
+            if (MODE == kCounts) ++h.n_inst;
+            const RgInst rec = recs[rec_idx];
+            const RgNode<W> *bn = reinterpret_cast<const RgNode<W> *>(rec.nodes);
+            // the bottom level's root box: the union of the root node's children
+            float blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+            {
+                const RgNode<W> r0 = bn[0];
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    blo[0] = fminf(blo[0], r0.lo_x[k]); blo[1] = fminf(blo[1], r0.lo_y[k]);
+                    blo[2] = fminf(blo[2], r0.lo_z[k]);
+                    bhi[0] = fmaxf(bhi[0], r0.hi_x[k]); bhi[1] = fmaxf(bhi[1], r0.hi_y[k]);
+                    bhi[2] = fmaxf(bhi[2], r0.hi_z[k]);
+                }
+            }
+            // object-space ray in double: o' = M^-1 (o - p), d' = M^-1 d
+            double q[3] = {(double)R.o[0] - (double)rec.p[0], (double)R.o[1] - (double)rec.p[1],
+                           (double)R.o[2] - (double)rec.p[2]};
+            double od[3], dd[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                double ir0 = rec.inv[3 * r], ir1 = rec.inv[3 * r + 1], ir2 = rec.inv[3 * r + 2];
+                od[r] = ir0 * q[0] + ir1 * q[1] + ir2 * q[2];
+                dd[r] = ir0 * (double)R.d[0] + ir1 * (double)R.d[1] + ir2 * (double)R.d[2];
+            }
+            // slide the origin to where the ray enters that box (not before tmin)
+            double ten = -INFINITY, tex = INFINITY;
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                if (dd[r] != 0.0) {
+                    double a = ((double)blo[r] - od[r]) / dd[r], b = ((double)bhi[r] - od[r]) / dd[r];
+                    ten = fmax(ten, fmin(a, b));
+                    tex = fmin(tex, fmax(a, b));
+                } else if (od[r] < (double)blo[r] || od[r] > (double)bhi[r]) {
+                    ten = INFINITY;
+                }
+            }
+            double ts = (ten <= tex && ten > (double)tmin) ? ten : (double)tmin;
+            if (ts > (double)R.tmax) ts = (double)R.tmax;
+            float t0f = (float)ts;
+            float lo_[3], ld_[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                lo_[r] = (float)(od[r] + (double)t0f * dd[r]);
+                ld_[r] = (float)dd[r];
+            }
+            ox = lo_[0]; oy = lo_[1]; oz = lo_[2];
+            lo3[0] = lo_[0]; lo3[1] = lo_[1]; lo3[2] = lo_[2];
+            ix = safe_rcp(ld_[0]); iy = safe_rcp(ld_[1]); iz = safe_rcp(ld_[2]);
+            sh = make_shear(ld_);
+            t0 = t0f;
+            tlo = tmin - t0;
+            tlo = tlo - fabsf(tlo) * 1.2e-7f;
+            thi = best - t0;
+            thi = thi + fabsf(thi) * 2.4e-7f;
+            nodes = reinterpret_cast<const RgNode<W> *>(rec.nodes);
+            tris = reinterpret_cast<const RgTri *>(rec.tris);
+            inst_id = (MODE == kRender) ? rec_idx : rec.inst;
+            in_blas = true;
+            st.push(kSentinel);
+            cur = 0;
+            continue;
+        } else {
+            // bottom-level leaf: up to 8 triangles
+            uint32_t f = rg_leaf_first(cur), n = rg_leaf_count(cur);
+            for (uint32_t j = 0; j < n; ++j) {
+                if (MODE == kCounts) ++h.n_tris;
+                const RgTri tri = tris[f + j];
+                float tl, u, v;
+                if (!tri_test(tri.v, lo3, sh, &tl, &u, &v)) continue;
+                float tw = t0 + tl;
+                if (!(tw >= tmin) || !(tw <= best)) continue;
+                uint32_t pid = (MODE == kRender) ? (f + j) : tri.prim;
+                if (!ANY && tw == best && found) {
+                    if (inst_id > h.inst || (inst_id == h.inst && pid >= h.prim)) continue;
+                }
+                found = true;
+                h.t = tw;
+                h.u = u;
+                h.v = v;
+                h.inst = inst_id;
+                h.prim = pid;
+                if (ANY) return true;
+                best = tw;
+                thi = best - t0;
+                thi = thi + fabsf(thi) * 2.4e-7f;
+            }
+        }
+        // pop
+        while (true) {
+            if (st.sp == 0) return found;
+            uint32_t e = st.pop();
+            if (e == kSentinel) {
+                in_blas = false;
+                nodes = tlas_nodes;
+                ox = R.o[0]; oy = R.o[1]; oz = R.o[2];
+                ix = widx; iy = widy; iz = widz;
+                t0 = 0.0f;
+                tlo = tmin;
+                thi = best;
+                continue;
+            }
+            cur = e;
+            break;
+        }
+    }
+}
+
+}  // namespace rgt
+
+// Arguments of the trace kernels (passed by value).
+struct RgTraceArgs {
+    const void *nodes;             // top-level nodes
+    const RgInst *recs;            // top-level instance records
+    const float *ray[8];           // ox oy oz dx dy dz tmin tmax
+    int64_t n;                     // number of rays (upper bound if `count` is set)
+    const uint32_t *count;         // device count of rays (nullable)
+    float *t, *u, *v;              // outputs (nullable)
+    uint32_t *inst, *prim;
+    uint8_t *occluded;             // any hit
+    uint32_t *counts;              // visit counts [n][3]
+};
+
+// Launches the traversal over a.n rays (or *a.count if set) on `stream`.
+// width: 2/4/8; any: any-hit; mode: rgt::Mode.
+rg_status rg_trace_launch(int width, bool any, int mode, const RgTraceArgs &a, hipStream_t stream);
+// Largest (W-1)*(top depth + bottom depth) + 1 the traversal stack holds.
+bool rg_trace_depth_ok(const rg_tlas *t);

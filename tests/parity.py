@@ -1,0 +1,86 @@
+"""Comparison of GPU results with the oracle, per the tolerance rules:
+
+closest hit, for every ray the oracle does not flag as ambiguous:
+  hit/miss agree; the GPU's (inst, prim) is in the oracle's tie set (exact
+  ties, and both triangles of a covered edge crossing); against that member's
+  FP64 values, |t - t*| <= max(1e-5 t*, delta) and |u - u*|, |v - v*| <=
+  max(1e-4, beta), where
+  delta and beta are the float32 error bands of that triangle's t and
+  barycentrics (delta exceeds 1e-5 t* only for hits much nearer than the
+  float32 coordinates' magnitude, e.g. a secondary ray hitting close by).
+any hit: occluded agrees on every non-ambiguous ray.
+render: RMSE over non-ambiguous pixels and all channels <= 1e-4.
+"""
+import numpy as np
+
+T_REL = 1e-5
+UV_ABS = 1e-4
+RMSE_MAX = 1e-4
+
+
+def check_closest(g, o, max_amb: float = 0.02, label: str = ""):
+    """g: dict of numpy arrays from the GPU (t, inst, prim, u, v); o: oracle."""
+    n = o["t"].shape[0]
+    ok = o["amb"] == 0
+    amb_frac = 1.0 - ok.mean() if n else 0.0
+    assert amb_frac <= max_amb, f"{label}: ambiguous fraction {amb_frac:.4f} > {max_amb}"
+    ghit = g["inst"].astype(np.uint32) != 0xFFFFFFFF
+    ohit = o["hit"] == 1
+    bad = np.nonzero(ok & (ghit != ohit))[0]
+    assert bad.size == 0, f"{label}: hit/miss differ on {bad.size} rays, e.g. {bad[:5]}"
+    miss = ok & ~ohit
+    assert np.isinf(g["t"][miss]).all()
+    assert (g["prim"][miss].astype(np.uint32) == 0xFFFFFFFF).all()
+    idx = np.nonzero(ok & ohit)[0]
+    worst_t = 0.0
+    worst_uv = 0.0
+    loose = 0
+    ratio_uv = 0.0   # observed error / band: how much of the band the GPU uses
+    ratio_t = 0.0
+    for i in idx:
+        gi, gp = np.uint32(g["inst"][i]), np.uint32(g["prim"][i])
+        k = o["nties"][i]
+        ties = o["ties"][i, :k]
+        sel = np.nonzero((ties[:, 0] == gi) & (ties[:, 1] == gp))[0]
+        assert sel.size > 0, (f"{label}: ray {i}: GPU hit ({gi},{gp}) t={g['t'][i]} not in the tie set "
+                              f"{ties.tolist()} (oracle ({o['inst'][i]},{o['prim'][i]}) t={o['t'][i]})")
+        tt, tu, tv = o["ties_tuv"][i, sel[0]]
+        dt = abs(float(g["t"][i]) - tt)
+        t_tol = max(T_REL * tt, o["delta"][i])
+        loose += t_tol > T_REL * tt
+        assert dt <= t_tol, f"{label}: ray {i}: t {g['t'][i]} vs {tt} (tol {t_tol:.3g})"
+        worst_t = max(worst_t, dt / max(o["t"][i], 1e-30))
+        tol = max(UV_ABS, o["beta"][i])
+        du = max(abs(float(g["u"][i]) - tu), abs(float(g["v"][i]) - tv))
+        assert du <= tol, f"{label}: ray {i}: uv ({g['u'][i]},{g['v'][i]}) vs ({tu},{tv}), tol {tol}"
+        worst_uv = max(worst_uv, du)
+        ratio_uv = max(ratio_uv, du / max(o["beta"][i], 1e-300))
+        ratio_t = max(ratio_t, dt / max(o["delta"][i], 1e-300))
+    return dict(band_use_uv=float(ratio_uv), band_use_t=float(ratio_t), n=n, amb_frac=float(amb_frac), hits=int(idx.size), worst_t_rel=worst_t, worst_uv=worst_uv,
+                t_band_used=int(loose))
+
+
+def check_any(occ, o, max_amb: float = 0.02, label: str = ""):
+    ok = o["amb"] == 0
+    amb_frac = 1.0 - ok.mean()
+    assert amb_frac <= max_amb, f"{label}: ambiguous fraction {amb_frac:.4f}"
+    bad = np.nonzero(ok & ((occ != 0) != (o["hit"] == 1)))[0]
+    assert bad.size == 0, f"{label}: occlusion differs on {bad.size} rays, e.g. {bad[:5]}"
+    return dict(n=int(occ.shape[0]), amb_frac=float(amb_frac), occluded=int((o["hit"] == 1).sum()))
+
+
+def check_image(img, o, max_amb: float = 0.02, label: str = ""):
+    """img: float [n,3] GPU pixels for the sampled pixels; o: oracle render."""
+    ok = o["amb"] == 0
+    amb_frac = 1.0 - ok.mean()
+    assert amb_frac <= max_amb, f"{label}: ambiguous pixel fraction {amb_frac:.4f}"
+    diff = img[ok].astype(np.float64) - o["rgb"][ok]
+    rmse = float(np.sqrt(np.mean(diff ** 2))) if diff.size else 0.0
+    full = float(np.sqrt(np.mean((img.astype(np.float64) - o["rgb"]) ** 2)))
+    assert rmse <= RMSE_MAX, f"{label}: masked RMSE {rmse:.3g} > {RMSE_MAX} (unmasked {full:.3g})"
+    return dict(n=int(img.shape[0]), amb_frac=float(amb_frac), rmse=rmse, rmse_unmasked=full,
+                max_abs=float(np.abs(diff).max()) if diff.size else 0.0)
+
+
+def hits_to_numpy(h):
+    return {k: v.cpu().numpy() for k, v in h.items()}

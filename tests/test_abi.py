@@ -1,0 +1,120 @@
+"""The C-ABI library: it loads, exports every function include/rg.h declares,
+and its host-side argument validation rejects bad calls before any GPU work
+(so these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rg.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(rg_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("rg_build_blas", "rg_build_tlas", "rg_trace_closest", "rg_trace_any", "rg_render"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2001_09792_amd as rg
+    lib = ctypes.CDLL(rg.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding covers the whole header
+    assert set(_declared()) == set(rg.SIGNATURES)
+
+
+def test_status_strings():
+    import paper_2001_09792_amd as rg
+    assert rg._lib.rg_status_string(0) == b"ok"
+    assert rg._lib.rg_status_string(-1) == b"invalid argument"
+    assert rg._lib.rg_status_string(-2) == b"buffer too small"
+
+
+def test_sizes_validation():
+    import paper_2001_09792_amd as rg
+    nb, ns = rg.blas_sizes(1000)
+    assert nb > 1000 * 40 and ns > 0
+    for bad in (0, -1, 2 ** 28 + 1):
+        with pytest.raises(rg.RgError):
+            rg.blas_sizes(bad)
+    with pytest.raises(rg.RgError):
+        rg.blas_sizes(10, width=3)
+    with pytest.raises(rg.RgError):
+        rg.blas_sizes(10, leaf_max=9)
+    # wider nodes are bigger
+    assert rg.blas_sizes(10000, 8)[0] > rg.blas_sizes(10000, 2)[0]
+
+
+def test_render_sizes_validation():
+    import paper_2001_09792_amd as rg
+    s1 = rg.render_sizes(64, 64, 1, 0)
+    s2 = rg.render_sizes(64, 64, 2, 0)
+    assert s2 > s1 > 0
+    assert rg.render_sizes(64, 64, 0, 1) > 0
+    for args in ((0, 64, 1, 0), (64, 64, 9, 0), (64, 64, -1, 0), (64, 64, 1, 2)):
+        with pytest.raises(rg.RgError):
+            rg.render_sizes(*args)
+
+
+def test_null_pointer_calls_are_rejected_on_the_host():
+    import paper_2001_09792_amd as rg
+    lib = rg._lib
+    d = rg.BlasDesc()
+    o = rg.BuildOpts(4, 4)
+    # NULL vertices
+    assert lib.rg_build_blas(None, 3, None, 1, None, ctypes.byref(o), None, 0, None, 0, None,
+                             ctypes.byref(d)) == -1
+    t = rg.TlasDesc()
+    assert lib.rg_trace_closest(None, rg.Rays(), 1, rg.Hits(), None) == -1
+    assert lib.rg_trace_any(ctypes.byref(t), rg.Rays(), 1, None, None, None) == -1
+    assert lib.rg_trace_counts(None, rg.Rays(), 1, 0, None, None) == -1
+    assert lib.rg_camera_rays(None, 4, 4, None, None) == -1
+    assert lib.rg_render(None, None, 0, None, None, 4, 4, 1, 0, 0, None, None, 0, None, None) == -1
+    # a top level over a singular matrix is rejected before any device work
+    xf = (ctypes.c_float * 12)(*([0.0] * 12))
+    bid = (ctypes.c_uint32 * 1)(0)
+    im = (ctypes.c_uint32 * 1)(0)
+    fake = rg.BlasDesc()
+    fake.buf = 256
+    fake.width = 4
+    blas = (rg.BlasDesc * 1)(fake)
+    assert lib.rg_build_tlas(blas, 1, xf, bid, im, 1, ctypes.byref(o), 256, 1 << 20, 256, 1 << 20, None,
+                             ctypes.byref(t)) == -1
+    # non-finite matrix entry
+    vals = [1.0, 0, 0, 0, 0, 1.0, 0, 0, 0, 0, 1.0, float("nan")]
+    xf2 = (ctypes.c_float * 12)(*vals)
+    assert lib.rg_build_tlas(blas, 1, xf2, bid, im, 1, ctypes.byref(o), 256, 1 << 20, 256, 1 << 20, None,
+                             ctypes.byref(t)) == -1
+    # blas id out of range
+    vals[11] = 0.0
+    xf3 = (ctypes.c_float * 12)(*vals)
+    bid2 = (ctypes.c_uint32 * 1)(1)
+    assert lib.rg_build_tlas(blas, 1, xf3, bid2, im, 1, ctypes.byref(o), 256, 1 << 20, 256, 1 << 20, None,
+                             ctypes.byref(t)) == -1
+    # mixed widths
+    fake.width = 8
+    blas = (rg.BlasDesc * 1)(fake)
+    assert lib.rg_build_tlas(blas, 1, xf3, bid, im, 1, ctypes.byref(o), 256, 1 << 20, 256, 1 << 20, None,
+                             ctypes.byref(t)) == -1
+
+
+def test_undersized_buffers_are_rejected():
+    import paper_2001_09792_amd as rg
+    lib = rg._lib
+    d = rg.BlasDesc()
+    o = rg.BuildOpts(4, 4)
+    nb, ns = rg.blas_sizes(100)
+    # pointers are never dereferenced because the size check fails first
+    assert lib.rg_build_blas(256, 300, 256, 100, None, ctypes.byref(o), 256, nb - 1, 256, ns, None,
+                             ctypes.byref(d)) == -2
+    assert lib.rg_build_blas(256, 300, 256, 100, None, ctypes.byref(o), 256, nb, 256, ns - 1, None,
+                             ctypes.byref(d)) == -2

@@ -1,0 +1,119 @@
+"""GPU hierarchy build (a1-a6): each stage against its plain definition in
+oracle/build_ref.py, bit for bit, and the wide nodes against structural
+invariants."""
+import numpy as np
+import pytest
+
+import scenegen as sg
+from oracle import build_ref as br
+from tests import bvh_check
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(mesh):
+    import torch
+    v = torch.from_numpy(np.ascontiguousarray(mesh.verts, np.float32)).cuda()
+    i = torch.from_numpy(np.ascontiguousarray(mesh.idx, np.uint32).view(np.int32)).cuda()
+    return v, i
+
+
+MESHES = {
+    "soup5000": lambda: sg.random_soup(5000, 21),          # 3 sort tiles and a ragged tail
+    "small": lambda: sg.config_small().blas[0],
+    "torus": lambda: sg.torus(48, 40, 1.0, 0.35, 0.08, 6.0, 3001),
+    "two": lambda: sg.random_soup(2, 5),
+    "dupes": lambda: sg.triangles_mesh(np.repeat(np.array([[[0, 0, 0], [1, 0, 0], [0, 1, 0]]]), 300, axis=0)),
+}
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_lbvh_stages_match_definitions(name):
+    import paper_2001_09792_amd as rg
+    mesh = MESHES[name]()
+    print(f"[build stages] {name}: {mesh.n_tris} tris", flush=True)
+    v, i = _dev(mesh)
+    st = rg.lbvh_stages(v, i)
+    keys = st["keys"].cpu().numpy().view(np.uint64)
+    ids = st["ids"].cpu().numpy().view(np.uint32)
+    ref_keys = br.morton_keys(mesh.verts, mesh.idx)
+    ref_sorted, ref_ids = br.sort_pairs(ref_keys)
+    assert np.array_equal(keys, ref_sorted), "Morton keys / sort differ"
+    assert np.array_equal(ids, ref_ids), "the sort must be stable"
+    n = mesh.n_tris
+    if n > 1:
+        left, right, first, last = br.radix_tree(ref_sorted)
+        assert np.array_equal(st["left"].cpu().numpy(), left.astype(np.int32))
+        assert np.array_equal(st["right"].cpu().numpy(), right.astype(np.int32))
+        lo, hi = br.tri_boxes(mesh.verts, mesh.idx)
+        blo, bhi = br.refit(lo[ref_ids], hi[ref_ids], first, last)
+        boxes = st["boxes"].cpu().numpy()
+        assert np.array_equal(boxes[: n - 1, :3], blo) and np.array_equal(boxes[: n - 1, 3:], bhi)
+        assert np.array_equal(boxes[n - 1:, :3], lo[ref_ids]) and np.array_equal(boxes[n - 1:, 3:], hi[ref_ids])
+
+
+@pytest.mark.parametrize("width", [2, 4, 8])
+@pytest.mark.parametrize("leaf_max", [1, 3, 8])
+def test_wide_blas_invariants(width, leaf_max):
+    import paper_2001_09792_amd as rg
+    mesh = sg.random_soup(3000, 31)
+    mesh.prim_mat = (np.arange(mesh.n_tris) % 7).astype(np.uint16)
+    print(f"[blas] W={width} L={leaf_max}", flush=True)
+    v, i = _dev(mesh)
+    import torch
+    pm = torch.from_numpy(mesh.prim_mat.view(np.int16)).cuda()
+    b = rg.build_blas(v, i, pm, width, leaf_max)
+    info = bvh_check.check_blas(b.buf.cpu().numpy(), b.desc)
+    # leaf-order triangles are the input triangles
+    V = mesh.verts[mesh.idx[info["prim"]]]
+    assert np.array_equal(info["verts"], V)
+    assert np.array_equal(info["tri_mats"], mesh.prim_mat[info["prim"]])
+    base = b.buf.data_ptr()
+    assert int(info["header"][0]) == base + b.desc.nodes_off
+    assert int(info["header"][1]) == base + b.desc.tris_off
+
+
+def test_tlas_invariants():
+    import paper_2001_09792_amd as rg
+    sc = sg.config_two_level(width=64, height=36)
+    print("[tlas] two-level", flush=True)
+    tl = rg.upload_scene(sc)
+    info = bvh_check.check_tlas(tl.buf.cpu().numpy(), tl.desc, [b.desc for b in tl.blas], sc.xform)
+    # each instance box holds the 8 transformed corners of its mesh box
+    X = sc.xform.astype(np.float64)
+    for r, i in enumerate(info["inst"]):
+        d = tl.blas[sc.blas_id[i]].desc
+        corners = np.array([[d.hi[0] if c & 1 else d.lo[0], d.hi[1] if c & 2 else d.lo[1],
+                             d.hi[2] if c & 4 else d.lo[2]] for c in range(8)], np.float64)
+        w = corners @ X[i, :, :3].T + X[i, :, 3]
+        assert np.all(info["boxes"][0][r] <= w.min(axis=0)) and np.all(info["boxes"][1][r] >= w.max(axis=0))
+
+
+def test_single_triangle_and_single_instance():
+    import paper_2001_09792_amd as rg
+    mesh = sg.triangles_mesh([[(0, 0, 0), (1, 0, 0), (0, 1, 0)]])
+    v, i = _dev(mesh)
+    for w in (2, 4, 8):
+        b = rg.build_blas(v, i, None, w, 4)
+        bvh_check.check_blas(b.buf.cpu().numpy(), b.desc)
+        tl = rg.build_tlas([b], sg.identity_xform(1), [0], [0], w)
+        bvh_check.check_tlas(tl.buf.cpu().numpy(), tl.desc, [b.desc], sg.identity_xform(1))
+
+
+def test_bad_inputs_are_rejected():
+    import torch
+    import paper_2001_09792_amd as rg
+    mesh = sg.random_soup(10, 3)
+    v, i = _dev(mesh)
+    bad = v.clone()
+    bad[4, 1] = float("nan")
+    with pytest.raises(rg.RgError):
+        rg.build_blas(bad, i)
+    bad_i = i.clone()
+    bad_i[3, 2] = 10 ** 6
+    with pytest.raises(rg.RgError):
+        rg.build_blas(v, bad_i)
+    # the rejected calls leave the device usable
+    b = rg.build_blas(v, i)
+    assert b.n_tris == 10
+    torch.cuda.synchronize()
