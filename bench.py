@@ -1,0 +1,291 @@
+"""Benchmark: closest-hit Mrays/s on primary + incoherent rays, one MI355X.
+
+Workload (default, `--workload incoherent`): 1,024 instances of 16 seeded
+displaced tori of 560x560 segments (627,200 triangles each, 10,035,200
+unique, 642M instanced), camera 1920x1080; per step: ray generation, a
+closest-hit pass over the 2,073,600 camera rays, ambient-occlusion ray
+generation (8 cosine-weighted rays per primary hit, tmax 5) and a
+closest-hit pass over those rays.  value = (primary + AO rays) / step time.
+The hierarchies are built once, before timing, and stay resident in HBM.
+
+`--workload two_level` times whole frames of the 64-instance scene instead
+(1920x1080, Whitted recursion depth 4: camera, closest, shade, shadow any-
+hit, reflection and refraction passes), value = all rays traced / frame time.
+
+One JSON line is printed.  `roofline` refers to the dominant kernel (the
+closest-hit traversal of the AO rays): algorithmic bytes per ray from the
+traversal's own visit counts (rays 32 B + hit 20 B + nodes x 128 B +
+triangles x 40 B + instances x 80 B) over the kernel's event-timed duration,
+against 8 TB/s.  `cpu_baseline` is the FP64 oracle timed on a bounded sample
+of the same rays on this host's cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+NODE_BYTES = {2: 64, 4: 128, 8: 256}
+TRI_BYTES, INST_BYTES, RAY_BYTES, HIT_BYTES = 40, 80, 32, 20
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(counts: np.ndarray, width: int) -> float:
+    c = counts.astype(np.float64)
+    return float(c.shape[0] * (RAY_BYTES + HIT_BYTES) + c[:, 0].sum() * NODE_BYTES[width]
+                 + c[:, 1].sum() * TRI_BYTES + c[:, 2].sum() * INST_BYTES)
+
+
+def cpu_threads() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline_incoherent(scene, n_primary: int, seconds: float = 15.0) -> dict:
+    """The oracle's closest-hit rate on rays it generates itself: camera rays
+    of sampled pixels and the AO rays of their hits."""
+    import oracle
+    import scenegen as sg
+    orc = oracle.Scene(scene, sphere_reject=True)
+    px = sg.sample_pixels(scene.width, scene.height, n_primary, 99)
+    cam = oracle.camera_rays(scene.camera, scene.width, scene.height, px)
+    prim = np.zeros((px.shape[0], 8), np.float32)
+    prim[:, :6] = cam
+    prim[:, 7] = np.inf
+    t0 = time.perf_counter()
+    orc.trace(prim[:4])          # one-time setup (mesh adjacency) outside the timing
+    log(f"oracle setup {time.perf_counter() - t0:.1f}s")
+    ao = orc.ao_rays(prim, scene.seed)
+    hit = ao["hit"] == 1
+    aor = np.zeros((int(hit.sum()) * 8, 8), np.float32)
+    aor[:, :6] = ao["rays"][hit].reshape(-1, 6)
+    aor[:, 7] = 5.0
+    # keep the primary : AO ratio of the full workload in the sample
+    rays = np.concatenate([prim, aor])
+    n_total = rays.shape[0]
+    # time a probe, then size the sample to about `seconds`
+    probe = rays[np.linspace(0, n_total - 1, min(64, n_total)).astype(int)]
+    t0 = time.perf_counter()
+    orc.trace(probe)
+    per_ray = (time.perf_counter() - t0) / probe.shape[0]
+    n = int(max(64, min(n_total, seconds / max(per_ray, 1e-9))))
+    sel = np.linspace(0, n_total - 1, n).astype(int)
+    t0 = time.perf_counter()
+    res = orc.trace(rays[sel])
+    dt = time.perf_counter() - t0
+    return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": cpu_threads(), "kind": "oracle",
+            "sample": f"{n} rays ({int((sel < prim.shape[0]).sum())} camera + AO rays of {px.shape[0]} "
+                      f"sampled pixels), FP64 brute force with exact bounding-sphere reject, "
+                      f"{res['tests'] / n:.3g} triangle tests per ray, {dt:.1f} s",
+            "tests_per_s": res["tests"] / dt}
+
+
+def cpu_baseline_frame(scene, n_pixels: int = 256, seconds: float = 15.0) -> dict:
+    import oracle
+    import scenegen as sg
+    orc = oracle.Scene(scene, sphere_reject=True)
+    px = sg.sample_pixels(scene.width, scene.height, n_pixels, 98)
+    orc.render(px[:2])
+    t0 = time.perf_counter()
+    r = orc.render(px)
+    dt = time.perf_counter() - t0
+    n = int(r["nrays"].sum())
+    return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": cpu_threads(), "kind": "oracle",
+            "sample": f"{px.shape[0]} sampled pixels, whole ray trees ({n} rays), {dt:.1f} s"}
+
+
+def bench_incoherent(args, torch, rg, sg):
+    t0 = time.perf_counter()
+    scene = sg.config_incoherent(segments=args.segments)
+    log(f"scene: {scene.unique_tris()} unique / {scene.instanced_tris()} instanced tris "
+        f"({time.perf_counter() - t0:.1f}s to generate)")
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    tl = rg.upload_scene(scene, width=args.width, leaf_max=args.leaf)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - tb
+    W, H = scene.width, scene.height
+    N = W * H
+    dev = "cuda"
+    cam = torch.empty((8, N), dtype=torch.float32, device=dev)
+    hits = rg.alloc_hits(N)
+    ao = torch.empty((8, 8 * N), dtype=torch.float32, device=dev)
+    src = torch.empty(8 * N, dtype=torch.int32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    ao_hits = rg.alloc_hits(8 * N)
+    ao_occ = torch.empty(8 * N, dtype=torch.uint8, device=dev)
+    need = rg.ctypes.c_uint64()
+    rg._lib.rg_ao_rays_scratch(N, rg.ctypes.byref(need))
+    ao_scratch = torch.empty(max(256, need.value), dtype=torch.uint8, device=dev)
+
+    def gen_primary():
+        rg.camera_rays(scene.camera, W, H, out=cam)
+        rg.trace_closest(tl, cam, out=hits)
+        rg.ao_rays(tl, cam, hits, scene.seed, 5.0, out=ao, src=src, count=cnt, scratch=ao_scratch)
+
+    gen_primary()
+    torch.cuda.synchronize()
+    n_ao = int(cnt.item())          # the same every step: same camera, hits and seed
+    ao_c = ao[:, :n_ao]             # rows of the AO ray buffer, traced in place
+    ao_hit_v = {k: v[:n_ao] for k, v in ao_hits.items()}
+    prim_hit_frac = float((hits["inst"] != -1).float().mean().item())
+
+    def step():
+        rg.camera_rays(scene.camera, W, H, out=cam)
+        rg.trace_closest(tl, cam, out=hits)
+        rg.ao_rays(tl, cam, hits, scene.seed, 5.0, out=ao, src=src, count=cnt, scratch=ao_scratch)
+        rg.trace_closest(tl, ao_c, out=ao_hit_v)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # timed region: exactly `steps` steps
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    rays_step = N + n_ao
+    # per-kernel times (events on the stream the kernels run on)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    t_prim, t_aogen, t_ao, t_any = [], [], [], []
+    for _ in range(args.steps):
+        ev[0].record()
+        rg.camera_rays(scene.camera, W, H, out=cam)
+        rg.trace_closest(tl, cam, out=hits)
+        ev[1].record()
+        rg.ao_rays(tl, cam, hits, scene.seed, 5.0, out=ao, src=src, count=cnt, scratch=ao_scratch)
+        ev[2].record()
+        rg.trace_closest(tl, ao_c, out=ao_hit_v)
+        ev[3].record()
+        rg.trace_any(tl, ao_c, occluded=ao_occ[:n_ao])
+        ev[4].record()
+        torch.cuda.synchronize()
+        t_prim.append(ev[0].elapsed_time(ev[1]))
+        t_aogen.append(ev[1].elapsed_time(ev[2]))
+        t_ao.append(ev[2].elapsed_time(ev[3]))
+        t_any.append(ev[3].elapsed_time(ev[4]))
+    t_prim, t_aogen, t_ao, t_any = (float(np.mean(x)) for x in (t_prim, t_aogen, t_ao, t_any))
+    counts = rg.trace_counts(tl, ao_c).cpu().numpy()
+    bytes_ao = algorithmic_bytes(counts, args.width)
+    achieved = bytes_ao / (t_ao * 1e-3) / 1e9
+    counts_p = rg.trace_counts(tl, cam).cpu().numpy()
+    out = {
+        "metric": "Mrays/s closest-hit (primary+incoherent)",
+        "value": rays_step / (ms_step * 1e-3) / 1e6,
+        "unit": "Mrays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "incoherent: 1024 instances of 16 seeded displaced tori "
+                               f"{args.segments}x{args.segments} ({scene.unique_tris()} unique tris), "
+                               f"{W}x{H} camera rays + 8 AO rays per primary hit (tmax 5), closest hit",
+                   "rays_per_step": rays_step, "primary_rays": N, "ao_rays": n_ao,
+                   "primary_hit_fraction": prim_hit_frac, "bvh_width": args.width, "leaf_max": args.leaf},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "closest-hit traversal of the AO rays",
+                     "bytes_per_ray": bytes_ao / n_ao, "kernel_ms": t_ao,
+                     "mean_nodes": float(counts[:, 0].mean()), "mean_tris": float(counts[:, 1].mean()),
+                     "mean_inst": float(counts[:, 2].mean())},
+        "primary_closest_mrays_s": N / (t_prim * 1e-3) / 1e6,
+        "primary_mean_nodes": float(counts_p[:, 0].mean()),
+        "ao_closest_mrays_s": n_ao / (t_ao * 1e-3) / 1e6,
+        "ao_anyhit_mrays_s": n_ao / (t_any * 1e-3) / 1e6,
+        "ao_raygen_ms": t_aogen,
+        "build_mtris_s": scene.unique_tris() / build_s / 1e6,
+        "wall_s_timed": wall,
+    }
+    return out, scene
+
+
+def bench_two_level(args, torch, rg, sg):
+    scene = sg.config_two_level()
+    tl = rg.upload_scene(scene, width=args.width, leaf_max=args.leaf)
+    r = rg.Renderer(scene.width, scene.height, scene.max_depth, 0)
+    _, st = r.render(tl, scene.materials, scene.camera, scene.light, scene.seed, stats=True)
+    rays = st["rays_traced"] + st["shadow_rays"]
+    for _ in range(args.warmup):
+        r.render(tl, scene.materials, scene.camera, scene.light, scene.seed)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        r.render(tl, scene.materials, scene.camera, scene.light, scene.seed)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    out = {
+        "metric": "Mrays/s closest-hit (primary+incoherent)",
+        "value": rays / (ms * 1e-3) / 1e6, "unit": "Mrays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "two-level: 64 instances of 3 meshes (184,320 unique tris), 1920x1080, "
+                               "Whitted depth 4, whole frames",
+                   "rays_per_frame": rays, "closest_rays": st["rays_traced"], "shadow_rays": st["shadow_rays"]},
+        "roofline": None,
+    }
+    return out, scene
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=["incoherent", "two_level"], default="incoherent")
+    ap.add_argument("--segments", type=int, default=560)
+    ap.add_argument("--width", type=int, default=4)
+    ap.add_argument("--leaf", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the measurement, copy this many MiB once (a plain copy kernel of known "
+                         "size, for scaling hardware byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the path runs on a single device (see the multi-GPU design "
+              "notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2001_09792_amd as rg
+    import scenegen as sg
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.workload == "incoherent":
+        out, scene = bench_incoherent(args, torch, rg, sg)
+        if not args.no_cpu_baseline:
+            log("timing the oracle on a sample")
+            out["cpu_baseline"] = cpu_baseline_incoherent(scene, 64, args.cpu_seconds)
+    else:
+        out, scene = bench_two_level(args, torch, rg, sg)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline_frame(scene, 128, args.cpu_seconds)
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

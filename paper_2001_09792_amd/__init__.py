@@ -255,12 +255,16 @@ def upload_scene(scene, width: int = 4, leaf_max: int = 4, device="cuda") -> Tla
 
 # ------------------------------------------------------------------- rays
 def rays_struct(r) -> Rays:
-    """r: CUDA float32 [8, N] (ox oy oz dx dy dz tmin tmax rows)."""
-    if r.dim() != 2 or r.shape[0] != 8:
-        raise ValueError("rays must be [8, N]")
-    base = _ptr(r)
-    n = r.shape[1]
-    return Rays(*[base + 4 * n * k for k in range(8)])
+    """r: CUDA float32 [8, N] (ox oy oz dx dy dz tmin tmax rows); each row
+    contiguous, rows may be strided (e.g. the first N columns of a larger
+    buffer)."""
+    if r.dim() != 2 or r.shape[0] != 8 or r.dtype != torch.float32:
+        raise ValueError("rays must be float32 [8, N]")
+    if not r.is_cuda or (r.shape[1] > 1 and r.stride(1) != 1):
+        raise ValueError("rays must be a CUDA tensor with contiguous rows")
+    base = r.data_ptr()
+    s0 = r.stride(0)
+    return Rays(*[base + 4 * s0 * k for k in range(8)])
 
 
 def rays_to_device(rays_np, device="cuda"):
