@@ -35,6 +35,36 @@ NODE_BYTES = {2: 64, 4: 128, 8: 256}
 TRI_BYTES, INST_BYTES, RAY_BYTES, HIT_BYTES = 40, 80, 32, 20
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ao_closest.json")
+KERNEL_SOURCES = ["paper_2001_09792_amd/csrc/trace_core.h", "paper_2001_09792_amd/csrc/trace.hip",
+                  "paper_2001_09792_amd/csrc/rg_internal.h"]
+
+
+def kernel_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(args):
+    """HBM bytes per launch of the AO closest-hit traversal as measured by
+    rocprofv3 counters (FETCH_SIZE, WRITE_SIZE, scaled by a copy probe), or
+    None once the traversal source or the configuration differs from the
+    measured one."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if (rec.get("kernel_sha256") != kernel_hash() or rec.get("bvh_width") != args.width
+            or rec.get("leaf_max") != args.leaf or rec.get("segments") != args.segments):
+        return None
+    return float(rec["read_bytes"]) + float(rec["write_bytes"])
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -199,7 +229,7 @@ def bench_incoherent(args, torch, rg, sg):
                    "rays_per_step": rays_step, "primary_rays": N, "ao_rays": n_ao,
                    "primary_hit_fraction": prim_hit_frac, "bvh_width": args.width, "leaf_max": args.leaf},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(args),
                      "kernel": "closest-hit traversal of the AO rays",
                      "bytes_per_ray": bytes_ao / n_ao, "kernel_ms": t_ao,
                      "mean_nodes": float(counts[:, 0].mean()), "mean_tris": float(counts[:, 1].mean()),
