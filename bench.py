@@ -227,6 +227,7 @@ def bench_incoherent(args, torch, rg, sg):
                                f"{args.segments}x{args.segments} ({scene.unique_tris()} unique tris), "
                                f"{W}x{H} camera rays + 8 AO rays per primary hit (tmax 5), closest hit",
                    "rays_per_step": rays_step, "primary_rays": N, "ao_rays": n_ao,
+                   "trace_tuning": rg.trace_tuning(),
                    "primary_hit_fraction": prim_hit_frac, "bvh_width": args.width, "leaf_max": args.leaf},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(args),
@@ -282,7 +283,9 @@ def main():
     ap.add_argument("--workload", choices=["incoherent", "two_level"], default="incoherent")
     ap.add_argument("--segments", type=int, default=560)
     ap.add_argument("--width", type=int, default=4)
-    ap.add_argument("--leaf", type=int, default=4)
+    ap.add_argument("--leaf", type=int, default=2)
+    ap.add_argument("--refill", type=int, default=None, help="traversal refill threshold (lanes)")
+    ap.add_argument("--waves-per-cu", type=int, default=None, help="persistent traversal waves per CU")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -297,6 +300,7 @@ def main():
     import paper_2001_09792_amd as rg
     import scenegen as sg
     assert torch.cuda.is_available(), "bench.py needs the GPU"
+    tune = rg.trace_tuning(args.refill, args.waves_per_cu)
     if args.workload == "incoherent":
         out, scene = bench_incoherent(args, torch, rg, sg)
         if not args.no_cpu_baseline:

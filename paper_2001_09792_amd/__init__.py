@@ -75,6 +75,10 @@ class LightDesc(ctypes.Structure):
     _fields_ = [("pos", c_f * 3), ("intensity", c_f * 3), ("ambient", c_f)]
 
 
+class TraceTune(ctypes.Structure):
+    _fields_ = [("refill", c_i32), ("waves_per_cu", c_i32)]
+
+
 class RenderStats(ctypes.Structure):
     _fields_ = [("rays_traced", c_u64), ("shadow_rays", c_u64), ("ms_total", c_f)]
 
@@ -90,6 +94,7 @@ SIGNATURES = {
     "rg_trace_closest": (c_i32, [c_p, Rays, c_i64, Hits, c_p]),
     "rg_trace_any": (c_i32, [c_p, Rays, c_i64, c_p, c_p, c_p]),
     "rg_trace_counts": (c_i32, [c_p, Rays, c_i64, c_i32, c_p, c_p]),
+    "rg_trace_tuning": (c_i32, [c_p, c_p]),
     "rg_camera_rays": (c_i32, [c_p, c_i32, c_i32, c_p, c_p]),
     "rg_ao_rays": (c_i32, [c_p, Rays, c_i64, c_p, c_p, c_p, c_u64, c_f, c_p, c_p, c_p, c_p, c_u64, c_p]),
     "rg_ao_rays_scratch": (c_i32, [c_i64, c_p]),
@@ -314,6 +319,17 @@ def trace_counts(tlas: Tlas, rays, any_hit: bool = False, counts=None, stream=No
     _check("rg_trace_counts", _lib.rg_trace_counts(tlas.ref, rays_struct(rays), n, 1 if any_hit else 0,
                                                    _ptr(counts), _stream(stream)))
     return counts
+
+
+def trace_tuning(refill: Optional[int] = None, waves_per_cu: Optional[int] = None) -> dict:
+    """Reads (and with arguments, sets) the traversal launch parameters."""
+    cur = TraceTune()
+    _check("rg_trace_tuning", _lib.rg_trace_tuning(None, ctypes.byref(cur)))
+    if refill is not None or waves_per_cu is not None:
+        new = TraceTune(cur.refill if refill is None else refill,
+                        cur.waves_per_cu if waves_per_cu is None else waves_per_cu)
+        _check("rg_trace_tuning", _lib.rg_trace_tuning(ctypes.byref(new), ctypes.byref(cur)))
+    return dict(refill=int(cur.refill), waves_per_cu=int(cur.waves_per_cu))
 
 
 def camera_desc(cam) -> CameraDesc:

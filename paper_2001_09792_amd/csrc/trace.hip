@@ -5,46 +5,108 @@
 
 namespace {
 
+// Persistent traversal: each wave walks its own sequence of 64-ray packets
+// (packets wave, wave + waves, wave + 2 waves, ... so that every wave samples
+// the whole batch), and lanes whose ray has finished take the next rays of
+// that sequence together, once at least `refill` lanes are idle.  Rays of a
+// packet stay neighbours, and no lane idles while its wave has work left.
 template <int W, bool ANY, int MODE>
-__global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a) {
+__global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refill) {
     __shared__ uint32_t lds_stack[rgt::kLdsStack * rgt::kThreads];
-    int64_t i = blockIdx.x * (int64_t)rgt::kThreads + threadIdx.x;
-    int64_t n = a.count ? (int64_t)*a.count : a.n;
-    if (i >= n) return;
-    rgt::Ray R;
-    R.o[0] = a.ray[0][i]; R.o[1] = a.ray[1][i]; R.o[2] = a.ray[2][i];
-    R.d[0] = a.ray[3][i]; R.d[1] = a.ray[4][i]; R.d[2] = a.ray[5][i];
-    R.tmin = a.ray[6][i];
-    R.tmax = a.ray[7][i];
-    rgt::Hit h;
-    bool f = rgt::trace_ray<W, ANY, MODE>(reinterpret_cast<const RgNode<W> *>(a.nodes), a.recs, R,
-                                          &lds_stack[threadIdx.x], h);
-    if (MODE == rgt::kCounts) {
-        a.counts[3 * i] = h.n_nodes;
-        a.counts[3 * i + 1] = h.n_tris;
-        a.counts[3 * i + 2] = h.n_inst;
-        return;
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const int64_t n = a.count ? (int64_t)*a.count : a.n;
+    const int64_t n_packets = (n + 63) >> 6;
+    const int64_t wave = ((int64_t)blockIdx.x * rgt::kThreads + threadIdx.x) >> 6;
+    const int64_t n_waves = (int64_t)gridDim.x * (rgt::kThreads / 64);
+    rgt::Tracer<W, ANY, MODE> tr;
+    tr.tlas_nodes = reinterpret_cast<const RgNode<W> *>(a.nodes);
+    tr.recs = a.recs;
+    uint32_t priv_stack[rgt::kPrivStack];
+    tr.st.lds = (uint32_t RG_LDS *)&lds_stack[threadIdx.x];
+    tr.st.priv = priv_stack;
+    int64_t next = 0;  // position in this wave's ray sequence (the same in all lanes)
+    int64_t ray_i = -1;
+    bool has = false;
+    while (true) {
+        bool finished = false;
+        // every ballot and every update of `next` below is executed by all
+        // lanes together, so `next` stays uniform across the wave
+        const uint64_t need = __ballot(!has);
+        const int n_need = __popcll(need);
+        if (n_need >= refill) {
+            if (!has) {
+                int64_t j = next + __popcll(need & lt);
+                int64_t pkt = wave + (j >> 6) * n_waves;
+                int64_t idx = pkt * 64 + (j & 63);
+                if (pkt < n_packets && idx < n) {
+                    rgt::Ray R;
+                    R.o[0] = a.ray[0][idx]; R.o[1] = a.ray[1][idx]; R.o[2] = a.ray[2][idx];
+                    R.d[0] = a.ray[3][idx]; R.d[1] = a.ray[4][idx]; R.d[2] = a.ray[5][idx];
+                    R.tmin = a.ray[6][idx];
+                    R.tmax = a.ray[7][idx];
+                    ray_i = idx;
+                    has = tr.begin(R);
+                    finished = !has;  // empty interval: a miss without traversal
+                }
+            }
+            next += n_need;
+        }
+        if (__ballot(has || finished) == 0) {
+            // no lane holds a ray after a refill attempt of all 64 lanes: the
+            // sequence is exhausted once its next packet is past the end
+            if (wave + (next >> 6) * n_waves >= n_packets) break;
+            continue;
+        }
+        if (has && tr.step()) {
+            has = false;
+            finished = true;
+        }
+        if (!finished) continue;
+        if (MODE == rgt::kCounts) {
+            a.counts[3 * ray_i] = tr.h.n_nodes;
+            a.counts[3 * ray_i + 1] = tr.h.n_tris;
+            a.counts[3 * ray_i + 2] = tr.h.n_inst;
+            continue;
+        }
+        if (ANY && a.occluded) a.occluded[ray_i] = tr.found ? 1 : 0;
+        if (a.t) a.t[ray_i] = tr.h.t;
+        if (a.u) a.u[ray_i] = tr.h.u;
+        if (a.v) a.v[ray_i] = tr.h.v;
+        if (a.inst) a.inst[ray_i] = tr.h.inst;
+        if (a.prim) a.prim[ray_i] = tr.h.prim;
     }
-    if (ANY && a.occluded) a.occluded[i] = f ? 1 : 0;
-    if (a.t) a.t[i] = h.t;
-    if (a.u) a.u[i] = h.u;
-    if (a.v) a.v[i] = h.v;
-    if (a.inst) a.inst[i] = h.inst;
-    if (a.prim) a.prim[i] = h.prim;
+}
+
+int g_refill = 8;         // lanes idle before a wave refills (tunable)
+int g_waves_per_cu = 16;  // resident waves per CU the grid is sized for
+
+unsigned persistent_blocks(int64_t n) {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    int64_t want = (int64_t)cus * g_waves_per_cu / (rgt::kThreads / 64);
+    int64_t need = rg_blocks(n, rgt::kThreads);
+    return (unsigned)(need < want ? need : want);
 }
 
 template <int W>
 rg_status launch_w(bool any, int mode, const RgTraceArgs &a, hipStream_t st) {
-    unsigned blocks = rg_blocks(a.n, rgt::kThreads);
+    unsigned blocks = persistent_blocks(a.n);
+    int refill = g_refill;
     if (mode == rgt::kCounts) {
-        if (any) k_trace<W, true, rgt::kCounts><<<blocks, rgt::kThreads, 0, st>>>(a);
-        else k_trace<W, false, rgt::kCounts><<<blocks, rgt::kThreads, 0, st>>>(a);
+        if (any) k_trace<W, true, rgt::kCounts><<<blocks, rgt::kThreads, 0, st>>>(a, refill);
+        else k_trace<W, false, rgt::kCounts><<<blocks, rgt::kThreads, 0, st>>>(a, refill);
     } else if (mode == rgt::kRender) {
-        if (any) k_trace<W, true, rgt::kRender><<<blocks, rgt::kThreads, 0, st>>>(a);
-        else k_trace<W, false, rgt::kRender><<<blocks, rgt::kThreads, 0, st>>>(a);
+        if (any) k_trace<W, true, rgt::kRender><<<blocks, rgt::kThreads, 0, st>>>(a, refill);
+        else k_trace<W, false, rgt::kRender><<<blocks, rgt::kThreads, 0, st>>>(a, refill);
     } else {
-        if (any) k_trace<W, true, rgt::kClosest><<<blocks, rgt::kThreads, 0, st>>>(a);
-        else k_trace<W, false, rgt::kClosest><<<blocks, rgt::kThreads, 0, st>>>(a);
+        if (any) k_trace<W, true, rgt::kClosest><<<blocks, rgt::kThreads, 0, st>>>(a, refill);
+        else k_trace<W, false, rgt::kClosest><<<blocks, rgt::kThreads, 0, st>>>(a, refill);
     }
     RG_LAUNCH_CHECK();
     return RG_OK;
@@ -80,6 +142,20 @@ rg_status rg_trace_launch(int width, bool any, int mode, const RgTraceArgs &a, h
 }
 
 extern "C" {
+
+rg_status rg_trace_tuning(const rg_trace_tune *set, rg_trace_tune *get) {
+    if (set) {
+        if (set->refill < 1 || set->refill > 64 || set->waves_per_cu < 4 || set->waves_per_cu > 64)
+            return RG_ERR_INVALID_ARG;
+        g_refill = set->refill;
+        g_waves_per_cu = set->waves_per_cu;
+    }
+    if (get) {
+        get->refill = g_refill;
+        get->waves_per_cu = g_waves_per_cu;
+    }
+    return RG_OK;
+}
 
 rg_status rg_trace_closest(const rg_tlas *tlas, rg_rays rays, int64_t n, rg_hits out, void *stream) {
     if (!tlas_ok(tlas) || n < 0 || (n > 0 && !rays_ok(rays))) return RG_ERR_INVALID_ARG;

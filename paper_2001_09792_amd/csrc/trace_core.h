@@ -29,7 +29,34 @@ constexpr int kPrivStack = 96;  // further entries per lane in private memory
 constexpr int kStackCap = kLdsStack + kPrivStack;
 constexpr uint32_t kSentinel = 0xFFFFFFFEu;
 constexpr uint32_t kMaxSteps = 1u << 22;  // loop bound: far above any traversal of a valid hierarchy
-constexpr float kFarWiden = 2.0f * (3.0f * 5.9604645e-8f) / (1.0f - 3.0f * 5.9604645e-8f);  // 2 gamma_3
+// The far distance of a slab is widened by 2 gamma_5 (gamma_n = n u / (1 - n u),
+// u = 2^-24): the subtraction, the hardware reciprocal (1 ulp) and the product
+// each add error to t, and the near distance may err the other way.
+constexpr float kFarWiden = 2.0f * (5.0f * 5.9604645e-8f) / (1.0f - 5.0f * 5.9604645e-8f);
+
+#define RG_GLOBAL __attribute__((address_space(1)))
+#define RG_LDS __attribute__((address_space(3)))
+
+template <class T>
+__device__ inline const RG_GLOBAL T *gptr(const void *p) {
+    return (const RG_GLOBAL T *)(p);
+}
+
+typedef uint32_t rg_u4 __attribute__((ext_vector_type(4)));
+typedef uint32_t rg_u2 __attribute__((ext_vector_type(2)));
+
+// Loads element i of a global array of T with global_load (T's size a
+// multiple of 16 bytes and 16-byte aligned, or of 8 bytes for rg_u2 pieces).
+template <class T, class V = rg_u4>
+__device__ inline T gload(const void *base, uint64_t i) {
+    static_assert(sizeof(T) % sizeof(V) == 0, "size");
+    T out;
+    const RG_GLOBAL V *src = (const RG_GLOBAL V *)((const char *)base + i * sizeof(T));
+    V *dst = reinterpret_cast<V *>(&out);
+#pragma unroll
+    for (uint32_t k = 0; k < sizeof(T) / sizeof(V); ++k) dst[k] = src[k];
+    return out;
+}
 
 enum Mode { kClosest = 0, kCounts = 1, kRender = 2 };
 
@@ -48,10 +75,10 @@ struct Hit {
 
 __device__ inline float safe_rcp(float x) {
     // zero components get a huge finite reciprocal of the same sign, so that
-    // (lo - o) * inv never evaluates 0 * inf
+    // (lo - o) * inv never evaluates 0 * inf; hardware reciprocal (1 ulp)
     const float tiny = 1e-30f;
     float y = fabsf(x) < tiny ? copysignf(tiny, x) : x;
-    return 1.0f / y;
+    return __builtin_amdgcn_rcpf(y);
 }
 
 // Ray-space shear constants (Woop, Benthin & Wald 2013).
@@ -71,20 +98,26 @@ __device__ inline Shear make_shear(const float d[3]) {
         s.kx = s.ky;
         s.ky = t;
     }
-    float dz = d[s.kz];
-    s.sx = d[s.kx] / dz;
-    s.sy = d[s.ky] / dz;
-    s.sz = 1.0f / dz;
+    // any consistent constants keep the test watertight: the same values
+    // serve every triangle of the instance
+    float rz = __builtin_amdgcn_rcpf(d[s.kz]);
+    s.sx = d[s.kx] * rz;
+    s.sy = d[s.ky] * rz;
+    s.sz = rz;
     return s;
 }
 
 __device__ inline float comp(const float v[3], int k) { return k == 0 ? v[0] : (k == 1 ? v[1] : v[2]); }
 
-// Watertight ray/triangle test in ray space.  Returns true on a hit and writes
-// t (in the ray's own frame), u (weight of v1), v (weight of v2).
-__device__ inline bool tri_test(const float *__restrict__ tv, const float o[3], const Shear &s, float *t_out,
-                                float *u_out, float *v_out) {
+// Watertight ray/triangle test in ray space.  Returns true on a hit whose
+// t (in the ray's own frame) lies in [lo, hi] (up to a relative 1e-6 slack
+// on either side, settled by the caller on the exact quotient), and writes
+// T and det (t = T / det) and the edge values V, W (u = V / det, v = W / det).
+// No division is done here: most triangles fail the edge or range test.
+__device__ inline bool tri_test(const RgTri &tri, const float o[3], const Shear &s, float lo, float hi,
+                                float &T_out, float &det_out, float &V_out, float &W_out) {
 #pragma clang fp contract(off)
+    const float *tv = tri.v;
     float a[3] = {tv[0] - o[0], tv[1] - o[1], tv[2] - o[2]};
     float b[3] = {tv[3] - o[0], tv[4] - o[1], tv[5] - o[2]};
     float c[3] = {tv[6] - o[0], tv[7] - o[1], tv[8] - o[2]};
@@ -101,17 +134,23 @@ __device__ inline bool tri_test(const float *__restrict__ tv, const float o[3], 
     float det = U + V + W;
     if (det == 0.0f) return false;
     float T = U * (s.sz * az) + V * (s.sz * bz) + W * (s.sz * cz);
-    *t_out = T / det;
-    *u_out = V / det;
-    *v_out = W / det;
+    // range test without dividing: t in [lo, hi] <=> T in det*[lo, hi] for
+    // det > 0 (reversed for det < 0); a small slack keeps it conservative
+    float ad = fabsf(det), sT = det < 0.0f ? -T : T;
+    float slack = 1e-6f * ad * fmaxf(fabsf(lo), fabsf(hi));
+    if (sT > hi * ad + slack || sT < lo * ad - slack) return false;
+    T_out = T;
+    det_out = det;
+    V_out = V;
+    W_out = W;
     return true;
 }
 
 // Stack with the first kLdsStack entries in LDS (lane-interleaved, so the
 // 64 lanes of a wave hit 64 different banks) and the rest in private memory.
 struct Stack {
-    uint32_t *lds;  // base of this lane's column: lds[e * kThreads]
-    uint32_t priv[kPrivStack];
+    uint32_t RG_LDS *lds;  // base of this lane's column: lds[e * kThreads]
+    uint32_t *priv;        // kPrivStack further entries (a private array of the kernel)
     int sp;
     __device__ inline void push(uint32_t v) {
         if (sp < kLdsStack) lds[sp * kThreads] = v;
@@ -147,43 +186,64 @@ __device__ inline void sort_children(float tn[W], uint32_t ch[W]) {
 #undef RG_CSWAP
 }
 
-// Closest (ANY = false) or any (ANY = true) hit of one ray.  `lds_col` is this
-// lane's LDS stack column.
+// Traversal of one ray as a resumable state machine: begin() loads the ray,
+// step() performs one unit of work (an inner node, an instance entry, or a
+// leaf's triangles, then the pop) and reports when the ray is finished.  The
+// kernels run many rays per lane through it, so that lanes whose ray has
+// finished can take a new one while the others continue.
 template <int W, bool ANY, int MODE>
-__device__ inline bool trace_ray(const RgNode<W> *__restrict__ tlas_nodes, const RgInst *__restrict__ recs,
-                                 const Ray &R, uint32_t *lds_col, Hit &h) {
-    h.t = INFINITY;
-    h.u = h.v = 0.0f;
-    h.inst = h.prim = RG_MISS;
-    h.n_nodes = h.n_tris = h.n_inst = 0;
-    const float tmin = R.tmin;
-    float best = R.tmax;  // closest: shrinks to the best hit; the interval stays closed
-    if (!(tmin <= best)) return false;
-    float widx = safe_rcp(R.d[0]), widy = safe_rcp(R.d[1]), widz = safe_rcp(R.d[2]);
-    // current frame
-    float ox = R.o[0], oy = R.o[1], oz = R.o[2];
-    float ix = widx, iy = widy, iz = widz;
-    float t0 = 0.0f;        // slide of the current frame's origin
-    float tlo = tmin;       // interval in the current frame
-    float thi = best;
-    const RgNode<W> *nodes = tlas_nodes;
-    const RgTri *tris = nullptr;
-    uint32_t rec_idx = 0, inst_id = 0;
-    float lo3[3] = {0, 0, 0};
+struct Tracer {
+    const RgNode<W> *tlas_nodes;
+    const RgInst *recs;
+    Ray R;
+    Hit h;
+    float best;                 // closest: shrinks to the best hit (closed interval)
+    float ox, oy, oz, ix, iy, iz;  // current frame: origin and reciprocal direction
+    float t0, tlo, thi;         // slide of the frame's origin, interval in the frame
+    const RgNode<W> *nodes;
+    const RgTri *tris;
+    uint32_t inst_id;
     Shear sh;
-    sh.kx = 0; sh.ky = 1; sh.kz = 2; sh.sx = sh.sy = 0.0f; sh.sz = 1.0f;
-    bool in_blas = false;
-    bool found = false;
     Stack st;
-    st.lds = lds_col;
-    st.sp = 0;
-    uint32_t cur = 0;  // root inner node of the top level
-    uint32_t steps = 0;
-    while (true) {
-        if (++steps > kMaxSteps) return found;
+    uint32_t cur, steps;
+    bool in_blas, found;
+
+    __device__ inline void world_frame() {
+        in_blas = false;
+        nodes = tlas_nodes;
+        ox = R.o[0]; oy = R.o[1]; oz = R.o[2];
+        ix = safe_rcp(R.d[0]); iy = safe_rcp(R.d[1]); iz = safe_rcp(R.d[2]);
+        t0 = 0.0f;
+        tlo = R.tmin;
+        thi = best;
+    }
+
+    // Returns false if the ray has nothing to do (empty interval).
+    __device__ inline bool begin(const Ray &ray) {
+        R = ray;
+        h.t = INFINITY;
+        h.u = h.v = 0.0f;
+        h.inst = h.prim = RG_MISS;
+        h.n_nodes = h.n_tris = h.n_inst = 0;
+        best = R.tmax;
+        found = false;
+        st.sp = 0;
+        cur = 0;  // root inner node of the top level
+        steps = 0;
+        tris = nullptr;
+        inst_id = 0;
+        sh.kx = 0; sh.ky = 1; sh.kz = 2; sh.sx = sh.sy = 0.0f; sh.sz = 1.0f;
+        world_frame();
+        return R.tmin <= R.tmax;
+    }
+
+    // One unit of work; returns true when the ray is finished (h holds the
+    // result, `found` whether there is a hit).
+    __device__ inline bool step() {
+        if (++steps > kMaxSteps) return true;
         if (!rg_is_leaf(cur)) {
             if (MODE == kCounts) ++h.n_nodes;
-            const RgNode<W> nd = nodes[cur];
+            const RgNode<W> nd = gload<RgNode<W>>(nodes, cur);
             float tn[W];
             uint32_t ch[W];
 #pragma unroll
@@ -218,18 +278,17 @@ __device__ inline bool trace_ray(const RgNode<W> *__restrict__ tlas_nodes, const
             }
             if (next != RG_EMPTY) {
                 cur = next;
-                continue;
+                return false;
             }
         } else if (!in_blas) {
             // top-level leaf: one instance
-            rec_idx = rg_leaf_first(cur);
+            uint32_t rec_idx = rg_leaf_first(cur);
             if (MODE == kCounts) ++h.n_inst;
-            const RgInst rec = recs[rec_idx];
-            const RgNode<W> *bn = reinterpret_cast<const RgNode<W> *>(rec.nodes);
+            const RgInst rec = gload<RgInst>(recs, rec_idx);
             // the bottom level's root box: the union of the root node's children
             float blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
             {
-                const RgNode<W> r0 = bn[0];
+                const RgNode<W> r0 = gload<RgNode<W>>((const void *)rec.nodes, 0);
 #pragma unroll
                 for (int k = 0; k < W; ++k) {
                     blo[0] = fminf(blo[0], r0.lo_x[k]); blo[1] = fminf(blo[1], r0.lo_y[k]);
@@ -248,33 +307,29 @@ __device__ inline bool trace_ray(const RgNode<W> *__restrict__ tlas_nodes, const
                 od[r] = ir0 * q[0] + ir1 * q[1] + ir2 * q[2];
                 dd[r] = ir0 * (double)R.d[0] + ir1 * (double)R.d[1] + ir2 * (double)R.d[2];
             }
-            // slide the origin to where the ray enters that box (not before tmin)
-            double ten = -INFINITY, tex = INFINITY;
+            // slide the origin to where the ray enters that box (not before
+            // tmin); the entry only needs to be near the box, so float suffices
+            float ten = -INFINITY, tex = INFINITY;
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
-                if (dd[r] != 0.0) {
-                    double a = ((double)blo[r] - od[r]) / dd[r], b = ((double)bhi[r] - od[r]) / dd[r];
-                    ten = fmax(ten, fmin(a, b));
-                    tex = fmin(tex, fmax(a, b));
-                } else if (od[r] < (double)blo[r] || od[r] > (double)bhi[r]) {
-                    ten = INFINITY;
-                }
+                float of = (float)od[r], df = (float)dd[r], rr = safe_rcp(df);
+                float a = (blo[r] - of) * rr, b = (bhi[r] - of) * rr;
+                ten = fmaxf(ten, fminf(a, b));
+                tex = fminf(tex, fmaxf(a, b));
             }
-            double ts = (ten <= tex && ten > (double)tmin) ? ten : (double)tmin;
+            double ts = (ten <= tex && ten > R.tmin) ? (double)ten : (double)R.tmin;
             if (ts > (double)R.tmax) ts = (double)R.tmax;
             float t0f = (float)ts;
-            float lo_[3], ld_[3];
+            float ld_[3];
+            ox = (float)(od[0] + (double)t0f * dd[0]);
+            oy = (float)(od[1] + (double)t0f * dd[1]);
+            oz = (float)(od[2] + (double)t0f * dd[2]);
 #pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                lo_[r] = (float)(od[r] + (double)t0f * dd[r]);
-                ld_[r] = (float)dd[r];
-            }
-            ox = lo_[0]; oy = lo_[1]; oz = lo_[2];
-            lo3[0] = lo_[0]; lo3[1] = lo_[1]; lo3[2] = lo_[2];
+            for (int r = 0; r < 3; ++r) ld_[r] = (float)dd[r];
             ix = safe_rcp(ld_[0]); iy = safe_rcp(ld_[1]); iz = safe_rcp(ld_[2]);
             sh = make_shear(ld_);
             t0 = t0f;
-            tlo = tmin - t0;
+            tlo = R.tmin - t0;
             tlo = tlo - fabsf(tlo) * 1.2e-7f;
             thi = best - t0;
             thi = thi + fabsf(thi) * 2.4e-7f;
@@ -284,25 +339,27 @@ __device__ inline bool trace_ray(const RgNode<W> *__restrict__ tlas_nodes, const
             in_blas = true;
             st.push(kSentinel);
             cur = 0;
-            continue;
+            return false;
         } else {
             // bottom-level leaf: up to 8 triangles
             uint32_t f = rg_leaf_first(cur), n = rg_leaf_count(cur);
+            const float o3[3] = {ox, oy, oz};
             for (uint32_t j = 0; j < n; ++j) {
                 if (MODE == kCounts) ++h.n_tris;
-                const RgTri tri = tris[f + j];
-                float tl, u, v;
-                if (!tri_test(tri.v, lo3, sh, &tl, &u, &v)) continue;
+                const RgTri tri = gload<RgTri, rg_u2>(tris, f + j);
+                float T, det, V, Wv;
+                if (!tri_test(tri, o3, sh, tlo, thi, T, det, V, Wv)) continue;
+                float tl = T / det;
                 float tw = t0 + tl;
-                if (!(tw >= tmin) || !(tw <= best)) continue;
+                if (!(tw >= R.tmin) || !(tw <= best)) continue;
                 uint32_t pid = (MODE == kRender) ? (f + j) : tri.prim;
                 if (!ANY && tw == best && found) {
                     if (inst_id > h.inst || (inst_id == h.inst && pid >= h.prim)) continue;
                 }
                 found = true;
                 h.t = tw;
-                h.u = u;
-                h.v = v;
+                h.u = V / det;
+                h.v = Wv / det;
                 h.inst = inst_id;
                 h.prim = pid;
                 if (ANY) return true;
@@ -313,23 +370,17 @@ __device__ inline bool trace_ray(const RgNode<W> *__restrict__ tlas_nodes, const
         }
         // pop
         while (true) {
-            if (st.sp == 0) return found;
+            if (st.sp == 0) return true;
             uint32_t e = st.pop();
             if (e == kSentinel) {
-                in_blas = false;
-                nodes = tlas_nodes;
-                ox = R.o[0]; oy = R.o[1]; oz = R.o[2];
-                ix = widx; iy = widy; iz = widz;
-                t0 = 0.0f;
-                tlo = tmin;
-                thi = best;
+                world_frame();
                 continue;
             }
             cur = e;
-            break;
+            return false;
         }
     }
-}
+};
 
 }  // namespace rgt
 
