@@ -275,12 +275,72 @@ def bench_two_level(args, torch, rg, sg):
     return out, scene
 
 
+def bench_batched(args, torch, rg, sg):
+    """Plain per-frame dispatch (one rg_render per frame, one stream) versus one
+    batch (every pass one launch over all frames), same frames, same images."""
+    t0 = time.perf_counter()
+    scenes = sg.config_batched(n_scenes=args.scenes)
+    log(f"{len(scenes)} scenes, {sum(s.unique_tris() for s in scenes)} unique tris, "
+        f"{sum(s.width * s.height for s in scenes)} pixels ({time.perf_counter() - t0:.0f}s to generate)")
+    frames = []
+    for sc in scenes:
+        tl = rg.upload_scene(sc, width=args.width, leaf_max=args.leaf)
+        frames.append((tl, sc.materials, sc.camera, sc.light, sc.width, sc.height, sc.max_depth))
+    torch.cuda.synchronize()
+    # plain: one scratch buffer sized for the largest frame, reused frame after frame
+    need = max(rg.render_sizes(W, H, D, 0) for (_, _, _, _, W, H, D) in frames)
+    scratch = torch.empty(need, dtype=torch.uint8, device="cuda")
+    imgs = [torch.empty((H, W, 3), dtype=torch.float32, device="cuda") for (_, _, _, _, W, H, D) in frames]
+
+    def plain():
+        for (tl, m, c, l, W, H, D), img in zip(frames, imgs):
+            rg.render_into(tl, m, c, l, W, H, D, img, scratch)
+
+    batch = rg.Batch(frames)
+    _, st = batch.render(stats=True)
+    rays = st["rays_traced"] + st["shadow_rays"]
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps, (time.perf_counter() - w0) / steps * 1e3
+
+    ms_plain, wall_plain = timed(plain, max(1, args.steps // 4))
+    ms_batch, wall_batch = timed(batch.render, args.steps)
+    same = all(torch.equal(a, b) for a, b in zip(imgs, batch.images))
+    out = {
+        "metric": "Mrays/s closest-hit (primary+incoherent)",
+        "value": rays / (ms_batch * 1e-3) / 1e6, "unit": "Mrays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_batch,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched: {len(scenes)} scenes (triangles log-uniform 1e3..2e6, 1..128 instances, "
+                               "64^2..1024^2 pixels), Whitted depth 2, all rays of a frame",
+                   "rays_per_step": rays, "frames": len(scenes),
+                   "pixels": int(sum(s.width * s.height for s in scenes)),
+                   "unique_tris": int(sum(s.unique_tris() for s in scenes))},
+        "plain_mrays_s": rays / (ms_plain * 1e-3) / 1e6, "plain_ms": ms_plain, "plain_wall_ms": wall_plain,
+        "batched_mrays_s": rays / (ms_batch * 1e-3) / 1e6, "batched_ms": ms_batch, "batched_wall_ms": wall_batch,
+        "speedup": ms_plain / ms_batch, "images_identical": bool(same),
+        "roofline": None,
+    }
+    return out, scenes
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["incoherent", "two_level"], default="incoherent")
+    ap.add_argument("--workload", choices=["incoherent", "two_level", "batched"], default="incoherent")
+    ap.add_argument("--scenes", type=int, default=256, help="frames of the batched workload")
     ap.add_argument("--segments", type=int, default=560)
     ap.add_argument("--width", type=int, default=4)
     ap.add_argument("--leaf", type=int, default=2)
@@ -306,10 +366,14 @@ def main():
         if not args.no_cpu_baseline:
             log("timing the oracle on a sample")
             out["cpu_baseline"] = cpu_baseline_incoherent(scene, 64, args.cpu_seconds)
-    else:
+    elif args.workload == "two_level":
         out, scene = bench_two_level(args, torch, rg, sg)
         if not args.no_cpu_baseline:
             out["cpu_baseline"] = cpu_baseline_frame(scene, 128, args.cpu_seconds)
+    else:
+        out, scenes = bench_batched(args, torch, rg, sg)
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline_frame(scenes[0], 64, args.cpu_seconds)
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")

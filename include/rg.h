@@ -265,6 +265,46 @@ rg_status rg_render(const rg_tlas *tlas, const rg_material *mats /*host*/, int32
                     void *scratch, uint64_t scratch_bytes, void *stream,
                     rg_render_stats *stats /*host, nullable*/);
 
+/* ------------------------------------------------------------ batches */
+/* Many frames of different scenes and sizes rendered together: every pass of
+ * the Whitted recursion (closest hit, shading, shadow any hit, shadow
+ * resolve) is one launch over the rays of all frames, each ray carrying its
+ * frame.  Each image is bitwise the one rg_render gives for the same frame.
+ * All frames must use top levels of one width; mode must be 0. */
+typedef struct {
+    const rg_tlas *tlas;      /* host pointer to the frame's top level */
+    const rg_material *mats;  /* host array of n_mats */
+    int32_t n_mats;
+    rg_camera cam;
+    rg_light light;
+    int32_t width, height, max_depth, mode;
+    uint64_t seed;
+    float *image;             /* device float[height][width][3] */
+} rg_job;
+
+/* Filled by rg_batch_prepare; describes the prepared scratch buffer. */
+typedef struct {
+    void *scratch;
+    uint64_t scratch_bytes;
+    int32_t n_jobs, width, max_depth, n_mats;
+    int64_t total_pixels, capacity;
+    int64_t cap_at[RG_MAX_DEPTH + 1]; /* queue bound per depth */
+} rg_batch;
+
+/* Scratch bytes for a batch (host call).  Errors: RG_ERR_INVALID_ARG for a
+ * bad frame, RG_ERR_UNSUPPORTED for mixed widths, mode 1 or more than 2^31
+ * queue entries. */
+rg_status rg_batch_sizes(const rg_job *jobs /*host*/, int32_t n_jobs, uint64_t *scratch_bytes /*host*/);
+
+/* Copies the frame, top-level and material tables into `scratch` and fills
+ * *out.  Synchronous: the host arrays may be released when it returns. */
+rg_status rg_batch_prepare(const rg_job *jobs /*host*/, int32_t n_jobs, void *scratch, uint64_t scratch_bytes,
+                           void *stream, rg_batch *out /*host*/);
+
+/* Renders a prepared batch: kernel launches only, so a HIP graph can capture
+ * it (then stats must be NULL).  Asynchronous unless stats is non-NULL. */
+rg_status rg_batch_render(const rg_batch *batch /*host*/, void *stream, rg_render_stats *stats /*host, nullable*/);
+
 /* ------------------------------------------------ build verification */
 /* Runs the first build stages of rg_build_blas and copies their results out
  * for verification: keys uint64[n] and ids uint32[n] after the sort,

@@ -79,6 +79,18 @@ class TraceTune(ctypes.Structure):
     _fields_ = [("refill", c_i32), ("waves_per_cu", c_i32)]
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("tlas", c_p), ("mats", c_p), ("n_mats", c_i32), ("cam", CameraDesc), ("light", LightDesc),
+                ("width", c_i32), ("height", c_i32), ("max_depth", c_i32), ("mode", c_i32), ("seed", c_u64),
+                ("image", c_p)]
+
+
+class BatchDesc(ctypes.Structure):
+    _fields_ = [("scratch", c_p), ("scratch_bytes", c_u64), ("n_jobs", c_i32), ("width", c_i32),
+                ("max_depth", c_i32), ("n_mats", c_i32), ("total_pixels", c_i64), ("capacity", c_i64),
+                ("cap_at", c_i64 * (MAX_DEPTH + 1))]
+
+
 class RenderStats(ctypes.Structure):
     _fields_ = [("rays_traced", c_u64), ("shadow_rays", c_u64), ("ms_total", c_f)]
 
@@ -102,6 +114,9 @@ SIGNATURES = {
     "rg_render": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_u64, c_p, c_p, c_u64,
                           c_p, c_p]),
     "rg_lbvh_stages": (c_i32, [c_p, c_i64, c_p, c_i64, c_p, c_p, c_p, c_p, c_p, c_p, c_u64, c_p]),
+    "rg_batch_sizes": (c_i32, [c_p, c_i32, c_p]),
+    "rg_batch_prepare": (c_i32, [c_p, c_i32, c_p, c_u64, c_p, c_p]),
+    "rg_batch_render": (c_i32, [c_p, c_p, c_p]),
 }
 
 
@@ -414,6 +429,55 @@ class Renderer:
             return self.image, dict(rays_traced=int(st.rays_traced), shadow_rays=int(st.shadow_rays),
                                     ms_total=float(st.ms_total))
         return self.image
+
+
+class Batch:
+    """Many frames rendered together (rg_batch_*): `frames` is a list of
+    (tlas, materials, camera, light, width, height, max_depth) tuples.  Owns
+    the images and the scratch buffer; render() may be repeated, and is a
+    pure launch sequence (capturable in a HIP graph)."""
+
+    def __init__(self, frames, seed: int = 0, stream=None, device="cuda"):
+        torch = _torch()
+        self.frames = list(frames)
+        n = len(self.frames)
+        self.images = []
+        self._mats = []
+        jobs = (Job * n)()
+        for k, (tl, mats, cam, light, W, H, D) in enumerate(self.frames):
+            img = torch.empty((H, W, 3), dtype=torch.float32, device=device)
+            self.images.append(img)
+            ma = materials_array(mats)
+            self._mats.append(ma)
+            jobs[k] = Job(ctypes.addressof(tl.desc), ctypes.addressof(ma), len(mats), camera_desc(cam),
+                          light_desc(light), W, H, D, 0, seed, img.data_ptr())
+        need = ctypes.c_uint64()
+        _check("rg_batch_sizes", _lib.rg_batch_sizes(jobs, n, ctypes.byref(need)))
+        self.scratch = _bytes(need.value, device)
+        self.desc = BatchDesc()
+        _check("rg_batch_prepare", _lib.rg_batch_prepare(jobs, n, _ptr(self.scratch), self.scratch.numel(),
+                                                         _stream(stream), ctypes.byref(self.desc)))
+
+    def render(self, stats: bool = False, stream=None):
+        st = RenderStats()
+        _check("rg_batch_render", _lib.rg_batch_render(ctypes.byref(self.desc), _stream(stream),
+                                                       ctypes.byref(st) if stats else None))
+        if stats:
+            return self.images, dict(rays_traced=int(st.rays_traced), shadow_rays=int(st.shadow_rays),
+                                     ms_total=float(st.ms_total))
+        return self.images
+
+
+def render_into(tlas: Tlas, mats, camera, light, width: int, height: int, max_depth: int, image, scratch,
+                mode: int = 0, seed: int = 0, stream=None):
+    """rg_render into a caller-owned image [H, W, 3] with a caller-owned
+    scratch buffer (at least render_sizes(...) bytes)."""
+    ma = materials_array(mats)
+    cd, ld = camera_desc(camera), light_desc(light)
+    _check("rg_render", _lib.rg_render(tlas.ref, ma, len(mats), ctypes.byref(cd), ctypes.byref(ld), width, height,
+                                       max_depth, mode, seed, _ptr(image), _ptr(scratch), scratch.numel(),
+                                       _stream(stream), None))
+    return image
 
 
 def render(tlas: Tlas, mats, camera, light, width: int, height: int, max_depth: int, mode: int = 0,

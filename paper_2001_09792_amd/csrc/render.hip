@@ -13,6 +13,8 @@
 // ranks).  Pixel sums are 64-bit fixed point (2^32 per unit), so the image
 // is independent of the order in which waves append and add.
 #include <cmath>
+#include <cstring>
+#include <vector>
 
 #include "trace_core.h"
 
@@ -63,11 +65,9 @@ __device__ inline void camera_dir(const CamF &k, int W, int H, int64_t pixel, fl
 }
 
 __global__ void k_camera_rays(rg_camera cam, int W, int H, float *o0, float *o1, float *o2, float *d0, float *d1,
-                              float *d2, float *tmin, float *tmax, uint32_t *pix, float *b0, float *b1, float *b2,
-                              uint32_t *count) {
+                              float *d2, float *tmin, float *tmax) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int64_t n = (int64_t)W * H;
-    if (i == 0 && count) *count = (uint32_t)n;
     if (i >= n) return;
     CamF k = camera_basis(cam);
     float d[3];
@@ -76,10 +76,6 @@ __global__ void k_camera_rays(rg_camera cam, int W, int H, float *o0, float *o1,
     d0[i] = d[0]; d1[i] = d[1]; d2[i] = d[2];
     tmin[i] = 0.0f;
     tmax[i] = INFINITY;
-    if (pix) {
-        pix[i] = (uint32_t)i;
-        b0[i] = 1.0f; b1[i] = 1.0f; b2[i] = 1.0f;
-    }
 }
 
 // ------------------------------------------------------ hit geometry
@@ -131,14 +127,16 @@ __device__ inline void accum_add(unsigned long long *acc, uint32_t pixel, const 
 }
 
 // --------------------------------------------------------- queues
+// A queue entry is a ray plus its payload: the pixel (index into the batch's
+// accumulators), the frame (job) it belongs to and its throughput.
 struct Queue {
     float *ray[8];
-    uint32_t *pix;
+    uint32_t *pix, *job;
     float *beta[3];
 };
 struct ShadowQ {
     float *ray[8];
-    uint32_t *pix;
+    uint32_t *pix, *job;
     float *pend[3];
     uint8_t *occ;
 };
@@ -166,22 +164,60 @@ __device__ inline uint32_t wave_append(uint32_t *counter, uint32_t cnt) {
     return base + before;
 }
 
+// One frame of a batch as the kernels see it.
+struct RgJobDev {
+    rg_camera cam;
+    rg_light light;
+    uint32_t pix_off, width, height, mat_off, n_mats;
+    int32_t max_depth;
+    float *image;
+};
+
+// The frame owning accumulator index p (frames are stored in pix_off order).
+__device__ inline uint32_t find_job(const RgJobDev *jobs, int n_jobs, uint32_t p) {
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].pix_off <= p) lo = mid;
+        else hi = mid - 1;
+    }
+    return (uint32_t)lo;
+}
+
+__global__ void k_camera_batch(const RgJobDev *__restrict__ jobs, int n_jobs, int64_t total, Queue q,
+                               uint32_t *count) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i == 0) *count = (uint32_t)total;
+    if (i >= total) return;
+    uint32_t j = find_job(jobs, n_jobs, (uint32_t)i);
+    const RgJobDev &J = jobs[j];
+    CamF k = camera_basis(J.cam);
+    float d[3];
+    camera_dir(k, (int)J.width, (int)J.height, i - J.pix_off, d);
+    float o[3] = {k.eye[0], k.eye[1], k.eye[2]};
+    put_ray(q.ray, (uint32_t)i, o, d, 0.0f, INFINITY);
+    q.pix[i] = (uint32_t)i;
+    q.job[i] = j;
+    q.beta[0][i] = 1.0f;
+    q.beta[1][i] = 1.0f;
+    q.beta[2][i] = 1.0f;
+}
+
 struct ShadeArgs {
     Queue in;
     const uint32_t *count_in;
     const float *hit_t;
     const uint32_t *hit_rec, *hit_slot;
-    const RgInst *recs;
-    const RgMat *mats;
-    int32_t n_mats;
-    rg_light light;
-    int32_t depth, max_depth;
+    const RgTlasRef *tlas;  // per job
+    const RgJobDev *jobs;
+    const RgMat *mats;      // all jobs' materials, job j's at jobs[j].mat_off
+    int32_t depth;
     unsigned long long *acc;
     Queue out;
     uint32_t *count_out;
     ShadowQ sq;
     uint32_t *count_sq;
-    int64_t cap;
+    int64_t cap_out, cap_sq;
 };
 
 __global__ void __launch_bounds__(kT) k_shade(ShadeArgs a) {
@@ -191,9 +227,10 @@ __global__ void __launch_bounds__(kT) k_shade(ShadeArgs a) {
     uint32_t n_child = 0, n_shadow = 0;
     float co[2][3], cd[2][3], cb[2][3];
     float so[3], sd[3], sp[3];
-    uint32_t pixel = 0;
+    uint32_t pixel = 0, job = 0;
     if (active) {
         pixel = a.in.pix[i];
+        job = a.in.job[i];
         float beta[3] = {a.in.beta[0][i], a.in.beta[1][i], a.in.beta[2][i]};
         float o[3] = {a.in.ray[0][i], a.in.ray[1][i], a.in.ray[2][i]};
         float d[3] = {a.in.ray[3][i], a.in.ray[4][i], a.in.ray[5][i]};
@@ -206,27 +243,28 @@ __global__ void __launch_bounds__(kT) k_shade(ShadeArgs a) {
             float v[3] = {beta[0] * sky[0], beta[1] * sky[1], beta[2] * sky[2]};
             accum_add(a.acc, pixel, v);
         } else {
+            const RgJobDev &J = a.jobs[job];
             HitGeom g;
-            hit_geometry(a.recs, rec, a.hit_slot[i], o, d, a.hit_t[i], g);
-            uint32_t mid = g.mat < (uint32_t)a.n_mats ? g.mat : (uint32_t)(a.n_mats - 1);
-            const RgMat M = a.mats[mid];
+            hit_geometry(a.tlas[job].recs, rec, a.hit_slot[i], o, d, a.hit_t[i], g);
+            uint32_t mid = g.mat < J.n_mats ? g.mat : J.n_mats - 1;
+            const RgMat M = a.mats[J.mat_off + mid];
             float eps = offset_eps(g.p);
             if (M.type == 0) {
-                float amb[3] = {beta[0] * M.rgb[0] * a.light.ambient, beta[1] * M.rgb[1] * a.light.ambient,
-                                beta[2] * M.rgb[2] * a.light.ambient};
+                float amb[3] = {beta[0] * M.rgb[0] * J.light.ambient, beta[1] * M.rgb[1] * J.light.ambient,
+                                beta[2] * M.rgb[2] * J.light.ambient};
                 accum_add(a.acc, pixel, amb);
-                float l[3] = {a.light.pos[0] - g.p[0], a.light.pos[1] - g.p[1], a.light.pos[2] - g.p[2]};
+                float l[3] = {J.light.pos[0] - g.p[0], J.light.pos[1] - g.p[1], J.light.pos[2] - g.p[2]};
                 normalize3(l);
                 float c = dot3(g.nf, l);
                 if (c > 0.0f) {
                     n_shadow = 1;
                     for (int q = 0; q < 3; ++q) {
                         so[q] = g.p[q] + eps * g.nf[q];
-                        sd[q] = a.light.pos[q] - so[q];
-                        sp[q] = beta[q] * M.rgb[q] * a.light.intensity[q] * c;
+                        sd[q] = J.light.pos[q] - so[q];
+                        sp[q] = beta[q] * M.rgb[q] * J.light.intensity[q] * c;
                     }
                 }
-            } else if (a.depth < a.max_depth) {
+            } else if (a.depth < J.max_depth) {
                 float dnf = dot3(g.dn, g.nf);
                 for (int q = 0; q < 3; ++q) {
                     co[0][q] = g.p[q] + eps * g.nf[q];
@@ -267,16 +305,18 @@ __global__ void __launch_bounds__(kT) k_shade(ShadeArgs a) {
     uint32_t ss = wave_append(a.count_sq, n_shadow);
     for (uint32_t c = 0; c < n_child; ++c) {
         uint32_t j = cs + c;
-        if ((int64_t)j >= a.cap) break;  // the queue holds n 2^D entries: never reached
+        if ((int64_t)j >= a.cap_out) break;  // the queue holds sum n 2^D entries: never reached
         put_ray(a.out.ray, j, co[c], cd[c], 0.0f, INFINITY);
         a.out.pix[j] = pixel;
+        a.out.job[j] = job;
         a.out.beta[0][j] = cb[c][0];
         a.out.beta[1][j] = cb[c][1];
         a.out.beta[2][j] = cb[c][2];
     }
-    if (n_shadow && (int64_t)ss < a.cap) {
+    if (n_shadow && (int64_t)ss < a.cap_sq) {
         put_ray(a.sq.ray, ss, so, sd, 0.0f, 1.0f - 1e-4f);
         a.sq.pix[ss] = pixel;
+        a.sq.job[ss] = job;
         a.sq.pend[0][ss] = sp[0];
         a.sq.pend[1][ss] = sp[1];
         a.sq.pend[2][ss] = sp[2];
@@ -291,10 +331,13 @@ __global__ void k_shadow_resolve(ShadowQ sq, const uint32_t *count, unsigned lon
     accum_add(acc, sq.pix[i], v);
 }
 
-__global__ void k_resolve(const unsigned long long *acc, int64_t n, float *image) {
+__global__ void k_resolve_batch(const unsigned long long *acc, const RgJobDev *__restrict__ jobs, int n_jobs,
+                                int64_t total) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= 3 * n) return;
-    image[i] = (float)((double)acc[i] * (1.0 / 4294967296.0));
+    if (i >= total) return;
+    const RgJobDev &J = jobs[find_job(jobs, n_jobs, (uint32_t)i)];
+    int64_t local = i - J.pix_off;
+    for (int c = 0; c < 3; ++c) J.image[3 * local + c] = (float)((double)acc[3 * i + c] * (1.0 / 4294967296.0));
 }
 
 __global__ void k_zero_u64(unsigned long long *p, int64_t n) {
@@ -429,48 +472,69 @@ rg_status ao_generate(AoArgs a, hipStream_t st) {
 }
 
 // ------------------------------------------------------ scratch layout
-struct RenderBufs {
+// Whitted batches: accumulators, per-depth queue capacity, two ray queues
+// and a shadow queue with the job of every entry, hit arrays, counters and
+// the job / top-level / material tables uploaded by rg_batch_prepare.
+struct BatchBufs {
     unsigned long long *acc, *stat;
+    uint32_t *counts;
+    RgJobDev *jobs;
+    RgTlasRef *tlas;
+    RgMat *mats;
+    float *hit_t;
+    uint32_t *hit_rec, *hit_slot;
     Queue q[2];
     ShadowQ sq;
+};
+
+bool carve_batch(RgArena &A, int64_t total_pix, int64_t cap, int32_t n_jobs, int32_t n_mats, BatchBufs &b) {
+    b.acc = A.take<unsigned long long>(3 * total_pix);
+    b.stat = A.take<unsigned long long>(4);
+    b.counts = A.take<uint32_t>(8);
+    b.jobs = A.take<RgJobDev>(n_jobs);
+    b.tlas = A.take<RgTlasRef>(n_jobs);
+    b.mats = A.take<RgMat>(n_mats);
+    b.hit_t = A.take<float>(cap);
+    b.hit_rec = A.take<uint32_t>(cap);
+    b.hit_slot = A.take<uint32_t>(cap);
+    for (int k = 0; k < 2; ++k) {
+        for (int c = 0; c < 8; ++c) b.q[k].ray[c] = A.take<float>(cap);
+        b.q[k].pix = A.take<uint32_t>(cap);
+        b.q[k].job = A.take<uint32_t>(cap);
+        for (int c = 0; c < 3; ++c) b.q[k].beta[c] = A.take<float>(cap);
+    }
+    for (int c = 0; c < 8; ++c) b.sq.ray[c] = A.take<float>(cap);
+    b.sq.pix = A.take<uint32_t>(cap);
+    b.sq.job = A.take<uint32_t>(cap);
+    for (int c = 0; c < 3; ++c) b.sq.pend[c] = A.take<float>(cap);
+    b.sq.occ = A.take<uint8_t>(cap);
+    return !A.overflow();
+}
+
+// ambient occlusion (one frame)
+struct AoBufs {
+    unsigned long long *acc, *stat;
+    uint32_t *counts;
     float *hit_t;
-    uint32_t *hit_rec, *hit_slot, *counts;
-    RgMat *mats;
-    // ambient occlusion
+    uint32_t *hit_rec, *hit_slot;
+    float *cam[8];
     float *ao_ray[8];
     uint32_t *ao_src, *ao_blk;
     uint8_t *ao_occ;
 };
 
-int64_t queue_cap(int64_t n, int32_t D, int32_t mode) { return mode == 1 ? n : n << D; }
-
-bool carve(RgArena &A, int64_t n, int32_t D, int32_t mode, RenderBufs &b) {
-    int64_t cap = queue_cap(n, D, mode);
+bool carve_ao(RgArena &A, int64_t n, AoBufs &b) {
     b.acc = A.take<unsigned long long>(3 * n);
     b.stat = A.take<unsigned long long>(4);
     b.counts = A.take<uint32_t>(8);
-    b.mats = A.take<RgMat>(256);
-    b.hit_t = A.take<float>(cap);
-    b.hit_rec = A.take<uint32_t>(cap);
-    b.hit_slot = A.take<uint32_t>(cap);
-    int nq = mode == 1 ? 1 : 2;
-    for (int k = 0; k < nq; ++k) {
-        for (int c = 0; c < 8; ++c) b.q[k].ray[c] = A.take<float>(cap);
-        b.q[k].pix = A.take<uint32_t>(cap);
-        for (int c = 0; c < 3; ++c) b.q[k].beta[c] = A.take<float>(cap);
-    }
-    if (mode == 1) {
-        b.q[1] = b.q[0];
-        for (int c = 0; c < 8; ++c) b.ao_ray[c] = A.take<float>(8 * n);
-        b.ao_src = A.take<uint32_t>(8 * n);
-        b.ao_blk = A.take<uint32_t>(rg_blocks(n, kT));
-        b.ao_occ = A.take<uint8_t>(8 * n);
-    } else {
-        for (int c = 0; c < 8; ++c) b.sq.ray[c] = A.take<float>(cap);
-        b.sq.pix = A.take<uint32_t>(cap);
-        for (int c = 0; c < 3; ++c) b.sq.pend[c] = A.take<float>(cap);
-        b.sq.occ = A.take<uint8_t>(cap);
-    }
+    b.hit_t = A.take<float>(n);
+    b.hit_rec = A.take<uint32_t>(n);
+    b.hit_slot = A.take<uint32_t>(n);
+    for (int c = 0; c < 8; ++c) b.cam[c] = A.take<float>(n);
+    for (int c = 0; c < 8; ++c) b.ao_ray[c] = A.take<float>(8 * n);
+    b.ao_src = A.take<uint32_t>(8 * n);
+    b.ao_blk = A.take<uint32_t>(rg_blocks(n, kT));
+    b.ao_occ = A.take<uint8_t>(8 * n);
     return !A.overflow();
 }
 
@@ -485,6 +549,122 @@ RgTraceArgs trace_args(const rg_tlas *t) {
     return a;
 }
 
+struct BatchShape {
+    int64_t total_pix = 0, cap = 0;
+    int64_t cap_at[RG_MAX_DEPTH + 1] = {};
+    int32_t n_mats = 0, max_depth = 0, width = 0;
+};
+
+rg_status batch_shape(const rg_job *jobs, int32_t n_jobs, BatchShape &sh) {
+    if (!jobs || n_jobs < 1 || n_jobs > (1 << 20)) return RG_ERR_INVALID_ARG;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const rg_job &J = jobs[j];
+        if (!tlas_valid(J.tlas) || !J.mats || J.n_mats < 1 || J.n_mats > 65536 || !J.image) return RG_ERR_INVALID_ARG;
+        if (J.width < 1 || J.height < 1 || J.max_depth < 0 || J.max_depth > RG_MAX_DEPTH) return RG_ERR_INVALID_ARG;
+        if (J.mode != 0) return RG_ERR_UNSUPPORTED;  // ambient occlusion renders one frame at a time
+        if (sh.width == 0) sh.width = J.tlas->width;
+        if (J.tlas->width != sh.width) return RG_ERR_UNSUPPORTED;  // one traversal width per batch
+        if (!rg_trace_depth_ok(J.tlas)) return RG_ERR_UNSUPPORTED;
+        int64_t n = (int64_t)J.width * J.height;
+        sh.total_pix += n;
+        sh.cap += n << J.max_depth;
+        for (int k = 0; k <= RG_MAX_DEPTH; ++k) sh.cap_at[k] += n << (k < J.max_depth ? k : J.max_depth);
+        sh.n_mats += J.n_mats;
+        if (J.max_depth > sh.max_depth) sh.max_depth = J.max_depth;
+    }
+    if (sh.cap > (1ll << 31) || sh.total_pix > (1ll << 31)) return RG_ERR_UNSUPPORTED;
+    return RG_OK;
+}
+
+uint64_t batch_bytes(const BatchShape &sh, int32_t n_jobs) {
+    RgArena A{nullptr, 0, 0};
+    BatchBufs b;
+    carve_batch(A, sh.total_pix, sh.cap, n_jobs, sh.n_mats, b);
+    return A.used;
+}
+
+rg_status run_batch(const rg_batch *B, hipStream_t st) {
+    RgArena A{(char *)B->scratch, B->scratch_bytes, 0};
+    BatchBufs b;
+    if (!carve_batch(A, B->total_pixels, B->capacity, B->n_jobs, B->n_mats, b)) return RG_ERR_OUT_OF_MEMORY;
+    const int64_t total = B->total_pixels;
+    k_zero_u64<<<rg_blocks(3 * total, kT), kT, 0, st>>>(b.acc, 3 * total);
+    k_zero_u64<<<1, kT, 0, st>>>(b.stat, 4);
+    k_fill_u32<<<1, kT, 0, st>>>(b.counts, 0u, 8);
+    k_camera_batch<<<rg_blocks(total, kT), kT, 0, st>>>(b.jobs, B->n_jobs, total, b.q[0], b.counts + 0);
+    RG_LAUNCH_CHECK();
+    for (int k = 0; k <= B->max_depth; ++k) {
+        Queue &qin = b.q[k & 1], &qout = b.q[(k + 1) & 1];
+        uint32_t *cin = b.counts + (k & 1), *cout = b.counts + ((k + 1) & 1), *csq = b.counts + 2;
+        const int64_t cap_k = B->cap_at[k];
+        const int64_t cap_next = B->cap_at[k < RG_MAX_DEPTH ? k + 1 : k];
+        RgTraceArgs tc = {};
+        for (int c = 0; c < 8; ++c) tc.ray[c] = qin.ray[c];
+        tc.n = cap_k;
+        tc.count = cin;
+        tc.ray_job = qin.job;
+        tc.jobs = b.tlas;
+        tc.t = b.hit_t;
+        tc.inst = b.hit_rec;
+        tc.prim = b.hit_slot;
+        rg_status r = rg_trace_launch(B->width, false, rgt::kRender, tc, st);
+        if (r != RG_OK) return r;
+        k_stat_add<<<1, 1, 0, st>>>(b.stat, cin);
+        k_fill_u32<<<1, 64, 0, st>>>(cout, 0u, 1);
+        k_fill_u32<<<1, 64, 0, st>>>(csq, 0u, 1);
+        ShadeArgs sa;
+        sa.in = qin;
+        sa.count_in = cin;
+        sa.hit_t = b.hit_t;
+        sa.hit_rec = b.hit_rec;
+        sa.hit_slot = b.hit_slot;
+        sa.tlas = b.tlas;
+        sa.jobs = b.jobs;
+        sa.mats = b.mats;
+        sa.depth = k;
+        sa.acc = b.acc;
+        sa.out = qout;
+        sa.count_out = cout;
+        sa.sq = b.sq;
+        sa.count_sq = csq;
+        sa.cap_out = cap_next;
+        sa.cap_sq = cap_k;
+        k_shade<<<rg_blocks(cap_k, kT), kT, 0, st>>>(sa);
+        RG_LAUNCH_CHECK();
+        RgTraceArgs ts = {};
+        for (int c = 0; c < 8; ++c) ts.ray[c] = b.sq.ray[c];
+        ts.n = cap_k;
+        ts.count = csq;
+        ts.ray_job = b.sq.job;
+        ts.jobs = b.tlas;
+        ts.occluded = b.sq.occ;
+        r = rg_trace_launch(B->width, true, rgt::kRender, ts, st);
+        if (r != RG_OK) return r;
+        k_stat_add<<<1, 1, 0, st>>>(b.stat + 1, csq);
+        k_shadow_resolve<<<rg_blocks(cap_k, kT), kT, 0, st>>>(b.sq, csq, b.acc);
+        RG_LAUNCH_CHECK();
+    }
+    k_resolve_batch<<<rg_blocks(total, kT), kT, 0, st>>>(b.acc, b.jobs, B->n_jobs, total);
+    RG_LAUNCH_CHECK();
+    return RG_OK;
+}
+
+rg_status finish_stats(hipStream_t st, hipEvent_t e0, hipEvent_t e1, const unsigned long long *dstat,
+                       rg_render_stats *stats) {
+    RG_HIP(hipEventRecord(e1, st));
+    unsigned long long hs[2] = {0, 0};
+    RG_HIP(hipMemcpyAsync(hs, dstat, 16, hipMemcpyDeviceToHost, st));
+    RG_HIP(hipStreamSynchronize(st));
+    float ms = 0.0f;
+    RG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    stats->rays_traced = hs[0];
+    stats->shadow_rays = hs[1];
+    stats->ms_total = ms;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return RG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -495,8 +675,7 @@ rg_status rg_camera_rays(const rg_camera *cam, int32_t width, int32_t height, fl
         if (!rays[k]) return RG_ERR_INVALID_ARG;
     int64_t n = (int64_t)width * height;
     k_camera_rays<<<rg_blocks(n, kT), kT, 0, (hipStream_t)stream>>>(
-        *cam, width, height, rays[0], rays[1], rays[2], rays[3], rays[4], rays[5], rays[6], rays[7], nullptr, nullptr,
-        nullptr, nullptr, nullptr);
+        *cam, width, height, rays[0], rays[1], rays[2], rays[3], rays[4], rays[5], rays[6], rays[7]);
     RG_LAUNCH_CHECK();
     return RG_OK;
 }
@@ -538,15 +717,103 @@ rg_status rg_ao_rays(const rg_tlas *tlas, rg_rays rays, int64_t n, const uint32_
     return ao_generate(a, (hipStream_t)stream);
 }
 
+rg_status rg_batch_sizes(const rg_job *jobs, int32_t n_jobs, uint64_t *scratch_bytes) {
+    if (!scratch_bytes) return RG_ERR_INVALID_ARG;
+    BatchShape sh;
+    rg_status r = batch_shape(jobs, n_jobs, sh);
+    if (r != RG_OK) return r;
+    *scratch_bytes = batch_bytes(sh, n_jobs);
+    return RG_OK;
+}
+
+rg_status rg_batch_prepare(const rg_job *jobs, int32_t n_jobs, void *scratch, uint64_t scratch_bytes, void *stream,
+                           rg_batch *out) {
+    if (!scratch || !out) return RG_ERR_INVALID_ARG;
+    BatchShape sh;
+    rg_status r = batch_shape(jobs, n_jobs, sh);
+    if (r != RG_OK) return r;
+    if (scratch_bytes < batch_bytes(sh, n_jobs)) return RG_ERR_OUT_OF_MEMORY;
+    std::vector<RgJobDev> hj((size_t)n_jobs);
+    std::vector<RgTlasRef> ht((size_t)n_jobs);
+    std::vector<RgMat> hm((size_t)sh.n_mats);
+    uint32_t pix = 0, mo = 0;
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const rg_job &J = jobs[j];
+        hj[j].cam = J.cam;
+        hj[j].light = J.light;
+        hj[j].pix_off = pix;
+        hj[j].width = (uint32_t)J.width;
+        hj[j].height = (uint32_t)J.height;
+        hj[j].mat_off = mo;
+        hj[j].n_mats = (uint32_t)J.n_mats;
+        hj[j].max_depth = J.max_depth;
+        hj[j].image = J.image;
+        ht[j].nodes = (const char *)J.tlas->buf + J.tlas->nodes_off;
+        ht[j].recs = (const RgInst *)((const char *)J.tlas->buf + J.tlas->inst_off);
+        memcpy(&hm[mo], J.mats, sizeof(RgMat) * (size_t)J.n_mats);
+        pix += (uint32_t)(J.width * J.height);
+        mo += (uint32_t)J.n_mats;
+    }
+    rg_batch B = {};
+    B.scratch = scratch;
+    B.scratch_bytes = scratch_bytes;
+    B.n_jobs = n_jobs;
+    B.width = sh.width;
+    B.max_depth = sh.max_depth;
+    B.n_mats = sh.n_mats;
+    B.total_pixels = sh.total_pix;
+    B.capacity = sh.cap;
+    for (int k = 0; k <= RG_MAX_DEPTH; ++k) B.cap_at[k] = sh.cap_at[k];
+    RgArena A{(char *)scratch, scratch_bytes, 0};
+    BatchBufs b;
+    if (!carve_batch(A, sh.total_pix, sh.cap, n_jobs, sh.n_mats, b)) return RG_ERR_OUT_OF_MEMORY;
+    hipStream_t st = (hipStream_t)stream;
+    RG_HIP(hipMemcpyAsync(b.jobs, hj.data(), sizeof(RgJobDev) * hj.size(), hipMemcpyHostToDevice, st));
+    RG_HIP(hipMemcpyAsync(b.tlas, ht.data(), sizeof(RgTlasRef) * ht.size(), hipMemcpyHostToDevice, st));
+    RG_HIP(hipMemcpyAsync(b.mats, hm.data(), sizeof(RgMat) * hm.size(), hipMemcpyHostToDevice, st));
+    RG_HIP(hipStreamSynchronize(st));  // the host tables may go away once this returns
+    *out = B;
+    return RG_OK;
+}
+
+rg_status rg_batch_render(const rg_batch *batch, void *stream, rg_render_stats *stats) {
+    if (!batch || !batch->scratch || batch->n_jobs < 1) return RG_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (stats) {
+        RG_HIP(hipEventCreate(&e0));
+        RG_HIP(hipEventCreate(&e1));
+        RG_HIP(hipEventRecord(e0, st));
+    }
+    rg_status r = run_batch(batch, st);
+    if (r != RG_OK) return r;
+    if (stats) {
+        RgArena A{(char *)batch->scratch, batch->scratch_bytes, 0};
+        BatchBufs b;
+        carve_batch(A, batch->total_pixels, batch->capacity, batch->n_jobs, batch->n_mats, b);
+        return finish_stats(st, e0, e1, b.stat, stats);
+    }
+    return RG_OK;
+}
+
 rg_status rg_render_sizes(int32_t width, int32_t height, int32_t max_depth, int32_t mode, uint64_t *scratch_bytes) {
     if (!scratch_bytes || width < 1 || height < 1 || max_depth < 0 || max_depth > RG_MAX_DEPTH ||
         (mode != 0 && mode != 1))
         return RG_ERR_INVALID_ARG;
     int64_t n = (int64_t)width * height;
-    if (queue_cap(n, max_depth, mode) > (1ll << 31)) return RG_ERR_UNSUPPORTED;
+    if ((n << (mode == 1 ? 3 : max_depth)) > (1ll << 31)) return RG_ERR_UNSUPPORTED;
     RgArena A{nullptr, 0, 0};
-    RenderBufs b;
-    carve(A, n, max_depth, mode, b);
+    if (mode == 1) {
+        AoBufs b;
+        carve_ao(A, n, b);
+    } else {
+        BatchShape sh;
+        sh.total_pix = n;
+        sh.cap = n << max_depth;
+        sh.n_mats = 256;
+        BatchBufs b;
+        carve_batch(A, sh.total_pix, sh.cap, 1, sh.n_mats, b);
+    }
     *scratch_bytes = A.used;
     return RG_OK;
 }
@@ -563,126 +830,78 @@ rg_status rg_render(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats
     if (scratch_bytes < need) return RG_ERR_OUT_OF_MEMORY;
     if (!rg_trace_depth_ok(tlas)) return RG_ERR_UNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
-    int64_t n = (int64_t)width * height;
+    if (mode == 0) {
+        // one frame is a batch of one
+        rg_job J;
+        J.tlas = tlas;
+        J.mats = mats;
+        J.n_mats = n_mats;
+        J.cam = *cam;
+        J.light = *light;
+        J.width = width;
+        J.height = height;
+        J.max_depth = max_depth;
+        J.mode = 0;
+        J.seed = seed;
+        J.image = image;
+        rg_batch B;
+        r = rg_batch_prepare(&J, 1, scratch, scratch_bytes, stream, &B);
+        if (r != RG_OK) return r;
+        return rg_batch_render(&B, stream, stats);
+    }
+    const int64_t n = (int64_t)width * height;
     RgArena A{(char *)scratch, scratch_bytes, 0};
-    RenderBufs b;
-    if (!carve(A, n, max_depth, mode, b)) return RG_ERR_OUT_OF_MEMORY;
+    AoBufs b;
+    if (!carve_ao(A, n, b)) return RG_ERR_OUT_OF_MEMORY;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (stats) {
         RG_HIP(hipEventCreate(&e0));
         RG_HIP(hipEventCreate(&e1));
         RG_HIP(hipEventRecord(e0, st));
     }
-    RG_HIP(hipMemcpyAsync(b.mats, mats, sizeof(RgMat) * n_mats, hipMemcpyHostToDevice, st));
     k_zero_u64<<<rg_blocks(3 * n, kT), kT, 0, st>>>(b.acc, 3 * n);
     k_zero_u64<<<1, kT, 0, st>>>(b.stat, 4);
     k_fill_u32<<<1, kT, 0, st>>>(b.counts, 0u, 8);
-    Queue &q0 = b.q[0];
-    k_camera_rays<<<rg_blocks(n, kT), kT, 0, st>>>(*cam, width, height, q0.ray[0], q0.ray[1], q0.ray[2], q0.ray[3],
-                                                   q0.ray[4], q0.ray[5], q0.ray[6], q0.ray[7], q0.pix, q0.beta[0],
-                                                   q0.beta[1], q0.beta[2], b.counts + 0);
+    k_camera_rays<<<rg_blocks(n, kT), kT, 0, st>>>(*cam, width, height, b.cam[0], b.cam[1], b.cam[2], b.cam[3],
+                                                   b.cam[4], b.cam[5], b.cam[6], b.cam[7]);
     RG_LAUNCH_CHECK();
     RgTraceArgs ta = trace_args(tlas);
-    if (mode == 1) {
-        for (int c = 0; c < 8; ++c) ta.ray[c] = q0.ray[c];
-        ta.n = n;
-        ta.t = b.hit_t;
-        ta.inst = b.hit_rec;
-        ta.prim = b.hit_slot;
-        r = rg_trace_launch(tlas->width, false, rgt::kRender, ta, st);
-        if (r != RG_OK) return r;
-        AoArgs a = {};
-        for (int c = 0; c < 6; ++c) a.ray[c] = q0.ray[c];
-        a.n = n;
-        a.hit_a = b.hit_rec;
-        a.hit_b = b.hit_slot;
-        a.hit_t = b.hit_t;
-        a.recs = ta.recs;
-        a.seed = seed;
-        a.tmax = 5.0f;
-        for (int c = 0; c < 8; ++c) a.out[c] = b.ao_ray[c];
-        a.src = b.ao_src;
-        a.count = b.counts + 2;
-        a.block_off = b.ao_blk;
-        a.map = false;
-        r = ao_generate(a, st);
-        if (r != RG_OK) return r;
-        RgTraceArgs tb = trace_args(tlas);
-        for (int c = 0; c < 8; ++c) tb.ray[c] = b.ao_ray[c];
-        tb.n = 8 * n;
-        tb.count = b.counts + 2;
-        tb.occluded = b.ao_occ;
-        r = rg_trace_launch(tlas->width, true, rgt::kRender, tb, st);
-        if (r != RG_OK) return r;
-        k_ao_accum<<<rg_blocks(8 * n, kT), kT, 0, st>>>(b.ao_occ, b.ao_src, b.counts + 2, b.acc);
-        k_ao_resolve<<<rg_blocks(n, kT), kT, 0, st>>>(b.acc, b.hit_rec, n, image);
-        RG_LAUNCH_CHECK();
-        k_stat_add<<<1, 1, 0, st>>>(b.stat, b.counts + 0);
-        k_stat_add<<<1, 1, 0, st>>>(b.stat + 1, b.counts + 2);
-    } else {
-        for (int k = 0; k <= max_depth; ++k) {
-            Queue &qin = b.q[k & 1], &qout = b.q[(k + 1) & 1];
-            uint32_t *cin = b.counts + (k & 1), *cout = b.counts + ((k + 1) & 1), *csq = b.counts + 2;
-            int64_t cap_k = n << k;
-            RgTraceArgs tc = ta;
-            for (int c = 0; c < 8; ++c) tc.ray[c] = qin.ray[c];
-            tc.n = cap_k;
-            tc.count = cin;
-            tc.t = b.hit_t;
-            tc.inst = b.hit_rec;
-            tc.prim = b.hit_slot;
-            r = rg_trace_launch(tlas->width, false, rgt::kRender, tc, st);
-            if (r != RG_OK) return r;
-            k_stat_add<<<1, 1, 0, st>>>(b.stat, cin);
-            k_fill_u32<<<1, 64, 0, st>>>(cout, 0u, 1);
-            k_fill_u32<<<1, 64, 0, st>>>(csq, 0u, 1);
-            ShadeArgs sa;
-            sa.in = qin;
-            sa.count_in = cin;
-            sa.hit_t = b.hit_t;
-            sa.hit_rec = b.hit_rec;
-            sa.hit_slot = b.hit_slot;
-            sa.recs = ta.recs;
-            sa.mats = b.mats;
-            sa.n_mats = n_mats;
-            sa.light = *light;
-            sa.depth = k;
-            sa.max_depth = max_depth;
-            sa.acc = b.acc;
-            sa.out = qout;
-            sa.count_out = cout;
-            sa.sq = b.sq;
-            sa.count_sq = csq;
-            sa.cap = queue_cap(n, max_depth, mode);
-            k_shade<<<rg_blocks(cap_k, kT), kT, 0, st>>>(sa);
-            RG_LAUNCH_CHECK();
-            RgTraceArgs ts = ta;
-            for (int c = 0; c < 8; ++c) ts.ray[c] = b.sq.ray[c];
-            ts.n = cap_k;
-            ts.count = csq;
-            ts.occluded = b.sq.occ;
-            r = rg_trace_launch(tlas->width, true, rgt::kRender, ts, st);
-            if (r != RG_OK) return r;
-            k_stat_add<<<1, 1, 0, st>>>(b.stat + 1, csq);
-            k_shadow_resolve<<<rg_blocks(cap_k, kT), kT, 0, st>>>(b.sq, csq, b.acc);
-            RG_LAUNCH_CHECK();
-        }
-        k_resolve<<<rg_blocks(3 * n, kT), kT, 0, st>>>(b.acc, n, image);
-        RG_LAUNCH_CHECK();
-    }
-    if (stats) {
-        RG_HIP(hipEventRecord(e1, st));
-        unsigned long long hs[2] = {0, 0};
-        RG_HIP(hipMemcpyAsync(hs, b.stat, 16, hipMemcpyDeviceToHost, st));
-        RG_HIP(hipStreamSynchronize(st));
-        float ms = 0.0f;
-        RG_HIP(hipEventElapsedTime(&ms, e0, e1));
-        stats->rays_traced = hs[0];
-        stats->shadow_rays = hs[1];
-        stats->ms_total = ms;
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
-    }
+    for (int c = 0; c < 8; ++c) ta.ray[c] = b.cam[c];
+    ta.n = n;
+    ta.t = b.hit_t;
+    ta.inst = b.hit_rec;
+    ta.prim = b.hit_slot;
+    r = rg_trace_launch(tlas->width, false, rgt::kRender, ta, st);
+    if (r != RG_OK) return r;
+    AoArgs a = {};
+    for (int c = 0; c < 6; ++c) a.ray[c] = b.cam[c];
+    a.n = n;
+    a.hit_a = b.hit_rec;
+    a.hit_b = b.hit_slot;
+    a.hit_t = b.hit_t;
+    a.recs = ta.recs;
+    a.seed = seed;
+    a.tmax = 5.0f;
+    for (int c = 0; c < 8; ++c) a.out[c] = b.ao_ray[c];
+    a.src = b.ao_src;
+    a.count = b.counts + 2;
+    a.block_off = b.ao_blk;
+    a.map = false;
+    r = ao_generate(a, st);
+    if (r != RG_OK) return r;
+    RgTraceArgs tb = trace_args(tlas);
+    for (int c = 0; c < 8; ++c) tb.ray[c] = b.ao_ray[c];
+    tb.n = 8 * n;
+    tb.count = b.counts + 2;
+    tb.occluded = b.ao_occ;
+    r = rg_trace_launch(tlas->width, true, rgt::kRender, tb, st);
+    if (r != RG_OK) return r;
+    k_ao_accum<<<rg_blocks(8 * n, kT), kT, 0, st>>>(b.ao_occ, b.ao_src, b.counts + 2, b.acc);
+    k_ao_resolve<<<rg_blocks(n, kT), kT, 0, st>>>(b.acc, b.hit_rec, n, image);
+    RG_LAUNCH_CHECK();
+    k_stat_add<<<1, 1, 0, st>>>(b.stat, b.counts + 0);
+    k_stat_add<<<1, 1, 0, st>>>(b.stat + 1, b.counts + 2);
+    if (stats) return finish_stats(st, e0, e1, b.stat, stats);
     return RG_OK;
 }
 

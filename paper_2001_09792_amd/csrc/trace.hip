@@ -46,6 +46,11 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
                     R.tmin = a.ray[6][idx];
                     R.tmax = a.ray[7][idx];
                     ray_i = idx;
+                    if (a.ray_job) {
+                        const RgTlasRef J = a.jobs[a.ray_job[idx]];
+                        tr.tlas_nodes = reinterpret_cast<const RgNode<W> *>(J.nodes);
+                        tr.recs = J.recs;
+                    }
                     has = tr.begin(R);
                     finished = !has;  // empty interval: a miss without traversal
                 }

@@ -384,10 +384,18 @@ struct Tracer {
 
 }  // namespace rgt
 
+// A top level as the kernels need it.
+struct RgTlasRef {
+    const void *nodes;
+    const RgInst *recs;
+};
+
 // Arguments of the trace kernels (passed by value).
 struct RgTraceArgs {
     const void *nodes;             // top-level nodes
     const RgInst *recs;            // top-level instance records
+    const uint32_t *ray_job;       // per ray: index into jobs (nullable: all rays use nodes/recs)
+    const RgTlasRef *jobs;
     const float *ray[8];           // ox oy oz dx dy dz tmin tmax
     int64_t n;                     // number of rays (upper bound if `count` is set)
     const uint32_t *count;         // device count of rays (nullable)

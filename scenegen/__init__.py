@@ -157,34 +157,33 @@ def icosphere(level: int, radius: float = 1.0) -> Mesh:
     """Icosahedron, `level` midpoint subdivisions, projected to the sphere.
 
     20*4**level triangles, 10*4**level+2 vertices, counter-clockwise outward.
+    Each level splits every face (a, b, c) into (a, ab, ca), (b, bc, ab),
+    (c, ca, bc), (ab, bc, ca); edge midpoints are shared between faces.
     """
     t = (1.0 + math.sqrt(5.0)) / 2.0
-    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0),
-         (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
-         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
-    verts = [np.array(p, np.float64) / np.linalg.norm(p) for p in v]
-    faces = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11),
-             (1, 5, 9), (5, 11, 4), (11, 10, 2), (10, 7, 6), (7, 1, 8),
-             (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9),
-             (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    V = np.array([(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0),
+                  (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+                  (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)], np.float64)
+    V /= np.linalg.norm(V, axis=1, keepdims=True)
+    F = np.array([(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11),
+                  (1, 5, 9), (5, 11, 4), (11, 10, 2), (10, 7, 6), (7, 1, 8),
+                  (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9),
+                  (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)], np.int64)
     for _ in range(level):
-        cache = {}
-
-        def mid(i, j):
-            key = (i, j) if i < j else (j, i)
-            if key not in cache:
-                m = verts[i] + verts[j]
-                verts.append(m / np.linalg.norm(m))
-                cache[key] = len(verts) - 1
-            return cache[key]
-
-        nf = []
-        for a, b, c in faces:
-            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
-            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
-        faces = nf
-    V = np.array(verts) * radius
-    F = np.array(faces, dtype=np.int64)
+        m = F.shape[0]
+        E = np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]])   # ab, bc, ca
+        E.sort(axis=1)
+        uniq, inv = np.unique(E, axis=0, return_inverse=True)
+        inv = inv.reshape(-1)
+        mid = V[uniq[:, 0]] + V[uniq[:, 1]]
+        mid /= np.linalg.norm(mid, axis=1, keepdims=True)
+        base = V.shape[0]
+        V = np.concatenate([V, mid])
+        ab, bc, ca = base + inv[:m], base + inv[m:2 * m], base + inv[2 * m:]
+        a, b, c = F[:, 0], F[:, 1], F[:, 2]
+        F = np.stack([np.stack([a, ab, ca], -1), np.stack([b, bc, ab], -1),
+                      np.stack([c, ca, bc], -1), np.stack([ab, bc, ca], -1)], 1).reshape(-1, 3)
+    V = V * radius
     cen = (V[F[:, 0]] + V[F[:, 1]] + V[F[:, 2]]) / 3.0
     F = _orient_outward(V, F, cen)
     return Mesh(V.astype(np.float32), F.astype(np.uint32))
@@ -409,6 +408,47 @@ def config_incoherent(seed: int = 3, segments: int = 560, width: int = 1920,
                  meshes, xf, bid, np.zeros(n_inst, np.uint32), mats,
                  Camera((0.0, 0.0, 45.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 60.0),
                  Light((30.0, 50.0, 40.0)), width, height, 0, 1, seed)
+
+
+def _mesh_near(kind: int, tris: float, seed: int) -> Mesh:
+    """A mesh of the given kind (0 icosphere, 1 torus, 2 displaced grid) at
+    the resolution whose triangle count is nearest (in log) to `tris`."""
+    tris = max(tris, 20.0)
+    if kind == 0:
+        level = int(np.clip(np.round(math.log(tris / 20.0, 4)), 0, 9))
+        return icosphere(level)
+    m = int(max(3, round(math.sqrt(tris / 2.0))))
+    if kind == 1:
+        return torus(m, m, 1.0, 0.3)
+    return grid(m, m, 0.15, 4.0, seed)
+
+
+def config_batched(seed: int = 4, n_scenes: int = 256, tri_range=(1e3, 2e6), max_inst: int = 128,
+                   pix_range=(64 ** 2, 1024 ** 2), max_depth: int = 2) -> List[Scene]:
+    """Independent scenes of uneven size: triangles log-uniform in tri_range,
+    instances log-uniform in [1, max_inst] over min(instances, 4) meshes
+    (icosphere / torus / displaced grid, the triangle budget split evenly),
+    positions in [-c, c]^3 with c = 2 instances^(1/3), pixels log-uniform in
+    pix_range (square images), per-instance materials as in the two-level
+    scene, camera at (0, 0, 3c + 4) looking at the origin, depth 2."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    out = []
+    for k in range(n_scenes):
+        T = float(np.round(np.exp(rng.uniform(math.log(tri_range[0]), math.log(tri_range[1])))))
+        I = int(np.round(np.exp(rng.uniform(0.0, math.log(max_inst)))))
+        nb = min(I, 4)
+        meshes = [_mesh_near(b % 3, T / nb, seed * 100000 + k * 10 + b) for b in range(nb)]
+        c = 2.0 * I ** (1.0 / 3.0)
+        xf = random_instances(rng, I, extent=c)
+        mats = _random_materials(rng, I)
+        P = float(np.exp(rng.uniform(math.log(pix_range[0]), math.log(pix_range[1]))))
+        W = max(1, int(round(math.sqrt(P))))
+        cam = Camera((0.0, 0.0, 3.0 * c + 4.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 60.0)
+        light = Light((c + 5.0, 2.0 * c + 10.0, c + 8.0))
+        out.append(Scene(f"batched #{k}: {I} instances of {nb} meshes, {W}x{W}", meshes, xf,
+                         (np.arange(I) % nb).astype(np.uint32), np.arange(I, dtype=np.uint32), mats,
+                         cam, light, W, W, max_depth, 0, seed * 1000 + k))
+    return out
 
 
 # ----------------------------------------------------------------------------
