@@ -282,11 +282,41 @@ def bench_batched(args, torch, rg, sg):
     scenes = sg.config_batched(n_scenes=args.scenes)
     log(f"{len(scenes)} scenes, {sum(s.unique_tris() for s in scenes)} unique tris, "
         f"{sum(s.width * s.height for s in scenes)} pixels ({time.perf_counter() - t0:.0f}s to generate)")
-    frames = []
-    for sc in scenes:
-        tl = rg.upload_scene(sc, width=args.width, leaf_max=args.leaf)
-        frames.append((tl, sc.materials, sc.camera, sc.light, sc.width, sc.height, sc.max_depth))
-    torch.cuda.synchronize()
+    def build(sel, width, leaf):
+        out = []
+        for sc in sel:
+            tl = rg.upload_scene(sc, width=width, leaf_max=leaf)
+            out.append((tl, sc.materials, sc.camera, sc.light, sc.width, sc.height, sc.max_depth))
+        torch.cuda.synchronize()
+        return out
+
+    frames = build(scenes, args.width, args.leaf)
+    default_launch = rg.trace_tuning()
+    tuned = None
+    if args.autotune:
+        from paper_2001_09792_amd import autotune
+        sub = scenes[::max(1, len(scenes) // 32)]
+        built = {}
+
+        def measure(cfg):
+            key = (cfg["width"], cfg["leaf"])
+            if key not in built:
+                built[key] = build(sub, *key)
+            autotune.apply_launch(cfg)
+            b = rg.Batch(built[key])
+            _, st = b.render(stats=True)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(3):
+                b.render()
+            torch.cuda.synchronize()
+            return (st["rays_traced"] + st["shadow_rays"]) * 3 / (time.perf_counter() - t) / 1e6
+
+        tuned = autotune.tuned("batch", sum(s.width * s.height for s in scenes),
+                               sum(s.unique_tris() for s in scenes), measure, log=log)
+        log(f"autotuned: {tuned}")
+        built.clear()
+        rg.trace_tuning(**default_launch)
     # plain: one scratch buffer sized for the largest frame, reused frame after frame
     need = max(rg.render_sizes(W, H, D, 0) for (_, _, _, _, W, H, D) in frames)
     scratch = torch.empty(need, dtype=torch.uint8, device="cuda")
@@ -296,9 +326,13 @@ def bench_batched(args, torch, rg, sg):
         for (tl, m, c, l, W, H, D), img in zip(frames, imgs):
             rg.render_into(tl, m, c, l, W, H, D, img, scratch)
 
-    batch = rg.Batch(frames)
-    _, st = batch.render(stats=True)
-    rays = st["rays_traced"] + st["shadow_rays"]
+    if tuned is not None:
+        cfg = tuned["config"]
+        bframes = frames if (cfg["width"], cfg["leaf"]) == (args.width, args.leaf) else build(
+            scenes, cfg["width"], cfg["leaf"])
+    else:
+        bframes = frames
+    batch = rg.Batch(bframes)
 
     def timed(fn, steps):
         for _ in range(args.warmup):
@@ -313,7 +347,14 @@ def bench_batched(args, torch, rg, sg):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / steps, (time.perf_counter() - w0) / steps * 1e3
 
+    # plain: every frame with the default launch parameters
+    rg.trace_tuning(**default_launch)
     ms_plain, wall_plain = timed(plain, max(1, args.steps // 4))
+    if tuned is not None:
+        from paper_2001_09792_amd import autotune
+        autotune.apply_launch(tuned["config"])
+    _, st = batch.render(stats=True)
+    rays = st["rays_traced"] + st["shadow_rays"]
     ms_batch, wall_batch = timed(batch.render, args.steps)
     same = all(torch.equal(a, b) for a, b in zip(imgs, batch.images))
     out = {
@@ -329,6 +370,7 @@ def bench_batched(args, torch, rg, sg):
         "plain_mrays_s": rays / (ms_plain * 1e-3) / 1e6, "plain_ms": ms_plain, "plain_wall_ms": wall_plain,
         "batched_mrays_s": rays / (ms_batch * 1e-3) / 1e6, "batched_ms": ms_batch, "batched_wall_ms": wall_batch,
         "speedup": ms_plain / ms_batch, "images_identical": bool(same),
+        "autotuned": tuned, "plain_launch": default_launch, "batched_launch": rg.trace_tuning(),
         "roofline": None,
     }
     return out, scenes
@@ -341,11 +383,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["incoherent", "two_level", "batched"], default="incoherent")
     ap.add_argument("--scenes", type=int, default=256, help="frames of the batched workload")
+    ap.add_argument("--autotune", action="store_true", help="batched: tune width, leaf size and launch "
+                    "parameters on a subsample first (cached per GPU and size bucket)")
     ap.add_argument("--segments", type=int, default=560)
     ap.add_argument("--width", type=int, default=4)
     ap.add_argument("--leaf", type=int, default=2)
     ap.add_argument("--refill", type=int, default=None, help="traversal refill threshold (lanes)")
     ap.add_argument("--waves-per-cu", type=int, default=None, help="persistent traversal waves per CU")
+    ap.add_argument("--lds-depth", type=int, default=None, help="traversal stack entries per lane in LDS")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -360,7 +405,7 @@ def main():
     import paper_2001_09792_amd as rg
     import scenegen as sg
     assert torch.cuda.is_available(), "bench.py needs the GPU"
-    tune = rg.trace_tuning(args.refill, args.waves_per_cu)
+    tune = rg.trace_tuning(args.refill, args.waves_per_cu, args.lds_depth)
     if args.workload == "incoherent":
         out, scene = bench_incoherent(args, torch, rg, sg)
         if not args.no_cpu_baseline:

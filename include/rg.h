@@ -210,12 +210,14 @@ rg_status rg_trace_counts(const rg_tlas *tlas, rg_rays rays, int64_t n, int32_t 
 /* Launch parameters of the traversal kernels (process-wide).  The kernels
  * are persistent: the grid holds waves_per_cu waves per compute unit, each
  * wave walks its own interleaved sequence of 64-ray packets, and its lanes
- * take new rays together once `refill` of them (1..64) are idle.  Either
- * pointer may be NULL.  Errors: RG_ERR_INVALID_ARG for values out of range
- * (refill 1..64, waves_per_cu 4..64). */
+ * take new rays together once `refill` of them (1..64) are idle.  The first
+ * lds_depth (8..32) entries of each lane's traversal stack live in LDS, the
+ * rest in private memory.  Either pointer may be NULL.  Errors:
+ * RG_ERR_INVALID_ARG for values out of range. */
 typedef struct {
     int32_t refill;
     int32_t waves_per_cu;
+    int32_t lds_depth;
 } rg_trace_tune;
 rg_status rg_trace_tuning(const rg_trace_tune *set /*host, nullable*/, rg_trace_tune *get /*host, nullable*/);
 

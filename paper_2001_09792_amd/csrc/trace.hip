@@ -11,8 +11,8 @@ namespace {
 // that sequence together, once at least `refill` lanes are idle.  Rays of a
 // packet stay neighbours, and no lane idles while its wave has work left.
 template <int W, bool ANY, int MODE>
-__global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refill) {
-    __shared__ uint32_t lds_stack[rgt::kLdsStack * rgt::kThreads];
+__global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refill, int lds_depth) {
+    extern __shared__ uint32_t lds_stack[];  // lds_depth * kThreads entries
     const int lane = threadIdx.x & 63;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const int64_t n = a.count ? (int64_t)*a.count : a.n;
@@ -25,6 +25,7 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
     uint32_t priv_stack[rgt::kPrivStack];
     tr.st.lds = (uint32_t RG_LDS *)&lds_stack[threadIdx.x];
     tr.st.priv = priv_stack;
+    tr.st.n_lds = lds_depth;
     int64_t next = 0;  // position in this wave's ray sequence (the same in all lanes)
     int64_t ray_i = -1;
     bool has = false;
@@ -85,6 +86,7 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
 
 int g_refill = 8;         // lanes idle before a wave refills (tunable)
 int g_waves_per_cu = 16;  // resident waves per CU the grid is sized for
+int g_lds_depth = 16;     // traversal stack entries per lane in LDS
 
 unsigned persistent_blocks(int64_t n) {
     static int cus = 0;
@@ -102,16 +104,17 @@ unsigned persistent_blocks(int64_t n) {
 template <int W>
 rg_status launch_w(bool any, int mode, const RgTraceArgs &a, hipStream_t st) {
     unsigned blocks = persistent_blocks(a.n);
-    int refill = g_refill;
+    int refill = g_refill, lds = g_lds_depth;
+    size_t shm = (size_t)lds * rgt::kThreads * sizeof(uint32_t);
     if (mode == rgt::kCounts) {
-        if (any) k_trace<W, true, rgt::kCounts><<<blocks, rgt::kThreads, 0, st>>>(a, refill);
-        else k_trace<W, false, rgt::kCounts><<<blocks, rgt::kThreads, 0, st>>>(a, refill);
+        if (any) k_trace<W, true, rgt::kCounts><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds);
+        else k_trace<W, false, rgt::kCounts><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds);
     } else if (mode == rgt::kRender) {
-        if (any) k_trace<W, true, rgt::kRender><<<blocks, rgt::kThreads, 0, st>>>(a, refill);
-        else k_trace<W, false, rgt::kRender><<<blocks, rgt::kThreads, 0, st>>>(a, refill);
+        if (any) k_trace<W, true, rgt::kRender><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds);
+        else k_trace<W, false, rgt::kRender><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds);
     } else {
-        if (any) k_trace<W, true, rgt::kClosest><<<blocks, rgt::kThreads, 0, st>>>(a, refill);
-        else k_trace<W, false, rgt::kClosest><<<blocks, rgt::kThreads, 0, st>>>(a, refill);
+        if (any) k_trace<W, true, rgt::kClosest><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds);
+        else k_trace<W, false, rgt::kClosest><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds);
     }
     RG_LAUNCH_CHECK();
     return RG_OK;
@@ -150,14 +153,17 @@ extern "C" {
 
 rg_status rg_trace_tuning(const rg_trace_tune *set, rg_trace_tune *get) {
     if (set) {
-        if (set->refill < 1 || set->refill > 64 || set->waves_per_cu < 4 || set->waves_per_cu > 64)
+        if (set->refill < 1 || set->refill > 64 || set->waves_per_cu < 4 || set->waves_per_cu > 64 ||
+            set->lds_depth < 8 || set->lds_depth > rgt::kMaxLdsStack)
             return RG_ERR_INVALID_ARG;
         g_refill = set->refill;
         g_waves_per_cu = set->waves_per_cu;
+        g_lds_depth = set->lds_depth;
     }
     if (get) {
         get->refill = g_refill;
         get->waves_per_cu = g_waves_per_cu;
+        get->lds_depth = g_lds_depth;
     }
     return RG_OK;
 }

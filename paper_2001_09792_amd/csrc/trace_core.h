@@ -23,10 +23,10 @@
 
 namespace rgt {
 
-constexpr int kThreads = 256;   // threads per workgroup of the trace kernels
-constexpr int kLdsStack = 16;   // stack entries per lane kept in LDS
-constexpr int kPrivStack = 96;  // further entries per lane in private memory
-constexpr int kStackCap = kLdsStack + kPrivStack;
+constexpr int kThreads = 256;     // threads per workgroup of the trace kernels
+constexpr int kMaxLdsStack = 32;  // most stack entries per lane kept in LDS (chosen per launch)
+constexpr int kPrivStack = 96;    // further entries per lane in private memory
+constexpr int kStackCap = 8 + kPrivStack;  // guaranteed capacity (at the smallest LDS depth, 8)
 constexpr uint32_t kSentinel = 0xFFFFFFFEu;
 constexpr uint32_t kMaxSteps = 1u << 22;  // loop bound: far above any traversal of a valid hierarchy
 // The far distance of a slab is widened by 2 gamma_5 (gamma_n = n u / (1 - n u),
@@ -146,20 +146,21 @@ __device__ inline bool tri_test(const RgTri &tri, const float o[3], const Shear 
     return true;
 }
 
-// Stack with the first kLdsStack entries in LDS (lane-interleaved, so the
+// Stack with the first n_lds entries in LDS (lane-interleaved, so the
 // 64 lanes of a wave hit 64 different banks) and the rest in private memory.
 struct Stack {
     uint32_t RG_LDS *lds;  // base of this lane's column: lds[e * kThreads]
     uint32_t *priv;        // kPrivStack further entries (a private array of the kernel)
     int sp;
+    int n_lds;             // entries kept in LDS (8..kMaxLdsStack)
     __device__ inline void push(uint32_t v) {
-        if (sp < kLdsStack) lds[sp * kThreads] = v;
-        else priv[sp - kLdsStack] = v;
+        if (sp < n_lds) lds[sp * kThreads] = v;
+        else priv[sp - n_lds] = v;
         ++sp;
     }
     __device__ inline uint32_t pop() {
         --sp;
-        return sp < kLdsStack ? lds[sp * kThreads] : priv[sp - kLdsStack];
+        return sp < n_lds ? lds[sp * kThreads] : priv[sp - n_lds];
     }
 };
 
