@@ -307,6 +307,96 @@ rg_status rg_batch_prepare(const rg_job *jobs /*host*/, int32_t n_jobs, void *sc
  * it (then stats must be NULL).  Asynchronous unless stats is non-NULL. */
 rg_status rg_batch_render(const rg_batch *batch /*host*/, void *stream, rg_render_stats *stats /*host, nullable*/);
 
+/* ------------------------------------------------------------ serving */
+/* The paper's renderer serves frames one dispatch at a time and keeps loaded
+ * resources for reuse (section 2.2).  The engine below renders many frames
+ * at once with continuous batching: it runs the Whitted recursion as passes
+ * (closest hit, shading, shadow any hit, direct term) over the queued rays of
+ * every frame in flight, each frame at its own depth.  A frame admitted
+ * between passes queues its camera rays for the next pass; a frame leaves
+ * after the pass at its max_depth, when its image is written.  Top levels,
+ * bottom levels and images stay owned by the caller and must outlive the
+ * frame.  Each image is bitwise the one rg_render gives for the same frame,
+ * whatever else is in flight (64-bit fixed-point sums).
+ *
+ * Admission reserves, per frame, the queue entries one pass can hold for it
+ * at worst (rg_job_reservation) and a contiguous range of pixel
+ * accumulators; rg_pool is that accounting on its own (host only, no GPU
+ * calls), for schedulers and tests.  Neither object is thread-safe. */
+typedef struct rg_pool rg_pool;
+typedef struct {
+    int64_t rays, pixels, largest_free_pixels; /* reserved entries / pixels; largest free pixel range */
+    int32_t jobs, reserved;                    /* frames holding a slot */
+} rg_pool_usage;
+
+/* A pool of max_rays queue entries (<= 2^31), max_pixels accumulator pixels
+ * (<= 2^31) and max_jobs frame slots (<= 2^20).  Host call. */
+rg_status rg_pool_create(int64_t max_rays, int64_t max_pixels, int32_t max_jobs, rg_pool **out /*host*/);
+rg_status rg_pool_destroy(rg_pool *pool);
+/* Reserves `rays` entries, `pixels` contiguous pixels (first fit) and the
+ * lowest free slot.  *slot = -1 (RG_OK) when it does not fit now;
+ * RG_ERR_OUT_OF_MEMORY when it could not fit an empty pool. */
+rg_status rg_pool_reserve(rg_pool *pool, int64_t rays, int64_t pixels, int32_t *slot /*host*/,
+                          int64_t *pix_off /*host*/);
+/* Frees a slot's reservation (coalescing its pixel range). */
+rg_status rg_pool_release(rg_pool *pool, int32_t slot);
+rg_status rg_pool_get_usage(const rg_pool *pool, rg_pool_usage *out /*host*/);
+
+/* Worst-case queue entries of one pass for a frame, and its pixels: a glass
+ * hit spawns two children, a mirror hit one, a diffuse hit none, so a pass
+ * at depth k holds at most width*height*2^k entries of a frame whose
+ * materials include glass (width*height otherwise).  Host call. */
+rg_status rg_job_reservation(const rg_job *job /*host*/, int64_t *rays /*host*/, int64_t *pixels /*host*/);
+
+typedef struct {
+    int64_t max_rays;   /* queue entries per pass (<= 2^31) */
+    int64_t max_pixels; /* accumulator pixels of all frames in flight (<= 2^31) */
+    int32_t max_jobs;   /* frames in flight */
+    int32_t max_mats;   /* materials per frame */
+    int32_t width;      /* node width of every top level admitted */
+    int32_t reserved;
+} rg_engine_desc;
+
+typedef struct rg_engine rg_engine;
+typedef struct {
+    int64_t passes, passes_done;      /* passes enqueued / known complete */
+    int64_t frames_live;              /* admitted, not yet returned by poll */
+    int64_t frames_active;            /* with passes still to enqueue */
+    int64_t admitted, completed;
+    int64_t rays_reserved, pixels_reserved;
+    int64_t max_frames_in_pass;       /* most frames sharing one pass so far */
+    int64_t max_depths_in_pass;       /* most distinct recursion depths in one pass */
+} rg_engine_info;
+
+/* Scratch bytes of an engine (host call). */
+rg_status rg_engine_sizes(const rg_engine_desc *desc /*host*/, uint64_t *scratch_bytes /*host*/);
+/* Carves the engine's queues, accumulators and tables from `scratch` (the
+ * library allocates no device memory) and enqueues their reset on `stream`;
+ * every later call enqueues on the same stream. */
+rg_status rg_engine_create(const rg_engine_desc *desc /*host*/, void *scratch, uint64_t scratch_bytes,
+                           void *stream, rg_engine **out /*host*/);
+/* Waits for the stream, then frees the host object. */
+rg_status rg_engine_destroy(rg_engine *engine);
+/* Admits a frame (mode 0) if its reservation fits: writes its record and
+ * materials through kernel arguments (job->mats may go away on return),
+ * zeroes its accumulators and queues its camera rays for the next pass.
+ * *admitted = 0 when there is no room now (retry after a poll).  Errors:
+ * RG_ERR_OUT_OF_MEMORY when the frame exceeds the whole engine,
+ * RG_ERR_UNSUPPORTED for another node width or mode 1, RG_ERR_INVALID_ARG. */
+rg_status rg_engine_admit(rg_engine *engine, const rg_job *job /*host*/, int64_t tag, int32_t *admitted /*host*/);
+/* Enqueues one pass over every frame with passes left, and the image
+ * resolve of the frames whose last pass it is.  *ran = 0 (nothing enqueued)
+ * when no frame is active.  Blocks only when 32 passes are outstanding. */
+rg_status rg_engine_step(rg_engine *engine, int32_t *ran /*host, nullable*/);
+/* Returns up to `cap` tags of frames whose images are complete, in order of
+ * completion, and frees their reservations.  wait != 0 first waits for the
+ * oldest outstanding pass. */
+rg_status rg_engine_poll(rg_engine *engine, int32_t wait, int64_t *tags /*host*/, int32_t cap,
+                         int32_t *n_done /*host*/);
+rg_status rg_engine_get_info(const rg_engine *engine, rg_engine_info *out /*host*/);
+/* Rays traced since creation (closest-hit and shadow).  Synchronous. */
+rg_status rg_engine_stats(rg_engine *engine, rg_render_stats *stats /*host*/);
+
 /* ------------------------------------------------ build verification */
 /* Runs the first build stages of rg_build_blas and copies their results out
  * for verification: keys uint64[n] and ids uint32[n] after the sort,

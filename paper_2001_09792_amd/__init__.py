@@ -95,6 +95,22 @@ class RenderStats(ctypes.Structure):
     _fields_ = [("rays_traced", c_u64), ("shadow_rays", c_u64), ("ms_total", c_f)]
 
 
+class PoolUsage(ctypes.Structure):
+    _fields_ = [("rays", c_i64), ("pixels", c_i64), ("largest_free_pixels", c_i64), ("jobs", c_i32),
+                ("reserved", c_i32)]
+
+
+class EngineDesc(ctypes.Structure):
+    _fields_ = [("max_rays", c_i64), ("max_pixels", c_i64), ("max_jobs", c_i32), ("max_mats", c_i32),
+                ("width", c_i32), ("reserved", c_i32)]
+
+
+class EngineInfo(ctypes.Structure):
+    _fields_ = [(k, c_i64) for k in ("passes", "passes_done", "frames_live", "frames_active", "admitted",
+                                     "completed", "rays_reserved", "pixels_reserved", "max_frames_in_pass",
+                                     "max_depths_in_pass")]
+
+
 # name -> (restype, argtypes); every function of include/rg.h
 SIGNATURES = {
     "rg_status_string": (ctypes.c_char_p, [c_i32]),
@@ -117,6 +133,20 @@ SIGNATURES = {
     "rg_batch_sizes": (c_i32, [c_p, c_i32, c_p]),
     "rg_batch_prepare": (c_i32, [c_p, c_i32, c_p, c_u64, c_p, c_p]),
     "rg_batch_render": (c_i32, [c_p, c_p, c_p]),
+    "rg_pool_create": (c_i32, [c_i64, c_i64, c_i32, c_p]),
+    "rg_pool_destroy": (c_i32, [c_p]),
+    "rg_pool_reserve": (c_i32, [c_p, c_i64, c_i64, c_p, c_p]),
+    "rg_pool_release": (c_i32, [c_p, c_i32]),
+    "rg_pool_get_usage": (c_i32, [c_p, c_p]),
+    "rg_job_reservation": (c_i32, [c_p, c_p, c_p]),
+    "rg_engine_sizes": (c_i32, [c_p, c_p]),
+    "rg_engine_create": (c_i32, [c_p, c_p, c_u64, c_p, c_p]),
+    "rg_engine_destroy": (c_i32, [c_p]),
+    "rg_engine_admit": (c_i32, [c_p, c_p, c_i64, c_p]),
+    "rg_engine_step": (c_i32, [c_p, c_p]),
+    "rg_engine_poll": (c_i32, [c_p, c_i32, c_p, c_i32, c_p]),
+    "rg_engine_get_info": (c_i32, [c_p, c_p]),
+    "rg_engine_stats": (c_i32, [c_p, c_p]),
 }
 
 
@@ -394,7 +424,10 @@ def ao_rays(tlas: Tlas, rays, hits, seed: int, tmax: float = 5.0, out=None, src=
 
 
 def materials_array(mats) -> ctypes.Array:
-    """Structured numpy (type, rgb[3], ior) -> rg_material[]."""
+    """Structured numpy (type, rgb[3], ior) -> rg_material[] (an
+    rg_material[] passes through)."""
+    if isinstance(mats, ctypes.Array):
+        return mats
     arr = (Material * len(mats))()
     for i, m in enumerate(mats):
         arr[i].type = int(m["type"])
@@ -486,6 +519,135 @@ def render(tlas: Tlas, mats, camera, light, width: int, height: int, max_depth: 
            seed: int = 0, stream=None):
     r = Renderer(width, height, max_depth, mode)
     return r.render(tlas, mats, camera, light, seed, stream=stream).clone()
+
+
+# ------------------------------------------------------------ serving
+class Pool:
+    """Admission accounting of the serving engine (rg_pool_*): host only."""
+
+    def __init__(self, max_rays: int, max_pixels: int, max_jobs: int):
+        self.h = c_p()
+        _check("rg_pool_create", _lib.rg_pool_create(max_rays, max_pixels, max_jobs, ctypes.byref(self.h)))
+
+    def reserve(self, rays: int, pixels: int):
+        """(slot, pixel offset), or None when it does not fit now; raises
+        RgError (RG_ERR_OUT_OF_MEMORY) when it never fits."""
+        slot, off = c_i32(), c_i64()
+        _check("rg_pool_reserve", _lib.rg_pool_reserve(self.h, rays, pixels, ctypes.byref(slot), ctypes.byref(off)))
+        return None if slot.value < 0 else (slot.value, off.value)
+
+    def release(self, slot: int):
+        _check("rg_pool_release", _lib.rg_pool_release(self.h, slot))
+
+    def usage(self) -> dict:
+        u = PoolUsage()
+        _check("rg_pool_get_usage", _lib.rg_pool_get_usage(self.h, ctypes.byref(u)))
+        return dict(rays=u.rays, pixels=u.pixels, largest_free_pixels=u.largest_free_pixels, jobs=u.jobs)
+
+    def close(self):
+        if self.h:
+            _lib.rg_pool_destroy(self.h)
+            self.h = c_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def job_struct(tlas_desc_addr: int, mats, cam, light, width: int, height: int, max_depth: int,
+               image_ptr: int = 0, mode: int = 0, seed: int = 0):
+    """An rg_job; `mats` is a materials_array (kept alive by the caller)."""
+    return Job(tlas_desc_addr, ctypes.addressof(mats), len(mats), camera_desc(cam), light_desc(light), width,
+               height, max_depth, mode, seed, image_ptr)
+
+
+def job_reservation(mats, width: int, height: int, max_depth: int):
+    """(queue entries per pass at worst, pixels) of a frame (rg_job_reservation)."""
+    ma = mats if isinstance(mats, ctypes.Array) else materials_array(mats)
+    j = Job(None, ctypes.addressof(ma), len(ma), CameraDesc(), LightDesc(), width, height, max_depth, 0, 0, None)
+    rays, pix = c_i64(), c_i64()
+    _check("rg_job_reservation", _lib.rg_job_reservation(ctypes.byref(j), ctypes.byref(rays), ctypes.byref(pix)))
+    return rays.value, pix.value
+
+
+def engine_sizes(max_rays: int, max_pixels: int, max_jobs: int = 64, max_mats: int = 256, width: int = 4) -> int:
+    d = EngineDesc(max_rays, max_pixels, max_jobs, max_mats, width, 0)
+    need = c_u64()
+    _check("rg_engine_sizes", _lib.rg_engine_sizes(ctypes.byref(d), ctypes.byref(need)))
+    return int(need.value)
+
+
+class Engine:
+    """Continuous-batching renderer (rg_engine_*).  Owns its scratch buffer;
+    frames are admitted with a tag and come back from poll() when complete.
+    All work goes to one stream (the current one at construction)."""
+
+    def __init__(self, max_rays: int, max_pixels: int, max_jobs: int = 64, max_mats: int = 256, width: int = 4,
+                 stream=None, device="cuda"):
+        torch = _torch()
+        self.desc = EngineDesc(max_rays, max_pixels, max_jobs, max_mats, width, 0)
+        self.scratch = _bytes(engine_sizes(max_rays, max_pixels, max_jobs, max_mats, width), device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.h = c_p()
+        _check("rg_engine_create", _lib.rg_engine_create(ctypes.byref(self.desc), _ptr(self.scratch),
+                                                         self.scratch.numel(), _stream(self.stream),
+                                                         ctypes.byref(self.h)))
+        self._tags = (c_i64 * 4096)()
+
+    @staticmethod
+    def for_budget(budget_bytes: int, max_jobs: int = 64, max_mats: int = 256, width: int = 4) -> dict:
+        """Largest max_rays (= max_pixels) whose engine fits budget_bytes."""
+        unit = 1 << 20
+        s1 = engine_sizes(unit, unit, max_jobs, max_mats, width)
+        s2 = engine_sizes(2 * unit, 2 * unit, max_jobs, max_mats, width)
+        per = (s2 - s1) / unit
+        n = int(min((budget_bytes - (s1 - per * unit)) / per, 1 << 31))
+        while n > 64 and engine_sizes(n, n, max_jobs, max_mats, width) > budget_bytes:
+            n = int(n * 0.999)
+        if n < 64:
+            raise ValueError(f"a budget of {budget_bytes} bytes holds no engine")
+        return dict(max_rays=n, max_pixels=n, max_jobs=max_jobs, max_mats=max_mats, width=width)
+
+    def admit(self, tlas: Tlas, mats, cam, light, width: int, height: int, max_depth: int, image, tag: int) -> bool:
+        ma = mats if isinstance(mats, ctypes.Array) else materials_array(mats)
+        j = job_struct(ctypes.addressof(tlas.desc), ma, cam, light, width, height, max_depth, _ptr(image))
+        ok = c_i32()
+        _check("rg_engine_admit", _lib.rg_engine_admit(self.h, ctypes.byref(j), tag, ctypes.byref(ok)))
+        return bool(ok.value)
+
+    def step(self) -> bool:
+        ran = c_i32()
+        _check("rg_engine_step", _lib.rg_engine_step(self.h, ctypes.byref(ran)))
+        return bool(ran.value)
+
+    def poll(self, wait: bool = False) -> List[int]:
+        n = c_i32()
+        _check("rg_engine_poll", _lib.rg_engine_poll(self.h, 1 if wait else 0, self._tags, len(self._tags),
+                                                     ctypes.byref(n)))
+        return [int(self._tags[i]) for i in range(n.value)]
+
+    def info(self) -> dict:
+        i = EngineInfo()
+        _check("rg_engine_get_info", _lib.rg_engine_get_info(self.h, ctypes.byref(i)))
+        return {k: int(getattr(i, k)) for k, _ in EngineInfo._fields_}
+
+    def stats(self) -> dict:
+        st = RenderStats()
+        _check("rg_engine_stats", _lib.rg_engine_stats(self.h, ctypes.byref(st)))
+        return dict(rays_traced=int(st.rays_traced), shadow_rays=int(st.shadow_rays))
+
+    def close(self):
+        if self.h:
+            h, self.h = self.h, c_p()
+            _check("rg_engine_destroy", _lib.rg_engine_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def lbvh_stages(verts, idx, stream=None) -> dict:

@@ -16,7 +16,7 @@
 #include <cstring>
 #include <vector>
 
-#include "trace_core.h"
+#include "wavefront.h"
 
 namespace {
 
@@ -127,20 +127,6 @@ __device__ inline void accum_add(unsigned long long *acc, uint32_t pixel, const 
 }
 
 // --------------------------------------------------------- queues
-// A queue entry is a ray plus its payload: the pixel (index into the batch's
-// accumulators), the frame (job) it belongs to and its throughput.
-struct Queue {
-    float *ray[8];
-    uint32_t *pix, *job;
-    float *beta[3];
-};
-struct ShadowQ {
-    float *ray[8];
-    uint32_t *pix, *job;
-    float *pend[3];
-    uint8_t *occ;
-};
-
 __device__ inline void put_ray(float *const ray[8], uint32_t j, const float o[3], const float d[3], float tmin,
                                float tmax) {
     ray[0][j] = o[0]; ray[1][j] = o[1]; ray[2][j] = o[2];
@@ -164,15 +150,6 @@ __device__ inline uint32_t wave_append(uint32_t *counter, uint32_t cnt) {
     return base + before;
 }
 
-// One frame of a batch as the kernels see it.
-struct RgJobDev {
-    rg_camera cam;
-    rg_light light;
-    uint32_t pix_off, width, height, mat_off, n_mats;
-    int32_t max_depth;
-    float *image;
-};
-
 // The frame owning accumulator index p (frames are stored in pix_off order).
 __device__ inline uint32_t find_job(const RgJobDev *jobs, int n_jobs, uint32_t p) {
     int lo = 0, hi = n_jobs - 1;
@@ -184,7 +161,7 @@ __device__ inline uint32_t find_job(const RgJobDev *jobs, int n_jobs, uint32_t p
     return (uint32_t)lo;
 }
 
-__global__ void k_camera_batch(const RgJobDev *__restrict__ jobs, int n_jobs, int64_t total, Queue q,
+__global__ void k_camera_batch(const RgJobDev *__restrict__ jobs, int n_jobs, int64_t total, RgQueue q,
                                uint32_t *count) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i == 0) *count = (uint32_t)total;
@@ -204,18 +181,18 @@ __global__ void k_camera_batch(const RgJobDev *__restrict__ jobs, int n_jobs, in
 }
 
 struct ShadeArgs {
-    Queue in;
+    RgQueue in;
     const uint32_t *count_in;
     const float *hit_t;
     const uint32_t *hit_rec, *hit_slot;
     const RgTlasRef *tlas;  // per job
     const RgJobDev *jobs;
     const RgMat *mats;      // all jobs' materials, job j's at jobs[j].mat_off
-    int32_t depth;
+    int64_t pass;           // entry depth = pass - jobs[job].start
     unsigned long long *acc;
-    Queue out;
+    RgQueue out;
     uint32_t *count_out;
-    ShadowQ sq;
+    RgShadowQ sq;
     uint32_t *count_sq;
     int64_t cap_out, cap_sq;
 };
@@ -264,7 +241,7 @@ __global__ void __launch_bounds__(kT) k_shade(ShadeArgs a) {
                         sp[q] = beta[q] * M.rgb[q] * J.light.intensity[q] * c;
                     }
                 }
-            } else if (a.depth < J.max_depth) {
+            } else if (a.pass - J.start < (int64_t)J.max_depth) {
                 float dnf = dot3(g.dn, g.nf);
                 for (int q = 0; q < 3; ++q) {
                     co[0][q] = g.p[q] + eps * g.nf[q];
@@ -323,7 +300,7 @@ __global__ void __launch_bounds__(kT) k_shade(ShadeArgs a) {
     }
 }
 
-__global__ void k_shadow_resolve(ShadowQ sq, const uint32_t *count, unsigned long long *acc) {
+__global__ void k_shadow_resolve(RgShadowQ sq, const uint32_t *count, unsigned long long *acc) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= (int64_t)*count) return;
     if (sq.occ[i]) return;
@@ -346,6 +323,49 @@ __global__ void k_zero_u64(unsigned long long *p, int64_t n) {
 }
 
 __global__ void k_stat_add(unsigned long long *stat, const uint32_t *count) { *stat += *count; }
+
+// Frame record and materials written through kernel arguments: nothing
+// for the host to keep alive, nothing to wait for, capturable.
+__global__ void k_put_job(RgJobDev *jobs, RgTlasRef *tlas, uint32_t slot, RgJobDev J, RgTlasRef T) {
+    if (threadIdx.x == 0) {
+        jobs[slot] = J;
+        tlas[slot] = T;
+    }
+}
+
+constexpr int kMatChunk = 64;
+struct MatChunk {
+    RgMat m[kMatChunk];
+};
+__global__ void k_put_mats(RgMat *dst, MatChunk c, int n) {
+    if ((int)threadIdx.x < n) dst[threadIdx.x] = c.m[threadIdx.x];
+}
+
+// Appends one camera ray per pixel of frame `slot` (one atomic per wave).
+__global__ void __launch_bounds__(kT) k_camera_job(RgJobDev J, uint32_t slot, RgQueue q, uint32_t *count,
+                                                   int64_t cap) {
+    int64_t i = blockIdx.x * (int64_t)kT + threadIdx.x;
+    const int64_t n = (int64_t)J.width * J.height;
+    const bool on = i < n;
+    uint32_t at = wave_append(count, on ? 1u : 0u);
+    if (!on || (int64_t)at >= cap) return;
+    CamF k = camera_basis(J.cam);
+    float d[3];
+    camera_dir(k, (int)J.width, (int)J.height, i, d);
+    float o[3] = {k.eye[0], k.eye[1], k.eye[2]};
+    put_ray(q.ray, at, o, d, 0.0f, INFINITY);
+    q.pix[at] = J.pix_off + (uint32_t)i;
+    q.job[at] = slot;
+    q.beta[0][at] = 1.0f;
+    q.beta[1][at] = 1.0f;
+    q.beta[2][at] = 1.0f;
+}
+
+__global__ void k_resolve_job(const unsigned long long *acc, int64_t n, float *image) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= 3 * n) return;
+    image[i] = (float)((double)acc[i] * (1.0 / 4294967296.0));
+}
 
 // -------------------------------------------------- ambient occlusion
 __device__ inline uint64_t splitmix_out(uint64_t z) {
@@ -472,45 +492,6 @@ rg_status ao_generate(AoArgs a, hipStream_t st) {
 }
 
 // ------------------------------------------------------ scratch layout
-// Whitted batches: accumulators, per-depth queue capacity, two ray queues
-// and a shadow queue with the job of every entry, hit arrays, counters and
-// the job / top-level / material tables uploaded by rg_batch_prepare.
-struct BatchBufs {
-    unsigned long long *acc, *stat;
-    uint32_t *counts;
-    RgJobDev *jobs;
-    RgTlasRef *tlas;
-    RgMat *mats;
-    float *hit_t;
-    uint32_t *hit_rec, *hit_slot;
-    Queue q[2];
-    ShadowQ sq;
-};
-
-bool carve_batch(RgArena &A, int64_t total_pix, int64_t cap, int32_t n_jobs, int32_t n_mats, BatchBufs &b) {
-    b.acc = A.take<unsigned long long>(3 * total_pix);
-    b.stat = A.take<unsigned long long>(4);
-    b.counts = A.take<uint32_t>(8);
-    b.jobs = A.take<RgJobDev>(n_jobs);
-    b.tlas = A.take<RgTlasRef>(n_jobs);
-    b.mats = A.take<RgMat>(n_mats);
-    b.hit_t = A.take<float>(cap);
-    b.hit_rec = A.take<uint32_t>(cap);
-    b.hit_slot = A.take<uint32_t>(cap);
-    for (int k = 0; k < 2; ++k) {
-        for (int c = 0; c < 8; ++c) b.q[k].ray[c] = A.take<float>(cap);
-        b.q[k].pix = A.take<uint32_t>(cap);
-        b.q[k].job = A.take<uint32_t>(cap);
-        for (int c = 0; c < 3; ++c) b.q[k].beta[c] = A.take<float>(cap);
-    }
-    for (int c = 0; c < 8; ++c) b.sq.ray[c] = A.take<float>(cap);
-    b.sq.pix = A.take<uint32_t>(cap);
-    b.sq.job = A.take<uint32_t>(cap);
-    for (int c = 0; c < 3; ++c) b.sq.pend[c] = A.take<float>(cap);
-    b.sq.occ = A.take<uint8_t>(cap);
-    return !A.overflow();
-}
-
 // ambient occlusion (one frame)
 struct AoBufs {
     unsigned long long *acc, *stat;
@@ -578,71 +559,24 @@ rg_status batch_shape(const rg_job *jobs, int32_t n_jobs, BatchShape &sh) {
 
 uint64_t batch_bytes(const BatchShape &sh, int32_t n_jobs) {
     RgArena A{nullptr, 0, 0};
-    BatchBufs b;
-    carve_batch(A, sh.total_pix, sh.cap, n_jobs, sh.n_mats, b);
+    RgWaveBufs b;
+    rg_wave_carve(A, sh.total_pix, sh.cap, n_jobs, sh.n_mats, b);
     return A.used;
 }
 
 rg_status run_batch(const rg_batch *B, hipStream_t st) {
     RgArena A{(char *)B->scratch, B->scratch_bytes, 0};
-    BatchBufs b;
-    if (!carve_batch(A, B->total_pixels, B->capacity, B->n_jobs, B->n_mats, b)) return RG_ERR_OUT_OF_MEMORY;
+    RgWaveBufs b;
+    if (!rg_wave_carve(A, B->total_pixels, B->capacity, B->n_jobs, B->n_mats, b)) return RG_ERR_OUT_OF_MEMORY;
     const int64_t total = B->total_pixels;
     k_zero_u64<<<rg_blocks(3 * total, kT), kT, 0, st>>>(b.acc, 3 * total);
-    k_zero_u64<<<1, kT, 0, st>>>(b.stat, 4);
-    k_fill_u32<<<1, kT, 0, st>>>(b.counts, 0u, 8);
+    rg_status r = rg_wave_reset(b, st);
+    if (r != RG_OK) return r;
     k_camera_batch<<<rg_blocks(total, kT), kT, 0, st>>>(b.jobs, B->n_jobs, total, b.q[0], b.counts + 0);
     RG_LAUNCH_CHECK();
     for (int k = 0; k <= B->max_depth; ++k) {
-        Queue &qin = b.q[k & 1], &qout = b.q[(k + 1) & 1];
-        uint32_t *cin = b.counts + (k & 1), *cout = b.counts + ((k + 1) & 1), *csq = b.counts + 2;
-        const int64_t cap_k = B->cap_at[k];
-        const int64_t cap_next = B->cap_at[k < RG_MAX_DEPTH ? k + 1 : k];
-        RgTraceArgs tc = {};
-        for (int c = 0; c < 8; ++c) tc.ray[c] = qin.ray[c];
-        tc.n = cap_k;
-        tc.count = cin;
-        tc.ray_job = qin.job;
-        tc.jobs = b.tlas;
-        tc.t = b.hit_t;
-        tc.inst = b.hit_rec;
-        tc.prim = b.hit_slot;
-        rg_status r = rg_trace_launch(B->width, false, rgt::kRender, tc, st);
+        r = rg_wave_pass(b, B->width, k, B->cap_at[k], st);
         if (r != RG_OK) return r;
-        k_stat_add<<<1, 1, 0, st>>>(b.stat, cin);
-        k_fill_u32<<<1, 64, 0, st>>>(cout, 0u, 1);
-        k_fill_u32<<<1, 64, 0, st>>>(csq, 0u, 1);
-        ShadeArgs sa;
-        sa.in = qin;
-        sa.count_in = cin;
-        sa.hit_t = b.hit_t;
-        sa.hit_rec = b.hit_rec;
-        sa.hit_slot = b.hit_slot;
-        sa.tlas = b.tlas;
-        sa.jobs = b.jobs;
-        sa.mats = b.mats;
-        sa.depth = k;
-        sa.acc = b.acc;
-        sa.out = qout;
-        sa.count_out = cout;
-        sa.sq = b.sq;
-        sa.count_sq = csq;
-        sa.cap_out = cap_next;
-        sa.cap_sq = cap_k;
-        k_shade<<<rg_blocks(cap_k, kT), kT, 0, st>>>(sa);
-        RG_LAUNCH_CHECK();
-        RgTraceArgs ts = {};
-        for (int c = 0; c < 8; ++c) ts.ray[c] = b.sq.ray[c];
-        ts.n = cap_k;
-        ts.count = csq;
-        ts.ray_job = b.sq.job;
-        ts.jobs = b.tlas;
-        ts.occluded = b.sq.occ;
-        r = rg_trace_launch(B->width, true, rgt::kRender, ts, st);
-        if (r != RG_OK) return r;
-        k_stat_add<<<1, 1, 0, st>>>(b.stat + 1, csq);
-        k_shadow_resolve<<<rg_blocks(cap_k, kT), kT, 0, st>>>(b.sq, csq, b.acc);
-        RG_LAUNCH_CHECK();
     }
     k_resolve_batch<<<rg_blocks(total, kT), kT, 0, st>>>(b.acc, b.jobs, B->n_jobs, total);
     RG_LAUNCH_CHECK();
@@ -666,6 +600,121 @@ rg_status finish_stats(hipStream_t st, hipEvent_t e0, hipEvent_t e1, const unsig
 }
 
 }  // namespace
+
+// ------------------------------------------------ wavefront passes
+bool rg_wave_carve(RgArena &A, int64_t pixels, int64_t cap, int64_t n_jobs, int64_t n_mats, RgWaveBufs &b) {
+    b.acc = A.take<unsigned long long>(3 * pixels);
+    b.stat = A.take<unsigned long long>(4);
+    b.counts = A.take<uint32_t>(8);
+    b.jobs = A.take<RgJobDev>(n_jobs);
+    b.tlas = A.take<RgTlasRef>(n_jobs);
+    b.mats = A.take<RgMat>(n_mats);
+    b.hit_t = A.take<float>(cap);
+    b.hit_rec = A.take<uint32_t>(cap);
+    b.hit_slot = A.take<uint32_t>(cap);
+    for (int k = 0; k < 2; ++k) {
+        for (int c = 0; c < 8; ++c) b.q[k].ray[c] = A.take<float>(cap);
+        b.q[k].pix = A.take<uint32_t>(cap);
+        b.q[k].job = A.take<uint32_t>(cap);
+        for (int c = 0; c < 3; ++c) b.q[k].beta[c] = A.take<float>(cap);
+    }
+    for (int c = 0; c < 8; ++c) b.sq.ray[c] = A.take<float>(cap);
+    b.sq.pix = A.take<uint32_t>(cap);
+    b.sq.job = A.take<uint32_t>(cap);
+    for (int c = 0; c < 3; ++c) b.sq.pend[c] = A.take<float>(cap);
+    b.sq.occ = A.take<uint8_t>(cap);
+    b.cap = cap;
+    return !A.overflow();
+}
+
+rg_status rg_wave_reset(const RgWaveBufs &b, hipStream_t st) {
+    k_zero_u64<<<1, kT, 0, st>>>(b.stat, 4);
+    k_fill_u32<<<1, kT, 0, st>>>(b.counts, 0u, 8);
+    RG_LAUNCH_CHECK();
+    return RG_OK;
+}
+
+rg_status rg_wave_put_job(const RgWaveBufs &b, uint32_t slot, const RgJobDev &J, const RgTlasRef &T,
+                          const rg_material *host_mats, int32_t n_mats, hipStream_t st) {
+    k_put_job<<<1, 64, 0, st>>>(b.jobs, b.tlas, slot, J, T);
+    for (int32_t c = 0; c < n_mats; c += kMatChunk) {
+        MatChunk m;
+        const int cnt = n_mats - c < kMatChunk ? n_mats - c : kMatChunk;
+        memcpy(m.m, host_mats + c, sizeof(RgMat) * (size_t)cnt);
+        k_put_mats<<<1, kMatChunk, 0, st>>>(b.mats + J.mat_off + c, m, cnt);
+    }
+    const int64_t n = 3 * (int64_t)J.width * J.height;
+    k_zero_u64<<<rg_blocks(n, kT), kT, 0, st>>>(b.acc + 3 * (uint64_t)J.pix_off, n);
+    RG_LAUNCH_CHECK();
+    return RG_OK;
+}
+
+rg_status rg_wave_camera(const RgWaveBufs &b, uint32_t slot, const RgJobDev &J, int queue, hipStream_t st) {
+    const int64_t n = (int64_t)J.width * J.height;
+    k_camera_job<<<rg_blocks(n, kT), kT, 0, st>>>(J, slot, b.q[queue & 1], b.counts + (queue & 1), b.cap);
+    RG_LAUNCH_CHECK();
+    return RG_OK;
+}
+
+rg_status rg_wave_pass(const RgWaveBufs &b, int32_t width, int64_t pass, int64_t bound, hipStream_t st) {
+    if (bound < 1) return RG_OK;
+    if (bound > b.cap) bound = b.cap;
+    const RgQueue &qin = b.q[pass & 1], &qout = b.q[(pass + 1) & 1];
+    uint32_t *cin = b.counts + (pass & 1), *cout = b.counts + ((pass + 1) & 1), *csq = b.counts + 2;
+    RgTraceArgs tc = {};
+    for (int c = 0; c < 8; ++c) tc.ray[c] = qin.ray[c];
+    tc.n = bound;
+    tc.count = cin;
+    tc.ray_job = qin.job;
+    tc.jobs = b.tlas;
+    tc.t = b.hit_t;
+    tc.inst = b.hit_rec;
+    tc.prim = b.hit_slot;
+    rg_status r = rg_trace_launch(width, false, rgt::kRender, tc, st);
+    if (r != RG_OK) return r;
+    k_stat_add<<<1, 1, 0, st>>>(b.stat, cin);
+    k_fill_u32<<<1, 64, 0, st>>>(cout, 0u, 1);
+    k_fill_u32<<<1, 64, 0, st>>>(csq, 0u, 1);
+    ShadeArgs sa;
+    sa.in = qin;
+    sa.count_in = cin;
+    sa.hit_t = b.hit_t;
+    sa.hit_rec = b.hit_rec;
+    sa.hit_slot = b.hit_slot;
+    sa.tlas = b.tlas;
+    sa.jobs = b.jobs;
+    sa.mats = b.mats;
+    sa.pass = pass;
+    sa.acc = b.acc;
+    sa.out = qout;
+    sa.count_out = cout;
+    sa.sq = b.sq;
+    sa.count_sq = csq;
+    sa.cap_out = b.cap;
+    sa.cap_sq = b.cap;
+    k_shade<<<rg_blocks(bound, kT), kT, 0, st>>>(sa);
+    RG_LAUNCH_CHECK();
+    RgTraceArgs ts = {};
+    for (int c = 0; c < 8; ++c) ts.ray[c] = b.sq.ray[c];
+    ts.n = bound;
+    ts.count = csq;
+    ts.ray_job = b.sq.job;
+    ts.jobs = b.tlas;
+    ts.occluded = b.sq.occ;
+    r = rg_trace_launch(width, true, rgt::kRender, ts, st);
+    if (r != RG_OK) return r;
+    k_stat_add<<<1, 1, 0, st>>>(b.stat + 1, csq);
+    k_shadow_resolve<<<rg_blocks(bound, kT), kT, 0, st>>>(b.sq, csq, b.acc);
+    RG_LAUNCH_CHECK();
+    return RG_OK;
+}
+
+rg_status rg_wave_resolve(const RgWaveBufs &b, const RgJobDev &J, hipStream_t st) {
+    const int64_t n = (int64_t)J.width * J.height;
+    k_resolve_job<<<rg_blocks(3 * n, kT), kT, 0, st>>>(b.acc + 3 * (uint64_t)J.pix_off, n, J.image);
+    RG_LAUNCH_CHECK();
+    return RG_OK;
+}
 
 extern "C" {
 
@@ -747,6 +796,7 @@ rg_status rg_batch_prepare(const rg_job *jobs, int32_t n_jobs, void *scratch, ui
         hj[j].mat_off = mo;
         hj[j].n_mats = (uint32_t)J.n_mats;
         hj[j].max_depth = J.max_depth;
+        hj[j].start = 0;
         hj[j].image = J.image;
         ht[j].nodes = (const char *)J.tlas->buf + J.tlas->nodes_off;
         ht[j].recs = (const RgInst *)((const char *)J.tlas->buf + J.tlas->inst_off);
@@ -765,8 +815,8 @@ rg_status rg_batch_prepare(const rg_job *jobs, int32_t n_jobs, void *scratch, ui
     B.capacity = sh.cap;
     for (int k = 0; k <= RG_MAX_DEPTH; ++k) B.cap_at[k] = sh.cap_at[k];
     RgArena A{(char *)scratch, scratch_bytes, 0};
-    BatchBufs b;
-    if (!carve_batch(A, sh.total_pix, sh.cap, n_jobs, sh.n_mats, b)) return RG_ERR_OUT_OF_MEMORY;
+    RgWaveBufs b;
+    if (!rg_wave_carve(A, sh.total_pix, sh.cap, n_jobs, sh.n_mats, b)) return RG_ERR_OUT_OF_MEMORY;
     hipStream_t st = (hipStream_t)stream;
     RG_HIP(hipMemcpyAsync(b.jobs, hj.data(), sizeof(RgJobDev) * hj.size(), hipMemcpyHostToDevice, st));
     RG_HIP(hipMemcpyAsync(b.tlas, ht.data(), sizeof(RgTlasRef) * ht.size(), hipMemcpyHostToDevice, st));
@@ -789,8 +839,8 @@ rg_status rg_batch_render(const rg_batch *batch, void *stream, rg_render_stats *
     if (r != RG_OK) return r;
     if (stats) {
         RgArena A{(char *)batch->scratch, batch->scratch_bytes, 0};
-        BatchBufs b;
-        carve_batch(A, batch->total_pixels, batch->capacity, batch->n_jobs, batch->n_mats, b);
+        RgWaveBufs b;
+        rg_wave_carve(A, batch->total_pixels, batch->capacity, batch->n_jobs, batch->n_mats, b);
         return finish_stats(st, e0, e1, b.stat, stats);
     }
     return RG_OK;
@@ -807,12 +857,8 @@ rg_status rg_render_sizes(int32_t width, int32_t height, int32_t max_depth, int3
         AoBufs b;
         carve_ao(A, n, b);
     } else {
-        BatchShape sh;
-        sh.total_pix = n;
-        sh.cap = n << max_depth;
-        sh.n_mats = 256;
-        BatchBufs b;
-        carve_batch(A, sh.total_pix, sh.cap, 1, sh.n_mats, b);
+        RgWaveBufs b;
+        rg_wave_carve(A, n, n << max_depth, 1, 256, b);
     }
     *scratch_bytes = A.used;
     return RG_OK;
@@ -831,23 +877,36 @@ rg_status rg_render(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats
     if (!rg_trace_depth_ok(tlas)) return RG_ERR_UNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
     if (mode == 0) {
-        // one frame is a batch of one
-        rg_job J;
-        J.tlas = tlas;
-        J.mats = mats;
-        J.n_mats = n_mats;
+        // one frame: the record goes in through kernel arguments, so the
+        // whole frame is launches only (no host wait unless stats)
+        const int64_t n = (int64_t)width * height;
+        RgArena A{(char *)scratch, scratch_bytes, 0};
+        RgWaveBufs b;
+        if (!rg_wave_carve(A, n, n << max_depth, 1, 256, b)) return RG_ERR_OUT_OF_MEMORY;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (stats) {
+            RG_HIP(hipEventCreate(&e0));
+            RG_HIP(hipEventCreate(&e1));
+            RG_HIP(hipEventRecord(e0, st));
+        }
+        RgJobDev J = {};
         J.cam = *cam;
         J.light = *light;
-        J.width = width;
-        J.height = height;
+        J.width = (uint32_t)width;
+        J.height = (uint32_t)height;
+        J.n_mats = (uint32_t)n_mats;
         J.max_depth = max_depth;
-        J.mode = 0;
-        J.seed = seed;
         J.image = image;
-        rg_batch B;
-        r = rg_batch_prepare(&J, 1, scratch, scratch_bytes, stream, &B);
-        if (r != RG_OK) return r;
-        return rg_batch_render(&B, stream, stats);
+        RgTlasRef T = {(const char *)tlas->buf + tlas->nodes_off,
+                       (const RgInst *)((const char *)tlas->buf + tlas->inst_off)};
+        if ((r = rg_wave_reset(b, st)) != RG_OK) return r;
+        if ((r = rg_wave_put_job(b, 0, J, T, mats, n_mats, st)) != RG_OK) return r;
+        if ((r = rg_wave_camera(b, 0, J, 0, st)) != RG_OK) return r;
+        for (int k = 0; k <= max_depth; ++k)
+            if ((r = rg_wave_pass(b, tlas->width, k, n << k, st)) != RG_OK) return r;
+        if ((r = rg_wave_resolve(b, J, st)) != RG_OK) return r;
+        if (stats) return finish_stats(st, e0, e1, b.stat, stats);
+        return RG_OK;
     }
     const int64_t n = (int64_t)width * height;
     RgArena A{(char *)scratch, scratch_bytes, 0};

@@ -15,7 +15,8 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
     extern __shared__ uint32_t lds_stack[];  // lds_depth * kThreads entries
     const int lane = threadIdx.x & 63;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    const int64_t n = a.count ? (int64_t)*a.count : a.n;
+    // a device count never exceeds the launch size (the queue capacity)
+    const int64_t n = a.count ? ((int64_t)*a.count < a.n ? (int64_t)*a.count : a.n) : a.n;
     const int64_t n_packets = (n + 63) >> 6;
     const int64_t wave = ((int64_t)blockIdx.x * rgt::kThreads + threadIdx.x) >> 6;
     const int64_t n_waves = (int64_t)gridDim.x * (rgt::kThreads / 64);

@@ -410,6 +410,33 @@ def config_incoherent(seed: int = 3, segments: int = 560, width: int = 1920,
                  Light((30.0, 50.0, 40.0)), width, height, 0, 1, seed)
 
 
+def serving_c3_scene(seed: int, meshes: List[Mesh], width: int = 1920, height: int = 1080,
+                     max_depth: int = 4) -> Scene:
+    """A Whitted scene over the 16 displaced tori: 1,024 instances placed as
+    in the incoherent configuration, each with one of 64 random diffuse /
+    mirror / glass materials."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    n_inst = 1024
+    xf = random_instances(rng, n_inst)
+    bid = rng.integers(0, len(meshes), n_inst).astype(np.uint32)
+    mats = _random_materials(rng, 64)
+    return Scene(f"serving C3-type: 1024 instances of {len(meshes)} shared tori, Whitted",
+                 meshes, xf, bid, (np.arange(n_inst) % 64).astype(np.uint32), mats,
+                 Camera((0.0, 0.0, 45.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 60.0),
+                 Light((30.0, 50.0, 40.0)), width, height, max_depth, 0, seed)
+
+
+def config_serving_pool(c3_segments: int = 560, n_c2: int = 32, n_c3: int = 32) -> List[Scene]:
+    """The serving pool: n_c2 two-level scenes (seeds 5000...) with their own
+    meshes, then n_c3 scenes (seeds 5100...) that share the 16 tori of
+    c3_meshes(c3_segments) and differ in instances and materials."""
+    pool = [config_two_level(seed=5000 + k) for k in range(n_c2)]
+    if n_c3:
+        shared = c3_meshes(c3_segments)
+        pool += [serving_c3_scene(5100 + k, shared) for k in range(n_c3)]
+    return pool
+
+
 def _mesh_near(kind: int, tris: float, seed: int) -> Mesh:
     """A mesh of the given kind (0 icosphere, 1 torus, 2 displaced grid) at
     the resolution whose triangle count is nearest (in log) to `tris`."""
