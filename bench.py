@@ -14,8 +14,9 @@ hit, reflection and refraction passes), value = all rays traced / frame time.
 
 One JSON line is printed.  `roofline` refers to the dominant kernel (the
 closest-hit traversal of the AO rays): algorithmic bytes per ray from the
-traversal's own visit counts (rays 32 B + hit 20 B + nodes x 128 B +
-triangles x 40 B + instances x 80 B) over the kernel's event-timed duration,
+traversal's own visit counts (rays 32 B + hit 20 B + nodes x 28W B (the
+node without its padding: 112 B at width 4) + triangles x 40 B + instance
+records x 112 B) over the kernel's event-timed duration,
 against 8 TB/s.  `cpu_baseline` is the FP64 oracle timed on a bounded sample
 of the same rays on this host's cores.
 """
@@ -32,8 +33,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-NODE_BYTES = {2: 64, 4: 128, 8: 256}
-TRI_BYTES, INST_BYTES, RAY_BYTES, HIT_BYTES = 40, 80, 32, 20
+NODE_BYTES = {2: 56, 4: 112, 8: 224}  # 28 W: the node without its padding
+TRI_BYTES, INST_BYTES, RAY_BYTES, HIT_BYTES = 40, 112, 32, 20
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ao_closest.json")

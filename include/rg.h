@@ -98,12 +98,13 @@ typedef struct {
 
 /* Top-level structure.  Layout of `buf`:
  *   nodes_off: nodes as above; leaves hold one instance each.
- *   inst_off:  n_inst 80-byte records in leaf order:
+ *   inst_off:  n_inst 112-byte records in leaf order:
  *              float inv[9] (world->object linear part, row-major),
  *              float p[3] (object->world translation),
  *              uint64 blas_nodes, blas_tris, blas_header (device addresses),
  *              uint32 material (RG_PER_PRIM = per primitive), uint32 inst
- *              (index in the input).
+ *              (index in the input), float blas_lo[3], blas_hi[3] (the
+ *              bottom level's root box), 8 bytes of padding.
  *   rec_off:   uint32 per input instance: its record's position.
  * It refers to the bottom levels' buffers, which must outlive it. */
 typedef struct {

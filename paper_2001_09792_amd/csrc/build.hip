@@ -511,6 +511,12 @@ __global__ void k_inst_setup(const float *__restrict__ xform, const uint32_t *__
     r.hdr = B.hdr;
     r.mat = inst_mat[i];
     r.inst = (uint32_t)i;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        r.blo[q] = B.lo[q];
+        r.bhi[q] = B.hi[q];
+    }
+    r.pad[0] = r.pad[1] = 0u;
     recs[i] = r;
 }
 

@@ -150,6 +150,41 @@ __device__ inline uint32_t wave_append(uint32_t *counter, uint32_t cnt) {
     return base + before;
 }
 
+// Block-wide append of two counts per thread (0..2 to `a`, 0..1 to `b`):
+// ballot ranks inside each wave, wave totals in LDS, one atomic per counter
+// per block.  Every thread of the block must call it.
+constexpr int kShadeT = 512;
+__device__ inline void block_append2(uint32_t *ctr_a, uint32_t cnt_a, uint32_t *ctr_b, uint32_t cnt_b,
+                                     uint32_t &pos_a, uint32_t &pos_b) {
+    constexpr int NW = kShadeT / 64;
+    __shared__ uint32_t wa[NW], wb[NW], base[2];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const uint64_t a1 = __ballot(cnt_a >= 1u), a2 = __ballot(cnt_a >= 2u), b1 = __ballot(cnt_b >= 1u);
+    const uint32_t ra = (uint32_t)(__popcll(a1 & lt) + __popcll(a2 & lt)), rb = (uint32_t)__popcll(b1 & lt);
+    if (lane == 0) {
+        wa[w] = (uint32_t)(__popcll(a1) + __popcll(a2));
+        wb[w] = (uint32_t)__popcll(b1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t sa = 0, sb = 0;
+        for (int k = 0; k < NW; ++k) {
+            uint32_t ta = wa[k], tb = wb[k];
+            wa[k] = sa;
+            wb[k] = sb;
+            sa += ta;
+            sb += tb;
+        }
+        base[0] = sa ? atomicAdd(ctr_a, sa) : 0u;
+        base[1] = sb ? atomicAdd(ctr_b, sb) : 0u;
+    }
+    __syncthreads();
+    pos_a = base[0] + wa[w] + ra;
+    pos_b = base[1] + wb[w] + rb;
+    __syncthreads();  // the next call may overwrite the LDS
+}
+
 // The frame owning accumulator index p (frames are stored in pix_off order).
 __device__ inline uint32_t find_job(const RgJobDev *jobs, int n_jobs, uint32_t p) {
     int lo = 0, hi = n_jobs - 1;
@@ -195,12 +230,16 @@ struct ShadeArgs {
     RgShadowQ sq;
     uint32_t *count_sq;
     int64_t cap_out, cap_sq;
+    int64_t n_max;          // entries the input queue can hold
 };
 
-__global__ void __launch_bounds__(kT) k_shade(ShadeArgs a) {
-    int64_t i = blockIdx.x * (int64_t)kT + threadIdx.x;
-    int64_t n = *a.count_in;
-    bool active = i < n;
+// Persistent: blocks stride over the queue; each round of kShadeT entries
+// appends its children and shadow rays with one atomic per counter.
+__global__ void __launch_bounds__(kShadeT) k_shade(ShadeArgs a) {
+    const int64_t n = (int64_t)*a.count_in < a.n_max ? (int64_t)*a.count_in : a.n_max;
+    for (int64_t base = (int64_t)blockIdx.x * kShadeT; base < n; base += (int64_t)gridDim.x * kShadeT) {
+    const int64_t i = base + threadIdx.x;
+    const bool active = i < n;
     uint32_t n_child = 0, n_shadow = 0;
     float co[2][3], cd[2][3], cb[2][3];
     float so[3], sd[3], sp[3];
@@ -278,8 +317,8 @@ __global__ void __launch_bounds__(kT) k_shade(ShadeArgs a) {
             }
         }
     }
-    uint32_t cs = wave_append(a.count_out, n_child);
-    uint32_t ss = wave_append(a.count_sq, n_shadow);
+    uint32_t cs, ss;
+    block_append2(a.count_out, n_child, a.count_sq, n_shadow, cs, ss);
     for (uint32_t c = 0; c < n_child; ++c) {
         uint32_t j = cs + c;
         if ((int64_t)j >= a.cap_out) break;  // the queue holds sum n 2^D entries: never reached
@@ -297,6 +336,7 @@ __global__ void __launch_bounds__(kT) k_shade(ShadeArgs a) {
         a.sq.pend[0][ss] = sp[0];
         a.sq.pend[1][ss] = sp[1];
         a.sq.pend[2][ss] = sp[2];
+    }
     }
 }
 
@@ -341,14 +381,19 @@ __global__ void k_put_mats(RgMat *dst, MatChunk c, int n) {
     if ((int)threadIdx.x < n) dst[threadIdx.x] = c.m[threadIdx.x];
 }
 
-// Appends one camera ray per pixel of frame `slot` (one atomic per wave).
-__global__ void __launch_bounds__(kT) k_camera_job(RgJobDev J, uint32_t slot, RgQueue q, uint32_t *count,
+// Reserves n consecutive queue entries for a frame's camera rays: *base =
+// old count.
+__global__ void k_reserve(uint32_t *count, uint32_t n, uint32_t *base) {
+    if (threadIdx.x == 0) *base = atomicAdd(count, n);
+}
+
+// One camera ray per pixel of frame `slot`, at *base + pixel.
+__global__ void __launch_bounds__(kT) k_camera_job(RgJobDev J, uint32_t slot, RgQueue q, const uint32_t *base,
                                                    int64_t cap) {
     int64_t i = blockIdx.x * (int64_t)kT + threadIdx.x;
     const int64_t n = (int64_t)J.width * J.height;
-    const bool on = i < n;
-    uint32_t at = wave_append(count, on ? 1u : 0u);
-    if (!on || (int64_t)at >= cap) return;
+    const int64_t at = (int64_t)*base + i;
+    if (i >= n || at >= cap) return;
     CamF k = camera_basis(J.cam);
     float d[3];
     camera_dir(k, (int)J.width, (int)J.height, i, d);
@@ -651,7 +696,8 @@ rg_status rg_wave_put_job(const RgWaveBufs &b, uint32_t slot, const RgJobDev &J,
 
 rg_status rg_wave_camera(const RgWaveBufs &b, uint32_t slot, const RgJobDev &J, int queue, hipStream_t st) {
     const int64_t n = (int64_t)J.width * J.height;
-    k_camera_job<<<rg_blocks(n, kT), kT, 0, st>>>(J, slot, b.q[queue & 1], b.counts + (queue & 1), b.cap);
+    k_reserve<<<1, 64, 0, st>>>(b.counts + (queue & 1), (uint32_t)n, b.counts + 4);
+    k_camera_job<<<rg_blocks(n, kT), kT, 0, st>>>(J, slot, b.q[queue & 1], b.counts + 4, b.cap);
     RG_LAUNCH_CHECK();
     return RG_OK;
 }
@@ -692,7 +738,12 @@ rg_status rg_wave_pass(const RgWaveBufs &b, int32_t width, int64_t pass, int64_t
     sa.count_sq = csq;
     sa.cap_out = b.cap;
     sa.cap_sq = b.cap;
-    k_shade<<<rg_blocks(bound, kT), kT, 0, st>>>(sa);
+    sa.n_max = bound;
+    {
+        const int64_t want = (int64_t)rg_cu_count() * 3;
+        const int64_t need = rg_blocks(bound, kShadeT);
+        k_shade<<<(unsigned)(need < want ? need : want), kShadeT, 0, st>>>(sa);
+    }
     RG_LAUNCH_CHECK();
     RgTraceArgs ts = {};
     for (int c = 0; c < 8; ++c) ts.ray[c] = b.sq.ray[c];

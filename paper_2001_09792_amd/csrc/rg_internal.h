@@ -49,8 +49,10 @@ struct RgInst {
     float p[3];    // object -> world translation (as given)
     uint64_t nodes, tris, hdr;
     uint32_t mat, inst;
+    float blo[3], bhi[3];  // the bottom level's root box (object space)
+    uint32_t pad[2];
 };
-static_assert(sizeof(RgInst) == 80, "inst");
+static_assert(sizeof(RgInst) == 112, "inst");
 
 // Material as stored on the device.
 struct RgMat {

@@ -89,15 +89,24 @@ int g_refill = 8;         // lanes idle before a wave refills (tunable)
 int g_waves_per_cu = 16;  // resident waves per CU the grid is sized for
 int g_lds_depth = 16;     // traversal stack entries per lane in LDS
 
-unsigned persistent_blocks(int64_t n) {
+}  // namespace
+
+int rg_cu_count() {
     static int cus = 0;
     if (cus == 0) {
-        int dev = 0;
+        int dev = 0, c = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            cus = 256;
+            hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+            c = 256;
+        cus = c;
     }
-    int64_t want = (int64_t)cus * g_waves_per_cu / (rgt::kThreads / 64);
+    return cus;
+}
+
+namespace {
+
+unsigned persistent_blocks(int64_t n) {
+    int64_t want = (int64_t)rg_cu_count() * g_waves_per_cu / (rgt::kThreads / 64);
     int64_t need = rg_blocks(n, rgt::kThreads);
     return (unsigned)(need < want ? need : want);
 }

@@ -44,6 +44,7 @@ __device__ inline const RG_GLOBAL T *gptr(const void *p) {
 
 typedef uint32_t rg_u4 __attribute__((ext_vector_type(4)));
 typedef uint32_t rg_u2 __attribute__((ext_vector_type(2)));
+typedef uint32_t rg_u4a8 __attribute__((ext_vector_type(4), aligned(8)));  // 16 bytes at 8-byte alignment
 
 // Loads element i of a global array of T with global_load (T's size a
 // multiple of 16 bytes and 16-byte aligned, or of 8 bytes for rg_u2 pieces).
@@ -240,25 +241,64 @@ struct Tracer {
 
     // One unit of work; returns true when the ray is finished (h holds the
     // result, `found` whether there is a hit).
+    //
+    // Whatever the unit -- an inner node, an instance record or the first
+    // two triangles of a leaf -- its bytes are requested before any of them
+    // is used, into one register block, so that a wave whose lanes are at
+    // different kinds of units waits for one memory round trip per step, not
+    // one per kind (the three branches below run one after another under
+    // divergence).  Leaves beyond two triangles load the rest as they go.
     __device__ inline bool step() {
         if (++steps > kMaxSteps) return true;
-        if (!rg_is_leaf(cur)) {
+        constexpr int kNodeU4 = (7 * W + 3) / 4;  // node bytes without padding, in 16 B
+        constexpr int kWords = 4 * kNodeU4 > 28 ? 4 * kNodeU4 : 28;
+        const bool inner = !rg_is_leaf(cur);
+        const bool inst = !inner && !in_blas;
+        const uint32_t lf = rg_leaf_first(cur), ln = rg_leaf_count(cur);
+        // The same load instructions serve every lane (only the address
+        // differs), so no lane's load waits for another kind's.  112 bytes
+        // cover a record, two triangles (a leaf of one reads into the next
+        // triangle or the arrays after the last: every structure keeps at
+        // least 112 bytes of its own buffer after each array) and a node of
+        // width 2 or 4; width 8 nodes load their second half separately.
+        const char *addr = inner ? (const char *)nodes + (uint64_t)cur * sizeof(RgNode<W>)
+                                 : (inst ? (const char *)recs + (uint64_t)lf * sizeof(RgInst)
+                                         : (const char *)tris + (uint64_t)lf * sizeof(RgTri));
+        uint32_t w[kWords];
+        {
+            const RG_GLOBAL rg_u4a8 *src = gptr<rg_u4a8>(addr);
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+                const rg_u4a8 v = src[k];
+                w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
+            }
+            if (kNodeU4 > 7 && inner) {
+#pragma unroll
+                for (int k = 7; k < kNodeU4; ++k) {
+                    const rg_u4a8 v = src[k];
+                    w[4 * k] = v.x; w[4 * k + 1] = v.y; w[4 * k + 2] = v.z; w[4 * k + 3] = v.w;
+                }
+            }
+        }
+        if (inner) {
             if (MODE == kCounts) ++h.n_nodes;
-            const RgNode<W> nd = gload<RgNode<W>>(nodes, cur);
             float tn[W];
             uint32_t ch[W];
 #pragma unroll
             for (int k = 0; k < W; ++k) {
-                float x0 = (nd.lo_x[k] - ox) * ix, x1 = (nd.hi_x[k] - ox) * ix;
-                float y0 = (nd.lo_y[k] - oy) * iy, y1 = (nd.hi_y[k] - oy) * iy;
-                float z0 = (nd.lo_z[k] - oz) * iz, z1 = (nd.hi_z[k] - oz) * iz;
+                const float lx = __uint_as_float(w[k]), ly = __uint_as_float(w[W + k]);
+                const float lz = __uint_as_float(w[2 * W + k]), hx = __uint_as_float(w[3 * W + k]);
+                const float hy = __uint_as_float(w[4 * W + k]), hz = __uint_as_float(w[5 * W + k]);
+                float x0 = (lx - ox) * ix, x1 = (hx - ox) * ix;
+                float y0 = (ly - oy) * iy, y1 = (hy - oy) * iy;
+                float z0 = (lz - oz) * iz, z1 = (hz - oz) * iz;
                 float n_ = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), tlo));
                 float f_ = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fmaxf(z0, z1));
                 f_ = f_ + fabsf(f_) * kFarWiden;
                 f_ = fminf(f_, thi);
-                bool hit = (n_ <= f_) && (nd.child[k] != RG_EMPTY);
+                ch[k] = w[6 * W + k];
+                bool hit = (n_ <= f_) && (ch[k] != RG_EMPTY);
                 tn[k] = hit ? n_ : INFINITY;
-                ch[k] = nd.child[k];
             }
             if (!ANY) sort_children<W>(tn, ch);
             // the nearest hit child continues; the others are pushed far first
@@ -281,40 +321,31 @@ struct Tracer {
                 cur = next;
                 return false;
             }
-        } else if (!in_blas) {
-            // top-level leaf: one instance
-            uint32_t rec_idx = rg_leaf_first(cur);
+        } else if (inst) {
+            // top-level leaf: one instance.  Record words: inv[9] 0..8, p[3]
+            // 9..11, nodes 12..13, tris 14..15, hdr 16..17, mat 18, inst 19,
+            // root box lo 20..22, hi 23..25.
             if (MODE == kCounts) ++h.n_inst;
-            const RgInst rec = gload<RgInst>(recs, rec_idx);
-            // the bottom level's root box: the union of the root node's children
-            float blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
-            {
-                const RgNode<W> r0 = gload<RgNode<W>>((const void *)rec.nodes, 0);
-#pragma unroll
-                for (int k = 0; k < W; ++k) {
-                    blo[0] = fminf(blo[0], r0.lo_x[k]); blo[1] = fminf(blo[1], r0.lo_y[k]);
-                    blo[2] = fminf(blo[2], r0.lo_z[k]);
-                    bhi[0] = fmaxf(bhi[0], r0.hi_x[k]); bhi[1] = fmaxf(bhi[1], r0.hi_y[k]);
-                    bhi[2] = fmaxf(bhi[2], r0.hi_z[k]);
-                }
-            }
             // object-space ray in double: o' = M^-1 (o - p), d' = M^-1 d
-            double q[3] = {(double)R.o[0] - (double)rec.p[0], (double)R.o[1] - (double)rec.p[1],
-                           (double)R.o[2] - (double)rec.p[2]};
+            double q[3] = {(double)R.o[0] - (double)__uint_as_float(w[9]),
+                           (double)R.o[1] - (double)__uint_as_float(w[10]),
+                           (double)R.o[2] - (double)__uint_as_float(w[11])};
             double od[3], dd[3];
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
-                double ir0 = rec.inv[3 * r], ir1 = rec.inv[3 * r + 1], ir2 = rec.inv[3 * r + 2];
+                double ir0 = __uint_as_float(w[3 * r]), ir1 = __uint_as_float(w[3 * r + 1]);
+                double ir2 = __uint_as_float(w[3 * r + 2]);
                 od[r] = ir0 * q[0] + ir1 * q[1] + ir2 * q[2];
                 dd[r] = ir0 * (double)R.d[0] + ir1 * (double)R.d[1] + ir2 * (double)R.d[2];
             }
-            // slide the origin to where the ray enters that box (not before
-            // tmin); the entry only needs to be near the box, so float suffices
+            // slide the origin to where the ray enters the bottom level's
+            // root box (not before tmin); the entry only needs to be near the
+            // box, so float suffices
             float ten = -INFINITY, tex = INFINITY;
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
                 float of = (float)od[r], df = (float)dd[r], rr = safe_rcp(df);
-                float a = (blo[r] - of) * rr, b = (bhi[r] - of) * rr;
+                float a = (__uint_as_float(w[20 + r]) - of) * rr, b = (__uint_as_float(w[23 + r]) - of) * rr;
                 ten = fmaxf(ten, fminf(a, b));
                 tex = fminf(tex, fmaxf(a, b));
             }
@@ -334,26 +365,32 @@ struct Tracer {
             tlo = tlo - fabsf(tlo) * 1.2e-7f;
             thi = best - t0;
             thi = thi + fabsf(thi) * 2.4e-7f;
-            nodes = reinterpret_cast<const RgNode<W> *>(rec.nodes);
-            tris = reinterpret_cast<const RgTri *>(rec.tris);
-            inst_id = (MODE == kRender) ? rec_idx : rec.inst;
+            nodes = reinterpret_cast<const RgNode<W> *>((uint64_t)w[12] | ((uint64_t)w[13] << 32));
+            tris = reinterpret_cast<const RgTri *>((uint64_t)w[14] | ((uint64_t)w[15] << 32));
+            inst_id = (MODE == kRender) ? lf : w[19];
             in_blas = true;
             st.push(kSentinel);
             cur = 0;
             return false;
         } else {
-            // bottom-level leaf: up to 8 triangles
-            uint32_t f = rg_leaf_first(cur), n = rg_leaf_count(cur);
+            // bottom-level leaf: up to 8 triangles, the first two already here
             const float o3[3] = {ox, oy, oz};
-            for (uint32_t j = 0; j < n; ++j) {
+            for (uint32_t j = 0; j < ln; ++j) {
                 if (MODE == kCounts) ++h.n_tris;
-                const RgTri tri = gload<RgTri, rg_u2>(tris, f + j);
+                RgTri tri;
+                if (j < 2) {
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) tri.v[k] = __uint_as_float(j == 0 ? w[k] : w[10 + k]);
+                    tri.prim = j == 0 ? w[9] : w[19];
+                } else {
+                    tri = gload<RgTri, rg_u2>(tris, lf + j);
+                }
                 float T, det, V, Wv;
                 if (!tri_test(tri, o3, sh, tlo, thi, T, det, V, Wv)) continue;
                 float tl = T / det;
                 float tw = t0 + tl;
                 if (!(tw >= R.tmin) || !(tw <= best)) continue;
-                uint32_t pid = (MODE == kRender) ? (f + j) : tri.prim;
+                uint32_t pid = (MODE == kRender) ? (lf + j) : tri.prim;
                 if (!ANY && tw == best && found) {
                     if (inst_id > h.inst || (inst_id == h.inst && pid >= h.prim)) continue;
                 }
@@ -409,5 +446,7 @@ struct RgTraceArgs {
 // Launches the traversal over a.n rays (or *a.count if set) on `stream`.
 // width: 2/4/8; any: any-hit; mode: rgt::Mode.
 rg_status rg_trace_launch(int width, bool any, int mode, const RgTraceArgs &a, hipStream_t stream);
+// Compute units of the current device (queried once).
+int rg_cu_count();
 // Largest (W-1)*(top depth + bottom depth) + 1 the traversal stack holds.
 bool rg_trace_depth_ok(const rg_tlas *t);

@@ -79,9 +79,9 @@ def check_tlas(buf: np.ndarray, desc, blas_descs, xform) -> dict:
     W = desc.width
     lo, hi, child = _nodes(buf, desc.nodes_off, desc.n_nodes, W)
     n = desc.n_inst
-    rec = buf[desc.inst_off: desc.inst_off + 80 * n]
-    recf = rec.view(np.float32).reshape(n, 20)
-    recu = rec.view(np.uint32).reshape(n, 20)
+    rec = buf[desc.inst_off: desc.inst_off + 112 * n]
+    recf = rec.view(np.float32).reshape(n, 28)
+    recu = rec.view(np.uint32).reshape(n, 28)
     inst = recu[:, 19]
     assert np.array_equal(np.sort(inst), np.arange(n, dtype=np.uint32))
     rec_of = buf[desc.rec_off: desc.rec_off + 4 * n].view(np.uint32)
@@ -106,4 +106,11 @@ def check_tlas(buf: np.ndarray, desc, blas_descs, xform) -> dict:
         inv = recf[r, 0:9].reshape(3, 3).astype(np.float64)
         assert np.allclose(inv @ X[i, :, :3], np.eye(3), atol=1e-5)
         assert np.array_equal(recf[r, 9:12], X[i, :, 3].astype(np.float32))
+    # each record carries its bottom level's root box
+    by_nodes = {int(b.buf) + int(b.nodes_off): b for b in blas_descs}
+    rec_nodes = rec.view(np.uint64).reshape(n, 14)[:, 6]
+    for r in range(n):
+        b = by_nodes[int(rec_nodes[r])]
+        assert np.array_equal(recf[r, 20:23], np.array(b.lo, np.float32))
+        assert np.array_equal(recf[r, 23:26], np.array(b.hi, np.float32))
     return dict(depth=depth, inst=inst, boxes=(boxes_lo, boxes_hi))
