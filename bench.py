@@ -512,6 +512,9 @@ def main():
     ap.add_argument("--refill", type=int, default=None, help="traversal refill threshold (lanes)")
     ap.add_argument("--waves-per-cu", type=int, default=None, help="persistent traversal waves per CU")
     ap.add_argument("--lds-depth", type=int, default=None, help="traversal stack entries per lane in LDS")
+    ap.add_argument("--leaf-batch", type=int, default=None, help="lanes waiting at leaves before a wave runs them")
+    ap.add_argument("--inst-batch", type=int, default=None,
+                    help="lanes waiting at instance entries before a wave runs them")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -526,7 +529,7 @@ def main():
     import paper_2001_09792_amd as rg
     import scenegen as sg
     assert torch.cuda.is_available(), "bench.py needs the GPU"
-    tune = rg.trace_tuning(args.refill, args.waves_per_cu, args.lds_depth)
+    tune = rg.trace_tuning(args.refill, args.waves_per_cu, args.lds_depth, args.leaf_batch, args.inst_batch)
     if args.workload == "incoherent":
         out, scene = bench_incoherent(args, torch, rg, sg)
         if not args.no_cpu_baseline:

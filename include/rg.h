@@ -213,12 +213,18 @@ rg_status rg_trace_counts(const rg_tlas *tlas, rg_rays rays, int64_t n, int32_t 
  * wave walks its own interleaved sequence of 64-ray packets, and its lanes
  * take new rays together once `refill` of them (1..64) are idle.  The first
  * lds_depth (8..32) entries of each lane's traversal stack live in LDS, the
- * rest in private memory.  Either pointer may be NULL.  Errors:
- * RG_ERR_INVALID_ARG for values out of range. */
+ * rest in private memory.  A wave runs its leaf code once leaf_batch (1..64)
+ * lanes wait at a leaf and its instance-entry code once inst_batch (1..64)
+ * lanes wait at an instance (or when no lane has other work); 1 runs them
+ * whenever any lane needs them.  Results do not depend on any of these.
+ * Either pointer may be NULL.  Errors: RG_ERR_INVALID_ARG for values out of
+ * range. */
 typedef struct {
     int32_t refill;
     int32_t waves_per_cu;
     int32_t lds_depth;
+    int32_t leaf_batch;
+    int32_t inst_batch;
 } rg_trace_tune;
 rg_status rg_trace_tuning(const rg_trace_tune *set /*host, nullable*/, rg_trace_tune *get /*host, nullable*/);
 

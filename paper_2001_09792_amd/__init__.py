@@ -76,7 +76,8 @@ class LightDesc(ctypes.Structure):
 
 
 class TraceTune(ctypes.Structure):
-    _fields_ = [("refill", c_i32), ("waves_per_cu", c_i32), ("lds_depth", c_i32)]
+    _fields_ = [("refill", c_i32), ("waves_per_cu", c_i32), ("lds_depth", c_i32), ("leaf_batch", c_i32),
+                ("inst_batch", c_i32)]
 
 
 class Job(ctypes.Structure):
@@ -366,17 +367,21 @@ def trace_counts(tlas: Tlas, rays, any_hit: bool = False, counts=None, stream=No
     return counts
 
 
+TUNE_KEYS = ("refill", "waves_per_cu", "lds_depth", "leaf_batch", "inst_batch")
+
+
 def trace_tuning(refill: Optional[int] = None, waves_per_cu: Optional[int] = None,
-                 lds_depth: Optional[int] = None) -> dict:
+                 lds_depth: Optional[int] = None, leaf_batch: Optional[int] = None,
+                 inst_batch: Optional[int] = None) -> dict:
     """Reads (and with arguments, sets) the traversal launch parameters."""
     cur = TraceTune()
     _check("rg_trace_tuning", _lib.rg_trace_tuning(None, ctypes.byref(cur)))
-    if refill is not None or waves_per_cu is not None or lds_depth is not None:
-        new = TraceTune(cur.refill if refill is None else refill,
-                        cur.waves_per_cu if waves_per_cu is None else waves_per_cu,
-                        cur.lds_depth if lds_depth is None else lds_depth)
+    args = dict(refill=refill, waves_per_cu=waves_per_cu, lds_depth=lds_depth, leaf_batch=leaf_batch,
+                inst_batch=inst_batch)
+    if any(v is not None for v in args.values()):
+        new = TraceTune(*[getattr(cur, k) if args[k] is None else args[k] for k in TUNE_KEYS])
         _check("rg_trace_tuning", _lib.rg_trace_tuning(ctypes.byref(new), ctypes.byref(cur)))
-    return dict(refill=int(cur.refill), waves_per_cu=int(cur.waves_per_cu), lds_depth=int(cur.lds_depth))
+    return {k: int(getattr(cur, k)) for k in TUNE_KEYS}
 
 
 def camera_desc(cam) -> CameraDesc:

@@ -17,10 +17,10 @@ import os
 import time
 from typing import Callable, Dict, Optional
 
-DEFAULT = dict(width=4, leaf=2, refill=8, waves_per_cu=16, lds_depth=16)
+DEFAULT = dict(width=4, leaf=2, refill=8, waves_per_cu=16, lds_depth=16, leaf_batch=16, inst_batch=8)
 SPACE = dict(width=(2, 4, 8), leaf=(1, 2, 4), lds_depth=(8, 16, 24), refill=(4, 8, 16, 32),
-             waves_per_cu=(12, 16, 24))
-LAUNCH_KEYS = ("refill", "waves_per_cu", "lds_depth")
+             waves_per_cu=(12, 16, 24), leaf_batch=(1, 8, 16, 32), inst_batch=(1, 8, 16, 32))
+LAUNCH_KEYS = ("refill", "waves_per_cu", "lds_depth", "leaf_batch", "inst_batch")
 
 
 def bucket(n_rays: int, n_tris: int) -> str:
@@ -96,7 +96,7 @@ def search(measure: Callable[[Dict[str, int]], float], space: Dict[str, tuple] =
 def apply_launch(cfg: Dict[str, int]) -> dict:
     """Sets the launch parameters of a configuration; returns them."""
     import paper_2001_09792_amd as rg
-    return rg.trace_tuning(cfg["refill"], cfg["waves_per_cu"], cfg["lds_depth"])
+    return rg.trace_tuning(**{k: cfg[k] for k in LAUNCH_KEYS if k in cfg})
 
 
 def tuned(kind: str, n_rays: int, n_tris: int, measure: Callable[[Dict[str, int]], float],

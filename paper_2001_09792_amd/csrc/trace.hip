@@ -11,7 +11,8 @@ namespace {
 // that sequence together, once at least `refill` lanes are idle.  Rays of a
 // packet stay neighbours, and no lane idles while its wave has work left.
 template <int W, bool ANY, int MODE>
-__global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refill, int lds_depth) {
+__global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refill, int lds_depth, int leaf_batch,
+                                                         int inst_batch) {
     extern __shared__ uint32_t lds_stack[];  // lds_depth * kThreads entries
     const int lane = threadIdx.x & 63;
     const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -63,31 +64,46 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
             // no lane holds a ray after a refill attempt of all 64 lanes: the
             // sequence is exhausted once its next packet is past the end
             if (wave + (next >> 6) * n_waves >= n_packets) break;
-            continue;
+        } else {
+            // Which kinds of unit run this round: inner nodes whenever a lane
+            // has one; leaves and instance entries (each a long stretch of code
+            // that runs for the whole wave if any lane needs it) once enough
+            // lanes wait for one, or when nothing else is left.  A lane that
+            // waits keeps its state; every round runs at least one kind present.
+            const uint32_t my = has ? tr.kind() : 0u;
+            const int n_inner = __popcll(__ballot(my == rgt::kUnitInner));
+            const int n_leaf = __popcll(__ballot(my == rgt::kUnitLeaf));
+            const int n_inst = __popcll(__ballot(my == rgt::kUnitInst));
+            uint32_t run = n_inner ? rgt::kUnitInner : 0u;
+            if (n_leaf && (n_leaf >= leaf_batch || n_inner == 0)) run |= rgt::kUnitLeaf;
+            if (n_inst && (n_inst >= inst_batch || run == 0)) run |= rgt::kUnitInst;
+            if ((run & my) != 0u && tr.step()) {  // my == 0 for lanes without a ray
+                has = false;
+                finished = true;
+            }
+            if (finished) {
+                if (MODE == rgt::kCounts) {
+                    a.counts[3 * ray_i] = tr.h.n_nodes;
+                    a.counts[3 * ray_i + 1] = tr.h.n_tris;
+                    a.counts[3 * ray_i + 2] = tr.h.n_inst;
+                } else {
+                    if (ANY && a.occluded) a.occluded[ray_i] = tr.found ? 1 : 0;
+                    if (a.t) a.t[ray_i] = tr.h.t;
+                    if (a.u) a.u[ray_i] = tr.h.u;
+                    if (a.v) a.v[ray_i] = tr.h.v;
+                    if (a.inst) a.inst[ray_i] = tr.h.inst;
+                    if (a.prim) a.prim[ray_i] = tr.h.prim;
+                }
+            }
         }
-        if (has && tr.step()) {
-            has = false;
-            finished = true;
-        }
-        if (!finished) continue;
-        if (MODE == rgt::kCounts) {
-            a.counts[3 * ray_i] = tr.h.n_nodes;
-            a.counts[3 * ray_i + 1] = tr.h.n_tris;
-            a.counts[3 * ray_i + 2] = tr.h.n_inst;
-            continue;
-        }
-        if (ANY && a.occluded) a.occluded[ray_i] = tr.found ? 1 : 0;
-        if (a.t) a.t[ray_i] = tr.h.t;
-        if (a.u) a.u[ray_i] = tr.h.u;
-        if (a.v) a.v[ray_i] = tr.h.v;
-        if (a.inst) a.inst[ray_i] = tr.h.inst;
-        if (a.prim) a.prim[ray_i] = tr.h.prim;
     }
 }
 
 int g_refill = 8;         // lanes idle before a wave refills (tunable)
 int g_waves_per_cu = 16;  // resident waves per CU the grid is sized for
 int g_lds_depth = 16;     // traversal stack entries per lane in LDS
+int g_leaf_batch = 16;    // lanes waiting at leaves before a wave runs the leaf code
+int g_inst_batch = 8;     // lanes waiting at instance entries before a wave runs that code
 
 }  // namespace
 
@@ -114,17 +130,17 @@ unsigned persistent_blocks(int64_t n) {
 template <int W>
 rg_status launch_w(bool any, int mode, const RgTraceArgs &a, hipStream_t st) {
     unsigned blocks = persistent_blocks(a.n);
-    int refill = g_refill, lds = g_lds_depth;
+    int refill = g_refill, lds = g_lds_depth, lb = g_leaf_batch, ib = g_inst_batch;
     size_t shm = (size_t)lds * rgt::kThreads * sizeof(uint32_t);
     if (mode == rgt::kCounts) {
-        if (any) k_trace<W, true, rgt::kCounts><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds);
-        else k_trace<W, false, rgt::kCounts><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds);
+        if (any) k_trace<W, true, rgt::kCounts><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
+        else k_trace<W, false, rgt::kCounts><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
     } else if (mode == rgt::kRender) {
-        if (any) k_trace<W, true, rgt::kRender><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds);
-        else k_trace<W, false, rgt::kRender><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds);
+        if (any) k_trace<W, true, rgt::kRender><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
+        else k_trace<W, false, rgt::kRender><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
     } else {
-        if (any) k_trace<W, true, rgt::kClosest><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds);
-        else k_trace<W, false, rgt::kClosest><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds);
+        if (any) k_trace<W, true, rgt::kClosest><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
+        else k_trace<W, false, rgt::kClosest><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
     }
     RG_LAUNCH_CHECK();
     return RG_OK;
@@ -164,16 +180,21 @@ extern "C" {
 rg_status rg_trace_tuning(const rg_trace_tune *set, rg_trace_tune *get) {
     if (set) {
         if (set->refill < 1 || set->refill > 64 || set->waves_per_cu < 4 || set->waves_per_cu > 64 ||
-            set->lds_depth < 8 || set->lds_depth > rgt::kMaxLdsStack)
+            set->lds_depth < 8 || set->lds_depth > rgt::kMaxLdsStack || set->leaf_batch < 1 ||
+            set->leaf_batch > 64 || set->inst_batch < 1 || set->inst_batch > 64)
             return RG_ERR_INVALID_ARG;
         g_refill = set->refill;
         g_waves_per_cu = set->waves_per_cu;
         g_lds_depth = set->lds_depth;
+        g_leaf_batch = set->leaf_batch;
+        g_inst_batch = set->inst_batch;
     }
     if (get) {
         get->refill = g_refill;
         get->waves_per_cu = g_waves_per_cu;
         get->lds_depth = g_lds_depth;
+        get->leaf_batch = g_leaf_batch;
+        get->inst_batch = g_inst_batch;
     }
     return RG_OK;
 }

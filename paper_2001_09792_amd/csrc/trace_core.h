@@ -60,6 +60,8 @@ __device__ inline T gload(const void *base, uint64_t i) {
 }
 
 enum Mode { kClosest = 0, kCounts = 1, kRender = 2 };
+// Kinds of traversal unit.
+constexpr uint32_t kUnitInner = 1, kUnitInst = 2, kUnitLeaf = 4;
 
 struct Ray {
     float o[3], d[3], tmin, tmax;
@@ -239,6 +241,11 @@ struct Tracer {
         return R.tmin <= R.tmax;
     }
 
+    // Kind of the next unit: kUnitInner, kUnitInst or kUnitLeaf.
+    __device__ inline uint32_t kind() const {
+        return !rg_is_leaf(cur) ? kUnitInner : (!in_blas ? kUnitInst : kUnitLeaf);
+    }
+
     // One unit of work; returns true when the ray is finished (h holds the
     // result, `found` whether there is a hit).
     //
@@ -248,8 +255,13 @@ struct Tracer {
     // different kinds of units waits for one memory round trip per step, not
     // one per kind (the three branches below run one after another under
     // divergence).  Leaves beyond two triangles load the rest as they go.
+    // The caller decides which lanes run a unit this round.  The function has
+    // one exit: early returns would each need their own copy of the whole
+    // state at the merge after the call.
     __device__ inline bool step() {
-        if (++steps > kMaxSteps) return true;
+        bool done = false;
+        bool pop = false;
+        ++steps;
         constexpr int kNodeU4 = (7 * W + 3) / 4;  // node bytes without padding, in 16 B
         constexpr int kWords = 4 * kNodeU4 > 28 ? 4 * kNodeU4 : 28;
         const bool inner = !rg_is_leaf(cur);
@@ -317,10 +329,8 @@ struct Tracer {
                     if (tn[k] != INFINITY) st.push(ch[k]);
                 if (tn[0] != INFINITY) next = ch[0];
             }
-            if (next != RG_EMPTY) {
-                cur = next;
-                return false;
-            }
+            if (next != RG_EMPTY) cur = next;
+            else pop = true;
         } else if (inst) {
             // top-level leaf: one instance.  Record words: inv[9] 0..8, p[3]
             // 9..11, nodes 12..13, tris 14..15, hdr 16..17, mat 18, inst 19,
@@ -371,10 +381,10 @@ struct Tracer {
             in_blas = true;
             st.push(kSentinel);
             cur = 0;
-            return false;
         } else {
             // bottom-level leaf: up to 8 triangles, the first two already here
             const float o3[3] = {ox, oy, oz};
+            bool stop = false;
             for (uint32_t j = 0; j < ln; ++j) {
                 if (MODE == kCounts) ++h.n_tris;
                 RgTri tri;
@@ -400,23 +410,32 @@ struct Tracer {
                 h.v = Wv / det;
                 h.inst = inst_id;
                 h.prim = pid;
-                if (ANY) return true;
+                if (ANY) {
+                    stop = true;
+                    break;
+                }
                 best = tw;
                 thi = best - t0;
                 thi = thi + fabsf(thi) * 2.4e-7f;
             }
+            if (stop) done = true;
+            else pop = true;
         }
-        // pop
-        while (true) {
-            if (st.sp == 0) return true;
-            uint32_t e = st.pop();
-            if (e == kSentinel) {
-                world_frame();
-                continue;
+        if (pop) {
+            // a sentinel (leaving an instance) is never directly above another
+            if (st.sp == 0) {
+                done = true;
+            } else {
+                uint32_t e = st.pop();
+                if (e == kSentinel) {
+                    world_frame();
+                    if (st.sp == 0) done = true;
+                    else e = st.pop();
+                }
+                cur = e;
             }
-            cur = e;
-            return false;
         }
+        return done || steps > kMaxSteps;
     }
 };
 

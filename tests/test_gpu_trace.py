@@ -227,3 +227,32 @@ def test_ao_rays_match_oracle():
     oc = orc.trace(rays_ao[sel])
     print(parity.check_closest(h, oc, 0.03, "ao"), flush=True)
     torch.cuda.synchronize()
+
+
+def test_launch_parameters_do_not_change_results():
+    """Refill threshold, resident waves, LDS stack depth and the leaf /
+    instance batching only reorder work: every hit is bitwise the same."""
+    import paper_2001_09792_amd as rg
+    sc = sg.config_two_level(width=192, height=108)
+    tl = rg.upload_scene(sc, 4, 2)
+    cam = rg.camera_rays(sc.camera, 192, 108).cpu().numpy().T.copy()
+    rays = rg.rays_to_device(np.concatenate([cam, sg.random_rays(20000, 9, extent=22.0)]))
+    saved = rg.trace_tuning()
+    ref = None
+    try:
+        for cfg in (dict(refill=8, waves_per_cu=16, lds_depth=16, leaf_batch=1, inst_batch=1),
+                    dict(refill=1, waves_per_cu=4, lds_depth=8, leaf_batch=64, inst_batch=64),
+                    dict(refill=64, waves_per_cu=24, lds_depth=32, leaf_batch=16, inst_batch=8),
+                    dict(refill=16, waves_per_cu=16, lds_depth=16, leaf_batch=32, inst_batch=1)):
+            print(f"[trace] launch {cfg}", flush=True)
+            rg.trace_tuning(**cfg)
+            h = parity.hits_to_numpy(rg.trace_closest(tl, rays))
+            occ = rg.trace_any(tl, rays).cpu().numpy()
+            if ref is None:
+                ref = (h, occ)
+                continue
+            for k in h:
+                assert np.array_equal(h[k].view(np.uint32), ref[0][k].view(np.uint32)), (cfg, k)
+            assert np.array_equal(occ, ref[1]), cfg
+    finally:
+        rg.trace_tuning(**saved)
