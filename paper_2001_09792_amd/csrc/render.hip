@@ -702,7 +702,8 @@ rg_status rg_wave_camera(const RgWaveBufs &b, uint32_t slot, const RgJobDev &J, 
     return RG_OK;
 }
 
-rg_status rg_wave_pass(const RgWaveBufs &b, int32_t width, int64_t pass, int64_t bound, hipStream_t st) {
+rg_status rg_wave_pass(const RgWaveBufs &b, int32_t width, int64_t pass, int64_t bound, hipStream_t st,
+                       RgShadowSide *side) {
     if (bound < 1) return RG_OK;
     if (bound > b.cap) bound = b.cap;
     const RgQueue &qin = b.q[pass & 1], &qout = b.q[(pass + 1) & 1];
@@ -718,6 +719,9 @@ rg_status rg_wave_pass(const RgWaveBufs &b, int32_t width, int64_t pass, int64_t
     tc.prim = b.hit_slot;
     rg_status r = rg_trace_launch(width, false, rgt::kRender, tc, st);
     if (r != RG_OK) return r;
+    // the shadow queue and its count are reused below: the previous pass's
+    // shadow work must be done with them
+    if (side && side->pending) RG_HIP(hipStreamWaitEvent(st, side->shadowed, 0));
     k_stat_add<<<1, 1, 0, st>>>(b.stat, cin);
     k_fill_u32<<<1, 64, 0, st>>>(cout, 0u, 1);
     k_fill_u32<<<1, 64, 0, st>>>(csq, 0u, 1);
@@ -745,6 +749,12 @@ rg_status rg_wave_pass(const RgWaveBufs &b, int32_t width, int64_t pass, int64_t
         k_shade<<<(unsigned)(need < want ? need : want), kShadeT, 0, st>>>(sa);
     }
     RG_LAUNCH_CHECK();
+    hipStream_t s2 = st;
+    if (side) {
+        RG_HIP(hipEventRecord(side->shaded, st));
+        RG_HIP(hipStreamWaitEvent(side->st, side->shaded, 0));
+        s2 = side->st;
+    }
     RgTraceArgs ts = {};
     for (int c = 0; c < 8; ++c) ts.ray[c] = b.sq.ray[c];
     ts.n = bound;
@@ -752,11 +762,15 @@ rg_status rg_wave_pass(const RgWaveBufs &b, int32_t width, int64_t pass, int64_t
     ts.ray_job = b.sq.job;
     ts.jobs = b.tlas;
     ts.occluded = b.sq.occ;
-    r = rg_trace_launch(width, true, rgt::kRender, ts, st);
+    r = rg_trace_launch(width, true, rgt::kRender, ts, s2);
     if (r != RG_OK) return r;
-    k_stat_add<<<1, 1, 0, st>>>(b.stat + 1, csq);
-    k_shadow_resolve<<<rg_blocks(bound, kT), kT, 0, st>>>(b.sq, csq, b.acc);
+    k_stat_add<<<1, 1, 0, s2>>>(b.stat + 1, csq);
+    k_shadow_resolve<<<rg_blocks(bound, kT), kT, 0, s2>>>(b.sq, csq, b.acc);
     RG_LAUNCH_CHECK();
+    if (side) {
+        RG_HIP(hipEventRecord(side->shadowed, s2));
+        side->pending = true;
+    }
     return RG_OK;
 }
 

@@ -144,12 +144,23 @@ struct rg_engine {
     int64_t pass = 0;                    // index of the next pass
     int64_t done_pass = 0;               // passes known complete
     hipEvent_t ev[kEventRing] = {};
+    RgShadowSide side = {};              // shadow half of each pass on a second stream
     std::map<int64_t, std::vector<int32_t>> finishing;  // pass -> slots whose last pass it is
     std::vector<int64_t> done_tags;      // completed, not yet returned by poll
     int64_t admitted = 0, completed = 0, max_frames_in_pass = 0, max_depths_in_pass = 0;
 };
 
 namespace {
+
+// Frees the host object and whatever HIP objects it holds (null ones skipped).
+void engine_free(rg_engine *E) {
+    for (int k = 0; k < kEventRing; ++k)
+        if (E->ev[k]) hipEventDestroy(E->ev[k]);
+    if (E->side.shaded) hipEventDestroy(E->side.shaded);
+    if (E->side.shadowed) hipEventDestroy(E->side.shadowed);
+    if (E->side.st) hipStreamDestroy(E->side.st);
+    delete E;
+}
 
 // Moves passes that completed on the device into done_tags, releasing their
 // frames.  block: wait for the oldest outstanding pass first.
@@ -261,19 +272,20 @@ rg_status rg_engine_create(const rg_engine_desc *d, void *scratch, uint64_t scra
     E->frames.resize((size_t)d->max_jobs);
     RgArena A{(char *)scratch, scratch_bytes, 0};
     rg_wave_carve(A, d->max_pixels, d->max_rays, d->max_jobs, (int64_t)d->max_jobs * d->max_mats, E->b);
-    for (int k = 0; k < kEventRing; ++k) {
-        hipError_t e = hipEventCreateWithFlags(&E->ev[k], hipEventDisableTiming);
-        if (e != hipSuccess) {
-            for (int j = 0; j < k; ++j) hipEventDestroy(E->ev[j]);
-            delete E;
-            rg_set_error(__FILE__, __LINE__, hipGetErrorName(e));
-            return RG_ERR_HIP;
-        }
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < kEventRing && e == hipSuccess; ++k)
+        e = hipEventCreateWithFlags(&E->ev[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&E->side.shaded, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&E->side.shadowed, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&E->side.st, hipStreamNonBlocking);  // default priority
+    if (e != hipSuccess) {
+        engine_free(E);
+        rg_set_error(__FILE__, __LINE__, hipGetErrorName(e));
+        return RG_ERR_HIP;
     }
     r = rg_wave_reset(E->b, E->st);
     if (r != RG_OK) {
-        for (int k = 0; k < kEventRing; ++k) hipEventDestroy(E->ev[k]);
-        delete E;
+        engine_free(E);
         return r;
     }
     *out = E;
@@ -283,8 +295,9 @@ rg_status rg_engine_create(const rg_engine_desc *d, void *scratch, uint64_t scra
 rg_status rg_engine_destroy(rg_engine *E) {
     if (!E) return RG_OK;
     hipError_t e = hipStreamSynchronize(E->st);
-    for (int k = 0; k < kEventRing; ++k) hipEventDestroy(E->ev[k]);
-    delete E;
+    hipError_t e2 = E->side.st ? hipStreamSynchronize(E->side.st) : hipSuccess;
+    if (e == hipSuccess) e = e2;
+    engine_free(E);
     if (e != hipSuccess) {
         rg_set_error(__FILE__, __LINE__, hipGetErrorName(e));
         return RG_ERR_HIP;
@@ -359,15 +372,16 @@ rg_status rg_engine_step(rg_engine *E, int32_t *ran) {
         rg_status r = harvest(E, true);
         if (r != RG_OK) return r;
     }
-    rg_status r = rg_wave_pass(E->b, E->d.width, E->pass, bound, E->st);
+    rg_status r = rg_wave_pass(E->b, E->d.width, E->pass, bound, E->st, &E->side);
     if (r != RG_OK) return r;
+    // the pass is complete once its shadow half (on the side stream) is
     auto it = E->finishing.find(E->pass);
     if (it != E->finishing.end())
         for (int32_t s : it->second) {
-            r = rg_wave_resolve(E->b, E->frames[(size_t)s].dev, E->st);
+            r = rg_wave_resolve(E->b, E->frames[(size_t)s].dev, E->side.st);
             if (r != RG_OK) return r;
         }
-    RG_HIP(hipEventRecord(E->ev[E->pass % kEventRing], E->st));
+    RG_HIP(hipEventRecord(E->ev[E->pass % kEventRing], E->side.st));
     E->pass += 1;
     E->max_frames_in_pass = std::max(E->max_frames_in_pass, frames);
     E->max_depths_in_pass = std::max<int64_t>(E->max_depths_in_pass, __builtin_popcount(depth_mask));
@@ -410,6 +424,7 @@ rg_status rg_engine_get_info(const rg_engine *E, rg_engine_info *out) {
 rg_status rg_engine_stats(rg_engine *E, rg_render_stats *stats) {
     if (!E || !stats) return RG_ERR_INVALID_ARG;
     unsigned long long hs[2] = {0, 0};
+    RG_HIP(hipStreamSynchronize(E->side.st));
     RG_HIP(hipMemcpyAsync(hs, E->b.stat, 16, hipMemcpyDeviceToHost, E->st));
     RG_HIP(hipStreamSynchronize(E->st));
     stats->rays_traced = hs[0];

@@ -71,10 +71,25 @@ rg_status rg_wave_put_job(const RgWaveBufs &b, uint32_t slot, const RgJobDev &J,
 // Appends the frame's camera rays (one per pixel) to ray queue `queue`.
 rg_status rg_wave_camera(const RgWaveBufs &b, uint32_t slot, const RgJobDev &J, int queue, hipStream_t st);
 
+// A second stream for the shadow half of each pass.  The shadow rays of
+// pass p are traced and their direct term added on `st` while the main
+// stream runs the closest-hit traversal of pass p+1 (the persistent kernels
+// of one fill the tail of the other).  `shaded` orders the shadow work after
+// the shading that queued it; `shadowed` orders the next pass's reuse of the
+// shadow queue after it.  Events owned by the caller.
+struct RgShadowSide {
+    hipStream_t st;
+    hipEvent_t shaded, shadowed;
+    bool pending;  // shadow work of an earlier pass was enqueued on st
+};
+
 // One pass over ray queue (pass & 1): closest hit, shading into the other
 // ray queue, shadow any hit, direct term.  `bound` >= the entries queued
 // (sizes the launches); width = node width of every top level involved.
-rg_status rg_wave_pass(const RgWaveBufs &b, int32_t width, int64_t pass, int64_t bound, hipStream_t st);
+// With `side`, the shadow half runs on side->st (see above): work that needs
+// the pass complete (image resolves) goes to side->st as well.
+rg_status rg_wave_pass(const RgWaveBufs &b, int32_t width, int64_t pass, int64_t bound, hipStream_t st,
+                       RgShadowSide *side = nullptr);
 
 // Converts the frame's accumulators to its float RGB image.
 rg_status rg_wave_resolve(const RgWaveBufs &b, const RgJobDev &J, hipStream_t st);
