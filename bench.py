@@ -229,7 +229,7 @@ def bench_incoherent(args, torch, rg, sg):
                                f"{args.segments}x{args.segments} ({scene.unique_tris()} unique tris), "
                                f"{W}x{H} camera rays + 8 AO rays per primary hit (tmax 5), closest hit",
                    "rays_per_step": rays_step, "primary_rays": N, "ao_rays": n_ao,
-                   "trace_tuning": rg.trace_tuning(),
+                   "trace_tuning": rg.trace_tuning(scope="trace"),
                    "primary_hit_fraction": prim_hit_frac, "bvh_width": args.width, "leaf_max": args.leaf},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(args),
@@ -271,7 +271,8 @@ def bench_two_level(args, torch, rg, sg):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "two-level: 64 instances of 3 meshes (184,320 unique tris), 1920x1080, "
                                "Whitted depth 4, whole frames",
-                   "rays_per_frame": rays, "closest_rays": st["rays_traced"], "shadow_rays": st["shadow_rays"]},
+                   "rays_per_frame": rays, "closest_rays": st["rays_traced"], "shadow_rays": st["shadow_rays"],
+                   "trace_tuning": rg.trace_tuning(scope="frame")},
         "roofline": None,
     }
     return out, scene
@@ -293,7 +294,7 @@ def bench_batched(args, torch, rg, sg):
         return out
 
     frames = build(scenes, args.width, args.leaf)
-    default_launch = rg.trace_tuning()
+    default_launch = rg.trace_tuning(scope="frame")
     tuned = None
     if args.autotune:
         from paper_2001_09792_amd import autotune
@@ -304,7 +305,7 @@ def bench_batched(args, torch, rg, sg):
             key = (cfg["width"], cfg["leaf"])
             if key not in built:
                 built[key] = build(sub, *key)
-            autotune.apply_launch(cfg)
+            autotune.apply_launch(cfg, "frame")
             b = rg.Batch(built[key])
             _, st = b.render(stats=True)
             torch.cuda.synchronize()
@@ -314,11 +315,12 @@ def bench_batched(args, torch, rg, sg):
             torch.cuda.synchronize()
             return (st["rays_traced"] + st["shadow_rays"]) * 3 / (time.perf_counter() - t) / 1e6
 
+        start = dict(autotune.DEFAULT, width=args.width, leaf=args.leaf, **default_launch)
         tuned = autotune.tuned("batch", sum(s.width * s.height for s in scenes),
-                               sum(s.unique_tris() for s in scenes), measure, log=log)
+                               sum(s.unique_tris() for s in scenes), measure, log=log, start=start)
         log(f"autotuned: {tuned}")
         built.clear()
-        rg.trace_tuning(**default_launch)
+        rg.trace_tuning(scope="frame", **default_launch)
     # plain: one scratch buffer sized for the largest frame, reused frame after frame
     need = max(rg.render_sizes(W, H, D, 0) for (_, _, _, _, W, H, D) in frames)
     scratch = torch.empty(need, dtype=torch.uint8, device="cuda")
@@ -350,12 +352,12 @@ def bench_batched(args, torch, rg, sg):
         return e0.elapsed_time(e1) / steps, (time.perf_counter() - w0) / steps * 1e3
 
     # plain: every frame with the default launch parameters
-    rg.trace_tuning(**default_launch)
+    rg.trace_tuning(scope="frame", **default_launch)
     ms_plain, wall_plain = timed(plain, max(1, args.steps // 4))
     if tuned is not None:
         from paper_2001_09792_amd import autotune
-        autotune.apply_launch(tuned["config"])
-    batched_launch = rg.trace_tuning()
+        autotune.apply_launch(tuned["config"], "frame")
+    batched_launch = rg.trace_tuning(scope="frame")
     _, st = batch.render(stats=True)
     rays = st["rays_traced"] + st["shadow_rays"]
     ms_batch, wall_batch = timed(batch.render, args.steps)
@@ -364,7 +366,7 @@ def bench_batched(args, torch, rg, sg):
     # by their largest difference and a default-configured batch by identity
     same_cfg = batch if bframes is frames else rg.Batch(frames)
     if same_cfg is not batch:
-        rg.trace_tuning(**default_launch)
+        rg.trace_tuning(scope="frame", **default_launch)
         same_cfg.render()
     same = all(torch.equal(a, b) for a, b in zip(imgs, same_cfg.images))
     max_diff = max(float((a - b).abs().max()) for a, b in zip(imgs, batch.images))
@@ -480,7 +482,8 @@ def bench_serving(args, torch, rg, sg):
         "config": {"workload": "serving: 64 resident scenes (32 two-level, 32 over 16 shared tori of "
                                f"{args.segments}^2), requests of 256^2..1920x1080, Whitted depth 1..4, "
                                "continuous batching", "budget_gb": args.budget_gb, "engine": ecfg,
-                   "requests_per_point": args.requests, "warm_requests": args.warm},
+                   "requests_per_point": args.requests, "warm_requests": args.warm,
+                   "engine_launch": rg.trace_tuning(scope="engine"), "plain_launch": rg.trace_tuning(scope="frame")},
         "saturated": {"engine": s_eng, "plain": s_plain, "speedup": s_eng["mrays_s"] / s_plain["mrays_s"]},
         "points": points,
         "engine_info": einfo,
@@ -529,7 +532,8 @@ def main():
     import paper_2001_09792_amd as rg
     import scenegen as sg
     assert torch.cuda.is_available(), "bench.py needs the GPU"
-    tune = rg.trace_tuning(args.refill, args.waves_per_cu, args.lds_depth, args.leaf_batch, args.inst_batch)
+    scope = {"incoherent": "trace", "two_level": "frame", "batched": "frame", "serving": "engine"}[args.workload]
+    rg.trace_tuning(args.refill, args.waves_per_cu, args.lds_depth, args.leaf_batch, args.inst_batch, scope=scope)
     if args.workload == "incoherent":
         out, scene = bench_incoherent(args, torch, rg, sg)
         if not args.no_cpu_baseline:

@@ -208,8 +208,12 @@ rg_status rg_trace_any(const rg_tlas *tlas, rg_rays rays, int64_t n, uint8_t *oc
 rg_status rg_trace_counts(const rg_tlas *tlas, rg_rays rays, int64_t n, int32_t any_hit,
                           uint32_t *counts, void *stream);
 
-/* Launch parameters of the traversal kernels (process-wide).  The kernels
- * are persistent: the grid holds waves_per_cu waves per compute unit, each
+/* Launch parameters of the traversal kernels, one set per family of calls
+ * (process-wide):
+ *   RG_TUNE_TRACE  rg_trace_closest, rg_trace_any, rg_trace_counts
+ *   RG_TUNE_FRAME  rg_render, rg_batch_render
+ *   RG_TUNE_ENGINE rg_engine_step
+ * The kernels are persistent: the grid holds waves_per_cu waves per compute unit, each
  * wave walks its own interleaved sequence of 64-ray packets, and its lanes
  * take new rays together once `refill` of them (1..64) are idle.  The first
  * lds_depth (8..32) entries of each lane's traversal stack live in LDS, the
@@ -217,8 +221,8 @@ rg_status rg_trace_counts(const rg_tlas *tlas, rg_rays rays, int64_t n, int32_t 
  * lanes wait at a leaf and its instance-entry code once inst_batch (1..64)
  * lanes wait at an instance (or when no lane has other work); 1 runs them
  * whenever any lane needs them.  Results do not depend on any of these.
- * Either pointer may be NULL.  Errors: RG_ERR_INVALID_ARG for values out of
- * range. */
+ * Either pointer may be NULL.  Errors: RG_ERR_INVALID_ARG for an unknown
+ * scope or values out of range. */
 typedef struct {
     int32_t refill;
     int32_t waves_per_cu;
@@ -226,7 +230,12 @@ typedef struct {
     int32_t leaf_batch;
     int32_t inst_batch;
 } rg_trace_tune;
-rg_status rg_trace_tuning(const rg_trace_tune *set /*host, nullable*/, rg_trace_tune *get /*host, nullable*/);
+#define RG_TUNE_TRACE 0
+#define RG_TUNE_FRAME 1
+#define RG_TUNE_ENGINE 2
+#define RG_TUNE_SCOPES 3
+rg_status rg_trace_tuning(int32_t scope, const rg_trace_tune *set /*host, nullable*/,
+                          rg_trace_tune *get /*host, nullable*/);
 
 /* ---------------------------------------------------- ray generation */
 /* Pinhole camera rays, one per pixel centre, y = 0 the top row, vertical

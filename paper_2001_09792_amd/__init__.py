@@ -123,7 +123,7 @@ SIGNATURES = {
     "rg_trace_closest": (c_i32, [c_p, Rays, c_i64, Hits, c_p]),
     "rg_trace_any": (c_i32, [c_p, Rays, c_i64, c_p, c_p, c_p]),
     "rg_trace_counts": (c_i32, [c_p, Rays, c_i64, c_i32, c_p, c_p]),
-    "rg_trace_tuning": (c_i32, [c_p, c_p]),
+    "rg_trace_tuning": (c_i32, [c_i32, c_p, c_p]),
     "rg_camera_rays": (c_i32, [c_p, c_i32, c_i32, c_p, c_p]),
     "rg_ao_rays": (c_i32, [c_p, Rays, c_i64, c_p, c_p, c_p, c_u64, c_f, c_p, c_p, c_p, c_p, c_u64, c_p]),
     "rg_ao_rays_scratch": (c_i32, [c_i64, c_p]),
@@ -368,19 +368,24 @@ def trace_counts(tlas: Tlas, rays, any_hit: bool = False, counts=None, stream=No
 
 
 TUNE_KEYS = ("refill", "waves_per_cu", "lds_depth", "leaf_batch", "inst_batch")
+# families of calls with their own launch parameters (RG_TUNE_*)
+TUNE_SCOPES = {"trace": 0, "frame": 1, "engine": 2}
 
 
 def trace_tuning(refill: Optional[int] = None, waves_per_cu: Optional[int] = None,
                  lds_depth: Optional[int] = None, leaf_batch: Optional[int] = None,
-                 inst_batch: Optional[int] = None) -> dict:
-    """Reads (and with arguments, sets) the traversal launch parameters."""
+                 inst_batch: Optional[int] = None, scope: str = "trace") -> dict:
+    """Reads (and with arguments, sets) the traversal launch parameters of
+    one family of calls: "trace" (trace_closest / trace_any / trace_counts),
+    "frame" (render, Batch) or "engine" (Engine)."""
+    sc = TUNE_SCOPES[scope]
     cur = TraceTune()
-    _check("rg_trace_tuning", _lib.rg_trace_tuning(None, ctypes.byref(cur)))
+    _check("rg_trace_tuning", _lib.rg_trace_tuning(sc, None, ctypes.byref(cur)))
     args = dict(refill=refill, waves_per_cu=waves_per_cu, lds_depth=lds_depth, leaf_batch=leaf_batch,
                 inst_batch=inst_batch)
     if any(v is not None for v in args.values()):
         new = TraceTune(*[getattr(cur, k) if args[k] is None else args[k] for k in TUNE_KEYS])
-        _check("rg_trace_tuning", _lib.rg_trace_tuning(ctypes.byref(new), ctypes.byref(cur)))
+        _check("rg_trace_tuning", _lib.rg_trace_tuning(sc, ctypes.byref(new), ctypes.byref(cur)))
     return {k: int(getattr(cur, k)) for k in TUNE_KEYS}
 
 

@@ -93,14 +93,16 @@ def search(measure: Callable[[Dict[str, int]], float], space: Dict[str, tuple] =
     return cfg, best, trials
 
 
-def apply_launch(cfg: Dict[str, int]) -> dict:
-    """Sets the launch parameters of a configuration; returns them."""
+def apply_launch(cfg: Dict[str, int], scope: str = "trace") -> dict:
+    """Sets the launch parameters of a configuration for one family of calls
+    ("trace", "frame" or "engine"); returns them."""
     import paper_2001_09792_amd as rg
-    return rg.trace_tuning(**{k: cfg[k] for k in LAUNCH_KEYS if k in cfg})
+    return rg.trace_tuning(scope=scope, **{k: cfg[k] for k in LAUNCH_KEYS if k in cfg})
 
 
 def tuned(kind: str, n_rays: int, n_tris: int, measure: Callable[[Dict[str, int]], float],
-          cache: Optional[TuneCache] = None, space: Dict[str, tuple] = SPACE, log=None) -> dict:
+          cache: Optional[TuneCache] = None, space: Dict[str, tuple] = SPACE, log=None,
+          start: Optional[Dict[str, int]] = None) -> dict:
     """The cached configuration for this workload bucket, or a fresh search
     (stored in the cache).  Returns {config, score, bucket, cached, seconds}."""
     cache = cache or TuneCache()
@@ -110,7 +112,7 @@ def tuned(kind: str, n_rays: int, n_tris: int, measure: Callable[[Dict[str, int]
     if hit is not None:
         return dict(config=hit["config"], score=hit["score"], bucket=bkt, cached=True, seconds=0.0)
     t0 = time.perf_counter()
-    cfg, best, trials = search(measure, space, log=log)
+    cfg, best, trials = search(measure, space, start=start, log=log)
     dt = time.perf_counter() - t0
     cache.put(a, kind, bkt, dict(config=cfg, score=best, trials=len(trials), seconds=dt))
     return dict(config=cfg, score=best, bucket=bkt, cached=False, seconds=dt)

@@ -620,7 +620,7 @@ rg_status run_batch(const rg_batch *B, hipStream_t st) {
     k_camera_batch<<<rg_blocks(total, kT), kT, 0, st>>>(b.jobs, B->n_jobs, total, b.q[0], b.counts + 0);
     RG_LAUNCH_CHECK();
     for (int k = 0; k <= B->max_depth; ++k) {
-        r = rg_wave_pass(b, B->width, k, B->cap_at[k], st);
+        r = rg_wave_pass(b, B->width, k, B->cap_at[k], st, RG_TUNE_FRAME);
         if (r != RG_OK) return r;
     }
     k_resolve_batch<<<rg_blocks(total, kT), kT, 0, st>>>(b.acc, b.jobs, B->n_jobs, total);
@@ -703,7 +703,7 @@ rg_status rg_wave_camera(const RgWaveBufs &b, uint32_t slot, const RgJobDev &J, 
 }
 
 rg_status rg_wave_pass(const RgWaveBufs &b, int32_t width, int64_t pass, int64_t bound, hipStream_t st,
-                       RgShadowSide *side) {
+                       int scope, RgShadowSide *side) {
     if (bound < 1) return RG_OK;
     if (bound > b.cap) bound = b.cap;
     const RgQueue &qin = b.q[pass & 1], &qout = b.q[(pass + 1) & 1];
@@ -717,7 +717,7 @@ rg_status rg_wave_pass(const RgWaveBufs &b, int32_t width, int64_t pass, int64_t
     tc.t = b.hit_t;
     tc.inst = b.hit_rec;
     tc.prim = b.hit_slot;
-    rg_status r = rg_trace_launch(width, false, rgt::kRender, tc, st);
+    rg_status r = rg_trace_launch(width, false, rgt::kRender, tc, st, scope);
     if (r != RG_OK) return r;
     // the shadow queue and its count are reused below: the previous pass's
     // shadow work must be done with them
@@ -762,7 +762,7 @@ rg_status rg_wave_pass(const RgWaveBufs &b, int32_t width, int64_t pass, int64_t
     ts.ray_job = b.sq.job;
     ts.jobs = b.tlas;
     ts.occluded = b.sq.occ;
-    r = rg_trace_launch(width, true, rgt::kRender, ts, s2);
+    r = rg_trace_launch(width, true, rgt::kRender, ts, s2, scope);
     if (r != RG_OK) return r;
     k_stat_add<<<1, 1, 0, s2>>>(b.stat + 1, csq);
     k_shadow_resolve<<<rg_blocks(bound, kT), kT, 0, s2>>>(b.sq, csq, b.acc);
@@ -968,7 +968,7 @@ rg_status rg_render(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats
         if ((r = rg_wave_put_job(b, 0, J, T, mats, n_mats, st)) != RG_OK) return r;
         if ((r = rg_wave_camera(b, 0, J, 0, st)) != RG_OK) return r;
         for (int k = 0; k <= max_depth; ++k)
-            if ((r = rg_wave_pass(b, tlas->width, k, n << k, st)) != RG_OK) return r;
+            if ((r = rg_wave_pass(b, tlas->width, k, n << k, st, RG_TUNE_FRAME)) != RG_OK) return r;
         if ((r = rg_wave_resolve(b, J, st)) != RG_OK) return r;
         if (stats) return finish_stats(st, e0, e1, b.stat, stats);
         return RG_OK;
@@ -995,7 +995,7 @@ rg_status rg_render(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats
     ta.t = b.hit_t;
     ta.inst = b.hit_rec;
     ta.prim = b.hit_slot;
-    r = rg_trace_launch(tlas->width, false, rgt::kRender, ta, st);
+    r = rg_trace_launch(tlas->width, false, rgt::kRender, ta, st, RG_TUNE_FRAME);
     if (r != RG_OK) return r;
     AoArgs a = {};
     for (int c = 0; c < 6; ++c) a.ray[c] = b.cam[c];
@@ -1018,7 +1018,7 @@ rg_status rg_render(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats
     tb.n = 8 * n;
     tb.count = b.counts + 2;
     tb.occluded = b.ao_occ;
-    r = rg_trace_launch(tlas->width, true, rgt::kRender, tb, st);
+    r = rg_trace_launch(tlas->width, true, rgt::kRender, tb, st, RG_TUNE_FRAME);
     if (r != RG_OK) return r;
     k_ao_accum<<<rg_blocks(8 * n, kT), kT, 0, st>>>(b.ao_occ, b.ao_src, b.counts + 2, b.acc);
     k_ao_resolve<<<rg_blocks(n, kT), kT, 0, st>>>(b.acc, b.hit_rec, n, image);

@@ -372,7 +372,7 @@ rg_status rg_engine_step(rg_engine *E, int32_t *ran) {
         rg_status r = harvest(E, true);
         if (r != RG_OK) return r;
     }
-    rg_status r = rg_wave_pass(E->b, E->d.width, E->pass, bound, E->st, &E->side);
+    rg_status r = rg_wave_pass(E->b, E->d.width, E->pass, bound, E->st, RG_TUNE_ENGINE, &E->side);
     if (r != RG_OK) return r;
     // the pass is complete once its shadow half (on the side stream) is
     auto it = E->finishing.find(E->pass);

@@ -99,11 +99,15 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
     }
 }
 
-int g_refill = 8;         // lanes idle before a wave refills (tunable)
-int g_waves_per_cu = 16;  // resident waves per CU the grid is sized for
-int g_lds_depth = 16;     // traversal stack entries per lane in LDS
-int g_leaf_batch = 16;    // lanes waiting at leaves before a wave runs the leaf code
-int g_inst_batch = 8;     // lanes waiting at instance entries before a wave runs that code
+// Launch parameters per family of calls (RG_TUNE_*): refill threshold,
+// resident waves per CU, LDS stack entries per lane, lanes waiting at leaves
+// / instance entries before a wave runs that code.  Incoherent ray batches
+// gain from waiting lanes; the coherent rays of frames do not.
+rg_trace_tune g_tune[RG_TUNE_SCOPES] = {
+    {8, 16, 16, 16, 8},  // RG_TUNE_TRACE: rg_trace_closest / any / counts
+    {8, 16, 16, 1, 1},   // RG_TUNE_FRAME: rg_render, rg_batch_render
+    {8, 16, 16, 8, 1},   // RG_TUNE_ENGINE: rg_engine_step
+};
 
 }  // namespace
 
@@ -121,16 +125,16 @@ int rg_cu_count() {
 
 namespace {
 
-unsigned persistent_blocks(int64_t n) {
-    int64_t want = (int64_t)rg_cu_count() * g_waves_per_cu / (rgt::kThreads / 64);
+unsigned persistent_blocks(int64_t n, int waves_per_cu) {
+    int64_t want = (int64_t)rg_cu_count() * waves_per_cu / (rgt::kThreads / 64);
     int64_t need = rg_blocks(n, rgt::kThreads);
     return (unsigned)(need < want ? need : want);
 }
 
 template <int W>
-rg_status launch_w(bool any, int mode, const RgTraceArgs &a, hipStream_t st) {
-    unsigned blocks = persistent_blocks(a.n);
-    int refill = g_refill, lds = g_lds_depth, lb = g_leaf_batch, ib = g_inst_batch;
+rg_status launch_w(bool any, int mode, const RgTraceArgs &a, hipStream_t st, const rg_trace_tune &t) {
+    unsigned blocks = persistent_blocks(a.n, t.waves_per_cu);
+    int refill = t.refill, lds = t.lds_depth, lb = t.leaf_batch, ib = t.inst_batch;
     size_t shm = (size_t)lds * rgt::kThreads * sizeof(uint32_t);
     if (mode == rgt::kCounts) {
         if (any) k_trace<W, true, rgt::kCounts><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
@@ -167,35 +171,28 @@ bool rg_trace_depth_ok(const rg_tlas *t) {
     return need <= rgt::kStackCap;
 }
 
-rg_status rg_trace_launch(int width, bool any, int mode, const RgTraceArgs &a, hipStream_t st) {
+rg_status rg_trace_launch(int width, bool any, int mode, const RgTraceArgs &a, hipStream_t st, int scope) {
     if (a.n <= 0) return RG_OK;
-    if (width == 2) return launch_w<2>(any, mode, a, st);
-    if (width == 4) return launch_w<4>(any, mode, a, st);
-    if (width == 8) return launch_w<8>(any, mode, a, st);
+    if (scope < 0 || scope >= RG_TUNE_SCOPES) return RG_ERR_INVALID_ARG;
+    const rg_trace_tune t = g_tune[scope];
+    if (width == 2) return launch_w<2>(any, mode, a, st, t);
+    if (width == 4) return launch_w<4>(any, mode, a, st, t);
+    if (width == 8) return launch_w<8>(any, mode, a, st, t);
     return RG_ERR_INVALID_ARG;
 }
 
 extern "C" {
 
-rg_status rg_trace_tuning(const rg_trace_tune *set, rg_trace_tune *get) {
+rg_status rg_trace_tuning(int32_t scope, const rg_trace_tune *set, rg_trace_tune *get) {
+    if (scope < 0 || scope >= RG_TUNE_SCOPES) return RG_ERR_INVALID_ARG;
     if (set) {
         if (set->refill < 1 || set->refill > 64 || set->waves_per_cu < 4 || set->waves_per_cu > 64 ||
             set->lds_depth < 8 || set->lds_depth > rgt::kMaxLdsStack || set->leaf_batch < 1 ||
             set->leaf_batch > 64 || set->inst_batch < 1 || set->inst_batch > 64)
             return RG_ERR_INVALID_ARG;
-        g_refill = set->refill;
-        g_waves_per_cu = set->waves_per_cu;
-        g_lds_depth = set->lds_depth;
-        g_leaf_batch = set->leaf_batch;
-        g_inst_batch = set->inst_batch;
+        g_tune[scope] = *set;
     }
-    if (get) {
-        get->refill = g_refill;
-        get->waves_per_cu = g_waves_per_cu;
-        get->lds_depth = g_lds_depth;
-        get->leaf_batch = g_leaf_batch;
-        get->inst_batch = g_inst_batch;
-    }
+    if (get) *get = g_tune[scope];
     return RG_OK;
 }
 
@@ -209,7 +206,7 @@ rg_status rg_trace_closest(const rg_tlas *tlas, rg_rays rays, int64_t n, rg_hits
     fill_rays(a, rays);
     a.n = n;
     a.t = out.t; a.u = out.u; a.v = out.v; a.inst = out.inst; a.prim = out.prim;
-    return rg_trace_launch(tlas->width, false, rgt::kClosest, a, (hipStream_t)stream);
+    return rg_trace_launch(tlas->width, false, rgt::kClosest, a, (hipStream_t)stream, RG_TUNE_TRACE);
 }
 
 rg_status rg_trace_any(const rg_tlas *tlas, rg_rays rays, int64_t n, uint8_t *occluded, const rg_hits *found,
@@ -226,7 +223,7 @@ rg_status rg_trace_any(const rg_tlas *tlas, rg_rays rays, int64_t n, uint8_t *oc
     if (found) {
         a.t = found->t; a.u = found->u; a.v = found->v; a.inst = found->inst; a.prim = found->prim;
     }
-    return rg_trace_launch(tlas->width, true, rgt::kClosest, a, (hipStream_t)stream);
+    return rg_trace_launch(tlas->width, true, rgt::kClosest, a, (hipStream_t)stream, RG_TUNE_TRACE);
 }
 
 rg_status rg_trace_counts(const rg_tlas *tlas, rg_rays rays, int64_t n, int32_t any_hit, uint32_t *counts,
@@ -240,7 +237,7 @@ rg_status rg_trace_counts(const rg_tlas *tlas, rg_rays rays, int64_t n, int32_t 
     fill_rays(a, rays);
     a.n = n;
     a.counts = counts;
-    return rg_trace_launch(tlas->width, any_hit != 0, rgt::kCounts, a, (hipStream_t)stream);
+    return rg_trace_launch(tlas->width, any_hit != 0, rgt::kCounts, a, (hipStream_t)stream, RG_TUNE_TRACE);
 }
 
 }  // extern "C"

@@ -464,7 +464,8 @@ struct RgTraceArgs {
 
 // Launches the traversal over a.n rays (or *a.count if set) on `stream`.
 // width: 2/4/8; any: any-hit; mode: rgt::Mode.
-rg_status rg_trace_launch(int width, bool any, int mode, const RgTraceArgs &a, hipStream_t stream);
+// scope: the RG_TUNE_* family whose launch parameters apply.
+rg_status rg_trace_launch(int width, bool any, int mode, const RgTraceArgs &a, hipStream_t stream, int scope);
 // Compute units of the current device (queried once).
 int rg_cu_count();
 // Largest (W-1)*(top depth + bottom depth) + 1 the traversal stack holds.

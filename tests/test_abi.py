@@ -118,3 +118,28 @@ def test_undersized_buffers_are_rejected():
                              ctypes.byref(d)) == -2
     assert lib.rg_build_blas(256, 300, 256, 100, None, ctypes.byref(o), 256, nb, 256, ns - 1, None,
                              ctypes.byref(d)) == -2
+
+
+def test_trace_tuning_scopes_host_only():
+    """rg_trace_tuning keeps one launch-parameter set per family of calls and
+    validates ranges (host state only, no GPU call)."""
+    import pytest
+    import paper_2001_09792_amd as rg
+    saved = {s: rg.trace_tuning(scope=s) for s in rg.TUNE_SCOPES}
+    try:
+        assert saved["trace"]["leaf_batch"] == 16 and saved["trace"]["inst_batch"] == 8
+        assert saved["frame"]["leaf_batch"] == 1 and saved["frame"]["inst_batch"] == 1
+        rg.trace_tuning(refill=32, leaf_batch=4, scope="engine")
+        assert rg.trace_tuning(scope="engine")["refill"] == 32
+        assert rg.trace_tuning(scope="trace") == saved["trace"]      # other scopes untouched
+        assert rg.trace_tuning(scope="frame") == saved["frame"]
+        for bad in (dict(refill=0), dict(refill=65), dict(waves_per_cu=3), dict(lds_depth=7), dict(lds_depth=33),
+                    dict(leaf_batch=0), dict(inst_batch=65)):
+            with pytest.raises(rg.RgError):
+                rg.trace_tuning(scope="trace", **bad)
+        assert rg.trace_tuning(scope="trace") == saved["trace"]      # a rejected set changes nothing
+        t = rg.TraceTune()
+        assert rg._lib.rg_trace_tuning(3, None, ctypes.byref(t)) == -1  # unknown scope
+    finally:
+        for s, v in saved.items():
+            rg.trace_tuning(scope=s, **v)

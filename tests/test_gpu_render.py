@@ -118,3 +118,23 @@ def test_oblique_glass_matches_snell_schlick():
         F = 0.04 + 0.96 * (1 - s) ** 5
         expect = F * sky(-s) + (1 - F) * sky(-s / 1.5)
         assert np.allclose(got, expect, atol=1e-5), mirror
+
+
+def test_frame_launch_parameters_do_not_change_images():
+    """The frame family's launch parameters reorder work only: bitwise the same image."""
+    import paper_2001_09792_amd as rg
+    sc = sg.config_two_level(width=160, height=90, max_depth=3)
+    tl = rg.upload_scene(sc, 4, 2)
+    saved = rg.trace_tuning(scope="frame")
+    try:
+        ref = None
+        for cfg in (dict(refill=8, waves_per_cu=16, lds_depth=16, leaf_batch=1, inst_batch=1),
+                    dict(refill=32, waves_per_cu=8, lds_depth=8, leaf_batch=16, inst_batch=8),
+                    dict(refill=1, waves_per_cu=24, lds_depth=32, leaf_batch=64, inst_batch=64)):
+            rg.trace_tuning(scope="frame", **cfg)
+            img = rg.render(tl, sc.materials, sc.camera, sc.light, 160, 90, 3).cpu().numpy()
+            if ref is None:
+                ref = img
+            assert np.array_equal(img.view(np.uint32), ref.view(np.uint32)), cfg
+    finally:
+        rg.trace_tuning(scope="frame", **saved)
