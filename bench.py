@@ -361,6 +361,9 @@ def bench_batched(args, torch, rg, sg):
     _, st = batch.render(stats=True)
     rays = st["rays_traced"] + st["shadow_rays"]
     ms_batch, wall_batch = timed(batch.render, args.steps)
+    graph = batch.capture()
+    ms_graph, wall_graph = timed(graph.replay, args.steps)
+    del graph
     # bitwise identity needs the same hierarchy and launch: a tuned width or
     # leaf size may flip rounding-level ties, so the tuned images are compared
     # by their largest difference and a default-configured batch by identity
@@ -382,6 +385,7 @@ def bench_batched(args, torch, rg, sg):
                    "unique_tris": int(sum(s.unique_tris() for s in scenes))},
         "plain_mrays_s": rays / (ms_plain * 1e-3) / 1e6, "plain_ms": ms_plain, "plain_wall_ms": wall_plain,
         "batched_mrays_s": rays / (ms_batch * 1e-3) / 1e6, "batched_ms": ms_batch, "batched_wall_ms": wall_batch,
+        "graph_ms": ms_graph, "graph_wall_ms": wall_graph,
         "speedup": ms_plain / ms_batch, "images_identical": bool(same), "tuned_max_abs_diff": max_diff,
         "autotuned": tuned, "plain_launch": default_launch, "batched_launch": batched_launch,
         "roofline": None,

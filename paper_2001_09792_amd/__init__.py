@@ -503,6 +503,22 @@ class Batch:
         _check("rg_batch_prepare", _lib.rg_batch_prepare(jobs, n, _ptr(self.scratch), self.scratch.numel(),
                                                          _stream(stream), ctypes.byref(self.desc)))
 
+    def capture(self):
+        """Captures one render() of the whole batch into a HIP graph
+        (torch.cuda.CUDAGraph): graph.replay() re-renders every frame into
+        the same images.  The batch is a launch sequence only (counters are
+        cleared by kernels, nothing waits on the host), so it captures as is."""
+        torch = _torch()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            self.render()             # warm-up outside the capture
+        torch.cuda.current_stream().wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.render()
+        return g
+
     def render(self, stats: bool = False, stream=None):
         st = RenderStats()
         _check("rg_batch_render", _lib.rg_batch_render(ctypes.byref(self.desc), _stream(stream),
