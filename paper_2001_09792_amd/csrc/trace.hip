@@ -31,8 +31,25 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
     int64_t next = 0;  // position in this wave's ray sequence (the same in all lanes)
     int64_t ray_i = -1;
     bool has = false;
+    // A finished ray's results stay in its lane until the lane takes its next
+    // ray (or the wave ends): writing them then puts the stores next to the
+    // new ray's loads, instead of making every round wait for stores.
+    bool pend = false;
+    auto write_result = [&]() {
+        if (MODE == rgt::kCounts) {
+            a.counts[3 * ray_i] = tr.h.n_nodes;
+            a.counts[3 * ray_i + 1] = tr.h.n_tris;
+            a.counts[3 * ray_i + 2] = tr.h.n_inst;
+        } else {
+            if (ANY && a.occluded) a.occluded[ray_i] = tr.found ? 1 : 0;
+            if (a.t) a.t[ray_i] = tr.h.t;
+            if (a.u) a.u[ray_i] = tr.h.u;
+            if (a.v) a.v[ray_i] = tr.h.v;
+            if (a.inst) a.inst[ray_i] = tr.h.inst;
+            if (a.prim) a.prim[ray_i] = tr.h.prim;
+        }
+    };
     while (true) {
-        bool finished = false;
         // every ballot and every update of `next` below is executed by all
         // lanes together, so `next` stays uniform across the wave
         const uint64_t need = __ballot(!has);
@@ -43,6 +60,7 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
                 int64_t pkt = wave + (j >> 6) * n_waves;
                 int64_t idx = pkt * 64 + (j & 63);
                 if (pkt < n_packets && idx < n) {
+                    if (pend) write_result();
                     rgt::Ray R;
                     R.o[0] = a.ray[0][idx]; R.o[1] = a.ray[1][idx]; R.o[2] = a.ray[2][idx];
                     R.d[0] = a.ray[3][idx]; R.d[1] = a.ray[4][idx]; R.d[2] = a.ray[5][idx];
@@ -55,48 +73,35 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
                         tr.recs = J.recs;
                     }
                     has = tr.begin(R);
-                    finished = !has;  // empty interval: a miss without traversal
+                    pend = !has;  // empty interval: a miss without traversal
                 }
             }
             next += n_need;
         }
-        if (__ballot(has || finished) == 0) {
+        if (__ballot(has) == 0) {
             // no lane holds a ray after a refill attempt of all 64 lanes: the
             // sequence is exhausted once its next packet is past the end
             if (wave + (next >> 6) * n_waves >= n_packets) break;
-        } else {
-            // Which kinds of unit run this round: inner nodes whenever a lane
-            // has one; leaves and instance entries (each a long stretch of code
-            // that runs for the whole wave if any lane needs it) once enough
-            // lanes wait for one, or when nothing else is left.  A lane that
-            // waits keeps its state; every round runs at least one kind present.
-            const uint32_t my = has ? tr.kind() : 0u;
-            const int n_inner = __popcll(__ballot(my == rgt::kUnitInner));
-            const int n_leaf = __popcll(__ballot(my == rgt::kUnitLeaf));
-            const int n_inst = __popcll(__ballot(my == rgt::kUnitInst));
-            uint32_t run = n_inner ? rgt::kUnitInner : 0u;
-            if (n_leaf && (n_leaf >= leaf_batch || n_inner == 0)) run |= rgt::kUnitLeaf;
-            if (n_inst && (n_inst >= inst_batch || run == 0)) run |= rgt::kUnitInst;
-            if ((run & my) != 0u && tr.step()) {  // my == 0 for lanes without a ray
-                has = false;
-                finished = true;
-            }
-            if (finished) {
-                if (MODE == rgt::kCounts) {
-                    a.counts[3 * ray_i] = tr.h.n_nodes;
-                    a.counts[3 * ray_i + 1] = tr.h.n_tris;
-                    a.counts[3 * ray_i + 2] = tr.h.n_inst;
-                } else {
-                    if (ANY && a.occluded) a.occluded[ray_i] = tr.found ? 1 : 0;
-                    if (a.t) a.t[ray_i] = tr.h.t;
-                    if (a.u) a.u[ray_i] = tr.h.u;
-                    if (a.v) a.v[ray_i] = tr.h.v;
-                    if (a.inst) a.inst[ray_i] = tr.h.inst;
-                    if (a.prim) a.prim[ray_i] = tr.h.prim;
-                }
-            }
+            continue;
+        }
+        // Which kinds of unit run this round: inner nodes whenever a lane
+        // has one; leaves and instance entries (each a long stretch of code
+        // that runs for the whole wave if any lane needs it) once enough
+        // lanes wait for one, or when nothing else is left.  A lane that
+        // waits keeps its state; every round runs at least one kind present.
+        const uint32_t my = has ? tr.kind() : 0u;
+        const int n_inner = __popcll(__ballot(my == rgt::kUnitInner));
+        const int n_leaf = __popcll(__ballot(my == rgt::kUnitLeaf));
+        const int n_inst = __popcll(__ballot(my == rgt::kUnitInst));
+        uint32_t run = n_inner ? rgt::kUnitInner : 0u;
+        if (n_leaf && (n_leaf >= leaf_batch || n_inner == 0)) run |= rgt::kUnitLeaf;
+        if (n_inst && (n_inst >= inst_batch || run == 0)) run |= rgt::kUnitInst;
+        if ((run & my) != 0u && tr.step()) {  // my == 0 for lanes without a ray
+            has = false;
+            pend = true;
         }
     }
+    if (pend) write_result();
 }
 
 // Launch parameters per family of calls (RG_TUNE_*): refill threshold,
