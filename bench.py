@@ -515,7 +515,7 @@ def main():
     ap.add_argument("--rate-factors", type=float, nargs="+", default=[0.25, 0.5, 0.75, 0.9, 1.0, 1.25])
     ap.add_argument("--plain-factors", type=float, nargs="*", default=[0.5, 0.9])
     ap.add_argument("--width", type=int, default=4)
-    ap.add_argument("--leaf", type=int, default=2)
+    ap.add_argument("--leaf", type=int, default=1)
     ap.add_argument("--refill", type=int, default=None, help="traversal refill threshold (lanes)")
     ap.add_argument("--waves-per-cu", type=int, default=None, help="persistent traversal waves per CU")
     ap.add_argument("--lds-depth", type=int, default=None, help="traversal stack entries per lane in LDS")

@@ -127,7 +127,7 @@ def test_trace_tuning_scopes_host_only():
     import paper_2001_09792_amd as rg
     saved = {s: rg.trace_tuning(scope=s) for s in rg.TUNE_SCOPES}
     try:
-        assert saved["trace"]["leaf_batch"] == 16 and saved["trace"]["inst_batch"] == 8
+        assert saved["trace"]["leaf_batch"] == 12 and saved["trace"]["inst_batch"] == 6
         assert saved["frame"]["leaf_batch"] == 1 and saved["frame"]["inst_batch"] == 1
         rg.trace_tuning(refill=32, leaf_batch=4, scope="engine")
         assert rg.trace_tuning(scope="engine")["refill"] == 32
