@@ -134,3 +134,98 @@ def refit(lo_sorted: np.ndarray, hi_sorted: np.ndarray, first, last):
         blo[k] = lo_sorted[first[k]:last[k] + 1].min(axis=0)
         bhi[k] = hi_sorted[first[k]:last[k] + 1].max(axis=0)
     return blo, bhi
+
+
+# ----------------------------------------------------------------------------
+# Locally-ordered clustering (PLOC; Meister & Bittner 2018, "Parallel
+# Locally-Ordered Clustering for Bounding Volume Hierarchy Construction")
+# ----------------------------------------------------------------------------
+def surface_area32(lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
+    """2 (dx dy + dy dz + dz dx) of boxes, float32, left to right, no FMA."""
+    d = (hi.astype(np.float32) - lo.astype(np.float32)).astype(np.float32)
+    a = (d[..., 0] * d[..., 1]).astype(np.float32)
+    b = (d[..., 1] * d[..., 2]).astype(np.float32)
+    c = (d[..., 2] * d[..., 0]).astype(np.float32)
+    return (np.float32(2.0) * ((a + b).astype(np.float32) + c).astype(np.float32)).astype(np.float32)
+
+
+def ploc(lo_sorted: np.ndarray, hi_sorted: np.ndarray, radius: int):
+    """Agglomerative clustering over the Morton-sorted leaves, as defined for
+    this build:
+
+      clusters  start as the leaves in sorted order (leaf p encoded -(p+1))
+      distance  d(i, j) = float32 surface area of the union of the boxes
+      nearest   n(i) = argmin over j in [i-radius, i+radius], j != i, of
+                (d(i, j), j): ties go to the smaller index
+      merge     i < n(i) and n(n(i)) == i: a new inner node with children
+                (cluster i, cluster n(i)) takes position i, n(i) is dropped;
+                the remaining clusters keep their order
+      numbering the k-th merge (iterations in order, positions ascending
+                within one) gets inner index n-2-k, so the root is 0
+
+    Returns left, right (int64[n-1], Karras-style encoding), the inner boxes
+    (lo, hi float32[n-1,3]) and the number of iterations."""
+    n = lo_sorted.shape[0]
+    left = np.zeros(max(n - 1, 0), np.int64)
+    right = np.zeros(max(n - 1, 0), np.int64)
+    blo = np.zeros((max(n - 1, 0), 3), np.float32)
+    bhi = np.zeros((max(n - 1, 0), 3), np.float32)
+    cid = -(np.arange(n, dtype=np.int64) + 1)
+    clo = lo_sorted.astype(np.float32).copy()
+    chi = hi_sorted.astype(np.float32).copy()
+    next_id = n - 2
+    its = 0
+    while cid.shape[0] > 1:
+        its += 1
+        m = cid.shape[0]
+        best_d = np.full(m, np.inf, np.float32)
+        best_j = np.full(m, m, np.int64)
+        for j_off in range(-radius, radius + 1):
+            if j_off == 0:
+                continue
+            j = np.arange(m) + j_off
+            ok = (j >= 0) & (j < m)
+            jj = np.where(ok, j, 0)
+            d = surface_area32(np.minimum(clo, clo[jj]), np.maximum(chi, chi[jj]))
+            d = np.where(ok, d, np.float32(np.inf))
+            better = ok & ((d < best_d) | ((d == best_d) & (jj < best_j)))
+            best_d = np.where(better, d, best_d)
+            best_j = np.where(better, jj, best_j)
+        i = np.arange(m)
+        mutual = best_j[best_j] == i
+        merge = mutual & (i < best_j)
+        a = i[merge]
+        b = best_j[merge]
+        ids = next_id - np.arange(a.shape[0])
+        next_id -= a.shape[0]
+        left[ids] = cid[a]
+        right[ids] = cid[b]
+        blo[ids] = np.minimum(clo[a], clo[b])
+        bhi[ids] = np.maximum(chi[a], chi[b])
+        cid[a] = ids
+        clo[a] = blo[ids]
+        chi[a] = bhi[ids]
+        keep = np.ones(m, bool)
+        keep[b] = False
+        cid, clo, chi = cid[keep], clo[keep], chi[keep]
+    return left, right, blo, bhi, its
+
+
+def leaf_order(left: np.ndarray, right: np.ndarray, n: int) -> np.ndarray:
+    """Rank of each leaf in the left-to-right order of the tree (the order
+    the triangles are stored in, so that every subtree is a contiguous
+    range)."""
+    rank = np.zeros(n, np.int64)
+    if n == 1:
+        return rank
+    k = 0
+    stack = [0]
+    while stack:
+        c = stack.pop()
+        if c < 0:
+            rank[-c - 1] = k
+            k += 1
+        else:
+            stack.append(right[c])
+            stack.append(left[c])
+    return rank

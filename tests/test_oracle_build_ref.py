@@ -1,6 +1,7 @@
 """Pins of the plain build-step definitions (linear BVH after Karras 2012):
 Morton interleave, stable sort, the radix-tree split rule and the refit."""
 import numpy as np
+import pytest
 
 import scenegen as sg
 from oracle import build_ref as br
@@ -73,3 +74,85 @@ def test_refit_contains_children():
         for c in (left[k], right[k]):
             clo, chi = (blo[c], bhi[c]) if c >= 0 else (lo[-c - 1], hi[-c - 1])
             assert (blo[k] <= clo).all() and (bhi[k] >= chi).all()
+
+
+# ----------------------------------------------------------------- PLOC
+def test_ploc_hand_case():
+    """Four unit-section boxes along x at [0,1], [1,2], [4,5], [9,10]:
+    union areas 2(2 dx + 1) give d(0,1) = 10, d(1,2) = 18, d(0,2) = 22,
+    d(2,3) = 26.  Iteration 1 merges the mutual pair (0,1) into inner 2;
+    iteration 2 pairs it with [4,5] (22 < 26) into inner 1; the root 0
+    joins [9,10]."""
+    lo = np.array([[0, 0, 0], [1, 0, 0], [4, 0, 0], [9, 0, 0]], np.float32)
+    hi = lo + np.array([1, 1, 1], np.float32)
+    left, right, blo, bhi, its = br.ploc(lo, hi, 3)
+    assert left.tolist() == [1, 2, -1] and right.tolist() == [-4, -3, -2]
+    assert its == 3
+    assert blo[0].tolist() == [0, 0, 0] and bhi[0].tolist() == [10, 1, 1]
+    assert bhi[1].tolist() == [5, 1, 1] and bhi[2].tolist() == [2, 1, 1]
+    # radius 1 sees the same pairs here
+    assert br.ploc(lo, hi, 1)[0].tolist() == [1, 2, -1]
+
+
+def test_ploc_surface_area_float32():
+    lo = np.array([[0.1, 0.2, 0.3]], np.float32)
+    hi = np.array([[1.7, 2.9, 0.8]], np.float32)
+    d = (hi - lo).astype(np.float32)
+    expect = np.float32(2) * ((d[0, 0] * d[0, 1] + d[0, 1] * d[0, 2]) + d[0, 2] * d[0, 0])
+    assert br.surface_area32(lo, hi)[0] == expect
+    assert abs(float(br.surface_area32(lo, hi)[0]) - 2 * (1.6 * 2.7 + 2.7 * 0.5 + 0.5 * 1.6)) < 1e-5
+
+
+@pytest.mark.parametrize("n,radius,seed", [(2, 1, 0), (3, 2, 1), (97, 4, 2), (600, 16, 3), (600, 1, 4)])
+def test_ploc_structure(n, radius, seed):
+    m = sg.random_soup(n, seed)
+    lo, hi = br.tri_boxes(m.verts, m.idx)
+    keys = br.morton_keys(m.verts, m.idx)
+    _, order = br.sort_pairs(keys)
+    slo, shi = lo[order], hi[order]
+    left, right, blo, bhi, its = br.ploc(slo, shi, radius)
+    # every leaf exactly once, every inner node except the root exactly once
+    kids = np.concatenate([left, right])
+    leaves = np.sort(-kids[kids < 0] - 1)
+    assert np.array_equal(leaves, np.arange(n))
+    inner = np.sort(kids[kids >= 0])
+    assert np.array_equal(inner, np.arange(1, n - 1))
+    # children are created before their parent: larger inner index
+    assert all(c > k for k in range(n - 1) for c in (left[k], right[k]) if c >= 0)
+    # inner box = exact union of the children's boxes
+    def box(c):
+        return (slo[-c - 1], shi[-c - 1]) if c < 0 else (blo[c], bhi[c])
+    for k in range(n - 1):
+        (a0, a1), (b0, b1) = box(left[k]), box(right[k])
+        assert np.array_equal(blo[k], np.minimum(a0, b0)) and np.array_equal(bhi[k], np.maximum(a1, b1))
+    # every iteration merges at least one pair (the globally closest neighbours)
+    assert its <= n - 1
+    # leaf order: a permutation under which every subtree is contiguous
+    rank = br.leaf_order(left, right, n)
+    assert np.array_equal(np.sort(rank), np.arange(n))
+    def span(c):
+        if c < 0:
+            return rank[-c - 1], rank[-c - 1], 1
+        l0, l1, ln = span(left[c])
+        r0, r1, rn = span(right[c])
+        assert l1 + 1 == r0                      # left subtree directly before the right one
+        return l0, r1, ln + rn
+    if n > 1:
+        f, l, cnt = span(0)
+        assert (f, l, cnt) == (0, n - 1, n)
+
+
+def test_ploc_tighter_than_lbvh_on_a_mesh():
+    """Not a theorem, a sanity pin on a smooth mesh: the summed inner-node
+    area of the clustered tree is below the radix tree's."""
+    mesh = sg.torus(40, 40, 1.0, 0.35, 0.0875, 6.0, 3001)
+    lo, hi = br.tri_boxes(mesh.verts, mesh.idx)
+    keys = br.morton_keys(mesh.verts, mesh.idx)
+    skeys, order = br.sort_pairs(keys)
+    slo, shi = lo[order], hi[order]
+    left, right, first, last = br.radix_tree(skeys)
+    klo, khi = br.refit(slo, shi, first, last)
+    _, _, plo, phi, _ = br.ploc(slo, shi, 16)
+    a_lbvh = br.surface_area32(klo, khi).astype(np.float64).sum()
+    a_ploc = br.surface_area32(plo, phi).astype(np.float64).sum()
+    assert a_ploc < 0.95 * a_lbvh
