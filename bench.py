@@ -62,7 +62,8 @@ def recorded_traffic(args):
     except (OSError, ValueError):
         return None
     if (rec.get("kernel_sha256") != kernel_hash() or rec.get("bvh_width") != args.width
-            or rec.get("leaf_max") != args.leaf or rec.get("segments") != args.segments):
+            or rec.get("leaf_max") != args.leaf or rec.get("segments") != args.segments
+            or rec.get("builder", "lbvh") != args.builder):
         return None
     return float(rec["read_bytes"]) + float(rec["write_bytes"])
 
@@ -144,7 +145,7 @@ def bench_incoherent(args, torch, rg, sg):
         f"({time.perf_counter() - t0:.1f}s to generate)")
     torch.cuda.synchronize()
     tb = time.perf_counter()
-    tl = rg.upload_scene(scene, width=args.width, leaf_max=args.leaf)
+    tl = rg.upload_scene(scene, width=args.width, leaf_max=args.leaf, builder=args.builder)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - tb
     W, H = scene.width, scene.height
@@ -230,7 +231,8 @@ def bench_incoherent(args, torch, rg, sg):
                                f"{W}x{H} camera rays + 8 AO rays per primary hit (tmax 5), closest hit",
                    "rays_per_step": rays_step, "primary_rays": N, "ao_rays": n_ao,
                    "trace_tuning": rg.trace_tuning(scope="trace"),
-                   "primary_hit_fraction": prim_hit_frac, "bvh_width": args.width, "leaf_max": args.leaf},
+                   "primary_hit_fraction": prim_hit_frac, "bvh_width": args.width, "leaf_max": args.leaf,
+                   "builder": args.builder},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(args),
                      "kernel": "closest-hit traversal of the AO rays",
@@ -250,7 +252,7 @@ def bench_incoherent(args, torch, rg, sg):
 
 def bench_two_level(args, torch, rg, sg):
     scene = sg.config_two_level()
-    tl = rg.upload_scene(scene, width=args.width, leaf_max=args.leaf)
+    tl = rg.upload_scene(scene, width=args.width, leaf_max=args.leaf, builder=args.builder)
     r = rg.Renderer(scene.width, scene.height, scene.max_depth, 0)
     _, st = r.render(tl, scene.materials, scene.camera, scene.light, scene.seed, stats=True)
     rays = st["rays_traced"] + st["shadow_rays"]
@@ -288,7 +290,7 @@ def bench_batched(args, torch, rg, sg):
     def build(sel, width, leaf):
         out = []
         for sc in sel:
-            tl = rg.upload_scene(sc, width=width, leaf_max=leaf)
+            tl = rg.upload_scene(sc, width=width, leaf_max=leaf, builder=args.builder)
             out.append((tl, sc.materials, sc.camera, sc.light, sc.width, sc.height, sc.max_depth))
         torch.cuda.synchronize()
         return out
@@ -410,11 +412,11 @@ def bench_serving(args, torch, rg, sg):
         sc = scenes[k]
         if k >= n_c2:                      # C3-type: shared bottom levels, own top level
             if not shared:
-                shared.extend(rg.upload_scene(sc, width=args.width, leaf_max=args.leaf).blas)
-            tl = rg.build_tlas(shared, sc.xform, sc.blas_id, sc.inst_mat, args.width)
+                shared.extend(rg.upload_scene(sc, width=args.width, leaf_max=args.leaf, builder=args.builder).blas)
+            tl = rg.build_tlas(shared, sc.xform, sc.blas_id, sc.inst_mat, args.width, builder=args.builder)
             nbytes = tl.buf.numel() + (sum(b.buf.numel() for b in shared) if k == n_c2 else 0)
         else:
-            tl = rg.upload_scene(sc, width=args.width, leaf_max=args.leaf)
+            tl = rg.upload_scene(sc, width=args.width, leaf_max=args.leaf, builder=args.builder)
             nbytes = tl.buf.numel() + sum(b.buf.numel() for b in tl.blas)
         return (tl, rg.materials_array(sc.materials), sc.camera, sc.light), nbytes
 
@@ -516,6 +518,8 @@ def main():
     ap.add_argument("--plain-factors", type=float, nargs="*", default=[0.5, 0.9])
     ap.add_argument("--width", type=int, default=4)
     ap.add_argument("--leaf", type=int, default=1)
+    ap.add_argument("--builder", choices=["lbvh", "ploc"], default="lbvh",
+                    help="hierarchy builder: linear BVH or locally-ordered clustering")
     ap.add_argument("--refill", type=int, default=None, help="traversal refill threshold (lanes)")
     ap.add_argument("--waves-per-cu", type=int, default=None, help="persistent traversal waves per CU")
     ap.add_argument("--lds-depth", type=int, default=None, help="traversal stack entries per lane in LDS")

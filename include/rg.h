@@ -59,11 +59,29 @@ typedef int32_t rg_status;
 #define RG_PER_PRIM 0xFFFFFFFFu   /* instance material: use the mesh's per-primitive ids */
 #define RG_MAX_DEPTH 8
 
+/* Hierarchy builders.  Both start from the primitives sorted by the Morton
+ * code of their box centres.
+ *   RG_BUILDER_LBVH: Karras's radix tree over the sorted codes, boxes refit
+ *     bottom-up (the linear BVH the paper's GPU build follows).
+ *   RG_BUILDER_PLOC: parallel locally-ordered clustering (Meister & Bittner
+ *     2018): each round every cluster takes the neighbour, within `radius`
+ *     positions of the sorted cluster list, whose union box has the least
+ *     surface area (float32; ties to the nearer-to-front position); mutual
+ *     nearest pairs merge into the lower position; repeated down to one
+ *     cluster.  Slower to build, tighter boxes, fewer node visits. */
+#define RG_BUILDER_LBVH 0
+#define RG_BUILDER_PLOC 1
+#define RG_PLOC_RADIUS_DEFAULT 16
+
 /* Hierarchy options.  width = children per node (2, 4 or 8); leaf_max =
- * most triangles per leaf (1..8).  NULL means {4, 4}. */
+ * most triangles per leaf (1..8); builder = RG_BUILDER_*; radius = search
+ * radius of RG_BUILDER_PLOC (1..32, 0 = RG_PLOC_RADIUS_DEFAULT; ignored by
+ * RG_BUILDER_LBVH).  NULL means {4, 4, RG_BUILDER_LBVH, 0}. */
 typedef struct {
     int32_t width;
     int32_t leaf_max;
+    int32_t builder;
+    int32_t radius;
 } rg_build_opts;
 
 typedef struct {
@@ -159,9 +177,10 @@ const char *rg_last_error(void);
  * Errors: RG_ERR_INVALID_ARG for n_tris < 1 or > 2^28, bad opts, NULL out. */
 rg_status rg_blas_sizes(int64_t n_tris, const rg_build_opts *opts, rg_sizes *out /*host*/);
 
-/* Builds a linear BVH (Morton codes of triangle-box centres, LSD radix sort
- * with LDS ranking, Karras's radix-tree hierarchy, bottom-up box refit) and
- * collapses it into `width`-wide nodes with leaves of at most leaf_max
+/* Builds a binary BVH (Morton codes of triangle-box centres, LSD radix sort
+ * with LDS ranking, then opts' builder: Karras's radix tree with a bottom-up
+ * box refit, or locally-ordered clustering) and collapses it into
+ * `width`-wide nodes with leaves of at most leaf_max
  * triangles; writes nodes, triangles in leaf order and per-triangle
  * materials into out_buf.  verts: float[n_verts][3]; idx: uint32[n_tris][3];
  * prim_material: uint16[n_tris] or NULL.  Synchronous (waits for `stream`).
@@ -414,14 +433,21 @@ rg_status rg_engine_get_info(const rg_engine *engine, rg_engine_info *out /*host
 rg_status rg_engine_stats(rg_engine *engine, rg_render_stats *stats /*host*/);
 
 /* ------------------------------------------------ build verification */
-/* Runs the first build stages of rg_build_blas and copies their results out
- * for verification: keys uint64[n] and ids uint32[n] after the sort,
- * left/right int32[n-1] of the radix tree (>= 0 inner node, < 0 leaf -(i+1)),
- * boxes float[2n-1][6] (inner nodes 0..n-2, then leaves in sorted order).
- * scratch as for rg_build_blas.  Synchronous. */
+/* Runs the binary-hierarchy stages of rg_build_blas (with opts' builder;
+ * opts NULL as for rg_build_blas) and copies their results out for
+ * verification: keys uint64[n], the sorted Morton codes; ids uint32[n], the
+ * triangle order of the leaves; left/right int32[n-1] of the binary
+ * hierarchy (>= 0 inner node, < 0 leaf -(i+1), leaf i holding triangle
+ * ids[i]; inner node 0 is the root); boxes float[2n-1][6] (inner nodes
+ * 0..n-2, then the leaves 0..n-1).  For RG_BUILDER_LBVH the leaves are in
+ * sorted order (ids = the sort's permutation); for RG_BUILDER_PLOC inner
+ * nodes are numbered n-2 downward in merge order (a round's merges in order
+ * of position) and the leaves are renumbered to the tree's left-to-right
+ * order.  scratch as for rg_build_blas.  Synchronous. */
 rg_status rg_lbvh_stages(const float *verts, int64_t n_verts, const uint32_t *idx, int64_t n_tris,
-                         uint64_t *keys, uint32_t *ids, int32_t *left, int32_t *right, float *boxes,
-                         void *scratch, uint64_t scratch_bytes, void *stream);
+                         const rg_build_opts *opts /*host, nullable*/, uint64_t *keys, uint32_t *ids,
+                         int32_t *left, int32_t *right, float *boxes, void *scratch,
+                         uint64_t scratch_bytes, void *stream);
 
 #ifdef __cplusplus
 }

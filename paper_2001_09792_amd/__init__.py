@@ -35,7 +35,7 @@ c_p = ctypes.c_void_p
 
 
 class BuildOpts(ctypes.Structure):
-    _fields_ = [("width", c_i32), ("leaf_max", c_i32)]
+    _fields_ = [("width", c_i32), ("leaf_max", c_i32), ("builder", c_i32), ("radius", c_i32)]
 
 
 class Sizes(ctypes.Structure):
@@ -130,7 +130,7 @@ SIGNATURES = {
     "rg_render_sizes": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_p]),
     "rg_render": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_u64, c_p, c_p, c_u64,
                           c_p, c_p]),
-    "rg_lbvh_stages": (c_i32, [c_p, c_i64, c_p, c_i64, c_p, c_p, c_p, c_p, c_p, c_p, c_u64, c_p]),
+    "rg_lbvh_stages": (c_i32, [c_p, c_i64, c_p, c_i64, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_u64, c_p]),
     "rg_batch_sizes": (c_i32, [c_p, c_i32, c_p]),
     "rg_batch_prepare": (c_i32, [c_p, c_i32, c_p, c_u64, c_p, c_p]),
     "rg_batch_render": (c_i32, [c_p, c_p, c_p]),
@@ -206,8 +206,15 @@ def _bytes(n: int, device):
     return torch.empty(max(int(n), 256), dtype=torch.uint8, device=device)
 
 
-def _opts(width: int, leaf_max: int) -> BuildOpts:
-    return BuildOpts(width, leaf_max)
+# hierarchy builders (include/rg.h RG_BUILDER_*)
+BUILDERS = {"lbvh": 0, "ploc": 1}
+PLOC_RADIUS_DEFAULT = 16
+
+
+def _opts(width: int, leaf_max: int, builder: str = "lbvh", radius: int = 0) -> BuildOpts:
+    if builder not in BUILDERS:
+        raise ValueError(f"builder must be one of {sorted(BUILDERS)}")
+    return BuildOpts(width, leaf_max, BUILDERS[builder], radius)
 
 
 # -------------------------------------------------------------- bottom level
@@ -227,24 +234,24 @@ class Blas:
         return int(self.desc.depth)
 
 
-def blas_sizes(n_tris: int, width: int = 4, leaf_max: int = 4):
+def blas_sizes(n_tris: int, width: int = 4, leaf_max: int = 4, builder: str = "lbvh", radius: int = 0):
     s = Sizes()
-    o = _opts(width, leaf_max)
+    o = _opts(width, leaf_max, builder, radius)
     _check("rg_blas_sizes", _lib.rg_blas_sizes(n_tris, ctypes.byref(o), ctypes.byref(s)))
     return int(s.bytes), int(s.scratch_bytes)
 
 
 def build_blas(verts, idx, prim_mat=None, width: int = 4, leaf_max: int = 4, scratch=None,
-               stream=None) -> Blas:
+               stream=None, builder: str = "lbvh", radius: int = 0) -> Blas:
     """verts: CUDA float32 [V,3]; idx: CUDA int32/uint32 [T,3]; prim_mat: CUDA
-    int16 [T] or None."""
+    int16 [T] or None; builder: "lbvh" or "ploc" (radius 0: the default)."""
     n_tris = int(idx.shape[0])
-    nb, ns = blas_sizes(n_tris, width, leaf_max)
+    nb, ns = blas_sizes(n_tris, width, leaf_max, builder, radius)
     buf = _bytes(nb, verts.device)
     if scratch is None or scratch.numel() < ns:
         scratch = _bytes(ns, verts.device)
     d = BlasDesc()
-    o = _opts(width, leaf_max)
+    o = _opts(width, leaf_max, builder, radius)
     _check("rg_build_blas", _lib.rg_build_blas(
         _ptr(verts), int(verts.shape[0]), _ptr(idx), n_tris, _ptr(prim_mat), ctypes.byref(o),
         _ptr(buf), buf.numel(), _ptr(scratch), scratch.numel(), _stream(stream), ctypes.byref(d)))
@@ -264,7 +271,7 @@ class Tlas:
 
 
 def build_tlas(blas: Sequence[Blas], xform, blas_id, inst_mat, width: int = 4, stream=None,
-               scratch=None) -> Tlas:
+               scratch=None, builder: str = "lbvh", radius: int = 0) -> Tlas:
     """xform: host float32 [I,3,4]; blas_id, inst_mat: host uint32 [I]."""
     torch = _torch()
     xform = np.ascontiguousarray(xform, np.float32).reshape(-1, 12)
@@ -272,7 +279,7 @@ def build_tlas(blas: Sequence[Blas], xform, blas_id, inst_mat, width: int = 4, s
     inst_mat = np.ascontiguousarray(inst_mat, np.uint32)
     n = xform.shape[0]
     s = Sizes()
-    o = _opts(width, 1)
+    o = _opts(width, 1, builder, radius)
     _check("rg_tlas_sizes", _lib.rg_tlas_sizes(n, ctypes.byref(o), ctypes.byref(s)))
     dev = blas[0].buf.device
     buf = _bytes(s.bytes, dev)
@@ -288,9 +295,11 @@ def build_tlas(blas: Sequence[Blas], xform, blas_id, inst_mat, width: int = 4, s
     return Tlas(buf, d, blas)
 
 
-def upload_scene(scene, width: int = 4, leaf_max: int = 4, device="cuda") -> Tlas:
+def upload_scene(scene, width: int = 4, leaf_max: int = 4, device="cuda", builder: str = "lbvh",
+                 radius: int = 0, tlas_builder: Optional[str] = None) -> Tlas:
     """Builds every mesh and the instance level of a scene object with
-    attributes blas (meshes with verts/idx/prim_mat), xform, blas_id, inst_mat."""
+    attributes blas (meshes with verts/idx/prim_mat), xform, blas_id, inst_mat.
+    tlas_builder None: the instance level uses `builder` as well."""
     torch = _torch()
     built: List[Blas] = []
     for m in scene.blas:
@@ -299,9 +308,10 @@ def upload_scene(scene, width: int = 4, leaf_max: int = 4, device="cuda") -> Tla
         pm = None
         if m.prim_mat is not None:
             pm = torch.from_numpy(np.ascontiguousarray(m.prim_mat, np.uint16).view(np.int16)).to(device)
-        built.append(build_blas(v, i, pm, width, leaf_max))
+        built.append(build_blas(v, i, pm, width, leaf_max, builder=builder, radius=radius))
         del v, i, pm
-    return build_tlas(built, scene.xform, scene.blas_id, scene.inst_mat, width)
+    return build_tlas(built, scene.xform, scene.blas_id, scene.inst_mat, width,
+                      builder=tlas_builder or builder, radius=radius)
 
 
 # ------------------------------------------------------------------- rays
@@ -676,11 +686,13 @@ class Engine:
             pass
 
 
-def lbvh_stages(verts, idx, stream=None) -> dict:
-    """Intermediate results of the bottom-level build (keys, ids, tree, boxes)."""
+def lbvh_stages(verts, idx, stream=None, builder: str = "lbvh", radius: int = 0) -> dict:
+    """Intermediate results of the bottom-level build (keys, ids, binary
+    tree, boxes) for the given builder."""
     torch = _torch()
     n = int(idx.shape[0])
-    _, ns = blas_sizes(n)
+    _, ns = blas_sizes(n, builder=builder, radius=radius)
+    o = _opts(4, 4, builder, radius)
     scratch = _bytes(ns, verts.device)
     dev = verts.device
     keys = torch.empty(n, dtype=torch.int64, device=dev)
@@ -688,7 +700,8 @@ def lbvh_stages(verts, idx, stream=None) -> dict:
     left = torch.empty(max(n - 1, 1), dtype=torch.int32, device=dev)
     right = torch.empty(max(n - 1, 1), dtype=torch.int32, device=dev)
     boxes = torch.empty((2 * n - 1, 6), dtype=torch.float32, device=dev)
-    _check("rg_lbvh_stages", _lib.rg_lbvh_stages(_ptr(verts), int(verts.shape[0]), _ptr(idx), n, _ptr(keys),
+    _check("rg_lbvh_stages", _lib.rg_lbvh_stages(_ptr(verts), int(verts.shape[0]), _ptr(idx), n,
+                                                 ctypes.byref(o), _ptr(keys),
                                                  _ptr(ids), _ptr(left), _ptr(right), _ptr(boxes),
                                                  _ptr(scratch), scratch.numel(), _stream(stream)))
     return dict(keys=keys, ids=ids, left=left[:n - 1], right=right[:n - 1], boxes=boxes)

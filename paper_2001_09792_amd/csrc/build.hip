@@ -424,6 +424,229 @@ __global__ void k_collapse_init(uint2 *q, uint32_t *q_count, uint32_t *node_coun
     *node_count = 1u;
 }
 
+// ------------------------------------ 5'. locally-ordered clustering
+// Alternative to steps 4-5 (Meister & Bittner 2018): the Morton-sorted
+// leaves start as clusters; each round every cluster finds its nearest
+// neighbour within `radius` positions (distance: surface area of the union
+// box, float32, ties to the smaller position), mutual nearest pairs merge
+// into a new inner node at the lower position, and the clusters are compacted
+// in order.  Inner nodes are numbered n-2, n-3, ... in merge order, so the
+// root is 0 and children carry larger indices than their parents.
+constexpr int kPlocT = 256;
+constexpr int kPlocMaxRadius = 32;
+
+__device__ inline float union_area(const float *a, const float *b) {
+#pragma clang fp contract(off)
+    const float dx = fmaxf(a[3], b[3]) - fminf(a[0], b[0]);
+    const float dy = fmaxf(a[4], b[4]) - fminf(a[1], b[1]);
+    const float dz = fmaxf(a[5], b[5]) - fminf(a[2], b[2]);
+    return 2.0f * ((dx * dy + dy * dz) + dz * dx);
+}
+
+__global__ void k_ploc_init(const float *__restrict__ prim_box, const uint32_t *__restrict__ ids, int64_t n,
+                            float *__restrict__ leaf_box, int32_t *__restrict__ cid, float *__restrict__ cbox) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t src = ids[i];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const float v = prim_box[6 * (int64_t)src + k];
+        leaf_box[6 * i + k] = v;
+        cbox[6 * i + k] = v;
+    }
+    cid[i] = -(int32_t)(i + 1);
+}
+
+// nearest[i] for m clusters; the block's boxes and a halo of `radius` on each
+// side are staged in LDS
+__global__ void __launch_bounds__(kPlocT) k_ploc_nearest(const float *__restrict__ cbox, int64_t m, int radius,
+                                                         int32_t *__restrict__ nearest) {
+    __shared__ float tile[(kPlocT + 2 * kPlocMaxRadius) * 6];
+    const int64_t base = (int64_t)blockIdx.x * kPlocT - radius;
+    const int span = (kPlocT + 2 * radius) * 6;
+    for (int t = threadIdx.x; t < span; t += kPlocT) {
+        const int64_t g = base + t / 6;
+        tile[t] = (g >= 0 && g < m) ? cbox[6 * g + t % 6] : 0.0f;
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * kPlocT + threadIdx.x;
+    if (i >= m) return;
+    const float *bi = tile + 6 * (threadIdx.x + radius);
+    float best = INFINITY;
+    int64_t bj = m;
+    for (int o = -radius; o <= radius; ++o) {
+        const int64_t j = i + o;
+        if (o == 0 || j < 0 || j >= m) continue;
+        const float d = union_area(bi, tile + 6 * (threadIdx.x + radius + o));
+        if (d < best) {  // ascending j: a tie keeps the smaller position
+            best = d;
+            bj = j;
+        }
+    }
+    nearest[i] = (int32_t)bj;
+}
+
+// Per block: merges (i < nearest, mutual) and kept clusters (all but the
+// upper partner of a mutual pair).  counts[nb] and counts2[nb] are zeroed
+// so that their exclusive scans end in the totals.
+__global__ void __launch_bounds__(kPlocT) k_ploc_flags(const int32_t *__restrict__ nearest, int64_t m,
+                                                       uint32_t *__restrict__ merges, uint32_t *__restrict__ keeps,
+                                                       int nb) {
+    __shared__ uint32_t sm[kPlocT / 64], sk[kPlocT / 64];
+    const int64_t i = (int64_t)blockIdx.x * kPlocT + threadIdx.x;
+    bool merge = false, keep = false;
+    if (i < m) {
+        const int32_t j = nearest[i];
+        const bool mutual = j >= 0 && j < m && nearest[j] == (int32_t)i;
+        merge = mutual && i < j;
+        keep = !(mutual && i > j);
+    }
+    const uint64_t bm = __ballot(merge), bk = __ballot(keep);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        sm[w] = (uint32_t)__popcll(bm);
+        sk[w] = (uint32_t)__popcll(bk);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t a = 0, b = 0;
+        for (int k = 0; k < kPlocT / 64; ++k) {
+            a += sm[k];
+            b += sk[k];
+        }
+        merges[blockIdx.x] = a;
+        keeps[blockIdx.x] = b;
+        if (blockIdx.x == 0) {
+            merges[nb] = 0u;
+            keeps[nb] = 0u;
+        }
+    }
+}
+
+// Writes the next round's clusters (order kept) and the new inner nodes.
+__global__ void __launch_bounds__(kPlocT) k_ploc_write(
+    const int32_t *__restrict__ nearest, int64_t m, const uint32_t *__restrict__ merge_off,
+    const uint32_t *__restrict__ keep_off, int64_t next_id, const int32_t *__restrict__ cid,
+    const float *__restrict__ cbox, int32_t *__restrict__ out_cid, float *__restrict__ out_cbox,
+    int32_t *__restrict__ left, int32_t *__restrict__ right, float *__restrict__ int_box,
+    int32_t *__restrict__ parent_int, int32_t *__restrict__ parent_leaf) {
+    __shared__ uint32_t sm[kPlocT / 64], sk[kPlocT / 64];
+    const int64_t i = (int64_t)blockIdx.x * kPlocT + threadIdx.x;
+    int32_t j = 0;
+    bool merge = false, keep = false;
+    if (i < m) {
+        j = nearest[i];
+        const bool mutual = j >= 0 && j < m && nearest[j] == (int32_t)i;
+        merge = mutual && i < j;
+        keep = !(mutual && i > j);
+    }
+    const uint64_t bm = __ballot(merge), bk = __ballot(keep);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    if (lane == 0) {
+        sm[w] = (uint32_t)__popcll(bm);
+        sk[w] = (uint32_t)__popcll(bk);
+    }
+    __syncthreads();
+    uint32_t rm = (uint32_t)__popcll(bm & lt), rk = (uint32_t)__popcll(bk & lt);
+    for (int k = 0; k < w; ++k) {
+        rm += sm[k];
+        rk += sk[k];
+    }
+    if (!keep) return;
+    const int64_t at = (int64_t)keep_off[blockIdx.x] + rk;
+    if (!merge) {
+        out_cid[at] = cid[i];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) out_cbox[6 * at + k] = cbox[6 * i + k];
+        return;
+    }
+    const int32_t node = (int32_t)(next_id - (int64_t)(merge_off[blockIdx.x] + rm));
+    const int32_t a = cid[i], b = cid[j];
+    left[node] = a;
+    right[node] = b;
+    if (a < 0) parent_leaf[-a - 1] = node;
+    else parent_int[a] = node;
+    if (b < 0) parent_leaf[-b - 1] = node;
+    else parent_int[b] = node;
+    float box[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        box[k] = fminf(cbox[6 * i + k], cbox[6 * (int64_t)j + k]);
+        box[3 + k] = fmaxf(cbox[6 * i + 3 + k], cbox[6 * (int64_t)j + 3 + k]);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        int_box[6 * (int64_t)node + k] = box[k];
+        out_cbox[6 * at + k] = box[k];
+    }
+    out_cid[at] = node;
+}
+
+// Leaf counts of the inner nodes, bottom-up (the second child to arrive at a
+// node continues upwards).
+__global__ void k_ploc_sizes(int64_t n, const int32_t *__restrict__ left, const int32_t *__restrict__ right,
+                             const int32_t *__restrict__ parent_int, const int32_t *__restrict__ parent_leaf,
+                             uint32_t *counter, int32_t *size) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t p = parent_leaf[i];
+    while (p >= 0 && p < n - 1) {
+        uint32_t old = __hip_atomic_fetch_add(&counter[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == 0u) return;
+        const int32_t a = left[p], b = right[p];
+        const int32_t sa = a < 0 ? 1 : __hip_atomic_load(&size[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t sb = b < 0 ? 1 : __hip_atomic_load(&size[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&size[p], sa + sb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        p = parent_int[p];
+    }
+}
+
+// Rank of each leaf in the tree's left-to-right order: the leaves of the
+// left siblings along its path to the root come before it.  The leaf is the
+// leftmost of the ancestors reached from left children only, whose leaf range
+// starts at its rank.  Triangle order and leaf boxes follow the ranks.
+__global__ void k_ploc_ranks(int64_t n, const int32_t *__restrict__ left, const int32_t *__restrict__ parent_int,
+                             const int32_t *__restrict__ parent_leaf, const int32_t *__restrict__ size,
+                             const uint32_t *__restrict__ ids, const float *__restrict__ leaf_box,
+                             int32_t *__restrict__ rank, int32_t *__restrict__ first, int32_t *__restrict__ last,
+                             uint32_t *__restrict__ ids_out, float *__restrict__ leaf_box_out) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t me = -(int32_t)(i + 1);
+    int32_t r = 0;
+    int32_t c = me, p = parent_leaf[i];
+    for (int64_t guard = 0; p >= 0 && guard < n; ++guard) {
+        const int32_t l = left[p];
+        if (l != c) r += l < 0 ? 1 : size[l];
+        c = p;
+        p = parent_int[p];
+    }
+    if (r >= n) return;  // only for an inconsistent hierarchy, which the collapse reports
+    rank[i] = r;
+    c = me;
+    p = parent_leaf[i];
+    for (int64_t guard = 0; p >= 0 && guard < n && left[p] == c; ++guard) {
+        first[p] = r;
+        last[p] = r + size[p] - 1;
+        c = p;
+        p = parent_int[p];
+    }
+    ids_out[r] = ids[i];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) leaf_box_out[6 * (int64_t)r + k] = leaf_box[6 * i + k];
+}
+
+// Leaf children re-encoded by rank.
+__global__ void k_ploc_relabel(int64_t n, int32_t *__restrict__ left, int32_t *__restrict__ right,
+                               const int32_t *__restrict__ rank) {
+    const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (x >= n - 1) return;
+    const int32_t a = left[x], b = right[x];
+    if (a < 0) left[x] = -(rank[-a - 1] + 1);
+    if (b < 0) right[x] = -(rank[-b - 1] + 1);
+}
+
 // ------------------------------------------------------ reordering
 __global__ void k_reorder_tris(const float *__restrict__ verts, const uint32_t *__restrict__ idx,
                                const uint32_t *__restrict__ ids, int64_t n, const uint16_t *__restrict__ pm,
@@ -530,12 +753,19 @@ __global__ void k_reorder_inst(const RgInst *__restrict__ in, const uint32_t *__
 
 int node_bytes(int w) { return 32 * w; }
 
-bool opts_ok(const rg_build_opts *o, int32_t *w, int32_t *leaf) {
-    int32_t W = o ? o->width : 4, L = o ? o->leaf_max : 4;
-    if (!(W == 2 || W == 4 || W == 8)) return false;
-    if (L < 1 || L > 8) return false;
-    *w = W;
-    *leaf = L;
+struct Opts {
+    int32_t w, leaf, builder, radius;
+};
+
+bool opts_ok(const rg_build_opts *o, Opts *out) {
+    Opts r{4, 4, RG_BUILDER_LBVH, 0};
+    if (o) r = Opts{o->width, o->leaf_max, o->builder, o->radius};
+    if (!(r.w == 2 || r.w == 4 || r.w == 8)) return false;
+    if (r.leaf < 1 || r.leaf > 8) return false;
+    if (r.builder != RG_BUILDER_LBVH && r.builder != RG_BUILDER_PLOC) return false;
+    if (r.radius == 0) r.radius = RG_PLOC_RADIUS_DEFAULT;
+    if (r.radius < 1 || r.radius > kPlocMaxRadius) return false;
+    *out = r;
     return true;
 }
 
@@ -547,9 +777,13 @@ struct LbvhScratch {
     uint32_t *ids, *ids2, *hist, *bounds, *counter, *qcount, *flags;
     int32_t *left, *right, *pint, *pleaf, *first, *last;
     uint2 *q0, *q1;
+    // clustering only
+    int32_t *cid[2], *nearest, *rank, *size;
+    float *cbox[2];
+    uint32_t *n_merge, *n_keep;
 };
 
-bool carve(RgArena &a, int64_t n, LbvhScratch &s) {
+bool carve(RgArena &a, int64_t n, int32_t builder, LbvhScratch &s) {
     int64_t nb = (n + kSortTile - 1) / kSortTile;
     int64_t ni = n > 1 ? n - 1 : 1;
     s.leaf_box = a.take<float>(6 * n);
@@ -571,7 +805,66 @@ bool carve(RgArena &a, int64_t n, LbvhScratch &s) {
     s.last = a.take<int32_t>(ni);
     s.q0 = a.take<uint2>(ni);
     s.q1 = a.take<uint2>(ni);
+    if (builder == RG_BUILDER_PLOC) {
+        int64_t pb = (n + kPlocT - 1) / kPlocT + 1;
+        for (int k = 0; k < 2; ++k) {
+            s.cid[k] = a.take<int32_t>(n);
+            s.cbox[k] = a.take<float>(6 * n);
+        }
+        s.nearest = a.take<int32_t>(n);
+        s.rank = a.take<int32_t>(n);
+        s.size = a.take<int32_t>(ni);
+        s.n_merge = a.take<uint32_t>(pb);
+        s.n_keep = a.take<uint32_t>(pb);
+    }
     return !a.overflow();
+}
+
+// Clustering over the n >= 2 sorted leaves (`ids`): fills left, right,
+// parents, inner boxes, first / last; leaves, leaf boxes (s.leaf_box) and
+// the triangle order (*ids_out) in the tree's left-to-right order.
+rg_status ploc_build(const float *prim_box, int64_t n, int radius, const uint32_t *ids, uint32_t *ids_out,
+                     LbvhScratch &s, hipStream_t st) {
+    k_ploc_init<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(prim_box, ids, n, s.leaf_box, s.cid[0], s.cbox[0]);
+    k_fill_u32<<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>((uint32_t *)s.pint, 0xFFFFFFFFu, n - 1);
+    RG_LAUNCH_CHECK();
+    int64_t m = n, next = n - 2;
+    int cur = 0;
+    for (int64_t its = 0; m > 1; ++its) {
+        if (its > n) return RG_ERR_HIP;  // every round merges at least one pair
+        const int nb = (int)((m + kPlocT - 1) / kPlocT);
+        k_ploc_nearest<<<nb, kPlocT, 0, st>>>(s.cbox[cur], m, radius, s.nearest);
+        k_ploc_flags<<<nb, kPlocT, 0, st>>>(s.nearest, m, s.n_merge, s.n_keep, nb);
+        RG_LAUNCH_CHECK();
+        rg_status r = rg_scan_excl_u32(s.n_merge, nb + 1, st);
+        if (r == RG_OK) r = rg_scan_excl_u32(s.n_keep, nb + 1, st);
+        if (r != RG_OK) return r;
+        k_ploc_write<<<nb, kPlocT, 0, st>>>(s.nearest, m, s.n_merge, s.n_keep, next, s.cid[cur], s.cbox[cur],
+                                            s.cid[cur ^ 1], s.cbox[cur ^ 1], s.left, s.right, s.int_box, s.pint,
+                                            s.pleaf);
+        RG_LAUNCH_CHECK();
+        uint32_t tot[2];
+        RG_HIP(hipMemcpyAsync(tot, s.n_merge + nb, 4, hipMemcpyDeviceToHost, st));
+        RG_HIP(hipMemcpyAsync(tot + 1, s.n_keep + nb, 4, hipMemcpyDeviceToHost, st));
+        RG_HIP(hipStreamSynchronize(st));
+        if (tot[0] == 0u || (int64_t)tot[1] != m - (int64_t)tot[0]) return RG_ERR_HIP;
+        next -= tot[0];
+        m = tot[1];
+        cur ^= 1;
+    }
+    if (next != -1) return RG_ERR_HIP;
+    k_fill_u32<<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>(s.counter, 0u, n - 1);
+    k_ploc_sizes<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(n, s.left, s.right, s.pint, s.pleaf, s.counter,
+                                                               s.size);
+    // the boxes in left-to-right order go to a cluster buffer, which then
+    // replaces the sorted-order leaf boxes
+    k_ploc_ranks<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(n, s.left, s.pint, s.pleaf, s.size, ids,
+                                                               s.leaf_box, s.rank, s.first, s.last, ids_out,
+                                                               s.cbox[cur]);
+    k_ploc_relabel<<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>(n, s.left, s.right, s.rank);
+    RG_LAUNCH_CHECK();
+    s.leaf_box = s.cbox[cur];
+    return RG_OK;
 }
 
 template <int W>
@@ -625,18 +918,19 @@ rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes_v,
 
 }  // namespace
 
-uint64_t rg_lbvh_scratch_bytes(int64_t n) {
+uint64_t rg_lbvh_scratch_bytes(int64_t n, int32_t builder) {
     RgArena a{nullptr, 0, 0};
     LbvhScratch s;
-    carve(a, n, s);
+    carve(a, n, builder, s);
     return a.used;
 }
 
-rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t leaf_max, void *nodes,
-                        RgArena &arena, hipStream_t st, RgLbvhOut *out, bool keep_stages, uint64_t *keys_out,
-                        int32_t *left_out, int32_t *right_out, float *boxes_out) {
+rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t leaf_max, int32_t builder,
+                        int32_t radius, void *nodes, RgArena &arena, hipStream_t st, RgLbvhOut *out,
+                        bool keep_stages, uint64_t *keys_out, int32_t *left_out, int32_t *right_out,
+                        float *boxes_out) {
     LbvhScratch s;
-    if (!carve(arena, n, s)) return RG_ERR_OUT_OF_MEMORY;
+    if (!carve(arena, n, builder, s)) return RG_ERR_OUT_OF_MEMORY;
     int nblocks = (int)((n + kSortTile - 1) / kSortTile);
     // bounds of the centres
     k_fill_u32<<<1, 64, 0, st>>>(s.bounds, 0xFFFFFFFFu, 3);
@@ -658,15 +952,21 @@ rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t
         uint64_t *tk = ka; ka = kb; kb = tk;
         uint32_t *ti = ia; ia = ib; ib = ti;
     }
-    if (n > 1) {
-        k_karras<<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>(ka, n, s.left, s.right, s.pint, s.pleaf, s.first,
-                                                                  s.last);
-        k_fill_u32<<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>(s.counter, 0u, n - 1);
+    if (builder == RG_BUILDER_PLOC && n > 1) {
+        rg_status r = ploc_build(prim_box, n, radius, ia, ib, s, st);
+        if (r != RG_OK) return r;
+        ia = ib;
+    } else {
+        if (n > 1) {
+            k_karras<<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>(ka, n, s.left, s.right, s.pint, s.pleaf,
+                                                                      s.first, s.last);
+            k_fill_u32<<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>(s.counter, 0u, n - 1);
+            RG_LAUNCH_CHECK();
+        }
+        k_refit<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(prim_box, ia, n, s.left, s.right, s.pint, s.pleaf,
+                                                             s.counter, s.int_box, s.leaf_box);
         RG_LAUNCH_CHECK();
     }
-    k_refit<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(prim_box, ia, n, s.left, s.right, s.pint, s.pleaf, s.counter,
-                                                         s.int_box, s.leaf_box);
-    RG_LAUNCH_CHECK();
     if (keep_stages) {
         RG_HIP(hipMemcpyAsync(keys_out, ka, 8 * n, hipMemcpyDeviceToDevice, st));
         if (n > 1) {
@@ -718,11 +1018,11 @@ uint64_t blas_out_bytes(int64_t n, int w, uint64_t *nodes_off, uint64_t *tris_of
     return off;
 }
 
-uint64_t blas_scratch_bytes(int64_t n) {
+uint64_t blas_scratch_bytes(int64_t n, int32_t builder) {
     RgArena a{nullptr, 0, 0};
     a.take<float>(6 * n);  // primitive boxes
     a.take<uint32_t>(8);   // flags
-    return a.used + rg_lbvh_scratch_bytes(n);
+    return a.used + rg_lbvh_scratch_bytes(n, builder);
 }
 
 uint64_t tlas_out_bytes(int64_t n, int w, uint64_t *nodes_off, uint64_t *inst_off, uint64_t *rec_off) {
@@ -737,7 +1037,7 @@ uint64_t tlas_out_bytes(int64_t n, int w, uint64_t *nodes_off, uint64_t *inst_of
     return off;
 }
 
-uint64_t tlas_scratch_bytes(int64_t n, int32_t n_blas) {
+uint64_t tlas_scratch_bytes(int64_t n, int32_t n_blas, int32_t builder) {
     RgArena a{nullptr, 0, 0};
     a.take<float>(12 * n);      // matrices
     a.take<uint32_t>(n);        // blas ids
@@ -745,7 +1045,7 @@ uint64_t tlas_scratch_bytes(int64_t n, int32_t n_blas) {
     a.take<BlasInfo>(n_blas > 0 ? n_blas : 1);
     a.take<float>(6 * n);       // instance boxes
     a.take<RgInst>(n);          // unsorted records
-    return a.used + rg_lbvh_scratch_bytes(n);
+    return a.used + rg_lbvh_scratch_bytes(n, builder);
 }
 
 }  // namespace
@@ -778,24 +1078,25 @@ const char *rg_status_string(rg_status s) {
 }
 
 rg_status rg_blas_sizes(int64_t n_tris, const rg_build_opts *opts, rg_sizes *out) {
-    int32_t w, l;
-    if (!out || n_tris < 1 || n_tris > RG_MAX_TRIS || !opts_ok(opts, &w, &l)) return RG_ERR_INVALID_ARG;
+    Opts o;
+    if (!out || n_tris < 1 || n_tris > RG_MAX_TRIS || !opts_ok(opts, &o)) return RG_ERR_INVALID_ARG;
     uint64_t a, b, c, d;
-    out->bytes = blas_out_bytes(n_tris, w, &a, &b, &c, &d);
-    out->scratch_bytes = blas_scratch_bytes(n_tris);
+    out->bytes = blas_out_bytes(n_tris, o.w, &a, &b, &c, &d);
+    out->scratch_bytes = blas_scratch_bytes(n_tris, o.builder);
     return RG_OK;
 }
 
 rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx, int64_t n_tris,
                         const uint16_t *prim_material, const rg_build_opts *opts, void *out_buf,
                         uint64_t out_bytes, void *scratch, uint64_t scratch_bytes, void *stream, rg_blas *out) {
-    int32_t w, l;
+    Opts o;
     if (!verts || !idx || !out_buf || !scratch || !out) return RG_ERR_INVALID_ARG;
     if (n_verts < 1 || n_verts > (1ll << 32) || n_tris < 1 || n_tris > RG_MAX_TRIS) return RG_ERR_INVALID_ARG;
-    if (!opts_ok(opts, &w, &l)) return RG_ERR_INVALID_ARG;
+    if (!opts_ok(opts, &o)) return RG_ERR_INVALID_ARG;
+    const int32_t w = o.w, l = o.leaf;
     uint64_t no, to, mo, so;
     uint64_t need = blas_out_bytes(n_tris, w, &no, &to, &mo, &so);
-    if (out_bytes < need || scratch_bytes < blas_scratch_bytes(n_tris)) return RG_ERR_OUT_OF_MEMORY;
+    if (out_bytes < need || scratch_bytes < blas_scratch_bytes(n_tris, o.builder)) return RG_ERR_OUT_OF_MEMORY;
     hipStream_t st = (hipStream_t)stream;
     RgArena arena{(char *)scratch, scratch_bytes, 0};
     float *pbox = arena.take<float>(6 * n_tris);
@@ -809,8 +1110,8 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
     if (hflags) return RG_ERR_INVALID_ARG;
     char *base = (char *)out_buf;
     RgLbvhOut lo;
-    rg_status r = rg_lbvh_build(pbox, n_tris, w, l, base + no, arena, st, &lo, false, nullptr, nullptr, nullptr,
-                                nullptr);
+    rg_status r = rg_lbvh_build(pbox, n_tris, w, l, o.builder, o.radius, base + no, arena, st, &lo, false, nullptr,
+                                nullptr, nullptr, nullptr);
     if (r != RG_OK) return r;
     k_reorder_tris<<<rg_blocks(n_tris, kThreads), kThreads, 0, st>>>(
         verts, idx, lo.ids, n_tris, prim_material, (RgTri *)(base + to), (uint16_t *)(base + mo),
@@ -838,21 +1139,22 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
 }
 
 rg_status rg_tlas_sizes(int64_t n_inst, const rg_build_opts *opts, rg_sizes *out) {
-    int32_t w, l;
-    if (!out || n_inst < 1 || n_inst > RG_MAX_TRIS || !opts_ok(opts, &w, &l)) return RG_ERR_INVALID_ARG;
+    Opts o;
+    if (!out || n_inst < 1 || n_inst > RG_MAX_TRIS || !opts_ok(opts, &o)) return RG_ERR_INVALID_ARG;
     uint64_t a, b, c;
-    out->bytes = tlas_out_bytes(n_inst, w, &a, &b, &c);
-    out->scratch_bytes = tlas_scratch_bytes(n_inst, 4096);
+    out->bytes = tlas_out_bytes(n_inst, o.w, &a, &b, &c);
+    out->scratch_bytes = tlas_scratch_bytes(n_inst, 4096, o.builder);
     return RG_OK;
 }
 
 rg_status rg_build_tlas(const rg_blas *blas, int32_t n_blas, const float *xform, const uint32_t *blas_id,
                         const uint32_t *inst_material, int64_t n_inst, const rg_build_opts *opts, void *out_buf,
                         uint64_t out_bytes, void *scratch, uint64_t scratch_bytes, void *stream, rg_tlas *out) {
-    int32_t w, l;
+    Opts o;
     if (!blas || !xform || !blas_id || !inst_material || !out_buf || !scratch || !out) return RG_ERR_INVALID_ARG;
     if (n_blas < 1 || n_blas > 4096 || n_inst < 1 || n_inst > RG_MAX_TRIS) return RG_ERR_INVALID_ARG;
-    if (!opts_ok(opts, &w, &l)) return RG_ERR_INVALID_ARG;
+    if (!opts_ok(opts, &o)) return RG_ERR_INVALID_ARG;
+    const int32_t w = o.w;
     int32_t max_depth = 0;
     std::vector<BlasInfo> info((size_t)n_blas);
     for (int32_t b = 0; b < n_blas; ++b) {
@@ -877,7 +1179,8 @@ rg_status rg_build_tlas(const rg_blas *blas, int32_t n_blas, const float *xform,
     }
     uint64_t no, io, ro;
     uint64_t need = tlas_out_bytes(n_inst, w, &no, &io, &ro);
-    if (out_bytes < need || scratch_bytes < tlas_scratch_bytes(n_inst, n_blas)) return RG_ERR_OUT_OF_MEMORY;
+    if (out_bytes < need || scratch_bytes < tlas_scratch_bytes(n_inst, n_blas, o.builder))
+        return RG_ERR_OUT_OF_MEMORY;
     hipStream_t st = (hipStream_t)stream;
     RgArena arena{(char *)scratch, scratch_bytes, 0};
     float *d_xf = arena.take<float>(12 * n_inst);
@@ -894,8 +1197,8 @@ rg_status rg_build_tlas(const rg_blas *blas, int32_t n_blas, const float *xform,
     RG_LAUNCH_CHECK();
     char *base = (char *)out_buf;
     RgLbvhOut lo;
-    rg_status r = rg_lbvh_build(d_box, n_inst, w, 1, base + no, arena, st, &lo, false, nullptr, nullptr, nullptr,
-                                nullptr);
+    rg_status r = rg_lbvh_build(d_box, n_inst, w, 1, o.builder, o.radius, base + no, arena, st, &lo, false, nullptr,
+                                nullptr, nullptr, nullptr);
     if (r != RG_OK) return r;
     k_reorder_inst<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(d_rec, lo.ids, n_inst, (RgInst *)(base + io),
                                                                       (uint32_t *)(base + ro));
@@ -918,13 +1221,14 @@ rg_status rg_build_tlas(const rg_blas *blas, int32_t n_blas, const float *xform,
     return RG_OK;
 }
 
-rg_status rg_lbvh_stages(const float *verts, int64_t n_verts, const uint32_t *idx, int64_t n_tris, uint64_t *keys,
-                         uint32_t *ids, int32_t *left, int32_t *right, float *boxes, void *scratch,
-                         uint64_t scratch_bytes, void *stream) {
+rg_status rg_lbvh_stages(const float *verts, int64_t n_verts, const uint32_t *idx, int64_t n_tris,
+                         const rg_build_opts *opts, uint64_t *keys, uint32_t *ids, int32_t *left, int32_t *right,
+                         float *boxes, void *scratch, uint64_t scratch_bytes, void *stream) {
+    Opts o;
     if (!verts || !idx || !keys || !ids || !boxes || !scratch) return RG_ERR_INVALID_ARG;
     if (n_tris > 1 && (!left || !right)) return RG_ERR_INVALID_ARG;
-    if (n_verts < 1 || n_tris < 1 || n_tris > RG_MAX_TRIS) return RG_ERR_INVALID_ARG;
-    if (scratch_bytes < blas_scratch_bytes(n_tris)) return RG_ERR_OUT_OF_MEMORY;
+    if (n_verts < 1 || n_tris < 1 || n_tris > RG_MAX_TRIS || !opts_ok(opts, &o)) return RG_ERR_INVALID_ARG;
+    if (scratch_bytes < blas_scratch_bytes(n_tris, o.builder)) return RG_ERR_OUT_OF_MEMORY;
     hipStream_t st = (hipStream_t)stream;
     RgArena arena{(char *)scratch, scratch_bytes, 0};
     float *pbox = arena.take<float>(6 * n_tris);
@@ -937,7 +1241,8 @@ rg_status rg_lbvh_stages(const float *verts, int64_t n_verts, const uint32_t *id
     RG_HIP(hipStreamSynchronize(st));
     if (hflags) return RG_ERR_INVALID_ARG;
     RgLbvhOut lo;
-    rg_status r = rg_lbvh_build(pbox, n_tris, 4, 4, nullptr, arena, st, &lo, true, keys, left, right, boxes);
+    rg_status r = rg_lbvh_build(pbox, n_tris, o.w, o.leaf, o.builder, o.radius, nullptr, arena, st, &lo, true, keys,
+                                left, right, boxes);
     if (r != RG_OK) return r;
     RG_HIP(hipMemcpyAsync(ids, lo.ids, 4 * n_tris, hipMemcpyDeviceToDevice, st));
     RG_HIP(hipStreamSynchronize(st));

@@ -124,10 +124,11 @@ struct RgLbvhOut {
     int64_t n_nodes;
     float lo[3], hi[3];
 };
-rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t leaf_max, void *nodes,
-                        RgArena &scratch, hipStream_t stream, RgLbvhOut *out, bool keep_stages,
-                        uint64_t *keys_out, int32_t *left_out, int32_t *right_out, float *boxes_out);
-uint64_t rg_lbvh_scratch_bytes(int64_t n);
+rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t leaf_max, int32_t builder,
+                        int32_t radius, void *nodes, RgArena &scratch, hipStream_t stream, RgLbvhOut *out,
+                        bool keep_stages, uint64_t *keys_out, int32_t *left_out, int32_t *right_out,
+                        float *boxes_out);
+uint64_t rg_lbvh_scratch_bytes(int64_t n, int32_t builder);
 
 // In-place exclusive prefix sum of m uint32 values (one workgroup).
 rg_status rg_scan_excl_u32(uint32_t *data, int64_t m, hipStream_t stream);

@@ -52,6 +52,19 @@ def test_sizes_validation():
         rg.blas_sizes(10, leaf_max=9)
     # wider nodes are bigger
     assert rg.blas_sizes(10000, 8)[0] > rg.blas_sizes(10000, 2)[0]
+    # builders: clustering needs more scratch, the same output; radius 1..32
+    nb_p, ns_p = rg.blas_sizes(1000, builder="ploc")
+    assert nb_p == nb and ns_p > ns
+    for r in (1, 32):
+        rg.blas_sizes(10, builder="ploc", radius=r)
+    for r in (-1, 33):
+        with pytest.raises(rg.RgError):
+            rg.blas_sizes(10, builder="ploc", radius=r)
+    o = rg.BuildOpts(4, 4, 2, 0)
+    s = rg.Sizes()
+    assert rg._lib.rg_blas_sizes(10, rg.ctypes.byref(o), rg.ctypes.byref(s)) == -1
+    with pytest.raises(ValueError):
+        rg.blas_sizes(10, builder="sah")
 
 
 def test_render_sizes_validation():

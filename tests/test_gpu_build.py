@@ -52,6 +52,55 @@ def test_lbvh_stages_match_definitions(name):
         assert np.array_equal(boxes[n - 1:, :3], lo[ref_ids]) and np.array_equal(boxes[n - 1:, 3:], hi[ref_ids])
 
 
+@pytest.mark.parametrize("name,radius", [("soup5000", 16), ("soup5000", 1), ("small", 32), ("torus", 8),
+                                         ("two", 16), ("dupes", 4)])
+def test_clustering_stages_match_definition(name, radius):
+    """Locally-ordered clustering: the GPU's binary tree, inner boxes, leaf
+    order and triangle order equal the reference clustering bit for bit
+    (nearest neighbours, merge numbering and float32 areas included)."""
+    import paper_2001_09792_amd as rg
+    mesh = MESHES[name]()
+    print(f"[build ploc] {name}: {mesh.n_tris} tris r={radius}", flush=True)
+    v, i = _dev(mesh)
+    st = rg.lbvh_stages(v, i, builder="ploc", radius=radius)
+    n = mesh.n_tris
+    ref_sorted, ref_ids = br.sort_pairs(br.morton_keys(mesh.verts, mesh.idx))
+    assert np.array_equal(st["keys"].cpu().numpy().view(np.uint64), ref_sorted)
+    lo, hi = br.tri_boxes(mesh.verts, mesh.idx)
+    lo_s, hi_s = lo[ref_ids], hi[ref_ids]
+    left, right, blo, bhi, its = br.ploc(lo_s, hi_s, radius)
+    rank = br.leaf_order(left, right, n)
+    relabel = lambda c: np.where(c < 0, -(rank[np.maximum(-c - 1, 0)] + 1), c)
+    ids = np.empty(n, np.uint32)
+    ids[rank] = ref_ids
+    assert np.array_equal(st["ids"].cpu().numpy().view(np.uint32), ids), "leaf order"
+    boxes = st["boxes"].cpu().numpy()
+    if n > 1:
+        assert np.array_equal(st["left"].cpu().numpy(), relabel(left).astype(np.int32))
+        assert np.array_equal(st["right"].cpu().numpy(), relabel(right).astype(np.int32))
+        assert np.array_equal(boxes[: n - 1, :3], blo) and np.array_equal(boxes[: n - 1, 3:], bhi)
+    leaf_lo = np.empty_like(lo_s)
+    leaf_hi = np.empty_like(hi_s)
+    leaf_lo[rank], leaf_hi[rank] = lo_s, hi_s
+    assert np.array_equal(boxes[n - 1:, :3], leaf_lo) and np.array_equal(boxes[n - 1:, 3:], leaf_hi)
+
+
+@pytest.mark.parametrize("width,leaf_max", [(2, 1), (4, 1), (4, 4), (8, 3), (8, 8)])
+def test_clustered_blas_and_tlas_invariants(width, leaf_max):
+    import paper_2001_09792_amd as rg
+    mesh = sg.random_soup(3000, 33)
+    print(f"[blas ploc] W={width} L={leaf_max}", flush=True)
+    v, i = _dev(mesh)
+    b = rg.build_blas(v, i, None, width, leaf_max, builder="ploc")
+    info = bvh_check.check_blas(b.buf.cpu().numpy(), b.desc)
+    assert np.array_equal(info["verts"], mesh.verts[mesh.idx[info["prim"]]])
+    sc = sg.config_two_level(width=64, height=36)
+    tl = rg.upload_scene(sc, width, leaf_max, builder="ploc")
+    bvh_check.check_tlas(tl.buf.cpu().numpy(), tl.desc, [b.desc for b in tl.blas], sc.xform)
+    for bb in tl.blas:
+        bvh_check.check_blas(bb.buf.cpu().numpy(), bb.desc)
+
+
 @pytest.mark.parametrize("width", [2, 4, 8])
 @pytest.mark.parametrize("leaf_max", [1, 3, 8])
 def test_wide_blas_invariants(width, leaf_max):
@@ -94,10 +143,11 @@ def test_single_triangle_and_single_instance():
     mesh = sg.triangles_mesh([[(0, 0, 0), (1, 0, 0), (0, 1, 0)]])
     v, i = _dev(mesh)
     for w in (2, 4, 8):
-        b = rg.build_blas(v, i, None, w, 4)
-        bvh_check.check_blas(b.buf.cpu().numpy(), b.desc)
-        tl = rg.build_tlas([b], sg.identity_xform(1), [0], [0], w)
-        bvh_check.check_tlas(tl.buf.cpu().numpy(), tl.desc, [b.desc], sg.identity_xform(1))
+        for builder in ("lbvh", "ploc"):
+            b = rg.build_blas(v, i, None, w, 4, builder=builder)
+            bvh_check.check_blas(b.buf.cpu().numpy(), b.desc)
+            tl = rg.build_tlas([b], sg.identity_xform(1), [0], [0], w, builder=builder)
+            bvh_check.check_tlas(tl.buf.cpu().numpy(), tl.desc, [b.desc], sg.identity_xform(1))
 
 
 def test_bad_inputs_are_rejected():

@@ -18,9 +18,9 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "triangle_hand_cases.json")
 
 
-def _upload(scene, width=4, leaf=4):
+def _upload(scene, width=4, leaf=4, builder="lbvh"):
     import paper_2001_09792_amd as rg
-    tl = rg.upload_scene(scene, width, leaf)
+    tl = rg.upload_scene(scene, width, leaf, builder=builder)
     for b in tl.blas:
         bvh_check.check_blas(b.buf.cpu().numpy(), b.desc)
     bvh_check.check_tlas(tl.buf.cpu().numpy(), tl.desc, [b.desc for b in tl.blas], scene.xform)
@@ -35,9 +35,9 @@ def _trace(tl, rays_np):
     return h, occ
 
 
-def _both(scene, rays_np, label, max_amb=0.02, width=4, leaf=4, sphere=False):
-    print(f"[trace] {label}: {rays_np.shape[0]} rays W={width} L={leaf}", flush=True)
-    tl = _upload(scene, width, leaf)
+def _both(scene, rays_np, label, max_amb=0.02, width=4, leaf=4, sphere=False, builder="lbvh"):
+    print(f"[trace] {label}: {rays_np.shape[0]} rays W={width} L={leaf} {builder}", flush=True)
+    tl = _upload(scene, width, leaf, builder)
     h, occ = _trace(tl, rays_np)
     orc = oracle.Scene(scene, sphere_reject=sphere)
     oc = orc.trace(rays_np)
@@ -97,6 +97,23 @@ def test_widths_and_leaf_sizes(width, leaf):
     mesh = sg.random_soup(3000, 51, extent=1.0, size=0.1)
     sc = scene_from_meshes([mesh])
     _both(sc, _soup_rays(mesh, 6000, 52), f"soup W{width} L{leaf}", width=width, leaf=leaf)
+
+
+@pytest.mark.parametrize("width,leaf", [(2, 1), (4, 1), (4, 4), (8, 2)])
+def test_clustered_hierarchy_parity(width, leaf):
+    """Hierarchies from locally-ordered clustering trace to the same hits."""
+    mesh = sg.random_soup(3000, 53, extent=1.0, size=0.1)
+    sc = scene_from_meshes([mesh])
+    _both(sc, _soup_rays(mesh, 6000, 54), f"soup ploc W{width} L{leaf}", width=width, leaf=leaf, builder="ploc")
+
+
+def test_clustered_two_level_parity():
+    import paper_2001_09792_amd as rg
+    sc = sg.config_two_level(width=192, height=108)
+    r = rg.camera_rays(sc.camera, 192, 108).cpu().numpy().T.copy()
+    sel = sg.sample_pixels(192, 108, 3000, 17)
+    rays = np.concatenate([r[sel], sg.random_rays(3000, 18, extent=22.0)])
+    _both(sc, rays, "two-level ploc", sphere=True, builder="ploc")
 
 
 def test_instanced_soup_parity():
