@@ -14,6 +14,10 @@ FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep float arithmetic scalar: packed fp32 forms are not used
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # wave-uniform branches stay plain scalar branches: structurizing them as
+    # if they were divergent makes the values they select between meet in
+    # joins that cost a register copy per value
+    "-mllvm", "-structurizecfg-skip-uniform-regions=true",
     "-Wno-unused-command-line-argument",
 ]
 
