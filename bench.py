@@ -68,6 +68,15 @@ def recorded_traffic(args):
     return float(rec["read_bytes"]) + float(rec["write_bytes"])
 
 
+# Hierarchy shape per workload (node width, leaf size, builder), the best
+# measured on MI355X: the incoherent AO rays and the serving mix (dominated by
+# the regular torus meshes) run fastest on width-4 linear BVHs; whole
+# two-level frames on width-8 clustered hierarchies (about 5% faster).  The
+# batched workload starts from its entry and can be autotuned.
+SHAPES = {"incoherent": (4, 1, "lbvh"), "two_level": (8, 1, "ploc"), "batched": (4, 1, "lbvh"),
+          "serving": (4, 1, "lbvh")}
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -274,7 +283,8 @@ def bench_two_level(args, torch, rg, sg):
         "config": {"workload": "two-level: 64 instances of 3 meshes (184,320 unique tris), 1920x1080, "
                                "Whitted depth 4, whole frames",
                    "rays_per_frame": rays, "closest_rays": st["rays_traced"], "shadow_rays": st["shadow_rays"],
-                   "trace_tuning": rg.trace_tuning(scope="frame")},
+                   "trace_tuning": rg.trace_tuning(scope="frame"), "bvh_width": args.width,
+                   "leaf_max": args.leaf, "builder": args.builder},
         "roofline": None,
     }
     return out, scene
@@ -287,15 +297,15 @@ def bench_batched(args, torch, rg, sg):
     scenes = sg.config_batched(n_scenes=args.scenes)
     log(f"{len(scenes)} scenes, {sum(s.unique_tris() for s in scenes)} unique tris, "
         f"{sum(s.width * s.height for s in scenes)} pixels ({time.perf_counter() - t0:.0f}s to generate)")
-    def build(sel, width, leaf):
+    def build(sel, width, leaf, builder):
         out = []
         for sc in sel:
-            tl = rg.upload_scene(sc, width=width, leaf_max=leaf, builder=args.builder)
+            tl = rg.upload_scene(sc, width=width, leaf_max=leaf, builder=builder)
             out.append((tl, sc.materials, sc.camera, sc.light, sc.width, sc.height, sc.max_depth))
         torch.cuda.synchronize()
         return out
 
-    frames = build(scenes, args.width, args.leaf)
+    frames = build(scenes, args.width, args.leaf, args.builder)
     default_launch = rg.trace_tuning(scope="frame")
     tuned = None
     if args.autotune:
@@ -304,7 +314,7 @@ def bench_batched(args, torch, rg, sg):
         built = {}
 
         def measure(cfg):
-            key = (cfg["width"], cfg["leaf"])
+            key = (cfg["width"], cfg["leaf"], cfg["builder"])
             if key not in built:
                 built[key] = build(sub, *key)
             autotune.apply_launch(cfg, "frame")
@@ -317,7 +327,7 @@ def bench_batched(args, torch, rg, sg):
             torch.cuda.synchronize()
             return (st["rays_traced"] + st["shadow_rays"]) * 3 / (time.perf_counter() - t) / 1e6
 
-        start = dict(autotune.DEFAULT, width=args.width, leaf=args.leaf, **default_launch)
+        start = dict(autotune.DEFAULT, builder=args.builder, width=args.width, leaf=args.leaf, **default_launch)
         tuned = autotune.tuned("batch", sum(s.width * s.height for s in scenes),
                                sum(s.unique_tris() for s in scenes), measure, log=log, start=start)
         log(f"autotuned: {tuned}")
@@ -334,8 +344,8 @@ def bench_batched(args, torch, rg, sg):
 
     if tuned is not None:
         cfg = tuned["config"]
-        bframes = frames if (cfg["width"], cfg["leaf"]) == (args.width, args.leaf) else build(
-            scenes, cfg["width"], cfg["leaf"])
+        shape = (cfg["width"], cfg["leaf"], cfg.get("builder", "lbvh"))
+        bframes = frames if shape == (args.width, args.leaf, args.builder) else build(scenes, *shape)
     else:
         bframes = frames
     batch = rg.Batch(bframes)
@@ -390,6 +400,7 @@ def bench_batched(args, torch, rg, sg):
         "graph_ms": ms_graph, "graph_wall_ms": wall_graph,
         "speedup": ms_plain / ms_batch, "images_identical": bool(same), "tuned_max_abs_diff": max_diff,
         "autotuned": tuned, "plain_launch": default_launch, "batched_launch": batched_launch,
+        "plain_shape": {"bvh_width": args.width, "leaf_max": args.leaf, "builder": args.builder},
         "roofline": None,
     }
     return out, scenes
@@ -488,6 +499,7 @@ def bench_serving(args, torch, rg, sg):
         "config": {"workload": "serving: 64 resident scenes (32 two-level, 32 over 16 shared tori of "
                                f"{args.segments}^2), requests of 256^2..1920x1080, Whitted depth 1..4, "
                                "continuous batching", "budget_gb": args.budget_gb, "engine": ecfg,
+                   "bvh_width": args.width, "leaf_max": args.leaf, "builder": args.builder,
                    "requests_per_point": args.requests, "warm_requests": args.warm,
                    "engine_launch": rg.trace_tuning(scope="engine"), "plain_launch": rg.trace_tuning(scope="frame")},
         "saturated": {"engine": s_eng, "plain": s_plain, "speedup": s_eng["mrays_s"] / s_plain["mrays_s"]},
@@ -512,14 +524,14 @@ def main():
     ap.add_argument("--segments", type=int, default=560)
     ap.add_argument("--requests", type=int, default=1000, help="serving: measured requests per rate")
     ap.add_argument("--warm", type=int, default=100, help="serving: warm-up requests per rate")
-    ap.add_argument("--budget-gb", type=float, default=16.0, help="serving: engine memory budget")
-    ap.add_argument("--max-jobs", type=int, default=64, help="serving: frames in flight")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: engine memory budget")
+    ap.add_argument("--max-jobs", type=int, default=128, help="serving: frames in flight")
     ap.add_argument("--rate-factors", type=float, nargs="+", default=[0.25, 0.5, 0.75, 0.9, 1.0, 1.25])
     ap.add_argument("--plain-factors", type=float, nargs="*", default=[0.5, 0.9])
-    ap.add_argument("--width", type=int, default=4)
-    ap.add_argument("--leaf", type=int, default=1)
-    ap.add_argument("--builder", choices=["lbvh", "ploc"], default="lbvh",
-                    help="hierarchy builder: linear BVH or locally-ordered clustering")
+    ap.add_argument("--width", type=int, default=None, help="node width (default: the workload's, see SHAPES)")
+    ap.add_argument("--leaf", type=int, default=None, help="most triangles per leaf (default: the workload's)")
+    ap.add_argument("--builder", choices=["lbvh", "ploc"], default=None,
+                    help="hierarchy builder: linear BVH or locally-ordered clustering (default: the workload's)")
     ap.add_argument("--refill", type=int, default=None, help="traversal refill threshold (lanes)")
     ap.add_argument("--waves-per-cu", type=int, default=None, help="persistent traversal waves per CU")
     ap.add_argument("--lds-depth", type=int, default=None, help="traversal stack entries per lane in LDS")
@@ -532,6 +544,10 @@ def main():
                     help="after the measurement, copy this many MiB once (a plain copy kernel of known "
                          "size, for scaling hardware byte counters)")
     args = ap.parse_args()
+    width, leaf, builder = SHAPES[args.workload]
+    args.width = width if args.width is None else args.width
+    args.leaf = leaf if args.leaf is None else args.leaf
+    args.builder = builder if args.builder is None else args.builder
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the path runs on a single device (see the multi-GPU design "
               "notes); run with --gpus 1", file=sys.stderr)

@@ -1,12 +1,13 @@
-"""Autotuner for the traversal: node width, leaf size, LDS stack depth, refill
-threshold and resident waves per CU, chosen by measurement.
+"""Autotuner for the traversal: hierarchy builder, node width, leaf size, LDS
+stack depth, refill threshold, resident waves per CU and leaf / instance
+batching, chosen by measurement.
 
 The best setting depends on the workload's size (rays per launch, triangles,
 coherence), so results are cached per GPU architecture, workload kind and
 size bucket in a JSON file ($RG_TUNE_CACHE, default
 ~/.cache/raygun_mi/tune.json).  The search is a coordinate descent: starting
 from the defaults, each parameter in turn takes the value that measured best
-with the others held, for `passes` rounds.  Width and leaf size are
+with the others held, for `passes` rounds.  Builder, width and leaf size are
 build-time choices: the caller's `measure` rebuilds when they change.
 """
 from __future__ import annotations
@@ -17,8 +18,10 @@ import os
 import time
 from typing import Callable, Dict, Optional
 
-DEFAULT = dict(width=4, leaf=1, refill=8, waves_per_cu=16, lds_depth=16, leaf_batch=12, inst_batch=6)
-SPACE = dict(width=(2, 4, 8), leaf=(1, 2, 4), lds_depth=(8, 16, 24), refill=(4, 8, 16, 32),
+DEFAULT = dict(builder="lbvh", width=4, leaf=1, refill=8, waves_per_cu=16, lds_depth=16, leaf_batch=12,
+               inst_batch=6)
+BUILD_KEYS = ("builder", "width", "leaf")
+SPACE = dict(builder=("lbvh", "ploc"), width=(2, 4, 8), leaf=(1, 2, 4), lds_depth=(8, 16, 24), refill=(4, 8, 16, 32),
              waves_per_cu=(12, 16, 24), leaf_batch=(1, 8, 12, 16, 24), inst_batch=(1, 4, 6, 8, 12))
 LAUNCH_KEYS = ("refill", "waves_per_cu", "lds_depth", "leaf_batch", "inst_batch")
 

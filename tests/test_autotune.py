@@ -10,7 +10,8 @@ def test_bucket():
 
 
 def test_search_finds_separable_optimum():
-    target = dict(width=8, leaf=1, lds_depth=24, refill=16, waves_per_cu=12, leaf_batch=16, inst_batch=8)
+    target = dict(builder="ploc", width=8, leaf=1, lds_depth=24, refill=16, waves_per_cu=12, leaf_batch=16,
+                  inst_batch=8)
 
     def measure(c):
         return 100.0 - sum(abs(at.SPACE[k].index(c[k]) - at.SPACE[k].index(target[k])) for k in c)
