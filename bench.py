@@ -38,8 +38,9 @@ TRI_BYTES, INST_BYTES, RAY_BYTES, HIT_BYTES = 40, 112, 32, 20
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ao_closest.json")
+# what the traversal kernel is compiled from (sources and compiler flags)
 KERNEL_SOURCES = ["paper_2001_09792_amd/csrc/trace_core.h", "paper_2001_09792_amd/csrc/trace.hip",
-                  "paper_2001_09792_amd/csrc/rg_internal.h"]
+                  "paper_2001_09792_amd/csrc/rg_internal.h", "paper_2001_09792_amd/_build.py"]
 
 
 def kernel_hash() -> str:
