@@ -104,11 +104,13 @@ typedef struct {
  *              float v0[3], v1[3], v2[3]; uint32 prim (index in the input).
  *   mats_off:  uint16 material per triangle in leaf order (0 if none given).
  *   slots_off: uint32 per input triangle: its position in leaf order.
+ *   parents_off: uint32 per node: (parent node << 3) | the parent's child
+ *              slot holding it; RG_MISS for the root (used by rg_refit_blas).
  * The build reads the vertex and index arrays only during the call; the
  * descriptor refers to `buf`, which must outlive every top level using it. */
 typedef struct {
     void *buf;
-    uint64_t nodes_off, tris_off, mats_off, slots_off;
+    uint64_t nodes_off, tris_off, mats_off, slots_off, parents_off;
     int64_t n_tris, n_nodes;
     int32_t width, leaf_max, depth, has_mats;
     float lo[3], hi[3]; /* root box (object space) */
@@ -191,6 +193,28 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
                         const uint16_t *prim_material, const rg_build_opts *opts,
                         void *out_buf, uint64_t out_bytes, void *scratch, uint64_t scratch_bytes,
                         void *stream, rg_blas *out /*host*/);
+
+/* Scratch for rg_refit_blas on `blas` (host call, no GPU work). */
+rg_status rg_refit_sizes(const rg_blas *blas /*host*/, uint64_t *scratch_bytes /*host*/);
+
+/* Refits a bottom level built by rg_build_blas to new positions of the same
+ * triangles (dynamic scenes: the per-frame update of moving geometry, the
+ * step before tracing that the paper's scene graph and physics drive): idx
+ * must be the index array of the build (n_tris equal), verts the new
+ * float[n_verts][3].  The triangles in leaf order are rewritten and every
+ * node box is recomputed bottom-up (min / max, exact: unchanged vertices
+ * reproduce the build bit for bit); the hierarchy itself is kept, so its
+ * quality degrades as triangles move far from where they were built.
+ * Updates blas->lo / hi (the root box); top levels over this bottom level
+ * carry its root box and must be rebuilt (rg_build_tlas) before tracing.
+ * scratch: rg_refit_sizes bytes.  Synchronous.
+ * Errors: RG_ERR_INVALID_ARG for NULL pointers, another n_tris, and (after
+ * the sync) an index >= n_verts or a non-finite vertex, in which case the
+ * bottom level's contents are undefined until it is refitted with valid
+ * data or rebuilt; RG_ERR_OUT_OF_MEMORY for a short scratch buffer. */
+rg_status rg_refit_blas(rg_blas *blas /*host, in/out*/, const float *verts, int64_t n_verts,
+                        const uint32_t *idx, int64_t n_tris, void *scratch, uint64_t scratch_bytes,
+                        void *stream);
 
 /* --------------------------------------------------------- top level */
 rg_status rg_tlas_sizes(int64_t n_inst, const rg_build_opts *opts, rg_sizes *out /*host*/);

@@ -44,7 +44,7 @@ class Sizes(ctypes.Structure):
 
 class BlasDesc(ctypes.Structure):
     _fields_ = [("buf", c_p), ("nodes_off", c_u64), ("tris_off", c_u64), ("mats_off", c_u64),
-                ("slots_off", c_u64), ("n_tris", c_i64), ("n_nodes", c_i64), ("width", c_i32),
+                ("slots_off", c_u64), ("parents_off", c_u64), ("n_tris", c_i64), ("n_nodes", c_i64), ("width", c_i32),
                 ("leaf_max", c_i32), ("depth", c_i32), ("has_mats", c_i32), ("lo", c_f * 3),
                 ("hi", c_f * 3)]
 
@@ -130,6 +130,8 @@ SIGNATURES = {
     "rg_render_sizes": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_p]),
     "rg_render": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_u64, c_p, c_p, c_u64,
                           c_p, c_p]),
+    "rg_refit_sizes": (c_i32, [c_p, c_p]),
+    "rg_refit_blas": (c_i32, [c_p, c_p, c_i64, c_p, c_i64, c_p, c_u64, c_p]),
     "rg_lbvh_stages": (c_i32, [c_p, c_i64, c_p, c_i64, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_u64, c_p]),
     "rg_batch_sizes": (c_i32, [c_p, c_i32, c_p]),
     "rg_batch_prepare": (c_i32, [c_p, c_i32, c_p, c_u64, c_p, c_p]),
@@ -159,7 +161,7 @@ class RgError(RuntimeError):
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
-        raise ImportError(f"{path} is missing: build it with `python -m paper_2001_09792_amd._build` "
+        raise ImportError(f"{path} is missing: build it with `python paper_2001_09792_amd/_build.py` "
                           "(there is no fallback implementation)")
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
@@ -256,6 +258,20 @@ def build_blas(verts, idx, prim_mat=None, width: int = 4, leaf_max: int = 4, scr
         _ptr(verts), int(verts.shape[0]), _ptr(idx), n_tris, _ptr(prim_mat), ctypes.byref(o),
         _ptr(buf), buf.numel(), _ptr(scratch), scratch.numel(), _stream(stream), ctypes.byref(d)))
     return Blas(buf, d)
+
+
+def refit_blas(blas: Blas, verts, idx, scratch=None, stream=None) -> Blas:
+    """Refits `blas` in place to new vertex positions of the same triangles
+    (verts: CUDA float32 [V,3]; idx: the index array it was built from).
+    Top levels over it must be rebuilt afterwards (build_tlas)."""
+    need = ctypes.c_uint64()
+    _check("rg_refit_sizes", _lib.rg_refit_sizes(ctypes.byref(blas.desc), ctypes.byref(need)))
+    if scratch is None or scratch.numel() < need.value:
+        scratch = _bytes(need.value, verts.device)
+    _check("rg_refit_blas", _lib.rg_refit_blas(
+        ctypes.byref(blas.desc), _ptr(verts), int(verts.shape[0]), _ptr(idx), int(idx.shape[0]),
+        _ptr(scratch), scratch.numel(), _stream(stream)))
+    return blas
 
 
 # ----------------------------------------------------------------- top level

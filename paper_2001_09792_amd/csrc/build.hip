@@ -331,7 +331,8 @@ __global__ void k_collapse(const int32_t *__restrict__ left, const int32_t *__re
                            const float *__restrict__ int_box, const float *__restrict__ leaf_box,
                            int leaf_max, const uint2 *__restrict__ q_in, const uint32_t *__restrict__ q_in_count,
                            uint2 *__restrict__ q_out, uint32_t *q_out_count, uint32_t *node_count,
-                           RgNode<W> *__restrict__ nodes, uint32_t cap, uint32_t *err) {
+                           RgNode<W> *__restrict__ nodes, uint32_t *__restrict__ parents, uint32_t cap,
+                           uint32_t *err) {
     uint32_t cnt = *q_in_count;
     if (cnt > cap) cnt = cap;
     for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < cnt; qi += gridDim.x * blockDim.x) {
@@ -385,6 +386,7 @@ __global__ void k_collapse(const int32_t *__restrict__ left, const int32_t *__re
                     uint32_t slot = atomicAdd(q_out_count, 1u);
                     if (nn < cap && slot < cap) {  // a BVH2 has n-1 inner nodes: never exceeded
                         q_out[slot] = make_uint2(nn, (uint32_t)c);
+                        if (parents) parents[nn] = (item.x << 3) | (uint32_t)k;
                         link = nn;
                     } else {
                         atomicOr(err, 4u);
@@ -418,10 +420,11 @@ __global__ void k_single_root(const float *__restrict__ leaf_box, RgNode<W> *nod
     nd->pad[k] = 0u;
 }
 
-__global__ void k_collapse_init(uint2 *q, uint32_t *q_count, uint32_t *node_count) {
+__global__ void k_collapse_init(uint2 *q, uint32_t *q_count, uint32_t *node_count, uint32_t *parents) {
     q[0] = make_uint2(0u, 0u);
     *q_count = 1u;
     *node_count = 1u;
+    if (parents) parents[0] = RG_MISS;  // the root
 }
 
 // ------------------------------------ 5'. locally-ordered clustering
@@ -674,6 +677,125 @@ __global__ void k_blas_header(RgBlasHdr *h, uint64_t nodes, uint64_t tris, uint6
     h->slots = slots;
 }
 
+// --------------------------------------------------------------- refit
+// A built bottom level over new positions of the same triangles keeps its
+// hierarchy: the leaf-order triangle copies are rewritten, then every box
+// is recomputed bottom-up.  Boxes are min / max of vertex coordinates, which
+// are exact, so refitting to unchanged vertices reproduces the build bit for
+// bit.  flags as for k_tri_boxes.
+__global__ void k_refit_tris(const float *__restrict__ verts, int64_t n_verts, const uint32_t *__restrict__ idx,
+                             int64_t n, RgTri *__restrict__ tris, uint32_t *__restrict__ flags) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const uint32_t prim = tris[s].prim;
+    uint32_t bad = 0;
+    uint32_t v3[3] = {0u, 0u, 0u};
+    if ((int64_t)prim >= n) {
+        bad |= 1u;
+    } else {
+        v3[0] = idx[3 * (int64_t)prim];
+        v3[1] = idx[3 * (int64_t)prim + 1];
+        v3[2] = idx[3 * (int64_t)prim + 2];
+        if ((int64_t)v3[0] >= n_verts || (int64_t)v3[1] >= n_verts || (int64_t)v3[2] >= n_verts) {
+            bad |= 1u;
+            v3[0] = v3[1] = v3[2] = 0u;
+        }
+    }
+    float v[9];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v[3 * j + k] = verts[3 * (int64_t)v3[j] + k];
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+        if (!isfinite(v[k])) bad |= 2u;
+    if (bad) {
+        atomicOr(flags, bad);
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) tris[s].v[k] = v[k];
+}
+
+// The boxes of each node's leaf children (their triangles' boxes) and the
+// number of inner children the node waits for before its own box is known.
+template <int W>
+__global__ void k_refit_leaves(RgNode<W> *__restrict__ nodes, int64_t n_nodes, const RgTri *__restrict__ tris,
+                               uint32_t *__restrict__ need, uint32_t *__restrict__ arrived) {
+    const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (x >= n_nodes) return;
+    RgNode<W> &nd = nodes[x];
+    uint32_t inner = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const uint32_t c = nd.child[k];
+        if (c == RG_EMPTY) continue;
+        if (!rg_is_leaf(c)) {
+            ++inner;
+            continue;
+        }
+        const uint32_t first = rg_leaf_first(c), cnt = rg_leaf_count(c);
+        float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+        for (uint32_t j = 0; j < cnt; ++j) {
+            const RgTri &t = tris[first + j];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                b[a] = fminf(b[a], fminf(fminf(t.v[a], t.v[3 + a]), t.v[6 + a]));
+                b[3 + a] = fmaxf(b[3 + a], fmaxf(fmaxf(t.v[a], t.v[3 + a]), t.v[6 + a]));
+            }
+        }
+        nd.lo_x[k] = b[0]; nd.lo_y[k] = b[1]; nd.lo_z[k] = b[2];
+        nd.hi_x[k] = b[3]; nd.hi_y[k] = b[4]; nd.hi_z[k] = b[5];
+    }
+    need[x] = inner;
+    arrived[x] = 0u;
+}
+
+// Bottom-up from the nodes without inner children: a node whose children are
+// all final writes the union of its child boxes into its parent's slot; the
+// last child to arrive at a parent continues with the parent (arrival
+// counters with acquire / release at agent scope, as in k_refit).  The
+// root's box goes to root_box.
+template <int W>
+__global__ void k_refit_up(RgNode<W> *nodes, int64_t n_nodes, const uint32_t *__restrict__ parents,
+                           const uint32_t *__restrict__ need, uint32_t *arrived, float *__restrict__ root_box) {
+    const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (x >= n_nodes || need[x] != 0u) return;
+    uint32_t node = (uint32_t)x;
+    for (int64_t guard = 0; guard <= n_nodes; ++guard) {
+        const RgNode<W> &nd = nodes[node];
+        float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            if (nd.child[k] == RG_EMPTY) continue;
+            b[0] = fminf(b[0], nd.lo_x[k]); b[1] = fminf(b[1], nd.lo_y[k]); b[2] = fminf(b[2], nd.lo_z[k]);
+            b[3] = fmaxf(b[3], nd.hi_x[k]); b[4] = fmaxf(b[4], nd.hi_y[k]); b[5] = fmaxf(b[5], nd.hi_z[k]);
+        }
+        const uint32_t p = parents[node];
+        if (p == RG_MISS) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) root_box[k] = b[k];
+            return;
+        }
+        const uint32_t pn = p >> 3, ps = p & 7u;
+        if ((int64_t)pn >= n_nodes || ps >= (uint32_t)W) return;  // never for a structure this library built
+        RgNode<W> &pd = nodes[pn];
+        pd.lo_x[ps] = b[0]; pd.lo_y[ps] = b[1]; pd.lo_z[ps] = b[2];
+        pd.hi_x[ps] = b[3]; pd.hi_y[ps] = b[4]; pd.hi_z[ps] = b[5];
+        const uint32_t old = __hip_atomic_fetch_add(&arrived[pn], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old + 1u < need[pn]) return;  // a sibling subtree is still being refitted
+        node = pn;
+    }
+}
+
+template <int W>
+void refit_launch(void *nodes, int64_t n_nodes, const uint32_t *parents, const RgTri *tris, uint32_t *need,
+                  uint32_t *arrived, float *root_box, hipStream_t st) {
+    RgNode<W> *nd = reinterpret_cast<RgNode<W> *>(nodes);
+    k_refit_leaves<W><<<rg_blocks(n_nodes, kThreads), kThreads, 0, st>>>(nd, n_nodes, tris, need, arrived);
+    k_refit_up<W><<<rg_blocks(n_nodes, kThreads), kThreads, 0, st>>>(nd, n_nodes, parents, need, arrived, root_box);
+}
+
 // ----------------------------------------------------------- top level
 struct BlasInfo {
     float lo[3], hi[3];
@@ -868,11 +990,12 @@ rg_status ploc_build(const float *prim_box, int64_t n, int radius, const uint32_
 }
 
 template <int W>
-rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes_v, hipStream_t st,
+rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes_v, uint32_t *parents, hipStream_t st,
                    int32_t *depth, int64_t *n_nodes) {
     RgNode<W> *nodes = reinterpret_cast<RgNode<W> *>(nodes_v);
     if (n == 1) {
         k_single_root<W><<<1, 64, 0, st>>>(s.leaf_box, nodes);
+        if (parents) k_fill_u32<<<1, 64, 0, st>>>(parents, RG_MISS, 1);
         RG_LAUNCH_CHECK();
         *depth = 1;
         *n_nodes = 1;
@@ -881,7 +1004,7 @@ rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes_v,
     uint32_t *qc = s.qcount;  // [0], [1] queue counts, [2] node count, [3] error flags
     const uint32_t cap = (uint32_t)(n - 1);
     k_fill_u32<<<1, 64, 0, st>>>(qc, 0u, 4);
-    k_collapse_init<<<1, 1, 0, st>>>(s.q0, qc, qc + 2);
+    k_collapse_init<<<1, 1, 0, st>>>(s.q0, qc, qc + 2, parents);
     RG_LAUNCH_CHECK();
     uint2 *qin = s.q0, *qout = s.q1;
     uint32_t *cin = qc, *cout = qc + 1;
@@ -893,7 +1016,8 @@ rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes_v,
         unsigned blocks = rg_blocks(count, kThreads);
         if (blocks > 4096) blocks = 4096;
         k_collapse<W><<<blocks, kThreads, 0, st>>>(s.left, s.right, s.first, s.last, s.int_box, s.leaf_box,
-                                                    leaf_max, qin, cin, qout, cout, qc + 2, nodes, cap, qc + 3);
+                                                    leaf_max, qin, cin, qout, cout, qc + 2, nodes, parents, cap,
+                                                    qc + 3);
         RG_LAUNCH_CHECK();
         uint32_t hq[4];
         RG_HIP(hipMemcpyAsync(hq, qc, 16, hipMemcpyDeviceToHost, st));
@@ -926,9 +1050,9 @@ uint64_t rg_lbvh_scratch_bytes(int64_t n, int32_t builder) {
 }
 
 rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t leaf_max, int32_t builder,
-                        int32_t radius, void *nodes, RgArena &arena, hipStream_t st, RgLbvhOut *out,
-                        bool keep_stages, uint64_t *keys_out, int32_t *left_out, int32_t *right_out,
-                        float *boxes_out) {
+                        int32_t radius, void *nodes, uint32_t *parents, RgArena &arena, hipStream_t st,
+                        RgLbvhOut *out, bool keep_stages, uint64_t *keys_out, int32_t *left_out,
+                        int32_t *right_out, float *boxes_out) {
     LbvhScratch s;
     if (!carve(arena, n, builder, s)) return RG_ERR_OUT_OF_MEMORY;
     int nblocks = (int)((n + kSortTile - 1) / kSortTile);
@@ -979,9 +1103,9 @@ rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t
     out->ids = ia;
     rg_status r = RG_OK;
     if (nodes) {
-        if (width == 2) r = collapse<2>(s, n, leaf_max, nodes, st, &out->depth, &out->n_nodes);
-        else if (width == 4) r = collapse<4>(s, n, leaf_max, nodes, st, &out->depth, &out->n_nodes);
-        else r = collapse<8>(s, n, leaf_max, nodes, st, &out->depth, &out->n_nodes);
+        if (width == 2) r = collapse<2>(s, n, leaf_max, nodes, parents, st, &out->depth, &out->n_nodes);
+        else if (width == 4) r = collapse<4>(s, n, leaf_max, nodes, parents, st, &out->depth, &out->n_nodes);
+        else r = collapse<8>(s, n, leaf_max, nodes, parents, st, &out->depth, &out->n_nodes);
         if (r != RG_OK) return r;
     }
     float rb[6];
@@ -1004,7 +1128,7 @@ rg_status rg_scan_excl_u32(uint32_t *data, int64_t m, hipStream_t st) {
 namespace {
 
 uint64_t blas_out_bytes(int64_t n, int w, uint64_t *nodes_off, uint64_t *tris_off, uint64_t *mats_off,
-                        uint64_t *slots_off) {
+                        uint64_t *slots_off, uint64_t *parents_off) {
     int64_t max_nodes = n > 1 ? n - 1 : 1;
     uint64_t off = 256;  // header
     *nodes_off = off;
@@ -1015,6 +1139,8 @@ uint64_t blas_out_bytes(int64_t n, int w, uint64_t *nodes_off, uint64_t *tris_of
     off = align256(off + (uint64_t)n * 2u);
     *slots_off = off;
     off = align256(off + (uint64_t)n * 4u);
+    *parents_off = off;
+    off = align256(off + (uint64_t)max_nodes * 4u);
     return off;
 }
 
@@ -1080,8 +1206,8 @@ const char *rg_status_string(rg_status s) {
 rg_status rg_blas_sizes(int64_t n_tris, const rg_build_opts *opts, rg_sizes *out) {
     Opts o;
     if (!out || n_tris < 1 || n_tris > RG_MAX_TRIS || !opts_ok(opts, &o)) return RG_ERR_INVALID_ARG;
-    uint64_t a, b, c, d;
-    out->bytes = blas_out_bytes(n_tris, o.w, &a, &b, &c, &d);
+    uint64_t a, b, c, d, e;
+    out->bytes = blas_out_bytes(n_tris, o.w, &a, &b, &c, &d, &e);
     out->scratch_bytes = blas_scratch_bytes(n_tris, o.builder);
     return RG_OK;
 }
@@ -1094,8 +1220,8 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
     if (n_verts < 1 || n_verts > (1ll << 32) || n_tris < 1 || n_tris > RG_MAX_TRIS) return RG_ERR_INVALID_ARG;
     if (!opts_ok(opts, &o)) return RG_ERR_INVALID_ARG;
     const int32_t w = o.w, l = o.leaf;
-    uint64_t no, to, mo, so;
-    uint64_t need = blas_out_bytes(n_tris, w, &no, &to, &mo, &so);
+    uint64_t no, to, mo, so, po;
+    uint64_t need = blas_out_bytes(n_tris, w, &no, &to, &mo, &so, &po);
     if (out_bytes < need || scratch_bytes < blas_scratch_bytes(n_tris, o.builder)) return RG_ERR_OUT_OF_MEMORY;
     hipStream_t st = (hipStream_t)stream;
     RgArena arena{(char *)scratch, scratch_bytes, 0};
@@ -1110,8 +1236,8 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
     if (hflags) return RG_ERR_INVALID_ARG;
     char *base = (char *)out_buf;
     RgLbvhOut lo;
-    rg_status r = rg_lbvh_build(pbox, n_tris, w, l, o.builder, o.radius, base + no, arena, st, &lo, false, nullptr,
-                                nullptr, nullptr, nullptr);
+    rg_status r = rg_lbvh_build(pbox, n_tris, w, l, o.builder, o.radius, base + no, (uint32_t *)(base + po), arena,
+                                st, &lo, false, nullptr, nullptr, nullptr, nullptr);
     if (r != RG_OK) return r;
     k_reorder_tris<<<rg_blocks(n_tris, kThreads), kThreads, 0, st>>>(
         verts, idx, lo.ids, n_tris, prim_material, (RgTri *)(base + to), (uint16_t *)(base + mo),
@@ -1125,6 +1251,7 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
     out->tris_off = to;
     out->mats_off = mo;
     out->slots_off = so;
+    out->parents_off = po;
     out->n_tris = n_tris;
     out->n_nodes = lo.n_nodes;
     out->width = w;
@@ -1134,6 +1261,55 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
     for (int k = 0; k < 3; ++k) {
         out->lo[k] = lo.lo[k];
         out->hi[k] = lo.hi[k];
+    }
+    return RG_OK;
+}
+
+rg_status rg_refit_sizes(const rg_blas *blas, uint64_t *scratch_bytes) {
+    if (!blas || !scratch_bytes || blas->n_nodes < 1) return RG_ERR_INVALID_ARG;
+    RgArena a{nullptr, 0, 0};
+    a.take<uint32_t>(blas->n_nodes);  // inner children per node
+    a.take<uint32_t>(blas->n_nodes);  // arrivals
+    a.take<float>(8);                 // root box
+    a.take<uint32_t>(8);              // flags
+    *scratch_bytes = a.used;
+    return RG_OK;
+}
+
+rg_status rg_refit_blas(rg_blas *blas, const float *verts, int64_t n_verts, const uint32_t *idx, int64_t n_tris,
+                        void *scratch, uint64_t scratch_bytes, void *stream) {
+    if (!blas || !blas->buf || !verts || !idx || !scratch) return RG_ERR_INVALID_ARG;
+    if (n_tris != blas->n_tris || n_verts < 1 || n_verts > (1ll << 32) || blas->n_nodes < 1) return RG_ERR_INVALID_ARG;
+    if (!(blas->width == 2 || blas->width == 4 || blas->width == 8)) return RG_ERR_INVALID_ARG;
+    uint64_t need_bytes = 0;
+    rg_refit_sizes(blas, &need_bytes);
+    if (scratch_bytes < need_bytes) return RG_ERR_OUT_OF_MEMORY;
+    hipStream_t st = (hipStream_t)stream;
+    RgArena arena{(char *)scratch, scratch_bytes, 0};
+    uint32_t *need = arena.take<uint32_t>(blas->n_nodes);
+    uint32_t *arrived = arena.take<uint32_t>(blas->n_nodes);
+    float *root = arena.take<float>(8);
+    uint32_t *flags = arena.take<uint32_t>(8);
+    char *base = (char *)blas->buf;
+    RgTri *tris = (RgTri *)(base + blas->tris_off);
+    const uint32_t *parents = (const uint32_t *)(base + blas->parents_off);
+    k_fill_u32<<<1, 64, 0, st>>>(flags, 0u, 1);
+    k_refit_tris<<<rg_blocks(n_tris, kThreads), kThreads, 0, st>>>(verts, n_verts, idx, n_tris, tris, flags);
+    RG_LAUNCH_CHECK();
+    void *nodes = base + blas->nodes_off;
+    if (blas->width == 2) refit_launch<2>(nodes, blas->n_nodes, parents, tris, need, arrived, root, st);
+    else if (blas->width == 4) refit_launch<4>(nodes, blas->n_nodes, parents, tris, need, arrived, root, st);
+    else refit_launch<8>(nodes, blas->n_nodes, parents, tris, need, arrived, root, st);
+    RG_LAUNCH_CHECK();
+    float hb[6];
+    uint32_t hflags = 0;
+    RG_HIP(hipMemcpyAsync(hb, root, 24, hipMemcpyDeviceToHost, st));
+    RG_HIP(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, st));
+    RG_HIP(hipStreamSynchronize(st));
+    if (hflags) return RG_ERR_INVALID_ARG;
+    for (int k = 0; k < 3; ++k) {
+        blas->lo[k] = hb[k];
+        blas->hi[k] = hb[3 + k];
     }
     return RG_OK;
 }
@@ -1197,8 +1373,8 @@ rg_status rg_build_tlas(const rg_blas *blas, int32_t n_blas, const float *xform,
     RG_LAUNCH_CHECK();
     char *base = (char *)out_buf;
     RgLbvhOut lo;
-    rg_status r = rg_lbvh_build(d_box, n_inst, w, 1, o.builder, o.radius, base + no, arena, st, &lo, false, nullptr,
-                                nullptr, nullptr, nullptr);
+    rg_status r = rg_lbvh_build(d_box, n_inst, w, 1, o.builder, o.radius, base + no, nullptr, arena, st, &lo, false,
+                                nullptr, nullptr, nullptr, nullptr);
     if (r != RG_OK) return r;
     k_reorder_inst<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(d_rec, lo.ids, n_inst, (RgInst *)(base + io),
                                                                       (uint32_t *)(base + ro));
@@ -1241,8 +1417,8 @@ rg_status rg_lbvh_stages(const float *verts, int64_t n_verts, const uint32_t *id
     RG_HIP(hipStreamSynchronize(st));
     if (hflags) return RG_ERR_INVALID_ARG;
     RgLbvhOut lo;
-    rg_status r = rg_lbvh_build(pbox, n_tris, o.w, o.leaf, o.builder, o.radius, nullptr, arena, st, &lo, true, keys,
-                                left, right, boxes);
+    rg_status r = rg_lbvh_build(pbox, n_tris, o.w, o.leaf, o.builder, o.radius, nullptr, nullptr, arena, st, &lo,
+                                true, keys, left, right, boxes);
     if (r != RG_OK) return r;
     RG_HIP(hipMemcpyAsync(ids, lo.ids, 4 * n_tris, hipMemcpyDeviceToDevice, st));
     RG_HIP(hipStreamSynchronize(st));

@@ -43,7 +43,7 @@ struct RgBlasHdr {
     uint64_t nodes, tris, mats, slots;
 };
 
-// Instance record in top-level leaf order: 80 bytes.
+// Instance record in top-level leaf order: 112 bytes.
 struct RgInst {
     float inv[9];  // world -> object linear part, row-major
     float p[3];    // object -> world translation (as given)
@@ -124,10 +124,12 @@ struct RgLbvhOut {
     int64_t n_nodes;
     float lo[3], hi[3];
 };
+// parents (nullable): per wide node, (parent node << 3) | slot in the parent,
+// RG_MISS for the root.
 rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t leaf_max, int32_t builder,
-                        int32_t radius, void *nodes, RgArena &scratch, hipStream_t stream, RgLbvhOut *out,
-                        bool keep_stages, uint64_t *keys_out, int32_t *left_out, int32_t *right_out,
-                        float *boxes_out);
+                        int32_t radius, void *nodes, uint32_t *parents, RgArena &scratch, hipStream_t stream,
+                        RgLbvhOut *out, bool keep_stages, uint64_t *keys_out, int32_t *left_out,
+                        int32_t *right_out, float *boxes_out);
 uint64_t rg_lbvh_scratch_bytes(int64_t n, int32_t builder);
 
 // In-place exclusive prefix sum of m uint32 values (one workgroup).

@@ -326,6 +326,46 @@ def identity_xform(n: int = 1) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
+# animation (dynamic scenes): moving vertices and moving instances
+# ----------------------------------------------------------------------------
+def animate_mesh(mesh: Mesh, t: float, amp: float = 0.05, seed: int = 0) -> np.ndarray:
+    """Vertex positions of `mesh` at time t: a travelling wave along a seeded
+    direction, displacing each vertex by up to `amp` times the mesh's extent
+    along a second seeded direction (same triangles, new positions)."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 77]))
+    k = rng.normal(size=3)
+    k /= np.linalg.norm(k)
+    a = rng.normal(size=3)
+    a /= np.linalg.norm(a)
+    v = mesh.verts.astype(np.float64)
+    ext = float(np.max(v.max(axis=0) - v.min(axis=0)))
+    phase = 2.0 * np.pi * (v @ k) / max(ext, 1e-9) + 2.0 * np.pi * t
+    return (v + amp * ext * np.sin(phase)[:, None] * a[None, :]).astype(np.float32)
+
+
+def animate_instances(xform: np.ndarray, t: float, seed: int = 0, spin: float = 0.5,
+                      drift: float = 1.0) -> np.ndarray:
+    """Instance matrices at time t: each instance turns about its own seeded
+    axis by spin*t*2pi radians (applied before its own rotation and scale) and
+    moves by drift*sin(2pi t + phase) along a seeded direction."""
+    X = np.asarray(xform, np.float64).reshape(-1, 3, 4)
+    n = X.shape[0]
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 78]))
+    axis = rng.normal(size=(n, 3))
+    axis /= np.linalg.norm(axis, axis=1, keepdims=True)
+    dirn = rng.normal(size=(n, 3))
+    dirn /= np.linalg.norm(dirn, axis=1, keepdims=True)
+    ph = rng.uniform(0.0, 2.0 * np.pi, n)
+    ang = spin * t * 2.0 * np.pi
+    q = np.concatenate([axis * np.sin(ang / 2.0), np.full((n, 1), np.cos(ang / 2.0))], axis=1)
+    R = quat_to_matrix(q)
+    out = np.empty_like(X)
+    out[:, :, :3] = X[:, :, :3] @ R
+    out[:, :, 3] = X[:, :, 3] + drift * np.sin(2.0 * np.pi * t + ph)[:, None] * dirn
+    return out.astype(np.float32)
+
+
+# ----------------------------------------------------------------------------
 # configurations
 # ----------------------------------------------------------------------------
 def config_small(seed: int = 1) -> Scene:

@@ -118,6 +118,14 @@ def test_null_pointer_calls_are_rejected_on_the_host():
     blas = (rg.BlasDesc * 1)(fake)
     assert lib.rg_build_tlas(blas, 1, xf3, bid, im, 1, ctypes.byref(o), 256, 1 << 20, 256, 1 << 20, None,
                              ctypes.byref(t)) == -1
+    # refit: sizes from the descriptor, NULL arrays, another triangle count, short scratch
+    fake.n_nodes, fake.n_tris = 100, 150
+    need = ctypes.c_uint64()
+    assert lib.rg_refit_sizes(ctypes.byref(fake), ctypes.byref(need)) == 0 and need.value >= 800
+    assert lib.rg_refit_sizes(None, ctypes.byref(need)) == -1
+    assert lib.rg_refit_blas(ctypes.byref(fake), None, 3, None, 150, None, 0, None) == -1
+    assert lib.rg_refit_blas(ctypes.byref(fake), 256, 3, 256, 149, 256, 1 << 20, None) == -1
+    assert lib.rg_refit_blas(ctypes.byref(fake), 256, 3, 256, 150, 256, 16, None) == -2
 
 
 def test_undersized_buffers_are_rejected():

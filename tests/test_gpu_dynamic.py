@@ -1,0 +1,123 @@
+"""Dynamic scenes on the GPU (moving geometry, the per-frame update before the
+path): a bottom level refitted to new vertex positions keeps its hierarchy
+and holds the new triangles; refitting to unchanged vertices reproduces the
+build bit for bit; a refitted scene with a rebuilt top level traces to the
+very hits of a scene built from scratch at the new positions, and to the FP64
+oracle's."""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen as sg
+from tests import bvh_check, parity
+from tests.helpers import scene_from_meshes
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(verts, idx):
+    import torch
+    v = torch.from_numpy(np.ascontiguousarray(verts, np.float32)).cuda()
+    i = torch.from_numpy(np.ascontiguousarray(idx, np.uint32).view(np.int32)).cuda()
+    return v, i
+
+
+@pytest.mark.parametrize("builder", ["lbvh", "ploc"])
+@pytest.mark.parametrize("width,leaf", [(2, 1), (4, 1), (4, 4), (8, 3)])
+def test_refit_to_unchanged_vertices_reproduces_the_build(builder, width, leaf):
+    import paper_2001_09792_amd as rg
+    mesh = sg.torus(48, 40, 1.0, 0.35, 0.08, 6.0, 3001)
+    print(f"[refit same] {builder} W{width} L{leaf}", flush=True)
+    v, i = _dev(mesh.verts, mesh.idx)
+    b = rg.build_blas(v, i, None, width, leaf, builder=builder)
+    before = b.buf.cpu().numpy().copy()
+    lo, hi = list(b.desc.lo), list(b.desc.hi)
+    rg.refit_blas(b, v, i)
+    after = b.buf.cpu().numpy()
+    assert np.array_equal(before, after)
+    assert list(b.desc.lo) == lo and list(b.desc.hi) == hi
+
+
+@pytest.mark.parametrize("width,leaf", [(2, 1), (4, 1), (8, 4)])
+def test_refit_to_moved_vertices_holds_the_new_mesh(width, leaf):
+    """Structure and boxes checked on the host; the triangles in leaf order
+    are the moved ones; hits against the oracle on the moved mesh."""
+    import paper_2001_09792_amd as rg
+    mesh = sg.torus(64, 48, 1.0, 0.35, 0.08, 6.0, 3002)
+    moved = sg.Mesh(sg.animate_mesh(mesh, 0.35, amp=0.08, seed=5), mesh.idx)
+    print(f"[refit moved] W{width} L{leaf}", flush=True)
+    v0, i = _dev(mesh.verts, mesh.idx)
+    b = rg.build_blas(v0, i, None, width, leaf)
+    v1, _ = _dev(moved.verts, moved.idx)
+    rg.refit_blas(b, v1, i)
+    info = bvh_check.check_blas(b.buf.cpu().numpy(), b.desc)
+    assert np.array_equal(info["verts"], moved.verts[moved.idx[info["prim"]]])
+    assert np.allclose(b.desc.lo, moved.verts.min(axis=0)) and np.allclose(b.desc.hi, moved.verts.max(axis=0))
+    # trace through a top level built over the refitted bottom level
+    tl = rg.build_tlas([b], sg.identity_xform(1), [0], [0], width)
+    rng = np.random.default_rng(7)
+    cen = moved.verts[moved.idx].mean(axis=1)
+    rays = np.concatenate([sg.random_rays(3000, 8, extent=1.8),
+                           sg.rays_through_points(cen[rng.integers(0, cen.shape[0], 3000)], 9, 3.0)])
+    h = parity.hits_to_numpy(rg.trace_closest(tl, rg.rays_to_device(rays)))
+    oc = oracle.Scene(scene_from_meshes([moved])).trace(rays)
+    print(parity.check_closest(h, oc, 0.02, "refit moved"), flush=True)
+
+
+def _moved_two_level(t):
+    sc = sg.config_two_level(width=160, height=90, max_depth=3)
+    meshes = [sg.Mesh(sg.animate_mesh(m, t, amp=0.04, seed=k), m.idx, m.prim_mat) for k, m in enumerate(sc.blas)]
+    xf = sg.animate_instances(sc.xform, t, seed=11)
+    return sc, meshes, xf
+
+
+def test_refitted_scene_traces_like_a_fresh_build():
+    """Hits do not depend on the hierarchy (ties go to the lowest instance and
+    input triangle, the instance slide point depends only on the root box,
+    which a refit computes exactly): the refitted scene gives bitwise the hits
+    of a scene built from scratch at the new positions."""
+    import paper_2001_09792_amd as rg
+    sc, moved, xf = _moved_two_level(0.3)
+    print("[dynamic] two-level, refit + top-level rebuild", flush=True)
+    tl0 = rg.upload_scene(sc, 4, 1)
+    for b, m in zip(tl0.blas, moved):
+        v, i = _dev(m.verts, m.idx)
+        rg.refit_blas(b, v, i)
+    tl_refit = rg.build_tlas(tl0.blas, xf, sc.blas_id, sc.inst_mat, 4)
+    fresh_scene = sg.Scene(sc.name, moved, xf, sc.blas_id, sc.inst_mat, sc.materials, sc.camera, sc.light,
+                           sc.width, sc.height, sc.max_depth, sc.mode, sc.seed)
+    tl_fresh = rg.upload_scene(fresh_scene, 4, 1)
+    for b in tl_refit.blas:
+        bvh_check.check_blas(b.buf.cpu().numpy(), b.desc)
+    bvh_check.check_tlas(tl_refit.buf.cpu().numpy(), tl_refit.desc, [b.desc for b in tl_refit.blas], xf)
+    cam = rg.camera_rays(sc.camera, sc.width, sc.height).cpu().numpy().T.copy()
+    rays = rg.rays_to_device(np.concatenate([cam, sg.random_rays(8000, 12, extent=22.0)]))
+    h1 = parity.hits_to_numpy(rg.trace_closest(tl_refit, rays))
+    h2 = parity.hits_to_numpy(rg.trace_closest(tl_fresh, rays))
+    for k in h1:
+        assert np.array_equal(h1[k].view(np.uint32), h2[k].view(np.uint32)), k
+    assert np.array_equal(rg.trace_any(tl_refit, rays).cpu().numpy(), rg.trace_any(tl_fresh, rays).cpu().numpy())
+    # the rendered frame against the oracle on the moved scene (sampled pixels)
+    img = rg.render(tl_refit, sc.materials, sc.camera, sc.light, sc.width, sc.height, sc.max_depth)
+    px = sg.sample_pixels(sc.width, sc.height, 800, 13)
+    ref = oracle.Scene(fresh_scene, sphere_reject=True).render(px, width=sc.width, height=sc.height,
+                                                               max_depth=sc.max_depth)
+    print(parity.check_image(img.cpu().numpy().reshape(-1, 3)[px], ref, 0.04, "refit render"), flush=True)
+
+
+def test_refit_errors():
+    import torch
+    import paper_2001_09792_amd as rg
+    mesh = sg.random_soup(200, 3)
+    v, i = _dev(mesh.verts, mesh.idx)
+    b = rg.build_blas(v, i)
+    with pytest.raises(rg.RgError):
+        rg.refit_blas(b, v, i[:100])          # other triangle count
+    bad = v.clone()
+    bad[7, 0] = float("inf")
+    with pytest.raises(rg.RgError):
+        rg.refit_blas(b, bad, i)
+    # a valid refit afterwards restores the structure
+    rg.refit_blas(b, v, i)
+    bvh_check.check_blas(b.buf.cpu().numpy(), b.desc)
+    torch.cuda.synchronize()
