@@ -75,7 +75,7 @@ def recorded_traffic(args):
 # two-level frames on width-8 clustered hierarchies (about 5% faster).  The
 # batched workload starts from its entry and can be autotuned.
 SHAPES = {"incoherent": (4, 1, "lbvh"), "two_level": (8, 1, "ploc"), "batched": (4, 1, "lbvh"),
-          "serving": (4, 1, "lbvh")}
+          "serving": (4, 1, "lbvh"), "dynamic": (4, 1, "lbvh")}
 
 
 def log(*a):
@@ -256,6 +256,114 @@ def bench_incoherent(args, torch, rg, sg):
         "ao_raygen_ms": t_aogen,
         "build_mtris_s": scene.unique_tris() / build_s / 1e6,
         "wall_s_timed": wall,
+    }
+    return out, scene
+
+
+def bench_dynamic(args, torch, rg, sg):
+    """Moving geometry over the incoherent scene: each step refits the 16
+    bottom levels to the next animation frame's vertex positions, rebuilds the
+    top level over the moved instances, and traces that frame's camera rays
+    and 8 AO rays per primary hit (closest hit), as the incoherent workload
+    does.  Frames alternate between two precomputed animation times whose
+    vertices are resident on the device.  Also measured: rebuilding the
+    bottom levels from scratch instead of refitting them, and the node visits
+    of the refitted hierarchy against a fresh build at the same positions."""
+    t0 = time.perf_counter()
+    scene = sg.config_incoherent(segments=args.segments)
+    times = (0.15, 0.4)
+    verts = [[torch.from_numpy(sg.animate_mesh(m, t, amp=0.02, seed=k)).cuda() for k, m in enumerate(scene.blas)]
+             for t in times]
+    xfs = [sg.animate_instances(scene.xform, t, seed=3) for t in times]
+    idx = [torch.from_numpy(np.ascontiguousarray(m.idx, np.uint32).view(np.int32)).cuda() for m in scene.blas]
+    log(f"scene and two animation frames ({time.perf_counter() - t0:.1f}s to generate)")
+    tl = rg.upload_scene(scene, width=args.width, leaf_max=args.leaf, builder=args.builder)
+    blas = tl.blas
+    need = rg.ctypes.c_uint64()
+    tl_scratch = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    W, H = scene.width, scene.height
+    N = W * H
+    cam = torch.empty((8, N), dtype=torch.float32, device="cuda")
+    hits = rg.alloc_hits(N)
+    ao = torch.empty((8, 8 * N), dtype=torch.float32, device="cuda")
+    src = torch.empty(8 * N, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ao_hits = rg.alloc_hits(8 * N)
+    rg._lib.rg_ao_rays_scratch(N, rg.ctypes.byref(need))
+    ao_scratch = torch.empty(max(256, need.value), dtype=torch.uint8, device="cuda")
+    state = {"tl": tl}
+
+    def update(f):
+        rg.refit_blas_many(blas, verts[f % 2], idx)
+        state["tl"] = rg.build_tlas(blas, xfs[f % 2], scene.blas_id, scene.inst_mat, args.width,
+                                    scratch=tl_scratch)
+
+    def trace():
+        t = state["tl"]
+        rg.camera_rays(scene.camera, W, H, out=cam)
+        rg.trace_closest(t, cam, out=hits)
+        rg.ao_rays(t, cam, hits, scene.seed, 5.0, out=ao, src=src, count=cnt, scratch=ao_scratch)
+        n_ao = int(cnt.item())
+        rg.trace_closest(t, ao[:, :n_ao], out={k: v[:n_ao] for k, v in ao_hits.items()})
+        return n_ao
+
+    for f in range(args.warmup):
+        update(f)
+        trace()
+    torch.cuda.synchronize()
+    rays, t_upd, t_tr = 0, 0.0, 0.0
+    w0 = time.perf_counter()
+    for f in range(args.steps):
+        a = time.perf_counter()
+        update(f)
+        torch.cuda.synchronize()
+        b_ = time.perf_counter()
+        rays += N + trace()
+        torch.cuda.synchronize()
+        c = time.perf_counter()
+        t_upd += b_ - a
+        t_tr += c - b_
+    wall = time.perf_counter() - w0
+    ms_step = wall * 1e3 / args.steps
+    # the update split: the refits alone, the top level alone
+    a = time.perf_counter()
+    rg.refit_blas_many(blas, verts[0], idx)
+    torch.cuda.synchronize()
+    t_refit = time.perf_counter() - a
+    a = time.perf_counter()
+    state["tl"] = rg.build_tlas(blas, xfs[0], scene.blas_id, scene.inst_mat, args.width, scratch=tl_scratch)
+    torch.cuda.synchronize()
+    t_tlas = time.perf_counter() - a
+    # refitted against freshly built bottom levels at the same positions
+    trace()
+    n_ao = int(cnt.item())
+    counts_refit = rg.trace_counts(state["tl"], ao[:, :n_ao]).cpu().numpy()
+    moved = sg.Scene(scene.name, [sg.Mesh(v.cpu().numpy(), m.idx) for v, m in zip(verts[0], scene.blas)], xfs[0],
+                     scene.blas_id, scene.inst_mat, scene.materials, scene.camera, scene.light, W, H,
+                     scene.max_depth, scene.mode, scene.seed)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    fresh = rg.upload_scene(moved, width=args.width, leaf_max=args.leaf, builder=args.builder)
+    torch.cuda.synchronize()
+    t_rebuild = time.perf_counter() - a
+    counts_fresh = rg.trace_counts(fresh, ao[:, :n_ao]).cpu().numpy()
+    n_tris = scene.unique_tris()
+    out = {
+        "metric": "Mrays/s closest-hit (primary+incoherent)",
+        "value": rays / wall / 1e6, "unit": "Mrays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "dynamic: the incoherent scene (1024 instances of 16 displaced tori "
+                               f"{args.segments}x{args.segments}, {n_tris} unique tris) with moving vertices "
+                               "and moving instances; per step: refit of every bottom level, top-level "
+                               "rebuild, 1920x1080 camera rays + 8 AO rays per primary hit, closest hit",
+                   "bvh_width": args.width, "leaf_max": args.leaf, "builder": args.builder},
+        "update_ms": t_upd * 1e3 / args.steps, "trace_ms": t_tr * 1e3 / args.steps,
+        "refit_ms": t_refit * 1e3, "refit_mtris_s": n_tris / t_refit / 1e6,
+        "tlas_rebuild_ms": t_tlas * 1e3, "blas_rebuild_ms": t_rebuild * 1e3,
+        "ao_mean_nodes_refit": float(counts_refit[:, 0].mean()),
+        "ao_mean_nodes_fresh": float(counts_fresh[:, 0].mean()),
+        "wall_s_timed": wall, "roofline": None,
     }
     return out, scene
 
@@ -518,7 +626,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["incoherent", "two_level", "batched", "serving"], default="incoherent")
+    ap.add_argument("--workload", choices=["incoherent", "two_level", "batched", "serving", "dynamic"],
+                    default="incoherent")
     ap.add_argument("--scenes", type=int, default=256, help="frames of the batched workload")
     ap.add_argument("--autotune", action="store_true", help="batched: tune width, leaf size and launch "
                     "parameters on a subsample first (cached per GPU and size bucket)")
@@ -557,13 +666,16 @@ def main():
     import paper_2001_09792_amd as rg
     import scenegen as sg
     assert torch.cuda.is_available(), "bench.py needs the GPU"
-    scope = {"incoherent": "trace", "two_level": "frame", "batched": "frame", "serving": "engine"}[args.workload]
+    scope = {"incoherent": "trace", "two_level": "frame", "batched": "frame", "serving": "engine",
+             "dynamic": "trace"}[args.workload]
     rg.trace_tuning(args.refill, args.waves_per_cu, args.lds_depth, args.leaf_batch, args.inst_batch, scope=scope)
     if args.workload == "incoherent":
         out, scene = bench_incoherent(args, torch, rg, sg)
         if not args.no_cpu_baseline:
             log("timing the oracle on a sample")
             out["cpu_baseline"] = cpu_baseline_incoherent(scene, 64, args.cpu_seconds)
+    elif args.workload == "dynamic":
+        out, scene = bench_dynamic(args, torch, rg, sg)
     elif args.workload == "two_level":
         out, scene = bench_two_level(args, torch, rg, sg)
         if not args.no_cpu_baseline:

@@ -58,6 +58,7 @@ typedef int32_t rg_status;
 #define RG_MISS 0xFFFFFFFFu
 #define RG_PER_PRIM 0xFFFFFFFFu   /* instance material: use the mesh's per-primitive ids */
 #define RG_MAX_DEPTH 8
+#define RG_LEVELS_CAP 255        /* deepest bottom level whose level table is kept */
 
 /* Hierarchy builders.  Both start from the primitives sorted by the Morton
  * code of their box centres.
@@ -91,8 +92,10 @@ typedef struct {
 
 /* Bottom-level structure: a POD descriptor of the caller's output buffer.
  * Layout of `buf` (all offsets in bytes from buf):
- *   0:         header of four uint64 device addresses: nodes, tris, mats,
- *              slots (the arrays below).
+ *   0:         64-byte header: four uint64 device addresses (nodes, tris,
+ *              mats, slots: the arrays below), the root box float lo[3],
+ *              hi[3] (kept current by rg_refit_blas), uint32 status of the
+ *              last refit's input check (0: valid), uint32 padding.
  *   nodes_off: n_nodes nodes of 32*width bytes (width 4: 128 B):
  *              float lo_x[w], lo_y[w], lo_z[w], hi_x[w], hi_y[w], hi_z[w];
  *              uint32 child[w]; padding to 32*width bytes.
@@ -106,14 +109,17 @@ typedef struct {
  *   slots_off: uint32 per input triangle: its position in leaf order.
  *   parents_off: uint32 per node: (parent node << 3) | the parent's child
  *              slot holding it; RG_MISS for the root (used by rg_refit_blas).
+ *   levels_off: uint32[RG_LEVELS_CAP + 1]: nodes are numbered level by level
+ *              (root level 0); entry l is the first node of level l and entry
+ *              `depth` the node count (written when depth <= RG_LEVELS_CAP).
  * The build reads the vertex and index arrays only during the call; the
  * descriptor refers to `buf`, which must outlive every top level using it. */
 typedef struct {
     void *buf;
-    uint64_t nodes_off, tris_off, mats_off, slots_off, parents_off;
+    uint64_t nodes_off, tris_off, mats_off, slots_off, parents_off, levels_off;
     int64_t n_tris, n_nodes;
     int32_t width, leaf_max, depth, has_mats;
-    float lo[3], hi[3]; /* root box (object space) */
+    float lo[3], hi[3]; /* root box (object space) at build time; the header holds the current one */
 } rg_blas;
 
 /* Top-level structure.  Layout of `buf`:
@@ -202,19 +208,40 @@ rg_status rg_refit_sizes(const rg_blas *blas /*host*/, uint64_t *scratch_bytes /
  * step before tracing that the paper's scene graph and physics drive): idx
  * must be the index array of the build (n_tris equal), verts the new
  * float[n_verts][3].  The triangles in leaf order are rewritten and every
- * node box is recomputed bottom-up (min / max, exact: unchanged vertices
- * reproduce the build bit for bit); the hierarchy itself is kept, so its
- * quality degrades as triangles move far from where they were built.
- * Updates blas->lo / hi (the root box); top levels over this bottom level
- * carry its root box and must be rebuilt (rg_build_tlas) before tracing.
- * scratch: rg_refit_sizes bytes.  Synchronous.
- * Errors: RG_ERR_INVALID_ARG for NULL pointers, another n_tris, and (after
- * the sync) an index >= n_verts or a non-finite vertex, in which case the
- * bottom level's contents are undefined until it is refitted with valid
- * data or rebuilt; RG_ERR_OUT_OF_MEMORY for a short scratch buffer. */
-rg_status rg_refit_blas(rg_blas *blas /*host, in/out*/, const float *verts, int64_t n_verts,
+ * node box is recomputed bottom-up, one launch per level (min / max, exact:
+ * unchanged vertices reproduce the build bit for bit); the hierarchy itself
+ * is kept, so its quality degrades as triangles move far from where they were
+ * built.  The new root box goes to the buffer's header, not to *blas.
+ * Top levels over this bottom level carry its root box and must be rebuilt
+ * (rg_build_tlas reads the root boxes from the headers) before tracing.
+ * scratch: rg_refit_sizes bytes, used only by hierarchies deeper than
+ * RG_LEVELS_CAP levels (may be NULL otherwise).  Asynchronous.
+ * Errors: RG_ERR_INVALID_ARG for NULL pointers or another n_tris;
+ * RG_ERR_OUT_OF_MEMORY for a short scratch buffer.  An index >= n_verts or a
+ * non-finite vertex is found on the device: it sets the header's status word
+ * (the offending triangles keep their old data, nothing is read out of
+ * bounds), rg_build_tlas over this bottom level then fails with
+ * RG_ERR_INVALID_ARG, and a later valid refit clears it. */
+rg_status rg_refit_blas(rg_blas *blas /*host*/, const float *verts, int64_t n_verts,
                         const uint32_t *idx, int64_t n_tris, void *scratch, uint64_t scratch_bytes,
                         void *stream);
+
+/* rg_refit_blas for n_blas bottom levels of one width at once (arrays of
+ * n_blas host entries: descriptors, device pointers to each one's new
+ * vertices and its index array, vertex and triangle counts): each launch
+ * covers one level of all of them, so a set of meshes costs about what the
+ * largest one costs.  scratch: the largest rg_refit_sizes among those deeper
+ * than RG_LEVELS_CAP (NULL if none is).  Asynchronous.  Errors as
+ * rg_refit_blas, and RG_ERR_INVALID_ARG for mixed widths. */
+rg_status rg_refit_blas_many(rg_blas *blas /*host [n_blas]*/, int32_t n_blas,
+                             const float *const *verts /*host [n_blas]*/, const int64_t *n_verts /*host*/,
+                             const uint32_t *const *idx /*host [n_blas]*/, const int64_t *n_tris /*host*/,
+                             void *scratch, uint64_t scratch_bytes, void *stream);
+
+/* Reads a bottom level's header: current root box and the status of its last
+ * refit (0: valid input).  Synchronous (waits for `stream`). */
+rg_status rg_blas_state(const rg_blas *blas /*host*/, float *lo /*host [3]*/, float *hi /*host [3]*/,
+                        uint32_t *status /*host*/, void *stream);
 
 /* --------------------------------------------------------- top level */
 rg_status rg_tlas_sizes(int64_t n_inst, const rg_build_opts *opts, rg_sizes *out /*host*/);
@@ -224,9 +251,11 @@ rg_status rg_tlas_sizes(int64_t n_inst, const rg_build_opts *opts, rg_sizes *out
  * object->world; blas_id, inst_material: host uint32[n_inst].  Instance boxes
  * are the 8 transformed corners of the bottom level's root box, computed in
  * double and rounded outward to float; the world->object inverse is computed
- * in double and stored as float.  Synchronous.
+ * in double and stored as float.  The bottom levels' root boxes are read
+ * from their headers on the device.  Synchronous.
  * Errors: RG_ERR_INVALID_ARG for NULL pointers, blas_id out of range, a
- * non-finite or singular matrix, mixed widths. */
+ * non-finite or singular matrix, mixed widths, or a bottom level whose last
+ * refit found invalid input (its header's status word is set). */
 rg_status rg_build_tlas(const rg_blas *blas, int32_t n_blas, const float *xform,
                         const uint32_t *blas_id, const uint32_t *inst_material, int64_t n_inst,
                         const rg_build_opts *opts, void *out_buf, uint64_t out_bytes,

@@ -26,6 +26,7 @@ RG_OK = 0
 MISS = 0xFFFFFFFF
 PER_PRIM = 0xFFFFFFFF
 MAX_DEPTH = 8
+RG_LEVELS_CAP = 255   # include/rg.h: deepest bottom level whose level table is kept
 
 c_f = ctypes.c_float
 c_i32 = ctypes.c_int32
@@ -44,7 +45,7 @@ class Sizes(ctypes.Structure):
 
 class BlasDesc(ctypes.Structure):
     _fields_ = [("buf", c_p), ("nodes_off", c_u64), ("tris_off", c_u64), ("mats_off", c_u64),
-                ("slots_off", c_u64), ("parents_off", c_u64), ("n_tris", c_i64), ("n_nodes", c_i64), ("width", c_i32),
+                ("slots_off", c_u64), ("parents_off", c_u64), ("levels_off", c_u64), ("n_tris", c_i64), ("n_nodes", c_i64), ("width", c_i32),
                 ("leaf_max", c_i32), ("depth", c_i32), ("has_mats", c_i32), ("lo", c_f * 3),
                 ("hi", c_f * 3)]
 
@@ -132,6 +133,8 @@ SIGNATURES = {
                           c_p, c_p]),
     "rg_refit_sizes": (c_i32, [c_p, c_p]),
     "rg_refit_blas": (c_i32, [c_p, c_p, c_i64, c_p, c_i64, c_p, c_u64, c_p]),
+    "rg_blas_state": (c_i32, [c_p, c_p, c_p, c_p, c_p]),
+    "rg_refit_blas_many": (c_i32, [c_p, c_i32, c_p, c_p, c_p, c_p, c_p, c_u64, c_p]),
     "rg_lbvh_stages": (c_i32, [c_p, c_i64, c_p, c_i64, c_p, c_p, c_p, c_p, c_p, c_p, c_p, c_u64, c_p]),
     "rg_batch_sizes": (c_i32, [c_p, c_i32, c_p]),
     "rg_batch_prepare": (c_i32, [c_p, c_i32, c_p, c_u64, c_p, c_p]),
@@ -262,8 +265,9 @@ def build_blas(verts, idx, prim_mat=None, width: int = 4, leaf_max: int = 4, scr
 
 def refit_blas(blas: Blas, verts, idx, scratch=None, stream=None) -> Blas:
     """Refits `blas` in place to new vertex positions of the same triangles
-    (verts: CUDA float32 [V,3]; idx: the index array it was built from).
-    Top levels over it must be rebuilt afterwards (build_tlas)."""
+    (verts: CUDA float32 [V,3]; idx: the index array it was built from),
+    asynchronously.  Top levels over it must be rebuilt afterwards
+    (build_tlas, which reports invalid vertex data found by the refit)."""
     need = ctypes.c_uint64()
     _check("rg_refit_sizes", _lib.rg_refit_sizes(ctypes.byref(blas.desc), ctypes.byref(need)))
     if scratch is None or scratch.numel() < need.value:
@@ -272,6 +276,38 @@ def refit_blas(blas: Blas, verts, idx, scratch=None, stream=None) -> Blas:
         ctypes.byref(blas.desc), _ptr(verts), int(verts.shape[0]), _ptr(idx), int(idx.shape[0]),
         _ptr(scratch), scratch.numel(), _stream(stream)))
     return blas
+
+
+def refit_blas_many(blas: Sequence[Blas], verts: Sequence, idx: Sequence, scratch=None, stream=None):
+    """refit_blas for several bottom levels of one width in one call (one
+    launch per level covers all of them); verts[k], idx[k] as for
+    refit_blas."""
+    n = len(blas)
+    descs = (BlasDesc * n)(*[b.desc for b in blas])
+    vp = (c_p * n)(*[_ptr(v) for v in verts])
+    ip = (c_p * n)(*[_ptr(i) for i in idx])
+    nv = (c_i64 * n)(*[int(v.shape[0]) for v in verts])
+    nt = (c_i64 * n)(*[int(i.shape[0]) for i in idx])
+    need = 0
+    for b in blas:
+        if b.desc.depth > RG_LEVELS_CAP:
+            q = ctypes.c_uint64()
+            _check("rg_refit_sizes", _lib.rg_refit_sizes(ctypes.byref(b.desc), ctypes.byref(q)))
+            need = max(need, q.value)
+    if need and (scratch is None or scratch.numel() < need):
+        scratch = _bytes(need, verts[0].device)
+    _check("rg_refit_blas_many", _lib.rg_refit_blas_many(
+        descs, n, vp, nv, ip, nt, _ptr(scratch) if need else None, scratch.numel() if need else 0,
+        _stream(stream)))
+    return blas
+
+
+def blas_state(blas: Blas, stream=None):
+    """(root box lo, root box hi, status of the last refit) from the
+    bottom level's header; waits for the stream."""
+    lo, hi, st = (c_f * 3)(), (c_f * 3)(), ctypes.c_uint32()
+    _check("rg_blas_state", _lib.rg_blas_state(ctypes.byref(blas.desc), lo, hi, ctypes.byref(st), _stream(stream)))
+    return list(lo), list(hi), int(st.value)
 
 
 # ----------------------------------------------------------------- top level

@@ -86,6 +86,10 @@ __global__ void k_centre_bounds(const float *__restrict__ box, int64_t n, uint32
             mx[k] = fmaxf(mx[k], c);
         }
     }
+    // waves, then the block through LDS, then one atomic per value and block
+    // (atomics on one address serialise: one per wave made this kernel slow)
+    __shared__ float part[6][kThreads / 64];
+    const int wv = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         mn[k] = wave_min(mn[k]);
@@ -94,9 +98,17 @@ __global__ void k_centre_bounds(const float *__restrict__ box, int64_t n, uint32
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            atomicMin(&bounds[k], rg_f2ord(mn[k]));
-            atomicMax(&bounds[3 + k], rg_f2ord(mx[k]));
+            part[k][wv] = mn[k];
+            part[3 + k][wv] = mx[k];
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        float v = part[k][0];
+        for (int q = 1; q < kThreads / 64; ++q) v = k < 3 ? fminf(v, part[k][q]) : fmaxf(v, part[k][q]);
+        if (k < 3) atomicMin(&bounds[k], rg_f2ord(v));
+        else atomicMax(&bounds[k], rg_f2ord(v));
     }
 }
 
@@ -670,55 +682,174 @@ __global__ void k_reorder_tris(const float *__restrict__ verts, const uint32_t *
     slots[s] = (uint32_t)i;
 }
 
-__global__ void k_blas_header(RgBlasHdr *h, uint64_t nodes, uint64_t tris, uint64_t mats, uint64_t slots) {
+__global__ void k_blas_header(RgBlasHdr *h, uint64_t nodes, uint64_t tris, uint64_t mats, uint64_t slots,
+                              float lx, float ly, float lz, float hx, float hy, float hz) {
     h->nodes = nodes;
     h->tris = tris;
     h->mats = mats;
     h->slots = slots;
+    h->lo[0] = lx; h->lo[1] = ly; h->lo[2] = lz;
+    h->hi[0] = hx; h->hi[1] = hy; h->hi[2] = hz;
+    h->status = 0u;
+    h->pad = 0u;
 }
 
 // --------------------------------------------------------------- refit
-// A built bottom level over new positions of the same triangles keeps its
-// hierarchy: the leaf-order triangle copies are rewritten, then every box
+// Built bottom levels over new positions of the same triangles keep their
+// hierarchies: the leaf-order triangle copies are rewritten, then every box
 // is recomputed bottom-up.  Boxes are min / max of vertex coordinates, which
 // are exact, so refitting to unchanged vertices reproduces the build bit for
-// bit.  flags as for k_tri_boxes.
-__global__ void k_refit_tris(const float *__restrict__ verts, int64_t n_verts, const uint32_t *__restrict__ idx,
-                             int64_t n, RgTri *__restrict__ tris, uint32_t *__restrict__ flags) {
-    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const uint32_t prim = tris[s].prim;
-    uint32_t bad = 0;
-    uint32_t v3[3] = {0u, 0u, 0u};
-    if ((int64_t)prim >= n) {
-        bad |= 1u;
-    } else {
-        v3[0] = idx[3 * (int64_t)prim];
-        v3[1] = idx[3 * (int64_t)prim + 1];
-        v3[2] = idx[3 * (int64_t)prim + 2];
-        if ((int64_t)v3[0] >= n_verts || (int64_t)v3[1] >= n_verts || (int64_t)v3[2] >= n_verts) {
-            bad |= 1u;
-            v3[0] = v3[1] = v3[2] = 0u;
-        }
-    }
-    float v[9];
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) v[3 * j + k] = verts[3 * (int64_t)v3[j] + k];
-#pragma unroll
-    for (int k = 0; k < 9; ++k)
-        if (!isfinite(v[k])) bad |= 2u;
-    if (bad) {
-        atomicOr(flags, bad);
-        return;
-    }
-#pragma unroll
-    for (int k = 0; k < 9; ++k) tris[s].v[k] = v[k];
+// bit.  Several bottom levels are refitted together: each launch covers one
+// level of every one of them (blockIdx.y picks the bottom level), so the
+// per-launch latency of a level is paid once for the whole set.
+constexpr int kRefitBatch = 32;
+struct RefitJob {
+    void *nodes;
+    RgTri *tris;
+    const uint32_t *levels;
+    RgBlasHdr *hdr;
+    const float *verts;
+    const uint32_t *idx;
+    int64_t n_verts, n_tris;
+    int32_t depth, pad;
+};
+struct RefitJobs {
+    RefitJob j[kRefitBatch];
+};
+
+__global__ void k_refit_begin(RefitJobs jobs, int n) {
+    if ((int)threadIdx.x < n) jobs.j[threadIdx.x].hdr->status = 0u;
 }
 
-// The boxes of each node's leaf children (their triangles' boxes) and the
-// number of inner children the node waits for before its own box is known.
+// New leaf-order triangle copies; an index out of range or a non-finite
+// coordinate sets the header's status word (flags as for k_tri_boxes) and
+// leaves that triangle as it was.
+__global__ void k_refit_tris(RefitJobs jobs) {
+    const RefitJob &J = jobs.j[blockIdx.y];
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < J.n_tris;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t prim = J.tris[s].prim;
+        uint32_t bad = 0;
+        uint32_t v3[3] = {0u, 0u, 0u};
+        if ((int64_t)prim >= J.n_tris) {
+            bad |= 1u;
+        } else {
+            v3[0] = J.idx[3 * (int64_t)prim];
+            v3[1] = J.idx[3 * (int64_t)prim + 1];
+            v3[2] = J.idx[3 * (int64_t)prim + 2];
+            if ((int64_t)v3[0] >= J.n_verts || (int64_t)v3[1] >= J.n_verts || (int64_t)v3[2] >= J.n_verts) {
+                bad |= 1u;
+                v3[0] = v3[1] = v3[2] = 0u;
+            }
+        }
+        float v[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) v[3 * a + k] = J.verts[3 * (int64_t)v3[a] + k];
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+            if (!isfinite(v[k])) bad |= 2u;
+        if (bad) {
+            atomicOr(&J.hdr->status, bad);
+            continue;
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) J.tris[s].v[k] = v[k];
+    }
+}
+
+// Stores W floats at a 16-byte aligned address with 16-byte stores (W >= 4)
+// or one 8-byte store (W = 2).
+template <int W>
+__device__ inline void store_row(float *dst, const float *v) {
+    if constexpr (W == 2) {
+        *reinterpret_cast<float2 *>(dst) = make_float2(v[0], v[1]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < W; q += 4)
+            *reinterpret_cast<float4 *>(dst + q) = make_float4(v[q], v[q + 1], v[q + 2], v[q + 3]);
+    }
+}
+
+// One node: every child box is recomputed from its triangles (a leaf) or
+// from the child node's own child boxes (already final: deeper levels go
+// first), all reads before the node's six box rows are written back with
+// vector stores (an empty slot is written its inverted box again).  Returns
+// the node's box in u.
+template <int W>
+__device__ inline void refit_node(RgNode<W> *nodes, uint32_t x, const RgTri *__restrict__ tris, float u[6]) {
+    RgNode<W> &nd = nodes[x];
+    float bx[6][W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const uint32_t c = nd.child[k];
+        float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+        if (c != RG_EMPTY && rg_is_leaf(c)) {
+            const uint32_t first = rg_leaf_first(c), cnt = rg_leaf_count(c);
+            for (uint32_t j = 0; j < cnt; ++j) {
+                const RgTri &t = tris[first + j];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    b[a] = fminf(b[a], fminf(fminf(t.v[a], t.v[3 + a]), t.v[6 + a]));
+                    b[3 + a] = fmaxf(b[3 + a], fmaxf(fmaxf(t.v[a], t.v[3 + a]), t.v[6 + a]));
+                }
+            }
+        } else if (c != RG_EMPTY) {
+            const RgNode<W> &cn = nodes[c];
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                if (cn.child[j] == RG_EMPTY) continue;
+                b[0] = fminf(b[0], cn.lo_x[j]); b[1] = fminf(b[1], cn.lo_y[j]); b[2] = fminf(b[2], cn.lo_z[j]);
+                b[3] = fmaxf(b[3], cn.hi_x[j]); b[4] = fmaxf(b[4], cn.hi_y[j]); b[5] = fmaxf(b[5], cn.hi_z[j]);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 6; ++a) bx[a][k] = b[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        u[a] = INFINITY;
+        u[3 + a] = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            u[a] = fminf(u[a], bx[a][k]);
+            u[3 + a] = fmaxf(u[3 + a], bx[3 + a][k]);
+        }
+    }
+    store_row<W>(nd.lo_x, bx[0]);
+    store_row<W>(nd.lo_y, bx[1]);
+    store_row<W>(nd.lo_z, bx[2]);
+    store_row<W>(nd.hi_x, bx[3]);
+    store_row<W>(nd.hi_y, bx[4]);
+    store_row<W>(nd.hi_z, bx[5]);
+}
+
+// Level `level` (counted from the root) of every bottom level deep enough,
+// its node range from the level table.  No atomics: launch order orders the
+// levels.  The root level writes the root box into the header.
+template <int W>
+__global__ void k_refit_level(RefitJobs jobs, int level) {
+    const RefitJob &J = jobs.j[blockIdx.y];
+    if (level >= J.depth) return;
+    RgNode<W> *nodes = reinterpret_cast<RgNode<W> *>(J.nodes);
+    const uint32_t lo = J.levels[level], hi = J.levels[level + 1];
+    for (uint32_t x = lo + blockIdx.x * blockDim.x + threadIdx.x; x < hi; x += gridDim.x * blockDim.x) {
+        float u[6];
+        refit_node<W>(nodes, x, J.tris, u);
+        if (level == 0 && x == 0) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                J.hdr->lo[k] = u[k];
+                J.hdr->hi[k] = u[3 + k];
+            }
+        }
+    }
+}
+
+// Hierarchies deeper than the level table: bottom-up with arrival counters.
+// The boxes of each node's leaf children and the number of inner children
+// the node waits for before its own box is known.
 template <int W>
 __global__ void k_refit_leaves(RgNode<W> *__restrict__ nodes, int64_t n_nodes, const RgTri *__restrict__ tris,
                                uint32_t *__restrict__ need, uint32_t *__restrict__ arrived) {
@@ -751,14 +882,13 @@ __global__ void k_refit_leaves(RgNode<W> *__restrict__ nodes, int64_t n_nodes, c
     arrived[x] = 0u;
 }
 
-// Bottom-up from the nodes without inner children: a node whose children are
+// From the nodes without inner children upwards: a node whose children are
 // all final writes the union of its child boxes into its parent's slot; the
-// last child to arrive at a parent continues with the parent (arrival
-// counters with acquire / release at agent scope, as in k_refit).  The
-// root's box goes to root_box.
+// last child to arrive at a parent continues with the parent (acquire /
+// release at agent scope).  The root's box goes to the header.
 template <int W>
 __global__ void k_refit_up(RgNode<W> *nodes, int64_t n_nodes, const uint32_t *__restrict__ parents,
-                           const uint32_t *__restrict__ need, uint32_t *arrived, float *__restrict__ root_box) {
+                           const uint32_t *__restrict__ need, uint32_t *arrived, RgBlasHdr *hdr) {
     const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (x >= n_nodes || need[x] != 0u) return;
     uint32_t node = (uint32_t)x;
@@ -774,7 +904,10 @@ __global__ void k_refit_up(RgNode<W> *nodes, int64_t n_nodes, const uint32_t *__
         const uint32_t p = parents[node];
         if (p == RG_MISS) {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) root_box[k] = b[k];
+            for (int k = 0; k < 3; ++k) {
+                hdr->lo[k] = b[k];
+                hdr->hi[k] = b[3 + k];
+            }
             return;
         }
         const uint32_t pn = p >> 3, ps = p & 7u;
@@ -789,16 +922,24 @@ __global__ void k_refit_up(RgNode<W> *nodes, int64_t n_nodes, const uint32_t *__
 }
 
 template <int W>
-void refit_launch(void *nodes, int64_t n_nodes, const uint32_t *parents, const RgTri *tris, uint32_t *need,
-                  uint32_t *arrived, float *root_box, hipStream_t st) {
-    RgNode<W> *nd = reinterpret_cast<RgNode<W> *>(nodes);
-    k_refit_leaves<W><<<rg_blocks(n_nodes, kThreads), kThreads, 0, st>>>(nd, n_nodes, tris, need, arrived);
-    k_refit_up<W><<<rg_blocks(n_nodes, kThreads), kThreads, 0, st>>>(nd, n_nodes, parents, need, arrived, root_box);
+void refit_levels(const RefitJobs &jobs, int n, int max_depth, unsigned blocks, hipStream_t st) {
+    for (int l = max_depth - 1; l >= 0; --l)
+        k_refit_level<W><<<dim3(blocks, (unsigned)n), kThreads, 0, st>>>(jobs, l);
+}
+
+template <int W>
+void refit_deep(const rg_blas &b, uint32_t *need, uint32_t *arrived, hipStream_t st) {
+    char *base = (char *)b.buf;
+    RgNode<W> *nd = reinterpret_cast<RgNode<W> *>(base + b.nodes_off);
+    const RgTri *tris = (const RgTri *)(base + b.tris_off);
+    const uint32_t *parents = (const uint32_t *)(base + b.parents_off);
+    k_refit_leaves<W><<<rg_blocks(b.n_nodes, kThreads), kThreads, 0, st>>>(nd, b.n_nodes, tris, need, arrived);
+    k_refit_up<W><<<rg_blocks(b.n_nodes, kThreads), kThreads, 0, st>>>(nd, b.n_nodes, parents, need, arrived,
+                                                                         (RgBlasHdr *)base);
 }
 
 // ----------------------------------------------------------- top level
 struct BlasInfo {
-    float lo[3], hi[3];
     uint64_t nodes, tris, hdr;
 };
 
@@ -813,15 +954,20 @@ __device__ inline float round_up(double x) {
     return f;
 }
 
+// The bottom level's root box and the status of its last refit come from its
+// header on the device (a refit updates them without a host round trip).
 __global__ void k_inst_setup(const float *__restrict__ xform, const uint32_t *__restrict__ blas_id,
                              const uint32_t *__restrict__ inst_mat, const BlasInfo *__restrict__ blas,
-                             int64_t n, float *__restrict__ box, RgInst *__restrict__ recs) {
+                             int64_t n, float *__restrict__ box, RgInst *__restrict__ recs,
+                             uint32_t *__restrict__ flags) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     double m[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) m[k] = (double)xform[12 * i + k];
-    const BlasInfo &B = blas[blas_id[i]];
+    const BlasInfo &BI = blas[blas_id[i]];
+    const RgBlasHdr &B = *reinterpret_cast<const RgBlasHdr *>(BI.hdr);
+    if (B.status != 0u) atomicOr(flags, 1u);
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int c = 0; c < 8; ++c) {
         double p[3] = {(double)((c & 1) ? B.hi[0] : B.lo[0]), (double)((c & 2) ? B.hi[1] : B.lo[1]),
@@ -851,9 +997,9 @@ __global__ void k_inst_setup(const float *__restrict__ xform, const uint32_t *__
     r.p[0] = xform[12 * i + 3];
     r.p[1] = xform[12 * i + 7];
     r.p[2] = xform[12 * i + 11];
-    r.nodes = B.nodes;
-    r.tris = B.tris;
-    r.hdr = B.hdr;
+    r.nodes = BI.nodes;
+    r.tris = BI.tris;
+    r.hdr = BI.hdr;
     r.mat = inst_mat[i];
     r.inst = (uint32_t)i;
 #pragma unroll
@@ -990,12 +1136,18 @@ rg_status ploc_build(const float *prim_box, int64_t n, int radius, const uint32_
 }
 
 template <int W>
-rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes_v, uint32_t *parents, hipStream_t st,
-                   int32_t *depth, int64_t *n_nodes) {
+rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes_v, uint32_t *parents,
+                   uint32_t *levels, hipStream_t st, int32_t *depth, int64_t *n_nodes) {
     RgNode<W> *nodes = reinterpret_cast<RgNode<W> *>(nodes_v);
+    // nodes are allocated level by level: starts[l] .. starts[l+1] is level l
+    std::vector<uint32_t> starts{0u, 1u};
     if (n == 1) {
         k_single_root<W><<<1, 64, 0, st>>>(s.leaf_box, nodes);
         if (parents) k_fill_u32<<<1, 64, 0, st>>>(parents, RG_MISS, 1);
+        if (levels) {
+            k_fill_u32<<<1, 64, 0, st>>>(levels, 0u, 1);
+            k_fill_u32<<<1, 64, 0, st>>>(levels + 1, 1u, 1);
+        }
         RG_LAUNCH_CHECK();
         *depth = 1;
         *n_nodes = 1;
@@ -1024,6 +1176,7 @@ rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes_v,
         RG_HIP(hipStreamSynchronize(st));
         host_count = hq[cout - qc];
         if (hq[3] != 0u || d > 4096) return RG_ERR_HIP;  // inconsistent hierarchy: never expected
+        if (host_count > 0u) starts.push_back(starts.back() + host_count);
         count = host_count;
         uint2 *tq = qin;
         qin = qout;
@@ -1034,7 +1187,10 @@ rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes_v,
     }
     uint32_t nn = 0;
     RG_HIP(hipMemcpyAsync(&nn, qc + 2, 4, hipMemcpyDeviceToHost, st));
+    if (levels && starts.size() <= (size_t)RG_LEVELS_CAP + 1)
+        RG_HIP(hipMemcpyAsync(levels, starts.data(), 4 * starts.size(), hipMemcpyHostToDevice, st));
     RG_HIP(hipStreamSynchronize(st));
+    if (starts.size() != (size_t)d + 1 || starts.back() != nn) return RG_ERR_HIP;  // never expected
     *depth = d;
     *n_nodes = nn;
     return RG_OK;
@@ -1050,8 +1206,8 @@ uint64_t rg_lbvh_scratch_bytes(int64_t n, int32_t builder) {
 }
 
 rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t leaf_max, int32_t builder,
-                        int32_t radius, void *nodes, uint32_t *parents, RgArena &arena, hipStream_t st,
-                        RgLbvhOut *out, bool keep_stages, uint64_t *keys_out, int32_t *left_out,
+                        int32_t radius, void *nodes, uint32_t *parents, uint32_t *levels, RgArena &arena,
+                        hipStream_t st, RgLbvhOut *out, bool keep_stages, uint64_t *keys_out, int32_t *left_out,
                         int32_t *right_out, float *boxes_out) {
     LbvhScratch s;
     if (!carve(arena, n, builder, s)) return RG_ERR_OUT_OF_MEMORY;
@@ -1060,7 +1216,7 @@ rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t
     k_fill_u32<<<1, 64, 0, st>>>(s.bounds, 0xFFFFFFFFu, 3);
     k_fill_u32<<<1, 64, 0, st>>>(s.bounds + 3, 0u, 3);
     unsigned bb = rg_blocks(n, kThreads);
-    if (bb > 1024) bb = 1024;
+    if (bb > 256) bb = 256;
     k_centre_bounds<<<bb, kThreads, 0, st>>>(prim_box, n, s.bounds);
     RG_LAUNCH_CHECK();
     k_morton<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(prim_box, n, s.bounds, s.keys, s.ids);
@@ -1103,9 +1259,9 @@ rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t
     out->ids = ia;
     rg_status r = RG_OK;
     if (nodes) {
-        if (width == 2) r = collapse<2>(s, n, leaf_max, nodes, parents, st, &out->depth, &out->n_nodes);
-        else if (width == 4) r = collapse<4>(s, n, leaf_max, nodes, parents, st, &out->depth, &out->n_nodes);
-        else r = collapse<8>(s, n, leaf_max, nodes, parents, st, &out->depth, &out->n_nodes);
+        if (width == 2) r = collapse<2>(s, n, leaf_max, nodes, parents, levels, st, &out->depth, &out->n_nodes);
+        else if (width == 4) r = collapse<4>(s, n, leaf_max, nodes, parents, levels, st, &out->depth, &out->n_nodes);
+        else r = collapse<8>(s, n, leaf_max, nodes, parents, levels, st, &out->depth, &out->n_nodes);
         if (r != RG_OK) return r;
     }
     float rb[6];
@@ -1128,7 +1284,7 @@ rg_status rg_scan_excl_u32(uint32_t *data, int64_t m, hipStream_t st) {
 namespace {
 
 uint64_t blas_out_bytes(int64_t n, int w, uint64_t *nodes_off, uint64_t *tris_off, uint64_t *mats_off,
-                        uint64_t *slots_off, uint64_t *parents_off) {
+                        uint64_t *slots_off, uint64_t *parents_off, uint64_t *levels_off) {
     int64_t max_nodes = n > 1 ? n - 1 : 1;
     uint64_t off = 256;  // header
     *nodes_off = off;
@@ -1141,6 +1297,8 @@ uint64_t blas_out_bytes(int64_t n, int w, uint64_t *nodes_off, uint64_t *tris_of
     off = align256(off + (uint64_t)n * 4u);
     *parents_off = off;
     off = align256(off + (uint64_t)max_nodes * 4u);
+    *levels_off = off;
+    off = align256(off + (uint64_t)(RG_LEVELS_CAP + 1) * 4u);
     return off;
 }
 
@@ -1171,6 +1329,7 @@ uint64_t tlas_scratch_bytes(int64_t n, int32_t n_blas, int32_t builder) {
     a.take<BlasInfo>(n_blas > 0 ? n_blas : 1);
     a.take<float>(6 * n);       // instance boxes
     a.take<RgInst>(n);          // unsorted records
+    a.take<uint32_t>(8);        // flags
     return a.used + rg_lbvh_scratch_bytes(n, builder);
 }
 
@@ -1206,8 +1365,8 @@ const char *rg_status_string(rg_status s) {
 rg_status rg_blas_sizes(int64_t n_tris, const rg_build_opts *opts, rg_sizes *out) {
     Opts o;
     if (!out || n_tris < 1 || n_tris > RG_MAX_TRIS || !opts_ok(opts, &o)) return RG_ERR_INVALID_ARG;
-    uint64_t a, b, c, d, e;
-    out->bytes = blas_out_bytes(n_tris, o.w, &a, &b, &c, &d, &e);
+    uint64_t a, b, c, d, e, f;
+    out->bytes = blas_out_bytes(n_tris, o.w, &a, &b, &c, &d, &e, &f);
     out->scratch_bytes = blas_scratch_bytes(n_tris, o.builder);
     return RG_OK;
 }
@@ -1220,8 +1379,8 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
     if (n_verts < 1 || n_verts > (1ll << 32) || n_tris < 1 || n_tris > RG_MAX_TRIS) return RG_ERR_INVALID_ARG;
     if (!opts_ok(opts, &o)) return RG_ERR_INVALID_ARG;
     const int32_t w = o.w, l = o.leaf;
-    uint64_t no, to, mo, so, po;
-    uint64_t need = blas_out_bytes(n_tris, w, &no, &to, &mo, &so, &po);
+    uint64_t no, to, mo, so, po, lvo;
+    uint64_t need = blas_out_bytes(n_tris, w, &no, &to, &mo, &so, &po, &lvo);
     if (out_bytes < need || scratch_bytes < blas_scratch_bytes(n_tris, o.builder)) return RG_ERR_OUT_OF_MEMORY;
     hipStream_t st = (hipStream_t)stream;
     RgArena arena{(char *)scratch, scratch_bytes, 0};
@@ -1236,14 +1395,15 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
     if (hflags) return RG_ERR_INVALID_ARG;
     char *base = (char *)out_buf;
     RgLbvhOut lo;
-    rg_status r = rg_lbvh_build(pbox, n_tris, w, l, o.builder, o.radius, base + no, (uint32_t *)(base + po), arena,
-                                st, &lo, false, nullptr, nullptr, nullptr, nullptr);
+    rg_status r = rg_lbvh_build(pbox, n_tris, w, l, o.builder, o.radius, base + no, (uint32_t *)(base + po),
+                                (uint32_t *)(base + lvo), arena, st, &lo, false, nullptr, nullptr, nullptr, nullptr);
     if (r != RG_OK) return r;
     k_reorder_tris<<<rg_blocks(n_tris, kThreads), kThreads, 0, st>>>(
         verts, idx, lo.ids, n_tris, prim_material, (RgTri *)(base + to), (uint16_t *)(base + mo),
         (uint32_t *)(base + so));
     k_blas_header<<<1, 1, 0, st>>>((RgBlasHdr *)base, (uint64_t)(base + no), (uint64_t)(base + to),
-                                   (uint64_t)(base + mo), (uint64_t)(base + so));
+                                   (uint64_t)(base + mo), (uint64_t)(base + so), lo.lo[0], lo.lo[1], lo.lo[2],
+                                   lo.hi[0], lo.hi[1], lo.hi[2]);
     RG_LAUNCH_CHECK();
     RG_HIP(hipStreamSynchronize(st));
     out->buf = out_buf;
@@ -1252,6 +1412,7 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
     out->mats_off = mo;
     out->slots_off = so;
     out->parents_off = po;
+    out->levels_off = lvo;
     out->n_tris = n_tris;
     out->n_nodes = lo.n_nodes;
     out->width = w;
@@ -1268,49 +1429,102 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
 rg_status rg_refit_sizes(const rg_blas *blas, uint64_t *scratch_bytes) {
     if (!blas || !scratch_bytes || blas->n_nodes < 1) return RG_ERR_INVALID_ARG;
     RgArena a{nullptr, 0, 0};
-    a.take<uint32_t>(blas->n_nodes);  // inner children per node
+    a.take<uint32_t>(blas->n_nodes);  // inner children per node (hierarchies deeper than the level table)
     a.take<uint32_t>(blas->n_nodes);  // arrivals
-    a.take<float>(8);                 // root box
-    a.take<uint32_t>(8);              // flags
     *scratch_bytes = a.used;
+    return RG_OK;
+}
+
+rg_status rg_refit_blas_many(rg_blas *blas, int32_t n_blas, const float *const *verts, const int64_t *n_verts,
+                             const uint32_t *const *idx, const int64_t *n_tris, void *scratch,
+                             uint64_t scratch_bytes, void *stream) {
+    if (!blas || !verts || !n_verts || !idx || !n_tris || n_blas < 1) return RG_ERR_INVALID_ARG;
+    const int32_t w = blas[0].width;
+    if (!(w == 2 || w == 4 || w == 8)) return RG_ERR_INVALID_ARG;
+    uint64_t scratch_need = 0;
+    for (int32_t b = 0; b < n_blas; ++b) {
+        const rg_blas &B = blas[b];
+        if (!B.buf || !verts[b] || !idx[b] || B.width != w || B.n_nodes < 1 || B.depth < 1) return RG_ERR_INVALID_ARG;
+        if (n_tris[b] != B.n_tris || n_verts[b] < 1 || n_verts[b] > (1ll << 32)) return RG_ERR_INVALID_ARG;
+        if (B.depth > RG_LEVELS_CAP) {
+            uint64_t need = 0;
+            rg_refit_sizes(&B, &need);
+            if (need > scratch_need) scratch_need = need;
+        }
+    }
+    if (scratch_need > 0 && (!scratch || scratch_bytes < scratch_need)) return RG_ERR_OUT_OF_MEMORY;
+    hipStream_t st = (hipStream_t)stream;
+    for (int32_t b0 = 0; b0 < n_blas; b0 += kRefitBatch) {
+        const int n = n_blas - b0 < kRefitBatch ? n_blas - b0 : kRefitBatch;
+        RefitJobs jobs;
+        std::memset(&jobs, 0, sizeof(jobs));
+        int64_t max_tris = 0;
+        int max_depth = 0;
+        for (int k = 0; k < n; ++k) {
+            const rg_blas &B = blas[b0 + k];
+            char *base = (char *)B.buf;
+            RefitJob &J = jobs.j[k];
+            J.nodes = base + B.nodes_off;
+            J.tris = (RgTri *)(base + B.tris_off);
+            J.levels = (const uint32_t *)(base + B.levels_off);
+            J.hdr = (RgBlasHdr *)base;
+            J.verts = verts[b0 + k];
+            J.idx = idx[b0 + k];
+            J.n_verts = n_verts[b0 + k];
+            J.n_tris = B.n_tris;
+            J.depth = B.depth <= RG_LEVELS_CAP ? B.depth : 0;  // deeper ones: refit_deep below
+            if (B.n_tris > max_tris) max_tris = B.n_tris;
+            if (J.depth > max_depth) max_depth = J.depth;
+        }
+        k_refit_begin<<<1, 64, 0, st>>>(jobs, n);
+        unsigned tb = rg_blocks(max_tris, kThreads);
+        if (tb > 1024) tb = 1024;
+        k_refit_tris<<<dim3(tb, (unsigned)n), kThreads, 0, st>>>(jobs);
+        RG_LAUNCH_CHECK();
+        // grid per level: enough blocks for the widest level of any of them
+        int64_t max_nodes = 0;
+        for (int k = 0; k < n; ++k)
+            if (blas[b0 + k].n_nodes > max_nodes) max_nodes = blas[b0 + k].n_nodes;
+        unsigned lb = rg_blocks(max_nodes, kThreads);
+        if (lb > 512) lb = 512;
+        if (max_depth > 0) {
+            if (w == 2) refit_levels<2>(jobs, n, max_depth, lb, st);
+            else if (w == 4) refit_levels<4>(jobs, n, max_depth, lb, st);
+            else refit_levels<8>(jobs, n, max_depth, lb, st);
+        }
+        RG_LAUNCH_CHECK();
+        for (int k = 0; k < n; ++k) {
+            const rg_blas &B = blas[b0 + k];
+            if (B.depth <= RG_LEVELS_CAP) continue;
+            RgArena arena{(char *)scratch, scratch_bytes, 0};
+            uint32_t *need = arena.take<uint32_t>(B.n_nodes);
+            uint32_t *arrived = arena.take<uint32_t>(B.n_nodes);
+            if (w == 2) refit_deep<2>(B, need, arrived, st);
+            else if (w == 4) refit_deep<4>(B, need, arrived, st);
+            else refit_deep<8>(B, need, arrived, st);
+            RG_LAUNCH_CHECK();
+        }
+    }
     return RG_OK;
 }
 
 rg_status rg_refit_blas(rg_blas *blas, const float *verts, int64_t n_verts, const uint32_t *idx, int64_t n_tris,
                         void *scratch, uint64_t scratch_bytes, void *stream) {
-    if (!blas || !blas->buf || !verts || !idx || !scratch) return RG_ERR_INVALID_ARG;
-    if (n_tris != blas->n_tris || n_verts < 1 || n_verts > (1ll << 32) || blas->n_nodes < 1) return RG_ERR_INVALID_ARG;
-    if (!(blas->width == 2 || blas->width == 4 || blas->width == 8)) return RG_ERR_INVALID_ARG;
-    uint64_t need_bytes = 0;
-    rg_refit_sizes(blas, &need_bytes);
-    if (scratch_bytes < need_bytes) return RG_ERR_OUT_OF_MEMORY;
+    if (!blas || !verts || !idx) return RG_ERR_INVALID_ARG;
+    return rg_refit_blas_many(blas, 1, &verts, &n_verts, &idx, &n_tris, scratch, scratch_bytes, stream);
+}
+
+rg_status rg_blas_state(const rg_blas *blas, float *lo, float *hi, uint32_t *status, void *stream) {
+    if (!blas || !blas->buf || !lo || !hi || !status) return RG_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
-    RgArena arena{(char *)scratch, scratch_bytes, 0};
-    uint32_t *need = arena.take<uint32_t>(blas->n_nodes);
-    uint32_t *arrived = arena.take<uint32_t>(blas->n_nodes);
-    float *root = arena.take<float>(8);
-    uint32_t *flags = arena.take<uint32_t>(8);
-    char *base = (char *)blas->buf;
-    RgTri *tris = (RgTri *)(base + blas->tris_off);
-    const uint32_t *parents = (const uint32_t *)(base + blas->parents_off);
-    k_fill_u32<<<1, 64, 0, st>>>(flags, 0u, 1);
-    k_refit_tris<<<rg_blocks(n_tris, kThreads), kThreads, 0, st>>>(verts, n_verts, idx, n_tris, tris, flags);
-    RG_LAUNCH_CHECK();
-    void *nodes = base + blas->nodes_off;
-    if (blas->width == 2) refit_launch<2>(nodes, blas->n_nodes, parents, tris, need, arrived, root, st);
-    else if (blas->width == 4) refit_launch<4>(nodes, blas->n_nodes, parents, tris, need, arrived, root, st);
-    else refit_launch<8>(nodes, blas->n_nodes, parents, tris, need, arrived, root, st);
-    RG_LAUNCH_CHECK();
-    float hb[6];
-    uint32_t hflags = 0;
-    RG_HIP(hipMemcpyAsync(hb, root, 24, hipMemcpyDeviceToHost, st));
-    RG_HIP(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, st));
+    RgBlasHdr h;
+    RG_HIP(hipMemcpyAsync(&h, blas->buf, sizeof(RgBlasHdr), hipMemcpyDeviceToHost, st));
     RG_HIP(hipStreamSynchronize(st));
-    if (hflags) return RG_ERR_INVALID_ARG;
     for (int k = 0; k < 3; ++k) {
-        blas->lo[k] = hb[k];
-        blas->hi[k] = hb[3 + k];
+        lo[k] = h.lo[k];
+        hi[k] = h.hi[k];
     }
+    *status = h.status;
     return RG_OK;
 }
 
@@ -1336,10 +1550,6 @@ rg_status rg_build_tlas(const rg_blas *blas, int32_t n_blas, const float *xform,
     for (int32_t b = 0; b < n_blas; ++b) {
         if (!blas[b].buf || blas[b].width != w) return RG_ERR_INVALID_ARG;
         if (blas[b].depth > max_depth) max_depth = blas[b].depth;
-        for (int k = 0; k < 3; ++k) {
-            info[b].lo[k] = blas[b].lo[k];
-            info[b].hi[k] = blas[b].hi[k];
-        }
         info[b].nodes = (uint64_t)((char *)blas[b].buf + blas[b].nodes_off);
         info[b].tris = (uint64_t)((char *)blas[b].buf + blas[b].tris_off);
         info[b].hdr = (uint64_t)blas[b].buf;
@@ -1365,21 +1575,27 @@ rg_status rg_build_tlas(const rg_blas *blas, int32_t n_blas, const float *xform,
     BlasInfo *d_info = arena.take<BlasInfo>(n_blas);
     float *d_box = arena.take<float>(6 * n_inst);
     RgInst *d_rec = arena.take<RgInst>(n_inst);
+    uint32_t *d_flags = arena.take<uint32_t>(8);
+    k_fill_u32<<<1, 64, 0, st>>>(d_flags, 0u, 1);
     RG_HIP(hipMemcpyAsync(d_xf, xform, 48 * n_inst, hipMemcpyHostToDevice, st));
     RG_HIP(hipMemcpyAsync(d_bid, blas_id, 4 * n_inst, hipMemcpyHostToDevice, st));
     RG_HIP(hipMemcpyAsync(d_mat, inst_material, 4 * n_inst, hipMemcpyHostToDevice, st));
     RG_HIP(hipMemcpyAsync(d_info, info.data(), sizeof(BlasInfo) * n_blas, hipMemcpyHostToDevice, st));
-    k_inst_setup<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(d_xf, d_bid, d_mat, d_info, n_inst, d_box, d_rec);
+    k_inst_setup<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(d_xf, d_bid, d_mat, d_info, n_inst, d_box, d_rec,
+                                                                    d_flags);
     RG_LAUNCH_CHECK();
     char *base = (char *)out_buf;
     RgLbvhOut lo;
-    rg_status r = rg_lbvh_build(d_box, n_inst, w, 1, o.builder, o.radius, base + no, nullptr, arena, st, &lo, false,
-                                nullptr, nullptr, nullptr, nullptr);
+    rg_status r = rg_lbvh_build(d_box, n_inst, w, 1, o.builder, o.radius, base + no, nullptr, nullptr, arena, st, &lo,
+                                false, nullptr, nullptr, nullptr, nullptr);
     if (r != RG_OK) return r;
     k_reorder_inst<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(d_rec, lo.ids, n_inst, (RgInst *)(base + io),
                                                                       (uint32_t *)(base + ro));
     RG_LAUNCH_CHECK();
+    uint32_t hflags = 0;
+    RG_HIP(hipMemcpyAsync(&hflags, d_flags, 4, hipMemcpyDeviceToHost, st));
     RG_HIP(hipStreamSynchronize(st));
+    if (hflags) return RG_ERR_INVALID_ARG;  // a bottom level was refitted to invalid vertex data
     out->buf = out_buf;
     out->nodes_off = no;
     out->inst_off = io;
@@ -1417,8 +1633,8 @@ rg_status rg_lbvh_stages(const float *verts, int64_t n_verts, const uint32_t *id
     RG_HIP(hipStreamSynchronize(st));
     if (hflags) return RG_ERR_INVALID_ARG;
     RgLbvhOut lo;
-    rg_status r = rg_lbvh_build(pbox, n_tris, o.w, o.leaf, o.builder, o.radius, nullptr, nullptr, arena, st, &lo,
-                                true, keys, left, right, boxes);
+    rg_status r = rg_lbvh_build(pbox, n_tris, o.w, o.leaf, o.builder, o.radius, nullptr, nullptr, nullptr, arena,
+                                st, &lo, true, keys, left, right, boxes);
     if (r != RG_OK) return r;
     RG_HIP(hipMemcpyAsync(ids, lo.ids, 4 * n_tris, hipMemcpyDeviceToDevice, st));
     RG_HIP(hipStreamSynchronize(st));

@@ -41,7 +41,11 @@ static_assert(sizeof(RgTri) == 40, "tri");
 // Header at the start of a bottom-level buffer (device addresses).
 struct RgBlasHdr {
     uint64_t nodes, tris, mats, slots;
+    float lo[3], hi[3];  // root box: written by the build and by every refit
+    uint32_t status;     // flags of the last refit's input check (0: valid)
+    uint32_t pad;
 };
+static_assert(sizeof(RgBlasHdr) == 64, "blas header");
 
 // Instance record in top-level leaf order: 112 bytes.
 struct RgInst {
@@ -125,11 +129,13 @@ struct RgLbvhOut {
     float lo[3], hi[3];
 };
 // parents (nullable): per wide node, (parent node << 3) | slot in the parent,
-// RG_MISS for the root.
+// RG_MISS for the root.  levels (nullable, RG_LEVELS_CAP + 1 entries): the
+// first node of each level and, after the last level, the node count (nodes
+// are allocated level by level); left unwritten for deeper hierarchies.
 rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t leaf_max, int32_t builder,
-                        int32_t radius, void *nodes, uint32_t *parents, RgArena &scratch, hipStream_t stream,
-                        RgLbvhOut *out, bool keep_stages, uint64_t *keys_out, int32_t *left_out,
-                        int32_t *right_out, float *boxes_out);
+                        int32_t radius, void *nodes, uint32_t *parents, uint32_t *levels, RgArena &scratch,
+                        hipStream_t stream, RgLbvhOut *out, bool keep_stages, uint64_t *keys_out,
+                        int32_t *left_out, int32_t *right_out, float *boxes_out);
 uint64_t rg_lbvh_scratch_bytes(int64_t n, int32_t builder);
 
 // In-place exclusive prefix sum of m uint32 values (one workgroup).

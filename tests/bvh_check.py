@@ -54,7 +54,7 @@ def walk(lo, hi, child, n_prims: int, leaf_boxes, max_leaf: int):
     return max_depth, seen_prim
 
 
-def check_blas(buf: np.ndarray, desc) -> dict:
+def check_blas(buf: np.ndarray, desc, refitted: bool = False) -> dict:
     W = desc.width
     lo, hi, child = _nodes(buf, desc.nodes_off, desc.n_nodes, W)
     n = desc.n_tris
@@ -67,15 +67,21 @@ def check_blas(buf: np.ndarray, desc) -> dict:
     assert np.array_equal(np.sort(prim), np.arange(n, dtype=np.uint32)), "leaf order is a permutation"
     slots = buf[desc.slots_off: desc.slots_off + 4 * n].view(np.uint32)
     assert np.array_equal(slots[prim], np.arange(n, dtype=np.uint32)), "slots invert the leaf order"
-    # the root box is the union of the triangles
-    assert np.allclose(np.array(desc.lo), v.reshape(-1, 3).min(axis=0), atol=0)
-    assert np.allclose(np.array(desc.hi), v.reshape(-1, 3).max(axis=0), atol=0)
+    # the root box in the header (kept current by refits) is the union of the
+    # triangles, and so is the descriptor's unless the level was refitted
+    root = buf[32:56].view(np.float32)
+    assert np.array_equal(root[:3], v.reshape(-1, 3).min(axis=0))
+    assert np.array_equal(root[3:], v.reshape(-1, 3).max(axis=0))
+    assert buf[56:60].view(np.uint32)[0] == 0, "status of the last refit"
+    if not refitted:
+        assert np.array_equal(np.array(desc.lo, np.float32), root[:3])
+        assert np.array_equal(np.array(desc.hi, np.float32), root[3:])
     hdr = buf[0:32].view(np.uint64)
     return dict(depth=depth, n_nodes=desc.n_nodes, prim=prim, verts=v, tri_mats=buf[
         desc.mats_off: desc.mats_off + 2 * n].view(np.uint16), header=hdr)
 
 
-def check_tlas(buf: np.ndarray, desc, blas_descs, xform) -> dict:
+def check_tlas(buf: np.ndarray, desc, blas_descs, xform, roots=None) -> dict:
     W = desc.width
     lo, hi, child = _nodes(buf, desc.nodes_off, desc.n_nodes, W)
     n = desc.n_inst
@@ -106,11 +112,14 @@ def check_tlas(buf: np.ndarray, desc, blas_descs, xform) -> dict:
         inv = recf[r, 0:9].reshape(3, 3).astype(np.float64)
         assert np.allclose(inv @ X[i, :, :3], np.eye(3), atol=1e-5)
         assert np.array_equal(recf[r, 9:12], X[i, :, 3].astype(np.float32))
-    # each record carries its bottom level's root box
-    by_nodes = {int(b.buf) + int(b.nodes_off): b for b in blas_descs}
+    # each record carries its bottom level's root box (the current one, from
+    # roots, after refits; else the descriptor's)
+    if roots is None:
+        roots = [(b.lo, b.hi) for b in blas_descs]
+    by_nodes = {int(b.buf) + int(b.nodes_off): rb for b, rb in zip(blas_descs, roots)}
     rec_nodes = rec.view(np.uint64).reshape(n, 14)[:, 6]
     for r in range(n):
-        b = by_nodes[int(rec_nodes[r])]
-        assert np.array_equal(recf[r, 20:23], np.array(b.lo, np.float32))
-        assert np.array_equal(recf[r, 23:26], np.array(b.hi, np.float32))
+        rlo, rhi = by_nodes[int(rec_nodes[r])]
+        assert np.array_equal(recf[r, 20:23], np.array(rlo, np.float32))
+        assert np.array_equal(recf[r, 23:26], np.array(rhi, np.float32))
     return dict(depth=depth, inst=inst, boxes=(boxes_lo, boxes_hi))

@@ -125,7 +125,19 @@ def test_null_pointer_calls_are_rejected_on_the_host():
     assert lib.rg_refit_sizes(None, ctypes.byref(need)) == -1
     assert lib.rg_refit_blas(ctypes.byref(fake), None, 3, None, 150, None, 0, None) == -1
     assert lib.rg_refit_blas(ctypes.byref(fake), 256, 3, 256, 149, 256, 1 << 20, None) == -1
+    assert lib.rg_refit_blas(ctypes.byref(fake), 256, 3, 256, 150, 256, 16, None) == -1   # depth 0
+    fake.depth = 300      # deeper than the level table: needs scratch for the counters
     assert lib.rg_refit_blas(ctypes.byref(fake), 256, 3, 256, 150, 256, 16, None) == -2
+    assert lib.rg_refit_blas(ctypes.byref(fake), 256, 3, 256, 150, None, 0, None) == -2
+    other = rg.BlasDesc()
+    other.buf, other.width, other.n_nodes, other.n_tris, other.depth = 256, 4, 10, 10, 3
+    two = (rg.BlasDesc * 2)(fake, other)
+    ptrs = (ctypes.c_void_p * 2)(256, 256)
+    nv = (ctypes.c_int64 * 2)(3, 3)
+    nt = (ctypes.c_int64 * 2)(150, 10)
+    assert lib.rg_refit_blas_many(two, 2, ptrs, nv, ptrs, nt, None, 0, None) == -1    # mixed widths
+    f3 = (ctypes.c_float * 3)()
+    assert lib.rg_blas_state(None, f3, f3, ctypes.byref(need), None) == -1
 
 
 def test_undersized_buffers_are_rejected():

@@ -32,10 +32,11 @@ def test_refit_to_unchanged_vertices_reproduces_the_build(builder, width, leaf):
     b = rg.build_blas(v, i, None, width, leaf, builder=builder)
     before = b.buf.cpu().numpy().copy()
     lo, hi = list(b.desc.lo), list(b.desc.hi)
+    assert rg.blas_state(b) == (lo, hi, 0)
     rg.refit_blas(b, v, i)
     after = b.buf.cpu().numpy()
-    assert np.array_equal(before, after)
-    assert list(b.desc.lo) == lo and list(b.desc.hi) == hi
+    assert np.array_equal(before, after)      # header (root box, status) included
+    assert rg.blas_state(b) == (lo, hi, 0)
 
 
 @pytest.mark.parametrize("width,leaf", [(2, 1), (4, 1), (8, 4)])
@@ -50,9 +51,12 @@ def test_refit_to_moved_vertices_holds_the_new_mesh(width, leaf):
     b = rg.build_blas(v0, i, None, width, leaf)
     v1, _ = _dev(moved.verts, moved.idx)
     rg.refit_blas(b, v1, i)
-    info = bvh_check.check_blas(b.buf.cpu().numpy(), b.desc)
+    info = bvh_check.check_blas(b.buf.cpu().numpy(), b.desc, refitted=True)
     assert np.array_equal(info["verts"], moved.verts[moved.idx[info["prim"]]])
-    assert np.allclose(b.desc.lo, moved.verts.min(axis=0)) and np.allclose(b.desc.hi, moved.verts.max(axis=0))
+    lo, hi, status = rg.blas_state(b)
+    assert status == 0
+    assert np.array_equal(np.float32(lo), moved.verts.min(axis=0)) and np.array_equal(np.float32(hi),
+                                                                                     moved.verts.max(axis=0))
     # trace through a top level built over the refitted bottom level
     tl = rg.build_tlas([b], sg.identity_xform(1), [0], [0], width)
     rng = np.random.default_rng(7)
@@ -88,8 +92,9 @@ def test_refitted_scene_traces_like_a_fresh_build():
                            sc.width, sc.height, sc.max_depth, sc.mode, sc.seed)
     tl_fresh = rg.upload_scene(fresh_scene, 4, 1)
     for b in tl_refit.blas:
-        bvh_check.check_blas(b.buf.cpu().numpy(), b.desc)
-    bvh_check.check_tlas(tl_refit.buf.cpu().numpy(), tl_refit.desc, [b.desc for b in tl_refit.blas], xf)
+        bvh_check.check_blas(b.buf.cpu().numpy(), b.desc, refitted=True)
+    roots = [rg.blas_state(b)[:2] for b in tl_refit.blas]
+    bvh_check.check_tlas(tl_refit.buf.cpu().numpy(), tl_refit.desc, [b.desc for b in tl_refit.blas], xf, roots)
     cam = rg.camera_rays(sc.camera, sc.width, sc.height).cpu().numpy().T.copy()
     rays = rg.rays_to_device(np.concatenate([cam, sg.random_rays(8000, 12, extent=22.0)]))
     h1 = parity.hits_to_numpy(rg.trace_closest(tl_refit, rays))
@@ -105,6 +110,45 @@ def test_refitted_scene_traces_like_a_fresh_build():
     print(parity.check_image(img.cpu().numpy().reshape(-1, 3)[px], ref, 0.04, "refit render"), flush=True)
 
 
+@pytest.mark.parametrize("width", [2, 4, 8])
+def test_refit_many_equals_one_by_one(width):
+    """Bottom levels of different sizes and depths refitted in one call: every
+    buffer (nodes, triangles, header) equals a refit of that level alone."""
+    import paper_2001_09792_amd as rg
+    meshes = [sg.torus(64, 48, 1.0, 0.35, 0.08, 6.0, 3003), sg.icosphere(2), sg.random_soup(5000, 4),
+              sg.triangles_mesh([[(0, 0, 0), (1, 0, 0), (0, 1, 0)]])]
+    print(f"[refit many] W{width}", flush=True)
+    dev = [_dev(m.verts, m.idx) for m in meshes]
+    moved = [_dev(sg.animate_mesh(m, 0.2, amp=0.05, seed=k), m.idx)[0] for k, m in enumerate(meshes)]
+    one = [rg.build_blas(v, i, None, width, 2) for v, i in dev]
+    # byte copies of the same builds (two builds of one mesh number their nodes
+    # in whatever order the collapse's threads claim them)
+    many = []
+    for b in one:
+        buf = b.buf.clone()
+        d = rg.BlasDesc.from_buffer_copy(b.desc)
+        d.buf = buf.data_ptr()
+        many.append(rg.Blas(buf, d))
+    for b, v, (_, i) in zip(one, moved, dev):
+        rg.refit_blas(b, v, i)
+    rg.refit_blas_many(many, moved, [i for _, i in dev])
+    def content(b):
+        # the arrays and the header's root box and status; not the header's
+        # device addresses, nor the alignment padding between arrays
+        buf, d = b.buf.cpu().numpy(), b.desc
+        return (buf[32:64], buf[d.nodes_off: d.nodes_off + d.n_nodes * 32 * d.width],
+                buf[d.tris_off: d.tris_off + 40 * d.n_tris])
+    for m, (a, b) in enumerate(zip(one, many)):
+        bvh_check.check_blas(a.buf.cpu().numpy(), a.desc, refitted=True)
+        bvh_check.check_blas(b.buf.cpu().numpy(), b.desc, refitted=True)
+        for part, x, y in zip(("header", "nodes", "triangles"), content(a), content(b)):
+            bad = np.nonzero(x != y)[0]
+            if bad.size:
+                print(f"mesh {m} ({a.desc.n_tris} tris, depth {a.desc.depth}): {part} differs at {bad.size} "
+                      f"bytes, first {bad[:8]}", flush=True)
+            assert bad.size == 0
+
+
 def test_refit_errors():
     import torch
     import paper_2001_09792_amd as rg
@@ -115,9 +159,17 @@ def test_refit_errors():
         rg.refit_blas(b, v, i[:100])          # other triangle count
     bad = v.clone()
     bad[7, 0] = float("inf")
+    rg.refit_blas(b, bad, i)                  # found on the device: recorded, reported by the top level
+    assert rg.blas_state(b)[2] != 0
     with pytest.raises(rg.RgError):
-        rg.refit_blas(b, bad, i)
-    # a valid refit afterwards restores the structure
+        rg.build_tlas([b], sg.identity_xform(1), [0], [0])
+    bad_i = i.clone()
+    bad_i[5, 1] = 10 ** 6
+    rg.refit_blas(b, v, bad_i)                # an index out of range: never read, recorded
+    assert rg.blas_state(b)[2] != 0
+    # a valid refit afterwards restores the structure and clears the status
     rg.refit_blas(b, v, i)
+    assert rg.blas_state(b)[2] == 0
     bvh_check.check_blas(b.buf.cpu().numpy(), b.desc)
+    rg.build_tlas([b], sg.identity_xform(1), [0], [0])
     torch.cuda.synchronize()
