@@ -36,6 +36,9 @@ _lib = None
 
 MISS = 0xFFFFFFFF
 MAX_TIES = 16
+# ray visibility / facing (rg_oracle.c)
+RAY_CULL_BACK, RAY_CULL_FRONT = 1, 2
+INST_CULL_DISABLE, INST_FLIP_FACING = 1 << 8, 1 << 9
 
 
 def build(force: bool = True) -> str:
@@ -65,7 +68,9 @@ def _load():
         lib.or_set_sphere_reject.argtypes = [P, i32]
         lib.or_set_materials.argtypes = [P, P, i32]
         lib.or_trace.restype = i64
-        lib.or_trace.argtypes = [P, P, i64, i32, i32, P, P, P, P, P, P, P, P, P, P, P, P, i32]
+        lib.or_trace.argtypes = [P, P, i64, i32, i32, P, P, P, P, P, P, P, P, P, P, P, P, i32, P,
+                                 ctypes.c_uint32, ctypes.c_uint32]
+        lib.or_set_inst_flags.argtypes = [P, P]
         lib.or_camera_rays.argtypes = [P, i32, i32, P, i64, P]
         lib.or_ao_uniforms.argtypes = [u64, u64, P, P]
         lib.or_ao_direction.argtypes = [P, ctypes.c_double, ctypes.c_double, P]
@@ -98,7 +103,9 @@ def light_array(light) -> np.ndarray:
 class Scene:
     """FP64 oracle view of a `scenegen.Scene` (or of explicit arrays)."""
 
-    def __init__(self, scene, sphere_reject: bool = False):
+    def __init__(self, scene, sphere_reject: bool = False, inst_flags=None):
+        """inst_flags: uint32 per instance (bits 0-7 visibility mask,
+        INST_CULL_DISABLE, INST_FLIP_FACING), default 0xFF."""
         lib = _load()
         self._lib = lib
         self.scene = scene
@@ -123,6 +130,10 @@ class Scene:
         self._mats = np.ascontiguousarray(scene.materials)
         lib.or_set_materials(self.h, _ptr(self._mats), len(self._mats))
         lib.or_set_sphere_reject(self.h, 1 if sphere_reject else 0)
+        if inst_flags is not None:
+            self._flags = np.ascontiguousarray(inst_flags, np.uint32)
+            assert self._flags.shape == (self._xf.shape[0],)
+            lib.or_set_inst_flags(self.h, _ptr(self._flags))
 
     def set_sphere_reject(self, on: bool):
         self._lib.or_set_sphere_reject(self.h, 1 if on else 0)
@@ -133,10 +144,12 @@ class Scene:
             self._lib.or_scene_free(h)
             self.h = None
 
-    def trace(self, rays: np.ndarray, any_hit: bool = False, threads: int = 0) -> dict:
+    def trace(self, rays: np.ndarray, any_hit: bool = False, threads: int = 0, ray_mask=None, mask: int = 0xFF,
+              cull: int = 0) -> dict:
         """rays f32[N,8].  Returns dict of per-ray arrays (t, u, v, inst,
         prim, hit, amb, beta, delta, nties, ties[N,16,2], ties_tuv[N,16,3], tests);
-        beta / delta are the float32 error bands of the hit's barycentrics / t."""
+        beta / delta are the float32 error bands of the hit's barycentrics / t.
+        ray_mask: uint8 per ray (else `mask` for every ray); cull: RAY_CULL_*."""
         rays = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
         n = rays.shape[0]
         out = dict(t=np.empty(n), u=np.empty(n), v=np.empty(n), beta=np.empty(n), delta=np.empty(n),
@@ -144,13 +157,15 @@ class Scene:
                    hit=np.empty(n, np.uint8), amb=np.empty(n, np.uint8),
                    nties=np.empty(n, np.int32), ties=np.zeros((n, MAX_TIES, 2), np.uint32),
                    ties_tuv=np.zeros((n, MAX_TIES, 3)))
+        rm = np.ascontiguousarray(ray_mask, np.uint8).reshape(n) if ray_mask is not None else None
         tests = self._lib.or_trace(self.h, _ptr(rays), n, 1 if any_hit else 0,
                                    threads or default_threads(),
                                    _ptr(out["t"]), _ptr(out["u"]), _ptr(out["v"]), _ptr(out["beta"]),
                                    _ptr(out["delta"]),
                                    _ptr(out["inst"]), _ptr(out["prim"]), _ptr(out["hit"]),
                                    _ptr(out["amb"]), _ptr(out["nties"]), _ptr(out["ties"]),
-                                   _ptr(out["ties_tuv"]), MAX_TIES)
+                                   _ptr(out["ties_tuv"]), MAX_TIES,
+                                   _ptr(rm) if rm is not None else None, mask, cull)
         out["tests"] = int(tests)
         return out
 

@@ -68,7 +68,20 @@ typedef struct {
     double wlo[3], whi[3]; /* world box of the transformed mesh box */
     int32_t blas;
     uint32_t mat;
+    uint32_t flags; /* bits 0-7 visibility mask, OR_INST_CULL_DISABLE, OR_INST_FLIP_FACING */
 } or_inst;
+
+/* Ray visibility and facing (the accept / ignore semantics of an any-hit
+ * stage, in the form of the RTX / Vulkan instance masks and cull flags): an
+ * instance is seen by a ray only if its 8-bit mask and the ray's share a bit;
+ * a triangle faces the ray when the ray travels against its winding normal
+ * (e1 x e2) in object space, inverted for instances flagged FLIP_FACING;
+ * CULL_BACK / CULL_FRONT ignore triangles that face away from / towards the
+ * ray, except in instances flagged CULL_DISABLE. */
+#define OR_RAY_CULL_BACK 1u
+#define OR_RAY_CULL_FRONT 2u
+#define OR_INST_CULL_DISABLE (1u << 8)
+#define OR_INST_FLIP_FACING (1u << 9)
 
 typedef struct {
     int32_t type;
@@ -201,6 +214,7 @@ or_scene *or_scene_new(int32_t n_blas, const int64_t *vert_off, const int64_t *t
         I->inv_fro = sqrt(f);
         I->blas = (int32_t)blas_id[i];
         I->mat = inst_mat[i];
+        I->flags = 0xFFu;
         const or_blas *B = &s->blas[I->blas];
         for (int k = 0; k < 3; ++k) { I->wlo[k] = INFINITY; I->whi[k] = -INFINITY; }
         for (int c = 0; c < 8; ++c) {
@@ -291,6 +305,22 @@ void or_scene_free(or_scene *s) {
 }
 
 void or_set_sphere_reject(or_scene *s, int32_t on) { s->sphere_reject = on; }
+
+/* Per-instance visibility mask and facing flags (default: mask 0xFF, none). */
+void or_set_inst_flags(or_scene *s, const uint32_t *flags) {
+    for (int64_t i = 0; i < s->ni; ++i) s->inst[i].flags = flags[i];
+}
+
+/* Whether triangle T of instance I is ignored by a ray with cull flags
+ * `cull` travelling along object-space d. */
+static inline int culled(const or_inst *I, uint32_t cull, const double *T, const double d[3]) {
+    if (!(cull & (OR_RAY_CULL_BACK | OR_RAY_CULL_FRONT)) || (I->flags & OR_INST_CULL_DISABLE)) return 0;
+    double n[3];
+    v_cross(n, T + 3, T + 6);
+    int front = v_dot(d, n) < 0.0;
+    if (I->flags & OR_INST_FLIP_FACING) front = !front;
+    return front ? (cull & OR_RAY_CULL_FRONT) != 0 : (cull & OR_RAY_CULL_BACK) != 0;
+}
 
 /* materials: type i32, rgb f32[3], ior f32 -> 20-byte records */
 void or_set_materials(or_scene *s, const void *rows, int32_t n) {
@@ -512,7 +542,8 @@ static void add_tie(or_result *res, uint32_t i, uint32_t j, const tri_eval_t *e)
  * unambiguous; any-hit always allows it, closest hit only where either of
  * the two triangles is an acceptable answer (not when flat shading depends
  * on which one is hit). */
-static void or_trace_one(const or_scene *S, const or_ray *R, int any, int cover, or_result *res) {
+static void or_trace_one(const or_scene *S, const or_ray *R, int any, int cover, uint32_t mask, uint32_t cull,
+                         or_result *res) {
     memset(res, 0, sizeof(*res));
     res->t = INFINITY;
     res->inst = res->prim = OR_MISS;
@@ -522,6 +553,7 @@ static void or_trace_one(const or_scene *S, const or_ray *R, int any, int cover,
     for (int64_t i = 0; i < S->ni; ++i) {
         const or_inst *I = &S->inst[i];
         const or_blas *B = &S->blas[I->blas];
+        if (((I->flags & 0xFFu) & mask) == 0u) continue;
         double o[3], d[3];
         xf_point(I->inv, R->o, o);
         xf_vec(I->inv, R->d, d);
@@ -532,6 +564,7 @@ static void or_trace_one(const or_scene *S, const or_ray *R, int any, int cover,
             if (!mt64(B->tri + 9 * j, o, d, &t, &u, &v, &det)) continue;
             if (u < 0.0 || v < 0.0 || 1.0 - u - v < 0.0) continue;
             if (t < R->tmin || t > R->tmax) continue;
+            if (culled(I, cull, B->tri + 9 * j, d)) continue;
             if (t < res->t) {
                 res->hit = 1; res->t = t; res->u = u; res->v = v;
                 res->inst = (uint32_t)i; res->prim = (uint32_t)j;
@@ -547,6 +580,7 @@ static void or_trace_one(const or_scene *S, const or_ray *R, int any, int cover,
     for (int64_t i = 0; i < S->ni; ++i) {
         const or_inst *I = &S->inst[i];
         const or_blas *B = &S->blas[I->blas];
+        if (((I->flags & 0xFFu) & mask) == 0u) continue;
         double o[3], d[3];
         xf_point(I->inv, R->o, o);
         xf_vec(I->inv, R->d, d);
@@ -564,6 +598,14 @@ static void or_trace_one(const or_scene *S, const or_ray *R, int any, int cover,
             if (!tri_eval(B->tri + 9 * j, &F, &e)) continue;
             if (!e.near) continue; /* robustly missed: no band can reach it */
             double t = e.t, m = e.m, beta = e.beta, delta = e.delta;
+            if (culled(I, cull, B->tri + 9 * j, d)) {
+                /* a float32 test may decide the facing of a nearly grazing
+                 * triangle the other way: ambiguous if it could be the hit */
+                if (e.cosg < 1e-3 && m >= -beta && t >= R->tmin - delta &&
+                    (any || t <= tlim * (1.0 + 1e-5) + delta))
+                    res->amb = 1;
+                continue;
+            }
             double tmax_band = fin_tmax ? fmax(1e-5 * R->tmax, delta) : 0.0;
             if (!any) {
                 int in_range = (t >= R->tmin - delta) && (t <= tlim * (1.0 + 1e-5) + delta);
@@ -655,6 +697,8 @@ typedef struct {
     double *ties_tuv; /* [N][max_ties][3] */
     int32_t max_ties;
     int64_t tests;
+    const uint8_t *ray_mask; /* per ray, or NULL: `mask` for all */
+    uint32_t mask, cull;
 } trace_ctx;
 
 static void trace_task(void *vctx, int64_t r) {
@@ -665,7 +709,7 @@ static void trace_task(void *vctx, int64_t r) {
     R.tmin = q[6]; R.tmax = q[7];
     R.sig_pos = R.sig_dir = 0.0;
     or_result res;
-    or_trace_one(c->S, &R, c->any, 1, &res);
+    or_trace_one(c->S, &R, c->any, 1, c->ray_mask ? c->ray_mask[r] : c->mask, c->cull, &res);
     c->t[r] = res.t; c->u[r] = res.u; c->v[r] = res.v; c->beta[r] = res.beta; c->delta[r] = res.delta;
     c->inst[r] = res.inst; c->prim[r] = res.prim;
     c->hit[r] = (uint8_t)res.hit; c->amb[r] = (uint8_t)res.amb;
@@ -687,10 +731,10 @@ static void trace_task(void *vctx, int64_t r) {
 int64_t or_trace(or_scene *S, const float *rays, int64_t n, int32_t any, int32_t nthreads,
                  double *t, double *u, double *v, double *beta, double *delta, uint32_t *inst,
                  uint32_t *prim, uint8_t *hit, uint8_t *amb, int32_t *nties, uint32_t *ties,
-                 double *ties_tuv, int32_t max_ties) {
+                 double *ties_tuv, int32_t max_ties, const uint8_t *ray_mask, uint32_t mask, uint32_t cull) {
     ensure_adjacency(S);
     trace_ctx c = {S, rays, any, t, u, v, beta, delta, inst, prim, hit, amb, nties, ties, ties_tuv,
-                   max_ties, 0};
+                   max_ties, 0, ray_mask, mask, cull};
     pool_run(trace_task, &c, n, nthreads);
     S->tests += c.tests;
     return c.tests;
@@ -826,7 +870,7 @@ static void radiance(render_ctx *C, const or_ray *R, int k, double out[3], int *
                      int64_t *tests) {
     const or_scene *S = C->S;
     or_result h;
-    or_trace_one(S, R, 0, 0, &h);
+    or_trace_one(S, R, 0, 0, 0xFFu, 0u, &h);
     ++*nrays;
     *tests += h.tests;
     if (h.amb) *amb = 1;
@@ -856,7 +900,7 @@ static void radiance(render_ctx *C, const or_ray *R, int k, double out[3], int *
             sr.tmax = 1.0 - 1e-4;
             child_sigma(R, &h, &g, 1.0, 1.0, &sr);
             or_result sh;
-            or_trace_one(S, &sr, 1, 1, &sh);
+            or_trace_one(S, &sr, 1, 1, 0xFFu, 0u, &sh);
             ++*nrays;
             *tests += sh.tests;
             if (sh.amb) *amb = 1;
@@ -918,7 +962,7 @@ static void ao_pixel(render_ctx *C, const or_ray *R, int64_t pixel, double out[3
                      int64_t *nrays, int64_t *tests) {
     const or_scene *S = C->S;
     or_result h;
-    or_trace_one(S, R, 0, 0, &h);
+    or_trace_one(S, R, 0, 0, 0xFFu, 0u, &h);
     ++*nrays;
     *tests += h.tests;
     if (h.amb) *amb = 1;
@@ -941,7 +985,7 @@ static void ao_pixel(render_ctx *C, const or_ray *R, int64_t pixel, double out[3
         child_sigma(R, &h, &g, 0.0, 1.0, &ar);
         ar.sig_dir += 8.0 * OR_K * OR_EPS32; /* float32 sin/cos/sqrt of the sample */
         or_result sh;
-        or_trace_one(S, &ar, 1, 1, &sh);
+        or_trace_one(S, &ar, 1, 1, 0xFFu, 0u, &sh);
         ++*nrays;
         *tests += sh.tests;
         if (sh.amb) *amb = 1;
@@ -1004,7 +1048,7 @@ static void aorays_task(void *vctx, int64_t r) {
     R.tmin = q[6]; R.tmax = q[7];
     R.sig_pos = R.sig_dir = 0.0;
     or_result h;
-    or_trace_one(c->S, &R, 0, 0, &h);
+    or_trace_one(c->S, &R, 0, 0, 0xFFu, 0u, &h);
     c->hit[r] = (uint8_t)h.hit;
     c->amb[r] = (uint8_t)h.amb;
     if (!h.hit) return;
