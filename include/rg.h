@@ -137,7 +137,8 @@ typedef struct {
     void *buf;
     uint64_t nodes_off, inst_off, rec_off;
     int64_t n_inst, n_nodes;
-    int32_t width, depth, max_blas_depth, reserved;
+    int32_t width, depth, max_blas_depth;
+    int32_t has_inst_flags; /* 1 when some instance carries flags other than RG_INST_MASK_ALL */
     float lo[3], hi[3]; /* world box */
 } rg_tlas;
 
@@ -261,6 +262,22 @@ rg_status rg_build_tlas(const rg_blas *blas, int32_t n_blas, const float *xform,
                         const rg_build_opts *opts, void *out_buf, uint64_t out_bytes,
                         void *scratch, uint64_t scratch_bytes, void *stream, rg_tlas *out /*host*/);
 
+/* Top level with per-instance flags (host uint32[n_inst], nullable: every
+ * instance RG_INST_MASK_ALL): bits 0-7 the visibility mask (a ray sees the
+ * instance only if its own mask shares a bit with it; a mask of 0 hides the
+ * instance from every ray, the render's included), RG_INST_CULL_DISABLE (face
+ * culling never applies to its triangles), RG_INST_FLIP_FACING (front and back
+ * exchange).  Other bits set: RG_ERR_INVALID_ARG.  Otherwise as
+ * rg_build_tlas, which is this call with NULL. */
+#define RG_INST_MASK_ALL 0xFFu
+#define RG_INST_CULL_DISABLE (1u << 8)
+#define RG_INST_FLIP_FACING (1u << 9)
+rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xform,
+                           const uint32_t *blas_id, const uint32_t *inst_material,
+                           const uint32_t *inst_flags /*host, nullable*/, int64_t n_inst,
+                           const rg_build_opts *opts, void *out_buf, uint64_t out_bytes,
+                           void *scratch, uint64_t scratch_bytes, void *stream, rg_tlas *out /*host*/);
+
 /* ---------------------------------------------------------- tracing */
 /* Closest hit for n rays.  Asynchronous.
  * Errors: RG_ERR_INVALID_ARG for NULL tlas/ray pointers or n < 0 (n == 0 is
@@ -273,6 +290,31 @@ rg_status rg_trace_closest(const rg_tlas *tlas, rg_rays rays, int64_t n, rg_hits
  * Asynchronous.  Errors as rg_trace_closest. */
 rg_status rg_trace_any(const rg_tlas *tlas, rg_rays rays, int64_t n, uint8_t *occluded,
                        const rg_hits *found /*host struct, nullable*/, void *stream);
+
+/* Ray visibility and facing for the *_ex trace calls: the accept / ignore
+ * decisions an any-hit stage makes in the paper's RTX model, in the form of
+ * instance masks and cull flags.  A triangle faces the ray when the ray
+ * travels against its winding normal (e1 x e2, e1 = v1 - v0, e2 = v2 - v0) in
+ * the instance's object space (so a mirroring instance does not flip it;
+ * RG_INST_FLIP_FACING does).  RG_RAY_CULL_BACK ignores triangles facing away
+ * from the ray, RG_RAY_CULL_FRONT those facing it, except in instances flagged
+ * RG_INST_CULL_DISABLE.  mask: the visibility mask of every ray (low 8 bits)
+ * unless ray_mask (device uint8 per ray) is given.  NULL opts: no culling,
+ * mask RG_INST_MASK_ALL (the plain calls).  Unknown flag bits or a mask above
+ * 0xFF: RG_ERR_INVALID_ARG, checked on the host before anything is launched;
+ * otherwise errors as the plain calls. */
+#define RG_RAY_CULL_BACK 1u
+#define RG_RAY_CULL_FRONT 2u
+typedef struct {
+    uint32_t flags;          /* RG_RAY_CULL_* */
+    uint32_t mask;
+    const uint8_t *ray_mask; /* device, nullable */
+} rg_trace_opts;
+rg_status rg_trace_closest_ex(const rg_tlas *tlas, rg_rays rays, int64_t n, rg_hits out,
+                              const rg_trace_opts *opts /*host, nullable*/, void *stream);
+rg_status rg_trace_any_ex(const rg_tlas *tlas, rg_rays rays, int64_t n, uint8_t *occluded,
+                          const rg_hits *found /*host struct, nullable*/,
+                          const rg_trace_opts *opts /*host, nullable*/, void *stream);
 
 /* Visit counts per ray of the same traversal (closest if any_hit == 0):
  * counts uint32[n][3] = inner nodes, triangles, instances visited.  Used to
@@ -379,6 +421,7 @@ typedef struct {
     int32_t n_jobs, width, max_depth, n_mats;
     int64_t total_pixels, capacity;
     int64_t cap_at[RG_MAX_DEPTH + 1]; /* queue bound per depth */
+    int32_t has_inst_flags, reserved; /* some frame's top level carries instance flags */
 } rg_batch;
 
 /* Scratch bytes for a batch (host call).  Errors: RG_ERR_INVALID_ARG for a

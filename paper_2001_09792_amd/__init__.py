@@ -32,6 +32,7 @@ c_f = ctypes.c_float
 c_i32 = ctypes.c_int32
 c_i64 = ctypes.c_int64
 c_u64 = ctypes.c_uint64
+c_u32 = ctypes.c_uint32
 c_p = ctypes.c_void_p
 
 
@@ -53,11 +54,15 @@ class BlasDesc(ctypes.Structure):
 class TlasDesc(ctypes.Structure):
     _fields_ = [("buf", c_p), ("nodes_off", c_u64), ("inst_off", c_u64), ("rec_off", c_u64),
                 ("n_inst", c_i64), ("n_nodes", c_i64), ("width", c_i32), ("depth", c_i32),
-                ("max_blas_depth", c_i32), ("reserved", c_i32), ("lo", c_f * 3), ("hi", c_f * 3)]
+                ("max_blas_depth", c_i32), ("has_inst_flags", c_i32), ("lo", c_f * 3), ("hi", c_f * 3)]
 
 
 class Rays(ctypes.Structure):
     _fields_ = [(k, c_p) for k in ("ox", "oy", "oz", "dx", "dy", "dz", "tmin", "tmax")]
+
+
+class TraceOpts(ctypes.Structure):
+    _fields_ = [("flags", c_u32), ("mask", c_u32), ("ray_mask", c_p)]
 
 
 class Hits(ctypes.Structure):
@@ -90,7 +95,7 @@ class Job(ctypes.Structure):
 class BatchDesc(ctypes.Structure):
     _fields_ = [("scratch", c_p), ("scratch_bytes", c_u64), ("n_jobs", c_i32), ("width", c_i32),
                 ("max_depth", c_i32), ("n_mats", c_i32), ("total_pixels", c_i64), ("capacity", c_i64),
-                ("cap_at", c_i64 * (MAX_DEPTH + 1))]
+                ("cap_at", c_i64 * (MAX_DEPTH + 1)), ("has_inst_flags", c_i32), ("reserved", c_i32)]
 
 
 class RenderStats(ctypes.Structure):
@@ -123,6 +128,9 @@ SIGNATURES = {
     "rg_build_tlas": (c_i32, [c_p, c_i32, c_p, c_p, c_p, c_i64, c_p, c_p, c_u64, c_p, c_u64, c_p, c_p]),
     "rg_trace_closest": (c_i32, [c_p, Rays, c_i64, Hits, c_p]),
     "rg_trace_any": (c_i32, [c_p, Rays, c_i64, c_p, c_p, c_p]),
+    "rg_trace_closest_ex": (c_i32, [c_p, Rays, c_i64, Hits, c_p, c_p]),
+    "rg_trace_any_ex": (c_i32, [c_p, Rays, c_i64, c_p, c_p, c_p, c_p]),
+    "rg_build_tlas_ex": (c_i32, [c_p, c_i32, c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_u64, c_p, c_u64, c_p, c_p]),
     "rg_trace_counts": (c_i32, [c_p, Rays, c_i64, c_i32, c_p, c_p]),
     "rg_trace_tuning": (c_i32, [c_i32, c_p, c_p]),
     "rg_camera_rays": (c_i32, [c_p, c_i32, c_i32, c_p, c_p]),
@@ -323,8 +331,10 @@ class Tlas:
 
 
 def build_tlas(blas: Sequence[Blas], xform, blas_id, inst_mat, width: int = 4, stream=None,
-               scratch=None, builder: str = "lbvh", radius: int = 0) -> Tlas:
-    """xform: host float32 [I,3,4]; blas_id, inst_mat: host uint32 [I]."""
+               scratch=None, builder: str = "lbvh", radius: int = 0, inst_flags=None) -> Tlas:
+    """xform: host float32 [I,3,4]; blas_id, inst_mat: host uint32 [I];
+    inst_flags: host uint32 [I] (visibility mask in bits 0-7,
+    INST_CULL_DISABLE, INST_FLIP_FACING) or None (all visible)."""
     torch = _torch()
     xform = np.ascontiguousarray(xform, np.float32).reshape(-1, 12)
     blas_id = np.ascontiguousarray(blas_id, np.uint32)
@@ -339,8 +349,10 @@ def build_tlas(blas: Sequence[Blas], xform, blas_id, inst_mat, width: int = 4, s
         scratch = _bytes(s.scratch_bytes, dev)
     arr = (BlasDesc * len(blas))(*[b.desc for b in blas])
     d = TlasDesc()
-    _check("rg_build_tlas", _lib.rg_build_tlas(
-        arr, len(blas), xform.ctypes.data, blas_id.ctypes.data, inst_mat.ctypes.data, n,
+    fl = np.ascontiguousarray(inst_flags, np.uint32).reshape(n) if inst_flags is not None else None
+    _check("rg_build_tlas", _lib.rg_build_tlas_ex(
+        arr, len(blas), xform.ctypes.data, blas_id.ctypes.data, inst_mat.ctypes.data,
+        fl.ctypes.data if fl is not None else None, n,
         ctypes.byref(o), _ptr(buf), buf.numel(), _ptr(scratch), scratch.numel(), _stream(stream),
         ctypes.byref(d)))
     del torch
@@ -348,7 +360,7 @@ def build_tlas(blas: Sequence[Blas], xform, blas_id, inst_mat, width: int = 4, s
 
 
 def upload_scene(scene, width: int = 4, leaf_max: int = 4, device="cuda", builder: str = "lbvh",
-                 radius: int = 0, tlas_builder: Optional[str] = None) -> Tlas:
+                 radius: int = 0, tlas_builder: Optional[str] = None, inst_flags=None) -> Tlas:
     """Builds every mesh and the instance level of a scene object with
     attributes blas (meshes with verts/idx/prim_mat), xform, blas_id, inst_mat.
     tlas_builder None: the instance level uses `builder` as well."""
@@ -363,7 +375,7 @@ def upload_scene(scene, width: int = 4, leaf_max: int = 4, device="cuda", builde
         built.append(build_blas(v, i, pm, width, leaf_max, builder=builder, radius=radius))
         del v, i, pm
     return build_tlas(built, scene.xform, scene.blas_id, scene.inst_mat, width,
-                      builder=tlas_builder or builder, radius=radius)
+                      builder=tlas_builder or builder, radius=radius, inst_flags=inst_flags)
 
 
 # ------------------------------------------------------------------- rays
@@ -399,23 +411,54 @@ def _hits_struct(h) -> Hits:
     return Hits(_ptr(h["t"]), _ptr(h["inst"]), _ptr(h["prim"]), _ptr(h["u"]), _ptr(h["v"]))
 
 
-def trace_closest(tlas: Tlas, rays, out=None, stream=None):
+# ray visibility and facing (include/rg.h)
+RAY_CULL_BACK, RAY_CULL_FRONT = 1, 2
+INST_MASK_ALL, INST_CULL_DISABLE, INST_FLIP_FACING = 0xFF, 1 << 8, 1 << 9
+
+
+def _opts_ref(cull: int, mask: int, ray_mask, n: int):
+    if cull == 0 and mask == INST_MASK_ALL and ray_mask is None:
+        return None
+    if ray_mask is not None:
+        torch = _torch()
+        if ray_mask.dtype != torch.uint8 or not ray_mask.is_cuda or not ray_mask.is_contiguous() \
+                or ray_mask.numel() < n:
+            raise ValueError("ray_mask must be a contiguous CUDA uint8 tensor with one entry per ray")
+    o = TraceOpts(cull, mask, _ptr(ray_mask) if ray_mask is not None else None)
+    return ctypes.byref(o), o
+
+
+def trace_closest(tlas: Tlas, rays, out=None, stream=None, cull: int = 0, mask: int = INST_MASK_ALL,
+                  ray_mask=None):
+    """cull: RAY_CULL_*; mask: visibility mask of every ray unless ray_mask
+    (CUDA uint8 per ray) is given."""
     n = rays.shape[1]
     if out is None:
         out = alloc_hits(n, rays.device)
-    _check("rg_trace_closest", _lib.rg_trace_closest(tlas.ref, rays_struct(rays), n, _hits_struct(out),
-                                                     _stream(stream)))
+    o = _opts_ref(cull, mask, ray_mask, n)
+    if o is None:
+        _check("rg_trace_closest", _lib.rg_trace_closest(tlas.ref, rays_struct(rays), n, _hits_struct(out),
+                                                         _stream(stream)))
+    else:
+        _check("rg_trace_closest_ex", _lib.rg_trace_closest_ex(tlas.ref, rays_struct(rays), n, _hits_struct(out),
+                                                               o[0], _stream(stream)))
     return out
 
 
-def trace_any(tlas: Tlas, rays, occluded=None, found=None, stream=None):
+def trace_any(tlas: Tlas, rays, occluded=None, found=None, stream=None, cull: int = 0, mask: int = INST_MASK_ALL,
+              ray_mask=None):
     torch = _torch()
     n = rays.shape[1]
     if occluded is None:
         occluded = torch.empty(n, dtype=torch.uint8, device=rays.device)
     fh = ctypes.byref(_hits_struct(found)) if found is not None else None
-    _check("rg_trace_any", _lib.rg_trace_any(tlas.ref, rays_struct(rays), n, _ptr(occluded), fh,
-                                             _stream(stream)))
+    o = _opts_ref(cull, mask, ray_mask, n)
+    if o is None:
+        _check("rg_trace_any", _lib.rg_trace_any(tlas.ref, rays_struct(rays), n, _ptr(occluded), fh,
+                                                 _stream(stream)))
+    else:
+        _check("rg_trace_any_ex", _lib.rg_trace_any_ex(tlas.ref, rays_struct(rays), n, _ptr(occluded), fh, o[0],
+                                                       _stream(stream)))
     return occluded
 
 

@@ -957,9 +957,9 @@ __device__ inline float round_up(double x) {
 // The bottom level's root box and the status of its last refit come from its
 // header on the device (a refit updates them without a host round trip).
 __global__ void k_inst_setup(const float *__restrict__ xform, const uint32_t *__restrict__ blas_id,
-                             const uint32_t *__restrict__ inst_mat, const BlasInfo *__restrict__ blas,
-                             int64_t n, float *__restrict__ box, RgInst *__restrict__ recs,
-                             uint32_t *__restrict__ flags) {
+                             const uint32_t *__restrict__ inst_mat, const uint32_t *__restrict__ inst_flags,
+                             const BlasInfo *__restrict__ blas, int64_t n, float *__restrict__ box,
+                             RgInst *__restrict__ recs, uint32_t *__restrict__ flags) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     double m[12];
@@ -1007,7 +1007,8 @@ __global__ void k_inst_setup(const float *__restrict__ xform, const uint32_t *__
         r.blo[q] = B.lo[q];
         r.bhi[q] = B.hi[q];
     }
-    r.pad[0] = r.pad[1] = 0u;
+    r.flags = inst_flags ? inst_flags[i] : RG_INST_MASK_ALL;
+    r.pad = 0u;
     recs[i] = r;
 }
 
@@ -1330,6 +1331,7 @@ uint64_t tlas_scratch_bytes(int64_t n, int32_t n_blas, int32_t builder) {
     a.take<float>(6 * n);       // instance boxes
     a.take<RgInst>(n);          // unsorted records
     a.take<uint32_t>(8);        // flags
+    a.take<uint32_t>(n);        // instance flags
     return a.used + rg_lbvh_scratch_bytes(n, builder);
 }
 
@@ -1537,9 +1539,10 @@ rg_status rg_tlas_sizes(int64_t n_inst, const rg_build_opts *opts, rg_sizes *out
     return RG_OK;
 }
 
-rg_status rg_build_tlas(const rg_blas *blas, int32_t n_blas, const float *xform, const uint32_t *blas_id,
-                        const uint32_t *inst_material, int64_t n_inst, const rg_build_opts *opts, void *out_buf,
-                        uint64_t out_bytes, void *scratch, uint64_t scratch_bytes, void *stream, rg_tlas *out) {
+rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xform, const uint32_t *blas_id,
+                           const uint32_t *inst_material, const uint32_t *inst_flags, int64_t n_inst,
+                           const rg_build_opts *opts, void *out_buf, uint64_t out_bytes, void *scratch,
+                           uint64_t scratch_bytes, void *stream, rg_tlas *out) {
     Opts o;
     if (!blas || !xform || !blas_id || !inst_material || !out_buf || !scratch || !out) return RG_ERR_INVALID_ARG;
     if (n_blas < 1 || n_blas > 4096 || n_inst < 1 || n_inst > RG_MAX_TRIS) return RG_ERR_INVALID_ARG;
@@ -1554,6 +1557,10 @@ rg_status rg_build_tlas(const rg_blas *blas, int32_t n_blas, const float *xform,
         info[b].tris = (uint64_t)((char *)blas[b].buf + blas[b].tris_off);
         info[b].hdr = (uint64_t)blas[b].buf;
     }
+    const uint32_t known = 0xFFu | RG_INST_CULL_DISABLE | RG_INST_FLIP_FACING;
+    if (inst_flags)
+        for (int64_t i = 0; i < n_inst; ++i)
+            if (inst_flags[i] & ~known) return RG_ERR_INVALID_ARG;
     for (int64_t i = 0; i < n_inst; ++i) {
         if (blas_id[i] >= (uint32_t)n_blas) return RG_ERR_INVALID_ARG;
         const float *m = xform + 12 * i;
@@ -1576,13 +1583,15 @@ rg_status rg_build_tlas(const rg_blas *blas, int32_t n_blas, const float *xform,
     float *d_box = arena.take<float>(6 * n_inst);
     RgInst *d_rec = arena.take<RgInst>(n_inst);
     uint32_t *d_flags = arena.take<uint32_t>(8);
+    uint32_t *d_iflags = inst_flags ? arena.take<uint32_t>(n_inst) : nullptr;
     k_fill_u32<<<1, 64, 0, st>>>(d_flags, 0u, 1);
+    if (inst_flags) RG_HIP(hipMemcpyAsync(d_iflags, inst_flags, 4 * n_inst, hipMemcpyHostToDevice, st));
     RG_HIP(hipMemcpyAsync(d_xf, xform, 48 * n_inst, hipMemcpyHostToDevice, st));
     RG_HIP(hipMemcpyAsync(d_bid, blas_id, 4 * n_inst, hipMemcpyHostToDevice, st));
     RG_HIP(hipMemcpyAsync(d_mat, inst_material, 4 * n_inst, hipMemcpyHostToDevice, st));
     RG_HIP(hipMemcpyAsync(d_info, info.data(), sizeof(BlasInfo) * n_blas, hipMemcpyHostToDevice, st));
-    k_inst_setup<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(d_xf, d_bid, d_mat, d_info, n_inst, d_box, d_rec,
-                                                                    d_flags);
+    k_inst_setup<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(d_xf, d_bid, d_mat, d_iflags, d_info, n_inst, d_box,
+                                                                    d_rec, d_flags);
     RG_LAUNCH_CHECK();
     char *base = (char *)out_buf;
     RgLbvhOut lo;
@@ -1605,12 +1614,22 @@ rg_status rg_build_tlas(const rg_blas *blas, int32_t n_blas, const float *xform,
     out->width = w;
     out->depth = lo.depth;
     out->max_blas_depth = max_depth;
-    out->reserved = 0;
+    out->has_inst_flags = 0;
+    if (inst_flags)
+        for (int64_t i = 0; i < n_inst; ++i)
+            if (inst_flags[i] != RG_INST_MASK_ALL) out->has_inst_flags = 1;
     for (int k = 0; k < 3; ++k) {
         out->lo[k] = lo.lo[k];
         out->hi[k] = lo.hi[k];
     }
     return RG_OK;
+}
+
+rg_status rg_build_tlas(const rg_blas *blas, int32_t n_blas, const float *xform, const uint32_t *blas_id,
+                        const uint32_t *inst_material, int64_t n_inst, const rg_build_opts *opts, void *out_buf,
+                        uint64_t out_bytes, void *scratch, uint64_t scratch_bytes, void *stream, rg_tlas *out) {
+    return rg_build_tlas_ex(blas, n_blas, xform, blas_id, inst_material, nullptr, n_inst, opts, out_buf, out_bytes,
+                            scratch, scratch_bytes, stream, out);
 }
 
 rg_status rg_lbvh_stages(const float *verts, int64_t n_verts, const uint32_t *idx, int64_t n_tris,

@@ -572,6 +572,7 @@ RgTraceArgs trace_args(const rg_tlas *t) {
     RgTraceArgs a = {};
     a.nodes = (const char *)t->buf + t->nodes_off;
     a.recs = (const RgInst *)((const char *)t->buf + t->inst_off);
+    a.opt = t->has_inst_flags != 0;
     return a;
 }
 
@@ -620,7 +621,7 @@ rg_status run_batch(const rg_batch *B, hipStream_t st) {
     k_camera_batch<<<rg_blocks(total, kT), kT, 0, st>>>(b.jobs, B->n_jobs, total, b.q[0], b.counts + 0);
     RG_LAUNCH_CHECK();
     for (int k = 0; k <= B->max_depth; ++k) {
-        r = rg_wave_pass(b, B->width, k, B->cap_at[k], st, RG_TUNE_FRAME);
+        r = rg_wave_pass(b, B->width, k, B->cap_at[k], st, RG_TUNE_FRAME, B->has_inst_flags != 0);
         if (r != RG_OK) return r;
     }
     k_resolve_batch<<<rg_blocks(total, kT), kT, 0, st>>>(b.acc, b.jobs, B->n_jobs, total);
@@ -703,7 +704,7 @@ rg_status rg_wave_camera(const RgWaveBufs &b, uint32_t slot, const RgJobDev &J, 
 }
 
 rg_status rg_wave_pass(const RgWaveBufs &b, int32_t width, int64_t pass, int64_t bound, hipStream_t st,
-                       int scope, RgShadowSide *side) {
+                       int scope, bool opt, RgShadowSide *side) {
     if (bound < 1) return RG_OK;
     if (bound > b.cap) bound = b.cap;
     const RgQueue &qin = b.q[pass & 1], &qout = b.q[(pass + 1) & 1];
@@ -717,6 +718,7 @@ rg_status rg_wave_pass(const RgWaveBufs &b, int32_t width, int64_t pass, int64_t
     tc.t = b.hit_t;
     tc.inst = b.hit_rec;
     tc.prim = b.hit_slot;
+    tc.opt = opt;
     rg_status r = rg_trace_launch(width, false, rgt::kRender, tc, st, scope);
     if (r != RG_OK) return r;
     // the shadow queue and its count are reused below: the previous pass's
@@ -762,6 +764,7 @@ rg_status rg_wave_pass(const RgWaveBufs &b, int32_t width, int64_t pass, int64_t
     ts.ray_job = b.sq.job;
     ts.jobs = b.tlas;
     ts.occluded = b.sq.occ;
+    ts.opt = opt;
     r = rg_trace_launch(width, true, rgt::kRender, ts, s2, scope);
     if (r != RG_OK) return r;
     k_stat_add<<<1, 1, 0, s2>>>(b.stat + 1, csq);
@@ -850,6 +853,7 @@ rg_status rg_batch_prepare(const rg_job *jobs, int32_t n_jobs, void *scratch, ui
     std::vector<RgJobDev> hj((size_t)n_jobs);
     std::vector<RgTlasRef> ht((size_t)n_jobs);
     std::vector<RgMat> hm((size_t)sh.n_mats);
+    rg_batch B = {};
     uint32_t pix = 0, mo = 0;
     for (int32_t j = 0; j < n_jobs; ++j) {
         const rg_job &J = jobs[j];
@@ -865,11 +869,11 @@ rg_status rg_batch_prepare(const rg_job *jobs, int32_t n_jobs, void *scratch, ui
         hj[j].image = J.image;
         ht[j].nodes = (const char *)J.tlas->buf + J.tlas->nodes_off;
         ht[j].recs = (const RgInst *)((const char *)J.tlas->buf + J.tlas->inst_off);
+        if (J.tlas->has_inst_flags) B.has_inst_flags = 1;
         memcpy(&hm[mo], J.mats, sizeof(RgMat) * (size_t)J.n_mats);
         pix += (uint32_t)(J.width * J.height);
         mo += (uint32_t)J.n_mats;
     }
-    rg_batch B = {};
     B.scratch = scratch;
     B.scratch_bytes = scratch_bytes;
     B.n_jobs = n_jobs;
@@ -968,7 +972,8 @@ rg_status rg_render(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats
         if ((r = rg_wave_put_job(b, 0, J, T, mats, n_mats, st)) != RG_OK) return r;
         if ((r = rg_wave_camera(b, 0, J, 0, st)) != RG_OK) return r;
         for (int k = 0; k <= max_depth; ++k)
-            if ((r = rg_wave_pass(b, tlas->width, k, n << k, st, RG_TUNE_FRAME)) != RG_OK) return r;
+            if ((r = rg_wave_pass(b, tlas->width, k, n << k, st, RG_TUNE_FRAME, tlas->has_inst_flags != 0)) != RG_OK)
+                return r;
         if ((r = rg_wave_resolve(b, J, st)) != RG_OK) return r;
         if (stats) return finish_stats(st, e0, e1, b.stat, stats);
         return RG_OK;

@@ -54,7 +54,8 @@ struct RgInst {
     uint64_t nodes, tris, hdr;
     uint32_t mat, inst;
     float blo[3], bhi[3];  // the bottom level's root box (object space)
-    uint32_t pad[2];
+    uint32_t flags;        // visibility mask (bits 0-7), RG_INST_CULL_DISABLE, RG_INST_FLIP_FACING
+    uint32_t pad;
 };
 static_assert(sizeof(RgInst) == 112, "inst");
 

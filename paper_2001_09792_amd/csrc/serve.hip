@@ -138,6 +138,7 @@ struct rg_engine {
         bool live = false;
         int64_t tag = 0, start = 0, last = 0, pix = 0;
         int32_t growth = 1;
+        bool flags = false;              // its top level carries instance flags
         RgJobDev dev;
     };
     std::vector<Frame> frames;           // per slot
@@ -344,6 +345,7 @@ rg_status rg_engine_admit(rg_engine *E, const rg_job *J, int64_t tag, int32_t *a
         return r;
     }
     F.live = true;
+    F.flags = t->has_inst_flags != 0;
     F.tag = tag;
     F.start = E->pass;
     F.last = E->pass + J->max_depth;
@@ -360,19 +362,21 @@ rg_status rg_engine_step(rg_engine *E, int32_t *ran) {
     if (ran) *ran = 0;
     int64_t bound = 0, frames = 0;
     uint32_t depth_mask = 0;
+    bool opt = false;
     for (const rg_engine::Frame &F : E->frames) {
         if (!F.live || F.last < E->pass) continue;
         const int64_t k = E->pass - F.start;
         bound += F.growth == 2 ? (F.pix << k) : F.pix;
         frames += 1;
         depth_mask |= 1u << k;
+        opt = opt || F.flags;
     }
     if (frames == 0) return RG_OK;
     if (E->pass - E->done_pass >= kEventRing) {
         rg_status r = harvest(E, true);
         if (r != RG_OK) return r;
     }
-    rg_status r = rg_wave_pass(E->b, E->d.width, E->pass, bound, E->st, RG_TUNE_ENGINE, &E->side);
+    rg_status r = rg_wave_pass(E->b, E->d.width, E->pass, bound, E->st, RG_TUNE_ENGINE, opt, &E->side);
     if (r != RG_OK) return r;
     // the pass is complete once its shadow half (on the side stream) is
     auto it = E->finishing.find(E->pass);

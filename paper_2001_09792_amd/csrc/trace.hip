@@ -10,7 +10,7 @@ namespace {
 // the whole batch), and lanes whose ray has finished take the next rays of
 // that sequence together, once at least `refill` lanes are idle.  Rays of a
 // packet stay neighbours, and no lane idles while its wave has work left.
-template <int W, bool ANY, int MODE>
+template <int W, bool ANY, int MODE, bool OPT>
 __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refill, int lds_depth, int leaf_batch,
                                                          int inst_batch) {
     extern __shared__ uint32_t lds_stack[];  // lds_depth * kThreads entries
@@ -21,13 +21,17 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
     const int64_t n_packets = (n + 63) >> 6;
     const int64_t wave = ((int64_t)blockIdx.x * rgt::kThreads + threadIdx.x) >> 6;
     const int64_t n_waves = (int64_t)gridDim.x * (rgt::kThreads / 64);
-    rgt::Tracer<W, ANY, MODE> tr;
+    rgt::Tracer<W, ANY, MODE, OPT> tr;
     tr.tlas_nodes = reinterpret_cast<const RgNode<W> *>(a.nodes);
     tr.recs = a.recs;
     uint32_t priv_stack[rgt::kPrivStack];
     tr.st.lds = (uint32_t RG_LDS *)&lds_stack[threadIdx.x];
     tr.st.priv = priv_stack;
     tr.st.n_lds = lds_depth;
+    if (OPT) {
+        tr.call_cull = a.ray_flags & (RG_RAY_CULL_BACK | RG_RAY_CULL_FRONT);
+        tr.rmask = a.mask;
+    }
     int64_t next = 0;  // position in this wave's ray sequence (the same in all lanes)
     int64_t ray_i = -1;
     bool has = false;
@@ -73,6 +77,7 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
                         tr.recs = J.recs;
                     }
                     has = tr.begin(R);
+                    if (OPT) tr.rmask = a.ray_mask ? (uint32_t)a.ray_mask[idx] : a.mask;
                     pend = !has;  // empty interval: a miss without traversal
                 }
             }
@@ -136,21 +141,28 @@ unsigned persistent_blocks(int64_t n, int waves_per_cu) {
     return (unsigned)(need < want ? need : want);
 }
 
+template <int W, bool OPT>
+void launch_mode(bool any, int mode, const RgTraceArgs &a, hipStream_t st, unsigned blocks, size_t shm,
+                 const rg_trace_tune &t) {
+    const int refill = t.refill, lds = t.lds_depth, lb = t.leaf_batch, ib = t.inst_batch;
+    if (mode == rgt::kCounts) {
+        if (any) k_trace<W, true, rgt::kCounts, OPT><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
+        else k_trace<W, false, rgt::kCounts, OPT><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
+    } else if (mode == rgt::kRender) {
+        if (any) k_trace<W, true, rgt::kRender, OPT><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
+        else k_trace<W, false, rgt::kRender, OPT><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
+    } else {
+        if (any) k_trace<W, true, rgt::kClosest, OPT><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
+        else k_trace<W, false, rgt::kClosest, OPT><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
+    }
+}
+
 template <int W>
 rg_status launch_w(bool any, int mode, const RgTraceArgs &a, hipStream_t st, const rg_trace_tune &t) {
     unsigned blocks = persistent_blocks(a.n, t.waves_per_cu);
-    int refill = t.refill, lds = t.lds_depth, lb = t.leaf_batch, ib = t.inst_batch;
-    size_t shm = (size_t)lds * rgt::kThreads * sizeof(uint32_t);
-    if (mode == rgt::kCounts) {
-        if (any) k_trace<W, true, rgt::kCounts><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
-        else k_trace<W, false, rgt::kCounts><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
-    } else if (mode == rgt::kRender) {
-        if (any) k_trace<W, true, rgt::kRender><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
-        else k_trace<W, false, rgt::kRender><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
-    } else {
-        if (any) k_trace<W, true, rgt::kClosest><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
-        else k_trace<W, false, rgt::kClosest><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
-    }
+    size_t shm = (size_t)t.lds_depth * rgt::kThreads * sizeof(uint32_t);
+    if (a.opt) launch_mode<W, true>(any, mode, a, st, blocks, shm, t);
+    else launch_mode<W, false>(any, mode, a, st, blocks, shm, t);
     RG_LAUNCH_CHECK();
     return RG_OK;
 }
@@ -163,6 +175,16 @@ void fill_rays(RgTraceArgs &a, const rg_rays &r) {
     a.ray[0] = r.ox; a.ray[1] = r.oy; a.ray[2] = r.oz;
     a.ray[3] = r.dx; a.ray[4] = r.dy; a.ray[5] = r.dz;
     a.ray[6] = r.tmin; a.ray[7] = r.tmax;
+}
+
+bool set_opts(RgTraceArgs &a, const rg_trace_opts *o) {
+    if (!o) return true;
+    if ((o->flags & ~(RG_RAY_CULL_BACK | RG_RAY_CULL_FRONT)) || o->mask > 0xFFu) return false;
+    a.ray_flags = o->flags;
+    a.mask = o->mask;
+    a.ray_mask = o->ray_mask;
+    a.opt = o->flags != 0u || o->mask != RG_INST_MASK_ALL || o->ray_mask != nullptr;
+    return true;
 }
 
 bool tlas_ok(const rg_tlas *t) {
@@ -202,10 +224,22 @@ rg_status rg_trace_tuning(int32_t scope, const rg_trace_tune *set, rg_trace_tune
 }
 
 rg_status rg_trace_closest(const rg_tlas *tlas, rg_rays rays, int64_t n, rg_hits out, void *stream) {
+    return rg_trace_closest_ex(tlas, rays, n, out, nullptr, stream);
+}
+
+rg_status rg_trace_any(const rg_tlas *tlas, rg_rays rays, int64_t n, uint8_t *occluded, const rg_hits *found,
+                       void *stream) {
+    return rg_trace_any_ex(tlas, rays, n, occluded, found, nullptr, stream);
+}
+
+rg_status rg_trace_closest_ex(const rg_tlas *tlas, rg_rays rays, int64_t n, rg_hits out, const rg_trace_opts *opts,
+                              void *stream) {
     if (!tlas_ok(tlas) || n < 0 || (n > 0 && !rays_ok(rays))) return RG_ERR_INVALID_ARG;
+    RgTraceArgs a = {};
+    if (!set_opts(a, opts)) return RG_ERR_INVALID_ARG;
+    a.opt = a.opt || tlas->has_inst_flags != 0;
     if (!rg_trace_depth_ok(tlas)) return RG_ERR_UNSUPPORTED;
     if (n == 0) return RG_OK;
-    RgTraceArgs a = {};
     a.nodes = (const char *)tlas->buf + tlas->nodes_off;
     a.recs = (const RgInst *)((const char *)tlas->buf + tlas->inst_off);
     fill_rays(a, rays);
@@ -214,12 +248,14 @@ rg_status rg_trace_closest(const rg_tlas *tlas, rg_rays rays, int64_t n, rg_hits
     return rg_trace_launch(tlas->width, false, rgt::kClosest, a, (hipStream_t)stream, RG_TUNE_TRACE);
 }
 
-rg_status rg_trace_any(const rg_tlas *tlas, rg_rays rays, int64_t n, uint8_t *occluded, const rg_hits *found,
-                       void *stream) {
+rg_status rg_trace_any_ex(const rg_tlas *tlas, rg_rays rays, int64_t n, uint8_t *occluded, const rg_hits *found,
+                          const rg_trace_opts *opts, void *stream) {
     if (!tlas_ok(tlas) || n < 0 || (n > 0 && (!rays_ok(rays) || !occluded))) return RG_ERR_INVALID_ARG;
+    RgTraceArgs a = {};
+    if (!set_opts(a, opts)) return RG_ERR_INVALID_ARG;
+    a.opt = a.opt || tlas->has_inst_flags != 0;
     if (!rg_trace_depth_ok(tlas)) return RG_ERR_UNSUPPORTED;
     if (n == 0) return RG_OK;
-    RgTraceArgs a = {};
     a.nodes = (const char *)tlas->buf + tlas->nodes_off;
     a.recs = (const RgInst *)((const char *)tlas->buf + tlas->inst_off);
     fill_rays(a, rays);
@@ -242,6 +278,7 @@ rg_status rg_trace_counts(const rg_tlas *tlas, rg_rays rays, int64_t n, int32_t 
     fill_rays(a, rays);
     a.n = n;
     a.counts = counts;
+    a.opt = tlas->has_inst_flags != 0;
     return rg_trace_launch(tlas->width, any_hit != 0, rgt::kCounts, a, (hipStream_t)stream, RG_TUNE_TRACE);
 }
 

@@ -28,6 +28,7 @@ constexpr int kMaxLdsStack = 32;  // most stack entries per lane kept in LDS (ch
 constexpr int kPrivStack = 96;    // further entries per lane in private memory
 constexpr int kStackCap = 8 + kPrivStack;  // guaranteed capacity (at the smallest LDS depth, 8)
 constexpr uint32_t kSentinel = 0xFFFFFFFEu;
+constexpr uint32_t kFlip = 4u;  // in Tracer::cull: the instance flips its facing
 constexpr uint32_t kMaxSteps = 1u << 22;  // loop bound: far above any traversal of a valid hierarchy
 // The far distance of a slab is widened by 2 gamma_5 (gamma_n = n u / (1 - n u),
 // u = 2^-24): the subtraction, the hardware reciprocal (1 ulp) and the product
@@ -195,7 +196,10 @@ __device__ inline void sort_children(float tn[W], uint32_t ch[W]) {
 // leaf's triangles, then the pop) and reports when the ray is finished.  The
 // kernels run many rays per lane through it, so that lanes whose ray has
 // finished can take a new one while the others continue.
-template <int W, bool ANY, int MODE>
+// OPT: visibility masks and face culling are compiled in (launches whose
+// rays carry options, or whose top levels carry instance flags); without it
+// the traversal has none of their registers or tests.
+template <int W, bool ANY, int MODE, bool OPT>
 struct Tracer {
     const RgNode<W> *tlas_nodes;
     const RgInst *recs;
@@ -210,6 +214,9 @@ struct Tracer {
     Shear sh;
     Stack st;
     uint32_t cur, steps;
+    uint32_t rmask;      // this ray's visibility mask
+    uint32_t call_cull;  // RG_RAY_CULL_* of the launch
+    uint32_t cull;       // culling in the current instance: RG_RAY_CULL_* | kFlip
     bool in_blas, found;
 
     __device__ inline void world_frame() {
@@ -237,6 +244,7 @@ struct Tracer {
         tris = nullptr;
         inst_id = 0;
         sh.kx = 0; sh.ky = 1; sh.kz = 2; sh.sx = sh.sy = 0.0f; sh.sz = 1.0f;
+        cull = 0u;
         world_frame();
         return R.tmin <= R.tmax;
     }
@@ -292,6 +300,7 @@ struct Tracer {
                 }
             }
         }
+        const bool skip = OPT && inst && ((w[26] & 0xFFu) & rmask) == 0u;  // masked instance
         if (inner) {
             if (MODE == kCounts) ++h.n_nodes;
             float tn[W];
@@ -331,10 +340,12 @@ struct Tracer {
             }
             if (next != RG_EMPTY) cur = next;
             else pop = true;
+        } else if (skip) {
+            pop = true;  // not visible to this ray: as if missed
         } else if (inst) {
             // top-level leaf: one instance.  Record words: inv[9] 0..8, p[3]
             // 9..11, nodes 12..13, tris 14..15, hdr 16..17, mat 18, inst 19,
-            // root box lo 20..22, hi 23..25.
+            // root box lo 20..22, hi 23..25, flags 26.
             if (MODE == kCounts) ++h.n_inst;
             // object-space ray in double: o' = M^-1 (o - p), d' = M^-1 d
             double q[3] = {(double)R.o[0] - (double)__uint_as_float(w[9]),
@@ -378,6 +389,10 @@ struct Tracer {
             nodes = reinterpret_cast<const RgNode<W> *>((uint64_t)w[12] | ((uint64_t)w[13] << 32));
             tris = reinterpret_cast<const RgTri *>((uint64_t)w[14] | ((uint64_t)w[15] << 32));
             inst_id = (MODE == kRender) ? lf : w[19];
+            if (OPT) {
+                cull = (w[26] & RG_INST_CULL_DISABLE) ? 0u : call_cull;
+                if (cull && (w[26] & RG_INST_FLIP_FACING)) cull |= kFlip;
+            }
             in_blas = true;
             st.push(kSentinel);
             cur = 0;
@@ -397,6 +412,12 @@ struct Tracer {
                 }
                 float T, det, V, Wv;
                 if (!tri_test(tri, o3, sh, tlo, thi, T, det, V, Wv)) continue;
+                if (OPT && cull) {
+                    // facing: det > 0 when the ray travels against the winding
+                    // normal (the sheared axes keep their handedness)
+                    const bool front = (det > 0.0f) != ((cull & kFlip) != 0u);
+                    if (cull & (front ? RG_RAY_CULL_FRONT : RG_RAY_CULL_BACK)) continue;
+                }
                 float tl = T / det;
                 float tw = t0 + tl;
                 if (!(tw >= R.tmin) || !(tw <= best)) continue;
@@ -452,6 +473,10 @@ struct RgTraceArgs {
     const void *nodes;             // top-level nodes
     const RgInst *recs;            // top-level instance records
     const uint32_t *ray_job;       // per ray: index into jobs (nullable: all rays use nodes/recs)
+    uint32_t ray_flags = 0u;       // RG_RAY_CULL_*
+    uint32_t mask = RG_INST_MASK_ALL;  // visibility mask of every ray, unless ray_mask
+    const uint8_t *ray_mask = nullptr;  // per ray (nullable)
+    bool opt = false;              // masks / culling in effect (ray options or instance flags)
     const RgTlasRef *jobs;
     const float *ray[8];           // ox oy oz dx dy dz tmin tmax
     int64_t n;                     // number of rays (upper bound if `count` is set)

@@ -88,9 +88,10 @@ struct RgShadowSide {
 // (sizes the launches); width = node width of every top level involved.
 // With `side`, the shadow half runs on side->st (see above): work that needs
 // the pass complete (image resolves) goes to side->st as well.
-// scope: the RG_TUNE_* launch parameters of the traversals.
+// scope: the RG_TUNE_* launch parameters of the traversals; opt: some
+// frame's top level carries instance flags (masks, cull flags).
 rg_status rg_wave_pass(const RgWaveBufs &b, int32_t width, int64_t pass, int64_t bound, hipStream_t st,
-                       int scope, RgShadowSide *side = nullptr);
+                       int scope, bool opt, RgShadowSide *side = nullptr);
 
 // Converts the frame's accumulators to its float RGB image.
 rg_status rg_wave_resolve(const RgWaveBufs &b, const RgJobDev &J, hipStream_t st);

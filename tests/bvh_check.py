@@ -81,7 +81,7 @@ def check_blas(buf: np.ndarray, desc, refitted: bool = False) -> dict:
         desc.mats_off: desc.mats_off + 2 * n].view(np.uint16), header=hdr)
 
 
-def check_tlas(buf: np.ndarray, desc, blas_descs, xform, roots=None) -> dict:
+def check_tlas(buf: np.ndarray, desc, blas_descs, xform, roots=None, inst_flags=None) -> dict:
     W = desc.width
     lo, hi, child = _nodes(buf, desc.nodes_off, desc.n_nodes, W)
     n = desc.n_inst
@@ -122,4 +122,7 @@ def check_tlas(buf: np.ndarray, desc, blas_descs, xform, roots=None) -> dict:
         rlo, rhi = by_nodes[int(rec_nodes[r])]
         assert np.array_equal(recf[r, 20:23], np.array(rlo, np.float32))
         assert np.array_equal(recf[r, 23:26], np.array(rhi, np.float32))
+    # the instance flags word (visibility mask, cull flags); all visible by default
+    want = np.full(n, 0xFF, np.uint32) if inst_flags is None else np.asarray(inst_flags, np.uint32)
+    assert np.array_equal(recu[:, 26], want[inst])
     return dict(depth=depth, inst=inst, boxes=(boxes_lo, boxes_hi))

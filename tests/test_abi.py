@@ -176,3 +176,29 @@ def test_trace_tuning_scopes_host_only():
     finally:
         for s, v in saved.items():
             rg.trace_tuning(scope=s, **v)
+
+
+def test_trace_options_and_instance_flags_are_checked_on_the_host():
+    """Unknown ray flags, a mask above 8 bits and unknown instance flag bits
+    are rejected before any device work; valid options on zero rays are a
+    no-op."""
+    import paper_2001_09792_amd as rg
+    lib = rg._lib
+    t = rg.TlasDesc()
+    t.buf, t.n_inst, t.width, t.depth = 256, 1, 4, 2
+    for flags, mask, want in ((4, 0xFF, -1), (rg.RAY_CULL_BACK, 0x100, -1), (rg.RAY_CULL_FRONT, 0x0F, 0),
+                              (rg.RAY_CULL_BACK | rg.RAY_CULL_FRONT, 0, 0)):
+        o = rg.TraceOpts(flags, mask, None)
+        assert lib.rg_trace_closest_ex(ctypes.byref(t), rg.Rays(), 0, rg.Hits(), ctypes.byref(o), None) == want
+        assert lib.rg_trace_any_ex(ctypes.byref(t), rg.Rays(), 0, None, None, ctypes.byref(o), None) == want
+    assert lib.rg_trace_closest_ex(None, rg.Rays(), 0, rg.Hits(), None, None) == -1
+    xf = (ctypes.c_float * 12)(*[1.0, 0, 0, 0, 0, 1.0, 0, 0, 0, 0, 1.0, 0])
+    bid = (ctypes.c_uint32 * 1)(0)
+    im = (ctypes.c_uint32 * 1)(0)
+    fl = (ctypes.c_uint32 * 1)(0xFF | (1 << 10))
+    fake = rg.BlasDesc()
+    fake.buf, fake.width = 256, 4
+    blas = (rg.BlasDesc * 1)(fake)
+    o = rg.BuildOpts(4, 4)
+    assert lib.rg_build_tlas_ex(blas, 1, xf, bid, im, fl, 1, ctypes.byref(o), 256, 1 << 20, 256, 1 << 20, None,
+                                ctypes.byref(t)) == -1
