@@ -12,6 +12,8 @@ Contents
                  that pins the FP64 oracle on tiny inputs.
   build_ref.py   plain definitions of the build steps (Morton codes, stable
                  sort, Karras hierarchy, box refit) in NumPy.
+  post.py        the frame's post-process passes (roughness blur, FXAA) in
+                 FP64 NumPy, with per-pixel decision margins.
 
 Ambient occlusion is not in the paper; it is the incoherent workload's
 definition: for each primary hit, 8 cosine-weighted directions (Malley's

@@ -556,3 +556,53 @@ def sample_pixels(width: int, height: int, n: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(np.random.SeedSequence(seed))
     n = min(n, width * height)
     return np.sort(rng.choice(width * height, n, replace=False)).astype(np.int64)
+
+
+# ----------------------------------------------------------------------------
+# post-process inputs: a traced frame and its primary-hit materials
+# ----------------------------------------------------------------------------
+def roughness_table(n_mats: int, seed: int) -> np.ndarray:
+    """Roughness per material in [0, 1]; about a quarter of the materials
+    are perfectly smooth (0)."""
+    rng = np.random.default_rng(seed)
+    r = rng.uniform(0.0, 1.0, n_mats)
+    r[rng.random(n_mats) < 0.25] = 0.0
+    return r.astype(np.float32)
+
+
+def post_frame(width: int, height: int, seed: int, n_mats: int = 8, n_shapes: int = 40):
+    """A frame as the tracer leaves it, drawn with one sample per pixel centre
+    (so every edge is aliased): a sky gradient (material MISS) behind
+    overlapping discs, triangles and half-planes, each of one material, with a
+    smooth shading ramp, a checker texture on some and values up to 2.
+    Returns image f32[H,W,3], primary material u32[H,W]."""
+    rng = np.random.default_rng(seed)
+    yy, xx = np.mgrid[0:height, 0:width].astype(np.float64) + 0.5
+    u, v = xx / width, yy / height
+    img = np.stack([1.0 - 0.5 * v, 1.0 - 0.3 * v, np.ones_like(v)], axis=-1)
+    mat = np.full((height, width), MISS, np.uint32)
+    scale = max(width, height)
+    for _ in range(n_shapes):
+        kind = rng.integers(0, 3)
+        if kind == 0:
+            c = rng.uniform(0, 1, 2) * np.array([width, height])
+            rad = rng.uniform(0.02, 0.25) * scale
+            inside = (xx - c[0]) ** 2 + (yy - c[1]) ** 2 <= rad * rad
+        elif kind == 1:
+            p = rng.uniform(-0.1, 1.1, (3, 2)) * np.array([width, height])
+            d = [(p[(k + 1) % 3, 0] - p[k, 0]) * (yy - p[k, 1]) - (p[(k + 1) % 3, 1] - p[k, 1]) * (xx - p[k, 0])
+                 for k in range(3)]
+            inside = ((d[0] >= 0) & (d[1] >= 0) & (d[2] >= 0)) | ((d[0] <= 0) & (d[1] <= 0) & (d[2] <= 0))
+        else:
+            a = rng.uniform(0, 2 * np.pi)
+            off = rng.uniform(0.2, 0.8, 2) * np.array([width, height])
+            inside = (np.cos(a) * (xx - off[0]) + np.sin(a) * (yy - off[1])) > rng.uniform(0.1, 0.4) * scale
+        m = rng.integers(0, n_mats)
+        col = rng.uniform(0.0, 1.0, 3) * (2.0 if rng.random() < 0.2 else 1.0)
+        ramp = 0.6 + 0.4 * np.cos(rng.uniform(2, 9) * u + rng.uniform(2, 9) * v + rng.uniform(0, 6))
+        if rng.random() < 0.3:
+            k = rng.integers(4, 24)
+            ramp = ramp * np.where(((xx // k + yy // k) % 2) == 0, 1.0, 0.55)
+        img[inside] = (ramp[..., None] * col)[inside]
+        mat[inside] = m
+    return img.astype(np.float32), mat
