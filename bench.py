@@ -75,7 +75,7 @@ def recorded_traffic(args):
 # two-level frames on width-8 clustered hierarchies (about 5% faster).  The
 # batched workload starts from its entry and can be autotuned.
 SHAPES = {"incoherent": (4, 1, "lbvh"), "two_level": (8, 1, "ploc"), "batched": (4, 1, "lbvh"),
-          "serving": (4, 1, "lbvh"), "dynamic": (4, 1, "lbvh")}
+          "serving": (4, 1, "lbvh"), "dynamic": (4, 1, "lbvh"), "post": (8, 1, "ploc")}
 
 
 def log(*a):
@@ -399,6 +399,74 @@ def bench_two_level(args, torch, rg, sg):
     return out, scene
 
 
+# algorithmic bytes per pixel of the post-process passes: each blur pass reads
+# the image (12) and the primary materials (4) and writes the image (12); the
+# luma pass reads the image and writes the luma (4); FXAA reads the luma
+# (its neighbours come from cache) and the image and writes the image
+POST_BYTES = {"blur": 2 * (12 + 4 + 12), "fxaa": (12 + 4) + (4 + 12 + 12)}
+
+
+def bench_post(args, torch, rg, sg):
+    """The two-level frame followed by its post-process passes (roughness
+    blur by the primary materials, then FXAA): the whole frame, and each
+    pass alone against the HBM roofline."""
+    scene = sg.config_two_level()
+    W, H = scene.width, scene.height
+    tl = rg.upload_scene(scene, width=args.width, leaf_max=args.leaf, builder=args.builder)
+    r = rg.Renderer(W, H, scene.max_depth, 0)
+    pm = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    rough = torch.from_numpy(sg.roughness_table(len(scene.materials), scene.seed)).cuda()
+    P = rg.Post(W, H)
+    blurred = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    final = torch.empty_like(blurred)
+    _, st = r.render(tl, scene.materials, scene.camera, scene.light, scene.seed, stats=True, primary_mat=pm)
+    rays = st["rays_traced"] + st["shadow_rays"]
+
+    def frame():
+        img = r.render(tl, scene.materials, scene.camera, scene.light, scene.seed, primary_mat=pm)
+        P.roughness_blur(img, pm, rough, args.post_radius, out=blurred)
+        P.fxaa(blurred, out=final)
+
+    def timed(fn, k):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(k):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    ms = timed(frame, args.steps)
+    img = r.image
+    passes = {"blur": lambda: P.roughness_blur(img, pm, rough, args.post_radius, out=blurred),
+              "fxaa": lambda: P.fxaa(blurred, out=final)}
+    post = {}
+    for name, fn in passes.items():
+        us = timed(fn, 10 * args.steps) * 1e3
+        gbs = POST_BYTES[name] * W * H / (us * 1e-6) / 1e9
+        post[name] = {"us": us, "bytes_per_pixel": POST_BYTES[name], "achieved_GBps": gbs,
+                      "frac_of_hbm": gbs / HBM_PEAK_GBS}
+    render_ms = timed(lambda: r.render(tl, scene.materials, scene.camera, scene.light, scene.seed,
+                                       primary_mat=pm), args.steps)
+    out = {
+        "metric": "Mrays/s closest-hit (primary+incoherent)",
+        "value": rays / (ms * 1e-3) / 1e6, "unit": "Mrays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "two-level: 64 instances of 3 meshes (184,320 unique tris), 1920x1080, "
+                               "Whitted depth 4, whole frames with the post-process passes (roughness blur "
+                               f"radius {args.post_radius} by primary material, FXAA)",
+                   "rays_per_frame": rays, "bvh_width": args.width, "leaf_max": args.leaf,
+                   "builder": args.builder},
+        "render_ms": render_ms, "post_ms": ms - render_ms, "post": post,
+        "roofline": None,
+    }
+    return out, scene
+
+
 def bench_batched(args, torch, rg, sg):
     """Plain per-frame dispatch (one rg_render per frame, one stream) versus one
     batch (every pass one launch over all frames), same frames, same images."""
@@ -626,12 +694,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["incoherent", "two_level", "batched", "serving", "dynamic"],
+    ap.add_argument("--workload", choices=["incoherent", "two_level", "batched", "serving", "dynamic", "post"],
                     default="incoherent")
     ap.add_argument("--scenes", type=int, default=256, help="frames of the batched workload")
     ap.add_argument("--autotune", action="store_true", help="batched: tune width, leaf size and launch "
                     "parameters on a subsample first (cached per GPU and size bucket)")
     ap.add_argument("--segments", type=int, default=560)
+    ap.add_argument("--post-radius", type=int, default=8, help="post: roughness blur window radius")
     ap.add_argument("--requests", type=int, default=1000, help="serving: measured requests per rate")
     ap.add_argument("--warm", type=int, default=100, help="serving: warm-up requests per rate")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: engine memory budget")
@@ -667,7 +736,7 @@ def main():
     import scenegen as sg
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     scope = {"incoherent": "trace", "two_level": "frame", "batched": "frame", "serving": "engine",
-             "dynamic": "trace"}[args.workload]
+             "dynamic": "trace", "post": "frame"}[args.workload]
     rg.trace_tuning(args.refill, args.waves_per_cu, args.lds_depth, args.leaf_batch, args.inst_batch, scope=scope)
     if args.workload == "incoherent":
         out, scene = bench_incoherent(args, torch, rg, sg)
@@ -676,6 +745,8 @@ def main():
             out["cpu_baseline"] = cpu_baseline_incoherent(scene, 64, args.cpu_seconds)
     elif args.workload == "dynamic":
         out, scene = bench_dynamic(args, torch, rg, sg)
+    elif args.workload == "post":
+        out, scene = bench_post(args, torch, rg, sg)
     elif args.workload == "two_level":
         out, scene = bench_two_level(args, torch, rg, sg)
         if not args.no_cpu_baseline:

@@ -397,6 +397,51 @@ rg_status rg_render(const rg_tlas *tlas, const rg_material *mats /*host*/, int32
                     void *scratch, uint64_t scratch_bytes, void *stream,
                     rg_render_stats *stats /*host, nullable*/);
 
+/* rg_render that also writes, per pixel, the material its primary ray shaded
+ * (the clamped material index; RG_MISS where the primary ray saw the sky)
+ * to primary_mat (device uint32[height][width], nullable): the input of the
+ * roughness blur below.  primary_mat needs mode 0 (RG_ERR_UNSUPPORTED
+ * otherwise). */
+rg_status rg_render_ex(const rg_tlas *tlas, const rg_material *mats /*host*/, int32_t n_mats,
+                       const rg_camera *cam /*host*/, const rg_light *light /*host*/, int32_t width,
+                       int32_t height, int32_t max_depth, int32_t mode, uint64_t seed, float *image,
+                       uint32_t *primary_mat, void *scratch, uint64_t scratch_bytes, void *stream,
+                       rg_render_stats *stats /*host, nullable*/);
+
+/* ------------------------------------------------------- post-process */
+/* The frame's post-process passes (section 2.1: the engine's compute system
+ * runs a screen-space roughness approximation and fast approximate
+ * anti-aliasing on the traced image).  Images are device float[height][width]
+ * [3] (the render's layout); input and output must not overlap, nor either
+ * overlap the scratch buffer.  Asynchronous.  width * height <= 2^30. */
+
+/* Scratch bytes for either pass (16 per pixel, rounded). */
+rg_status rg_post_sizes(int32_t width, int32_t height, uint64_t *scratch_bytes /*host*/);
+
+/* Material-aware Gaussian blur whose width follows the roughness of the
+ * material seen at each pixel: two 1-D passes (along x, then y), each over
+ * the taps k = -radius..radius with weights exp(-k^2 / (2 sigma^2)), sigma =
+ * r radius / 3 (r = roughness[mat] clamped to [0, 1]); a tap counts if it lies
+ * inside the image and shows the centre pixel's material; weights are
+ * normalised over the taps that count.  Pixels whose material is RG_MISS,
+ * >= n_mats or has roughness below 1/256 are copied.  mat: device
+ * uint32[height][width]; roughness: device float[n_mats].
+ * Errors: RG_ERR_INVALID_ARG (NULL pointers, sizes, radius outside
+ * 0..RG_BLUR_RADIUS_MAX, overlapping buffers), RG_ERR_OUT_OF_MEMORY (scratch
+ * below rg_post_sizes). */
+#define RG_BLUR_RADIUS_MAX 16
+rg_status rg_roughness_blur(const float *in, const uint32_t *mat, const float *roughness, int32_t n_mats,
+                            int32_t width, int32_t height, int32_t radius, float *out, void *scratch,
+                            uint64_t scratch_bytes, void *stream);
+
+/* Fast approximate anti-aliasing (Lottes 2009, the "quality" variant) on the
+ * perceptual luma sqrt(clamp(0.299 R + 0.587 G + 0.114 B, 0, 1)): edge
+ * threshold max(1/16, 1/8 of the local maximum luma), edge search steps 1 (x5),
+ * 1.5, 2 (x4), 4, 8 pixels each way, sub-pixel strength 3/4, clamp-to-edge.
+ * Errors as rg_roughness_blur. */
+rg_status rg_fxaa(const float *in, int32_t width, int32_t height, float *out, void *scratch,
+                  uint64_t scratch_bytes, void *stream);
+
 /* ------------------------------------------------------------ batches */
 /* Many frames of different scenes and sizes rendered together: every pass of
  * the Whitted recursion (closest hit, shading, shadow any hit, shadow

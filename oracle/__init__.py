@@ -79,6 +79,7 @@ def _load():
         lib.or_ao_rays.argtypes = [P, P, i64, u64, i32, P, P, P]
         lib.or_render.restype = i64
         lib.or_render.argtypes = [P, P, P, i32, i32, i32, i32, u64, P, i64, i32, P, P, P]
+        lib.or_primary_materials.argtypes = [P, P, i32, i32, P, i64, i32, P, P]
         _lib = lib
         return lib
 
@@ -205,6 +206,21 @@ class Scene:
         tests = self._lib.or_render(self.h, _ptr(cam), _ptr(light), W, H, D, M, S, _ptr(pixels), n,
                                     threads or default_threads(), _ptr(rgb), _ptr(amb), _ptr(nrays))
         return dict(rgb=rgb, amb=amb, nrays=nrays, tests=int(tests))
+
+
+    def primary_materials(self, pixels, width=None, height=None, threads: int = 0) -> dict:
+        """The material index of each listed pixel's primary hit (MISS for the
+        sky) and whether that hit is ambiguous."""
+        sc = self.scene
+        W = sc.width if width is None else width
+        H = sc.height if height is None else height
+        pixels = np.ascontiguousarray(pixels, np.int64)
+        n = pixels.shape[0]
+        mat = np.empty(n, np.uint32)
+        amb = np.empty(n, np.uint8)
+        self._lib.or_primary_materials(self.h, _ptr(camera_array(sc.camera)), W, H, _ptr(pixels), n,
+                                       threads or default_threads(), _ptr(mat), _ptr(amb))
+        return dict(mat=mat, amb=amb)
 
 
 def camera_rays(camera, width: int, height: int, pixels) -> np.ndarray:

@@ -1029,6 +1029,45 @@ int64_t or_render(or_scene *S, const float *cam, const float *light, int32_t W, 
     return C.tests;
 }
 
+/* The material index each listed pixel's primary ray meets (0xFFFFFFFF for
+ * the sky) and whether that primary hit is ambiguous: the first shading
+ * decision of the render above, on its own. */
+typedef struct {
+    const or_scene *S;
+    const float *cam;
+    int32_t W, H;
+    const int64_t *pixels;
+    uint32_t *mat;
+    uint8_t *amb;
+} primary_ctx;
+
+static void primary_task(void *vctx, int64_t i) {
+    primary_ctx *c = (primary_ctx *)vctx;
+    or_ray R;
+    camera_ray(c->cam, c->W, c->H, c->pixels[i], R.o, R.d);
+    R.tmin = 0.0;
+    R.tmax = INFINITY;
+    R.sig_pos = 0.0;
+    R.sig_dir = OR_K * OR_EPS32;
+    or_result h;
+    or_trace_one(c->S, &R, 0, 0, 0xFFu, 0u, &h);
+    c->amb[i] = (uint8_t)h.amb;
+    if (!h.hit) {
+        c->mat[i] = 0xFFFFFFFFu;
+        return;
+    }
+    hit_geom g;
+    hit_geometry(c->S, &R, &h, &g);
+    c->mat[i] = g.mat;
+}
+
+void or_primary_materials(or_scene *S, const float *cam, int32_t W, int32_t H, const int64_t *pixels, int64_t n,
+                          int32_t nthreads, uint32_t *mat, uint8_t *amb) {
+    ensure_adjacency(S);
+    primary_ctx C = {S, cam, W, H, pixels, mat, amb};
+    pool_run(primary_task, &C, n, nthreads);
+}
+
 /* Ambient-occlusion rays of input rays: for each ray with a closest hit, the
  * 8 rays (origin, direction) the incoherent workload spawns there; out is
  * [n][8][6] (undefined for misses), hit/amb per input ray. */

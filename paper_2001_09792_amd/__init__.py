@@ -27,6 +27,7 @@ MISS = 0xFFFFFFFF
 PER_PRIM = 0xFFFFFFFF
 MAX_DEPTH = 8
 RG_LEVELS_CAP = 255   # include/rg.h: deepest bottom level whose level table is kept
+RG_BLUR_RADIUS_MAX = 16  # include/rg.h: widest roughness-blur window
 
 c_f = ctypes.c_float
 c_i32 = ctypes.c_int32
@@ -139,6 +140,11 @@ SIGNATURES = {
     "rg_render_sizes": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_p]),
     "rg_render": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_u64, c_p, c_p, c_u64,
                           c_p, c_p]),
+    "rg_render_ex": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_u64, c_p, c_p, c_p,
+                             c_u64, c_p, c_p]),
+    "rg_post_sizes": (c_i32, [c_i32, c_i32, c_p]),
+    "rg_roughness_blur": (c_i32, [c_p, c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_p, c_p, c_u64, c_p]),
+    "rg_fxaa": (c_i32, [c_p, c_i32, c_i32, c_p, c_p, c_u64, c_p]),
     "rg_refit_sizes": (c_i32, [c_p, c_p]),
     "rg_refit_blas": (c_i32, [c_p, c_p, c_i64, c_p, c_i64, c_p, c_u64, c_p]),
     "rg_blas_state": (c_i32, [c_p, c_p, c_p, c_p, c_p]),
@@ -567,18 +573,71 @@ class Renderer:
         self.scratch = _bytes(render_sizes(width, height, max_depth, mode), device)
         self.image = torch.empty((height, width, 3), dtype=torch.float32, device=device)
 
-    def render(self, tlas: Tlas, mats, camera, light, seed: int = 0, stats: bool = False, stream=None):
+    def render(self, tlas: Tlas, mats, camera, light, seed: int = 0, stats: bool = False, stream=None,
+               primary_mat=None):
+        """primary_mat: optional CUDA int32/uint32 [H, W] receiving the material
+        each primary ray shaded (0xFFFFFFFF for the sky)."""
         ma = materials_array(mats)
         cd, ld = camera_desc(camera), light_desc(light)
         st = RenderStats()
-        _check("rg_render", _lib.rg_render(tlas.ref, ma, len(mats), ctypes.byref(cd), ctypes.byref(ld),
-                                           self.width, self.height, self.max_depth, self.mode, seed,
-                                           _ptr(self.image), _ptr(self.scratch), self.scratch.numel(),
-                                           _stream(stream), ctypes.byref(st) if stats else None))
+        if primary_mat is not None:
+            _need_image(primary_mat, self.height, self.width, 1, "primary_mat")
+        _check("rg_render_ex", _lib.rg_render_ex(tlas.ref, ma, len(mats), ctypes.byref(cd), ctypes.byref(ld),
+                                                 self.width, self.height, self.max_depth, self.mode, seed,
+                                                 _ptr(self.image), _ptr(primary_mat), _ptr(self.scratch),
+                                                 self.scratch.numel(), _stream(stream),
+                                                 ctypes.byref(st) if stats else None))
         if stats:
             return self.image, dict(rays_traced=int(st.rays_traced), shadow_rays=int(st.shadow_rays),
                                     ms_total=float(st.ms_total))
         return self.image
+
+
+def _need_image(t, h: int, w: int, c: int, name: str):
+    torch = _torch()
+    want = (h, w, 3) if c == 3 else (h, w)
+    ok_dtype = (torch.float32,) if c == 3 else (torch.int32, torch.uint32) if hasattr(torch, "uint32") \
+        else (torch.int32,)
+    if tuple(t.shape) != want or t.dtype not in ok_dtype or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous CUDA tensor of shape {want} and dtype {ok_dtype}")
+
+
+def post_sizes(width: int, height: int) -> int:
+    s = ctypes.c_uint64()
+    _check("rg_post_sizes", _lib.rg_post_sizes(width, height, ctypes.byref(s)))
+    return int(s.value)
+
+
+class Post:
+    """The frame's post-process passes (rg_roughness_blur, rg_fxaa) with
+    their scratch buffer for one image size."""
+
+    def __init__(self, width: int, height: int, device="cuda"):
+        self.width, self.height = width, height
+        self.scratch = _bytes(post_sizes(width, height), device)
+
+    def _out(self, image, out):
+        torch = _torch()
+        _need_image(image, self.height, self.width, 3, "image")
+        if out is None:
+            out = torch.empty_like(image)
+        _need_image(out, self.height, self.width, 3, "out")
+        return out
+
+    def roughness_blur(self, image, primary_mat, roughness, radius: int = 8, out=None, stream=None):
+        """roughness: CUDA float32 [n_mats]."""
+        out = self._out(image, out)
+        _need_image(primary_mat, self.height, self.width, 1, "primary_mat")
+        _check("rg_roughness_blur", _lib.rg_roughness_blur(
+            _ptr(image), _ptr(primary_mat), _ptr(roughness), roughness.numel(), self.width, self.height, radius,
+            _ptr(out), _ptr(self.scratch), self.scratch.numel(), _stream(stream)))
+        return out
+
+    def fxaa(self, image, out=None, stream=None):
+        out = self._out(image, out)
+        _check("rg_fxaa", _lib.rg_fxaa(_ptr(image), self.width, self.height, _ptr(out), _ptr(self.scratch),
+                                       self.scratch.numel(), _stream(stream)))
+        return out
 
 
 class Batch:

@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librg.so")
-SOURCES = ["build.hip", "trace.hip", "render.hip", "serve.hip"]
+SOURCES = ["build.hip", "trace.hip", "render.hip", "serve.hip", "post.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -251,7 +251,10 @@ __global__ void __launch_bounds__(kShadeT) k_shade(ShadeArgs a) {
         float o[3] = {a.in.ray[0][i], a.in.ray[1][i], a.in.ray[2][i]};
         float d[3] = {a.in.ray[3][i], a.in.ray[4][i], a.in.ray[5][i]};
         uint32_t rec = a.hit_rec[i];
+        const bool primary = a.pass == a.jobs[job].start;
+        uint32_t *gbuf = primary ? a.jobs[job].gbuf : nullptr;
         if (rec == RG_MISS) {
+            if (gbuf) gbuf[pixel - a.jobs[job].pix_off] = RG_MISS;
             float dn[3] = {d[0], d[1], d[2]};
             normalize3(dn);
             float s = 0.5f * (dn[1] + 1.0f);
@@ -263,6 +266,7 @@ __global__ void __launch_bounds__(kShadeT) k_shade(ShadeArgs a) {
             HitGeom g;
             hit_geometry(a.tlas[job].recs, rec, a.hit_slot[i], o, d, a.hit_t[i], g);
             uint32_t mid = g.mat < J.n_mats ? g.mat : J.n_mats - 1;
+            if (gbuf) gbuf[pixel - J.pix_off] = mid;
             const RgMat M = a.mats[J.mat_off + mid];
             float eps = offset_eps(g.p);
             if (M.type == 0) {
@@ -937,8 +941,17 @@ rg_status rg_render(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats
                     const rg_light *light, int32_t width, int32_t height, int32_t max_depth, int32_t mode,
                     uint64_t seed, float *image, void *scratch, uint64_t scratch_bytes, void *stream,
                     rg_render_stats *stats) {
+    return rg_render_ex(tlas, mats, n_mats, cam, light, width, height, max_depth, mode, seed, image, nullptr,
+                        scratch, scratch_bytes, stream, stats);
+}
+
+rg_status rg_render_ex(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats, const rg_camera *cam,
+                       const rg_light *light, int32_t width, int32_t height, int32_t max_depth, int32_t mode,
+                       uint64_t seed, float *image, uint32_t *primary_mat, void *scratch, uint64_t scratch_bytes,
+                       void *stream, rg_render_stats *stats) {
     if (!tlas_valid(tlas) || !mats || n_mats < 1 || n_mats > 256 || !cam || !light || !image || !scratch)
         return RG_ERR_INVALID_ARG;
+    if (primary_mat && mode != 0) return RG_ERR_UNSUPPORTED;
     uint64_t need = 0;
     rg_status r = rg_render_sizes(width, height, max_depth, mode, &need);
     if (r != RG_OK) return r;
@@ -966,6 +979,7 @@ rg_status rg_render(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats
         J.n_mats = (uint32_t)n_mats;
         J.max_depth = max_depth;
         J.image = image;
+        J.gbuf = primary_mat;
         RgTlasRef T = {(const char *)tlas->buf + tlas->nodes_off,
                        (const RgInst *)((const char *)tlas->buf + tlas->inst_off)};
         if ((r = rg_wave_reset(b, st)) != RG_OK) return r;

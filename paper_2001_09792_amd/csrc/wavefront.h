@@ -35,6 +35,7 @@ struct RgJobDev {
     int32_t max_depth;
     int64_t start;
     float *image;
+    uint32_t *gbuf;  // nullable: the material each primary ray shaded (RG_MISS: sky)
 };
 
 // Device buffers of a wavefront render, carved from one caller buffer:

@@ -202,3 +202,27 @@ def test_trace_options_and_instance_flags_are_checked_on_the_host():
     o = rg.BuildOpts(4, 4)
     assert lib.rg_build_tlas_ex(blas, 1, xf, bid, im, fl, 1, ctypes.byref(o), 256, 1 << 20, 256, 1 << 20, None,
                                 ctypes.byref(t)) == -1
+
+
+def test_post_process_arguments_are_checked_on_the_host():
+    import paper_2001_09792_amd as rg
+    lib = rg._lib
+    need = ctypes.c_uint64()
+    assert lib.rg_post_sizes(1920, 1080, ctypes.byref(need)) == 0 and need.value >= 16 * 1920 * 1080
+    assert lib.rg_post_sizes(0, 10, ctypes.byref(need)) == -1
+    assert lib.rg_post_sizes(1 << 16, 1 << 15, ctypes.byref(need)) == -1      # above 2^30 pixels
+    lib.rg_post_sizes(64, 32, ctypes.byref(need))
+    n = 64 * 32
+    a, b, m, r, s = 1 << 20, 1 << 24, 1 << 26, 1 << 27, 1 << 28        # disjoint fake device addresses
+    big = need.value
+    assert lib.rg_roughness_blur(None, m, r, 4, 64, 32, 8, b, s, big, None) == -1
+    assert lib.rg_roughness_blur(a, m, r, 0, 64, 32, 8, b, s, big, None) == -1            # no materials
+    assert lib.rg_roughness_blur(a, m, r, 4, 64, 32, rg.RG_BLUR_RADIUS_MAX + 1, b, s, big, None) == -1
+    assert lib.rg_roughness_blur(a, m, r, 4, 64, 32, -1, b, s, big, None) == -1
+    assert lib.rg_roughness_blur(a, m, r, 4, 64, 32, 8, b, s, big - 1, None) == -2      # short scratch
+    assert lib.rg_roughness_blur(a, m, r, 4, 64, 32, 8, a + 12 * n - 4, s, big, None) == -1   # in / out overlap
+    assert lib.rg_roughness_blur(a, m, r, 4, 64, 32, 8, b, a + 8, big, None) == -1       # scratch over the input
+    assert lib.rg_fxaa(a, 64, 32, a, s, big, None) == -1
+    assert lib.rg_fxaa(a, 64, 32, b, s, 100, None) == -2
+    assert lib.rg_fxaa(a, 64, 0, b, s, big, None) == -1
+    assert lib.rg_fxaa(a, 64, 32, b, b - 12 * n + 256, big, None) == -1                 # luma scratch over the output

@@ -164,3 +164,32 @@ def test_fxaa_edge_end_by_hand():
     assert r["offset"][4, 2] == pytest.approx(off, abs=1e-15)
     assert np.allclose(r["rgb"][4, 2], 1.0 - off, atol=1e-15)
     assert (r["nx"][4, 2], r["ny"][4, 2]) == (2, 3)
+
+
+def test_primary_materials_by_hand():
+    """Two quads side by side at z = 0 seen from z = 5 (vertical field of view
+    90 degrees, so the image plane at z = 0 spans y in [-5, 5]): the left quad
+    x in [-2, 0] has per-triangle materials 3 (lower triangle) and 4, the
+    right one x in [0, 2] the instance material 1; pixels whose centre ray
+    meets neither are sky."""
+    import oracle
+    from tests.helpers import scene_from_meshes
+    left = sg.triangles_mesh([[(-2, -2, 0), (0, -2, 0), (0, 2, 0)], [(-2, -2, 0), (0, 2, 0), (-2, 2, 0)]])
+    left.prim_mat = np.array([3, 4], np.uint16)
+    right = sg.triangles_mesh([[(0, -2, 0), (2, -2, 0), (2, 2, 0)], [(0, -2, 0), (2, 2, 0), (0, 2, 0)]])
+    mats = sg.materials([(sg.DIFFUSE, (0.5, 0.5, 0.5), 1.5)] * 5)
+    W = H = 20
+    sc = scene_from_meshes([left, right], inst_mat=[sg.PER_PRIM, 1], mats=mats, width=W, height=H,
+                           camera=sg.Camera((0.0, 0.0, 5.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 90.0))
+    px = np.arange(W * H)
+    r = oracle.Scene(sc).primary_materials(px)
+    # pixel centre (i + 1/2, j + 1/2) -> world x = (i + 1/2 - 10) / 2, y = (10 - j - 1/2) / 2 at z = 0
+    i, j = px % W, px // W
+    x, y = (i + 0.5 - W / 2) / 2.0, (H / 2 - j - 0.5) / 2.0
+    # the left quad's diagonal runs from (-2, -2) to (0, 2): below it (y < 2x + 2) is triangle 0
+    want = np.where((np.abs(x) > 2) | (np.abs(y) > 2), sg.MISS,
+                    np.where(x > 0, 1, np.where(y < 2 * x + 2, 3, 4))).astype(np.uint32)
+    ok = r["amb"] == 0
+    assert ok.mean() > 0.9
+    assert np.array_equal(r["mat"][ok], want[ok])
+    assert set(np.unique(want[ok])) == {1, 3, 4, sg.MISS}
