@@ -73,6 +73,7 @@ def _load():
         lib.or_trace.argtypes = [P, P, i64, i32, i32, P, P, P, P, P, P, P, P, P, P, P, P, i32, P,
                                  ctypes.c_uint32, ctypes.c_uint32]
         lib.or_set_inst_flags.argtypes = [P, P]
+        lib.or_set_alpha.argtypes = [P, i32, P, i32]
         lib.or_camera_rays.argtypes = [P, i32, i32, P, i64, P]
         lib.or_ao_uniforms.argtypes = [u64, u64, P, P]
         lib.or_ao_direction.argtypes = [P, ctypes.c_double, ctypes.c_double, P]
@@ -106,9 +107,11 @@ def light_array(light) -> np.ndarray:
 class Scene:
     """FP64 oracle view of a `scenegen.Scene` (or of explicit arrays)."""
 
-    def __init__(self, scene, sphere_reject: bool = False, inst_flags=None):
+    def __init__(self, scene, sphere_reject: bool = False, inst_flags=None, alpha=None):
         """inst_flags: uint32 per instance (bits 0-7 visibility mask,
-        INST_CULL_DISABLE, INST_FLIP_FACING), default 0xFF."""
+        INST_CULL_DISABLE, INST_FLIP_FACING), default 0xFF.  alpha: per
+        bottom level None or (uint64 mask per triangle, level 0..3): the
+        opacity of the triangle's 4^level micro-triangles (see or_set_alpha)."""
         lib = _load()
         self._lib = lib
         self.scene = scene
@@ -137,6 +140,14 @@ class Scene:
             self._flags = np.ascontiguousarray(inst_flags, np.uint32)
             assert self._flags.shape == (self._xf.shape[0],)
             lib.or_set_inst_flags(self.h, _ptr(self._flags))
+        self._alpha = []
+        for b, a in enumerate(alpha or []):
+            if a is None:
+                continue
+            mask, level = np.ascontiguousarray(a[0], np.uint64), int(a[1])
+            assert mask.shape == (scene.blas[b].n_tris,) and 0 <= level <= 3
+            self._alpha.append(mask)
+            lib.or_set_alpha(self.h, b, _ptr(mask), level)
 
     def set_sphere_reject(self, on: bool):
         self._lib.or_set_sphere_reject(self.h, 1 if on else 0)

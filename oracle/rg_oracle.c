@@ -58,6 +58,8 @@ typedef struct {
     int8_t *nslot;            /* [T][3] that edge's slot in the neighbour */
     double lo[3], hi[3];      /* object-space box of the vertices */
     double sc[3], sr;         /* bounding sphere */
+    const uint64_t *alpha;    /* borrowed, may be NULL: opacity of 4^alpha_level micro-triangles per triangle */
+    int32_t alpha_level;
 } or_blas;
 
 typedef struct {
@@ -309,6 +311,53 @@ void or_set_sphere_reject(or_scene *s, int32_t on) { s->sphere_reject = on; }
 /* Per-instance visibility mask and facing flags (default: mask 0xFF, none). */
 void or_set_inst_flags(or_scene *s, const uint32_t *flags) {
     for (int64_t i = 0; i < s->ni; ++i) s->inst[i].flags = flags[i];
+}
+
+/* Opacity masks (alpha-tested triangles): triangle j of bottom level b is
+ * split into 4^level micro-triangles by cutting each edge into n = 2^level
+ * equal parts; in barycentric coordinates (u, v) (the weights of the second
+ * and third vertex) scaled by n, the cell (i, j) = (floor U, floor V) holds an
+ * upright micro-triangle (fractional parts summing to at most 1) and, unless
+ * it touches the far edge, an inverted one; they are numbered row by row
+ * (row j starts at j (2n - j)), upright 2i, inverted 2i + 1.  Bit k of the
+ * triangle's mask set: micro-triangle k is opaque (its hits are accepted). */
+void or_set_alpha(or_scene *s, int32_t b, const uint64_t *alpha, int32_t level) {
+    s->blas[b].alpha = alpha;
+    s->blas[b].alpha_level = level;
+}
+
+static int alpha_index(int level, double u, double v) {
+    const int n = 1 << level;
+    const double U = u * n, V = v * n;
+    int i = (int)floor(U), j = (int)floor(V);
+    if (i < 0) i = 0;
+    if (j < 0) j = 0;
+    if (i > n - 1) i = n - 1;
+    if (j > n - 1 - i) j = n - 1 - i;
+    const int inverted = (U - i) + (V - j) > 1.0 && i + j < n - 1;
+    return j * (2 * n - j) + 2 * i + inverted;
+}
+
+/* 1: the hit at (u, v) is accepted; 0: ignored. */
+static int alpha_open(const or_blas *B, int64_t j, double u, double v) {
+    if (!B->alpha) return 1;
+    return (int)((B->alpha[j] >> alpha_index(B->alpha_level, u, v)) & 1u);
+}
+
+/* As alpha_open, or -1 when float32 barycentrics within `beta` of (u, v)
+ * could fall on a micro-triangle of the other opacity: within 2 beta of a
+ * cut line (U, V or U + V an integer, the triangle's own edges included)
+ * of a triangle whose micro-triangles are not all alike. */
+static int alpha_state(const or_blas *B, int64_t j, double u, double v, double beta) {
+    if (!B->alpha) return 1;
+    const int n = 1 << B->alpha_level;
+    const uint64_t all = n == 8 ? ~0ull : ((1ull << (n * n)) - 1ull);
+    const uint64_t m = B->alpha[j] & all;
+    const int open = (int)((B->alpha[j] >> alpha_index(B->alpha_level, u, v)) & 1u);
+    if (m == 0 || m == all) return open;
+    const double U = u * n, V = v * n, S = U + V;
+    const double d = fmin(fmin(fabs(U - nearbyint(U)), fabs(V - nearbyint(V))), fabs(S - nearbyint(S)) / 1.4142135623730951);
+    return d <= 2.0 * beta * n ? -1 : open;
 }
 
 /* Whether triangle T of instance I is ignored by a ray with cull flags
@@ -565,6 +614,7 @@ static void or_trace_one(const or_scene *S, const or_ray *R, int any, int cover,
             if (u < 0.0 || v < 0.0 || 1.0 - u - v < 0.0) continue;
             if (t < R->tmin || t > R->tmax) continue;
             if (culled(I, cull, B->tri + 9 * j, d)) continue;
+            if (!alpha_open(B, j, u, v)) continue;
             if (t < res->t) {
                 res->hit = 1; res->t = t; res->u = u; res->v = v;
                 res->inst = (uint32_t)i; res->prim = (uint32_t)j;
@@ -602,8 +652,21 @@ static void or_trace_one(const or_scene *S, const or_ray *R, int any, int cover,
                 /* a float32 test may decide the facing of a nearly grazing
                  * triangle the other way: ambiguous if it could be the hit */
                 if (e.cosg < 1e-3 && m >= -beta && t >= R->tmin - delta &&
-                    (any || t <= tlim * (1.0 + 1e-5) + delta))
-                    res->amb = 1;
+                    (any || t <= tlim * (1.0 + 1e-5) + delta)) {
+                    if (any) near_band = 1;
+                    else res->amb = 1;
+                }
+                continue;
+            }
+            const int open = alpha_state(B, j, e.u, e.v, beta);
+            if (open <= 0) {
+                /* ignored by its opacity mask; ambiguous if float32
+                 * barycentrics may land on an opaque micro-triangle and the
+                 * triangle could be the hit */
+                if (open < 0 && m >= -beta && t >= R->tmin - delta && (any || t <= tlim * (1.0 + 1e-5) + delta)) {
+                    if (any) near_band = 1;
+                    else res->amb = 1;
+                }
                 continue;
             }
             double tmax_band = fin_tmax ? fmax(1e-5 * R->tmax, delta) : 0.0;
