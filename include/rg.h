@@ -92,10 +92,12 @@ typedef struct {
 
 /* Bottom-level structure: a POD descriptor of the caller's output buffer.
  * Layout of `buf` (all offsets in bytes from buf):
- *   0:         64-byte header: four uint64 device addresses (nodes, tris,
+ *   0:         128-byte header: four uint64 device addresses (nodes, tris,
  *              mats, slots: the arrays below), the root box float lo[3],
  *              hi[3] (kept current by rg_refit_blas), uint32 status of the
- *              last refit's input check (0: valid), uint32 padding.
+ *              last refit's input check (0: valid), uint32 padding, uint64
+ *              device address of the opacity masks (0: none), uint32 their
+ *              level, padding.
  *   nodes_off: n_nodes nodes of 32*width bytes (width 4: 128 B):
  *              float lo_x[w], lo_y[w], lo_z[w], hi_x[w], hi_y[w], hi_z[w];
  *              uint32 child[w]; padding to 32*width bytes.
@@ -120,6 +122,7 @@ typedef struct {
     int64_t n_tris, n_nodes;
     int32_t width, leaf_max, depth, has_mats;
     float lo[3], hi[3]; /* root box (object space) at build time; the header holds the current one */
+    int32_t has_alpha, alpha_level; /* opacity masks attached by rg_blas_set_alpha */
 } rg_blas;
 
 /* Top-level structure.  Layout of `buf`:
@@ -238,6 +241,24 @@ rg_status rg_refit_blas_many(rg_blas *blas /*host [n_blas]*/, int32_t n_blas,
                              const float *const *verts /*host [n_blas]*/, const int64_t *n_verts /*host*/,
                              const uint32_t *const *idx /*host [n_blas]*/, const int64_t *n_tris /*host*/,
                              void *scratch, uint64_t scratch_bytes, void *stream);
+
+/* Opacity masks: the accept / ignore decision an any-hit stage takes for
+ * alpha-tested geometry, per point of a triangle.  Each triangle is cut into
+ * 4^level micro-triangles by splitting every edge into n = 2^level equal
+ * parts; with (u, v) the barycentric weights of its second and third vertex
+ * (those of rg_hits), scaled by n, the cell (i, j) = (floor(n u), floor(n v))
+ * holds an upright micro-triangle (fractional parts summing to at most 1)
+ * and, unless it touches the far edge, an inverted one; they are numbered
+ * row by row, row j starting at j (2n - j), upright 2i, inverted 2i + 1.  Bit
+ * k of a triangle's mask set: hits on micro-triangle k are accepted, else the
+ * ray passes through.  alpha: device uint64[n_tris] in input order, read
+ * while tracing (it must outlive every trace and render of the bottom level),
+ * NULL to remove the masks; level 0..RG_ALPHA_LEVEL_MAX.  Writes the buffer's
+ * header (asynchronous, on `stream`) and updates *blas; top levels over the
+ * bottom level must be built again afterwards.  The masks apply to every
+ * trace and render call.  Errors: RG_ERR_INVALID_ARG. */
+#define RG_ALPHA_LEVEL_MAX 3
+rg_status rg_blas_set_alpha(rg_blas *blas, const uint64_t *alpha, int32_t level, void *stream);
 
 /* Reads a bottom level's header: current root box and the status of its last
  * refit (0: valid input).  Synchronous (waits for `stream`). */

@@ -28,6 +28,7 @@ PER_PRIM = 0xFFFFFFFF
 MAX_DEPTH = 8
 RG_LEVELS_CAP = 255   # include/rg.h: deepest bottom level whose level table is kept
 RG_BLUR_RADIUS_MAX = 16  # include/rg.h: widest roughness-blur window
+RG_ALPHA_LEVEL_MAX = 3   # include/rg.h: finest opacity-mask subdivision (4^3 micro-triangles)
 
 c_f = ctypes.c_float
 c_i32 = ctypes.c_int32
@@ -49,7 +50,7 @@ class BlasDesc(ctypes.Structure):
     _fields_ = [("buf", c_p), ("nodes_off", c_u64), ("tris_off", c_u64), ("mats_off", c_u64),
                 ("slots_off", c_u64), ("parents_off", c_u64), ("levels_off", c_u64), ("n_tris", c_i64), ("n_nodes", c_i64), ("width", c_i32),
                 ("leaf_max", c_i32), ("depth", c_i32), ("has_mats", c_i32), ("lo", c_f * 3),
-                ("hi", c_f * 3)]
+                ("hi", c_f * 3), ("has_alpha", c_i32), ("alpha_level", c_i32)]
 
 
 class TlasDesc(ctypes.Structure):
@@ -143,6 +144,7 @@ SIGNATURES = {
     "rg_render_ex": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_u64, c_p, c_p, c_p,
                              c_u64, c_p, c_p]),
     "rg_post_sizes": (c_i32, [c_i32, c_i32, c_p]),
+    "rg_blas_set_alpha": (c_i32, [c_p, c_p, c_i32, c_p]),
     "rg_roughness_blur": (c_i32, [c_p, c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_p, c_p, c_u64, c_p]),
     "rg_fxaa": (c_i32, [c_p, c_i32, c_i32, c_p, c_p, c_u64, c_p]),
     "rg_refit_sizes": (c_i32, [c_p, c_p]),
@@ -243,6 +245,7 @@ class Blas:
     def __init__(self, buf, desc: BlasDesc):
         self.buf = buf
         self.desc = desc
+        self.alpha = None  # opacity masks attached with set_alpha (kept alive here)
 
     @property
     def n_tris(self) -> int:
@@ -591,6 +594,23 @@ class Renderer:
             return self.image, dict(rays_traced=int(st.rays_traced), shadow_rays=int(st.shadow_rays),
                                     ms_total=float(st.ms_total))
         return self.image
+
+
+def set_alpha(blas: Blas, masks, level: int = 3, stream=None) -> Blas:
+    """Attaches opacity masks to a bottom level (rg_blas_set_alpha): masks is
+    a CUDA int64 tensor with one 64-bit mask per input triangle (bit k: the
+    k-th of the 4^level micro-triangles is opaque), or None to remove them.
+    The bottom level keeps a reference to the tensor; top levels over it must
+    be built again."""
+    torch = _torch()
+    if masks is not None:
+        if masks.dtype not in (torch.int64,) + ((torch.uint64,) if hasattr(torch, "uint64") else ()) or \
+                not masks.is_cuda or not masks.is_contiguous() or masks.numel() != blas.desc.n_tris:
+            raise ValueError("masks must be a contiguous CUDA int64 tensor with one entry per triangle")
+    _check("rg_blas_set_alpha", _lib.rg_blas_set_alpha(ctypes.byref(blas.desc), _ptr(masks), level,
+                                                       _stream(stream)))
+    blas.alpha = masks
+    return blas
 
 
 def _need_image(t, h: int, w: int, c: int, name: str):

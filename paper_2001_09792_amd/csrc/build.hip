@@ -692,6 +692,13 @@ __global__ void k_blas_header(RgBlasHdr *h, uint64_t nodes, uint64_t tris, uint6
     h->hi[0] = hx; h->hi[1] = hy; h->hi[2] = hz;
     h->status = 0u;
     h->pad = 0u;
+    h->alpha = 0ull;
+    h->alpha_level = 0u;
+}
+
+__global__ void k_blas_alpha(RgBlasHdr *h, uint64_t alpha, uint32_t level) {
+    h->alpha = alpha;
+    h->alpha_level = level;
 }
 
 // --------------------------------------------------------------- refit
@@ -1007,7 +1014,7 @@ __global__ void k_inst_setup(const float *__restrict__ xform, const uint32_t *__
         r.blo[q] = B.lo[q];
         r.bhi[q] = B.hi[q];
     }
-    r.flags = inst_flags ? inst_flags[i] : RG_INST_MASK_ALL;
+    r.flags = (inst_flags ? inst_flags[i] : RG_INST_MASK_ALL) | (B.alpha ? RG_INST_ALPHA : 0u);
     r.pad = 0u;
     recs[i] = r;
 }
@@ -1425,6 +1432,8 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
         out->lo[k] = lo.lo[k];
         out->hi[k] = lo.hi[k];
     }
+    out->has_alpha = 0;
+    out->alpha_level = 0;
     return RG_OK;
 }
 
@@ -1530,6 +1539,16 @@ rg_status rg_blas_state(const rg_blas *blas, float *lo, float *hi, uint32_t *sta
     return RG_OK;
 }
 
+rg_status rg_blas_set_alpha(rg_blas *blas, const uint64_t *alpha, int32_t level, void *stream) {
+    if (!blas || !blas->buf || (alpha && (level < 0 || level > RG_ALPHA_LEVEL_MAX))) return RG_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    k_blas_alpha<<<1, 1, 0, st>>>((RgBlasHdr *)blas->buf, (uint64_t)alpha, alpha ? (uint32_t)level : 0u);
+    RG_LAUNCH_CHECK();
+    blas->has_alpha = alpha ? 1 : 0;
+    blas->alpha_level = alpha ? level : 0;
+    return RG_OK;
+}
+
 rg_status rg_tlas_sizes(int64_t n_inst, const rg_build_opts *opts, rg_sizes *out) {
     Opts o;
     if (!out || n_inst < 1 || n_inst > RG_MAX_TRIS || !opts_ok(opts, &o)) return RG_ERR_INVALID_ARG;
@@ -1615,6 +1634,8 @@ rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xfo
     out->depth = lo.depth;
     out->max_blas_depth = max_depth;
     out->has_inst_flags = 0;
+    for (int32_t b = 0; b < n_blas; ++b)
+        if (blas[b].has_alpha) out->has_inst_flags = 1;
     if (inst_flags)
         for (int64_t i = 0; i < n_inst; ++i)
             if (inst_flags[i] != RG_INST_MASK_ALL) out->has_inst_flags = 1;

@@ -44,8 +44,16 @@ struct RgBlasHdr {
     float lo[3], hi[3];  // root box: written by the build and by every refit
     uint32_t status;     // flags of the last refit's input check (0: valid)
     uint32_t pad;
+    uint64_t alpha;        // opacity masks, uint64 per input triangle (0: every triangle opaque)
+    uint32_t alpha_level;  // micro-triangles per triangle: 4^alpha_level
+    uint32_t pad2[13];
 };
-static_assert(sizeof(RgBlasHdr) == 64, "blas header");
+static_assert(sizeof(RgBlasHdr) == 128, "blas header");
+static_assert(sizeof(rg_blas) == 120, "rg_blas layout (mirrored by the Python binding)");
+
+// Instance record flag set by the top-level build when the instance's
+// bottom level carries opacity masks (beside the caller's RG_INST_* bits).
+#define RG_INST_ALPHA (1u << 16)
 
 // Instance record in top-level leaf order: 112 bytes.
 struct RgInst {
@@ -54,7 +62,7 @@ struct RgInst {
     uint64_t nodes, tris, hdr;
     uint32_t mat, inst;
     float blo[3], bhi[3];  // the bottom level's root box (object space)
-    uint32_t flags;        // visibility mask (bits 0-7), RG_INST_CULL_DISABLE, RG_INST_FLIP_FACING
+    uint32_t flags;        // visibility mask (bits 0-7), RG_INST_CULL_DISABLE, RG_INST_FLIP_FACING, RG_INST_ALPHA
     uint32_t pad;
 };
 static_assert(sizeof(RgInst) == 112, "inst");

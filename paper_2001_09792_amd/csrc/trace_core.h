@@ -196,9 +196,23 @@ __device__ inline void sort_children(float tn[W], uint32_t ch[W]) {
 // leaf's triangles, then the pop) and reports when the ray is finished.  The
 // kernels run many rays per lane through it, so that lanes whose ray has
 // finished can take a new one while the others continue.
-// OPT: visibility masks and face culling are compiled in (launches whose
-// rays carry options, or whose top levels carry instance flags); without it
-// the traversal has none of their registers or tests.
+// Opacity of the micro-triangle holding barycentrics (u, v) of a triangle cut
+// into 4^level: cell (floor(n u), floor(n v)), n = 2^level, upright or
+// inverted, numbered row by row (row j starts at j (2n - j)).
+__device__ inline bool alpha_open(uint64_t mask, uint32_t level, float u, float v) {
+    const int n = 1 << level;
+    const float U = u * (float)n, V = v * (float)n;
+    int i = (int)floorf(U), j = (int)floorf(V);
+    i = i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+    j = j < 0 ? 0 : (j > n - 1 - i ? n - 1 - i : j);
+    const int inv = ((U - (float)i) + (V - (float)j) > 1.0f && i + j < n - 1) ? 1 : 0;
+    return ((mask >> (j * (2 * n - j) + 2 * i + inv)) & 1ull) != 0ull;
+}
+
+// OPT: visibility masks, face culling and opacity masks are compiled in
+// (launches whose rays carry options, or whose top levels carry instance
+// flags or opacity masks); without it the traversal has none of their
+// registers or tests.
 template <int W, bool ANY, int MODE, bool OPT>
 struct Tracer {
     const RgNode<W> *tlas_nodes;
@@ -217,6 +231,8 @@ struct Tracer {
     uint32_t rmask;      // this ray's visibility mask
     uint32_t call_cull;  // RG_RAY_CULL_* of the launch
     uint32_t cull;       // culling in the current instance: RG_RAY_CULL_* | kFlip
+    const uint64_t *alpha;  // opacity masks of the current instance's triangles (null: opaque)
+    uint32_t alpha_level;
     bool in_blas, found;
 
     __device__ inline void world_frame() {
@@ -245,6 +261,8 @@ struct Tracer {
         inst_id = 0;
         sh.kx = 0; sh.ky = 1; sh.kz = 2; sh.sx = sh.sy = 0.0f; sh.sz = 1.0f;
         cull = 0u;
+        alpha = nullptr;
+        alpha_level = 0u;
         world_frame();
         return R.tmin <= R.tmax;
     }
@@ -392,6 +410,12 @@ struct Tracer {
             if (OPT) {
                 cull = (w[26] & RG_INST_CULL_DISABLE) ? 0u : call_cull;
                 if (cull && (w[26] & RG_INST_FLIP_FACING)) cull |= kFlip;
+                alpha = nullptr;
+                if (w[26] & RG_INST_ALPHA) {
+                    const RgBlasHdr *H = reinterpret_cast<const RgBlasHdr *>((uint64_t)w[16] | ((uint64_t)w[17] << 32));
+                    alpha = reinterpret_cast<const uint64_t *>(H->alpha);
+                    alpha_level = H->alpha_level;
+                }
             }
             in_blas = true;
             st.push(kSentinel);
@@ -421,6 +445,7 @@ struct Tracer {
                 float tl = T / det;
                 float tw = t0 + tl;
                 if (!(tw >= R.tmin) || !(tw <= best)) continue;
+                if (OPT && alpha && !alpha_open(alpha[tri.prim], alpha_level, V / det, Wv / det)) continue;
                 uint32_t pid = (MODE == kRender) ? (lf + j) : tri.prim;
                 if (!ANY && tw == best && found) {
                     if (inst_id > h.inst || (inst_id == h.inst && pid >= h.prim)) continue;

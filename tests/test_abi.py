@@ -226,3 +226,15 @@ def test_post_process_arguments_are_checked_on_the_host():
     assert lib.rg_fxaa(a, 64, 32, b, s, 100, None) == -2
     assert lib.rg_fxaa(a, 64, 0, b, s, big, None) == -1
     assert lib.rg_fxaa(a, 64, 32, b, b - 12 * n + 256, big, None) == -1                 # luma scratch over the output
+
+
+def test_opacity_mask_arguments_are_checked_on_the_host():
+    import paper_2001_09792_amd as rg
+    lib = rg._lib
+    fake = rg.BlasDesc()
+    assert lib.rg_blas_set_alpha(None, 256, 3, None) == -1
+    assert lib.rg_blas_set_alpha(ctypes.byref(fake), 256, 3, None) == -1            # no buffer
+    fake.buf = 256
+    assert lib.rg_blas_set_alpha(ctypes.byref(fake), 512, rg.RG_ALPHA_LEVEL_MAX + 1, None) == -1
+    assert lib.rg_blas_set_alpha(ctypes.byref(fake), 512, -1, None) == -1
+    assert ctypes.sizeof(rg.BlasDesc) == 120
