@@ -229,3 +229,156 @@ def leaf_order(left: np.ndarray, right: np.ndarray, n: int) -> np.ndarray:
             stack.append(right[c])
             stack.append(left[c])
     return rank
+
+
+# Treelet restructuring (Karras & Aila 2013, "Fast Parallel Construction of
+# High-Quality Bounding Volume Hierarchies")
+# ----------------------------------------------------------------------------
+def _subtree_leaves(left, right, n):
+    """Leaf count below every inner node."""
+    cnt = np.zeros(max(n - 1, 0), np.int64)
+
+    def count(c):
+        return 1 if c < 0 else cnt[c]
+
+    for node in _post_order(left, right, n):
+        cnt[node] = count(left[node]) + count(right[node])
+    return cnt
+
+
+def _post_order(left, right, n):
+    """Inner nodes, every node after the inner nodes below it (children
+    left before right)."""
+    if n < 2:
+        return []
+    out, stack = [], [(0, False)]
+    while stack:
+        c, seen = stack.pop()
+        if seen:
+            out.append(c)
+            continue
+        stack.append((c, True))
+        for k in (right[c], left[c]):
+            if k >= 0:
+                stack.append((k, False))
+    return out
+
+
+def optimal_treelet(lo: np.ndarray, hi: np.ndarray):
+    """The binary tree over m <= 7 leaf boxes with the least sum of float32
+    surface areas of its inner nodes (the surface-area cost the leaves do
+    not change), by dynamic programming over the subsets S of the leaves:
+    cost(S) = 0 for one leaf, else area(S) + min over the splits (P, S \\ P)
+    of cost(P) + cost(S \\ P), P holding the lowest leaf of S and enumerated
+    in increasing bit order, the first minimum kept; every sum float32.
+    Returns cost, split (per subset bit mask) and the union boxes."""
+    m = lo.shape[0]
+    full = (1 << m) - 1
+    slo = np.zeros((full + 1, 3), np.float32)
+    shi = np.zeros((full + 1, 3), np.float32)
+    area = np.zeros(full + 1, np.float32)
+    for S in range(1, full + 1):
+        bits = [k for k in range(m) if (S >> k) & 1]
+        slo[S] = np.min(lo[bits], axis=0)
+        shi[S] = np.max(hi[bits], axis=0)
+        area[S] = surface_area32(slo[S], shi[S])
+    cost = np.zeros(full + 1, np.float32)
+    split = np.zeros(full + 1, np.int64)
+    for S in sorted(range(1, full + 1), key=lambda s: (bin(s).count("1"), s)):
+        if S & (S - 1) == 0:
+            continue
+        low = S & -S
+        rest = S ^ low
+        best, bp = np.float32(np.inf), 0
+        Q = 0
+        while True:
+            P = low | Q
+            if P != S:
+                v = np.float32(cost[P] + cost[S ^ P])
+                if v < best:
+                    best, bp = v, P
+            if Q == rest:
+                break
+            Q = (Q - rest) & rest
+        cost[S] = np.float32(area[S] + best)
+        split[S] = bp
+    return cost, split, slo, shi
+
+
+def treelet_optimise(left, right, leaf_lo, leaf_hi, int_lo, int_hi, rounds: int = 3, size: int = 7):
+    """Rounds of treelet restructuring over a binary hierarchy (Karras-style
+    encoding, leaves -(i+1)), as defined for this build:
+
+      order     each round visits the inner nodes with at least three
+                leaves below them, every node after the inner nodes below
+                it (as the tree stood when the round began)
+      treelet   starts as the node's two children; while it has fewer than
+                `size` leaves, its inner leaf of largest float32 surface
+                area (first in the list on ties) is replaced in place by its
+                left child, its right child appended
+      topology  optimal_treelet over the treelet's leaves
+      rebuild   the node keeps its index; the treelet's other inner nodes
+                take the replaced nodes' indices in increasing order, in
+                pre-order of the new topology (left subtree first); inner
+                boxes are the unions of their leaves' boxes
+
+    Returns left, right, inner lo, inner hi (new arrays)."""
+    left = np.array(left, np.int64)
+    right = np.array(right, np.int64)
+    blo = np.array(int_lo, np.float32)
+    bhi = np.array(int_hi, np.float32)
+    n = leaf_lo.shape[0]
+
+    def box(c):
+        return (leaf_lo[-c - 1], leaf_hi[-c - 1]) if c < 0 else (blo[c], bhi[c])
+
+    for _ in range(rounds):
+        cnt = _subtree_leaves(left, right, n)
+        for node in _post_order(left, right, n):
+            if cnt[node] < 3:
+                continue
+            leaves = [int(left[node]), int(right[node])]
+            removed = []
+            while len(leaves) < size:
+                best_k, best_a = -1, np.float32(-np.inf)
+                for k, c in enumerate(leaves):
+                    if c >= 0:
+                        a = surface_area32(blo[c], bhi[c])
+                        if a > best_a:
+                            best_k, best_a = k, a
+                if best_k < 0:
+                    break
+                c = leaves[best_k]
+                removed.append(c)
+                leaves[best_k] = int(left[c])
+                leaves.append(int(right[c]))
+            m = len(leaves)
+            lo = np.array([box(c)[0] for c in leaves], np.float32)
+            hi = np.array([box(c)[1] for c in leaves], np.float32)
+            _, split, slo, shi = optimal_treelet(lo, hi)
+            ids = sorted(removed)
+            nxt = 0
+            full = (1 << m) - 1
+            stack = [(full ^ int(split[full]), node, 1), (int(split[full]), node, 0)]
+            while stack:
+                T, parent, side = stack.pop()
+                if T & (T - 1) == 0:
+                    child = leaves[T.bit_length() - 1]
+                else:
+                    child = ids[nxt]
+                    nxt += 1
+                    blo[child], bhi[child] = slo[T], shi[T]
+                    stack.append((T ^ int(split[T]), child, 1))
+                    stack.append((int(split[T]), child, 0))
+                if side == 0:
+                    left[parent] = child
+                else:
+                    right[parent] = child
+    return left, right, blo, bhi
+
+
+def sah_cost(left, right, leaf_lo, leaf_hi, int_lo, int_hi) -> float:
+    """Sum of inner-node surface areas over the root's (FP64)."""
+    d = (int_hi.astype(np.float64) - int_lo.astype(np.float64))
+    a = 2.0 * (d[:, 0] * d[:, 1] + d[:, 1] * d[:, 2] + d[:, 2] * d[:, 0])
+    return float(a.sum() / a[0])
