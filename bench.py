@@ -40,7 +40,8 @@ TRI_BYTES, INST_BYTES, RAY_BYTES, HIT_BYTES = 40, 112, 32, 20
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ao_closest.json")
 # what the traversal kernel is compiled from (sources and compiler flags)
 KERNEL_SOURCES = ["paper_2001_09792_amd/csrc/trace_core.h", "paper_2001_09792_amd/csrc/trace.hip",
-                  "paper_2001_09792_amd/csrc/rg_internal.h", "paper_2001_09792_amd/_build.py"]
+                  "paper_2001_09792_amd/csrc/rg_internal.h", "paper_2001_09792_amd/csrc/build.hip",
+                  "paper_2001_09792_amd/_build.py"]
 
 
 def kernel_hash() -> str:
@@ -70,12 +71,13 @@ def recorded_traffic(args):
 
 
 # Hierarchy shape per workload (node width, leaf size, builder), the best
-# measured on MI355X: the incoherent AO rays and the serving mix (dominated by
-# the regular torus meshes) run fastest on width-4 linear BVHs; whole
-# two-level frames on width-8 clustered hierarchies (about 5% faster).  The
+# measured on MI355X: the incoherent AO rays run fastest on width-4 linear
+# BVHs restructured by treelets (7% over the plain linear BVH, 9% fewer node
+# visits); the serving mix (dominated by the regular torus meshes) on width-4
+# linear BVHs; whole two-level frames on width-8 clustered hierarchies.  The
 # batched workload starts from its entry and can be autotuned.
-SHAPES = {"incoherent": (4, 1, "lbvh"), "two_level": (8, 1, "ploc"), "batched": (4, 1, "lbvh"),
-          "serving": (4, 1, "lbvh"), "dynamic": (4, 1, "lbvh"), "post": (8, 1, "ploc")}
+SHAPES = {"incoherent": (4, 1, "treelet"), "two_level": (8, 1, "ploc"), "batched": (4, 1, "lbvh"),
+          "serving": (4, 1, "lbvh"), "dynamic": (4, 1, "treelet"), "post": (8, 1, "ploc")}
 
 
 def log(*a):
@@ -709,7 +711,7 @@ def main():
     ap.add_argument("--plain-factors", type=float, nargs="*", default=[0.5, 0.9])
     ap.add_argument("--width", type=int, default=None, help="node width (default: the workload's, see SHAPES)")
     ap.add_argument("--leaf", type=int, default=None, help="most triangles per leaf (default: the workload's)")
-    ap.add_argument("--builder", choices=["lbvh", "ploc"], default=None,
+    ap.add_argument("--builder", choices=["lbvh", "ploc", "treelet"], default=None,
                     help="hierarchy builder: linear BVH or locally-ordered clustering (default: the workload's)")
     ap.add_argument("--refill", type=int, default=None, help="traversal refill threshold (lanes)")
     ap.add_argument("--waves-per-cu", type=int, default=None, help="persistent traversal waves per CU")

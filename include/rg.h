@@ -69,15 +69,25 @@ typedef int32_t rg_status;
  *     positions of the sorted cluster list, whose union box has the least
  *     surface area (float32; ties to the nearer-to-front position); mutual
  *     nearest pairs merge into the lower position; repeated down to one
- *     cluster.  Slower to build, tighter boxes, fewer node visits. */
+ *     cluster.  Slower to build, tighter boxes, fewer node visits.
+ *   RG_BUILDER_TREELET: the linear BVH, then rounds of treelet
+ *     restructuring (Karras & Aila 2013): at every inner node with at least
+ *     three leaves below it (each after the nodes below it), a treelet of up
+ *     to 7 leaves grown by repeatedly opening its inner leaf of largest
+ *     surface area is rebuilt with the topology of least total float32
+ *     surface area (dynamic programming over the leaf subsets); the leaves
+ *     are then renumbered in the tree's left-to-right order. */
 #define RG_BUILDER_LBVH 0
 #define RG_BUILDER_PLOC 1
+#define RG_BUILDER_TREELET 2
 #define RG_PLOC_RADIUS_DEFAULT 16
+#define RG_TREELET_ROUNDS_DEFAULT 3
 
 /* Hierarchy options.  width = children per node (2, 4 or 8); leaf_max =
  * most triangles per leaf (1..8); builder = RG_BUILDER_*; radius = search
- * radius of RG_BUILDER_PLOC (1..32, 0 = RG_PLOC_RADIUS_DEFAULT; ignored by
- * RG_BUILDER_LBVH).  NULL means {4, 4, RG_BUILDER_LBVH, 0}. */
+ * radius of RG_BUILDER_PLOC (1..32, 0 = RG_PLOC_RADIUS_DEFAULT), rounds of
+ * RG_BUILDER_TREELET (1..8, 0 = RG_TREELET_ROUNDS_DEFAULT), ignored by
+ * RG_BUILDER_LBVH.  NULL means {4, 4, RG_BUILDER_LBVH, 0}. */
 typedef struct {
     int32_t width;
     int32_t leaf_max;
@@ -605,7 +615,8 @@ rg_status rg_engine_stats(rg_engine *engine, rg_render_stats *stats /*host*/);
  * sorted order (ids = the sort's permutation); for RG_BUILDER_PLOC inner
  * nodes are numbered n-2 downward in merge order (a round's merges in order
  * of position) and the leaves are renumbered to the tree's left-to-right
- * order.  scratch as for rg_build_blas.  Synchronous. */
+ * order; for RG_BUILDER_TREELET the restructured linear BVH, its leaves
+ * renumbered likewise.  scratch as for rg_build_blas.  Synchronous. */
 rg_status rg_lbvh_stages(const float *verts, int64_t n_verts, const uint32_t *idx, int64_t n_tris,
                          const rg_build_opts *opts /*host, nullable*/, uint64_t *keys, uint32_t *ids,
                          int32_t *left, int32_t *right, float *boxes, void *scratch,

@@ -228,7 +228,7 @@ def _bytes(n: int, device):
 
 
 # hierarchy builders (include/rg.h RG_BUILDER_*)
-BUILDERS = {"lbvh": 0, "ploc": 1}
+BUILDERS = {"lbvh": 0, "ploc": 1, "treelet": 2}
 PLOC_RADIUS_DEFAULT = 16
 
 

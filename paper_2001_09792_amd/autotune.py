@@ -21,7 +21,7 @@ from typing import Callable, Dict, Optional
 DEFAULT = dict(builder="lbvh", width=4, leaf=1, refill=8, waves_per_cu=16, lds_depth=16, leaf_batch=12,
                inst_batch=6)
 BUILD_KEYS = ("builder", "width", "leaf")
-SPACE = dict(builder=("lbvh", "ploc"), width=(2, 4, 8), leaf=(1, 2, 4), lds_depth=(8, 16, 24), refill=(4, 8, 16, 32),
+SPACE = dict(builder=("lbvh", "ploc", "treelet"), width=(2, 4, 8), leaf=(1, 2, 4), lds_depth=(8, 16, 24), refill=(4, 8, 16, 32),
              waves_per_cu=(12, 16, 24), leaf_batch=(1, 8, 12, 16, 24), inst_batch=(1, 4, 6, 8, 12))
 LAUNCH_KEYS = ("refill", "waves_per_cu", "lds_depth", "leaf_batch", "inst_batch")
 

@@ -606,7 +606,7 @@ __global__ void k_ploc_sizes(int64_t n, const int32_t *__restrict__ left, const 
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     int32_t p = parent_leaf[i];
-    while (p >= 0 && p < n - 1) {
+    for (int64_t guard = 0; p >= 0 && p < n - 1 && guard < n; ++guard) {
         uint32_t old = __hip_atomic_fetch_add(&counter[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (old == 0u) return;
         const int32_t a = left[p], b = right[p];
@@ -660,6 +660,185 @@ __global__ void k_ploc_relabel(int64_t n, int32_t *__restrict__ left, int32_t *_
     const int32_t a = left[x], b = right[x];
     if (a < 0) left[x] = -(rank[-a - 1] + 1);
     if (b < 0) right[x] = -(rank[-b - 1] + 1);
+}
+
+// ------------------------------------ 5''. treelet restructuring
+// Karras & Aila 2013 over the binary hierarchy.  A round visits every inner
+// node with at least three leaves below it after the nodes below it; nodes of
+// one height (longest path down to a leaf, taken when the round begins) are
+// never above one another, so each height is one launch, one wave per node.
+// The treelet starts as the node's children; its inner leaf of largest
+// surface area (first on ties) is replaced in place by its left child and its
+// right child appended, up to kTreelet leaves.  The topology of least total
+// surface area comes from a dynamic program over the leaf subsets (float32,
+// no fused multiply-add, splits holding the subset's lowest leaf tried in
+// increasing bit order, the first minimum kept); the node keeps its index and
+// the other inner nodes take the opened nodes' indices, ascending, in
+// pre-order (left subtree first).
+constexpr int kTreelet = 7;
+constexpr int kTreeletMaxRounds = 8;
+
+__device__ inline float area32(const float *lo, const float *hi) {
+#pragma clang fp contract(off)
+    const float dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+    return 2.0f * ((dx * dy + dy * dz) + dz * dx);
+}
+
+// Height of every inner node (leaves 0), bottom-up: the second child to
+// arrive continues upwards; counts per height and the largest height.
+__global__ void k_heights(int64_t n, const int32_t *__restrict__ left, const int32_t *__restrict__ right,
+                          const int32_t *__restrict__ parent_int, const int32_t *__restrict__ parent_leaf,
+                          uint32_t *counter, int32_t *height, uint32_t *hcount, uint32_t *hmax) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t p = parent_leaf[i];
+    // a consistent tree has fewer than n inner nodes above a leaf
+    for (int64_t guard = 0; p >= 0 && p < n - 1 && guard < n; ++guard) {
+        uint32_t old = __hip_atomic_fetch_add(&counter[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == 0u) return;
+        const int32_t a = left[p], b = right[p];
+        const int32_t ha = a < 0 ? 0 : __hip_atomic_load(&height[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t hb = b < 0 ? 0 : __hip_atomic_load(&height[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t h = 1 + (ha > hb ? ha : hb);
+        __hip_atomic_store(&height[p], h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((int64_t)h < n) atomicAdd(&hcount[h], 1u);  // always: a height is below n
+        atomicMax(hmax, (uint32_t)h);
+        p = parent_int[p];
+    }
+}
+
+// Inner nodes grouped by height: order[hstart[h] ...] holds height h.
+__global__ void k_height_scatter(int64_t m, const int32_t *__restrict__ height, const uint32_t *__restrict__ hstart,
+                                 uint32_t *hcursor, int32_t hmax, int32_t *__restrict__ order) {
+    const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (x >= m) return;
+    const int32_t h = height[x];
+    if (h < 1 || h > hmax) return;  // never once the host has checked the counts
+    order[hstart[h] + atomicAdd(&hcursor[h], 1u)] = (int32_t)x;
+}
+
+__global__ void __launch_bounds__(64) k_treelet(const int32_t *__restrict__ order, int32_t *left, int32_t *right,
+                                                int32_t *parent_int, int32_t *parent_leaf, float *int_box,
+                                                const float *__restrict__ leaf_box) {
+    __shared__ float ulo[1 << kTreelet][3], uhi[1 << kTreelet][3];
+    __shared__ float area[1 << kTreelet], cost[1 << kTreelet];
+    __shared__ uint8_t split[1 << kTreelet];
+    __shared__ int32_t leaves[kTreelet], opened[kTreelet];
+    __shared__ int n_leaves, n_opened;
+    const int lane = threadIdx.x;
+    const int32_t node = order[blockIdx.x];
+    if (lane == 0) {
+        int m = 2, r = 0;
+        leaves[0] = left[node];
+        leaves[1] = right[node];
+        while (m < kTreelet) {
+            int bk = -1;
+            float ba = -INFINITY;
+            for (int k = 0; k < m; ++k) {
+                const int32_t c = leaves[k];
+                if (c < 0) continue;
+                const float a = area32(int_box + 6 * (int64_t)c, int_box + 6 * (int64_t)c + 3);
+                if (a > ba) {
+                    ba = a;
+                    bk = k;
+                }
+            }
+            if (bk < 0) break;
+            const int32_t c = leaves[bk];
+            opened[r++] = c;
+            leaves[bk] = left[c];
+            leaves[m++] = right[c];
+        }
+        for (int k = 1; k < r; ++k)  // ascending: the order the indices are handed out in
+            for (int q = k; q > 0 && opened[q - 1] > opened[q]; --q) {
+                const int32_t t = opened[q];
+                opened[q] = opened[q - 1];
+                opened[q - 1] = t;
+            }
+        n_leaves = m;
+        n_opened = r;
+    }
+    __syncthreads();
+    const int m = n_leaves;
+    const uint32_t full = (1u << m) - 1u;
+    for (uint32_t S = (uint32_t)lane + 1u; S <= full; S += 64u) {
+        float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int k = 0; k < m; ++k) {
+            if (!((S >> k) & 1u)) continue;
+            const int32_t c = leaves[k];
+            const float *b = c < 0 ? leaf_box + 6 * (int64_t)(-c - 1) : int_box + 6 * (int64_t)c;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                lo[q] = fminf(lo[q], b[q]);
+                hi[q] = fmaxf(hi[q], b[3 + q]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            ulo[S][q] = lo[q];
+            uhi[S][q] = hi[q];
+        }
+        area[S] = area32(lo, hi);
+        cost[S] = 0.0f;
+        split[S] = 0;
+    }
+    __syncthreads();
+    for (int k = 2; k <= m; ++k) {
+        for (uint32_t S = (uint32_t)lane + 1u; S <= full; S += 64u) {
+            if (__popc(S) != k) continue;
+            const uint32_t low = S & (0u - S), rest = S ^ low;
+            float best = INFINITY;
+            uint32_t bp = 0u, Q = 0u;
+            while (true) {
+                const uint32_t P = low | Q;
+                if (P != S) {
+                    const float v = cost[P] + cost[S ^ P];
+                    if (v < best) {
+                        best = v;
+                        bp = P;
+                    }
+                }
+                if (Q == rest) break;
+                Q = (Q - rest) & rest;
+            }
+            cost[S] = area[S] + best;
+            split[S] = (uint8_t)bp;
+        }
+        __syncthreads();
+    }
+    if (lane != 0) return;
+    // rebuild: entries (subset, parent, side) popped in pre-order
+    uint32_t st_set[2 * kTreelet];
+    int32_t st_parent[2 * kTreelet];
+    int st_side[2 * kTreelet];
+    int sp = 0, next = 0;
+    st_set[sp] = full ^ split[full]; st_parent[sp] = node; st_side[sp] = 1; ++sp;
+    st_set[sp] = split[full]; st_parent[sp] = node; st_side[sp] = 0; ++sp;
+    while (sp > 0) {
+        --sp;
+        const uint32_t T = st_set[sp];
+        const int32_t parent = st_parent[sp];
+        const int side = st_side[sp];
+        int32_t child;
+        if ((T & (T - 1u)) == 0u) {
+            child = leaves[__ffs((int)T) - 1];
+        } else {
+            if (next >= n_opened || sp + 2 > 2 * kTreelet) return;  // never: m - 2 opened nodes, depth < m
+            child = opened[next++];
+            float *b = int_box + 6 * (int64_t)child;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                b[q] = ulo[T][q];
+                b[3 + q] = uhi[T][q];
+            }
+            st_set[sp] = T ^ split[T]; st_parent[sp] = child; st_side[sp] = 1; ++sp;
+            st_set[sp] = split[T]; st_parent[sp] = child; st_side[sp] = 0; ++sp;
+        }
+        if (side == 0) left[parent] = child;
+        else right[parent] = child;
+        if (child < 0) parent_leaf[-child - 1] = parent;
+        else parent_int[child] = parent;
+    }
 }
 
 // ------------------------------------------------------ reordering
@@ -1038,9 +1217,14 @@ bool opts_ok(const rg_build_opts *o, Opts *out) {
     if (o) r = Opts{o->width, o->leaf_max, o->builder, o->radius};
     if (!(r.w == 2 || r.w == 4 || r.w == 8)) return false;
     if (r.leaf < 1 || r.leaf > 8) return false;
-    if (r.builder != RG_BUILDER_LBVH && r.builder != RG_BUILDER_PLOC) return false;
-    if (r.radius == 0) r.radius = RG_PLOC_RADIUS_DEFAULT;
-    if (r.radius < 1 || r.radius > kPlocMaxRadius) return false;
+    if (r.builder == RG_BUILDER_TREELET) {
+        if (r.radius == 0) r.radius = RG_TREELET_ROUNDS_DEFAULT;
+        if (r.radius < 1 || r.radius > kTreeletMaxRounds) return false;
+    } else {
+        if (r.builder != RG_BUILDER_LBVH && r.builder != RG_BUILDER_PLOC) return false;
+        if (r.radius == 0) r.radius = RG_PLOC_RADIUS_DEFAULT;
+        if (r.radius < 1 || r.radius > kPlocMaxRadius) return false;
+    }
     *out = r;
     return true;
 }
@@ -1057,6 +1241,9 @@ struct LbvhScratch {
     int32_t *cid[2], *nearest, *rank, *size;
     float *cbox[2];
     uint32_t *n_merge, *n_keep;
+    // treelet restructuring only (with rank, size, cbox[0])
+    int32_t *height, *order;
+    uint32_t *hcount, *hcursor, *hstart, *hmax;
 };
 
 bool carve(RgArena &a, int64_t n, int32_t builder, LbvhScratch &s) {
@@ -1093,7 +1280,35 @@ bool carve(RgArena &a, int64_t n, int32_t builder, LbvhScratch &s) {
         s.n_merge = a.take<uint32_t>(pb);
         s.n_keep = a.take<uint32_t>(pb);
     }
+    if (builder == RG_BUILDER_TREELET) {
+        s.cbox[0] = a.take<float>(6 * n);
+        s.rank = a.take<int32_t>(n);
+        s.size = a.take<int32_t>(ni);
+        s.height = a.take<int32_t>(ni);
+        s.order = a.take<int32_t>(ni);
+        s.hcount = a.take<uint32_t>(n + 1);
+        s.hcursor = a.take<uint32_t>(n + 1);
+        s.hstart = a.take<uint32_t>(n + 1);
+        s.hmax = a.take<uint32_t>(8);
+    }
     return !a.overflow();
+}
+
+// Renumbers the leaves of the binary hierarchy in s (n >= 2) in the tree's
+// left-to-right order: triangle order ids -> ids_out, leaf boxes to box_out
+// (which then replaces s.leaf_box), inner leaf ranges first / last.
+rg_status relabel_leaves(LbvhScratch &s, int64_t n, const uint32_t *ids, uint32_t *ids_out, float *box_out,
+                         hipStream_t st) {
+    k_fill_u32<<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>(s.counter, 0u, n - 1);
+    k_ploc_sizes<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(n, s.left, s.right, s.pint, s.pleaf, s.counter,
+                                                               s.size);
+    k_ploc_ranks<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(n, s.left, s.pint, s.pleaf, s.size, ids,
+                                                               s.leaf_box, s.rank, s.first, s.last, ids_out,
+                                                               box_out);
+    k_ploc_relabel<<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>(n, s.left, s.right, s.rank);
+    RG_LAUNCH_CHECK();
+    s.leaf_box = box_out;
+    return RG_OK;
 }
 
 // Clustering over the n >= 2 sorted leaves (`ids`): fills left, right,
@@ -1129,18 +1344,51 @@ rg_status ploc_build(const float *prim_box, int64_t n, int radius, const uint32_
         cur ^= 1;
     }
     if (next != -1) return RG_ERR_HIP;
-    k_fill_u32<<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>(s.counter, 0u, n - 1);
-    k_ploc_sizes<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(n, s.left, s.right, s.pint, s.pleaf, s.counter,
-                                                               s.size);
-    // the boxes in left-to-right order go to a cluster buffer, which then
-    // replaces the sorted-order leaf boxes
-    k_ploc_ranks<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(n, s.left, s.pint, s.pleaf, s.size, ids,
-                                                               s.leaf_box, s.rank, s.first, s.last, ids_out,
-                                                               s.cbox[cur]);
-    k_ploc_relabel<<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>(n, s.left, s.right, s.rank);
-    RG_LAUNCH_CHECK();
-    s.leaf_box = s.cbox[cur];
-    return RG_OK;
+    return relabel_leaves(s, n, ids, ids_out, s.cbox[cur], st);
+}
+
+// Rounds of treelet restructuring over the binary hierarchy in s (n >= 2),
+// then the leaves renumbered in left-to-right order (ids -> ids_out).
+rg_status treelet_build(int64_t n, int rounds, const uint32_t *ids, uint32_t *ids_out, LbvhScratch &s,
+                        hipStream_t st) {
+    const int64_t m = n - 1;
+    std::vector<uint32_t> cnt, start;
+    for (int round = 0; round < rounds; ++round) {
+        k_fill_u32<<<rg_blocks(m, kThreads), kThreads, 0, st>>>(s.counter, 0u, m);
+        k_fill_u32<<<rg_blocks(n + 1, kThreads), kThreads, 0, st>>>(s.hcount, 0u, n + 1);
+        k_fill_u32<<<1, 64, 0, st>>>(s.hmax, 0u, 1);
+        k_heights<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(n, s.left, s.right, s.pint, s.pleaf, s.counter,
+                                                                s.height, s.hcount, s.hmax);
+        RG_LAUNCH_CHECK();
+        uint32_t hmax = 0;
+        RG_HIP(hipMemcpyAsync(&hmax, s.hmax, 4, hipMemcpyDeviceToHost, st));
+        RG_HIP(hipStreamSynchronize(st));
+        if (hmax < 2u) break;  // no inner node has three leaves below it
+        if ((int64_t)hmax > m) return RG_ERR_HIP;  // never: a height is below the inner node count
+        cnt.assign(hmax + 1, 0u);
+        start.assign(hmax + 1, 0u);
+        RG_HIP(hipMemcpyAsync(cnt.data(), s.hcount, 4 * (hmax + 1), hipMemcpyDeviceToHost, st));
+        RG_HIP(hipStreamSynchronize(st));
+        uint64_t total = 0;
+        for (uint32_t h = 1; h <= hmax; ++h) {
+            start[h] = (uint32_t)total;
+            total += cnt[h];
+        }
+        if ((int64_t)total != m) return RG_ERR_HIP;  // never: every inner node has a height
+        RG_HIP(hipMemcpyAsync(s.hstart, start.data(), 4 * (hmax + 1), hipMemcpyHostToDevice, st));
+        k_fill_u32<<<rg_blocks(hmax + 1, kThreads), kThreads, 0, st>>>(s.hcursor, 0u, hmax + 1);
+        k_height_scatter<<<rg_blocks(m, kThreads), kThreads, 0, st>>>(m, s.height, s.hstart, s.hcursor,
+                                                                       (int32_t)hmax, s.order);
+        RG_LAUNCH_CHECK();
+        for (uint32_t h = 2; h <= hmax; ++h) {
+            if (cnt[h] == 0u) continue;
+            k_treelet<<<cnt[h], 64, 0, st>>>(s.order + start[h], s.left, s.right, s.pint, s.pleaf, s.int_box,
+                                             s.leaf_box);
+        }
+        RG_LAUNCH_CHECK();
+        RG_HIP(hipStreamSynchronize(st));  // the host vectors above are reused next round
+    }
+    return relabel_leaves(s, n, ids, ids_out, s.cbox[0], st);
 }
 
 template <int W>
@@ -1254,6 +1502,11 @@ rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t
         k_refit<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(prim_box, ia, n, s.left, s.right, s.pint, s.pleaf,
                                                              s.counter, s.int_box, s.leaf_box);
         RG_LAUNCH_CHECK();
+        if (builder == RG_BUILDER_TREELET && n > 1) {
+            rg_status r = treelet_build(n, radius, ia, ib, s, st);
+            if (r != RG_OK) return r;
+            ia = ib;
+        }
     }
     if (keep_stages) {
         RG_HIP(hipMemcpyAsync(keys_out, ka, 8 * n, hipMemcpyDeviceToDevice, st));

@@ -60,7 +60,7 @@ def test_sizes_validation():
     for r in (-1, 33):
         with pytest.raises(rg.RgError):
             rg.blas_sizes(10, builder="ploc", radius=r)
-    o = rg.BuildOpts(4, 4, 2, 0)
+    o = rg.BuildOpts(4, 4, 3, 0)  # no such builder
     s = rg.Sizes()
     assert rg._lib.rg_blas_sizes(10, rg.ctypes.byref(o), rg.ctypes.byref(s)) == -1
     with pytest.raises(ValueError):
@@ -238,3 +238,16 @@ def test_opacity_mask_arguments_are_checked_on_the_host():
     assert lib.rg_blas_set_alpha(ctypes.byref(fake), 512, rg.RG_ALPHA_LEVEL_MAX + 1, None) == -1
     assert lib.rg_blas_set_alpha(ctypes.byref(fake), 512, -1, None) == -1
     assert ctypes.sizeof(rg.BlasDesc) == 120
+
+
+def test_treelet_builder_options():
+    import paper_2001_09792_amd as rg
+    lib = rg._lib
+    s = rg.Sizes()
+    for radius, want in ((0, 0), (1, 0), (8, 0), (9, -1), (-1, -1)):
+        o = rg.BuildOpts(4, 4, 2, radius)
+        assert lib.rg_blas_sizes(1000, ctypes.byref(o), ctypes.byref(s)) == want, radius
+    o = rg.BuildOpts(4, 4, 3, 0)
+    assert lib.rg_blas_sizes(1000, ctypes.byref(o), ctypes.byref(s)) == -1       # unknown builder
+    lbvh, tr = rg.blas_sizes(5000, builder="lbvh"), rg.blas_sizes(5000, builder="treelet")
+    assert tr[0] == lbvh[0] and tr[1] > lbvh[1]          # same output, more scratch

@@ -167,3 +167,61 @@ def test_bad_inputs_are_rejected():
     b = rg.build_blas(v, i)
     assert b.n_tris == 10
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name,rounds", [("soup1500", 1), ("soup1500", 3), ("small", 2), ("torus_small", 2),
+                                         ("two", 3), ("dupes", 2), ("three", 1)])
+def test_treelet_stages_match_definition(name, rounds):
+    """Treelet restructuring of the linear BVH: tree, inner boxes, leaf
+    order and triangle order equal the reference restructuring bit for bit
+    (treelet growth, float32 dynamic program, index reuse)."""
+    import paper_2001_09792_amd as rg
+    mesh = {"soup1500": lambda: sg.random_soup(1500, 22), "small": lambda: sg.config_small().blas[0],
+            "torus_small": lambda: sg.torus(32, 24, 1.0, 0.35, 0.08, 6.0, 3001), "two": lambda: sg.random_soup(2, 5),
+            "three": lambda: sg.random_soup(3, 6),
+            "dupes": MESHES["dupes"]}[name]()
+    print(f"[build treelet] {name}: {mesh.n_tris} tris rounds={rounds}", flush=True)
+    v, i = _dev(mesh)
+    st = rg.lbvh_stages(v, i, builder="treelet", radius=rounds)
+    n = mesh.n_tris
+    ref_sorted, ref_ids = br.sort_pairs(br.morton_keys(mesh.verts, mesh.idx))
+    assert np.array_equal(st["keys"].cpu().numpy().view(np.uint64), ref_sorted)
+    lo, hi = br.tri_boxes(mesh.verts, mesh.idx)
+    lo_s, hi_s = lo[ref_ids], hi[ref_ids]
+    left, right, first, last = br.radix_tree(ref_sorted)
+    blo, bhi = br.refit(lo_s, hi_s, first, last)
+    L, R, BLO, BHI = br.treelet_optimise(left, right, lo_s, hi_s, blo, bhi, rounds=rounds)
+    rank = br.leaf_order(L, R, n)
+    relabel = lambda c: np.where(c < 0, -(rank[np.maximum(-c - 1, 0)] + 1), c)
+    ids = np.empty(n, np.uint32)
+    ids[rank] = ref_ids
+    assert np.array_equal(st["ids"].cpu().numpy().view(np.uint32), ids), "leaf order"
+    boxes = st["boxes"].cpu().numpy()
+    assert np.array_equal(st["left"].cpu().numpy(), relabel(L).astype(np.int32))
+    assert np.array_equal(st["right"].cpu().numpy(), relabel(R).astype(np.int32))
+    assert np.array_equal(boxes[: n - 1, :3], BLO) and np.array_equal(boxes[: n - 1, 3:], BHI)
+    leaf_lo = np.empty_like(lo_s)
+    leaf_hi = np.empty_like(hi_s)
+    leaf_lo[rank], leaf_hi[rank] = lo_s, hi_s
+    assert np.array_equal(boxes[n - 1:, :3], leaf_lo) and np.array_equal(boxes[n - 1:, 3:], leaf_hi)
+    if name in ("soup1500", "torus_small"):
+        before = br.sah_cost(left, right, lo_s, hi_s, blo, bhi)
+        after = br.sah_cost(L, R, lo_s, hi_s, BLO, BHI)
+        print(f"  surface-area cost {before:.2f} -> {after:.2f}", flush=True)
+        assert after < 0.95 * before
+
+
+@pytest.mark.parametrize("width,leaf_max", [(2, 1), (4, 1), (4, 4), (8, 3)])
+def test_treelet_blas_and_tlas_invariants(width, leaf_max):
+    import paper_2001_09792_amd as rg
+    mesh = sg.random_soup(3000, 34)
+    print(f"[blas treelet] W={width} L={leaf_max}", flush=True)
+    v, i = _dev(mesh)
+    b = rg.build_blas(v, i, None, width, leaf_max, builder="treelet")
+    info = bvh_check.check_blas(b.buf.cpu().numpy(), b.desc)
+    assert np.array_equal(info["verts"], mesh.verts[mesh.idx[info["prim"]]])
+    sc = sg.config_two_level(width=64, height=36)
+    tl = rg.upload_scene(sc, width, leaf_max, builder="treelet")
+    bvh_check.check_tlas(tl.buf.cpu().numpy(), tl.desc, [b.desc for b in tl.blas], sc.xform)
+    for bb in tl.blas:
+        bvh_check.check_blas(bb.buf.cpu().numpy(), bb.desc)

@@ -116,6 +116,24 @@ def test_clustered_two_level_parity():
     _both(sc, rays, "two-level ploc", sphere=True, builder="ploc")
 
 
+@pytest.mark.parametrize("width,leaf", [(2, 1), (4, 4), (8, 2)])
+def test_treelet_hierarchy_parity(width, leaf):
+    """Hierarchies restructured by treelets trace to the same hits."""
+    mesh = sg.random_soup(3000, 55, extent=1.0, size=0.1)
+    sc = scene_from_meshes([mesh])
+    _both(sc, _soup_rays(mesh, 6000, 56), f"soup treelet W{width} L{leaf}", width=width, leaf=leaf,
+          builder="treelet")
+
+
+def test_treelet_two_level_parity():
+    import paper_2001_09792_amd as rg
+    sc = sg.config_two_level(width=192, height=108)
+    r = rg.camera_rays(sc.camera, 192, 108).cpu().numpy().T.copy()
+    sel = sg.sample_pixels(192, 108, 3000, 19)
+    rays = np.concatenate([r[sel], sg.random_rays(3000, 20, extent=22.0)])
+    _both(sc, rays, "two-level treelet", sphere=True, builder="treelet")
+
+
 def test_instanced_soup_parity():
     meshes = [sg.random_soup(2000, 61, 1.0, 0.1), sg.icosphere(3), sg.torus(40, 30, 1.0, 0.3)]
     rng = np.random.default_rng(62)
