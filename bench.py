@@ -744,7 +744,7 @@ def main():
         out, scene = bench_incoherent(args, torch, rg, sg)
         if not args.no_cpu_baseline:
             log("timing the oracle on a sample")
-            out["cpu_baseline"] = cpu_baseline_incoherent(scene, 64, args.cpu_seconds)
+            out["cpu_baseline"] = cpu_baseline_incoherent(scene, 640, args.cpu_seconds)
     elif args.workload == "dynamic":
         out, scene = bench_dynamic(args, torch, rg, sg)
     elif args.workload == "post":
