@@ -7,8 +7,11 @@
 //   1. primitive boxes and the bounds of their centres,
 //   2. 63-bit Morton codes of the quantised centres,
 //   3. a stable LSD radix sort of (key, id), 8-bit digits, ranked in LDS,
-//   4. Karras's parallel radix-tree construction (HPG 2012),
-//   5. bottom-up box refit with arrival counters,
+//   4. Karras's parallel radix-tree construction (HPG 2012), or
+//      locally-ordered clustering (Meister & Bittner 2018),
+//   5. box refit level by level from the deepest (the inner nodes grouped
+//      by their depth from the root), then optionally rounds of treelet
+//      restructuring (Karras & Aila 2013),
 //   6. top-down collapse into W-wide nodes (repeatedly opening the inner
 //      child with the largest surface area), leaves of <= leaf_max prims,
 // followed by reordering the primitives into leaf order.
@@ -300,36 +303,8 @@ __global__ void k_karras(const uint64_t *__restrict__ keys, int64_t n, int32_t *
 }
 
 // -------------------------------------------------------- 5. box refit
-__global__ void k_refit(const float *__restrict__ prim_box, const uint32_t *__restrict__ ids, int64_t n,
-                        const int32_t *__restrict__ left, const int32_t *__restrict__ right,
-                        const int32_t *__restrict__ parent_int, const int32_t *__restrict__ parent_leaf,
-                        uint32_t *counter, float *int_box, float *leaf_box) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t src = ids[i];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) leaf_box[6 * i + k] = prim_box[6 * (int64_t)src + k];
-    if (n < 2) return;
-    int32_t p = parent_leaf[i];
-    while (p >= 0 && p < n - 1) {
-        uint32_t old = __hip_atomic_fetch_add(&counter[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == 0u) return;  // the sibling's subtree is still being built
-        int32_t c[2] = {left[p], right[p]};
-        float b[12];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const float *src_box = c[s] < 0 ? leaf_box + 6 * (int64_t)(-c[s] - 1) : int_box + 6 * (int64_t)c[s];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) b[6 * s + k] = src_box[k];
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            int_box[6 * (int64_t)p + k] = fminf(b[k], b[6 + k]);
-            int_box[6 * (int64_t)p + 3 + k] = fmaxf(b[3 + k], b[9 + k]);
-        }
-        p = parent_int[p];
-    }
-}
+// Inner boxes are computed level by level from the root's depth order
+// (k_boxes_at below), after k_leaf_boxes has gathered the leaf boxes.
 
 // --------------------------------------------------- 6. wide collapse
 __device__ inline float surface_area(const float *b) {
@@ -598,25 +573,6 @@ __global__ void __launch_bounds__(kPlocT) k_ploc_write(
     out_cid[at] = node;
 }
 
-// Leaf counts of the inner nodes, bottom-up (the second child to arrive at a
-// node continues upwards).
-__global__ void k_ploc_sizes(int64_t n, const int32_t *__restrict__ left, const int32_t *__restrict__ right,
-                             const int32_t *__restrict__ parent_int, const int32_t *__restrict__ parent_leaf,
-                             uint32_t *counter, int32_t *size) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t p = parent_leaf[i];
-    for (int64_t guard = 0; p >= 0 && p < n - 1 && guard < n; ++guard) {
-        uint32_t old = __hip_atomic_fetch_add(&counter[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == 0u) return;
-        const int32_t a = left[p], b = right[p];
-        const int32_t sa = a < 0 ? 1 : __hip_atomic_load(&size[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int32_t sb = b < 0 ? 1 : __hip_atomic_load(&size[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&size[p], sa + sb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        p = parent_int[p];
-    }
-}
-
 // Rank of each leaf in the tree's left-to-right order: the leaves of the
 // left siblings along its path to the root come before it.  The leaf is the
 // leftmost of the ancestors reached from left children only, whose leaf range
@@ -664,9 +620,12 @@ __global__ void k_ploc_relabel(int64_t n, int32_t *__restrict__ left, int32_t *_
 
 // ------------------------------------ 5''. treelet restructuring
 // Karras & Aila 2013 over the binary hierarchy.  A round visits every inner
-// node with at least three leaves below it after the nodes below it; nodes of
-// one height (longest path down to a leaf, taken when the round begins) are
-// never above one another, so each height is one launch, one wave per node.
+// node with at least three leaves below it after the nodes below it (a node
+// with two leaf children has one topology and is skipped): depths from the
+// root are taken when the round begins, deepest first, one launch per depth
+// and one wave per node; nodes of one depth have disjoint subtrees, and a
+// restructure never changes the set of leaves below its node, so the result
+// is that of any order that puts every node after those below it.
 // The treelet starts as the node's children; its inner leaf of largest
 // surface area (first on ties) is replaced in place by its left child and its
 // right child appended, up to kTreelet leaves.  The topology of least total
@@ -684,37 +643,99 @@ __device__ inline float area32(const float *lo, const float *hi) {
     return 2.0f * ((dx * dy + dy * dz) + dz * dx);
 }
 
-// Height of every inner node (leaves 0), bottom-up: the second child to
-// arrive continues upwards; counts per height and the largest height.
-__global__ void k_heights(int64_t n, const int32_t *__restrict__ left, const int32_t *__restrict__ right,
-                          const int32_t *__restrict__ parent_int, const int32_t *__restrict__ parent_leaf,
-                          uint32_t *counter, int32_t *height, uint32_t *hcount, uint32_t *hmax) {
+// Depth of every inner node (the root 0) by walking its parent links, and
+// the count of nodes per depth; counts of depths below kDepthBins are summed
+// per block in LDS first, so the global counters take one atomic per block
+// and depth.
+constexpr int kDepthBins = 256;
+
+__global__ void __launch_bounds__(kThreads) k_depths(int64_t m, const int32_t *__restrict__ parent_int,
+                                                     int32_t *__restrict__ depth, uint32_t *hcount, uint32_t *hmax) {
+    __shared__ uint32_t bins[kDepthBins];
+    __shared__ uint32_t bmax;
+    for (int k = threadIdx.x; k < kDepthBins; k += blockDim.x) bins[k] = 0u;
+    if (threadIdx.x == 0) bmax = 0u;
+    __syncthreads();
+    const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (x < m) {
+        int32_t d = 0, p = parent_int[x];
+        // a consistent tree has fewer than m inner nodes above any node
+        for (; p >= 0 && p < m && d < m; p = parent_int[p]) ++d;
+        depth[x] = d;
+        if (d < kDepthBins) atomicAdd(&bins[d], 1u);
+        else if (d < m) atomicAdd(&hcount[d], 1u);
+        atomicMax(&bmax, (uint32_t)d);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kDepthBins; k += blockDim.x)
+        if (bins[k]) atomicAdd(&hcount[k], bins[k]);
+    if (threadIdx.x == 0) atomicMax(hmax, bmax);
+}
+
+// Inner nodes grouped by depth: order[hstart[d] ...] holds depth d (in no
+// particular order within a depth).  Positions are handed out per block and
+// depth, then per node within the block.
+__global__ void __launch_bounds__(kThreads) k_depth_scatter(int64_t m, const int32_t *__restrict__ depth,
+                                                            const uint32_t *__restrict__ hstart, uint32_t *hcursor,
+                                                            int32_t dmax, int32_t *__restrict__ order) {
+    __shared__ uint32_t bins[kDepthBins], base[kDepthBins];
+    for (int k = threadIdx.x; k < kDepthBins; k += blockDim.x) bins[k] = 0u;
+    __syncthreads();
+    const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int32_t d = -1;
+    uint32_t local = 0u;
+    if (x < m) {
+        d = depth[x];
+        if (d < 0 || d > dmax) d = -1;  // never once the host has checked the counts
+        else if (d < kDepthBins) local = atomicAdd(&bins[d], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kDepthBins; k += blockDim.x)
+        if (bins[k]) base[k] = atomicAdd(&hcursor[k], bins[k]);
+    __syncthreads();
+    if (d < 0) return;
+    const uint32_t at = d < kDepthBins ? base[d] + local : atomicAdd(&hcursor[d], 1u);
+    order[hstart[d] + at] = (int32_t)x;
+}
+
+// Per-depth passes over the nodes of one depth (order[0 .. count)), run
+// deepest first: the children of a node are deeper, so their values are final.
+__global__ void k_boxes_at(const int32_t *__restrict__ order, int64_t count, const int32_t *__restrict__ left,
+                           const int32_t *__restrict__ right, float *int_box, const float *__restrict__ leaf_box) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int32_t p = parent_leaf[i];
-    // a consistent tree has fewer than n inner nodes above a leaf
-    for (int64_t guard = 0; p >= 0 && p < n - 1 && guard < n; ++guard) {
-        uint32_t old = __hip_atomic_fetch_add(&counter[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == 0u) return;
-        const int32_t a = left[p], b = right[p];
-        const int32_t ha = a < 0 ? 0 : __hip_atomic_load(&height[a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int32_t hb = b < 0 ? 0 : __hip_atomic_load(&height[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int32_t h = 1 + (ha > hb ? ha : hb);
-        __hip_atomic_store(&height[p], h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((int64_t)h < n) atomicAdd(&hcount[h], 1u);  // always: a height is below n
-        atomicMax(hmax, (uint32_t)h);
-        p = parent_int[p];
+    if (i >= count) return;
+    const int32_t x = order[i];
+    const int32_t c[2] = {left[x], right[x]};
+    float b[12];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float *src = c[k] < 0 ? leaf_box + 6 * (int64_t)(-c[k] - 1) : int_box + 6 * (int64_t)c[k];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) b[6 * k + q] = src[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        int_box[6 * (int64_t)x + q] = fminf(b[q], b[6 + q]);
+        int_box[6 * (int64_t)x + 3 + q] = fmaxf(b[3 + q], b[9 + q]);
     }
 }
 
-// Inner nodes grouped by height: order[hstart[h] ...] holds height h.
-__global__ void k_height_scatter(int64_t m, const int32_t *__restrict__ height, const uint32_t *__restrict__ hstart,
-                                 uint32_t *hcursor, int32_t hmax, int32_t *__restrict__ order) {
-    const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (x >= m) return;
-    const int32_t h = height[x];
-    if (h < 1 || h > hmax) return;  // never once the host has checked the counts
-    order[hstart[h] + atomicAdd(&hcursor[h], 1u)] = (int32_t)x;
+__global__ void k_sizes_at(const int32_t *__restrict__ order, int64_t count, const int32_t *__restrict__ left,
+                           const int32_t *__restrict__ right, int32_t *size) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int32_t x = order[i];
+    const int32_t a = left[x], b = right[x];
+    size[x] = (a < 0 ? 1 : size[a]) + (b < 0 ? 1 : size[b]);
+}
+
+__global__ void k_leaf_boxes(const float *__restrict__ prim_box, const uint32_t *__restrict__ ids, int64_t n,
+                             float *__restrict__ leaf_box) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t src = ids[i];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) leaf_box[6 * i + k] = prim_box[6 * (int64_t)src + k];
 }
 
 __global__ void __launch_bounds__(64) k_treelet(const int32_t *__restrict__ order, int32_t *left, int32_t *right,
@@ -727,6 +748,7 @@ __global__ void __launch_bounds__(64) k_treelet(const int32_t *__restrict__ orde
     __shared__ int n_leaves, n_opened;
     const int lane = threadIdx.x;
     const int32_t node = order[blockIdx.x];
+    if (left[node] < 0 && right[node] < 0) return;  // two leaves: one topology, nothing to change
     if (lane == 0) {
         int m = 2, r = 0;
         leaves[0] = left[node];
@@ -1234,14 +1256,15 @@ uint64_t align256(uint64_t x) { return (x + 255u) & ~uint64_t(255); }
 struct LbvhScratch {
     float *leaf_box, *int_box;
     uint64_t *keys, *keys2;
-    uint32_t *ids, *ids2, *hist, *bounds, *counter, *qcount, *flags;
+    uint32_t *ids, *ids2, *hist, *bounds, *qcount, *flags;
     int32_t *left, *right, *pint, *pleaf, *first, *last;
     uint2 *q0, *q1;
     // clustering only
     int32_t *cid[2], *nearest, *rank, *size;
     float *cbox[2];
     uint32_t *n_merge, *n_keep;
-    // treelet restructuring only (with rank, size, cbox[0])
+    // inner nodes grouped by depth (depth, order, counts); treelet
+    // restructuring also takes rank, size and cbox[0]
     int32_t *height, *order;
     uint32_t *hcount, *hcursor, *hstart, *hmax;
 };
@@ -1257,7 +1280,6 @@ bool carve(RgArena &a, int64_t n, int32_t builder, LbvhScratch &s) {
     s.ids2 = a.take<uint32_t>(n);
     s.hist = a.take<uint32_t>(256 * nb);
     s.bounds = a.take<uint32_t>(8);
-    s.counter = a.take<uint32_t>(ni);
     s.qcount = a.take<uint32_t>(8);
     s.flags = a.take<uint32_t>(8);
     s.left = a.take<int32_t>(ni);
@@ -1284,14 +1306,47 @@ bool carve(RgArena &a, int64_t n, int32_t builder, LbvhScratch &s) {
         s.cbox[0] = a.take<float>(6 * n);
         s.rank = a.take<int32_t>(n);
         s.size = a.take<int32_t>(ni);
-        s.height = a.take<int32_t>(ni);
-        s.order = a.take<int32_t>(ni);
-        s.hcount = a.take<uint32_t>(n + 1);
-        s.hcursor = a.take<uint32_t>(n + 1);
-        s.hstart = a.take<uint32_t>(n + 1);
-        s.hmax = a.take<uint32_t>(8);
     }
+    s.height = a.take<int32_t>(ni);
+    s.order = a.take<int32_t>(ni);
+    s.hcount = a.take<uint32_t>(n + 1);
+    s.hcursor = a.take<uint32_t>(n + 1);
+    s.hstart = a.take<uint32_t>(n + 1);
+    s.hmax = a.take<uint32_t>(8);
     return !a.overflow();
+}
+
+// The m >= 1 inner nodes of the binary hierarchy in s grouped by depth from
+// the root: s.order[start[d] .. start[d] + cnt[d]) holds depth d.
+struct DepthOrder {
+    uint32_t dmax = 0;
+    std::vector<uint32_t> cnt, start;
+};
+
+rg_status depth_order(LbvhScratch &s, int64_t m, hipStream_t st, DepthOrder &o) {
+    k_fill_u32<<<rg_blocks(m + 2, kThreads), kThreads, 0, st>>>(s.hcount, 0u, m + 2);
+    k_fill_u32<<<1, 64, 0, st>>>(s.hmax, 0u, 1);
+    k_depths<<<rg_blocks(m, kThreads), kThreads, 0, st>>>(m, s.pint, s.height, s.hcount, s.hmax);
+    RG_LAUNCH_CHECK();
+    RG_HIP(hipMemcpyAsync(&o.dmax, s.hmax, 4, hipMemcpyDeviceToHost, st));
+    RG_HIP(hipStreamSynchronize(st));
+    if ((int64_t)o.dmax >= m) return RG_ERR_HIP;  // never: a depth is below the inner node count
+    o.cnt.assign(o.dmax + 1, 0u);
+    o.start.assign(o.dmax + 1, 0u);
+    RG_HIP(hipMemcpyAsync(o.cnt.data(), s.hcount, 4 * (o.dmax + 1), hipMemcpyDeviceToHost, st));
+    RG_HIP(hipStreamSynchronize(st));
+    uint64_t total = 0;
+    for (uint32_t d = 0; d <= o.dmax; ++d) {
+        o.start[d] = (uint32_t)total;
+        total += o.cnt[d];
+    }
+    if ((int64_t)total != m) return RG_ERR_HIP;  // never: every inner node has one depth
+    RG_HIP(hipMemcpyAsync(s.hstart, o.start.data(), 4 * (o.dmax + 1), hipMemcpyHostToDevice, st));
+    k_fill_u32<<<rg_blocks(o.dmax + 1, kThreads), kThreads, 0, st>>>(s.hcursor, 0u, o.dmax + 1);
+    k_depth_scatter<<<rg_blocks(m, kThreads), kThreads, 0, st>>>(m, s.height, s.hstart, s.hcursor, (int32_t)o.dmax,
+                                                                  s.order);
+    RG_LAUNCH_CHECK();
+    return RG_OK;
 }
 
 // Renumbers the leaves of the binary hierarchy in s (n >= 2) in the tree's
@@ -1299,9 +1354,14 @@ bool carve(RgArena &a, int64_t n, int32_t builder, LbvhScratch &s) {
 // (which then replaces s.leaf_box), inner leaf ranges first / last.
 rg_status relabel_leaves(LbvhScratch &s, int64_t n, const uint32_t *ids, uint32_t *ids_out, float *box_out,
                          hipStream_t st) {
-    k_fill_u32<<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>(s.counter, 0u, n - 1);
-    k_ploc_sizes<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(n, s.left, s.right, s.pint, s.pleaf, s.counter,
-                                                               s.size);
+    DepthOrder o;
+    rg_status r = depth_order(s, n - 1, st, o);
+    if (r != RG_OK) return r;
+    for (int64_t d = o.dmax; d >= 0; --d)
+        k_sizes_at<<<rg_blocks(o.cnt[d], kThreads), kThreads, 0, st>>>(s.order + o.start[d], o.cnt[d], s.left,
+                                                                        s.right, s.size);
+    RG_LAUNCH_CHECK();
+    RG_HIP(hipStreamSynchronize(st));  // the host vectors of `o` go away on return
     k_ploc_ranks<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(n, s.left, s.pint, s.pleaf, s.size, ids,
                                                                s.leaf_box, s.rank, s.first, s.last, ids_out,
                                                                box_out);
@@ -1352,37 +1412,18 @@ rg_status ploc_build(const float *prim_box, int64_t n, int radius, const uint32_
 rg_status treelet_build(int64_t n, int rounds, const uint32_t *ids, uint32_t *ids_out, LbvhScratch &s,
                         hipStream_t st) {
     const int64_t m = n - 1;
-    std::vector<uint32_t> cnt, start;
     for (int round = 0; round < rounds; ++round) {
-        k_fill_u32<<<rg_blocks(m, kThreads), kThreads, 0, st>>>(s.counter, 0u, m);
-        k_fill_u32<<<rg_blocks(n + 1, kThreads), kThreads, 0, st>>>(s.hcount, 0u, n + 1);
-        k_fill_u32<<<1, 64, 0, st>>>(s.hmax, 0u, 1);
-        k_heights<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(n, s.left, s.right, s.pint, s.pleaf, s.counter,
-                                                                s.height, s.hcount, s.hmax);
-        RG_LAUNCH_CHECK();
-        uint32_t hmax = 0;
-        RG_HIP(hipMemcpyAsync(&hmax, s.hmax, 4, hipMemcpyDeviceToHost, st));
-        RG_HIP(hipStreamSynchronize(st));
-        if (hmax < 2u) break;  // no inner node has three leaves below it
-        if ((int64_t)hmax > m) return RG_ERR_HIP;  // never: a height is below the inner node count
-        cnt.assign(hmax + 1, 0u);
-        start.assign(hmax + 1, 0u);
-        RG_HIP(hipMemcpyAsync(cnt.data(), s.hcount, 4 * (hmax + 1), hipMemcpyDeviceToHost, st));
-        RG_HIP(hipStreamSynchronize(st));
-        uint64_t total = 0;
-        for (uint32_t h = 1; h <= hmax; ++h) {
-            start[h] = (uint32_t)total;
-            total += cnt[h];
-        }
-        if ((int64_t)total != m) return RG_ERR_HIP;  // never: every inner node has a height
-        RG_HIP(hipMemcpyAsync(s.hstart, start.data(), 4 * (hmax + 1), hipMemcpyHostToDevice, st));
-        k_fill_u32<<<rg_blocks(hmax + 1, kThreads), kThreads, 0, st>>>(s.hcursor, 0u, hmax + 1);
-        k_height_scatter<<<rg_blocks(m, kThreads), kThreads, 0, st>>>(m, s.height, s.hstart, s.hcursor,
-                                                                       (int32_t)hmax, s.order);
-        RG_LAUNCH_CHECK();
-        for (uint32_t h = 2; h <= hmax; ++h) {
-            if (cnt[h] == 0u) continue;
-            k_treelet<<<cnt[h], 64, 0, st>>>(s.order + start[h], s.left, s.right, s.pint, s.pleaf, s.int_box,
+        DepthOrder o;
+        rg_status r = depth_order(s, m, st, o);
+        if (r != RG_OK) return r;
+        if (o.dmax < 1u) break;  // only the root: no inner node has three leaves below it
+        const std::vector<uint32_t> &cnt = o.cnt, &start = o.start;
+        const uint32_t dmax = o.dmax;
+        // deepest first: a node's descendants are deeper, nodes of one depth
+        // have disjoint subtrees
+        for (int64_t d = dmax; d >= 0; --d) {
+            if (cnt[d] == 0u) continue;
+            k_treelet<<<cnt[d], 64, 0, st>>>(s.order + start[d], s.left, s.right, s.pint, s.pleaf, s.int_box,
                                              s.leaf_box);
         }
         RG_LAUNCH_CHECK();
@@ -1496,12 +1537,21 @@ rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t
         if (n > 1) {
             k_karras<<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>(ka, n, s.left, s.right, s.pint, s.pleaf,
                                                                       s.first, s.last);
-            k_fill_u32<<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>(s.counter, 0u, n - 1);
             RG_LAUNCH_CHECK();
         }
-        k_refit<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(prim_box, ia, n, s.left, s.right, s.pint, s.pleaf,
-                                                             s.counter, s.int_box, s.leaf_box);
+        k_leaf_boxes<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(prim_box, ia, n, s.leaf_box);
         RG_LAUNCH_CHECK();
+        if (n > 1) {  // inner boxes level by level, deepest first
+            DepthOrder o;
+            rg_status r = depth_order(s, n - 1, st, o);
+            if (r != RG_OK) return r;
+            for (int64_t d = o.dmax; d >= 0; --d)
+                k_boxes_at<<<rg_blocks(o.cnt[d], kThreads), kThreads, 0, st>>>(s.order + o.start[d], o.cnt[d],
+                                                                                s.left, s.right, s.int_box,
+                                                                                s.leaf_box);
+            RG_LAUNCH_CHECK();
+            RG_HIP(hipStreamSynchronize(st));  // the host vectors of `o` go away here
+        }
         if (builder == RG_BUILDER_TREELET && n > 1) {
             rg_status r = treelet_build(n, radius, ia, ib, s, st);
             if (r != RG_OK) return r;
