@@ -71,13 +71,13 @@ def recorded_traffic(args):
 
 
 # Hierarchy shape per workload (node width, leaf size, builder), the best
-# measured on MI355X: the incoherent AO rays run fastest on width-4 linear
-# BVHs restructured by treelets (7% over the plain linear BVH, 9% fewer node
-# visits); the serving mix (dominated by the regular torus meshes) on width-4
-# linear BVHs; whole two-level frames on width-8 clustered hierarchies.  The
-# batched workload starts from its entry and can be autotuned.
-SHAPES = {"incoherent": (4, 1, "treelet"), "two_level": (8, 1, "ploc"), "batched": (4, 1, "lbvh"),
-          "serving": (4, 1, "lbvh"), "dynamic": (4, 1, "treelet"), "post": (8, 1, "ploc")}
+# measured on MI355X: linear BVHs restructured by treelets throughout, at
+# width 4 for the incoherent AO rays (7% over the plain linear BVH, 9% fewer
+# node visits), the serving mix and the dynamic scene, at width 8 for whole
+# two-level frames (2% over clustering, 4% over width 4).  The batched
+# workload starts from its entry and can be autotuned.
+SHAPES = {"incoherent": (4, 1, "treelet"), "two_level": (8, 1, "treelet"), "batched": (4, 1, "lbvh"),
+          "serving": (4, 1, "treelet"), "dynamic": (4, 1, "treelet"), "post": (8, 1, "treelet")}
 
 
 def log(*a):
