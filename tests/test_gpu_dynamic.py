@@ -22,7 +22,7 @@ def _dev(verts, idx):
     return v, i
 
 
-@pytest.mark.parametrize("builder", ["lbvh", "ploc"])
+@pytest.mark.parametrize("builder", ["lbvh", "ploc", "treelet"])
 @pytest.mark.parametrize("width,leaf", [(2, 1), (4, 1), (4, 4), (8, 3)])
 def test_refit_to_unchanged_vertices_reproduces_the_build(builder, width, leaf):
     import paper_2001_09792_amd as rg
@@ -39,16 +39,16 @@ def test_refit_to_unchanged_vertices_reproduces_the_build(builder, width, leaf):
     assert rg.blas_state(b) == (lo, hi, 0)
 
 
-@pytest.mark.parametrize("width,leaf", [(2, 1), (4, 1), (8, 4)])
-def test_refit_to_moved_vertices_holds_the_new_mesh(width, leaf):
+@pytest.mark.parametrize("width,leaf,builder", [(2, 1, "lbvh"), (4, 1, "lbvh"), (8, 4, "lbvh"), (4, 1, "treelet")])
+def test_refit_to_moved_vertices_holds_the_new_mesh(width, leaf, builder):
     """Structure and boxes checked on the host; the triangles in leaf order
     are the moved ones; hits against the oracle on the moved mesh."""
     import paper_2001_09792_amd as rg
     mesh = sg.torus(64, 48, 1.0, 0.35, 0.08, 6.0, 3002)
     moved = sg.Mesh(sg.animate_mesh(mesh, 0.35, amp=0.08, seed=5), mesh.idx)
-    print(f"[refit moved] W{width} L{leaf}", flush=True)
+    print(f"[refit moved] W{width} L{leaf} {builder}", flush=True)
     v0, i = _dev(mesh.verts, mesh.idx)
-    b = rg.build_blas(v0, i, None, width, leaf)
+    b = rg.build_blas(v0, i, None, width, leaf, builder=builder)
     v1, _ = _dev(moved.verts, moved.idx)
     rg.refit_blas(b, v1, i)
     info = bvh_check.check_blas(b.buf.cpu().numpy(), b.desc, refitted=True)
@@ -75,22 +75,23 @@ def _moved_two_level(t):
     return sc, meshes, xf
 
 
-def test_refitted_scene_traces_like_a_fresh_build():
+@pytest.mark.parametrize("builder", ["lbvh", "treelet"])
+def test_refitted_scene_traces_like_a_fresh_build(builder):
     """Hits do not depend on the hierarchy (ties go to the lowest instance and
     input triangle, the instance slide point depends only on the root box,
     which a refit computes exactly): the refitted scene gives bitwise the hits
     of a scene built from scratch at the new positions."""
     import paper_2001_09792_amd as rg
     sc, moved, xf = _moved_two_level(0.3)
-    print("[dynamic] two-level, refit + top-level rebuild", flush=True)
-    tl0 = rg.upload_scene(sc, 4, 1)
+    print(f"[dynamic] two-level, refit + top-level rebuild ({builder})", flush=True)
+    tl0 = rg.upload_scene(sc, 4, 1, builder=builder)
     for b, m in zip(tl0.blas, moved):
         v, i = _dev(m.verts, m.idx)
         rg.refit_blas(b, v, i)
-    tl_refit = rg.build_tlas(tl0.blas, xf, sc.blas_id, sc.inst_mat, 4)
+    tl_refit = rg.build_tlas(tl0.blas, xf, sc.blas_id, sc.inst_mat, 4, builder=builder)
     fresh_scene = sg.Scene(sc.name, moved, xf, sc.blas_id, sc.inst_mat, sc.materials, sc.camera, sc.light,
                            sc.width, sc.height, sc.max_depth, sc.mode, sc.seed)
-    tl_fresh = rg.upload_scene(fresh_scene, 4, 1)
+    tl_fresh = rg.upload_scene(fresh_scene, 4, 1, builder=builder)
     for b in tl_refit.blas:
         bvh_check.check_blas(b.buf.cpu().numpy(), b.desc, refitted=True)
     roots = [rg.blas_state(b)[:2] for b in tl_refit.blas]
