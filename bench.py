@@ -119,16 +119,18 @@ def cpu_baseline_incoherent(scene, n_primary: int, seconds: float = 15.0) -> dic
     # keep the primary : AO ratio of the full workload in the sample
     rays = np.concatenate([prim, aor])
     n_total = rays.shape[0]
-    # time a probe, then size the sample to about `seconds`
-    probe = rays[np.linspace(0, n_total - 1, min(64, n_total)).astype(int)]
-    t0 = time.perf_counter()
-    orc.trace(probe)
-    per_ray = (time.perf_counter() - t0) / probe.shape[0]
-    n = int(max(64, min(n_total, seconds / max(per_ray, 1e-9))))
-    sel = np.linspace(0, n_total - 1, n).astype(int)
-    t0 = time.perf_counter()
-    res = orc.trace(rays[sel])
-    dt = time.perf_counter() - t0
+    # trace the sample in interleaved chunks (every chunk keeps the camera : AO
+    # mix) until about `seconds` have passed or the sample is used up
+    order = np.argsort((np.arange(n_total) * 0.6180339887498949) % 1.0, kind="stable")
+    n, dt, tests = 0, 0.0, 0
+    while n < n_total and dt < seconds:
+        chunk = order[n: n + 256]
+        t0 = time.perf_counter()
+        tests += orc.trace(rays[chunk])["tests"]
+        dt += time.perf_counter() - t0
+        n += chunk.shape[0]
+    sel = order[:n]
+    res = {"tests": tests}
     return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": cpu_threads(), "kind": "oracle",
             "sample": f"{n} rays ({int((sel < prim.shape[0]).sum())} camera + AO rays of {px.shape[0]} "
                       f"sampled pixels), FP64 brute force with exact bounding-sphere reject, "
