@@ -10,8 +10,8 @@
 // the perceptual luma sqrt(clamp(0.299 R + 0.587 G + 0.114 B, 0, 1)).
 //
 // Both are memory-bound stencils over float[h][w][3] images: one thread per
-// pixel, 64 x 4 pixel blocks, so that a wave reads one row segment and a
-// block's taps along y stay in the same cache lines.
+// pixel, 64 x 4 pixel blocks, so that a wave reads one row segment; the blur
+// stages each block's pixels and their halo along its axis in LDS.
 #include "rg_internal.h"
 
 namespace {
@@ -34,44 +34,68 @@ __device__ inline void st3(float *__restrict__ img, int64_t p, Px3 v) {
     img[3 * p + 2] = v.b;
 }
 
-// One pass of the blur along x (AXIS 0) or y (AXIS 1).
+// One pass of the blur along x (AXIS 0) or y (AXIS 1).  The block's pixels
+// and the `radius` pixels beyond them along the axis are staged in LDS once,
+// each as (r, g, b, material bits) in 16 bytes, so a tap is one LDS read.
+constexpr uint32_t kOutside = 0xFFFFFFFEu;  // material of positions outside the image
+
 template <int AXIS>
 __global__ void __launch_bounds__(kBX *kBY) k_blur(const float *__restrict__ in, const uint32_t *__restrict__ mat,
                                                    const float *__restrict__ rough, uint32_t n_mats, int w, int h,
                                                    int radius, float *__restrict__ out) {
-    const int x = blockIdx.x * kBX + threadIdx.x, y = blockIdx.y * kBY + threadIdx.y;
-    if (x >= w || y >= h) return;
+    extern __shared__ float4 tile[];
+    const int tid = threadIdx.y * kBX + threadIdx.x;
+    const int x0 = blockIdx.x * kBX, y0 = blockIdx.y * kBY;
+    const int x = x0 + threadIdx.x, y = y0 + threadIdx.y;
+    const bool inside = x < w && y < h;
     const int64_t p = (int64_t)y * w + x;
-    const uint32_t m = mat[p];
+    const uint32_t m = inside ? mat[p] : kOutside;
     float r = 0.0f;
     if (m < n_mats) r = fminf(fmaxf(rough[m], 0.0f), 1.0f);
-    if (!(r >= kRoughMin) || radius == 0) {  // sky, unknown material, smooth, NaN roughness, no window
-        st3(out, p, ld3(in, p));
+    // sky, unknown material, smooth, NaN roughness or no window: a copy; a
+    // block without any pixel to blur stages nothing
+    const bool blur = inside && r >= kRoughMin && radius > 0;
+    if (!__syncthreads_or(blur)) {
+        if (inside) st3(out, p, ld3(in, p));
+        return;
+    }
+    const int TW = AXIS == 0 ? kBX + 2 * radius : kBX, TH = AXIS == 0 ? kBY : kBY + 2 * radius;
+    const int gx0 = AXIS == 0 ? x0 - radius : x0, gy0 = AXIS == 0 ? y0 : y0 - radius;
+    for (int i = tid; i < TW * TH; i += kBX * kBY) {
+        const int gx = gx0 + i % TW, gy = gy0 + i / TW;
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, __uint_as_float(kOutside));
+        if (gx >= 0 && gx < w && gy >= 0 && gy < h) {
+            const int64_t q = (int64_t)gy * w + gx;
+            v = make_float4(in[3 * q], in[3 * q + 1], in[3 * q + 2], __uint_as_float(mat[q]));
+        }
+        tile[i] = v;
+    }
+    __syncthreads();
+    if (!inside) return;
+    const int c = AXIS == 0 ? threadIdx.y * TW + threadIdx.x + radius : (threadIdx.y + radius) * TW + threadIdx.x;
+    const int step = AXIS == 0 ? 1 : TW;
+    const float4 c0 = tile[c];
+    if (!blur) {
+        st3(out, p, {c0.x, c0.y, c0.z});
         return;
     }
     const float sigma = r * (float)radius / 3.0f;
     const float inv = 1.0f / (2.0f * sigma * sigma);
-    const int pos = AXIS == 0 ? x : y, lim = AXIS == 0 ? w : h;
-    const int64_t stride = AXIS == 0 ? 1 : (int64_t)w;
-    const Px3 c0 = ld3(in, p);
-    float nr = c0.r, ng = c0.g, nb = c0.b, den = 1.0f;  // the centre tap, weight 1
+    float nr = c0.x, ng = c0.y, nb = c0.z, den = 1.0f;  // the centre tap, weight 1
     // taps -k and +k share their weight: one exponential per distance
     for (int k = 1; k <= radius; ++k) {
-        const bool lo_in = pos - k >= 0, hi_in = pos + k < lim;
-        if (!lo_in && !hi_in) break;
         const float wt = expf(-(float)(k * k) * inv);
-        if (lo_in && mat[p - k * stride] == m) {
-            const Px3 c = ld3(in, p - k * stride);
-            nr += wt * c.r;
-            ng += wt * c.g;
-            nb += wt * c.b;
+        const float4 a = tile[c - k * step], b = tile[c + k * step];
+        if (__float_as_uint(a.w) == m) {
+            nr += wt * a.x;
+            ng += wt * a.y;
+            nb += wt * a.z;
             den += wt;
         }
-        if (hi_in && mat[p + k * stride] == m) {
-            const Px3 c = ld3(in, p + k * stride);
-            nr += wt * c.r;
-            ng += wt * c.g;
-            nb += wt * c.b;
+        if (__float_as_uint(b.w) == m) {
+            nr += wt * b.x;
+            ng += wt * b.y;
+            nb += wt * b.z;
             den += wt;
         }
     }
@@ -202,8 +226,10 @@ rg_status rg_roughness_blur(const float *in, const uint32_t *mat, const float *r
         return RG_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
     const dim3 g = grid_of(width, height), b(kBX, kBY);
-    k_blur<0><<<g, b, 0, st>>>(in, mat, roughness, (uint32_t)n_mats, width, height, radius, tmp);
-    k_blur<1><<<g, b, 0, st>>>(tmp, mat, roughness, (uint32_t)n_mats, width, height, radius, out);
+    const size_t lds_x = sizeof(float4) * (size_t)(kBX + 2 * radius) * kBY;
+    const size_t lds_y = sizeof(float4) * (size_t)kBX * (kBY + 2 * radius);
+    k_blur<0><<<g, b, lds_x, st>>>(in, mat, roughness, (uint32_t)n_mats, width, height, radius, tmp);
+    k_blur<1><<<g, b, lds_y, st>>>(tmp, mat, roughness, (uint32_t)n_mats, width, height, radius, out);
     RG_LAUNCH_CHECK();
     return RG_OK;
 }
