@@ -78,7 +78,7 @@ def _scene(seed):
     return sc, masks, rng
 
 
-@pytest.mark.parametrize("builder,width,leaf", [("lbvh", 4, 4), ("ploc", 8, 3), ("lbvh", 2, 1)])
+@pytest.mark.parametrize("builder,width,leaf", [("lbvh", 4, 4), ("ploc", 8, 3), ("lbvh", 2, 1), ("treelet", 4, 1)])
 def test_parity_with_the_oracle(builder, width, leaf):
     """Levels 0, 1, 2, 3 on four meshes (one without masks in the second
     case), alone and with culling and per-ray masks."""
@@ -153,6 +153,34 @@ def test_render_with_opacity_masks_matches_oracle():
     plain = rg.render(rg.upload_scene(sc, 4, 1), sc.materials, sc.camera, sc.light, sc.width, sc.height,
                       sc.max_depth).cpu().numpy()
     assert not np.array_equal(img, plain)
+
+
+def test_masks_survive_a_refit():
+    """The masks belong to the triangles (input order), not to the hierarchy:
+    after a refit to moved vertices the top level rebuilt over the bottom
+    level still ignores the transparent micro-triangles of the moved mesh."""
+    rg = _rg()
+    mesh = sg.torus(48, 40, 1.0, 0.35, 0.08, 6.0, 3004)
+    moved = sg.Mesh(sg.animate_mesh(mesh, 0.3, amp=0.06, seed=9), mesh.idx)
+    rng = np.random.default_rng(60)
+    masks = rng.integers(0, 2 ** 63, mesh.n_tris, dtype=np.int64).astype(np.uint64)
+    import torch
+    v0 = torch.from_numpy(mesh.verts).cuda()
+    idx = torch.from_numpy(mesh.idx.view(np.int32)).cuda()
+    b = rg.build_blas(v0, idx, None, 4, 1, builder="treelet")
+    rg.set_alpha(b, _masks(masks), 2)
+    rg.refit_blas(b, torch.from_numpy(moved.verts).cuda(), idx)
+    tl = rg.build_tlas([b], sg.identity_xform(1), [0], [0], 4)
+    assert tl.desc.has_inst_flags == 1
+    cen = moved.verts[moved.idx].mean(axis=1)
+    rays = np.concatenate([sg.random_rays(3000, 61, extent=1.8),
+                           sg.rays_through_points(cen[rng.integers(0, cen.shape[0], 3000)], 62, 3.0)])
+    rd = rg.rays_to_device(rays)
+    orc = oracle.Scene(scene_from_meshes([moved]), alpha=[(masks, 2)])
+    print("[alpha refit]", flush=True)
+    res = parity.check_closest(parity.hits_to_numpy(rg.trace_closest(tl, rd)), orc.trace(rays), 0.04, "alpha refit")
+    parity.check_any(rg.trace_any(tl, rd).cpu().numpy(), orc.trace(rays, any_hit=True), 0.04, "alpha refit any")
+    print(f"  {res}", flush=True)
 
 
 def test_bad_masks_are_rejected():
