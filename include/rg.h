@@ -54,6 +54,12 @@ typedef int32_t rg_status;
 #define RG_ERR_HIP (-3)           /* a HIP runtime call or kernel launch failed */
 #define RG_ERR_UNSUPPORTED (-4)   /* valid request outside what this build handles */
 #define RG_ERR_UNIMPLEMENTED (-5)
+/* Asynchronous calls (tracing, rendering, batches, the engine's step, refits,
+ * opacity masks, post-process passes, ray generation) only enqueue work: a
+ * device fault surfaces at the caller's next synchronisation.  With RG_DEBUG=1
+ * in the environment (read once per process) each of them waits for its
+ * stream before returning and reports a failed launch or a fault as
+ * RG_ERR_HIP (rg_last_error() names it). */
 
 #define RG_MISS 0xFFFFFFFFu
 #define RG_PER_PRIM 0xFFFFFFFFu   /* instance material: use the mesh's per-primitive ids */

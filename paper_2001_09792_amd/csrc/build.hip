@@ -16,6 +16,7 @@
 //      child with the largest surface area), leaves of <= leaf_max prims,
 // followed by reordering the primitives into leaf order.
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <vector>
@@ -1658,6 +1659,21 @@ void rg_set_error(const char *file, int line, const char *what) {
     snprintf(g_last_error, sizeof(g_last_error), "%s:%d: %s", base, line, what);
 }
 
+rg_status rg_debug_done(rg_status r, hipStream_t st) {
+    static const bool on = [] {
+        const char *v = getenv("RG_DEBUG");
+        return v && v[0] && !(v[0] == '0' && v[1] == 0);
+    }();
+    if (!on || r != RG_OK) return r;
+    hipError_t e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) {
+        rg_set_error(__FILE__, __LINE__, hipGetErrorName(e));
+        return RG_ERR_HIP;
+    }
+    return RG_OK;
+}
+
 extern "C" {
 
 const char *rg_last_error(void) { return g_last_error; }
@@ -1819,7 +1835,7 @@ rg_status rg_refit_blas_many(rg_blas *blas, int32_t n_blas, const float *const *
             RG_LAUNCH_CHECK();
         }
     }
-    return RG_OK;
+    return rg_debug_done(RG_OK, st);
 }
 
 rg_status rg_refit_blas(rg_blas *blas, const float *verts, int64_t n_verts, const uint32_t *idx, int64_t n_tris,
@@ -1849,7 +1865,7 @@ rg_status rg_blas_set_alpha(rg_blas *blas, const uint64_t *alpha, int32_t level,
     RG_LAUNCH_CHECK();
     blas->has_alpha = alpha ? 1 : 0;
     blas->alpha_level = alpha ? level : 0;
-    return RG_OK;
+    return rg_debug_done(RG_OK, st);
 }
 
 rg_status rg_tlas_sizes(int64_t n_inst, const rg_build_opts *opts, rg_sizes *out) {

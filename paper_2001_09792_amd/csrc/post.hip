@@ -231,7 +231,7 @@ rg_status rg_roughness_blur(const float *in, const uint32_t *mat, const float *r
     k_blur<0><<<g, b, lds_x, st>>>(in, mat, roughness, (uint32_t)n_mats, width, height, radius, tmp);
     k_blur<1><<<g, b, lds_y, st>>>(tmp, mat, roughness, (uint32_t)n_mats, width, height, radius, out);
     RG_LAUNCH_CHECK();
-    return RG_OK;
+    return rg_debug_done(RG_OK, st);
 }
 
 rg_status rg_fxaa(const float *in, int32_t width, int32_t height, float *out, void *scratch, uint64_t scratch_bytes,
@@ -249,7 +249,7 @@ rg_status rg_fxaa(const float *in, int32_t width, int32_t height, float *out, vo
     k_luma<<<g, b, 0, st>>>(in, width, height, luma);
     k_fxaa<<<g, b, 0, st>>>(in, luma, width, height, out);
     RG_LAUNCH_CHECK();
-    return RG_OK;
+    return rg_debug_done(RG_OK, st);
 }
 
 }  // extern "C"

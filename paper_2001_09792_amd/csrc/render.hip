@@ -798,7 +798,7 @@ rg_status rg_camera_rays(const rg_camera *cam, int32_t width, int32_t height, fl
     k_camera_rays<<<rg_blocks(n, kT), kT, 0, (hipStream_t)stream>>>(
         *cam, width, height, rays[0], rays[1], rays[2], rays[3], rays[4], rays[5], rays[6], rays[7]);
     RG_LAUNCH_CHECK();
-    return RG_OK;
+    return rg_debug_done(RG_OK, (hipStream_t)stream);
 }
 
 rg_status rg_ao_rays_scratch(int64_t n, uint64_t *scratch_bytes) {
@@ -835,7 +835,7 @@ rg_status rg_ao_rays(const rg_tlas *tlas, rg_rays rays, int64_t n, const uint32_
     a.count = out_count;
     a.block_off = (uint32_t *)scratch;
     a.map = true;
-    return ao_generate(a, (hipStream_t)stream);
+    return rg_debug_done(ao_generate(a, (hipStream_t)stream), (hipStream_t)stream);
 }
 
 rg_status rg_batch_sizes(const rg_job *jobs, int32_t n_jobs, uint64_t *scratch_bytes) {
@@ -899,7 +899,13 @@ rg_status rg_batch_prepare(const rg_job *jobs, int32_t n_jobs, void *scratch, ui
     return RG_OK;
 }
 
+static rg_status batch_impl(const rg_batch *batch, void *stream, rg_render_stats *stats);
+
 rg_status rg_batch_render(const rg_batch *batch, void *stream, rg_render_stats *stats) {
+    return rg_debug_done(batch_impl(batch, stream, stats), (hipStream_t)stream);
+}
+
+static rg_status batch_impl(const rg_batch *batch, void *stream, rg_render_stats *stats) {
     if (!batch || !batch->scratch || batch->n_jobs < 1) return RG_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -945,10 +951,24 @@ rg_status rg_render(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats
                         scratch, scratch_bytes, stream, stats);
 }
 
+static rg_status render_impl(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats, const rg_camera *cam,
+                             const rg_light *light, int32_t width, int32_t height, int32_t max_depth, int32_t mode,
+                             uint64_t seed, float *image, uint32_t *primary_mat, void *scratch,
+                             uint64_t scratch_bytes, void *stream, rg_render_stats *stats);
+
 rg_status rg_render_ex(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats, const rg_camera *cam,
                        const rg_light *light, int32_t width, int32_t height, int32_t max_depth, int32_t mode,
                        uint64_t seed, float *image, uint32_t *primary_mat, void *scratch, uint64_t scratch_bytes,
                        void *stream, rg_render_stats *stats) {
+    return rg_debug_done(render_impl(tlas, mats, n_mats, cam, light, width, height, max_depth, mode, seed, image,
+                                     primary_mat, scratch, scratch_bytes, stream, stats),
+                         (hipStream_t)stream);
+}
+
+static rg_status render_impl(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats, const rg_camera *cam,
+                             const rg_light *light, int32_t width, int32_t height, int32_t max_depth, int32_t mode,
+                             uint64_t seed, float *image, uint32_t *primary_mat, void *scratch,
+                             uint64_t scratch_bytes, void *stream, rg_render_stats *stats) {
     if (!tlas_valid(tlas) || !mats || n_mats < 1 || n_mats > 256 || !cam || !light || !image || !scratch)
         return RG_ERR_INVALID_ARG;
     if (primary_mat && mode != 0) return RG_ERR_UNSUPPORTED;

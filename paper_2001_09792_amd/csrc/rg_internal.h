@@ -78,6 +78,11 @@ static_assert(sizeof(RgMat) == sizeof(rg_material), "material");
 // Host-side error plumbing: the failing call is recorded per thread and
 // reported by rg_last_error().
 void rg_set_error(const char *file, int line, const char *what);
+
+// With RG_DEBUG=1 in the environment (read once), an asynchronous entry point
+// waits for its stream before returning and reports a failed launch or a
+// device fault as RG_ERR_HIP; otherwise returns r unchanged.
+rg_status rg_debug_done(rg_status r, hipStream_t st);
 #define RG_HIP(x)                                                  \
     do {                                                           \
         hipError_t e_ = (x);                                       \

@@ -390,7 +390,7 @@ rg_status rg_engine_step(rg_engine *E, int32_t *ran) {
     E->max_frames_in_pass = std::max(E->max_frames_in_pass, frames);
     E->max_depths_in_pass = std::max<int64_t>(E->max_depths_in_pass, __builtin_popcount(depth_mask));
     if (ran) *ran = 1;
-    return RG_OK;
+    return rg_debug_done(RG_OK, E->st);
 }
 
 rg_status rg_engine_poll(rg_engine *E, int32_t wait, int64_t *tags, int32_t cap, int32_t *n_done) {

@@ -202,9 +202,9 @@ rg_status rg_trace_launch(int width, bool any, int mode, const RgTraceArgs &a, h
     if (a.n <= 0) return RG_OK;
     if (scope < 0 || scope >= RG_TUNE_SCOPES) return RG_ERR_INVALID_ARG;
     const rg_trace_tune t = g_tune[scope];
-    if (width == 2) return launch_w<2>(any, mode, a, st, t);
-    if (width == 4) return launch_w<4>(any, mode, a, st, t);
-    if (width == 8) return launch_w<8>(any, mode, a, st, t);
+    if (width == 2) return rg_debug_done(launch_w<2>(any, mode, a, st, t), st);
+    if (width == 4) return rg_debug_done(launch_w<4>(any, mode, a, st, t), st);
+    if (width == 8) return rg_debug_done(launch_w<8>(any, mode, a, st, t), st);
     return RG_ERR_INVALID_ARG;
 }
 
