@@ -77,7 +77,8 @@ def recorded_traffic(args):
 # two-level frames (2% over clustering, 4% over width 4).  The batched
 # workload starts from its entry and can be autotuned.
 SHAPES = {"incoherent": (4, 1, "treelet"), "two_level": (8, 1, "treelet"), "batched": (4, 1, "lbvh"),
-          "serving": (4, 1, "treelet"), "dynamic": (4, 1, "treelet"), "post": (8, 1, "treelet")}
+          "serving": (4, 1, "treelet"), "dynamic": (4, 1, "treelet"), "post": (8, 1, "treelet"),
+          "build": (4, 1, "treelet")}
 
 
 def log(*a):
@@ -471,6 +472,38 @@ def bench_post(args, torch, rg, sg):
     return out, scene
 
 
+def bench_build(args, torch, rg, sg):
+    """Bottom-level builds of the incoherent scene's 16 displaced tori
+    (10,035,200 triangles) with each builder, device-resident vertices."""
+    scene = sg.config_incoherent(segments=args.segments)
+    dev = [(torch.from_numpy(m.verts).cuda(), torch.from_numpy(m.idx.view(np.int32)).cuda()) for m in scene.blas]
+    n_tris = sum(m.n_tris for m in scene.blas)
+    res = {}
+    for builder in ("lbvh", "ploc", "treelet"):
+        for _ in range(args.warmup):
+            for v, i in dev:
+                rg.build_blas(v, i, None, args.width, args.leaf, builder=builder)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for v, i in dev:
+                rg.build_blas(v, i, None, args.width, args.leaf, builder=builder)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        res[builder] = {"ms_per_scene": ms, "mtris_s": n_tris / (ms * 1e-3) / 1e6}
+    width, leaf, builder = SHAPES["incoherent"]
+    out = {
+        "metric": "Mtris/s bottom-level build", "value": res[builder]["mtris_s"], "unit": "Mtris/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": res[builder]["ms_per_scene"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"bottom levels of 16 displaced tori {args.segments}x{args.segments} "
+                               f"({n_tris} triangles), one synchronous build per mesh, value for the "
+                               f"{builder} builder", "bvh_width": args.width, "leaf_max": args.leaf},
+        "builders": res, "roofline": None,
+    }
+    return out, scene
+
+
 def bench_batched(args, torch, rg, sg):
     """Plain per-frame dispatch (one rg_render per frame, one stream) versus one
     batch (every pass one launch over all frames), same frames, same images."""
@@ -698,7 +731,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["incoherent", "two_level", "batched", "serving", "dynamic", "post"],
+    ap.add_argument("--workload", choices=["incoherent", "two_level", "batched", "serving", "dynamic", "post",
+                                           "build"],
                     default="incoherent")
     ap.add_argument("--scenes", type=int, default=256, help="frames of the batched workload")
     ap.add_argument("--autotune", action="store_true", help="batched: tune width, leaf size and launch "
@@ -740,7 +774,7 @@ def main():
     import scenegen as sg
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     scope = {"incoherent": "trace", "two_level": "frame", "batched": "frame", "serving": "engine",
-             "dynamic": "trace", "post": "frame"}[args.workload]
+             "dynamic": "trace", "post": "frame", "build": "trace"}[args.workload]
     rg.trace_tuning(args.refill, args.waves_per_cu, args.lds_depth, args.leaf_batch, args.inst_batch, scope=scope)
     if args.workload == "incoherent":
         out, scene = bench_incoherent(args, torch, rg, sg)
@@ -751,6 +785,8 @@ def main():
         out, scene = bench_dynamic(args, torch, rg, sg)
     elif args.workload == "post":
         out, scene = bench_post(args, torch, rg, sg)
+    elif args.workload == "build":
+        out, scene = bench_build(args, torch, rg, sg)
     elif args.workload == "two_level":
         out, scene = bench_two_level(args, torch, rg, sg)
         if not args.no_cpu_baseline:
