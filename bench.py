@@ -78,7 +78,7 @@ def recorded_traffic(args):
 # workload starts from its entry and can be autotuned.
 SHAPES = {"incoherent": (4, 1, "treelet"), "two_level": (8, 1, "treelet"), "batched": (4, 1, "lbvh"),
           "serving": (4, 1, "treelet"), "dynamic": (4, 1, "treelet"), "post": (8, 1, "treelet"),
-          "build": (4, 1, "treelet")}
+          "build": (4, 1, "treelet"), "options": (4, 1, "treelet")}
 
 
 def log(*a):
@@ -472,6 +472,66 @@ def bench_post(args, torch, rg, sg):
     return out, scene
 
 
+def bench_options(args, torch, rg, sg):
+    """The incoherent workload traced with the any-hit accept / ignore options
+    on: back faces culled, every second instance flagged to another
+    visibility mask than the rays', half of the meshes alpha-tested (level-3
+    opacity masks with 3 in 4 micro-triangles opaque); the same rays traced
+    plainly on the same hierarchies for comparison."""
+    scene = sg.config_incoherent(segments=args.segments)
+    W, H = scene.width, scene.height
+    N = W * H
+    n_inst = scene.xform.shape[0]
+    flags = np.where(np.arange(n_inst) % 2 == 0, 0x01, 0x03).astype(np.uint32)   # rays carry mask 0x02
+    tl = rg.upload_scene(scene, width=args.width, leaf_max=args.leaf, builder=args.builder)
+    plain = rg.build_tlas(tl.blas, scene.xform, scene.blas_id, scene.inst_mat, args.width, builder=args.builder)
+    rng = np.random.default_rng(7)
+    for b in tl.blas[::2]:
+        m = rng.integers(0, 2 ** 63, (b.n_tris, 2), dtype=np.int64)
+        masks = torch.from_numpy((m[:, 0] | m[:, 1]).astype(np.int64)).cuda()   # about 3 in 4 bits set
+        rg.set_alpha(b, masks, 3)
+    opt = rg.build_tlas(tl.blas, scene.xform, scene.blas_id, scene.inst_mat, args.width, builder=args.builder,
+                        inst_flags=flags)
+    cam = rg.camera_rays(scene.camera, W, H)
+    hits = rg.trace_closest(plain, cam)
+    ao, src, cnt = rg.ao_rays(plain, cam, hits, seed=scene.seed, tmax=5.0)
+    n_ao = int(cnt.item())
+    ao = ao[:, :n_ao]
+    out_hits = rg.alloc_hits(n_ao)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    ms_plain = timed(lambda: rg.trace_closest(plain, ao, out=out_hits))
+    # `plain` was built before the masks were attached: its records carry no
+    # flags and its traversal is the plain variant; `opt` takes the option one
+    ms_masks = timed(lambda: rg.trace_closest(opt, ao, out=out_hits, mask=0x02, cull=rg.RAY_CULL_BACK))
+    hit_frac = float((out_hits["inst"] != -1).float().mean().item())
+    counts = rg.trace_counts(plain, ao).cpu().numpy()
+    out = {
+        "metric": "Mrays/s closest-hit (primary+incoherent)", "value": n_ao / (ms_masks * 1e-3) / 1e6,
+        "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_masks,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "incoherent AO rays (10,315,840) with ray options: back faces culled, rays of mask "
+                               "0x02 (half of the 1,024 instances carry mask 0x01 only), 8 of the 16 meshes "
+                               "alpha-tested at level 3 (3 in 4 micro-triangles opaque)",
+                   "ao_rays": n_ao, "bvh_width": args.width, "leaf_max": args.leaf, "builder": args.builder},
+        "plain_mrays_s": n_ao / (ms_plain * 1e-3) / 1e6, "plain_ms": ms_plain,
+        "hit_fraction_with_options": hit_frac, "mean_nodes_plain": float(counts[:, 0].mean()),
+        "roofline": None,
+    }
+    return out, scene
+
+
 def bench_build(args, torch, rg, sg):
     """Bottom-level builds of the incoherent scene's 16 displaced tori
     (10,035,200 triangles) with each builder, device-resident vertices."""
@@ -732,7 +792,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", choices=["incoherent", "two_level", "batched", "serving", "dynamic", "post",
-                                           "build"],
+                                           "build", "options"],
                     default="incoherent")
     ap.add_argument("--scenes", type=int, default=256, help="frames of the batched workload")
     ap.add_argument("--autotune", action="store_true", help="batched: tune width, leaf size and launch "
@@ -774,7 +834,7 @@ def main():
     import scenegen as sg
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     scope = {"incoherent": "trace", "two_level": "frame", "batched": "frame", "serving": "engine",
-             "dynamic": "trace", "post": "frame", "build": "trace"}[args.workload]
+             "dynamic": "trace", "post": "frame", "build": "trace", "options": "trace"}[args.workload]
     rg.trace_tuning(args.refill, args.waves_per_cu, args.lds_depth, args.leaf_batch, args.inst_batch, scope=scope)
     if args.workload == "incoherent":
         out, scene = bench_incoherent(args, torch, rg, sg)
@@ -787,6 +847,8 @@ def main():
         out, scene = bench_post(args, torch, rg, sg)
     elif args.workload == "build":
         out, scene = bench_build(args, torch, rg, sg)
+    elif args.workload == "options":
+        out, scene = bench_options(args, torch, rg, sg)
     elif args.workload == "two_level":
         out, scene = bench_two_level(args, torch, rg, sg)
         if not args.no_cpu_baseline:
