@@ -481,15 +481,12 @@ def bench_options(args, torch, rg, sg):
     scene = sg.config_incoherent(segments=args.segments)
     W, H = scene.width, scene.height
     N = W * H
-    n_inst = scene.xform.shape[0]
-    flags = np.where(np.arange(n_inst) % 2 == 0, 0x01, 0x03).astype(np.uint32)   # rays carry mask 0x02
+    flags, alpha = sg.option_inputs(scene)        # rays carry mask 0x02
     tl = rg.upload_scene(scene, width=args.width, leaf_max=args.leaf, builder=args.builder)
     plain = rg.build_tlas(tl.blas, scene.xform, scene.blas_id, scene.inst_mat, args.width, builder=args.builder)
-    rng = np.random.default_rng(7)
-    for b in tl.blas[::2]:
-        m = rng.integers(0, 2 ** 63, (b.n_tris, 2), dtype=np.int64)
-        masks = torch.from_numpy((m[:, 0] | m[:, 1]).astype(np.int64)).cuda()   # about 3 in 4 bits set
-        rg.set_alpha(b, masks, 3)
+    for b, a in zip(tl.blas, alpha):
+        if a is not None:
+            rg.set_alpha(b, torch.from_numpy(a[0].view(np.int64)).cuda(), a[1])
     opt = rg.build_tlas(tl.blas, scene.xform, scene.blas_id, scene.inst_mat, args.width, builder=args.builder,
                         inst_flags=flags)
     cam = rg.camera_rays(scene.camera, W, H)

@@ -559,6 +559,31 @@ def sample_pixels(width: int, height: int, n: int, seed: int) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
+# ray-option inputs: instance visibility flags and opacity masks
+# ----------------------------------------------------------------------------
+def option_inputs(scene: Scene, seed: int = 7, level: int = 3):
+    """Instance flags and opacity masks for tracing `scene` with the ray
+    options on: even-numbered instances carry visibility mask 0x01 only, the
+    others 0x03 (so rays of mask 0x02 see half of them); every second mesh is
+    alpha-tested at `level`, each of its triangles with a 64-bit mask whose
+    bits are set with probability 3/4 (the OR of two uniform words).
+
+    Returns (flags uint32[n_inst], alpha), alpha[b] = (uint64 mask per
+    triangle, level) for the tested meshes and None for the others."""
+    n_inst = scene.xform.shape[0]
+    flags = np.where(np.arange(n_inst) % 2 == 0, 0x01, 0x03).astype(np.uint32)
+    rng = np.random.default_rng(seed)
+    alpha = []
+    for b, m in enumerate(scene.blas):
+        if b % 2:
+            alpha.append(None)
+            continue
+        w = rng.integers(0, 2 ** 64, (m.idx.shape[0], 2), dtype=np.uint64)
+        alpha.append((w[:, 0] | w[:, 1], level))
+    return flags, alpha
+
+
+# ----------------------------------------------------------------------------
 # post-process inputs: a traced frame and its primary-hit materials
 # ----------------------------------------------------------------------------
 def roughness_table(n_mats: int, seed: int) -> np.ndarray:
