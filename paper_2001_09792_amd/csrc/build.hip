@@ -638,6 +638,47 @@ __global__ void k_ploc_relabel(int64_t n, int32_t *__restrict__ left, int32_t *_
 constexpr int kTreelet = 7;
 constexpr int kTreeletMaxRounds = 8;
 
+// The 127 non-empty subsets of 7 leaves ordered by size, then by value, and
+// where each size starts.  Subsets within the low m bits precede the others
+// of their size, so for a treelet of m leaves the subsets of size k are the
+// first C(m, k) entries of block k.
+struct TreeletSubsets {
+    uint8_t s[(1 << kTreelet) - 1];
+    uint8_t off[kTreelet + 2];
+    uint8_t binom[kTreelet + 1][kTreelet + 1];
+};
+
+constexpr int popc_const(int v) { return v ? (v & 1) + popc_const(v >> 1) : 0; }
+
+constexpr TreeletSubsets make_treelet_subsets() {
+    TreeletSubsets t{};
+    int n = 0;
+    for (int k = 1; k <= kTreelet; ++k) {
+        t.off[k] = (uint8_t)n;
+        for (int S = 1; S < (1 << kTreelet); ++S)
+            if (popc_const(S) == k) t.s[n++] = (uint8_t)S;
+    }
+    t.off[kTreelet + 1] = (uint8_t)n;
+    for (int m = 0; m <= kTreelet; ++m)
+        for (int k = 0; k <= kTreelet; ++k) {
+            int c = 0;
+            for (int S = 0; S < (1 << m); ++S) c += popc_const(S) == k;
+            t.binom[m][k] = (uint8_t)c;
+        }
+    return t;
+}
+
+__constant__ TreeletSubsets kSubsets = make_treelet_subsets();
+
+// The j-th subset of `mask` in increasing order: the bits of j placed on the
+// set bits of mask, lowest first.
+__device__ inline uint32_t deposit(uint32_t j, uint32_t mask) {
+    uint32_t r = 0u;
+    for (uint32_t b = mask; b; b &= b - 1u, j >>= 1)
+        if (j & 1u) r |= b & (0u - b);
+    return r;
+}
+
 __device__ inline float area32(const float *lo, const float *hi) {
 #pragma clang fp contract(off)
     const float dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
@@ -746,31 +787,51 @@ __global__ void __launch_bounds__(64) k_treelet(const int32_t *__restrict__ orde
     __shared__ float area[1 << kTreelet], cost[1 << kTreelet];
     __shared__ uint8_t split[1 << kTreelet];
     __shared__ int32_t leaves[kTreelet], opened[kTreelet];
+    __shared__ float lbox[kTreelet][6], larea[kTreelet];
     __shared__ int n_leaves, n_opened;
     const int lane = threadIdx.x;
     const int32_t node = order[blockIdx.x];
     if (left[node] < 0 && right[node] < 0) return;  // two leaves: one topology, nothing to change
     if (lane == 0) {
+        // Each treelet leaf's box and area are read once, when it joins, and
+        // kept in LDS: a growth step then waits on two loads (the opened
+        // node's children, then both their boxes) whatever the leaf count.
+        auto join = [&](int k0, int32_t c0, int k1, int32_t c1) {
+            const float *p0 = c0 < 0 ? leaf_box + 6 * (int64_t)(-c0 - 1) : int_box + 6 * (int64_t)c0;
+            const float *p1 = c1 < 0 ? leaf_box + 6 * (int64_t)(-c1 - 1) : int_box + 6 * (int64_t)c1;
+            float b0[6], b1[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                b0[q] = p0[q];
+                b1[q] = p1[q];
+            }
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                lbox[k0][q] = b0[q];
+                lbox[k1][q] = b1[q];
+            }
+            leaves[k0] = c0;
+            leaves[k1] = c1;
+            larea[k0] = area32(b0, b0 + 3);
+            larea[k1] = area32(b1, b1 + 3);
+        };
         int m = 2, r = 0;
-        leaves[0] = left[node];
-        leaves[1] = right[node];
+        join(0, left[node], 1, right[node]);
         while (m < kTreelet) {
             int bk = -1;
             float ba = -INFINITY;
             for (int k = 0; k < m; ++k) {
-                const int32_t c = leaves[k];
-                if (c < 0) continue;
-                const float a = area32(int_box + 6 * (int64_t)c, int_box + 6 * (int64_t)c + 3);
-                if (a > ba) {
-                    ba = a;
+                if (leaves[k] < 0) continue;   // a primitive cannot be opened
+                if (larea[k] > ba) {
+                    ba = larea[k];
                     bk = k;
                 }
             }
             if (bk < 0) break;
             const int32_t c = leaves[bk];
             opened[r++] = c;
-            leaves[bk] = left[c];
-            leaves[m++] = right[c];
+            join(bk, left[c], m, right[c]);
+            ++m;
         }
         for (int k = 1; k < r; ++k)  // ascending: the order the indices are handed out in
             for (int q = k; q > 0 && opened[q - 1] > opened[q]; --q) {
@@ -788,8 +849,7 @@ __global__ void __launch_bounds__(64) k_treelet(const int32_t *__restrict__ orde
         float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
         for (int k = 0; k < m; ++k) {
             if (!((S >> k) & 1u)) continue;
-            const int32_t c = leaves[k];
-            const float *b = c < 0 ? leaf_box + 6 * (int64_t)(-c - 1) : int_box + 6 * (int64_t)c;
+            const float *b = lbox[k];
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 lo[q] = fminf(lo[q], b[q]);
@@ -806,34 +866,53 @@ __global__ void __launch_bounds__(64) k_treelet(const int32_t *__restrict__ orde
         split[S] = 0;
     }
     __syncthreads();
+    // Subsets of one size at a time.  A subset S splits into P (holding its
+    // lowest leaf) and S \ P; P = low | Q for the proper subsets Q of the rest,
+    // Q the j-th in increasing order.  The first cheapest split in that order
+    // is kept.  The subsets of a size share the wave: g lanes per subset,
+    // each taking every g-th j, then the least (cost, j) over the group.
     for (int k = 2; k <= m; ++k) {
-        for (uint32_t S = (uint32_t)lane + 1u; S <= full; S += 64u) {
-            if (__popc(S) != k) continue;
-            const uint32_t low = S & (0u - S), rest = S ^ low;
-            float best = INFINITY;
-            uint32_t bp = 0u, Q = 0u;
-            while (true) {
-                const uint32_t P = low | Q;
-                if (P != S) {
-                    const float v = cost[P] + cost[S ^ P];
-                    if (v < best) {
-                        best = v;
-                        bp = P;
-                    }
+        const int nk = kSubsets.binom[m][k];
+        const uint32_t np = (1u << (k - 1)) - 1u;   // splits of a k-subset
+        int g = 1;
+        while (2 * g * nk <= 64 && (uint32_t)g < np) g *= 2;
+        const int si = lane / g, part = lane % g;
+        uint32_t S = 0u, low = 0u, rest = 0u, bj = 0xFFFFFFFFu;
+        float best = INFINITY;
+        if (si < nk) {
+            S = kSubsets.s[kSubsets.off[k] + si];
+            low = S & (0u - S);
+            rest = S ^ low;
+            for (uint32_t j = (uint32_t)part; j < np; j += (uint32_t)g) {
+                const uint32_t P = low | deposit(j, rest);
+                const float v = cost[P] + cost[S ^ P];
+                if (v < best) {
+                    best = v;
+                    bj = j;
                 }
-                if (Q == rest) break;
-                Q = (Q - rest) & rest;
             }
+        }
+        for (int d = 1; d < g; d <<= 1) {
+            const float ov = __shfl_xor(best, d);
+            const uint32_t oj = __shfl_xor(bj, d);
+            if (ov < best || (ov == best && oj < bj)) {
+                best = ov;
+                bj = oj;
+            }
+        }
+        if (si < nk && part == 0) {
             cost[S] = area[S] + best;
-            split[S] = (uint8_t)bp;
+            split[S] = (uint8_t)(bj == 0xFFFFFFFFu ? 0u : (low | deposit(bj, rest)));
         }
         __syncthreads();
     }
     if (lane != 0) return;
-    // rebuild: entries (subset, parent, side) popped in pre-order
-    uint32_t st_set[2 * kTreelet];
-    int32_t st_parent[2 * kTreelet];
-    int st_side[2 * kTreelet];
+    // rebuild: entries (subset, parent, side) popped in pre-order; the stack
+    // lives in LDS, which keeps the kernel's registers low enough for more
+    // waves per SIMD (the walk is one lane's)
+    __shared__ uint32_t st_set[2 * kTreelet];
+    __shared__ int32_t st_parent[2 * kTreelet];
+    __shared__ int32_t st_side[2 * kTreelet];
     int sp = 0, next = 0;
     st_set[sp] = full ^ split[full]; st_parent[sp] = node; st_side[sp] = 1; ++sp;
     st_set[sp] = split[full]; st_parent[sp] = node; st_side[sp] = 0; ++sp;
