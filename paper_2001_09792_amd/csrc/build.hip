@@ -15,6 +15,7 @@
 //   6. top-down collapse into W-wide nodes (repeatedly opening the inner
 //      child with the largest surface area), leaves of <= leaf_max prims,
 // followed by reordering the primitives into leaf order.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
@@ -313,78 +314,144 @@ __device__ inline float surface_area(const float *b) {
     return 2.0f * (dx * dy + dy * dz + dz * dx);
 }
 
+constexpr int kCollapseRing = 16;   // per-level bookkeeping slots on the device
+constexpr int kCollapseBatch = 4;   // levels launched between host reads (< kCollapseRing - 2)
+
+// One thread per node of the level (queue items: node index, binary node it
+// stands for).  Its children are opened largest-area first up to W; each
+// candidate's area is computed once, when it joins.  Children that stay
+// inner nodes join the next level's queue: one counter add per wave, and a
+// child's node index is the next level's first index plus its queue slot.
 template <int W>
 __global__ void k_collapse(const int32_t *__restrict__ left, const int32_t *__restrict__ right,
                            const int32_t *__restrict__ first, const int32_t *__restrict__ last,
                            const float *__restrict__ int_box, const float *__restrict__ leaf_box,
-                           int leaf_max, const uint2 *__restrict__ q_in, const uint32_t *__restrict__ q_in_count,
-                           uint2 *__restrict__ q_out, uint32_t *q_out_count, uint32_t *node_count,
-                           RgNode<W> *__restrict__ nodes, uint32_t *__restrict__ parents, uint32_t cap,
-                           uint32_t *err) {
-    uint32_t cnt = *q_in_count;
+                           int leaf_max, const uint2 *__restrict__ q_in, uint2 *__restrict__ q_out,
+                           uint32_t *ring, int level, RgNode<W> *__restrict__ nodes,
+                           uint32_t *__restrict__ parents, uint32_t cap) {
+    // ring: [0, R) node count of level l at l % R, [R, 2R) first node index of
+    // level l at R + l % R, [2R] error flags.  A level's kernel sets up the
+    // next level's first index and clears the count two levels ahead, so
+    // levels can be launched back to back with no host step between them.
+    uint32_t *count_in = ring + level % kCollapseRing, *q_out_count = ring + (level + 1) % kCollapseRing;
+    uint32_t cnt = *count_in;
     if (cnt > cap) cnt = cap;
-    for (uint32_t qi = blockIdx.x * blockDim.x + threadIdx.x; qi < cnt; qi += gridDim.x * blockDim.x) {
-        uint2 item = q_in[qi];
+    const uint32_t next_base = ring[kCollapseRing + level % kCollapseRing] + cnt;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ring[kCollapseRing + (level + 1) % kCollapseRing] = next_base;
+        ring[(level + 2) % kCollapseRing] = 0u;
+    }
+    uint32_t *err = ring + 2 * kCollapseRing;
+    const int lane = threadIdx.x & 63;
+    // the loop bound is the same for every lane of a block, so whole waves
+    // take part in the scan below
+    for (uint32_t base = blockIdx.x * blockDim.x; base < cnt; base += gridDim.x * blockDim.x) {
+        const uint32_t qi = base + threadIdx.x;
+        const bool active = qi < cnt;
         int32_t C[W];
+        float A[W];
 #pragma unroll
-        for (int k = 0; k < W; ++k) C[k] = 0;
-        C[0] = left[item.y];
-        C[1] = right[item.y];
-        int m = 2;
-        while (m < W) {
-            int best = -1;
-            float bsa = -1.0f;
-            for (int k = 0; k < m; ++k) {
-                if (C[k] >= 0) {
-                    float sa = surface_area(int_box + 6 * (int64_t)C[k]);
-                    if (sa > bsa) {
-                        bsa = sa;
+        for (int k = 0; k < W; ++k) {
+            C[k] = -1;
+            A[k] = -1.0f;
+        }
+        uint2 item = make_uint2(0u, 0u);
+        int m = 0;
+        if (active) {
+            item = q_in[qi];
+            C[0] = left[item.y];
+            C[1] = right[item.y];
+            m = 2;
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+                if (C[k] >= 0) A[k] = surface_area(int_box + 6 * (int64_t)C[k]);
+            while (m < W) {
+                int best = -1;
+                float bsa = -1.0f;
+#pragma unroll
+                for (int k = 0; k < W; ++k)
+                    if (k < m && C[k] >= 0 && A[k] > bsa) {
+                        bsa = A[k];
                         best = k;
                     }
+                if (best < 0) break;
+                int32_t c = 0;
+#pragma unroll
+                for (int k = 0; k < W; ++k)
+                    if (k == best) c = C[k];
+                const int32_t l = left[c], r = right[c];
+                const float al = l >= 0 ? surface_area(int_box + 6 * (int64_t)l) : -1.0f;
+                const float ar = r >= 0 ? surface_area(int_box + 6 * (int64_t)r) : -1.0f;
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    if (k == best) {
+                        C[k] = l;
+                        A[k] = al;
+                    }
+                    if (k == m) {
+                        C[k] = r;
+                        A[k] = ar;
+                    }
                 }
+                ++m;
             }
-            if (best < 0) break;
-            int32_t c = C[best];
-            C[best] = left[c];
-            C[m++] = right[c];
         }
+        // which children stay inner nodes
+        uint32_t link[W];
+        uint32_t inner = 0u;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            link[k] = RG_EMPTY;
+            if (k >= m) continue;
+            const int32_t c = C[k];
+            if (c < 0) {
+                link[k] = rg_leaf((uint32_t)(-c - 1), 1u);
+            } else {
+                const int32_t f = first[c], size = last[c] - f + 1;
+                if (size <= leaf_max) link[k] = rg_leaf((uint32_t)f, (uint32_t)size);
+                else inner |= 1u << k;
+            }
+        }
+        // queue slots: an exclusive scan of the inner-child counts over the wave
+        const uint32_t nc = __popc(inner);
+        uint32_t incl = nc;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += y;
+        }
+        const uint32_t total = __shfl(incl, 63, 64);
+        uint32_t wbase = 0u;
+        if (lane == 63 && total) wbase = atomicAdd(q_out_count, total);
+        wbase = __shfl(wbase, 63, 64);
+        uint32_t slot = wbase + incl - nc;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            if (!((inner >> k) & 1u)) continue;
+            const uint32_t nn = next_base + slot;
+            if (nn < cap && slot < cap) {  // a BVH2 has n-1 inner nodes: never exceeded
+                q_out[slot] = make_uint2(nn, (uint32_t)C[k]);
+                if (parents) parents[nn] = (item.x << 3) | (uint32_t)k;
+                link[k] = nn;
+            } else {
+                atomicOr(err, 4u);
+            }
+            ++slot;
+        }
+        if (!active) continue;
         RgNode<W> *nd = nodes + item.x;
+#pragma unroll
         for (int k = 0; k < W; ++k) {
             if (k >= m) {
                 nd->lo_x[k] = INFINITY; nd->lo_y[k] = INFINITY; nd->lo_z[k] = INFINITY;
                 nd->hi_x[k] = -INFINITY; nd->hi_y[k] = -INFINITY; nd->hi_z[k] = -INFINITY;
-                nd->child[k] = RG_EMPTY;
-                nd->pad[k] = 0u;
-                continue;
-            }
-            int32_t c = C[k];
-            const float *b;
-            uint32_t link;
-            if (c < 0) {
-                int32_t leaf = -c - 1;
-                b = leaf_box + 6 * (int64_t)leaf;
-                link = rg_leaf((uint32_t)leaf, 1u);
             } else {
-                b = int_box + 6 * (int64_t)c;
-                int32_t size = last[c] - first[c] + 1;
-                if (size <= leaf_max) {
-                    link = rg_leaf((uint32_t)first[c], (uint32_t)size);
-                } else {
-                    uint32_t nn = atomicAdd(node_count, 1u);
-                    uint32_t slot = atomicAdd(q_out_count, 1u);
-                    if (nn < cap && slot < cap) {  // a BVH2 has n-1 inner nodes: never exceeded
-                        q_out[slot] = make_uint2(nn, (uint32_t)c);
-                        if (parents) parents[nn] = (item.x << 3) | (uint32_t)k;
-                        link = nn;
-                    } else {
-                        atomicOr(err, 4u);
-                        link = RG_EMPTY;
-                    }
-                }
+                const int32_t c = C[k];
+                const float *b = c < 0 ? leaf_box + 6 * (int64_t)(-c - 1) : int_box + 6 * (int64_t)c;
+                nd->lo_x[k] = b[0]; nd->lo_y[k] = b[1]; nd->lo_z[k] = b[2];
+                nd->hi_x[k] = b[3]; nd->hi_y[k] = b[4]; nd->hi_z[k] = b[5];
             }
-            nd->lo_x[k] = b[0]; nd->lo_y[k] = b[1]; nd->lo_z[k] = b[2];
-            nd->hi_x[k] = b[3]; nd->hi_y[k] = b[4]; nd->hi_z[k] = b[5];
-            nd->child[k] = link;
+            nd->child[k] = link[k];
             nd->pad[k] = 0u;
         }
     }
@@ -408,10 +475,10 @@ __global__ void k_single_root(const float *__restrict__ leaf_box, RgNode<W> *nod
     nd->pad[k] = 0u;
 }
 
-__global__ void k_collapse_init(uint2 *q, uint32_t *q_count, uint32_t *node_count, uint32_t *parents) {
+__global__ void k_collapse_init(uint2 *q, uint32_t *ring, uint32_t *parents) {
     q[0] = make_uint2(0u, 0u);
-    *q_count = 1u;
-    *node_count = 1u;
+    for (int k = 0; k <= 2 * kCollapseRing; ++k) ring[k] = 0u;
+    ring[0] = 1u;  // level 0: the root, node 0
     if (parents) parents[0] = RG_MISS;  // the root
 }
 
@@ -1360,7 +1427,7 @@ bool carve(RgArena &a, int64_t n, int32_t builder, LbvhScratch &s) {
     s.ids2 = a.take<uint32_t>(n);
     s.hist = a.take<uint32_t>(256 * nb);
     s.bounds = a.take<uint32_t>(8);
-    s.qcount = a.take<uint32_t>(8);
+    s.qcount = a.take<uint32_t>(2 * kCollapseRing + 8);
     s.flags = a.take<uint32_t>(8);
     s.left = a.take<int32_t>(ni);
     s.right = a.take<int32_t>(ni);
@@ -1530,44 +1597,51 @@ rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes_v,
         *n_nodes = 1;
         return RG_OK;
     }
-    uint32_t *qc = s.qcount;  // [0], [1] queue counts, [2] node count, [3] error flags
+    uint32_t *ring = s.qcount;
     const uint32_t cap = (uint32_t)(n - 1);
-    k_fill_u32<<<1, 64, 0, st>>>(qc, 0u, 4);
-    k_collapse_init<<<1, 1, 0, st>>>(s.q0, qc, qc + 2, parents);
+    k_collapse_init<<<1, 1, 0, st>>>(s.q0, ring, parents);
     RG_LAUNCH_CHECK();
-    uint2 *qin = s.q0, *qout = s.q1;
-    uint32_t *cin = qc, *cout = qc + 1;
-    uint32_t count = 1, host_count = 0;
-    int32_t d = 0;
-    while (count > 0) {
-        ++d;
-        k_fill_u32<<<1, 64, 0, st>>>(cout, 0u, 1);
-        unsigned blocks = rg_blocks(count, kThreads);
-        if (blocks > 4096) blocks = 4096;
-        k_collapse<W><<<blocks, kThreads, 0, st>>>(s.left, s.right, s.first, s.last, s.int_box, s.leaf_box,
-                                                    leaf_max, qin, cin, qout, cout, qc + 2, nodes, parents, cap,
-                                                    qc + 3);
+    uint2 *q[2] = {s.q0, s.q1};
+    // levels go in batches; the host learns their sizes after each batch.  A
+    // level's size is at most W times the one before, which bounds the grids
+    // of the levels launched before their sizes are known.  Levels launched
+    // after the last one find an empty queue and return.
+    uint32_t known = 1;  // size of level `d`, the first of the next batch
+    int32_t d = 0, levels_n = 0;
+    while (levels_n == 0) {
+        uint64_t bound = known;
+        for (int j = 0; j < kCollapseBatch; ++j) {
+            unsigned blocks = rg_blocks((int64_t)(bound ? bound : 1), kThreads);
+            if (blocks > 1024) blocks = 1024;
+            const int level = d + j;
+            k_collapse<W><<<blocks, kThreads, 0, st>>>(s.left, s.right, s.first, s.last, s.int_box, s.leaf_box,
+                                                        leaf_max, q[level & 1], q[(level + 1) & 1], ring, level,
+                                                        nodes, parents, cap);
+            bound = std::min<uint64_t>((uint64_t)cap, bound * (uint64_t)W);
+        }
         RG_LAUNCH_CHECK();
-        uint32_t hq[4];
-        RG_HIP(hipMemcpyAsync(hq, qc, 16, hipMemcpyDeviceToHost, st));
+        uint32_t hr[2 * kCollapseRing + 1];
+        RG_HIP(hipMemcpyAsync(hr, ring, sizeof(hr), hipMemcpyDeviceToHost, st));
         RG_HIP(hipStreamSynchronize(st));
-        host_count = hq[cout - qc];
-        if (hq[3] != 0u || d > 4096) return RG_ERR_HIP;  // inconsistent hierarchy: never expected
-        if (host_count > 0u) starts.push_back(starts.back() + host_count);
-        count = host_count;
-        uint2 *tq = qin;
-        qin = qout;
-        qout = tq;
-        uint32_t *tc = cin;
-        cin = cout;
-        cout = tc;
+        if (hr[2 * kCollapseRing] != 0u) return RG_ERR_HIP;  // inconsistent hierarchy: never expected
+        for (int j = 0; j < kCollapseBatch; ++j) {
+            const uint32_t c = hr[(d + j + 1) % kCollapseRing];  // nodes of level d + j + 1
+            if (c == 0u) {
+                levels_n = d + j + 1;
+                break;
+            }
+            starts.push_back(starts.back() + c);
+            known = c;
+        }
+        d += kCollapseBatch;
+        if (d > 4096) return RG_ERR_HIP;  // never expected
     }
-    uint32_t nn = 0;
-    RG_HIP(hipMemcpyAsync(&nn, qc + 2, 4, hipMemcpyDeviceToHost, st));
+    d = levels_n;
+    const uint32_t nn = starts.back();  // levels are numbered contiguously
     if (levels && starts.size() <= (size_t)RG_LEVELS_CAP + 1)
         RG_HIP(hipMemcpyAsync(levels, starts.data(), 4 * starts.size(), hipMemcpyHostToDevice, st));
     RG_HIP(hipStreamSynchronize(st));
-    if (starts.size() != (size_t)d + 1 || starts.back() != nn) return RG_ERR_HIP;  // never expected
+    if (starts.size() != (size_t)d + 1) return RG_ERR_HIP;  // never expected
     *depth = d;
     *n_nodes = nn;
     return RG_OK;
