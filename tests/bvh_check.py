@@ -54,6 +54,35 @@ def walk(lo, hi, child, n_prims: int, leaf_boxes, max_leaf: int):
     return max_depth, seen_prim
 
 
+LEVELS_CAP = 255   # RG_LEVELS_CAP
+
+
+def _check_levels_and_parents(buf: np.ndarray, desc, child: np.ndarray):
+    """Nodes are numbered level by level: the level table's entry l is the
+    first node at depth l (root 0) and entry `depth` the node count; each
+    node's parent link names the node and child slot that point to it."""
+    n_nodes, depth = desc.n_nodes, desc.depth
+    parents = buf[desc.parents_off: desc.parents_off + 4 * n_nodes].view(np.uint32)
+    assert parents[0] == EMPTY, "the root has no parent"
+    node_depth = np.full(n_nodes, -1, np.int64)
+    node_depth[0] = 0
+    for node in range(n_nodes):       # parents precede their children
+        assert node_depth[node] >= 0, f"node {node} numbered before its parent"
+        for k in range(child.shape[1]):
+            c = int(child[node, k])
+            if c == EMPTY or c & LEAF:
+                continue
+            assert c > node
+            node_depth[c] = node_depth[node] + 1
+            assert parents[c] == (node << 3) | k, f"parent link of node {c}"
+    assert node_depth.max() + 1 == depth
+    if depth <= LEVELS_CAP:
+        levels = buf[desc.levels_off: desc.levels_off + 4 * (depth + 1)].view(np.uint32).astype(np.int64)
+        assert levels[0] == 0 and levels[depth] == n_nodes
+        assert np.array_equal(np.searchsorted(levels, np.arange(n_nodes), side="right") - 1, node_depth), \
+            "level table"
+
+
 def check_blas(buf: np.ndarray, desc, refitted: bool = False) -> dict:
     W = desc.width
     lo, hi, child = _nodes(buf, desc.nodes_off, desc.n_nodes, W)
@@ -73,6 +102,7 @@ def check_blas(buf: np.ndarray, desc, refitted: bool = False) -> dict:
     assert np.array_equal(root[:3], v.reshape(-1, 3).min(axis=0))
     assert np.array_equal(root[3:], v.reshape(-1, 3).max(axis=0))
     assert buf[56:60].view(np.uint32)[0] == 0, "status of the last refit"
+    _check_levels_and_parents(buf, desc, child)
     if not refitted:
         assert np.array_equal(np.array(desc.lo, np.float32), root[:3])
         assert np.array_equal(np.array(desc.hi, np.float32), root[3:])

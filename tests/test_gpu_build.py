@@ -122,6 +122,28 @@ def test_wide_blas_invariants(width, leaf_max):
     assert int(info["header"][1]) == base + b.desc.tris_off
 
 
+@pytest.mark.parametrize("builder", ["lbvh", "ploc", "treelet"])
+@pytest.mark.parametrize("width", [2, 4])
+def test_level_table_across_depths(width, builder):
+    """The wide collapse launches its levels in batches, with per-level counts
+    and first indices on the device: hierarchies of every depth from one level
+    to well past the batch and slot counts keep level tables and parent links
+    that match their trees."""
+    import paper_2001_09792_amd as rg
+    sizes = [1, 2, 3, 4, 5, 7, 9, 13, 17, 33, 65, 129, 257, 513, 1025, 2049, 4097, 8193, 20000]
+    print(f"[levels] W={width} {builder}", flush=True)
+    depths = []
+    for n in sizes:
+        mesh = sg.random_soup(n, 500 + n)
+        v, i = _dev(mesh)
+        b = rg.build_blas(v, i, None, width, 1, builder=builder)
+        depths.append(bvh_check.check_blas(b.buf.cpu().numpy(), b.desc)["depth"])
+    # past the 16 device slots at width 2, past a batch of 4 levels at width 4
+    assert depths[0] == 1 and max(depths) > (16 if width == 2 else 4)
+    assert len(set(depths)) >= (10 if width == 2 else 6)
+    print(f"  depths {depths}", flush=True)
+
+
 def test_tlas_invariants():
     import paper_2001_09792_amd as rg
     sc = sg.config_two_level(width=64, height=36)
