@@ -166,19 +166,29 @@ __global__ void k_sort_hist(const uint64_t *__restrict__ keys, int64_t n, int sh
     ghist[(int64_t)t * nblocks + blockIdx.x] = h[t];
 }
 
-// In-place exclusive prefix sum of m entries with one workgroup.
+// Exclusive scan in place by one block.  Each thread takes kScanPer
+// consecutive elements per pass (their loads in flight together), scans them
+// serially, and the block scans the per-thread totals.
+constexpr int kScanPer = 4;
+
 __global__ void __launch_bounds__(kScanThreads) k_scan_excl(uint32_t *data, int64_t m) {
     __shared__ uint32_t wsum[kScanThreads / 64];
     __shared__ uint32_t carry;
-    int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     if (t == 0) carry = 0;
     __syncthreads();
-    for (int64_t base = 0; base < m; base += kScanThreads) {
-        uint32_t v = (base + t < m) ? data[base + t] : 0u;
-        uint32_t x = v;
+    for (int64_t base = 0; base < m; base += (int64_t)kScanThreads * kScanPer) {
+        const int64_t i0 = base + (int64_t)t * kScanPer;
+        uint32_t v[kScanPer];
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) v[k] = (i0 + k < m) ? data[i0 + k] : 0u;
+        uint32_t tot = 0u;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) tot += v[k];
+        uint32_t x = tot;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
-            uint32_t y = __shfl_up(x, o, 64);
+            const uint32_t y = __shfl_up(x, o, 64);
             if (lane >= o) x += y;
         }
         if (lane == 63) wsum[w] = x;
@@ -187,15 +197,19 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_excl(uint32_t *data, int6
             uint32_t s = lane < kScanThreads / 64 ? wsum[lane] : 0u;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
-                uint32_t y = __shfl_up(s, o, 64);
+                const uint32_t y = __shfl_up(s, o, 64);
                 if (lane >= o) s += y;
             }
             if (lane < kScanThreads / 64) wsum[lane] = s;  // inclusive wave totals
         }
         __syncthreads();
-        uint32_t before = (w > 0 ? wsum[w - 1] : 0u) + x - v;
-        uint32_t c = carry;
-        if (base + t < m) data[base + t] = c + before;
+        const uint32_t c = carry;
+        uint32_t run = c + (w > 0 ? wsum[w - 1] : 0u) + x - tot;
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            if (i0 + k < m) data[i0 + k] = run;
+            run += v[k];
+        }
         __syncthreads();
         if (t == kScanThreads - 1) carry = c + wsum[kScanThreads / 64 - 1];
         __syncthreads();
