@@ -64,3 +64,26 @@ def test_incoherent_config_small_segments():
     assert sc.n_inst == 1024 and len(sc.blas) == 16
     assert sc.blas[0].n_tris == 800
     assert sc.mode == 1
+
+
+def test_option_inputs():
+    """Instance flags alternate between mask 0x01 and 0x03, every second
+    mesh carries one 64-bit opacity mask per triangle with about 3 in 4
+    bits set, and the same seed gives the same masks."""
+    sc = sg.config_incoherent(segments=24)
+    flags, alpha = sg.option_inputs(sc)
+    assert flags.dtype == np.uint32 and flags.shape == (sc.xform.shape[0],)
+    assert np.array_equal(flags[0::2], np.full_like(flags[0::2], 0x01))
+    assert np.array_equal(flags[1::2], np.full_like(flags[1::2], 0x03))
+    assert len(alpha) == len(sc.blas)
+    bits = []
+    for b, (a, m) in enumerate(zip(alpha, sc.blas)):
+        if b % 2:
+            assert a is None
+            continue
+        mask, level = a
+        assert level == 3 and mask.dtype == np.uint64 and mask.shape == (m.n_tris,)
+        bits.append(np.unpackbits(mask.view(np.uint8)).mean())
+    assert abs(np.mean(bits) - 0.75) < 0.01
+    again = sg.option_inputs(sc)[1]
+    assert all((x is None and y is None) or np.array_equal(x[0], y[0]) for x, y in zip(alpha, again))
