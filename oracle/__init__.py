@@ -57,32 +57,54 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     with _lock:
-        if _lib is not None:
-            return _lib
-        if not os.path.exists(_LIB):
-            build()
-        lib = ctypes.CDLL(_LIB)
-        P = ctypes.c_void_p
-        i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
-        lib.or_scene_new.restype = P
-        lib.or_scene_new.argtypes = [i32, P, P, P, P, P, i64, P, P, P]
-        lib.or_scene_free.argtypes = [P]
-        lib.or_set_sphere_reject.argtypes = [P, i32]
-        lib.or_set_materials.argtypes = [P, P, i32]
-        lib.or_trace.restype = i64
-        lib.or_trace.argtypes = [P, P, i64, i32, i32, P, P, P, P, P, P, P, P, P, P, P, P, i32, P,
-                                 ctypes.c_uint32, ctypes.c_uint32]
-        lib.or_set_inst_flags.argtypes = [P, P]
-        lib.or_set_alpha.argtypes = [P, i32, P, i32]
-        lib.or_camera_rays.argtypes = [P, i32, i32, P, i64, P]
-        lib.or_ao_uniforms.argtypes = [u64, u64, P, P]
-        lib.or_ao_direction.argtypes = [P, ctypes.c_double, ctypes.c_double, P]
-        lib.or_ao_rays.argtypes = [P, P, i64, u64, i32, P, P, P]
-        lib.or_render.restype = i64
-        lib.or_render.argtypes = [P, P, P, i32, i32, i32, i32, u64, P, i64, i32, P, P, P]
-        lib.or_primary_materials.argtypes = [P, P, i32, i32, P, i64, i32, P, P]
-        _lib = lib
-        return lib
+        if _lib is None:
+            if not os.path.exists(_LIB):
+                build()
+            _lib = _bind(_LIB)
+        return _lib
+
+
+def build_variant(source: str, path: str):
+    """Compiles C source text with the oracle's own flags into `path` and
+    returns the loaded library.  For tests that plant a mistake in a copy of
+    the oracle and check that a pin catches it; the oracle itself is not
+    changed."""
+    src = path + ".c"
+    with open(src, "w") as fh:
+        fh.write(source)
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",
+                           "-shared", "-fPIC", "-pthread", src, "-o", path, "-lm"])
+    return _bind(path)
+
+
+def source() -> str:
+    with open(_SRC) as fh:
+        return fh.read()
+
+
+def _bind(path: str):
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    lib.or_scene_new.restype = P
+    lib.or_scene_new.argtypes = [i32, P, P, P, P, P, i64, P, P, P]
+    lib.or_scene_free.argtypes = [P]
+    lib.or_set_sphere_reject.argtypes = [P, i32]
+    lib.or_set_materials.argtypes = [P, P, i32]
+    lib.or_trace.restype = i64
+    lib.or_trace.argtypes = [P, P, i64, i32, i32, P, P, P, P, P, P, P, P, P, P, P, P, i32, P,
+                             ctypes.c_uint32, ctypes.c_uint32]
+    lib.or_set_inst_flags.argtypes = [P, P]
+    lib.or_set_alpha.argtypes = [P, i32, P, i32]
+    lib.or_camera_rays.argtypes = [P, i32, i32, P, i64, P]
+    lib.or_ao_uniforms.argtypes = [u64, u64, P, P]
+    lib.or_ao_direction.argtypes = [P, ctypes.c_double, ctypes.c_double, P]
+    lib.or_ao_rays.argtypes = [P, P, i64, u64, i32, P, P, P]
+    lib.or_render.restype = i64
+    lib.or_render.argtypes = [P, P, P, i32, i32, i32, i32, u64, P, i64, i32, P, P, P]
+    lib.or_primary_materials.argtypes = [P, P, i32, i32, P, i64, i32, P, P]
+    lib.or_eval_hits.argtypes = [P, P, i64, P, P, P]
+    return lib
 
 
 def _ptr(a: np.ndarray):
@@ -107,12 +129,13 @@ def light_array(light) -> np.ndarray:
 class Scene:
     """FP64 oracle view of a `scenegen.Scene` (or of explicit arrays)."""
 
-    def __init__(self, scene, sphere_reject: bool = False, inst_flags=None, alpha=None):
+    def __init__(self, scene, sphere_reject: bool = False, inst_flags=None, alpha=None, lib=None):
         """inst_flags: uint32 per instance (bits 0-7 visibility mask,
         INST_CULL_DISABLE, INST_FLIP_FACING), default 0xFF.  alpha: per
         bottom level None or (uint64 mask per triangle, level 0..3): the
-        opacity of the triangle's 4^level micro-triangles (see or_set_alpha)."""
-        lib = _load()
+        opacity of the triangle's 4^level micro-triangles (see or_set_alpha).
+        lib: a library from build_variant (default: the oracle)."""
+        lib = _load() if lib is None else lib
         self._lib = lib
         self.scene = scene
         vo, to = [0], [0]
@@ -182,6 +205,18 @@ class Scene:
                                    _ptr(rm) if rm is not None else None, mask, cull)
         out["tests"] = int(tests)
         return out
+
+    def eval_hits(self, rays: np.ndarray, inst, prim) -> dict:
+        """The given triangle (inst[i], prim[i]) against ray i in FP64: t, u,
+        v, m (least barycentric weight, >= 0 inside), beta, delta (its float32
+        error bands); NaN where inst is MISS."""
+        rays = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
+        n = rays.shape[0]
+        inst = np.ascontiguousarray(inst, np.uint32).reshape(n)
+        prim = np.ascontiguousarray(prim, np.uint32).reshape(n)
+        out = np.empty((n, 6))
+        self._lib.or_eval_hits(self.h, _ptr(rays), n, _ptr(inst), _ptr(prim), _ptr(out))
+        return dict(t=out[:, 0], u=out[:, 1], v=out[:, 2], m=out[:, 3], beta=out[:, 4], delta=out[:, 5])
 
     def ao_rays(self, rays: np.ndarray, seed: int, threads: int = 0) -> dict:
         """The 8 ambient-occlusion rays spawned at each input ray's closest hit:

@@ -573,6 +573,19 @@ static int64_t covering(const or_blas *B, int64_t j, const tri_eval_t *ej, const
     return k;
 }
 
+/* The ray in instance I's object space (o' = M^-1 o, d' = M^-1 d: t is
+ * unchanged) and the origin a float32 traversal uses there: moved along the
+ * ray to where it enters the mesh's box, never before tmin nor past tmax. */
+static void inst_frame(const or_inst *I, const or_blas *B, const or_ray *R, double o[3], double d[3],
+                       double o0[3]) {
+    xf_point(I->inv, R->o, o);
+    xf_vec(I->inv, R->d, d);
+    double te0, te1, ts = R->tmin;
+    if (box_enter(B->lo, B->hi, o, d, &te0, &te1) && te0 > ts) ts = te0;
+    if (ts > R->tmax) ts = R->tmax;
+    for (int k = 0; k < 3; ++k) o0[k] = o[k] + ts * d[k];
+}
+
 static void add_tie(or_result *res, uint32_t i, uint32_t j, const tri_eval_t *e) {
     for (int q = 0; q < res->nties; ++q)
         if (res->tie_inst[q] == i && res->tie_prim[q] == j) return;
@@ -627,20 +640,24 @@ static void or_trace_one(const or_scene *S, const or_ray *R, int any, int cover,
     double tlim = res->hit ? res->t : R->tmax;
     int fin_tmax = isfinite(R->tmax);
     int robust_hit = 0, near_band = 0;
+    /* the hit's own t band: a second surface nearer to t* than the two bands
+     * together cannot be ordered by a float32 traversal */
+    double hit_delta = 0.0;
+    if (res->hit && !any) {
+        const or_inst *I = &S->inst[res->inst];
+        double o[3], d[3], o0[3];
+        inst_frame(I, &S->blas[I->blas], R, o, d, o0);
+        ray_frame F = {o, d, o0, v_len(o0), v_len(d), dlen, I->inv_fro, R};
+        tri_eval_t e;
+        if (tri_eval(S->blas[I->blas].tri + 9 * (int64_t)res->prim, &F, &e)) hit_delta = e.delta;
+    }
     for (int64_t i = 0; i < S->ni; ++i) {
         const or_inst *I = &S->inst[i];
         const or_blas *B = &S->blas[I->blas];
         if (((I->flags & 0xFFu) & mask) == 0u) continue;
-        double o[3], d[3];
-        xf_point(I->inv, R->o, o);
-        xf_vec(I->inv, R->d, d);
+        double o[3], d[3], o0[3];
+        inst_frame(I, B, R, o, d, o0);
         if (S->sphere_reject && sphere_skip(B, o, d, R->tmin, R->tmax)) continue;
-        /* origin a float32 traversal would use: moved to where the ray enters
-         * the mesh's box (object space), never before tmin */
-        double te0, te1, ts = R->tmin;
-        if (box_enter(B->lo, B->hi, o, d, &te0, &te1) && te0 > ts) ts = te0;
-        if (ts > R->tmax) ts = R->tmax;
-        double o0[3] = {o[0] + ts * d[0], o[1] + ts * d[1], o[2] + ts * d[2]};
         ray_frame F = {o, d, o0, v_len(o0), v_len(d), dlen, I->inv_fro, R};
         for (int64_t j = 0; j < B->n; ++j) {
             tri_eval_t e, ek;
@@ -690,6 +707,9 @@ static void or_trace_one(const or_scene *S, const or_ray *R, int any, int cover,
                     res->amb = 1;
                 if (res->hit && m >= -beta && t >= R->tmin && t <= R->tmax && fabs(t - res->t) <= 1e-6 * res->t)
                     add_tie(res, (uint32_t)i, (uint32_t)j, &e);
+                else if (res->hit && m > beta && t >= R->tmin - delta && fabs(t - res->t) <= delta + hit_delta &&
+                         !((uint32_t)i == res->inst && (uint32_t)j == res->prim))
+                    res->amb = 1; /* a second surface within float32 reach of t*, not a tie */
                 if (res->hit && (uint32_t)i == res->inst && (uint32_t)j == res->prim) {
                     res->beta = beta;
                     res->delta = delta;
@@ -801,6 +821,35 @@ int64_t or_trace(or_scene *S, const float *rays, int64_t n, int32_t any, int32_t
     pool_run(trace_task, &c, n, nthreads);
     S->tests += c.tests;
     return c.tests;
+}
+
+/* One given triangle per ray: for ray r, triangle prim[r] of instance
+ * inst[r] evaluated in FP64 (Moller-Trumbore in the instance's object
+ * space), with its float32 error bands.  out[r][6] = t, u, v, m (the least
+ * barycentric weight: >= 0 inside the closed triangle), beta, delta; all NaN
+ * for inst[r] == OR_MISS, an out-of-range index or a ray parallel to the
+ * triangle's plane.  Used to check a reported hit that need not be the
+ * closest (any hit: any genuine hit of the ray is a correct answer). */
+void or_eval_hits(const or_scene *S, const float *rays, int64_t n, const uint32_t *inst, const uint32_t *prim,
+                  double *out) {
+    for (int64_t r = 0; r < n; ++r) {
+        double *q = out + 6 * r;
+        for (int k = 0; k < 6; ++k) q[k] = NAN;
+        if (inst[r] == OR_MISS || (int64_t)inst[r] >= S->ni) continue;
+        const or_inst *I = &S->inst[inst[r]];
+        const or_blas *B = &S->blas[I->blas];
+        if ((int64_t)prim[r] >= B->n) continue;
+        or_ray R;
+        for (int k = 0; k < 3; ++k) { R.o[k] = rays[8 * r + k]; R.d[k] = rays[8 * r + 3 + k]; }
+        R.tmin = rays[8 * r + 6]; R.tmax = rays[8 * r + 7];
+        R.sig_pos = R.sig_dir = 0.0;
+        double o[3], d[3], o0[3];
+        inst_frame(I, B, &R, o, d, o0);
+        ray_frame F = {o, d, o0, v_len(o0), v_len(d), v_len(R.d), I->inv_fro, &R};
+        tri_eval_t e;
+        if (!tri_eval(B->tri + 9 * (int64_t)prim[r], &F, &e)) continue;
+        q[0] = e.t; q[1] = e.u; q[2] = e.v; q[3] = e.m; q[4] = e.beta; q[5] = e.delta;
+    }
 }
 
 /* ------------------------------------------------------- camera and AO */
