@@ -691,7 +691,9 @@ static void or_trace_one(const or_scene *S, const or_ray *R, int any, int cover,
                 int in_range = (t >= R->tmin - delta) && (t <= tlim * (1.0 + 1e-5) + delta);
                 if (in_range && fabs(m) <= beta) {
                     int64_t k = cover ? covering(B, j, &e, &F, &ek) : -1;
-                    double ttol = res->hit ? fmax(1e-5 * res->t, fmin(e.delta, k >= 0 ? ek.delta : e.delta)) : 0.0;
+                    /* both triangles of a covered crossing are correct answers
+                     * only if each one's t is within 1e-5 t* */
+                    double ttol = res->hit ? 1e-5 * res->t : 0.0;
                     if (k >= 0 && res->hit && fabs(t - res->t) <= ttol && fabs(ek.t - res->t) <= ttol &&
                         t >= R->tmin + delta && ek.t >= R->tmin + ek.delta &&
                         (!fin_tmax || (t <= R->tmax - tmax_band && ek.t <= R->tmax - tmax_band))) {

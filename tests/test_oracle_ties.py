@@ -61,6 +61,14 @@ def fin_mesh():
     return sg.Mesh(V, np.array([[0, 1, 2], [1, 0, 3]], np.uint32))
 
 
+def roof_mesh():
+    """A roof: two triangles sharing the ridge (0,0,0)-(1,0,0), sloping down
+    at 45 degrees towards -y (triangle 0) and +y (triangle 1).  Seen from
+    above the ridge separates them: a shared interior edge."""
+    V = np.array([[0, 0, 0], [1, 0, 0], [0.5, -1, -1], [0.5, 1, -1]], np.float32)
+    return sg.Mesh(V, np.array([[0, 1, 2], [1, 0, 3]], np.uint32))
+
+
 def single_mesh(x0=0.0):
     V = np.array([[x0, 0, 0], [x0 + 1, 0, 0], [x0, 1, 0]], np.float32)
     return sg.Mesh(V, np.array([[0, 1, 2]], np.uint32))
@@ -129,6 +137,22 @@ def check_fin_far_below_ridge(lib=None):
     res = _trace(m, r, lib)
     assert res["hit"][0] == 1 and res["prim"][0] == 0 and res["amb"][0] == 0
     assert _ties(res) == {(0, 0)}
+
+
+def check_folded_edge(lib=None):
+    """A ray straight down 2^-20 (about half of beta) on triangle 1's side of
+    the roof's ridge.  The other face's plane is crossed 2 * 2^-20 higher up
+    (45 degree slopes).  From 1 above the ridge that is 1.9e-6 of t: a
+    covered crossing, both faces in the tie set.  From 0.1 above it is
+    1.9e-5 of t, beyond 1e-5: float32 cannot tell which face is hit and the
+    two t differ by more than the tolerance, so the ray is ambiguous."""
+    m = roof_mesh()
+    far = _trace(m, ray((0.5, 2 ** -20, 1.0), DOWN), lib)
+    assert far["hit"][0] == 1 and far["prim"][0] == 1 and far["amb"][0] == 0
+    assert _ties(far) == {(0, 0), (0, 1)}
+    near = _trace(m, ray((0.5, 2 ** -20, 0.1), DOWN), lib)
+    assert near["hit"][0] == 1 and near["prim"][0] == 1 and near["amb"][0] == 1
+    assert _trace(m, ray((0.5, 2 ** -20, 0.1), DOWN), lib, any_hit=True)["amb"][0] == 0
 
 
 def check_boundary_edge(lib=None):
@@ -224,7 +248,7 @@ def check_grazing(lib=None):
         assert res["hit"][0] == 1 and res["amb"][0] == amb, (c, res["amb"][0])
 
 
-HAND_CHECKS = [check_covered_interior_edge, check_interior_off_edge, check_silhouette_ridge,
+HAND_CHECKS = [check_covered_interior_edge, check_interior_off_edge, check_silhouette_ridge, check_folded_edge,
                check_fin_far_below_ridge, check_boundary_edge, check_vertex, check_tmax_band, check_tmin_band,
                check_second_surface, check_grazing]
 
@@ -365,6 +389,8 @@ MUTATIONS = [
      "                    res->amb = 1;",
      "                ;"),
     ("grazing flag dropped", "                    if (e.cosg < 1e-3) res->amb = 1;", "                    ;"),
+    ("covered pair t tolerance widened to delta", "                    double ttol = res->hit ? 1e-5 * res->t : 0.0;",
+     "                    double ttol = res->hit ? fmax(1e-5 * res->t, 100.0 * e.delta) : 0.0;"),
 ]
 
 
