@@ -151,10 +151,13 @@ typedef struct {
  *              (index in the input), float blas_lo[3], blas_hi[3] (the
  *              bottom level's root box), 8 bytes of padding.
  *   rec_off:   uint32 per input instance: its record's position.
+ *   xf_off:    float[n_inst][3][4]: the object->world matrices as given,
+ *              in input order (the trace calls recompute reported hits
+ *              from them).
  * It refers to the bottom levels' buffers, which must outlive it. */
 typedef struct {
     void *buf;
-    uint64_t nodes_off, inst_off, rec_off;
+    uint64_t nodes_off, inst_off, rec_off, xf_off;
     int64_t n_inst, n_nodes;
     int32_t width, depth, max_blas_depth;
     int32_t has_inst_flags; /* 1 when some instance carries flags other than RG_INST_MASK_ALL */
@@ -167,7 +170,9 @@ typedef struct {
 } rg_rays;
 
 /* Hit records in structure-of-arrays form (device).  Any pointer may be
- * NULL to skip that field.  Miss: t = +inf, inst = prim = RG_MISS, u = v = 0. */
+ * NULL to skip that field, except that t, u and v are computed from the hit's
+ * identity: a call that asks for any of them must also pass inst and prim.
+ * Miss: t = +inf, inst = prim = RG_MISS, u = v = 0. */
 typedef struct {
     float *t;
     uint32_t *inst, *prim;
@@ -316,15 +321,24 @@ rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xfo
                            void *scratch, uint64_t scratch_bytes, void *stream, rg_tlas *out /*host*/);
 
 /* ---------------------------------------------------------- tracing */
-/* Closest hit for n rays.  Asynchronous.
- * Errors: RG_ERR_INVALID_ARG for NULL tlas/ray pointers or n < 0 (n == 0 is
- * a no-op); RG_ERR_UNSUPPORTED if the hierarchy is deeper than the traversal
- * stack holds (never for the configurations built here). */
+/* Closest hit for n rays (section 1: the closest-hit / miss outcome of each
+ * ray against the two-level structure).  The traversal decides in float32,
+ * with the watertight edge test, which triangle is hit; the reported t, u and
+ * v are then recomputed for that triangle in double from the float32 inputs
+ * (ray, instance matrix, vertices), so they carry no float32 cancellation
+ * (t relative error ~1e-7 even for rays that start next to the surface);
+ * t is clamped to [tmin, tmax], u and v to [0, 1].  Asynchronous.
+ * Errors: RG_ERR_INVALID_ARG for NULL tlas/ray pointers, n < 0 (n == 0 is a
+ * no-op) or t/u/v asked for without inst and prim; RG_ERR_UNSUPPORTED if the
+ * hierarchy is deeper than the traversal stack holds (never for the
+ * configurations built here). */
 rg_status rg_trace_closest(const rg_tlas *tlas, rg_rays rays, int64_t n, rg_hits out, void *stream);
 
-/* Any hit: occluded[i] = 1 if some triangle is hit in [tmin, tmax], else 0.
- * `found` (nullable) receives one such hit (not necessarily the closest).
- * Asynchronous.  Errors as rg_trace_closest. */
+/* Any hit (section 1: the any-hit outcome; section 2.1: shadow rays):
+ * occluded[i] = 1 if some triangle is hit in [tmin, tmax], else 0.  `found`
+ * (nullable) receives one such hit (not necessarily the closest), its t, u, v
+ * recomputed in double as for rg_trace_closest.  Asynchronous.  Errors as
+ * rg_trace_closest. */
 rg_status rg_trace_any(const rg_tlas *tlas, rg_rays rays, int64_t n, uint8_t *occluded,
                        const rg_hits *found /*host struct, nullable*/, void *stream);
 

@@ -54,7 +54,7 @@ class BlasDesc(ctypes.Structure):
 
 
 class TlasDesc(ctypes.Structure):
-    _fields_ = [("buf", c_p), ("nodes_off", c_u64), ("inst_off", c_u64), ("rec_off", c_u64),
+    _fields_ = [("buf", c_p), ("nodes_off", c_u64), ("inst_off", c_u64), ("rec_off", c_u64), ("xf_off", c_u64),
                 ("n_inst", c_i64), ("n_nodes", c_i64), ("width", c_i32), ("depth", c_i32),
                 ("max_blas_depth", c_i32), ("has_inst_flags", c_i32), ("lo", c_f * 3), ("hi", c_f * 3)]
 

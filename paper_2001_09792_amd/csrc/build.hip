@@ -1788,7 +1788,8 @@ uint64_t blas_scratch_bytes(int64_t n, int32_t builder) {
     return a.used + rg_lbvh_scratch_bytes(n, builder);
 }
 
-uint64_t tlas_out_bytes(int64_t n, int w, uint64_t *nodes_off, uint64_t *inst_off, uint64_t *rec_off) {
+uint64_t tlas_out_bytes(int64_t n, int w, uint64_t *nodes_off, uint64_t *inst_off, uint64_t *rec_off,
+                        uint64_t *xf_off) {
     int64_t max_nodes = n > 1 ? n - 1 : 1;
     uint64_t off = 0;
     *nodes_off = off;
@@ -1797,12 +1798,13 @@ uint64_t tlas_out_bytes(int64_t n, int w, uint64_t *nodes_off, uint64_t *inst_of
     off = align256(off + (uint64_t)n * sizeof(RgInst));
     *rec_off = off;
     off = align256(off + (uint64_t)n * 4u);
+    *xf_off = off;
+    off = align256(off + (uint64_t)n * 48u);
     return off;
 }
 
 uint64_t tlas_scratch_bytes(int64_t n, int32_t n_blas, int32_t builder) {
     RgArena a{nullptr, 0, 0};
-    a.take<float>(12 * n);      // matrices
     a.take<uint32_t>(n);        // blas ids
     a.take<uint32_t>(n);        // materials
     a.take<BlasInfo>(n_blas > 0 ? n_blas : 1);
@@ -2038,8 +2040,8 @@ rg_status rg_blas_set_alpha(rg_blas *blas, const uint64_t *alpha, int32_t level,
 rg_status rg_tlas_sizes(int64_t n_inst, const rg_build_opts *opts, rg_sizes *out) {
     Opts o;
     if (!out || n_inst < 1 || n_inst > RG_MAX_TRIS || !opts_ok(opts, &o)) return RG_ERR_INVALID_ARG;
-    uint64_t a, b, c;
-    out->bytes = tlas_out_bytes(n_inst, o.w, &a, &b, &c);
+    uint64_t a, b, c, d;
+    out->bytes = tlas_out_bytes(n_inst, o.w, &a, &b, &c, &d);
     out->scratch_bytes = tlas_scratch_bytes(n_inst, 4096, o.builder);
     return RG_OK;
 }
@@ -2075,13 +2077,13 @@ rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xfo
         double det = a * (e * k - f * h) - b * (d * k - f * g) + c * (d * h - e * g);
         if (!(std::fabs(det) > 0.0) || !std::isfinite(det)) return RG_ERR_INVALID_ARG;
     }
-    uint64_t no, io, ro;
-    uint64_t need = tlas_out_bytes(n_inst, w, &no, &io, &ro);
+    uint64_t no, io, ro, xo;
+    uint64_t need = tlas_out_bytes(n_inst, w, &no, &io, &ro, &xo);
     if (out_bytes < need || scratch_bytes < tlas_scratch_bytes(n_inst, n_blas, o.builder))
         return RG_ERR_OUT_OF_MEMORY;
     hipStream_t st = (hipStream_t)stream;
     RgArena arena{(char *)scratch, scratch_bytes, 0};
-    float *d_xf = arena.take<float>(12 * n_inst);
+    float *d_xf = (float *)((char *)out_buf + xo);  // kept: the trace calls recompute hits from it
     uint32_t *d_bid = arena.take<uint32_t>(n_inst);
     uint32_t *d_mat = arena.take<uint32_t>(n_inst);
     BlasInfo *d_info = arena.take<BlasInfo>(n_blas);
@@ -2114,6 +2116,7 @@ rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xfo
     out->nodes_off = no;
     out->inst_off = io;
     out->rec_off = ro;
+    out->xf_off = xo;
     out->n_inst = n_inst;
     out->n_nodes = lo.n_nodes;
     out->width = w;

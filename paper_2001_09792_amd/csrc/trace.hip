@@ -33,7 +33,7 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
         tr.rmask = a.mask;
     }
     int64_t next = 0;  // position in this wave's ray sequence (the same in all lanes)
-    int64_t ray_i = -1;
+    uint32_t ray_i = 0;  // launches hold fewer than 2^31 rays
     bool has = false;
     // A finished ray's results stay in its lane until the lane takes its next
     // ray (or the wave ends): writing them then puts the stores next to the
@@ -41,14 +41,14 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
     bool pend = false;
     auto write_result = [&]() {
         if (MODE == rgt::kCounts) {
-            a.counts[3 * ray_i] = tr.h.n_nodes;
-            a.counts[3 * ray_i + 1] = tr.h.n_tris;
-            a.counts[3 * ray_i + 2] = tr.h.n_inst;
+            a.counts[3 * (uint64_t)ray_i] = tr.h.n_nodes;
+            a.counts[3 * (uint64_t)ray_i + 1] = tr.h.n_tris;
+            a.counts[3 * (uint64_t)ray_i + 2] = tr.h.n_inst;
         } else {
             if (ANY && a.occluded) a.occluded[ray_i] = tr.found ? 1 : 0;
-            if (a.t) a.t[ray_i] = tr.h.t;
-            if (a.u) a.u[ray_i] = tr.h.u;
-            if (a.v) a.v[ray_i] = tr.h.v;
+            // the render's closest hits carry their float32 t to shading;
+            // the trace calls get t, u, v from k_refine
+            if (MODE == rgt::kRender && !ANY && a.t) a.t[ray_i] = tr.found ? tr.best : INFINITY;
             if (a.inst) a.inst[ray_i] = tr.h.inst;
             if (a.prim) a.prim[ray_i] = tr.h.prim;
         }
@@ -70,8 +70,8 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
                     R.d[0] = a.ray[3][idx]; R.d[1] = a.ray[4][idx]; R.d[2] = a.ray[5][idx];
                     R.tmin = a.ray[6][idx];
                     R.tmax = a.ray[7][idx];
-                    ray_i = idx;
-                    if (a.ray_job) {
+                    ray_i = (uint32_t)idx;
+                    if (MODE == rgt::kRender && a.ray_job) {  // only frames carry per-ray top levels
                         const RgTlasRef J = a.jobs[a.ray_job[idx]];
                         tr.tlas_nodes = reinterpret_cast<const RgNode<W> *>(J.nodes);
                         tr.recs = J.recs;
@@ -107,6 +107,76 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
         }
     }
     if (pend) write_result();
+}
+
+// The reported hit in double precision.  The traversal decides in float32
+// which triangle a ray hits (the decisions are the watertight ones); float32
+// cannot give that triangle's t to 1e-5 of its value when the ray starts
+// close to it (a secondary ray leaving a surface: the vertex offsets cancel
+// to a few bits).  So the trace calls recompute t, u and v of the chosen
+// triangle from the exact float32 inputs: the triangle's object-space
+// vertices mapped to world space with the instance's matrix, and the world
+// ray, intersected with Moller-Trumbore (Moller & Trumbore 1997) in double.
+// t is parametric in the ray, so the world-space t is the object-space t.
+// One thread per ray; reads the ray and the traversal's (inst, prim) in
+// order, gathers the matrix, the triangle's leaf slot and the triangle.
+struct RefineArgs {
+    const float *ray[8];
+    int64_t n;
+    const uint32_t *inst, *prim;  // the traversal's result (input indices)
+    float *t, *u, *v;             // outputs, nullable
+    const RgInst *recs;
+    const uint32_t *rec_of;       // record of each input instance
+    const float *xf;              // object -> world matrices, input order
+};
+
+__global__ void __launch_bounds__(256) k_refine(RefineArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    const uint32_t in = a.inst[i];
+    float t = INFINITY, u = 0.0f, v = 0.0f;
+    if (in != RG_MISS) {
+        const uint32_t p = a.prim[i];
+        const RgBlasHdr *H = reinterpret_cast<const RgBlasHdr *>(a.recs[a.rec_of[in]].hdr);
+        const uint32_t slot = reinterpret_cast<const uint32_t *>(H->slots)[p];
+        const RgTri tri = reinterpret_cast<const RgTri *>(H->tris)[slot];
+        const float *M = a.xf + 12 * (uint64_t)in;
+        double P[3][3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+                P[k][r] = (double)M[4 * r] * tri.v[3 * k] + (double)M[4 * r + 1] * tri.v[3 * k + 1] +
+                          (double)M[4 * r + 2] * tri.v[3 * k + 2] + (double)M[4 * r + 3];
+        const double o[3] = {a.ray[0][i], a.ray[1][i], a.ray[2][i]};
+        const double d[3] = {a.ray[3][i], a.ray[4][i], a.ray[5][i]};
+        const float tmin = a.ray[6][i], tmax = a.ray[7][i];
+        double e1[3], e2[3], s[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            e1[r] = P[1][r] - P[0][r];
+            e2[r] = P[2][r] - P[0][r];
+            s[r] = o[r] - P[0][r];
+        }
+        const double pv[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
+        const double det = e1[0] * pv[0] + e1[1] * pv[1] + e1[2] * pv[2];
+        t = tmin;  // a hit whose plane is exactly parallel to the ray in double: grazing, reported at tmin
+        if (det != 0.0) {
+            const double q[3] = {s[1] * e1[2] - s[2] * e1[1], s[2] * e1[0] - s[0] * e1[2], s[0] * e1[1] - s[1] * e1[0]};
+            const double r = 1.0 / det;
+            const double uu = (s[0] * pv[0] + s[1] * pv[1] + s[2] * pv[2]) * r;
+            const double vv = (d[0] * q[0] + d[1] * q[1] + d[2] * q[2]) * r;
+            const double tt = (e2[0] * q[0] + e2[1] * q[1] + e2[2] * q[2]) * r;
+            // the hit was found inside the triangle and the interval by the
+            // float32 test: keep the refined values there too
+            t = fminf(fmaxf((float)tt, tmin), tmax);
+            u = fminf(fmaxf((float)uu, 0.0f), 1.0f);
+            v = fminf(fmaxf((float)vv, 0.0f), 1.0f);
+        }
+    }
+    if (a.t) a.t[i] = t;
+    if (a.u) a.u[i] = u;
+    if (a.v) a.v[i] = v;
 }
 
 // Launch parameters per family of calls (RG_TUNE_*): refill threshold,
@@ -187,8 +257,33 @@ bool set_opts(RgTraceArgs &a, const rg_trace_opts *o) {
     return true;
 }
 
+// rays per trace call: the kernels keep a ray's index in 32 bits
+constexpr int64_t kMaxRays = 0xFFFFFFFFll;
+
 bool tlas_ok(const rg_tlas *t) {
     return t && t->buf && t->n_inst >= 1 && (t->width == 2 || t->width == 4 || t->width == 8);
+}
+
+// t, u and v are computed from the hit's identity: asking for any of them
+// needs inst and prim too.
+bool hits_ok(const rg_hits &h) { return !(h.t || h.u || h.v) || (h.inst && h.prim); }
+
+rg_status refine(const rg_tlas *tlas, const RgTraceArgs &a, const rg_hits &h, hipStream_t st) {
+    if (!(h.t || h.u || h.v)) return RG_OK;
+    RefineArgs r;
+    for (int c = 0; c < 8; ++c) r.ray[c] = a.ray[c];
+    r.n = a.n;
+    r.inst = h.inst;
+    r.prim = h.prim;
+    r.t = h.t;
+    r.u = h.u;
+    r.v = h.v;
+    r.recs = a.recs;
+    r.rec_of = (const uint32_t *)((const char *)tlas->buf + tlas->rec_off);
+    r.xf = (const float *)((const char *)tlas->buf + tlas->xf_off);
+    k_refine<<<rg_blocks(a.n, 256), 256, 0, st>>>(r);
+    RG_LAUNCH_CHECK();
+    return RG_OK;
 }
 
 }  // namespace
@@ -234,7 +329,8 @@ rg_status rg_trace_any(const rg_tlas *tlas, rg_rays rays, int64_t n, uint8_t *oc
 
 rg_status rg_trace_closest_ex(const rg_tlas *tlas, rg_rays rays, int64_t n, rg_hits out, const rg_trace_opts *opts,
                               void *stream) {
-    if (!tlas_ok(tlas) || n < 0 || (n > 0 && !rays_ok(rays))) return RG_ERR_INVALID_ARG;
+    if (!tlas_ok(tlas) || n < 0 || n > kMaxRays || (n > 0 && !rays_ok(rays)) || !hits_ok(out))
+        return RG_ERR_INVALID_ARG;
     RgTraceArgs a = {};
     if (!set_opts(a, opts)) return RG_ERR_INVALID_ARG;
     a.opt = a.opt || tlas->has_inst_flags != 0;
@@ -244,13 +340,19 @@ rg_status rg_trace_closest_ex(const rg_tlas *tlas, rg_rays rays, int64_t n, rg_h
     a.recs = (const RgInst *)((const char *)tlas->buf + tlas->inst_off);
     fill_rays(a, rays);
     a.n = n;
-    a.t = out.t; a.u = out.u; a.v = out.v; a.inst = out.inst; a.prim = out.prim;
-    return rg_trace_launch(tlas->width, false, rgt::kClosest, a, (hipStream_t)stream, RG_TUNE_TRACE);
+    a.inst = out.inst;
+    a.prim = out.prim;
+    const hipStream_t st = (hipStream_t)stream;
+    rg_status r = rg_trace_launch(tlas->width, false, rgt::kClosest, a, st, RG_TUNE_TRACE);
+    if (r != RG_OK) return r;
+    return rg_debug_done(refine(tlas, a, out, st), st);
 }
 
 rg_status rg_trace_any_ex(const rg_tlas *tlas, rg_rays rays, int64_t n, uint8_t *occluded, const rg_hits *found,
                           const rg_trace_opts *opts, void *stream) {
-    if (!tlas_ok(tlas) || n < 0 || (n > 0 && (!rays_ok(rays) || !occluded))) return RG_ERR_INVALID_ARG;
+    if (!tlas_ok(tlas) || n < 0 || n > kMaxRays || (n > 0 && (!rays_ok(rays) || !occluded)))
+        return RG_ERR_INVALID_ARG;
+    if (found && !hits_ok(*found)) return RG_ERR_INVALID_ARG;
     RgTraceArgs a = {};
     if (!set_opts(a, opts)) return RG_ERR_INVALID_ARG;
     a.opt = a.opt || tlas->has_inst_flags != 0;
@@ -262,14 +364,19 @@ rg_status rg_trace_any_ex(const rg_tlas *tlas, rg_rays rays, int64_t n, uint8_t 
     a.n = n;
     a.occluded = occluded;
     if (found) {
-        a.t = found->t; a.u = found->u; a.v = found->v; a.inst = found->inst; a.prim = found->prim;
+        a.inst = found->inst;
+        a.prim = found->prim;
     }
-    return rg_trace_launch(tlas->width, true, rgt::kClosest, a, (hipStream_t)stream, RG_TUNE_TRACE);
+    const hipStream_t st = (hipStream_t)stream;
+    rg_status r = rg_trace_launch(tlas->width, true, rgt::kClosest, a, st, RG_TUNE_TRACE);
+    if (r != RG_OK || !found) return r;
+    return rg_debug_done(refine(tlas, a, *found, st), st);
 }
 
 rg_status rg_trace_counts(const rg_tlas *tlas, rg_rays rays, int64_t n, int32_t any_hit, uint32_t *counts,
                           void *stream) {
-    if (!tlas_ok(tlas) || n < 0 || (n > 0 && (!rays_ok(rays) || !counts))) return RG_ERR_INVALID_ARG;
+    if (!tlas_ok(tlas) || n < 0 || n > kMaxRays || (n > 0 && (!rays_ok(rays) || !counts)))
+        return RG_ERR_INVALID_ARG;
     if (!rg_trace_depth_ok(tlas)) return RG_ERR_UNSUPPORTED;
     if (n == 0) return RG_OK;
     RgTraceArgs a = {};

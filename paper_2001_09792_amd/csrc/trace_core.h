@@ -68,11 +68,12 @@ struct Ray {
     float o[3], d[3], tmin, tmax;
 };
 
-// Result of one traversal.  For kRender `inst` is the top-level record index
-// and `prim` the bottom-level triangle slot (leaf order); otherwise they are
-// the input indices.
+// Result of one traversal: which triangle is hit.  For kRender `inst` is the
+// top-level record index and `prim` the bottom-level triangle slot (leaf
+// order); otherwise they are the input indices.  The hit's t is the
+// tracer's `best` (closest hit); the trace entry points recompute t and the
+// barycentrics of the chosen triangle in double afterwards (k_refine).
 struct Hit {
-    float t, u, v;
     uint32_t inst, prim;
     uint32_t n_nodes, n_tris, n_inst;  // visit counts (kCounts)
 };
@@ -248,8 +249,6 @@ struct Tracer {
     // Returns false if the ray has nothing to do (empty interval).
     __device__ inline bool begin(const Ray &ray) {
         R = ray;
-        h.t = INFINITY;
-        h.u = h.v = 0.0f;
         h.inst = h.prim = RG_MISS;
         h.n_nodes = h.n_tris = h.n_inst = 0;
         best = R.tmax;
@@ -451,9 +450,6 @@ struct Tracer {
                     if (inst_id > h.inst || (inst_id == h.inst && pid >= h.prim)) continue;
                 }
                 found = true;
-                h.t = tw;
-                h.u = V / det;
-                h.v = Wv / det;
                 h.inst = inst_id;
                 h.prim = pid;
                 if (ANY) {

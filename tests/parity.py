@@ -2,12 +2,14 @@
 
 closest hit, for every ray the oracle does not flag as ambiguous:
   hit/miss agree; the GPU's (inst, prim) is in the oracle's tie set (exact
-  ties, and both triangles of a covered edge crossing); against that member's
-  FP64 values, |t - t*| <= max(1e-5 t*, delta) and |u - u*|, |v - v*| <=
-  max(1e-4, beta), where
-  delta and beta are the float32 error bands of that triangle's t and
-  barycentrics (delta exceeds 1e-5 t* only for hits much nearer than the
-  float32 coordinates' magnitude, e.g. a secondary ray hitting close by).
+  ties within 1e-6 t*, and both triangles of a covered edge crossing, each
+  within 1e-5 t*); against that member's FP64 values (u, v clamped to
+  [0, 1] as the library reports them), |t - t*| <= 1e-5 t* and
+  |u - u*|, |v - v*| <= 1e-4.  The trace calls report t, u, v recomputed in
+  double for the triangle the float32 traversal chose.
+  With t_band=True (hits a render pass keeps internally, whose t is the
+  float32 traversal's): |t - t*| <= max(1e-5 t*, delta), delta the float32
+  error band of that triangle's t; u, v are not compared.
 any hit: occluded agrees on every non-ambiguous ray.
 render: RMSE over non-ambiguous pixels and all channels <= 1e-4.
 """
@@ -18,8 +20,9 @@ UV_ABS = 1e-4
 RMSE_MAX = 1e-4
 
 
-def check_closest(g, o, max_amb: float = 0.02, label: str = ""):
-    """g: dict of numpy arrays from the GPU (t, inst, prim, u, v); o: oracle."""
+def check_closest(g, o, max_amb: float = 0.02, label: str = "", t_band: bool = False):
+    """g: dict of numpy arrays from the GPU (t, inst, prim, u, v; u, v not
+    needed with t_band); o: oracle."""
     n = o["t"].shape[0]
     ok = o["amb"] == 0
     amb_frac = 1.0 - ok.mean() if n else 0.0
@@ -46,16 +49,18 @@ def check_closest(g, o, max_amb: float = 0.02, label: str = ""):
                               f"{ties.tolist()} (oracle ({o['inst'][i]},{o['prim'][i]}) t={o['t'][i]})")
         tt, tu, tv = o["ties_tuv"][i, sel[0]]
         dt = abs(float(g["t"][i]) - tt)
-        t_tol = max(T_REL * tt, o["delta"][i])
+        t_tol = max(T_REL * tt, o["delta"][i]) if t_band else T_REL * tt
         loose += t_tol > T_REL * tt
         assert dt <= t_tol, f"{label}: ray {i}: t {g['t'][i]} vs {tt} (tol {t_tol:.3g})"
         worst_t = max(worst_t, dt / max(o["t"][i], 1e-30))
-        tol = max(UV_ABS, o["beta"][i])
+        ratio_t = max(ratio_t, dt / max(o["delta"][i], 1e-300))
+        if t_band:
+            continue
+        tu, tv = min(max(tu, 0.0), 1.0), min(max(tv, 0.0), 1.0)
         du = max(abs(float(g["u"][i]) - tu), abs(float(g["v"][i]) - tv))
-        assert du <= tol, f"{label}: ray {i}: uv ({g['u'][i]},{g['v'][i]}) vs ({tu},{tv}), tol {tol}"
+        assert du <= UV_ABS, f"{label}: ray {i}: uv ({g['u'][i]},{g['v'][i]}) vs ({tu},{tv}), tol {UV_ABS}"
         worst_uv = max(worst_uv, du)
         ratio_uv = max(ratio_uv, du / max(o["beta"][i], 1e-300))
-        ratio_t = max(ratio_t, dt / max(o["delta"][i], 1e-300))
     return dict(band_use_uv=float(ratio_uv), band_use_t=float(ratio_t), n=n, amb_frac=float(amb_frac), hits=int(idx.size), worst_t_rel=worst_t, worst_uv=worst_uv,
                 t_band_used=int(loose))
 
@@ -67,6 +72,36 @@ def check_any(occ, o, max_amb: float = 0.02, label: str = ""):
     bad = np.nonzero(ok & ((occ != 0) != (o["hit"] == 1)))[0]
     assert bad.size == 0, f"{label}: occlusion differs on {bad.size} rays, e.g. {bad[:5]}"
     return dict(n=int(occ.shape[0]), amb_frac=float(amb_frac), occluded=int((o["hit"] == 1).sum()))
+
+
+def check_found(found, occ, rays, orc, oa, label: str = ""):
+    """The any-hit call's reported hit: for every occluded ray that the
+    oracle's any-hit result `oa` does not flag, the reported (inst, prim) must
+    be a genuine hit of the ray (paper section 1: any hit; several answers are
+    correct, so this checks validity, not equality): the FP64 evaluation of
+    that triangle (orc.eval_hits) is inside it (least barycentric weight
+    >= -beta) with t in [tmin - delta, tmax + delta], and the reported t, u, v
+    are that triangle's within 1e-5 relative / 1e-4.  Rays not occluded
+    report a miss."""
+    rays = np.asarray(rays, np.float32).reshape(-1, 8)
+    gi = found["inst"].astype(np.uint32)
+    occ = occ != 0
+    assert np.array_equal(occ, gi != 0xFFFFFFFF), f"{label}: found hit and occluded disagree"
+    assert np.isinf(found["t"][~occ]).all()
+    sel = np.nonzero(occ & (oa["amb"] == 0))[0]
+    ev = orc.eval_hits(rays[sel], gi[sel], found["prim"].astype(np.uint32)[sel])
+    tmin, tmax = rays[sel, 6].astype(np.float64), rays[sel, 7].astype(np.float64)
+    assert np.isfinite(ev["t"]).all(), f"{label}: reported hit is parallel to its ray or out of range"
+    bad = ev["m"] < -ev["beta"]
+    assert not bad.any(), f"{label}: {bad.sum()} reported hits lie outside their triangle, e.g. {sel[bad][:5]}"
+    bad = (ev["t"] < tmin - ev["delta"]) | (ev["t"] > tmax + ev["delta"])
+    assert not bad.any(), f"{label}: {bad.sum()} reported hits lie outside [tmin, tmax]"
+    gt = found["t"][sel].astype(np.float64)
+    bad = np.abs(gt - ev["t"]) > T_REL * np.abs(ev["t"]) + 1e-30
+    assert not bad.any(), f"{label}: t of {bad.sum()} reported hits, e.g. {gt[bad][:3]} vs {ev['t'][bad][:3]}"
+    du = np.maximum(np.abs(found["u"][sel] - np.clip(ev["u"], 0, 1)), np.abs(found["v"][sel] - np.clip(ev["v"], 0, 1)))
+    assert (du <= UV_ABS).all(), f"{label}: u, v of reported hits off by up to {du.max():.3g}"
+    return dict(checked=int(sel.size), worst_t_rel=float(np.max(np.abs(gt - ev["t"]) / np.abs(ev["t"]))) if sel.size else 0.0)
 
 
 def check_image(img, o, max_amb: float = 0.02, label: str = ""):

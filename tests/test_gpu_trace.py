@@ -27,26 +27,34 @@ def _upload(scene, width=4, leaf=4, builder="lbvh"):
     return tl
 
 
-def _trace(tl, rays_np):
+def _trace(tl, rays_np, with_found=False):
     import paper_2001_09792_amd as rg
     r = rg.rays_to_device(rays_np)
     h = parity.hits_to_numpy(rg.trace_closest(tl, r))
-    occ = rg.trace_any(tl, r).cpu().numpy()
+    found = rg.alloc_hits(r.shape[1]) if with_found else None
+    occ = rg.trace_any(tl, r, found=found).cpu().numpy()
+    if with_found:
+        return h, occ, parity.hits_to_numpy(found)
     return h, occ
 
 
 def _both(scene, rays_np, label, max_amb=0.02, width=4, leaf=4, sphere=False, builder="lbvh"):
     print(f"[trace] {label}: {rays_np.shape[0]} rays W={width} L={leaf} {builder}", flush=True)
     tl = _upload(scene, width, leaf, builder)
-    h, occ = _trace(tl, rays_np)
+    h, occ, found = _trace(tl, rays_np, with_found=True)
     orc = oracle.Scene(scene, sphere_reject=sphere)
     oc = orc.trace(rays_np)
     oa = orc.trace(rays_np, any_hit=True)
     sc = parity.check_closest(h, oc, max_amb, label)
     sa = parity.check_any(occ, oa, max_amb, label)
-    # GPU-internal invariant: occluded == a closest hit exists
+    sf = parity.check_found(found, occ, rays_np, orc, oa, label)
+    # GPU-internal invariants: occluded == a closest hit exists; the closest
+    # hit is no farther than the reported any hit (where float32 can order
+    # the surfaces)
     assert np.array_equal(occ != 0, h["inst"].astype(np.uint32) != 0xFFFFFFFF)
-    print(f"  closest {sc}\n  any {sa}", flush=True)
+    both = (occ != 0) & (oc["amb"] == 0) & (oa["amb"] == 0)
+    assert (h["t"][both] <= found["t"][both] * (1 + 1e-6)).all()
+    print(f"  closest {sc}\n  any {sa}\n  found {sf}", flush=True)
     return h, occ, oc
 
 
