@@ -642,6 +642,27 @@ rg_status rg_lbvh_stages(const float *verts, int64_t n_verts, const uint32_t *id
                          int32_t *left, int32_t *right, float *boxes, void *scratch,
                          uint64_t scratch_bytes, void *stream);
 
+/* ------------------------------------------ rendering without allocation */
+/* rg_render for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * frame runs exactly as rg_render (image bitwise the same), with its scratch
+ * in a device array of RG_STATIC_SCRATCH_BYTES inside the library (each GPU
+ * holds one from the library's first use on it until the process ends), so
+ * the caller passes only the inputs and the image, and the call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine; no stats, so
+ * no events either).  Frames whose rg_render_sizes exceed the array are
+ * refused with RG_ERR_OUT_OF_MEMORY before anything is enqueued (64 MiB holds
+ * for instance 256x256 at depth 2, 128x128 at depth 4).  Every call on one
+ * GPU uses that GPU's single array: calls that overlap on one GPU (other
+ * streams, other threads) race, so serialise them; a call clears what it
+ * needs cleared itself.  The first call on a device looks up the array's
+ * address there (hipGetSymbolAddress).  Other errors as rg_render. */
+#define RG_STATIC_SCRATCH_BYTES (64ull << 20)
+rg_status rg_render_static(const rg_tlas *tlas, const rg_material *mats /*host*/, int32_t n_mats,
+                           const rg_camera *cam /*host*/, const rg_light *light /*host*/, int32_t width,
+                           int32_t height, int32_t max_depth, int32_t mode, uint64_t seed, float *image,
+                           void *stream);
+
 #ifdef __cplusplus
 }
 #endif

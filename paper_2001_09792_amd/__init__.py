@@ -143,6 +143,7 @@ SIGNATURES = {
                           c_p, c_p]),
     "rg_render_ex": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_u64, c_p, c_p, c_p,
                              c_u64, c_p, c_p]),
+    "rg_render_static": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_u64, c_p, c_p]),
     "rg_post_sizes": (c_i32, [c_i32, c_i32, c_p]),
     "rg_blas_set_alpha": (c_i32, [c_p, c_p, c_i32, c_p]),
     "rg_roughness_blur": (c_i32, [c_p, c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_p, c_p, c_u64, c_p]),
@@ -417,7 +418,9 @@ def alloc_hits(n: int, device="cuda"):
 
 
 def _hits_struct(h) -> Hits:
-    return Hits(_ptr(h["t"]), _ptr(h["inst"]), _ptr(h["prim"]), _ptr(h["u"]), _ptr(h["v"]))
+    """h: dict of CUDA tensors; a missing key skips that field (t, u, v need
+    inst and prim)."""
+    return Hits(_ptr(h.get("t")), _ptr(h.get("inst")), _ptr(h.get("prim")), _ptr(h.get("u")), _ptr(h.get("v")))
 
 
 # ray visibility and facing (include/rg.h)
@@ -711,6 +714,22 @@ class Batch:
             return self.images, dict(rays_traced=int(st.rays_traced), shadow_rays=int(st.shadow_rays),
                                      ms_total=float(st.ms_total))
         return self.images
+
+
+STATIC_SCRATCH_BYTES = 64 << 20  # RG_STATIC_SCRATCH_BYTES
+
+
+def render_static(tlas: Tlas, mats, camera, light, width: int, height: int, max_depth: int, image,
+                  mode: int = 0, seed: int = 0, stream=None):
+    """rg_render_static: rg_render into a caller-owned image [H, W, 3] with the
+    library's own device-resident scratch (no allocation; frames up to
+    STATIC_SCRATCH_BYTES of render_sizes; calls on one GPU must not overlap)."""
+    ma = materials_array(mats)
+    cd, ld = camera_desc(camera), light_desc(light)
+    _check("rg_render_static", _lib.rg_render_static(tlas.ref, ma, len(mats), ctypes.byref(cd), ctypes.byref(ld),
+                                                     width, height, max_depth, mode, seed, _ptr(image),
+                                                     _stream(stream)))
+    return image
 
 
 def render_into(tlas: Tlas, mats, camera, light, width: int, height: int, max_depth: int, image, scratch,

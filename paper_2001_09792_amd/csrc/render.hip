@@ -14,6 +14,7 @@
 // is independent of the order in which waves append and add.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "wavefront.h"
@@ -1069,3 +1070,51 @@ static rg_status render_impl(const rg_tlas *tlas, const rg_material *mats, int32
 }
 
 }  // extern "C"
+
+// ------------------------------------------------ rg_render_static
+// Scratch memory of rg_render_static: a device array of RG_STATIC_SCRATCH_BYTES
+// in the library's code object.  Each GPU the library runs on holds its own
+// copy, from the module's load on that device until the process ends.  Host
+// code never uses the array's name as an address (on the host it names a
+// stand-in, not device memory): the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[RG_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices] = {};
+
+rg_status static_scratch(void **out) {
+    int dev = 0;
+    RG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return RG_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        RG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return RG_ERR_HIP;
+        g_static_ptr[dev] = p;
+    }
+    *out = g_static_ptr[dev];
+    return RG_OK;
+}
+}  // namespace
+
+extern "C" rg_status rg_render_static(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats,
+                                      const rg_camera *cam, const rg_light *light, int32_t width, int32_t height,
+                                      int32_t max_depth, int32_t mode, uint64_t seed, float *image, void *stream) {
+    uint64_t need = 0;
+    rg_status r = rg_render_sizes(width, height, max_depth, mode, &need);
+    if (r != RG_OK) return r;
+    if (need > RG_STATIC_SCRATCH_BYTES) {
+        rg_set_error(__FILE__, __LINE__, "rg_render_static: frame needs more scratch than RG_STATIC_SCRATCH_BYTES");
+        return RG_ERR_OUT_OF_MEMORY;
+    }
+    void *p = nullptr;
+    if ((r = static_scratch(&p)) != RG_OK) return r;
+    // the same passes as rg_render; every counter, statistic and accumulator
+    // that must start at zero is cleared by the passes' own fill kernels
+    return rg_render_ex(tlas, mats, n_mats, cam, light, width, height, max_depth, mode, seed, image, nullptr, p,
+                        RG_STATIC_SCRATCH_BYTES, stream, nullptr);
+}
