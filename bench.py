@@ -14,11 +14,16 @@ hit, reflection and refraction passes), value = all rays traced / frame time.
 
 One JSON line is printed.  `roofline` refers to the dominant kernel (the
 closest-hit traversal of the AO rays): algorithmic bytes per ray from the
-traversal's own visit counts (rays 32 B + hit 20 B + nodes x 28W B (the
-node without its padding: 112 B at width 4) + triangles x 40 B + instance
-records x 112 B) over the kernel's event-timed duration,
-against 8 TB/s.  `cpu_baseline` is the FP64 oracle timed on a bounded sample
-of the same rays on this host's cores.
+traversal's own visit counts (ray 32 B + hit 20 B + nodes x 28W B rounded up
+to 64 / 128 / 256 B + triangles x 40 B + instance entries x 56 B: the 3x4
+inverse and the bottom level's root / id) over the kernel's event-timed
+duration, against 8 TB/s and against the copy bandwidth measured on the same
+GPU; beside it the surface-area cost of the hierarchies it walks.
+`cpu_baseline` is the FP64 oracle timed on a bounded sample of the same rays
+on this host's cores.  The default run also measures, on the same GPU, the
+batched form (256 scenes: one batch against one rg_render per frame) and the
+served form (64 resident scenes: saturated engine against plain dispatch,
+p50 / p99 latency at 0.9 of plain dispatch's saturated rate).
 """
 import argparse
 import math
@@ -33,8 +38,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-NODE_BYTES = {2: 56, 4: 112, 8: 224}  # 28 W: the node without its padding
-TRI_BYTES, INST_BYTES, RAY_BYTES, HIT_BYTES = 40, 112, 32, 20
+NODE_BYTES = {2: 64, 4: 128, 8: 256}  # 28 W rounded up to 64 / 128 / 256
+# a triangle (9 floats + id), an instance entry (3x4 inverse 48 + root / id 8),
+# a ray (8 floats) and a hit (t, inst, prim, u, v)
+TRI_BYTES, INST_BYTES, RAY_BYTES, HIT_BYTES = 40, 56, 32, 20
+# surface-area cost constants: one box test per node visit, one triangle test
+SAH_C_NODE, SAH_C_TRI = 1.0, 1.0
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_ao_closest.json")
@@ -91,6 +100,61 @@ def algorithmic_bytes(counts: np.ndarray, width: int) -> float:
                  + c[:, 1].sum() * TRI_BYTES + c[:, 2].sum() * INST_BYTES)
 
 
+def sah_cost(buf: np.ndarray, nodes_off: int, n_nodes: int, width: int) -> float:
+    """Surface-area cost of a wide hierarchy (layout of include/rg.h):
+    (A(root) C_node + sum over inner children A(child) C_node + sum over leaf
+    children A(leaf) n_prims C_tri) / A(root), A the box's surface area."""
+    W = width
+    words = buf[nodes_off: nodes_off + n_nodes * 32 * W].view(np.uint32).reshape(n_nodes, 8 * W)
+    raw = words.view(np.float32).astype(np.float64)
+    lo = np.stack([raw[:, 0:W], raw[:, W:2 * W], raw[:, 2 * W:3 * W]], -1)
+    hi = np.stack([raw[:, 3 * W:4 * W], raw[:, 4 * W:5 * W], raw[:, 5 * W:6 * W]], -1)
+    child = words[:, 6 * W:7 * W]
+    used = child != 0xFFFFFFFF
+    e = np.where(used[..., None], hi - lo, 0.0)
+    area = 2.0 * (e[..., 0] * e[..., 1] + e[..., 1] * e[..., 2] + e[..., 2] * e[..., 0])
+    leaf = used & ((child & 0x80000000) != 0)
+    cnt = ((child >> 28) & 7) + 1
+    m = used[0]
+    rl, rh = lo[0][m].min(axis=0), hi[0][m].max(axis=0)
+    r = rh - rl
+    a_root = 2.0 * (r[0] * r[1] + r[1] * r[2] + r[2] * r[0])
+    inner = used & ~leaf
+    total = a_root * SAH_C_NODE + (area * inner).sum() * SAH_C_NODE + (area * leaf * cnt).sum() * SAH_C_TRI
+    return float(total / a_root)
+
+
+def copy_bandwidth(torch, mib: int = 2048, reps: int = 5) -> float:
+    """GB/s of a device-to-device copy of `mib` MiB (bytes read + written)."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * n * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_threads() -> int:
     try:
         return len(os.sched_getaffinity(0))
@@ -132,7 +196,8 @@ def cpu_baseline_incoherent(scene, n_primary: int, seconds: float = 15.0) -> dic
         n += chunk.shape[0]
     sel = order[:n]
     res = {"tests": tests}
-    return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": cpu_threads(), "kind": "oracle",
+    return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": cpu_threads(), "cpu_model": cpu_model(),
+            "kind": "oracle",
             "sample": f"{n} rays ({int((sel < prim.shape[0]).sum())} camera + AO rays of {px.shape[0]} "
                       f"sampled pixels), FP64 brute force with exact bounding-sphere reject, "
                       f"{res['tests'] / n:.3g} triangle tests per ray, {dt:.1f} s",
@@ -149,8 +214,8 @@ def cpu_baseline_frame(scene, n_pixels: int = 256, seconds: float = 15.0) -> dic
     r = orc.render(px)
     dt = time.perf_counter() - t0
     n = int(r["nrays"].sum())
-    return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": cpu_threads(), "kind": "oracle",
-            "sample": f"{px.shape[0]} sampled pixels, whole ray trees ({n} rays), {dt:.1f} s"}
+    return {"value": n / dt / 1e6, "unit": "Mrays/s", "cores": cpu_threads(), "cpu_model": cpu_model(),
+            "kind": "oracle", "sample": f"{px.shape[0]} sampled pixels, whole ray trees ({n} rays), {dt:.1f} s"}
 
 
 def bench_incoherent(args, torch, rg, sg):
@@ -210,9 +275,14 @@ def bench_incoherent(args, torch, rg, sg):
     wall = time.perf_counter() - w0
     ms_step = e0.elapsed_time(e1) / args.steps
     rays_step = N + n_ao
-    # per-kernel times (events on the stream the kernels run on)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
-    t_prim, t_aogen, t_ao, t_any = [], [], [], []
+    # per-kernel times (events on the stream the kernels run on; torch's
+    # current stream, which the binding passes to every call).  The AO
+    # closest-hit call is the traversal kernel followed by the refinement of
+    # the reported t, u, v: the traversal alone is timed by asking for the
+    # hit identities only.
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+    ao_ids = {"inst": ao_hit_v["inst"], "prim": ao_hit_v["prim"]}
+    t_prim, t_aogen, t_ao, t_any, t_kern, t_ref = [], [], [], [], [], []
     for _ in range(args.steps):
         ev[0].record()
         rg.camera_rays(scene.camera, W, H, out=cam)
@@ -224,16 +294,22 @@ def bench_incoherent(args, torch, rg, sg):
         ev[3].record()
         rg.trace_any(tl, ao_c, occluded=ao_occ[:n_ao])
         ev[4].record()
+        rg.trace_closest(tl, ao_c, out=ao_ids)
+        ev[5].record()
         torch.cuda.synchronize()
         t_prim.append(ev[0].elapsed_time(ev[1]))
         t_aogen.append(ev[1].elapsed_time(ev[2]))
         t_ao.append(ev[2].elapsed_time(ev[3]))
         t_any.append(ev[3].elapsed_time(ev[4]))
-    t_prim, t_aogen, t_ao, t_any = (float(np.mean(x)) for x in (t_prim, t_aogen, t_ao, t_any))
+        t_kern.append(ev[4].elapsed_time(ev[5]))
+    t_prim, t_aogen, t_ao, t_any, t_kern = (float(np.mean(x)) for x in (t_prim, t_aogen, t_ao, t_any, t_kern))
     counts = rg.trace_counts(tl, ao_c).cpu().numpy()
     bytes_ao = algorithmic_bytes(counts, args.width)
-    achieved = bytes_ao / (t_ao * 1e-3) / 1e9
+    achieved = bytes_ao / (t_kern * 1e-3) / 1e9
     counts_p = rg.trace_counts(tl, cam).cpu().numpy()
+    copy_gbs = copy_bandwidth(torch)
+    blas_sah = [sah_cost(b.buf.cpu().numpy(), b.desc.nodes_off, b.desc.n_nodes, args.width) for b in tl.blas]
+    tlas_sah = sah_cost(tl.buf.cpu().numpy(), tl.desc.nodes_off, tl.desc.n_nodes, args.width)
     out = {
         "metric": "Mrays/s closest-hit (primary+incoherent)",
         "value": rays_step / (ms_step * 1e-3) / 1e6,
@@ -250,10 +326,15 @@ def bench_incoherent(args, torch, rg, sg):
                    "builder": args.builder},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(args),
-                     "kernel": "closest-hit traversal of the AO rays",
-                     "bytes_per_ray": bytes_ao / n_ao, "kernel_ms": t_ao,
+                     "kernel": "closest-hit traversal of the AO rays (k_trace<4,closest>)",
+                     "bytes_per_ray": bytes_ao / n_ao, "kernel_ms": t_kern,
+                     "copy_GBps": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                      "mean_nodes": float(counts[:, 0].mean()), "mean_tris": float(counts[:, 1].mean()),
-                     "mean_inst": float(counts[:, 2].mean())},
+                     "mean_inst": float(counts[:, 2].mean()),
+                     "sah_cost": {"bottom_mean": float(np.mean(blas_sah)), "bottom_min": float(np.min(blas_sah)),
+                                  "bottom_max": float(np.max(blas_sah)), "top": tlas_sah,
+                                  "c_node": SAH_C_NODE, "c_tri": SAH_C_TRI}},
+        "ao_closest_call_ms": t_ao, "ao_refine_ms": t_ao - t_kern,
         "primary_closest_mrays_s": N / (t_prim * 1e-3) / 1e6,
         "primary_mean_nodes": float(counts_p[:, 0].mean()),
         "ao_closest_mrays_s": n_ao / (t_ao * 1e-3) / 1e6,
@@ -783,6 +864,45 @@ def bench_serving(args, torch, rg, sg):
     return out, scenes
 
 
+def served_and_batched(args, torch, rg, sg) -> dict:
+    """The two serving forms measured on the same GPU, for the default run:
+    the batched workload (256 scenes, one batch against one rg_render per
+    frame) and the serving workload (64 resident scenes; saturated engine
+    against plain dispatch, p50 / p99 at 0.9 of plain dispatch's saturated
+    rate, 1,000 measured requests after 100 warm-up ones)."""
+    import copy
+    out = {}
+    b = copy.copy(args)
+    b.width, b.leaf, b.builder = SHAPES["batched"]
+    b.steps, b.warmup, b.scenes, b.autotune = 4, 1, 256, False
+    res, _ = bench_batched(b, torch, rg, sg)
+    out["batched"] = {k: res[k] for k in ("plain_mrays_s", "batched_mrays_s", "speedup", "plain_ms", "batched_ms",
+                                          "graph_ms", "images_identical")}
+    out["batched"]["workload"] = res["config"]["workload"]
+    out["batched"].update({k: res["config"][k] for k in ("frames", "pixels", "unique_tris", "rays_per_step")})
+    torch.cuda.empty_cache()
+    v = copy.copy(args)
+    v.width, v.leaf, v.builder = SHAPES["serving"]
+    v.rate_factors, v.plain_factors, v.requests, v.warm = [0.9], [0.9], 1000, 100
+    res, _ = bench_serving(v, torch, rg, sg)
+    sat = res["saturated"]
+    pts = {p["executor"]: p for p in res["points"]}
+    out["served"] = {
+        "workload": res["config"]["workload"],
+        "saturated_requests": sat["engine"]["requests"],
+        "saturated_engine_req_s": sat["engine"]["req_per_s"], "saturated_plain_req_s": sat["plain"]["req_per_s"],
+        "saturated_engine_mrays_s": sat["engine"]["mrays_s"], "saturated_plain_mrays_s": sat["plain"]["mrays_s"],
+        "speedup": sat["speedup"],
+        "rate_factor": 0.9, "rate_req_s": pts["engine"]["rate_req_s"],
+        "measured_requests": v.requests, "warm_requests": v.warm,
+        "engine_p50_ms": pts["engine"]["p50_ms"], "engine_p99_ms": pts["engine"]["p99_ms"],
+        "engine_mrays_s": pts["engine"]["mrays_s"],
+        "plain_p50_ms": pts["plain"]["p50_ms"], "plain_p99_ms": pts["plain"]["p99_ms"],
+    }
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -813,6 +933,8 @@ def main():
     ap.add_argument("--inst-batch", type=int, default=None,
                     help="lanes waiting at instance entries before a wave runs them")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving-forms", action="store_true",
+                    help="incoherent: skip the batched and served measurements that follow the main one")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the measurement, copy this many MiB once (a plain copy kernel of known "
@@ -838,6 +960,10 @@ def main():
         if not args.no_cpu_baseline:
             log("timing the oracle on a sample")
             out["cpu_baseline"] = cpu_baseline_incoherent(scene, 640, args.cpu_seconds)
+        if not args.no_serving_forms:
+            del scene
+            log("batched and served forms")
+            out.update(served_and_batched(args, torch, rg, sg))
     elif args.workload == "dynamic":
         out, scene = bench_dynamic(args, torch, rg, sg)
     elif args.workload == "post":
