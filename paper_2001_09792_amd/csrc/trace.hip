@@ -5,6 +5,36 @@
 
 namespace {
 
+// Results of finished rays are gathered per 64-ray packet in LDS and written
+// out packet by packet (one coalesced store per output array), instead of one
+// scattered store per ray and array whenever a ray finishes.  Each wave keeps
+// a ring of kStageSlots packets; a packet's slot is claimed when its first
+// ray is taken, filled as its rays finish (a bit per ray in the slot's mask),
+// and written out when all its rays are in.  A packet that still has a ray in
+// flight when its slot is needed again (a straggler) is written out as far as
+// it got; its late rays then store their results directly.
+constexpr int kStageSlots = 4;
+template <bool ANY, int MODE>
+struct StageShape {
+    // words per ray: closest hit (inst, prim); any hit (occluded, inst, prim);
+    // render closest hit (t, record, slot); render any hit (occluded)
+    static constexpr int K = MODE == rgt::kCounts ? 0
+                             : MODE == rgt::kRender ? (ANY ? 1 : 3)
+                                                    : (ANY ? 3 : 2);
+};
+// LDS bytes per wave of the staging ring
+template <int K>
+constexpr size_t stage_wave_bytes() {
+    return K == 0 ? 0 : (size_t)kStageSlots * (K * 64 * 4 + 16);
+}
+// Orders one wave's LDS accesses across lanes: a compiler fence at
+// wavefront scope and a wave barrier (the LDS serves a wave's accesses in
+// order).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Persistent traversal: each wave walks its own sequence of 64-ray packets
 // (packets wave, wave + waves, wave + 2 waves, ... so that every wave samples
 // the whole batch), and lanes whose ray has finished take the next rays of
@@ -13,14 +43,17 @@ namespace {
 template <int W, bool ANY, int MODE, bool OPT>
 __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refill, int lds_depth, int leaf_batch,
                                                          int inst_batch) {
-    extern __shared__ uint32_t lds_stack[];  // lds_depth * kThreads entries
+    constexpr int K = StageShape<ANY, MODE>::K;
+    extern __shared__ uint32_t lds_stack[];  // lds_depth * kThreads stack entries, then the staging rings
     const int lane = threadIdx.x & 63;
-    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     // a device count never exceeds the launch size (the queue capacity)
-    const int64_t n = a.count ? ((int64_t)*a.count < a.n ? (int64_t)*a.count : a.n) : a.n;
-    const int64_t n_packets = (n + 63) >> 6;
-    const int64_t wave = ((int64_t)blockIdx.x * rgt::kThreads + threadIdx.x) >> 6;
-    const int64_t n_waves = (int64_t)gridDim.x * (rgt::kThreads / 64);
+    // (a launch holds fewer than 2^31 rays: positions and indices fit 32 bits)
+    const uint32_t n = (uint32_t)(a.count ? ((int64_t)*a.count < a.n ? (int64_t)*a.count : a.n) : a.n);
+    const uint32_t n_packets = (n + 63) >> 6;
+    // wave-uniform values kept in scalar registers
+    const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave in the block
+    const uint32_t wave = blockIdx.x * (rgt::kThreads / 64) + wib;
+    const uint32_t n_waves = gridDim.x * (rgt::kThreads / 64);
     rgt::Tracer<W, ANY, MODE, OPT> tr;
     tr.tlas_nodes = reinterpret_cast<const RgNode<W> *>(a.nodes);
     tr.recs = a.recs;
@@ -32,25 +65,128 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
         tr.call_cull = a.ray_flags & (RG_RAY_CULL_BACK | RG_RAY_CULL_FRONT);
         tr.rmask = a.mask;
     }
-    int64_t next = 0;  // position in this wave's ray sequence (the same in all lanes)
-    uint32_t ray_i = 0;  // launches hold fewer than 2^31 rays
+    // this wave's staging ring: words [slot][K][64], owner [slot] (packet
+    // number in the wave's sequence, ~0u: free), mask [slot]
+    char RG_LDS *ring = (char RG_LDS *)&lds_stack[lds_depth * rgt::kThreads] + wib * stage_wave_bytes<K>();
+    uint32_t RG_LDS *sw = (uint32_t RG_LDS *)ring;
+    uint64_t RG_LDS *smask = (uint64_t RG_LDS *)(ring + kStageSlots * K * 64 * 4);
+    uint32_t RG_LDS *sown = (uint32_t RG_LDS *)(ring + kStageSlots * (K * 64 * 4 + 8));
+    if (K > 0) {
+        if (lane < kStageSlots) {
+            sown[lane] = ~0u;
+            smask[lane] = 0ull;
+        }
+        wave_sync();
+    }
+    uint32_t next = 0;   // position in this wave's ray sequence (the same in all lanes)
+    uint32_t ray_j = 0;  // position of this lane's ray in the sequence
     bool has = false;
-    // A finished ray's results stay in its lane until the lane takes its next
-    // ray (or the wave ends): writing them then puts the stores next to the
-    // new ray's loads, instead of making every round wait for stores.
+    // A finished ray's result stays in its lane until the next refill round
+    // (or the wave's end), where all finished lanes place theirs together.
     bool pend = false;
-    auto write_result = [&]() {
-        if (MODE == rgt::kCounts) {
-            a.counts[3 * (uint64_t)ray_i] = tr.h.n_nodes;
-            a.counts[3 * (uint64_t)ray_i + 1] = tr.h.n_tris;
-            a.counts[3 * (uint64_t)ray_i + 2] = tr.h.n_inst;
+    uint32_t stalled = 0u;  // rounds since a ray of this wave last finished or was taken
+    auto ray_index = [&](uint32_t j) -> uint32_t { return (wave + (j >> 6) * n_waves) * 64 + (j & 63); };
+    auto word = [&](int w) -> uint32_t {
+        if (MODE == rgt::kRender && !ANY) {
+            // the render's closest hits carry their float32 t to shading
+            if (w == 0) return __float_as_uint(tr.found ? tr.best : INFINITY);
+            return w == 1 ? tr.h.inst : tr.h.prim;
+        }
+        if (ANY) return w == 0 ? (tr.found ? 1u : 0u) : (w == 1 ? tr.h.inst : tr.h.prim);
+        return w == 0 ? tr.h.inst : tr.h.prim;
+    };
+    // word w of a ray goes to ...
+    auto store = [&](int w, uint32_t i, uint32_t v) {
+        if (MODE == rgt::kRender && !ANY) {
+            if (w == 0) { if (a.t) a.t[i] = __uint_as_float(v); }
+            else if (w == 1) { if (a.inst) a.inst[i] = v; }
+            else if (a.prim) a.prim[i] = v;
+        } else if (ANY) {
+            if (w == 0) { if (a.occluded) a.occluded[i] = (uint8_t)v; }
+            else if (w == 1) { if (a.inst) a.inst[i] = v; }
+            else if (a.prim) a.prim[i] = v;
         } else {
-            if (ANY && a.occluded) a.occluded[ray_i] = tr.found ? 1 : 0;
-            // the render's closest hits carry their float32 t to shading;
-            // the trace calls get t, u, v from k_refine
-            if (MODE == rgt::kRender && !ANY && a.t) a.t[ray_i] = tr.found ? tr.best : INFINITY;
-            if (a.inst) a.inst[ray_i] = tr.h.inst;
-            if (a.prim) a.prim[ray_i] = tr.h.prim;
+            if (w == 0) { if (a.inst) a.inst[i] = v; }
+            else if (a.prim) a.prim[i] = v;
+        }
+    };
+    auto write_result = [&]() {  // the visit counts: stored directly
+        const uint64_t i = ray_index(ray_j);
+        a.counts[3 * i] = tr.h.n_nodes;
+        a.counts[3 * i + 1] = tr.h.n_tris;
+        a.counts[3 * i + 2] = tr.h.n_inst;
+    };
+    // Writes slot s's staged rays (all lanes together; uniform arguments).
+    auto flush_slot = [&](int s, uint32_t q, uint64_t m) {
+        if ((m >> lane) & 1ull) {
+            const uint32_t i = ray_index(q * 64 + lane);
+#pragma unroll
+            for (int w = 0; w < K; ++w) store(w, i, sw[(s * K + w) * 64 + lane]);
+        }
+    };
+    // Rays of packet q (its first ray in the sequence at 64 q): 64, fewer
+    // for the batch's last packet.
+    auto full_mask = [&](uint32_t q) -> uint64_t {
+        const uint32_t first = (wave + q * n_waves) * 64;
+        const uint32_t cnt = n - first < 64u ? n - first : 64u;
+        return cnt >= 64u ? ~0ull : ((1ull << cnt) - 1ull);
+    };
+    // Places the results of lanes with `pend` (all lanes together), then
+    // writes out complete packets; with `all`, writes out every slot.
+    auto place = [&](bool all) {
+        const uint32_t q = ray_j >> 6;
+        const int s = (int)(q & (kStageSlots - 1));
+        if (pend) {
+            if (sown[s] == q) {
+#pragma unroll
+                for (int w = 0; w < K; ++w) sw[(s * K + w) * 64 + (ray_j & 63)] = word(w);
+                __hip_atomic_fetch_or(&smask[s], 1ull << (ray_j & 63), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WAVEFRONT);
+            } else {
+                const uint32_t i = ray_index(ray_j);  // a straggler's packet left the ring
+#pragma unroll
+                for (int w = 0; w < K; ++w) store(w, i, word(w));
+            }
+            pend = false;
+        }
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < kStageSlots; ++k) {
+            const uint32_t o = __builtin_amdgcn_readfirstlane(sown[k]);
+            if (o == ~0u) continue;
+            const uint64_t m = smask[k];
+            const uint64_t mu = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(m >> 32)) << 32) |
+                                __builtin_amdgcn_readfirstlane((uint32_t)m);
+            if (all || mu == full_mask(o)) {
+                flush_slot(k, o, mu);
+                wave_sync();
+                if (lane == 0) {
+                    sown[k] = ~0u;
+                    smask[k] = 0ull;
+                }
+                wave_sync();
+            }
+        }
+    };
+    // Claims the slots of the packets whose first ray is among the positions
+    // [p0, p0 + cnt) of the sequence (all lanes together).
+    auto claim = [&](uint32_t p0, uint32_t cnt) {
+        for (uint32_t q = (p0 + 63) >> 6; q * 64 < p0 + cnt; ++q) {
+            if (wave + q * n_waves >= n_packets) break;
+            const int k = (int)(q & (kStageSlots - 1));
+            const uint32_t o = __builtin_amdgcn_readfirstlane(sown[k]);
+            if (o != ~0u) {  // a straggler: write out what it has
+                const uint64_t m = smask[k];
+                const uint64_t mu = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(m >> 32)) << 32) |
+                                    __builtin_amdgcn_readfirstlane((uint32_t)m);
+                flush_slot(k, o, mu);
+                wave_sync();
+            }
+            if (lane == 0) {
+                sown[k] = (uint32_t)q;
+                smask[k] = 0ull;
+            }
+            wave_sync();
         }
     };
     while (true) {
@@ -58,19 +194,26 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
         // lanes together, so `next` stays uniform across the wave
         const uint64_t need = __ballot(!has);
         const int n_need = __popcll(need);
+        bool took = false;
         if (n_need >= refill) {
+            if (K > 0) {
+                place(false);
+                claim(next, (uint32_t)n_need);
+            }
             if (!has) {
-                int64_t j = next + __popcll(need & lt);
-                int64_t pkt = wave + (j >> 6) * n_waves;
-                int64_t idx = pkt * 64 + (j & 63);
+                // this lane's rank among the idle lanes
+                const uint32_t j = next + __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+                const uint32_t pkt = wave + (j >> 6) * n_waves;
+                const uint32_t idx = pkt * 64 + (j & 63);
                 if (pkt < n_packets && idx < n) {
-                    if (pend) write_result();
+                    if (K == 0 && pend) write_result();
                     rgt::Ray R;
                     R.o[0] = a.ray[0][idx]; R.o[1] = a.ray[1][idx]; R.o[2] = a.ray[2][idx];
                     R.d[0] = a.ray[3][idx]; R.d[1] = a.ray[4][idx]; R.d[2] = a.ray[5][idx];
                     R.tmin = a.ray[6][idx];
                     R.tmax = a.ray[7][idx];
-                    ray_i = (uint32_t)idx;
+                    ray_j = j;
                     if (MODE == rgt::kRender && a.ray_job) {  // only frames carry per-ray top levels
                         const RgTlasRef J = a.jobs[a.ray_job[idx]];
                         tr.tlas_nodes = reinterpret_cast<const RgNode<W> *>(J.nodes);
@@ -79,6 +222,7 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
                     has = tr.begin(R);
                     if (OPT) tr.rmask = a.ray_mask ? (uint32_t)a.ray_mask[idx] : a.mask;
                     pend = !has;  // empty interval: a miss without traversal
+                    took = true;
                 }
             }
             next += n_need;
@@ -101,12 +245,22 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
         uint32_t run = n_inner ? rgt::kUnitInner : 0u;
         if (n_leaf && (n_leaf >= leaf_batch || n_inner == 0)) run |= rgt::kUnitLeaf;
         if (n_inst && (n_inst >= inst_batch || run == 0)) run |= rgt::kUnitInst;
-        if ((run & my) != 0u && tr.step()) {  // my == 0 for lanes without a ray
+        const bool fin = (run & my) != 0u && tr.step();  // my == 0 for lanes without a ray
+        if (fin) {
             has = false;
             pend = true;
         }
+        // loop bound: a wave whose rays stop finishing (only a corrupt
+        // hierarchy can make a traversal cycle) gives up on them
+        if (__ballot(fin || took) != 0ull) {
+            stalled = 0u;
+        } else if (++stalled > rgt::kMaxSteps) {
+            if (has) pend = true;
+            has = false;
+        }
     }
-    if (pend) write_result();
+    if (K > 0) place(true);
+    else if (pend) write_result();
 }
 
 // The reported hit in double precision.  The traversal decides in float32
@@ -230,7 +384,10 @@ void launch_mode(bool any, int mode, const RgTraceArgs &a, hipStream_t st, unsig
 template <int W>
 rg_status launch_w(bool any, int mode, const RgTraceArgs &a, hipStream_t st, const rg_trace_tune &t) {
     unsigned blocks = persistent_blocks(a.n, t.waves_per_cu);
-    size_t shm = (size_t)t.lds_depth * rgt::kThreads * sizeof(uint32_t);
+    // the traversal stacks, then one staging ring per wave
+    const int K = mode == rgt::kCounts ? 0 : (mode == rgt::kRender ? (any ? 1 : 3) : (any ? 3 : 2));
+    size_t shm = (size_t)t.lds_depth * rgt::kThreads * sizeof(uint32_t) +
+                 (rgt::kThreads / 64) * (K == 0 ? 0 : (size_t)kStageSlots * (K * 64 * 4 + 16));
     if (a.opt) launch_mode<W, true>(any, mode, a, st, blocks, shm, t);
     else launch_mode<W, false>(any, mode, a, st, blocks, shm, t);
     RG_LAUNCH_CHECK();
@@ -257,8 +414,9 @@ bool set_opts(RgTraceArgs &a, const rg_trace_opts *o) {
     return true;
 }
 
-// rays per trace call: the kernels keep a ray's index in 32 bits
-constexpr int64_t kMaxRays = 0xFFFFFFFFll;
+// rays per trace call: the kernels keep a ray's index and its position in
+// the wave's sequence in 32 bits
+constexpr int64_t kMaxRays = 0x7FFFFFFFll;
 
 bool tlas_ok(const rg_tlas *t) {
     return t && t->buf && t->n_inst >= 1 && (t->width == 2 || t->width == 4 || t->width == 8);

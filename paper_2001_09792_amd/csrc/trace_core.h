@@ -29,7 +29,9 @@ constexpr int kPrivStack = 96;    // further entries per lane in private memory
 constexpr int kStackCap = 8 + kPrivStack;  // guaranteed capacity (at the smallest LDS depth, 8)
 constexpr uint32_t kSentinel = 0xFFFFFFFEu;
 constexpr uint32_t kFlip = 4u;  // in Tracer::cull: the instance flips its facing
-constexpr uint32_t kMaxSteps = 1u << 22;  // loop bound: far above any traversal of a valid hierarchy
+// rounds a wave may run without any of its rays finishing: far above any
+// traversal of a valid hierarchy (a loop bound, not a limit of the method)
+constexpr uint32_t kMaxSteps = 1u << 22;
 // The far distance of a slab is widened by 2 gamma_5 (gamma_n = n u / (1 - n u),
 // u = 2^-24): the subtraction, the hardware reciprocal (1 ulp) and the product
 // each add error to t, and the near distance may err the other way.
@@ -224,11 +226,11 @@ struct Tracer {
     float ox, oy, oz, ix, iy, iz;  // current frame: origin and reciprocal direction
     float t0, tlo, thi;         // slide of the frame's origin, interval in the frame
     const RgNode<W> *nodes;
-    const RgTri *tris;
+    uint32_t tri_off;           // the bottom level's triangles: nodes + 16 tri_off bytes
     uint32_t inst_id;
     Shear sh;
     Stack st;
-    uint32_t cur, steps;
+    uint32_t cur;
     uint32_t rmask;      // this ray's visibility mask
     uint32_t call_cull;  // RG_RAY_CULL_* of the launch
     uint32_t cull;       // culling in the current instance: RG_RAY_CULL_* | kFlip
@@ -255,8 +257,7 @@ struct Tracer {
         found = false;
         st.sp = 0;
         cur = 0;  // root inner node of the top level
-        steps = 0;
-        tris = nullptr;
+        tri_off = 0u;
         inst_id = 0;
         sh.kx = 0; sh.ky = 1; sh.kz = 2; sh.sx = sh.sy = 0.0f; sh.sz = 1.0f;
         cull = 0u;
@@ -286,7 +287,6 @@ struct Tracer {
     __device__ inline bool step() {
         bool done = false;
         bool pop = false;
-        ++steps;
         constexpr int kNodeU4 = (7 * W + 3) / 4;  // node bytes without padding, in 16 B
         constexpr int kWords = 4 * kNodeU4 > 28 ? 4 * kNodeU4 : 28;
         const bool inner = !rg_is_leaf(cur);
@@ -300,7 +300,7 @@ struct Tracer {
         // width 2 or 4; width 8 nodes load their second half separately.
         const char *addr = inner ? (const char *)nodes + (uint64_t)cur * sizeof(RgNode<W>)
                                  : (inst ? (const char *)recs + (uint64_t)lf * sizeof(RgInst)
-                                         : (const char *)tris + (uint64_t)lf * sizeof(RgTri));
+                                         : (const char *)nodes + 16ull * tri_off + (uint64_t)lf * sizeof(RgTri));
         uint32_t w[kWords];
         {
             const RG_GLOBAL rg_u4a8 *src = gptr<rg_u4a8>(addr);
@@ -404,7 +404,10 @@ struct Tracer {
             thi = best - t0;
             thi = thi + fabsf(thi) * 2.4e-7f;
             nodes = reinterpret_cast<const RgNode<W> *>((uint64_t)w[12] | ((uint64_t)w[13] << 32));
-            tris = reinterpret_cast<const RgTri *>((uint64_t)w[14] | ((uint64_t)w[15] << 32));
+            // both arrays lie in the bottom level's buffer, 256-byte aligned,
+            // the triangles after the nodes (at most 64 GB apart)
+            tri_off = (uint32_t)((((uint64_t)w[14] | ((uint64_t)w[15] << 32)) -
+                                  ((uint64_t)w[12] | ((uint64_t)w[13] << 32))) >> 4);
             inst_id = (MODE == kRender) ? lf : w[19];
             if (OPT) {
                 cull = (w[26] & RG_INST_CULL_DISABLE) ? 0u : call_cull;
@@ -431,7 +434,7 @@ struct Tracer {
                     for (int k = 0; k < 9; ++k) tri.v[k] = __uint_as_float(j == 0 ? w[k] : w[10 + k]);
                     tri.prim = j == 0 ? w[9] : w[19];
                 } else {
-                    tri = gload<RgTri, rg_u2>(tris, lf + j);
+                    tri = gload<RgTri, rg_u2>((const char *)nodes + 16ull * tri_off, lf + j);
                 }
                 float T, det, V, Wv;
                 if (!tri_test(tri, o3, sh, tlo, thi, T, det, V, Wv)) continue;
@@ -477,7 +480,7 @@ struct Tracer {
                 cur = e;
             }
         }
-        return done || steps > kMaxSteps;
+        return done;
     }
 };
 
