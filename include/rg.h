@@ -459,6 +459,33 @@ rg_status rg_render_ex(const rg_tlas *tlas, const rg_material *mats /*host*/, in
                        uint32_t *primary_mat, void *scratch, uint64_t scratch_bytes, void *stream,
                        rg_render_stats *stats /*host, nullable*/);
 
+/* Trace parity inside a render (verification): rg_render (mode 0) that also
+ * copies, after each pass k = 0..max_depth, that pass's queues to the caller:
+ * the closest-hit rays exactly as traced (float32, origin and direction of
+ * the secondary rays as spawned by shading), each one's float32 hit t and
+ * its hit as input indices, and the shadow rays with their any-hit result.
+ * So the traversal inside a render can be checked against an exact trace of
+ * the very rays it traced, apart from the drift of secondary rays.  Buffers
+ * (device): rays, shadow_rays float[max_depth + 1][8][capacity] (rows ox, oy,
+ * oz, dx, dy, dz, tmin, tmax); t float, inst, prim uint32 and occluded uint8
+ * [max_depth + 1][capacity]; counts uint32[max_depth + 1][2] = the pass's
+ * queued closest-hit and shadow rays (only the first `capacity` of each are
+ * copied).  The image is the same as rg_render's.  Asynchronous.
+ * Errors: RG_ERR_INVALID_ARG for NULL capture buffers or capacity < 1,
+ * otherwise as rg_render. */
+typedef struct {
+    int64_t capacity;
+    float *rays, *t;
+    uint32_t *inst, *prim;
+    float *shadow_rays;
+    uint8_t *occluded;
+    uint32_t *counts;
+} rg_capture;
+rg_status rg_render_capture(const rg_tlas *tlas, const rg_material *mats /*host*/, int32_t n_mats,
+                            const rg_camera *cam /*host*/, const rg_light *light /*host*/, int32_t width,
+                            int32_t height, int32_t max_depth, uint64_t seed, float *image, void *scratch,
+                            uint64_t scratch_bytes, const rg_capture *capture /*host*/, void *stream);
+
 /* ------------------------------------------------------- post-process */
 /* The frame's post-process passes (section 2.1: the engine's compute system
  * runs a screen-space roughness approximation and fast approximate
@@ -607,6 +634,11 @@ rg_status rg_engine_destroy(rg_engine *engine);
 /* Admits a frame (mode 0) if its reservation fits: writes its record and
  * materials through kernel arguments (job->mats may go away on return),
  * zeroes its accumulators and queues its camera rays for the next pass.
+ * Lifetime: the frame's top level, the bottom levels it refers to and its
+ * image are read and written by the engine's passes (on its stream and a
+ * side stream of its own) until rg_engine_poll returns the frame's tag; the
+ * caller must keep them allocated until then (a caching allocator that
+ * tracks streams does not see the engine's side stream).
  * *admitted = 0 when there is no room now (retry after a poll).  Errors:
  * RG_ERR_OUT_OF_MEMORY when the frame exceeds the whole engine,
  * RG_ERR_UNSUPPORTED for another node width or mode 1, RG_ERR_INVALID_ARG. */

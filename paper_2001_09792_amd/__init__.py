@@ -71,6 +71,11 @@ class Hits(ctypes.Structure):
     _fields_ = [("t", c_p), ("inst", c_p), ("prim", c_p), ("u", c_p), ("v", c_p)]
 
 
+class Capture(ctypes.Structure):
+    _fields_ = [("capacity", c_i64), ("rays", c_p), ("t", c_p), ("inst", c_p), ("prim", c_p),
+                ("shadow_rays", c_p), ("occluded", c_p), ("counts", c_p)]
+
+
 class Material(ctypes.Structure):
     _fields_ = [("type", c_i32), ("rgb", c_f * 3), ("ior", c_f)]
 
@@ -144,6 +149,7 @@ SIGNATURES = {
     "rg_render_ex": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_u64, c_p, c_p, c_p,
                              c_u64, c_p, c_p]),
     "rg_render_static": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_u64, c_p, c_p]),
+    "rg_render_capture": (c_i32, [c_p, c_p, c_i32, c_p, c_p, c_i32, c_i32, c_i32, c_u64, c_p, c_p, c_u64, c_p, c_p]),
     "rg_post_sizes": (c_i32, [c_i32, c_i32, c_p]),
     "rg_blas_set_alpha": (c_i32, [c_p, c_p, c_i32, c_p]),
     "rg_roughness_blur": (c_i32, [c_p, c_p, c_p, c_i32, c_i32, c_i32, c_i32, c_p, c_p, c_u64, c_p]),
@@ -716,6 +722,43 @@ class Batch:
         return self.images
 
 
+def render_capture(tlas: Tlas, mats, camera, light, width: int, height: int, max_depth: int, capacity: int,
+                   seed: int = 0, stream=None):
+    """rg_render_capture: renders a frame and keeps each pass's queues.
+    Returns (image [H, W, 3], passes), passes[k] a dict of CPU numpy arrays:
+    rays [m, 8] (the closest-hit rays as traced), t, inst, prim (their float32
+    t and input-index hits), shadow [s, 8] and occluded [s], counts (queued
+    closest-hit and shadow rays; m, s = min(count, capacity))."""
+    torch = _torch()
+    P = max_depth + 1
+    dev = "cuda"
+    rays = torch.empty((P, 8, capacity), dtype=torch.float32, device=dev)
+    t = torch.empty((P, capacity), dtype=torch.float32, device=dev)
+    inst = torch.empty((P, capacity), dtype=torch.int32, device=dev)
+    prim = torch.empty((P, capacity), dtype=torch.int32, device=dev)
+    srays = torch.empty((P, 8, capacity), dtype=torch.float32, device=dev)
+    occ = torch.empty((P, capacity), dtype=torch.uint8, device=dev)
+    counts = torch.zeros((P, 2), dtype=torch.int32, device=dev)
+    image = torch.empty((height, width, 3), dtype=torch.float32, device=dev)
+    scratch = _bytes(render_sizes(width, height, max_depth, 0), dev)
+    cap = Capture(capacity, _ptr(rays), _ptr(t), _ptr(inst), _ptr(prim), _ptr(srays), _ptr(occ), _ptr(counts))
+    ma = materials_array(mats)
+    cd, ld = camera_desc(camera), light_desc(light)
+    _check("rg_render_capture", _lib.rg_render_capture(tlas.ref, ma, len(mats), ctypes.byref(cd), ctypes.byref(ld),
+                                                       width, height, max_depth, seed, _ptr(image), _ptr(scratch),
+                                                       scratch.numel(), ctypes.byref(cap), _stream(stream)))
+    torch.cuda.synchronize()
+    cnt = counts.cpu().numpy().astype(np.int64)
+    R, T, I, Pm, S, O = (x.cpu().numpy() for x in (rays, t, inst, prim, srays, occ))
+    passes = []
+    for k in range(P):
+        m, sn = min(int(cnt[k, 0]), capacity), min(int(cnt[k, 1]), capacity)
+        passes.append(dict(rays=R[k, :, :m].T.copy(), t=T[k, :m], inst=I[k, :m].view(np.uint32),
+                           prim=Pm[k, :m].view(np.uint32), shadow=S[k, :, :sn].T.copy(), occluded=O[k, :sn],
+                           counts=(int(cnt[k, 0]), int(cnt[k, 1]))))
+    return image, passes
+
+
 STATIC_SCRATCH_BYTES = 64 << 20  # RG_STATIC_SCRATCH_BYTES
 
 
@@ -824,6 +867,11 @@ class Engine:
                                                          self.scratch.numel(), _stream(self.stream),
                                                          ctypes.byref(self.h)))
         self._tags = (c_i64 * 4096)()
+        # what the device reads or writes for each frame in flight (its top
+        # level and the bottom levels behind it, its image), held by tag until
+        # poll() returns the tag: the engine's side stream uses them after
+        # admit() returns, where torch's caching allocator cannot see it
+        self._held = {}
 
     @staticmethod
     def for_budget(budget_bytes: int, max_jobs: int = 64, max_mats: int = 256, width: int = 4) -> dict:
@@ -844,6 +892,8 @@ class Engine:
         j = job_struct(ctypes.addressof(tlas.desc), ma, cam, light, width, height, max_depth, _ptr(image))
         ok = c_i32()
         _check("rg_engine_admit", _lib.rg_engine_admit(self.h, ctypes.byref(j), tag, ctypes.byref(ok)))
+        if ok.value:
+            self._held[int(tag)] = (tlas, image)
         return bool(ok.value)
 
     def step(self) -> bool:
@@ -855,7 +905,10 @@ class Engine:
         n = c_i32()
         _check("rg_engine_poll", _lib.rg_engine_poll(self.h, 1 if wait else 0, self._tags, len(self._tags),
                                                      ctypes.byref(n)))
-        return [int(self._tags[i]) for i in range(n.value)]
+        done = [int(self._tags[i]) for i in range(n.value)]
+        for t in done:
+            self._held.pop(t, None)
+        return done
 
     def info(self) -> dict:
         i = EngineInfo()
@@ -870,7 +923,8 @@ class Engine:
     def close(self):
         if self.h:
             h, self.h = self.h, c_p()
-            _check("rg_engine_destroy", _lib.rg_engine_destroy(h))
+            _check("rg_engine_destroy", _lib.rg_engine_destroy(h))   # waits for the stream
+            self._held.clear()
 
     def __del__(self):
         try:

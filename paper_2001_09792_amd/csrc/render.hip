@@ -650,6 +650,50 @@ rg_status finish_stats(hipStream_t st, hipEvent_t e0, hipEvent_t e1, const unsig
     return RG_OK;
 }
 
+// Copies one pass's queues into a caller's capture buffers: the closest-hit
+// rays with their float32 t and their hit as input indices (the record's
+// instance, the leaf-order triangle's input index), and the shadow rays with
+// their any-hit result; the first `cap` entries of each, and both counts.
+struct CaptureArgs {
+    RgQueue q;
+    const float *hit_t;
+    const uint32_t *hit_rec, *hit_slot, *ccount;
+    RgShadowQ sq;
+    const uint32_t *scount;
+    RgTlasRef T;
+    int64_t cap;
+    int k;
+    rg_capture out;
+};
+
+__global__ void __launch_bounds__(kT) k_capture(CaptureArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    const int64_t nc = (int64_t)*a.ccount < a.cap ? (int64_t)*a.ccount : a.cap;
+    const int64_t ns = (int64_t)*a.scount < a.cap ? (int64_t)*a.scount : a.cap;
+    if (i == 0) {
+        a.out.counts[2 * a.k] = *a.ccount;
+        a.out.counts[2 * a.k + 1] = *a.scount;
+    }
+    const uint64_t base = (uint64_t)a.k * a.cap;
+    if (i < nc) {
+        for (int c = 0; c < 8; ++c) a.out.rays[(8 * (uint64_t)a.k + c) * a.cap + i] = a.q.ray[c][i];
+        a.out.t[base + i] = a.hit_t[i];
+        const uint32_t rec = a.hit_rec[i];
+        uint32_t inst = RG_MISS, prim = RG_MISS;
+        if (rec != RG_MISS) {
+            const RgInst &R = a.T.recs[rec];
+            inst = R.inst;
+            prim = reinterpret_cast<const RgTri *>(R.tris)[a.hit_slot[i]].prim;
+        }
+        a.out.inst[base + i] = inst;
+        a.out.prim[base + i] = prim;
+    }
+    if (i < ns) {
+        for (int c = 0; c < 8; ++c) a.out.shadow_rays[(8 * (uint64_t)a.k + c) * a.cap + i] = a.sq.ray[c][i];
+        a.out.occluded[base + i] = a.sq.occ[i];
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------ wavefront passes
@@ -955,7 +999,8 @@ rg_status rg_render(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats
 static rg_status render_impl(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats, const rg_camera *cam,
                              const rg_light *light, int32_t width, int32_t height, int32_t max_depth, int32_t mode,
                              uint64_t seed, float *image, uint32_t *primary_mat, void *scratch,
-                             uint64_t scratch_bytes, void *stream, rg_render_stats *stats);
+                             uint64_t scratch_bytes, void *stream, rg_render_stats *stats,
+                             const rg_capture *capture = nullptr);
 
 rg_status rg_render_ex(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats, const rg_camera *cam,
                        const rg_light *light, int32_t width, int32_t height, int32_t max_depth, int32_t mode,
@@ -966,10 +1011,23 @@ rg_status rg_render_ex(const rg_tlas *tlas, const rg_material *mats, int32_t n_m
                          (hipStream_t)stream);
 }
 
+rg_status rg_render_capture(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats, const rg_camera *cam,
+                            const rg_light *light, int32_t width, int32_t height, int32_t max_depth, uint64_t seed,
+                            float *image, void *scratch, uint64_t scratch_bytes, const rg_capture *capture,
+                            void *stream) {
+    if (!capture || capture->capacity < 1 || !capture->rays || !capture->t || !capture->inst || !capture->prim ||
+        !capture->shadow_rays || !capture->occluded || !capture->counts)
+        return RG_ERR_INVALID_ARG;
+    return rg_debug_done(render_impl(tlas, mats, n_mats, cam, light, width, height, max_depth, 0, seed, image,
+                                     nullptr, scratch, scratch_bytes, stream, nullptr, capture),
+                         (hipStream_t)stream);
+}
+
 static rg_status render_impl(const rg_tlas *tlas, const rg_material *mats, int32_t n_mats, const rg_camera *cam,
                              const rg_light *light, int32_t width, int32_t height, int32_t max_depth, int32_t mode,
                              uint64_t seed, float *image, uint32_t *primary_mat, void *scratch,
-                             uint64_t scratch_bytes, void *stream, rg_render_stats *stats) {
+                             uint64_t scratch_bytes, void *stream, rg_render_stats *stats,
+                             const rg_capture *capture) {
     if (!tlas_valid(tlas) || !mats || n_mats < 1 || n_mats > 256 || !cam || !light || !image || !scratch)
         return RG_ERR_INVALID_ARG;
     if (primary_mat && mode != 0) return RG_ERR_UNSUPPORTED;
@@ -1006,9 +1064,28 @@ static rg_status render_impl(const rg_tlas *tlas, const rg_material *mats, int32
         if ((r = rg_wave_reset(b, st)) != RG_OK) return r;
         if ((r = rg_wave_put_job(b, 0, J, T, mats, n_mats, st)) != RG_OK) return r;
         if ((r = rg_wave_camera(b, 0, J, 0, st)) != RG_OK) return r;
-        for (int k = 0; k <= max_depth; ++k)
+        for (int k = 0; k <= max_depth; ++k) {
             if ((r = rg_wave_pass(b, tlas->width, k, n << k, st, RG_TUNE_FRAME, tlas->has_inst_flags != 0)) != RG_OK)
                 return r;
+            if (capture) {
+                // pass k's queues, before pass k + 1 reuses them
+                CaptureArgs ca;
+                ca.q = b.q[k & 1];
+                ca.hit_t = b.hit_t;
+                ca.hit_rec = b.hit_rec;
+                ca.hit_slot = b.hit_slot;
+                ca.ccount = b.counts + (k & 1);
+                ca.sq = b.sq;
+                ca.scount = b.counts + 2;
+                ca.T = T;
+                ca.cap = capture->capacity;
+                ca.k = k;
+                ca.out = *capture;
+                const int64_t m = (n << k) < capture->capacity ? (n << k) : capture->capacity;
+                k_capture<<<rg_blocks(m, kT), kT, 0, st>>>(ca);
+                RG_LAUNCH_CHECK();
+            }
+        }
         if ((r = rg_wave_resolve(b, J, st)) != RG_OK) return r;
         if (stats) return finish_stats(st, e0, e1, b.stat, stats);
         return RG_OK;

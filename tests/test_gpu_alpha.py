@@ -100,8 +100,8 @@ def test_parity_with_the_oracle(builder, width, leaf):
             h = parity.hits_to_numpy(rg.trace_closest(tl, rd, **kw))
             occ = rg.trace_any(tl, rd, **kw).cpu().numpy()
             okw = dict(cull=cull, ray_mask=rm_np if per_ray else None)
-            res = parity.check_closest(h, orc.trace(rays, **okw), 0.04, label)
-            parity.check_any(occ, orc.trace(rays, any_hit=True, **okw), 0.04, label)
+            res = parity.check_closest(h, orc.trace(rays, **okw), 0.002, label)
+            parity.check_any(occ, orc.trace(rays, any_hit=True, **okw), 0.002, label)
             assert np.array_equal(occ != 0, h["inst"].astype(np.uint32) != 0xFFFFFFFF)
             print(f"  {res}", flush=True)
 
@@ -149,7 +149,7 @@ def test_render_with_opacity_masks_matches_oracle():
     img = rg.render(tl, sc.materials, sc.camera, sc.light, sc.width, sc.height, sc.max_depth).cpu().numpy()
     px = sg.sample_pixels(sc.width, sc.height, 800, 51)
     ref = oracle.Scene(sc, sphere_reject=True, alpha=alpha).render(px)
-    print(parity.check_image(img.reshape(-1, 3)[px], ref, 0.06, "alpha render"), flush=True)
+    print(parity.check_image(img.reshape(-1, 3)[px], ref, 0.045, "alpha render"), flush=True)
     plain = rg.render(rg.upload_scene(sc, 4, 1), sc.materials, sc.camera, sc.light, sc.width, sc.height,
                       sc.max_depth).cpu().numpy()
     assert not np.array_equal(img, plain)
@@ -178,8 +178,8 @@ def test_masks_survive_a_refit():
     rd = rg.rays_to_device(rays)
     orc = oracle.Scene(scene_from_meshes([moved]), alpha=[(masks, 2)])
     print("[alpha refit]", flush=True)
-    res = parity.check_closest(parity.hits_to_numpy(rg.trace_closest(tl, rd)), orc.trace(rays), 0.04, "alpha refit")
-    parity.check_any(rg.trace_any(tl, rd).cpu().numpy(), orc.trace(rays, any_hit=True), 0.04, "alpha refit any")
+    res = parity.check_closest(parity.hits_to_numpy(rg.trace_closest(tl, rd)), orc.trace(rays), 0.003, "alpha refit")
+    parity.check_any(rg.trace_any(tl, rd).cpu().numpy(), orc.trace(rays, any_hit=True), 0.003, "alpha refit any")
     print(f"  {res}", flush=True)
 
 

@@ -65,7 +65,7 @@ def test_refit_to_moved_vertices_holds_the_new_mesh(width, leaf, builder):
                            sg.rays_through_points(cen[rng.integers(0, cen.shape[0], 3000)], 9, 3.0)])
     h = parity.hits_to_numpy(rg.trace_closest(tl, rg.rays_to_device(rays)))
     oc = oracle.Scene(scene_from_meshes([moved])).trace(rays)
-    print(parity.check_closest(h, oc, 0.02, "refit moved"), flush=True)
+    print(parity.check_closest(h, oc, 0.002, "refit moved"), flush=True)
 
 
 def _moved_two_level(t):
@@ -108,7 +108,7 @@ def test_refitted_scene_traces_like_a_fresh_build(builder):
     px = sg.sample_pixels(sc.width, sc.height, 800, 13)
     ref = oracle.Scene(fresh_scene, sphere_reject=True).render(px, width=sc.width, height=sc.height,
                                                                max_depth=sc.max_depth)
-    print(parity.check_image(img.cpu().numpy().reshape(-1, 3)[px], ref, 0.04, "refit render"), flush=True)
+    print(parity.check_image(img.cpu().numpy().reshape(-1, 3)[px], ref, 0.015, "refit render"), flush=True)
 
 
 @pytest.mark.parametrize("width", [2, 4, 8])

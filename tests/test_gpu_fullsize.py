@@ -59,10 +59,10 @@ def test_incoherent_workload_at_full_size():
         h = parity.hits_to_numpy(rg.trace_closest(tl, d))
         _check_tiles(h, rays.shape[0], label)
         first = {k: v[: rays.shape[0]] for k, v in h.items()}
-        res = parity.check_closest(first, orc.trace(rays), 0.03, f"full-size {label}")
+        res = parity.check_closest(first, orc.trace(rays), 0.006, f"full-size {label}")
         occ = rg.trace_any(tl, d).cpu().numpy()
         assert np.array_equal(occ[: rays.shape[0]], occ[rays.shape[0]: 2 * rays.shape[0]])
-        parity.check_any(occ[: rays.shape[0]], orc.trace(rays, any_hit=True), 0.03, f"full-size {label} any")
+        parity.check_any(occ[: rays.shape[0]], orc.trace(rays, any_hit=True), 0.006, f"full-size {label} any")
         print(f"  {res}", flush=True)
         del d
         torch.cuda.empty_cache()
@@ -106,13 +106,13 @@ def test_options_workload_at_full_size():
     _check_tiles(h, k, "options ao")
     first = {key: v[:k] for key, v in h.items()}
     ref = orc.trace(aor, mask=0x02, cull=oracle.RAY_CULL_BACK)
-    res = parity.check_closest(first, ref, 0.03, "full-size options ao")
+    res = parity.check_closest(first, ref, 0.008, "full-size options ao")
     # the options change the answer: the plain oracle finds hits they remove
     plain_hit = oracle.Scene(scene, sphere_reject=True).trace(aor)["hit"] == 1
     assert (plain_hit & (ref["hit"] == 0)).sum() > 0.05 * plain_hit.sum()
     occ = rg.trace_any(opt, d, mask=0x02, cull=rg.RAY_CULL_BACK).cpu().numpy()
     assert np.array_equal(occ[:k], occ[k: 2 * k])
-    parity.check_any(occ[:k], orc.trace(aor, any_hit=True, mask=0x02, cull=oracle.RAY_CULL_BACK), 0.03,
+    parity.check_any(occ[:k], orc.trace(aor, any_hit=True, mask=0x02, cull=oracle.RAY_CULL_BACK), 0.008,
                      "full-size options any")
     print(f"  {res}", flush=True)
 
@@ -128,4 +128,4 @@ def test_two_level_frame_at_full_size():
     img = img.cpu().numpy().reshape(-1, 3)
     px = sg.sample_pixels(sc.width, sc.height, 400, 72)
     ref = oracle.Scene(sc, sphere_reject=True).render(px)
-    print(parity.check_image(img[px], ref, 0.04, "full-size two-level"), flush=True)
+    print(parity.check_image(img[px], ref, 0.01, "full-size two-level"), flush=True)

@@ -145,8 +145,8 @@ def test_parity_with_the_oracle_under_every_option(builder, width, leaf):
             okw = dict(cull=cull, mask=mask, ray_mask=rm_np if per_ray else None)
             oc = orc.trace(rays, **okw)
             oa = orc.trace(rays, any_hit=True, **okw)
-            sc_ = parity.check_closest(h, oc, 0.03, label)
-            parity.check_any(occ, oa, 0.03, label)
+            sc_ = parity.check_closest(h, oc, 0.002, label)
+            parity.check_any(occ, oa, 0.002, label)
             assert np.array_equal(occ != 0, h["inst"].astype(np.uint32) != 0xFFFFFFFF)
             if cull == rg.RAY_CULL_BACK | rg.RAY_CULL_FRONT:
                 # culled everywhere except in the cull-disabled instances
@@ -199,7 +199,7 @@ def test_hidden_instances_leave_the_frame_as_if_absent():
     px = sg.sample_pixels(sc.width, sc.height, 800, 41)
     ref = oracle.Scene(sc, sphere_reject=True, inst_flags=flags).render(px, width=sc.width, height=sc.height,
                                                                           max_depth=sc.max_depth)
-    print(parity.check_image(img.reshape(-1, 3)[px], ref, 0.04, "masked render"), flush=True)
+    print(parity.check_image(img.reshape(-1, 3)[px], ref, 0.01, "masked render"), flush=True)
 
 
 def _flagged_frames():

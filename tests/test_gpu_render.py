@@ -71,7 +71,7 @@ def test_small_config_full_frame():
     img, st = _render(sc)
     assert st["rays_traced"] >= sc.width * sc.height
     ref = oracle.Scene(sc).render()
-    res = parity.check_image(img, ref, 0.005, "small frame")
+    res = parity.check_image(img, ref, 0.002, "small frame")
     print(res, flush=True)
     img2, _ = _render(sc)
     assert np.array_equal(img, img2), "fixed-point sums make frames bitwise reproducible"
@@ -85,7 +85,7 @@ def test_two_level_frame_sampled(D):
     img, st = _render(sc)
     px = sg.sample_pixels(W, H, 1500, 11)
     ref = oracle.Scene(sc, sphere_reject=True).render(px)
-    res = parity.check_image(img[px], ref, 0.04, f"two-level D={D}")
+    res = parity.check_image(img[px], ref, 0.025, f"two-level D={D}")
     print(res, st, flush=True)
 
 
@@ -97,7 +97,7 @@ def test_ao_frame_sampled():
     assert np.all((img == 1.0) | (np.abs(img * 8 - np.round(img * 8)) < 1e-6))
     px = sg.sample_pixels(W, H, 1500, 12)
     ref = oracle.Scene(sc, sphere_reject=True).render(px)
-    res = parity.check_image(img[px], ref, 0.02, "ao")
+    res = parity.check_image(img[px], ref, 0.008, "ao")
     print(res, st, flush=True)
 
 

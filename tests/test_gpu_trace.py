@@ -38,14 +38,14 @@ def _trace(tl, rays_np, with_found=False):
     return h, occ
 
 
-def _both(scene, rays_np, label, max_amb=0.02, width=4, leaf=4, sphere=False, builder="lbvh"):
+def _both(scene, rays_np, label, max_amb=0.002, width=4, leaf=4, sphere=False, builder="lbvh"):
     print(f"[trace] {label}: {rays_np.shape[0]} rays W={width} L={leaf} {builder}", flush=True)
     tl = _upload(scene, width, leaf, builder)
     h, occ, found = _trace(tl, rays_np, with_found=True)
     orc = oracle.Scene(scene, sphere_reject=sphere)
     oc = orc.trace(rays_np)
     oa = orc.trace(rays_np, any_hit=True)
-    sc = parity.check_closest(h, oc, max_amb, label)
+    sc = parity.check_closest(h, oc, max_amb, label, orc=orc, rays=rays_np)
     sa = parity.check_any(occ, oa, max_amb, label)
     sf = parity.check_found(found, occ, rays_np, orc, oa, label)
     # GPU-internal invariants: occluded == a closest hit exists; the closest
@@ -268,7 +268,7 @@ def test_ao_rays_match_oracle():
     sel = np.arange(0, n_ao, max(1, n_ao // 4000))
     h = parity.hits_to_numpy(rg.trace_closest(tl, rg.rays_to_device(rays_ao[sel])))
     oc = orc.trace(rays_ao[sel])
-    print(parity.check_closest(h, oc, 0.03, "ao"), flush=True)
+    print(parity.check_closest(h, oc, 0.002, "ao"), flush=True)
     torch.cuda.synchronize()
 
 
