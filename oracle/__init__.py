@@ -32,7 +32,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rg_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# RG_ORACLE_LIBRARY names another build of rg_oracle.c (the sanitizer build
+# made by tests/run_sanitizers.py); build() leaves it alone
+_LIB = os.environ.get("RG_ORACLE_LIBRARY") or os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
 
@@ -45,6 +47,8 @@ INST_CULL_DISABLE, INST_FLIP_FACING = 1 << 8, 1 << 9
 
 def build(force: bool = True) -> str:
     """Compile the C oracle with gcc (plain -O2, no fast-math, no contraction)."""
+    if os.environ.get("RG_ORACLE_LIBRARY"):
+        return _LIB
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fno-fast-math",

@@ -20,7 +20,9 @@ import numpy as np
 import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librg.so")
+# RG_LIBRARY names another build of the same sources (the sanitizer build of
+# the host code used by tests/run_sanitizers.py)
+LIB_PATH = os.environ.get("RG_LIBRARY") or os.path.join(_HERE, "librg.so")
 
 RG_OK = 0
 MISS = 0xFFFFFFFF
