@@ -128,24 +128,30 @@ __device__ inline uint64_t spread21(uint64_t x) {
     return x;
 }
 
-__global__ void k_morton(const float *__restrict__ box, int64_t n, const uint32_t *__restrict__ bounds,
-                         uint64_t *__restrict__ keys, uint32_t *__restrict__ ids) {
+// The key of one primitive box from the centre bounds (order-preserving
+// uints: lo[0..2], hi[3..5]).
+__device__ inline uint64_t morton_key(const float *__restrict__ b, const uint32_t *bounds) {
 #pragma clang fp contract(off)
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
     uint64_t q[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         float lo = rg_ord2f(bounds[k]), hi = rg_ord2f(bounds[3 + k]);
         float ext = hi - lo;
         float s = ext > 0.0f ? 2097152.0f / ext : 0.0f;
-        float c = (box[6 * i + k] + box[6 * i + 3 + k]) * 0.5f;
+        float c = (b[k] + b[3 + k]) * 0.5f;
         float x = (c - lo) * s;
         x = floorf(x);
         uint64_t v = (x > 0.0f) ? (uint64_t)x : 0ull;  // NaN -> 0
         q[k] = v > 2097151ull ? 2097151ull : v;
     }
-    keys[i] = (spread21(q[0]) << 2) | (spread21(q[1]) << 1) | spread21(q[2]);
+    return (spread21(q[0]) << 2) | (spread21(q[1]) << 1) | spread21(q[2]);
+}
+
+__global__ void k_morton(const float *__restrict__ box, int64_t n, const uint32_t *__restrict__ bounds,
+                         uint64_t *__restrict__ keys, uint32_t *__restrict__ ids) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = morton_key(box + 6 * i, bounds);
     ids[i] = (uint32_t)i;
 }
 
@@ -269,19 +275,19 @@ __global__ void __launch_bounds__(kThreads) k_sort_scatter(
 }
 
 // ------------------------------------------------- 4. Karras hierarchy
-__device__ inline int k_delta(const uint64_t *__restrict__ k, int64_t n, int64_t i, int64_t j) {
+__device__ inline int k_delta(const uint64_t *k, int64_t n, int64_t i, int64_t j) {
     if (j < 0 || j >= n) return -1;
     uint64_t a = k[i], b = k[j];
     if (a == b) return 64 + __clz((int)((uint32_t)i ^ (uint32_t)j));
     return __clzll((long long)(a ^ b));
 }
 
-__global__ void k_karras(const uint64_t *__restrict__ keys, int64_t n, int32_t *__restrict__ left,
-                         int32_t *__restrict__ right, int32_t *__restrict__ parent_int,
-                         int32_t *__restrict__ parent_leaf, int32_t *__restrict__ first,
-                         int32_t *__restrict__ last) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n - 1) return;
+// Inner node i of the radix tree over n sorted keys (keys may be in LDS):
+// its children (>= 0 inner, < 0 leaf -(j+1)), parent links and leaf range.
+__device__ inline void karras_node(const uint64_t *keys, int64_t n, int64_t i, int32_t *__restrict__ left,
+                                   int32_t *__restrict__ right, int32_t *__restrict__ parent_int,
+                                   int32_t *__restrict__ parent_leaf, int32_t *__restrict__ first,
+                                   int32_t *__restrict__ last) {
     int d = (k_delta(keys, n, i, i + 1) - k_delta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
     int dmin = k_delta(keys, n, i, i - d);
     int64_t lmax = 2;
@@ -318,6 +324,15 @@ __global__ void k_karras(const uint64_t *__restrict__ keys, int64_t n, int32_t *
     if (i == 0) parent_int[0] = -1;
 }
 
+__global__ void k_karras(const uint64_t *__restrict__ keys, int64_t n, int32_t *__restrict__ left,
+                         int32_t *__restrict__ right, int32_t *__restrict__ parent_int,
+                         int32_t *__restrict__ parent_leaf, int32_t *__restrict__ first,
+                         int32_t *__restrict__ last) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    karras_node(keys, n, i, left, right, parent_int, parent_leaf, first, last);
+}
+
 // -------------------------------------------------------- 5. box refit
 // Inner boxes are computed level by level from the root's depth order
 // (k_boxes_at below), after k_leaf_boxes has gathered the leaf boxes.
@@ -331,11 +346,106 @@ __device__ inline float surface_area(const float *b) {
 constexpr int kCollapseRing = 16;   // per-level bookkeeping slots on the device
 constexpr int kCollapseBatch = 4;   // levels launched between host reads (< kCollapseRing - 2)
 
+// The children of the wide node that stands for binary inner node b: b's
+// two children, then repeatedly the inner one of largest surface area opened
+// into its two children, up to W (each candidate's area computed once, when
+// it joins).  C[k] >= 0 an inner node, < 0 leaf -(j+1).  Returns the count.
+template <int W>
+__device__ inline int collapse_children(int32_t b, const int32_t *__restrict__ left,
+                                        const int32_t *__restrict__ right, const float *__restrict__ int_box,
+                                        int32_t C[W]) {
+    float A[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        C[k] = -1;
+        A[k] = -1.0f;
+    }
+    C[0] = left[b];
+    C[1] = right[b];
+    int m = 2;
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+        if (C[k] >= 0) A[k] = surface_area(int_box + 6 * (int64_t)C[k]);
+    while (m < W) {
+        int best = -1;
+        float bsa = -1.0f;
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            if (k < m && C[k] >= 0 && A[k] > bsa) {
+                bsa = A[k];
+                best = k;
+            }
+        if (best < 0) break;
+        int32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < W; ++k)
+            if (k == best) c = C[k];
+        const int32_t l = left[c], r = right[c];
+        const float al = l >= 0 ? surface_area(int_box + 6 * (int64_t)l) : -1.0f;
+        const float ar = r >= 0 ? surface_area(int_box + 6 * (int64_t)r) : -1.0f;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            if (k == best) {
+                C[k] = l;
+                A[k] = al;
+            }
+            if (k == m) {
+                C[k] = r;
+                A[k] = ar;
+            }
+        }
+        ++m;
+    }
+    return m;
+}
+
+// Links of the m children: a leaf (a binary leaf, or an inner node whose
+// range holds at most leaf_max primitives), RG_EMPTY past m; returns the
+// mask of the children that stay inner nodes (their links set by the caller).
+template <int W>
+__device__ inline uint32_t collapse_links(const int32_t C[W], int m, const int32_t *__restrict__ first,
+                                          const int32_t *__restrict__ last, int leaf_max, uint32_t link[W]) {
+    uint32_t inner = 0u;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        link[k] = RG_EMPTY;
+        if (k >= m) continue;
+        const int32_t c = C[k];
+        if (c < 0) {
+            link[k] = rg_leaf((uint32_t)(-c - 1), 1u);
+        } else {
+            const int32_t f = first[c], size = last[c] - f + 1;
+            if (size <= leaf_max) link[k] = rg_leaf((uint32_t)f, (uint32_t)size);
+            else inner |= 1u << k;
+        }
+    }
+    return inner;
+}
+
+// Writes a wide node: the children's boxes (empty slots inverted) and links.
+template <int W>
+__device__ inline void write_wide_node(RgNode<W> *nd, const int32_t C[W], int m, const uint32_t link[W],
+                                       const float *__restrict__ int_box, const float *__restrict__ leaf_box) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        if (k >= m) {
+            nd->lo_x[k] = INFINITY; nd->lo_y[k] = INFINITY; nd->lo_z[k] = INFINITY;
+            nd->hi_x[k] = -INFINITY; nd->hi_y[k] = -INFINITY; nd->hi_z[k] = -INFINITY;
+        } else {
+            const int32_t c = C[k];
+            const float *b = c < 0 ? leaf_box + 6 * (int64_t)(-c - 1) : int_box + 6 * (int64_t)c;
+            nd->lo_x[k] = b[0]; nd->lo_y[k] = b[1]; nd->lo_z[k] = b[2];
+            nd->hi_x[k] = b[3]; nd->hi_y[k] = b[4]; nd->hi_z[k] = b[5];
+        }
+        nd->child[k] = link[k];
+        nd->pad[k] = 0u;
+    }
+}
+
 // One thread per node of the level (queue items: node index, binary node it
-// stands for).  Its children are opened largest-area first up to W; each
-// candidate's area is computed once, when it joins.  Children that stay
-// inner nodes join the next level's queue: one counter add per wave, and a
-// child's node index is the next level's first index plus its queue slot.
+// stands for).  Children that stay inner nodes join the next level's queue:
+// one counter add per wave, and a child's node index is the next level's
+// first index plus its queue slot.
 template <int W>
 __global__ void k_collapse(const int32_t *__restrict__ left, const int32_t *__restrict__ right,
                            const int32_t *__restrict__ first, const int32_t *__restrict__ last,
@@ -363,69 +473,14 @@ __global__ void k_collapse(const int32_t *__restrict__ left, const int32_t *__re
         const uint32_t qi = base + threadIdx.x;
         const bool active = qi < cnt;
         int32_t C[W];
-        float A[W];
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-            C[k] = -1;
-            A[k] = -1.0f;
-        }
         uint2 item = make_uint2(0u, 0u);
         int m = 0;
         if (active) {
             item = q_in[qi];
-            C[0] = left[item.y];
-            C[1] = right[item.y];
-            m = 2;
-#pragma unroll
-            for (int k = 0; k < 2; ++k)
-                if (C[k] >= 0) A[k] = surface_area(int_box + 6 * (int64_t)C[k]);
-            while (m < W) {
-                int best = -1;
-                float bsa = -1.0f;
-#pragma unroll
-                for (int k = 0; k < W; ++k)
-                    if (k < m && C[k] >= 0 && A[k] > bsa) {
-                        bsa = A[k];
-                        best = k;
-                    }
-                if (best < 0) break;
-                int32_t c = 0;
-#pragma unroll
-                for (int k = 0; k < W; ++k)
-                    if (k == best) c = C[k];
-                const int32_t l = left[c], r = right[c];
-                const float al = l >= 0 ? surface_area(int_box + 6 * (int64_t)l) : -1.0f;
-                const float ar = r >= 0 ? surface_area(int_box + 6 * (int64_t)r) : -1.0f;
-#pragma unroll
-                for (int k = 0; k < W; ++k) {
-                    if (k == best) {
-                        C[k] = l;
-                        A[k] = al;
-                    }
-                    if (k == m) {
-                        C[k] = r;
-                        A[k] = ar;
-                    }
-                }
-                ++m;
-            }
+            m = collapse_children<W>((int32_t)item.y, left, right, int_box, C);
         }
-        // which children stay inner nodes
         uint32_t link[W];
-        uint32_t inner = 0u;
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-            link[k] = RG_EMPTY;
-            if (k >= m) continue;
-            const int32_t c = C[k];
-            if (c < 0) {
-                link[k] = rg_leaf((uint32_t)(-c - 1), 1u);
-            } else {
-                const int32_t f = first[c], size = last[c] - f + 1;
-                if (size <= leaf_max) link[k] = rg_leaf((uint32_t)f, (uint32_t)size);
-                else inner |= 1u << k;
-            }
-        }
+        const uint32_t inner = active ? collapse_links<W>(C, m, first, last, leaf_max, link) : 0u;
         // queue slots: an exclusive scan of the inner-child counts over the wave
         const uint32_t nc = __popc(inner);
         uint32_t incl = nc;
@@ -453,21 +508,7 @@ __global__ void k_collapse(const int32_t *__restrict__ left, const int32_t *__re
             ++slot;
         }
         if (!active) continue;
-        RgNode<W> *nd = nodes + item.x;
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-            if (k >= m) {
-                nd->lo_x[k] = INFINITY; nd->lo_y[k] = INFINITY; nd->lo_z[k] = INFINITY;
-                nd->hi_x[k] = -INFINITY; nd->hi_y[k] = -INFINITY; nd->hi_z[k] = -INFINITY;
-            } else {
-                const int32_t c = C[k];
-                const float *b = c < 0 ? leaf_box + 6 * (int64_t)(-c - 1) : int_box + 6 * (int64_t)c;
-                nd->lo_x[k] = b[0]; nd->lo_y[k] = b[1]; nd->lo_z[k] = b[2];
-                nd->hi_x[k] = b[3]; nd->hi_y[k] = b[4]; nd->hi_z[k] = b[5];
-            }
-            nd->child[k] = link[k];
-            nd->pad[k] = 0u;
-        }
+        write_wide_node<W>(nodes + item.x, C, m, link, int_box, leaf_box);
     }
 }
 
@@ -494,6 +535,204 @@ __global__ void k_collapse_init(uint2 *q, uint32_t *ring, uint32_t *parents) {
     for (int k = 0; k <= 2 * kCollapseRing; ++k) ring[k] = 0u;
     ring[0] = 1u;  // level 0: the root, node 0
     if (parents) parents[0] = RG_MISS;  // the root
+}
+
+// ------------------------------------- whole build in one workgroup
+// For up to kSmallMax primitives (top levels, small meshes) the steps above
+// run in one workgroup of one launch, the keys in LDS: the same centre
+// bounds and Morton codes, a bitonic sort by (key, input index) -- the order
+// of the stable sort --, the same radix tree and box unions (boxes round by
+// round: a node's box once both children's are known), and the same wide
+// collapse level by level (a queue slot per inner child from an LDS
+// counter).  No host step in between; the result summary goes to `res`.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallMax = 4096;
+struct SmallResult {
+    uint32_t depth, n_nodes, err, pad;
+    float lo[3], hi[3];
+};
+
+struct SmallArgs {
+    const float *prim_box;
+    int32_t n, leaf_max;
+    uint64_t *keys_out;             // sorted keys (nullable: only for the stage check)
+    uint32_t *ids;                  // sorted primitive order
+    int32_t *left, *right, *pint, *pleaf, *first, *last;
+    float *int_box, *leaf_box;
+    uint2 *q[2];
+    void *nodes;                    // nullable: binary hierarchy only
+    uint32_t *parents, *levels;     // nullable
+    SmallResult *res;
+};
+
+template <int W>
+__global__ void __launch_bounds__(kSmallThreads) k_small_build(SmallArgs a) {
+    __shared__ uint64_t key[kSmallMax];
+    __shared__ uint32_t id[kSmallMax];
+    __shared__ uint32_t bnd[6];
+    __shared__ uint32_t done[2][kSmallMax / 32];
+    __shared__ uint32_t qcount, lstart[RG_LEVELS_CAP + 2];
+    const int t = threadIdx.x, n = a.n;
+    if (t < 3) bnd[t] = 0xFFFFFFFFu;
+    else if (t < 6) bnd[t] = 0u;
+    for (int i = t; i < kSmallMax / 32; i += kSmallThreads) done[0][i] = done[1][i] = 0u;
+    __syncthreads();
+    // centre bounds (exact min / max, any order)
+    for (int i = t; i < n; i += kSmallThreads) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float c = (a.prim_box[6 * i + k] + a.prim_box[6 * i + 3 + k]) * 0.5f;
+            atomicMin(&bnd[k], rg_f2ord(c));
+            atomicMax(&bnd[3 + k], rg_f2ord(c));
+        }
+    }
+    __syncthreads();
+    int P = 1;
+    while (P < n) P <<= 1;
+    for (int i = t; i < P; i += kSmallThreads) {
+        key[i] = i < n ? morton_key(a.prim_box + 6 * i, bnd) : ~0ull;  // padding sorts last
+        id[i] = (uint32_t)i;
+    }
+    // bitonic sort by (key, index)
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            __syncthreads();
+            for (int i = t; i < P; i += kSmallThreads) {
+                const int l = i ^ j;
+                if (l <= i) continue;
+                const uint64_t ki = key[i], kl = key[l];
+                const uint32_t ii = id[i], il = id[l];
+                const bool gt = ki > kl || (ki == kl && ii > il);
+                if (((i & k) == 0) == gt) {
+                    key[i] = kl; key[l] = ki;
+                    id[i] = il; id[l] = ii;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += kSmallThreads) {
+        a.ids[i] = id[i];
+        if (a.keys_out) a.keys_out[i] = key[i];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) a.leaf_box[6 * i + q] = a.prim_box[6 * (int64_t)id[i] + q];
+    }
+    for (int i = t; i < n - 1; i += kSmallThreads)
+        karras_node(key, n, i, a.left, a.right, a.pint, a.pleaf, a.first, a.last);
+    __syncthreads();
+    // inner boxes, round by round: a node whose children were final at the
+    // start of the round takes the union of their boxes
+    for (int round = 0; n > 1 && round < n; ++round) {
+        for (int i = t; i < n - 1; i += kSmallThreads) {
+            if ((done[0][i >> 5] >> (i & 31)) & 1u) continue;
+            const int32_t c[2] = {a.left[i], a.right[i]};
+            bool ready = true;
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                if (c[q] >= 0 && !((done[0][c[q] >> 5] >> (c[q] & 31)) & 1u)) ready = false;
+            if (!ready) continue;
+            float b[12];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const float *src = c[q] < 0 ? a.leaf_box + 6 * (int64_t)(-c[q] - 1) : a.int_box + 6 * (int64_t)c[q];
+#pragma unroll
+                for (int z = 0; z < 6; ++z) b[6 * q + z] = src[z];
+            }
+#pragma unroll
+            for (int z = 0; z < 3; ++z) {
+                a.int_box[6 * i + z] = fminf(b[z], b[6 + z]);
+                a.int_box[6 * i + 3 + z] = fmaxf(b[3 + z], b[9 + z]);
+            }
+            atomicOr(&done[1][i >> 5], 1u << (i & 31));
+        }
+        __syncthreads();
+        for (int i = t; i < kSmallMax / 32; i += kSmallThreads) done[0][i] |= done[1][i];
+        __syncthreads();
+        if (done[0][0] & 1u) break;  // the root
+    }
+    const float *root = n > 1 ? a.int_box : a.leaf_box;
+    if (t == 0) {
+#pragma unroll
+        for (int z = 0; z < 3; ++z) {
+            a.res->lo[z] = root[z];
+            a.res->hi[z] = root[3 + z];
+        }
+        a.res->err = (n > 1 && !(done[0][0] & 1u)) ? 1u : 0u;
+    }
+    if (!a.nodes) return;
+    RgNode<W> *nodes = reinterpret_cast<RgNode<W> *>(a.nodes);
+    if (n == 1) {
+        if (t < W) {
+            RgNode<W> *nd = nodes;
+            const int k = t;
+            if (k == 0) {
+                nd->lo_x[0] = a.leaf_box[0]; nd->lo_y[0] = a.leaf_box[1]; nd->lo_z[0] = a.leaf_box[2];
+                nd->hi_x[0] = a.leaf_box[3]; nd->hi_y[0] = a.leaf_box[4]; nd->hi_z[0] = a.leaf_box[5];
+                nd->child[0] = rg_leaf(0u, 1u);
+            } else {
+                nd->lo_x[k] = INFINITY; nd->lo_y[k] = INFINITY; nd->lo_z[k] = INFINITY;
+                nd->hi_x[k] = -INFINITY; nd->hi_y[k] = -INFINITY; nd->hi_z[k] = -INFINITY;
+                nd->child[k] = RG_EMPTY;
+            }
+            nd->pad[k] = 0u;
+        }
+        if (t == 0) {
+            if (a.parents) a.parents[0] = RG_MISS;
+            if (a.levels) {
+                a.levels[0] = 0u;
+                a.levels[1] = 1u;
+            }
+            a.res->depth = 1u;
+            a.res->n_nodes = 1u;
+        }
+        return;
+    }
+    // wide collapse, level by level
+    if (t == 0) {
+        a.q[0][0] = make_uint2(0u, 0u);
+        if (a.parents) a.parents[0] = RG_MISS;
+        lstart[0] = 0u;
+    }
+    uint32_t count = 1u, start = 0u;
+    int level = 0;
+    __syncthreads();
+    while (count > 0u) {
+        if (t == 0) qcount = 0u;
+        __syncthreads();
+        const uint32_t next_base = start + count;
+        const uint2 *qin = a.q[level & 1];
+        uint2 *qout = a.q[(level + 1) & 1];
+        for (uint32_t qi = t; qi < count; qi += kSmallThreads) {
+            const uint2 item = qin[qi];
+            int32_t C[W];
+            const int m = collapse_children<W>((int32_t)item.y, a.left, a.right, a.int_box, C);
+            uint32_t link[W];
+            const uint32_t inner = collapse_links<W>(C, m, a.first, a.last, a.leaf_max, link);
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                if (!((inner >> k) & 1u)) continue;
+                const uint32_t slot = atomicAdd(&qcount, 1u);
+                const uint32_t nn = next_base + slot;
+                qout[slot] = make_uint2(nn, (uint32_t)C[k]);
+                if (a.parents) a.parents[nn] = (item.x << 3) | (uint32_t)k;
+                link[k] = nn;
+            }
+            write_wide_node<W>(nodes + item.x, C, m, link, a.int_box, a.leaf_box);
+        }
+        __syncthreads();
+        start = next_base;
+        count = qcount;
+        ++level;
+        if (t == 0 && level <= RG_LEVELS_CAP) lstart[level] = start;
+        __syncthreads();
+    }
+    // `level` levels, nodes [0, start)
+    if (t == 0) {
+        a.res->depth = (uint32_t)level;
+        a.res->n_nodes = start;
+    }
+    if (a.levels && level <= RG_LEVELS_CAP)
+        for (int l = t; l <= level; l += kSmallThreads) a.levels[l] = lstart[l];
 }
 
 // ------------------------------------ 5'. locally-ordered clustering
@@ -1025,7 +1264,9 @@ __global__ void __launch_bounds__(64) k_treelet(const int32_t *__restrict__ orde
 }
 
 // ------------------------------------------------------ reordering
-__global__ void k_reorder_tris(const float *__restrict__ verts, const uint32_t *__restrict__ idx,
+// An index out of range reads vertex 0 instead (the input check then fails
+// the call; a build in one workgroup reorders before the check is read).
+__global__ void k_reorder_tris(const float *__restrict__ verts, int64_t n_verts, const uint32_t *__restrict__ idx,
                                const uint32_t *__restrict__ ids, int64_t n, const uint16_t *__restrict__ pm,
                                RgTri *__restrict__ tris, uint16_t *__restrict__ mats, uint32_t *__restrict__ slots) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1035,6 +1276,7 @@ __global__ void k_reorder_tris(const float *__restrict__ verts, const uint32_t *
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
         uint32_t vi = idx[3 * (int64_t)s + v];
+        if ((int64_t)vi >= n_verts) vi = 0u;
 #pragma unroll
         for (int k = 0; k < 3; ++k) t.v[3 * v + k] = verts[3 * (int64_t)vi + k];
     }
@@ -1044,14 +1286,15 @@ __global__ void k_reorder_tris(const float *__restrict__ verts, const uint32_t *
     slots[s] = (uint32_t)i;
 }
 
+// root: the root box (lo xyz, hi xyz) as the build left it on the device
 __global__ void k_blas_header(RgBlasHdr *h, uint64_t nodes, uint64_t tris, uint64_t mats, uint64_t slots,
-                              float lx, float ly, float lz, float hx, float hy, float hz) {
+                              const float *root) {
     h->nodes = nodes;
     h->tris = tris;
     h->mats = mats;
     h->slots = slots;
-    h->lo[0] = lx; h->lo[1] = ly; h->lo[2] = lz;
-    h->hi[0] = hx; h->hi[1] = hy; h->hi[2] = hz;
+    h->lo[0] = root[0]; h->lo[1] = root[1]; h->lo[2] = root[2];
+    h->hi[0] = root[3]; h->hi[1] = root[4]; h->hi[2] = root[5];
     h->status = 0u;
     h->pad = 0u;
     h->alpha = 0ull;
@@ -1428,6 +1671,7 @@ struct LbvhScratch {
     // restructuring also takes rank, size and cbox[0]
     int32_t *height, *order;
     uint32_t *hcount, *hcursor, *hstart, *hmax;
+    SmallResult *small;  // summary of a one-workgroup build
 };
 
 bool carve(RgArena &a, int64_t n, int32_t builder, LbvhScratch &s) {
@@ -1474,6 +1718,7 @@ bool carve(RgArena &a, int64_t n, int32_t builder, LbvhScratch &s) {
     s.hcursor = a.take<uint32_t>(n + 1);
     s.hstart = a.take<uint32_t>(n + 1);
     s.hmax = a.take<uint32_t>(8);
+    s.small = a.take<SmallResult>(1);
     return !a.overflow();
 }
 
@@ -1676,6 +1921,53 @@ rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t
                         int32_t *right_out, float *boxes_out) {
     LbvhScratch s;
     if (!carve(arena, n, builder, s)) return RG_ERR_OUT_OF_MEMORY;
+    if (builder == RG_BUILDER_LBVH && n <= kSmallMax) {
+        // the whole build in one workgroup, one host wait for its summary
+        SmallArgs sa;
+        sa.prim_box = prim_box;
+        sa.n = (int32_t)n;
+        sa.leaf_max = leaf_max;
+        sa.keys_out = keep_stages ? keys_out : nullptr;
+        sa.ids = s.ids;
+        sa.left = s.left; sa.right = s.right; sa.pint = s.pint; sa.pleaf = s.pleaf;
+        sa.first = s.first; sa.last = s.last;
+        sa.int_box = s.int_box;
+        sa.leaf_box = s.leaf_box;
+        sa.q[0] = s.q0;
+        sa.q[1] = s.q1;
+        sa.nodes = nodes;
+        sa.parents = parents;
+        sa.levels = levels;
+        sa.res = s.small;
+        if (width == 2) k_small_build<2><<<1, kSmallThreads, 0, st>>>(sa);
+        else if (width == 4) k_small_build<4><<<1, kSmallThreads, 0, st>>>(sa);
+        else k_small_build<8><<<1, kSmallThreads, 0, st>>>(sa);
+        RG_LAUNCH_CHECK();
+        if (keep_stages) {
+            if (n > 1) {
+                RG_HIP(hipMemcpyAsync(left_out, s.left, 4 * (n - 1), hipMemcpyDeviceToDevice, st));
+                RG_HIP(hipMemcpyAsync(right_out, s.right, 4 * (n - 1), hipMemcpyDeviceToDevice, st));
+                RG_HIP(hipMemcpyAsync(boxes_out, s.int_box, 24 * (n - 1), hipMemcpyDeviceToDevice, st));
+            }
+            RG_HIP(hipMemcpyAsync(boxes_out + 6 * (n - 1), s.leaf_box, 24 * n, hipMemcpyDeviceToDevice, st));
+        }
+        static_assert(sizeof(SmallResult) == 10 * sizeof(uint32_t), "summary layout");
+        out->ids = s.ids;
+        out->root_dev = s.small->lo;
+        if (out->deferred) {
+            RG_HIP(hipMemcpyAsync(out->deferred, s.small, sizeof(SmallResult), hipMemcpyDeviceToHost, st));
+            out->pending = true;
+            return RG_OK;
+        }
+        uint32_t res[10];
+        out->deferred = res;
+        RG_HIP(hipMemcpyAsync(res, s.small, sizeof(SmallResult), hipMemcpyDeviceToHost, st));
+        RG_HIP(hipStreamSynchronize(st));
+        out->pending = true;
+        rg_status r = rg_lbvh_finish(out, nodes != nullptr);
+        out->deferred = nullptr;
+        return r;
+    }
     int nblocks = (int)((n + kSortTile - 1) / kSortTile);
     // bounds of the centres
     k_fill_u32<<<1, 64, 0, st>>>(s.bounds, 0xFFFFFFFFu, 3);
@@ -1743,12 +2035,28 @@ rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t
         else r = collapse<8>(s, n, leaf_max, nodes, parents, levels, st, &out->depth, &out->n_nodes);
         if (r != RG_OK) return r;
     }
+    out->root_dev = n > 1 ? s.int_box : s.leaf_box;
     float rb[6];
     RG_HIP(hipMemcpyAsync(rb, n > 1 ? s.int_box : s.leaf_box, 24, hipMemcpyDeviceToHost, st));
     RG_HIP(hipStreamSynchronize(st));
     for (int k = 0; k < 3; ++k) {
         out->lo[k] = rb[k];
         out->hi[k] = rb[3 + k];
+    }
+    return RG_OK;
+}
+
+rg_status rg_lbvh_finish(RgLbvhOut *out, bool with_nodes) {
+    if (!out->pending) return RG_OK;
+    out->pending = false;
+    SmallResult res;
+    memcpy(&res, out->deferred, sizeof(res));
+    if (res.err) return RG_ERR_HIP;  // never: every inner node gets a box
+    out->depth = with_nodes ? (int32_t)res.depth : 0;
+    out->n_nodes = with_nodes ? (int64_t)res.n_nodes : 0;
+    for (int k = 0; k < 3; ++k) {
+        out->lo[k] = res.lo[k];
+        out->hi[k] = res.hi[k];
     }
     return RG_OK;
 }
@@ -1805,9 +2113,7 @@ uint64_t tlas_out_bytes(int64_t n, int w, uint64_t *nodes_off, uint64_t *inst_of
 
 uint64_t tlas_scratch_bytes(int64_t n, int32_t n_blas, int32_t builder) {
     RgArena a{nullptr, 0, 0};
-    a.take<uint32_t>(n);        // blas ids
-    a.take<uint32_t>(n);        // materials
-    a.take<BlasInfo>(n_blas > 0 ? n_blas : 1);
+    a.take<char>(12 * (size_t)n + sizeof(BlasInfo) * (size_t)(n_blas > 0 ? n_blas : 1));  // host tables
     a.take<float>(6 * n);       // instance boxes
     a.take<RgInst>(n);          // unsorted records
     a.take<uint32_t>(8);        // flags
@@ -1886,23 +2192,37 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
     k_fill_u32<<<1, 64, 0, st>>>(flags, 0u, 1);
     k_tri_boxes<<<rg_blocks(n_tris, kThreads), kThreads, 0, st>>>(verts, n_verts, idx, n_tris, pbox, flags);
     RG_LAUNCH_CHECK();
-    uint32_t hflags = 0;
-    RG_HIP(hipMemcpyAsync(&hflags, flags, 4, hipMemcpyDeviceToHost, st));
-    RG_HIP(hipStreamSynchronize(st));
-    if (hflags) return RG_ERR_INVALID_ARG;
+    // a build in one workgroup (small meshes, linear BVH) runs on whatever the
+    // boxes hold and the input check is read with its summary at the one
+    // wait of the call; a larger build checks the input first
+    const bool small = o.builder == RG_BUILDER_LBVH && n_tris <= kSmallMax;
+    uint32_t summary[11] = {};  // a one-workgroup build's summary, then the flags word
+    if (!small) {
+        RG_HIP(hipMemcpyAsync(summary + 10, flags, 4, hipMemcpyDeviceToHost, st));
+        RG_HIP(hipStreamSynchronize(st));
+        if (summary[10]) return RG_ERR_INVALID_ARG;
+    }
     char *base = (char *)out_buf;
     RgLbvhOut lo;
+    lo.deferred = summary;
     rg_status r = rg_lbvh_build(pbox, n_tris, w, l, o.builder, o.radius, base + no, (uint32_t *)(base + po),
                                 (uint32_t *)(base + lvo), arena, st, &lo, false, nullptr, nullptr, nullptr, nullptr);
-    if (r != RG_OK) return r;
+    if (r != RG_OK) {
+        if (lo.pending) hipStreamSynchronize(st);  // the summary copy targets this frame
+        return r;
+    }
     k_reorder_tris<<<rg_blocks(n_tris, kThreads), kThreads, 0, st>>>(
-        verts, idx, lo.ids, n_tris, prim_material, (RgTri *)(base + to), (uint16_t *)(base + mo),
+        verts, n_verts, idx, lo.ids, n_tris, prim_material, (RgTri *)(base + to), (uint16_t *)(base + mo),
         (uint32_t *)(base + so));
     k_blas_header<<<1, 1, 0, st>>>((RgBlasHdr *)base, (uint64_t)(base + no), (uint64_t)(base + to),
-                                   (uint64_t)(base + mo), (uint64_t)(base + so), lo.lo[0], lo.lo[1], lo.lo[2],
-                                   lo.hi[0], lo.hi[1], lo.hi[2]);
-    RG_LAUNCH_CHECK();
+                                   (uint64_t)(base + mo), (uint64_t)(base + so), lo.root_dev);
+    const hipError_t le = hipGetLastError();
+    const hipError_t ce = (le == hipSuccess && small) ?
+                          hipMemcpyAsync(summary + 10, flags, 4, hipMemcpyDeviceToHost, st) : le;
     RG_HIP(hipStreamSynchronize(st));
+    RG_HIP(ce);
+    if ((r = rg_lbvh_finish(&lo, true)) != RG_OK) return r;
+    if (summary[10]) return RG_ERR_INVALID_ARG;
     out->buf = out_buf;
     out->nodes_off = no;
     out->tris_off = to;
@@ -2084,34 +2404,43 @@ rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xfo
     hipStream_t st = (hipStream_t)stream;
     RgArena arena{(char *)scratch, scratch_bytes, 0};
     float *d_xf = (float *)((char *)out_buf + xo);  // kept: the trace calls recompute hits from it
-    uint32_t *d_bid = arena.take<uint32_t>(n_inst);
-    uint32_t *d_mat = arena.take<uint32_t>(n_inst);
-    BlasInfo *d_info = arena.take<BlasInfo>(n_blas);
+    // the host tables go over in one copy: blas ids, materials, flags, bottom levels
+    const size_t t_bytes = 4 * (size_t)n_inst * (inst_flags ? 3 : 2) + sizeof(BlasInfo) * (size_t)n_blas;
+    char *d_tab = arena.take<char>(t_bytes);
     float *d_box = arena.take<float>(6 * n_inst);
     RgInst *d_rec = arena.take<RgInst>(n_inst);
     uint32_t *d_flags = arena.take<uint32_t>(8);
-    uint32_t *d_iflags = inst_flags ? arena.take<uint32_t>(n_inst) : nullptr;
+    uint32_t *d_bid = (uint32_t *)d_tab, *d_mat = d_bid + n_inst;
+    uint32_t *d_iflags = inst_flags ? d_mat + n_inst : nullptr;
+    BlasInfo *d_info = (BlasInfo *)(d_tab + 4 * (size_t)n_inst * (inst_flags ? 3 : 2));
+    std::vector<char> tab(t_bytes);
+    memcpy(tab.data(), blas_id, 4 * (size_t)n_inst);
+    memcpy(tab.data() + 4 * (size_t)n_inst, inst_material, 4 * (size_t)n_inst);
+    if (inst_flags) memcpy(tab.data() + 8 * (size_t)n_inst, inst_flags, 4 * (size_t)n_inst);
+    memcpy(tab.data() + 4 * (size_t)n_inst * (inst_flags ? 3 : 2), info.data(), sizeof(BlasInfo) * (size_t)n_blas);
     k_fill_u32<<<1, 64, 0, st>>>(d_flags, 0u, 1);
-    if (inst_flags) RG_HIP(hipMemcpyAsync(d_iflags, inst_flags, 4 * n_inst, hipMemcpyHostToDevice, st));
     RG_HIP(hipMemcpyAsync(d_xf, xform, 48 * n_inst, hipMemcpyHostToDevice, st));
-    RG_HIP(hipMemcpyAsync(d_bid, blas_id, 4 * n_inst, hipMemcpyHostToDevice, st));
-    RG_HIP(hipMemcpyAsync(d_mat, inst_material, 4 * n_inst, hipMemcpyHostToDevice, st));
-    RG_HIP(hipMemcpyAsync(d_info, info.data(), sizeof(BlasInfo) * n_blas, hipMemcpyHostToDevice, st));
+    RG_HIP(hipMemcpyAsync(d_tab, tab.data(), t_bytes, hipMemcpyHostToDevice, st));
     k_inst_setup<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(d_xf, d_bid, d_mat, d_iflags, d_info, n_inst, d_box,
                                                                     d_rec, d_flags);
     RG_LAUNCH_CHECK();
     char *base = (char *)out_buf;
     RgLbvhOut lo;
+    uint32_t summary[11];  // a one-workgroup build's summary, then the flags word
+    lo.deferred = summary;
     rg_status r = rg_lbvh_build(d_box, n_inst, w, 1, o.builder, o.radius, base + no, nullptr, nullptr, arena, st, &lo,
                                 false, nullptr, nullptr, nullptr, nullptr);
     if (r != RG_OK) return r;
     k_reorder_inst<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(d_rec, lo.ids, n_inst, (RgInst *)(base + io),
                                                                       (uint32_t *)(base + ro));
-    RG_LAUNCH_CHECK();
-    uint32_t hflags = 0;
-    RG_HIP(hipMemcpyAsync(&hflags, d_flags, 4, hipMemcpyDeviceToHost, st));
-    RG_HIP(hipStreamSynchronize(st));
-    if (hflags) return RG_ERR_INVALID_ARG;  // a bottom level was refitted to invalid vertex data
+    const hipError_t le = hipGetLastError();
+    const hipError_t ce = le == hipSuccess ? hipMemcpyAsync(summary + 10, d_flags, 4, hipMemcpyDeviceToHost, st)
+                                           : le;
+    RG_HIP(hipStreamSynchronize(st));  // the one wait of the call (also before any error return: the
+                                       // summary copy targets this frame)
+    RG_HIP(ce);
+    if ((r = rg_lbvh_finish(&lo, true)) != RG_OK) return r;
+    if (summary[10]) return RG_ERR_INVALID_ARG;  // a bottom level was refitted to invalid vertex data
     out->buf = out_buf;
     out->nodes_off = no;
     out->inst_off = io;

@@ -141,7 +141,18 @@ struct RgLbvhOut {
     int32_t depth;
     int64_t n_nodes;
     float lo[3], hi[3];
+    // Set by the caller to let a one-workgroup build (small n, linear BVH)
+    // return without waiting: it then enqueues the copy of its summary
+    // (depth, node count, error flag, root box: 10 uint32 / float words) to
+    // *deferred and sets `pending`; the caller waits for the stream and calls
+    // rg_lbvh_finish.
+    uint32_t *deferred = nullptr;
+    bool pending = false;
+    const float *root_dev = nullptr;  // the root box (lo xyz, hi xyz) on the device, once the stream gets there
 };
+// Fills depth, n_nodes and the root box of a pending one-workgroup build
+// from its summary (after the caller's wait); RG_ERR_HIP if it failed.
+rg_status rg_lbvh_finish(RgLbvhOut *out, bool with_nodes);
 // parents (nullable): per wide node, (parent node << 3) | slot in the parent,
 // RG_MISS for the root.  levels (nullable, RG_LEVELS_CAP + 1 entries): the
 // first node of each level and, after the last level, the node count (nodes

@@ -24,6 +24,11 @@ MESHES = {
     "torus": lambda: sg.torus(48, 40, 1.0, 0.35, 0.08, 6.0, 3001),
     "two": lambda: sg.random_soup(2, 5),
     "dupes": lambda: sg.triangles_mesh(np.repeat(np.array([[[0, 0, 0], [1, 0, 0], [0, 1, 0]]]), 300, axis=0)),
+    # the largest build done by one workgroup, and the smallest done by the
+    # multi-launch path
+    "soup4096": lambda: sg.random_soup(4096, 23),
+    "soup4097": lambda: sg.random_soup(4097, 24),
+    "one": lambda: sg.random_soup(1, 25),
 }
 
 
