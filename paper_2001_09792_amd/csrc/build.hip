@@ -38,12 +38,48 @@ constexpr int kScanThreads = 1024;
 
 // --------------------------------------------------------------- helpers
 
+// The value that lane (this lane ^ J) of the wave holds, J = 1 .. 32, with
+// every lane active: DPP quad permutes and row mirrors below 16 (4 = half-row
+// mirror then quad reversal, 8 = row mirror then half-row mirror), the
+// gfx950 row swaps for 16 and 32 (each returns both swapped operands; a lane
+// takes the half that came from the other row).
+template <int J>
+__device__ inline uint32_t lane_xor(uint32_t v) {
+    if constexpr (J == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+    else if constexpr (J == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+    else if constexpr (J == 4)
+        return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false), 0x1B, 0xF, 0xF, false);
+    else if constexpr (J == 8)
+        return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false), 0x141, 0xF, 0xF, false);
+    else if constexpr (J == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (__lane_id() & 16) ? r[0] : r[1];
+    } else {
+        static_assert(J == 32, "lane distance");
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (__lane_id() & 32) ? r[0] : r[1];
+    }
+}
+__device__ inline uint32_t lane_xor(uint32_t v, int j) {  // j a constant after unrolling
+    switch (j) {
+        case 1: return lane_xor<1>(v);
+        case 2: return lane_xor<2>(v);
+        case 4: return lane_xor<4>(v);
+        case 8: return lane_xor<8>(v);
+        case 16: return lane_xor<16>(v);
+        default: return lane_xor<32>(v);
+    }
+}
+__device__ inline float lane_xor(float v, int j) { return __uint_as_float(lane_xor(__float_as_uint(v), j)); }
+
 __device__ inline float wave_min(float v) {
-    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, lane_xor(v, o));
     return v;
 }
 __device__ inline float wave_max(float v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, lane_xor(v, o));
     return v;
 }
 
@@ -275,52 +311,56 @@ __global__ void __launch_bounds__(kThreads) k_sort_scatter(
 }
 
 // ------------------------------------------------- 4. Karras hierarchy
-__device__ inline int k_delta(const uint64_t *k, int64_t n, int64_t i, int64_t j) {
+// Index arithmetic in 32 bits: n <= RG_MAX_TRIS = 2^28, so every probe
+// i + m * d below stays within (-2^30, 2^30).
+__device__ inline int k_delta(const uint64_t *k, int n, int i, int j) {
     if (j < 0 || j >= n) return -1;
-    uint64_t a = k[i], b = k[j];
+    const uint64_t a = k[i], b = k[j];
     if (a == b) return 64 + __clz((int)((uint32_t)i ^ (uint32_t)j));
     return __clzll((long long)(a ^ b));
 }
 
 // Inner node i of the radix tree over n sorted keys (keys may be in LDS):
 // its children (>= 0 inner, < 0 leaf -(j+1)), parent links and leaf range.
-__device__ inline void karras_node(const uint64_t *keys, int64_t n, int64_t i, int32_t *__restrict__ left,
+__device__ inline void karras_node(const uint64_t *keys, int64_t n64, int64_t i64, int32_t *__restrict__ left,
                                    int32_t *__restrict__ right, int32_t *__restrict__ parent_int,
                                    int32_t *__restrict__ parent_leaf, int32_t *__restrict__ first,
                                    int32_t *__restrict__ last) {
-    int d = (k_delta(keys, n, i, i + 1) - k_delta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
-    int dmin = k_delta(keys, n, i, i - d);
-    int64_t lmax = 2;
+    static_assert(RG_MAX_TRIS <= (1ll << 28), "32-bit index arithmetic");
+    const int n = (int)n64, i = (int)i64;
+    const int d = (k_delta(keys, n, i, i + 1) - k_delta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
+    const int dmin = k_delta(keys, n, i, i - d);
+    int lmax = 2;
     while (k_delta(keys, n, i, i + lmax * d) > dmin) lmax <<= 1;
-    int64_t l = 0;
-    for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
+    int l = 0;
+    for (int t = lmax >> 1; t >= 1; t >>= 1)
         if (k_delta(keys, n, i, i + (l + t) * d) > dmin) l += t;
-    int64_t j = i + l * d;
-    int dnode = k_delta(keys, n, i, j);
-    int64_t s = 0, t = l;
+    const int j = i + l * d;
+    const int dnode = k_delta(keys, n, i, j);
+    int s = 0, t = l;
     do {
         t = (t + 1) >> 1;
         if (k_delta(keys, n, i, i + (s + t) * d) > dnode) s += t;
     } while (t > 1);
-    int64_t g = i + s * d + (d < 0 ? -1 : 0);
-    int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+    const int g = i + s * d + (d < 0 ? -1 : 0);
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
     if (g < 0 || g + 1 > n - 1 || lo < 0 || hi > n - 1) return;  // unreachable for sorted keys
     if (lo == g) {
-        left[i] = -(int32_t)(g + 1);
-        parent_leaf[g] = (int32_t)i;
+        left[i] = -(g + 1);
+        parent_leaf[g] = i;
     } else {
-        left[i] = (int32_t)g;
-        parent_int[g] = (int32_t)i;
+        left[i] = g;
+        parent_int[g] = i;
     }
     if (hi == g + 1) {
-        right[i] = -(int32_t)(g + 2);
-        parent_leaf[g + 1] = (int32_t)i;
+        right[i] = -(g + 2);
+        parent_leaf[g + 1] = i;
     } else {
-        right[i] = (int32_t)(g + 1);
-        parent_int[g + 1] = (int32_t)i;
+        right[i] = g + 1;
+        parent_int[g + 1] = i;
     }
-    first[i] = (int32_t)lo;
-    last[i] = (int32_t)hi;
+    first[i] = lo;
+    last[i] = hi;
     if (i == 0) parent_int[0] = -1;
 }
 
@@ -422,24 +462,30 @@ __device__ inline uint32_t collapse_links(const int32_t C[W], int m, const int32
     return inner;
 }
 
-// Writes a wide node: the children's boxes (empty slots inverted) and links.
+// Writes a wide node: the children's boxes (empty slots inverted) and links,
+// assembled in registers and stored 16 bytes at a time (a node is 64-byte
+// aligned): 2W stores per node instead of 8W.
 template <int W>
 __device__ inline void write_wide_node(RgNode<W> *nd, const int32_t C[W], int m, const uint32_t link[W],
                                        const float *__restrict__ int_box, const float *__restrict__ leaf_box) {
+    uint32_t w[8 * W];
 #pragma unroll
     for (int k = 0; k < W; ++k) {
-        if (k >= m) {
-            nd->lo_x[k] = INFINITY; nd->lo_y[k] = INFINITY; nd->lo_z[k] = INFINITY;
-            nd->hi_x[k] = -INFINITY; nd->hi_y[k] = -INFINITY; nd->hi_z[k] = -INFINITY;
-        } else {
+        float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+        if (k < m) {
             const int32_t c = C[k];
-            const float *b = c < 0 ? leaf_box + 6 * (int64_t)(-c - 1) : int_box + 6 * (int64_t)c;
-            nd->lo_x[k] = b[0]; nd->lo_y[k] = b[1]; nd->lo_z[k] = b[2];
-            nd->hi_x[k] = b[3]; nd->hi_y[k] = b[4]; nd->hi_z[k] = b[5];
+            const float *src = c < 0 ? leaf_box + 6 * (int64_t)(-c - 1) : int_box + 6 * (int64_t)c;
+#pragma unroll
+            for (int z = 0; z < 6; ++z) b[z] = src[z];
         }
-        nd->child[k] = link[k];
-        nd->pad[k] = 0u;
+#pragma unroll
+        for (int z = 0; z < 6; ++z) w[z * W + k] = __float_as_uint(b[z]);
+        w[6 * W + k] = link[k];
+        w[7 * W + k] = 0u;
     }
+    uint4 *dst = reinterpret_cast<uint4 *>(nd);
+#pragma unroll
+    for (int q = 0; q < 2 * W; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
 }
 
 // One thread per node of the level (queue items: node index, binary node it
@@ -548,7 +594,7 @@ __global__ void k_collapse_init(uint2 *q, uint32_t *ring, uint32_t *parents) {
 constexpr int kSmallThreads = 1024;
 constexpr int kSmallMax = 4096;
 struct SmallResult {
-    uint32_t depth, n_nodes, err, pad;
+    uint32_t depth, n_nodes, err, flag;  // flag: a copy of *SmallArgs::flag_in (0 without)
     float lo[3], hi[3];
 };
 
@@ -562,95 +608,240 @@ struct SmallArgs {
     uint2 *q[2];
     void *nodes;                    // nullable: binary hierarchy only
     uint32_t *parents, *levels;     // nullable
+    const uint32_t *flag_in;        // nullable: a word of an earlier step returned with the summary
     SmallResult *res;
 };
 
-template <int W>
+// LDS of the one-workgroup build (dynamic).  Up to kResidentMax primitives
+// everything the steps read again and again stays in LDS: keys, order, tree
+// links, ranges and parents, inner boxes, the primitive boxes in input and in
+// leaf order (108 bytes per primitive).  Above that: the keys and the order.
+constexpr int kResidentMax = 1024;
+constexpr size_t kSmallLdsResident = (size_t)kResidentMax * (8 + 4 + 6 * 4 + 3 * 24);
+constexpr size_t kSmallLdsGlobal = (size_t)kSmallMax * (8 + 4);
+size_t small_lds_bytes(int64_t n) { return n <= kResidentMax ? kSmallLdsResident : kSmallLdsGlobal; }
+static_assert(8 * 2 + 1 <= 24, "the wide-children table fits the primitive-box area (W <= 8)");
+
+template <int W, bool RESIDENT>
 __global__ void __launch_bounds__(kSmallThreads) k_small_build(SmallArgs a) {
-    __shared__ uint64_t key[kSmallMax];
-    __shared__ uint32_t id[kSmallMax];
+    extern __shared__ uint64_t small_lds[];
     __shared__ uint32_t bnd[6];
     __shared__ uint32_t done[2][kSmallMax / 32];
-    __shared__ uint32_t qcount, lstart[RG_LEVELS_CAP + 2];
-    const int t = threadIdx.x, n = a.n;
+    __shared__ uint32_t qcnt[3], lstart[RG_LEVELS_CAP + 2];
+    const int t = threadIdx.x, n = a.n, lane = t & 63;
+    constexpr int cap = RESIDENT ? kResidentMax : kSmallMax;
+    uint64_t *key = small_lds;
+    uint32_t *id = reinterpret_cast<uint32_t *>(key + cap);
+    // tree links, ranges, parents and boxes: LDS when resident, else the
+    // scratch arrays.  Once the tree is built the key area holds the arrival
+    // counters and the collapse queues (resident).
+    int32_t *left = a.left, *right = a.right, *first = a.first, *last = a.last, *pint = a.pint, *pleaf = a.pleaf;
+    float *int_box = a.int_box, *lbox = a.leaf_box, *pbox = nullptr;
+    uint32_t *arrive = reinterpret_cast<uint32_t *>(key);
+    uint32_t *const lq = arrive + cap;  // two queues of cap items (by offset: the pointer stays an LDS one)
+    if (RESIDENT) {
+        left = reinterpret_cast<int32_t *>(id + cap);
+        right = left + cap;
+        first = right + cap;
+        last = first + cap;
+        pint = last + cap;
+        pleaf = pint + cap;
+        int_box = reinterpret_cast<float *>(pleaf + cap);
+        pbox = int_box + 6 * cap;
+        lbox = pbox + 6 * cap;
+    }
     if (t < 3) bnd[t] = 0xFFFFFFFFu;
     else if (t < 6) bnd[t] = 0u;
+    if (t < 3) qcnt[t] = t == 0 ? 1u : 0u;  // the collapse starts from the root
     for (int i = t; i < kSmallMax / 32; i += kSmallThreads) done[0][i] = done[1][i] = 0u;
     __syncthreads();
-    // centre bounds (exact min / max, any order)
-    for (int i = t; i < n; i += kSmallThreads) {
+    // centre bounds (exact min / max, any order): per wave, then LDS atomics;
+    // resident, each thread keeps its primitive's box in LDS
+    {
+        float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int i = t; i < n; i += kSmallThreads) {
+            float b[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) b[q] = a.prim_box[6 * i + q];
+            if (RESIDENT) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) pbox[6 * i + q] = b[q];
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const float c = (b[k] + b[3 + k]) * 0.5f;
+                mn[k] = fminf(mn[k], c);
+                mx[k] = fmaxf(mx[k], c);
+            }
+        }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const float c = (a.prim_box[6 * i + k] + a.prim_box[6 * i + 3 + k]) * 0.5f;
-            atomicMin(&bnd[k], rg_f2ord(c));
-            atomicMax(&bnd[3 + k], rg_f2ord(c));
+            mn[k] = wave_min(mn[k]);
+            mx[k] = wave_max(mx[k]);
+        }
+        if (lane == 0 && mn[0] <= mx[0]) {  // a wave with elements
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                atomicMin(&bnd[k], rg_f2ord(mn[k]));
+                atomicMax(&bnd[3 + k], rg_f2ord(mx[k]));
+            }
         }
     }
     __syncthreads();
-    int P = 1;
-    while (P < n) P <<= 1;
-    for (int i = t; i < P; i += kSmallThreads) {
-        key[i] = i < n ? morton_key(a.prim_box + 6 * i, bnd) : ~0ull;  // padding sorts last
-        id[i] = (uint32_t)i;
-    }
-    // bitonic sort by (key, index)
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            __syncthreads();
-            for (int i = t; i < P; i += kSmallThreads) {
-                const int l = i ^ j;
-                if (l <= i) continue;
-                const uint64_t ki = key[i], kl = key[l];
-                const uint32_t ii = id[i], il = id[l];
-                const bool gt = ki > kl || (ki == kl && ii > il);
-                if (((i & k) == 0) == gt) {
-                    key[i] = kl; key[l] = ki;
-                    id[i] = il; id[l] = ii;
+    if (RESIDENT) {
+        // one element per thread (padding past n sorts last): bitonic sort by
+        // (key, index) in registers, partners within a wave by shuffles,
+        // across waves through LDS
+        uint64_t k0 = t < n ? morton_key(pbox + 6 * t, bnd) : ~0ull;
+        uint32_t v0 = (uint32_t)t;
+#pragma unroll
+        for (int kk = 2; kk <= kResidentMax; kk <<= 1) {
+#pragma unroll
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                uint64_t ko;
+                uint32_t vo;
+                if (j >= 64) {
+                    __syncthreads();
+                    key[t] = k0;
+                    id[t] = v0;
+                    __syncthreads();
+                    ko = key[t ^ j];
+                    vo = id[t ^ j];
+                } else {
+                    ko = ((uint64_t)lane_xor((uint32_t)(k0 >> 32), j) << 32) | lane_xor((uint32_t)k0, j);
+                    vo = lane_xor(v0, j);
+                }
+                // the lower end of an ascending run keeps the smaller one: take
+                // the partner's when greater, with the sense flipped where
+                // exactly one of "descending run" and "upper end" holds
+                // (pairs are distinct); selects, not branches
+                const bool gt = k0 > ko || (k0 == ko && v0 > vo);
+                const bool take = gt != (((t & kk) != 0) != ((t & j) != 0));
+                k0 = take ? ko : k0;
+                v0 = take ? vo : v0;
+            }
+        }
+        __syncthreads();
+        key[t] = k0;
+        if (t < n) {
+            a.ids[t] = v0;
+            if (a.keys_out) a.keys_out[t] = k0;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const float b = pbox[6 * v0 + q];
+                lbox[6 * t + q] = b;
+                a.leaf_box[6 * t + q] = b;
+            }
+        }
+        __syncthreads();
+    } else {
+        int P = 1;
+        while (P < n) P <<= 1;
+        for (int i = t; i < P; i += kSmallThreads) {
+            key[i] = i < n ? morton_key(a.prim_box + 6 * i, bnd) : ~0ull;  // padding sorts last
+            id[i] = (uint32_t)i;
+        }
+        // bitonic sort by (key, index)
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                __syncthreads();
+                for (int i = t; i < P; i += kSmallThreads) {
+                    const int l = i ^ j;
+                    if (l <= i) continue;
+                    const uint64_t ki = key[i], kl = key[l];
+                    const uint32_t ii = id[i], il = id[l];
+                    const bool gt = ki > kl || (ki == kl && ii > il);
+                    if (((i & k) == 0) == gt) {
+                        key[i] = kl; key[l] = ki;
+                        id[i] = il; id[l] = ii;
+                    }
                 }
             }
         }
+        __syncthreads();
+        for (int i = t; i < n; i += kSmallThreads) {
+            a.ids[i] = id[i];
+            if (a.keys_out) a.keys_out[i] = key[i];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) a.leaf_box[6 * i + q] = a.prim_box[6 * (int64_t)id[i] + q];
+        }
     }
+    for (int i = t; i < n - 1; i += kSmallThreads) karras_node(key, n, i, left, right, pint, pleaf, first, last);
     __syncthreads();
-    for (int i = t; i < n; i += kSmallThreads) {
-        a.ids[i] = id[i];
-        if (a.keys_out) a.keys_out[i] = key[i];
+    if (RESIDENT) {
+        // inner boxes bottom-up: each leaf's thread climbs; at a node the
+        // first child to arrive stops, the second takes the union of both
+        // children's boxes (written before their arrival was counted)
+        for (int i = t; i < cap; i += kSmallThreads) arrive[i] = 0u;
+        __syncthreads();
+        if (t < n && n > 1) {
+            int32_t node = pleaf[t];
+            for (int guard = 0; node >= 0 && guard < n; ++guard) {
+                __threadfence_block();  // this thread's box writes before its arrival
+                if (atomicAdd(&arrive[node], 1u) == 0u) break;  // the sibling's thread continues
+                __threadfence_block();  // the sibling's box reads after its arrival
+                const int32_t c[2] = {left[node], right[node]};
+                float b[12];
 #pragma unroll
-        for (int q = 0; q < 6; ++q) a.leaf_box[6 * i + q] = a.prim_box[6 * (int64_t)id[i] + q];
-    }
-    for (int i = t; i < n - 1; i += kSmallThreads)
-        karras_node(key, n, i, a.left, a.right, a.pint, a.pleaf, a.first, a.last);
-    __syncthreads();
-    // inner boxes, round by round: a node whose children were final at the
-    // start of the round takes the union of their boxes
-    for (int round = 0; n > 1 && round < n; ++round) {
-        for (int i = t; i < n - 1; i += kSmallThreads) {
-            if ((done[0][i >> 5] >> (i & 31)) & 1u) continue;
-            const int32_t c[2] = {a.left[i], a.right[i]};
-            bool ready = true;
+                for (int q = 0; q < 2; ++q) {
+                    const float *src = c[q] < 0 ? lbox + 6 * (-c[q] - 1) : int_box + 6 * c[q];
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
-                if (c[q] >= 0 && !((done[0][c[q] >> 5] >> (c[q] & 31)) & 1u)) ready = false;
-            if (!ready) continue;
-            float b[12];
+                    for (int z = 0; z < 6; ++z) b[6 * q + z] = src[z];
+                }
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const float *src = c[q] < 0 ? a.leaf_box + 6 * (int64_t)(-c[q] - 1) : a.int_box + 6 * (int64_t)c[q];
-#pragma unroll
-                for (int z = 0; z < 6; ++z) b[6 * q + z] = src[z];
+                for (int z = 0; z < 3; ++z) {
+                    int_box[6 * node + z] = fminf(b[z], b[6 + z]);
+                    int_box[6 * node + 3 + z] = fmaxf(b[3 + z], b[9 + z]);
+                }
+                if (node == 0) {
+                    atomicOr(&done[0][0], 1u);  // the root is final
+                    break;
+                }
+                node = pint[node];
             }
-#pragma unroll
-            for (int z = 0; z < 3; ++z) {
-                a.int_box[6 * i + z] = fminf(b[z], b[6 + z]);
-                a.int_box[6 * i + 3 + z] = fmaxf(b[3 + z], b[9 + z]);
-            }
-            atomicOr(&done[1][i >> 5], 1u << (i & 31));
         }
         __syncthreads();
-        for (int i = t; i < kSmallMax / 32; i += kSmallThreads) done[0][i] |= done[1][i];
-        __syncthreads();
-        if (done[0][0] & 1u) break;  // the root
+    } else {
+        // inner boxes, round by round: a node whose children were final at the
+        // start of the round takes the union of their boxes
+        for (int round = 0; n > 1 && round < n; ++round) {
+            for (int i = t; i < n - 1; i += kSmallThreads) {
+                if ((done[0][i >> 5] >> (i & 31)) & 1u) continue;
+                const int32_t c[2] = {left[i], right[i]};
+                bool ready = true;
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    if (c[q] >= 0 && !((done[0][c[q] >> 5] >> (c[q] & 31)) & 1u)) ready = false;
+                if (!ready) continue;
+                float b[12];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const float *src = c[q] < 0 ? a.leaf_box + 6 * (int64_t)(-c[q] - 1) : int_box + 6 * (int64_t)c[q];
+#pragma unroll
+                    for (int z = 0; z < 6; ++z) b[6 * q + z] = src[z];
+                }
+#pragma unroll
+                for (int z = 0; z < 3; ++z) {
+                    int_box[6 * i + z] = fminf(b[z], b[6 + z]);
+                    int_box[6 * i + 3 + z] = fmaxf(b[3 + z], b[9 + z]);
+                }
+                atomicOr(&done[1][i >> 5], 1u << (i & 31));
+            }
+            __syncthreads();
+            for (int i = t; i < kSmallMax / 32; i += kSmallThreads) done[0][i] |= done[1][i];
+            __syncthreads();
+            if (done[0][0] & 1u) break;  // the root
+        }
     }
-    const float *root = n > 1 ? a.int_box : a.leaf_box;
+    if (RESIDENT && a.keys_out) {  // the stage check reads the binary tree from the scratch arrays
+        for (int i = t; i < n - 1; i += kSmallThreads) {
+            a.left[i] = left[i];
+            a.right[i] = right[i];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) a.int_box[6 * i + q] = int_box[6 * i + q];
+        }
+    }
+    const float *root = n > 1 ? int_box : lbox;
     if (t == 0) {
 #pragma unroll
         for (int z = 0; z < 3; ++z) {
@@ -658,6 +849,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_build(SmallArgs a) {
             a.res->hi[z] = root[3 + z];
         }
         a.res->err = (n > 1 && !(done[0][0] & 1u)) ? 1u : 0u;
+        a.res->flag = a.flag_in ? *a.flag_in : 0u;
     }
     if (!a.nodes) return;
     RgNode<W> *nodes = reinterpret_cast<RgNode<W> *>(a.nodes);
@@ -666,8 +858,8 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_build(SmallArgs a) {
             RgNode<W> *nd = nodes;
             const int k = t;
             if (k == 0) {
-                nd->lo_x[0] = a.leaf_box[0]; nd->lo_y[0] = a.leaf_box[1]; nd->lo_z[0] = a.leaf_box[2];
-                nd->hi_x[0] = a.leaf_box[3]; nd->hi_y[0] = a.leaf_box[4]; nd->hi_z[0] = a.leaf_box[5];
+                nd->lo_x[0] = lbox[0]; nd->lo_y[0] = lbox[1]; nd->lo_z[0] = lbox[2];
+                nd->hi_x[0] = lbox[3]; nd->hi_y[0] = lbox[4]; nd->hi_z[0] = lbox[5];
                 nd->child[0] = rg_leaf(0u, 1u);
             } else {
                 nd->lo_x[k] = INFINITY; nd->lo_y[k] = INFINITY; nd->lo_z[k] = INFINITY;
@@ -687,41 +879,110 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_build(SmallArgs a) {
         }
         return;
     }
-    // wide collapse, level by level
+    // resident: the children every inner node would get as the root of a wide
+    // node (the opening order depends on that node alone), all at once, into
+    // the primitive-box area (dead since the leaf boxes were gathered):
+    // binary node ids as int16 (leaves negative, 0x7FFF past the last child)
+    // and the mask of the children that stay inner nodes
+    int16_t *wch = reinterpret_cast<int16_t *>(pbox);
+    uint8_t *winner = reinterpret_cast<uint8_t *>(wch + W * cap);
+    if (RESIDENT) {
+        for (int i = t; i < n - 1; i += kSmallThreads) {
+            int32_t C[W];
+            uint32_t link[W];
+            const int m = collapse_children<W>(i, left, right, int_box, C);
+            winner[i] = (uint8_t)collapse_links<W>(C, m, first, last, a.leaf_max, link);
+#pragma unroll
+            for (int k = 0; k < W; ++k) wch[W * i + k] = k < m ? (int16_t)C[k] : (int16_t)0x7FFF;
+        }
+        __syncthreads();
+    }
+    // wide collapse, level by level; queue items (node, binary node): packed
+    // 16 + 16 bits in LDS when resident, else the scratch queues.  Three
+    // counters rotate: level L reads its size from qcnt[L % 3], appends to
+    // qcnt[(L + 1) % 3] and clears qcnt[(L + 2) % 3] (read by every thread
+    // at the start of level L - 1), so one barrier per level suffices.
     if (t == 0) {
-        a.q[0][0] = make_uint2(0u, 0u);
+        if (RESIDENT) lq[0] = 0u;
+        else a.q[0][0] = make_uint2(0u, 0u);
         if (a.parents) a.parents[0] = RG_MISS;
         lstart[0] = 0u;
     }
-    uint32_t count = 1u, start = 0u;
+    uint32_t start = 0u;
     int level = 0;
     __syncthreads();
-    while (count > 0u) {
-        if (t == 0) qcount = 0u;
-        __syncthreads();
+    for (;;) {
+        const uint32_t count = qcnt[level % 3];
+        if (count == 0u) break;
+        if (t == 0) qcnt[(level + 2) % 3] = 0u;
         const uint32_t next_base = start + count;
-        const uint2 *qin = a.q[level & 1];
-        uint2 *qout = a.q[(level + 1) & 1];
-        for (uint32_t qi = t; qi < count; qi += kSmallThreads) {
-            const uint2 item = qin[qi];
+        for (uint32_t base = 0; base < count; base += kSmallThreads) {
+            const uint32_t qi = base + t;
+            const bool active = qi < count;
+            uint32_t ix = 0u, iy = 0u;
             int32_t C[W];
-            const int m = collapse_children<W>((int32_t)item.y, a.left, a.right, a.int_box, C);
-            uint32_t link[W];
-            const uint32_t inner = collapse_links<W>(C, m, a.first, a.last, a.leaf_max, link);
+            int m = 0;
+            uint32_t link[W], inner = 0u;
+            if (active) {
+                if (RESIDENT) {
+                    const uint32_t w = lq[(level & 1) * cap + qi];
+                    ix = w >> 16;
+                    iy = w & 0xFFFFu;
+                    m = W;
 #pragma unroll
-            for (int k = 0; k < W; ++k) {
-                if (!((inner >> k) & 1u)) continue;
-                const uint32_t slot = atomicAdd(&qcount, 1u);
-                const uint32_t nn = next_base + slot;
-                qout[slot] = make_uint2(nn, (uint32_t)C[k]);
-                if (a.parents) a.parents[nn] = (item.x << 3) | (uint32_t)k;
-                link[k] = nn;
+                    for (int k = W - 1; k >= 0; --k) {
+                        C[k] = wch[W * iy + k];
+                        if (C[k] == 0x7FFF) m = k;
+                    }
+                    inner = winner[iy];
+#pragma unroll
+                    for (int k = 0; k < W; ++k) {  // the links of the children that end as leaves
+                        link[k] = RG_EMPTY;
+                        if (k >= m || ((inner >> k) & 1u)) continue;
+                        if (C[k] < 0) {
+                            link[k] = rg_leaf((uint32_t)(-C[k] - 1), 1u);
+                        } else {
+                            const int32_t f = first[C[k]];
+                            link[k] = rg_leaf((uint32_t)f, (uint32_t)(last[C[k]] - f + 1));
+                        }
+                    }
+                } else {
+                    const uint2 item = a.q[level & 1][qi];
+                    ix = item.x;
+                    iy = item.y;
+                    m = collapse_children<W>((int32_t)iy, left, right, int_box, C);
+                    inner = collapse_links<W>(C, m, first, last, a.leaf_max, link);
+                }
             }
-            write_wide_node<W>(nodes + item.x, C, m, link, a.int_box, a.leaf_box);
+            // queue slots: a scan of the inner-child counts over the wave, one
+            // LDS add per wave
+            const uint32_t nc = __popc(inner);
+            uint32_t incl = nc;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(incl, o, 64);
+                if (lane >= o) incl += y;
+            }
+            const uint32_t total = __shfl(incl, 63, 64);
+            uint32_t wbase = 0u;
+            if (lane == 63 && total) wbase = atomicAdd(&qcnt[(level + 1) % 3], total);
+            wbase = __shfl(wbase, 63, 64);
+            uint32_t slot = wbase + incl - nc;
+            if (active) {
+#pragma unroll
+                for (int k = 0; k < W; ++k) {
+                    if (!((inner >> k) & 1u)) continue;
+                    const uint32_t nn = next_base + slot;
+                    if (RESIDENT) lq[((level + 1) & 1) * cap + slot] = (nn << 16) | (uint32_t)C[k];
+                    else a.q[(level + 1) & 1][slot] = make_uint2(nn, (uint32_t)C[k]);
+                    if (a.parents) a.parents[nn] = (ix << 3) | (uint32_t)k;
+                    link[k] = nn;
+                    ++slot;
+                }
+                write_wide_node<W>(nodes + ix, C, m, link, int_box, lbox);
+            }
         }
-        __syncthreads();
         start = next_base;
-        count = qcount;
         ++level;
         if (t == 0 && level <= RG_LEVELS_CAP) lstart[level] = start;
         __syncthreads();
@@ -1318,7 +1579,7 @@ constexpr int kRefitBatch = 32;
 struct RefitJob {
     void *nodes;
     RgTri *tris;
-    const uint32_t *levels;
+    const uint32_t *levels, *parents;
     RgBlasHdr *hdr;
     const float *verts;
     const uint32_t *idx;
@@ -1384,62 +1645,15 @@ __device__ inline void store_row(float *dst, const float *v) {
     }
 }
 
-// One node: every child box is recomputed from its triangles (a leaf) or
-// from the child node's own child boxes (already final: deeper levels go
-// first), all reads before the node's six box rows are written back with
-// vector stores (an empty slot is written its inverted box again).  Returns
-// the node's box in u.
-template <int W>
-__device__ inline void refit_node(RgNode<W> *nodes, uint32_t x, const RgTri *__restrict__ tris, float u[6]) {
-    RgNode<W> &nd = nodes[x];
-    float bx[6][W];
-#pragma unroll
-    for (int k = 0; k < W; ++k) {
-        const uint32_t c = nd.child[k];
-        float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
-        if (c != RG_EMPTY && rg_is_leaf(c)) {
-            const uint32_t first = rg_leaf_first(c), cnt = rg_leaf_count(c);
-            for (uint32_t j = 0; j < cnt; ++j) {
-                const RgTri &t = tris[first + j];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    b[a] = fminf(b[a], fminf(fminf(t.v[a], t.v[3 + a]), t.v[6 + a]));
-                    b[3 + a] = fmaxf(b[3 + a], fmaxf(fmaxf(t.v[a], t.v[3 + a]), t.v[6 + a]));
-                }
-            }
-        } else if (c != RG_EMPTY) {
-            const RgNode<W> &cn = nodes[c];
-#pragma unroll
-            for (int j = 0; j < W; ++j) {
-                if (cn.child[j] == RG_EMPTY) continue;
-                b[0] = fminf(b[0], cn.lo_x[j]); b[1] = fminf(b[1], cn.lo_y[j]); b[2] = fminf(b[2], cn.lo_z[j]);
-                b[3] = fmaxf(b[3], cn.hi_x[j]); b[4] = fmaxf(b[4], cn.hi_y[j]); b[5] = fmaxf(b[5], cn.hi_z[j]);
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < 6; ++a) bx[a][k] = b[a];
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        u[a] = INFINITY;
-        u[3 + a] = -INFINITY;
-#pragma unroll
-        for (int k = 0; k < W; ++k) {
-            u[a] = fminf(u[a], bx[a][k]);
-            u[3 + a] = fmaxf(u[3 + a], bx[3 + a][k]);
-        }
-    }
-    store_row<W>(nd.lo_x, bx[0]);
-    store_row<W>(nd.lo_y, bx[1]);
-    store_row<W>(nd.lo_z, bx[2]);
-    store_row<W>(nd.hi_x, bx[3]);
-    store_row<W>(nd.hi_y, bx[4]);
-    store_row<W>(nd.hi_z, bx[5]);
-}
-
 // Level `level` (counted from the root) of every bottom level deep enough,
-// its node range from the level table.  No atomics: launch order orders the
-// levels.  The root level writes the root box into the header.
+// its node range from the level table, deepest levels first (launch order
+// orders them; no atomics).  Each node's inner children have already put
+// their boxes into its rows (one launch earlier, see below); the node
+// computes the boxes of its leaf children from their triangles, writes its
+// rows back if it has any leaf child (vector stores), and puts the union of
+// its child boxes into its own slot of its parent's rows: so a level reads
+// only its own nodes, not its children's.  The root's union goes to the
+// header.  Boxes are min / max of coordinates, exact in any order.
 template <int W>
 __global__ void k_refit_level(RefitJobs jobs, int level) {
     const RefitJob &J = jobs.j[blockIdx.y];
@@ -1447,14 +1661,64 @@ __global__ void k_refit_level(RefitJobs jobs, int level) {
     RgNode<W> *nodes = reinterpret_cast<RgNode<W> *>(J.nodes);
     const uint32_t lo = J.levels[level], hi = J.levels[level + 1];
     for (uint32_t x = lo + blockIdx.x * blockDim.x + threadIdx.x; x < hi; x += gridDim.x * blockDim.x) {
-        float u[6];
-        refit_node<W>(nodes, x, J.tris, u);
-        if (level == 0 && x == 0) {
+        RgNode<W> &nd = nodes[x];
+        float bx[6][W];
+        uint32_t ch[W];
+        bool any_leaf = false;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            ch[k] = nd.child[k];
+            bx[0][k] = nd.lo_x[k]; bx[1][k] = nd.lo_y[k]; bx[2][k] = nd.lo_z[k];
+            bx[3][k] = nd.hi_x[k]; bx[4][k] = nd.hi_y[k]; bx[5][k] = nd.hi_z[k];
+        }
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const uint32_t c = ch[k];
+            if (c == RG_EMPTY || !rg_is_leaf(c)) continue;
+            any_leaf = true;
+            float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+            const uint32_t first = rg_leaf_first(c), cnt = rg_leaf_count(c);
+            for (uint32_t j = 0; j < cnt; ++j) {
+                const RgTri &t = J.tris[first + j];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    b[a] = fminf(b[a], fminf(fminf(t.v[a], t.v[3 + a]), t.v[6 + a]));
+                    b[3 + a] = fmaxf(b[3 + a], fmaxf(fmaxf(t.v[a], t.v[3 + a]), t.v[6 + a]));
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < 6; ++a) bx[a][k] = b[a];
+        }
+        float u[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            if (ch[k] == RG_EMPTY) continue;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                u[a] = fminf(u[a], bx[a][k]);
+                u[3 + a] = fmaxf(u[3 + a], bx[3 + a][k]);
+            }
+        }
+        if (any_leaf) {
+            store_row<W>(nd.lo_x, bx[0]);
+            store_row<W>(nd.lo_y, bx[1]);
+            store_row<W>(nd.lo_z, bx[2]);
+            store_row<W>(nd.hi_x, bx[3]);
+            store_row<W>(nd.hi_y, bx[4]);
+            store_row<W>(nd.hi_z, bx[5]);
+        }
+        const uint32_t p = J.parents[x];
+        if (p == RG_MISS) {  // the root
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 J.hdr->lo[k] = u[k];
                 J.hdr->hi[k] = u[3 + k];
             }
+        } else {
+            RgNode<W> &pd = nodes[p >> 3];
+            const uint32_t ps = p & 7u;
+            pd.lo_x[ps] = u[0]; pd.lo_y[ps] = u[1]; pd.lo_z[ps] = u[2];
+            pd.hi_x[ps] = u[3]; pd.hi_y[ps] = u[4]; pd.hi_z[ps] = u[5];
         }
     }
 }
@@ -1571,12 +1835,15 @@ __device__ inline float round_up(double x) {
 __global__ void k_inst_setup(const float *__restrict__ xform, const uint32_t *__restrict__ blas_id,
                              const uint32_t *__restrict__ inst_mat, const uint32_t *__restrict__ inst_flags,
                              const BlasInfo *__restrict__ blas, int64_t n, float *__restrict__ box,
-                             RgInst *__restrict__ recs, uint32_t *__restrict__ flags) {
+                             RgInst *__restrict__ recs, uint32_t *__restrict__ flags, float *__restrict__ xf_keep) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     double m[12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) m[k] = (double)xform[12 * i + k];
+    for (int k = 0; k < 12; ++k) {
+        m[k] = (double)xform[12 * i + k];
+        xf_keep[12 * i + k] = xform[12 * i + k];
+    }
     const BlasInfo &BI = blas[blas_id[i]];
     const RgBlasHdr &B = *reinterpret_cast<const RgBlasHdr *>(BI.hdr);
     if (B.status != 0u) atomicOr(flags, 1u);
@@ -1938,10 +2205,18 @@ rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t
         sa.nodes = nodes;
         sa.parents = parents;
         sa.levels = levels;
+        sa.flag_in = out->flag_in;
         sa.res = s.small;
-        if (width == 2) k_small_build<2><<<1, kSmallThreads, 0, st>>>(sa);
-        else if (width == 4) k_small_build<4><<<1, kSmallThreads, 0, st>>>(sa);
-        else k_small_build<8><<<1, kSmallThreads, 0, st>>>(sa);
+        const size_t lds = small_lds_bytes(n);
+        if (n <= kResidentMax) {
+            if (width == 2) k_small_build<2, true><<<1, kSmallThreads, lds, st>>>(sa);
+            else if (width == 4) k_small_build<4, true><<<1, kSmallThreads, lds, st>>>(sa);
+            else k_small_build<8, true><<<1, kSmallThreads, lds, st>>>(sa);
+        } else {
+            if (width == 2) k_small_build<2, false><<<1, kSmallThreads, lds, st>>>(sa);
+            else if (width == 4) k_small_build<4, false><<<1, kSmallThreads, lds, st>>>(sa);
+            else k_small_build<8, false><<<1, kSmallThreads, lds, st>>>(sa);
+        }
         RG_LAUNCH_CHECK();
         if (keep_stages) {
             if (n > 1) {
@@ -2046,12 +2321,34 @@ rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t
     return RG_OK;
 }
 
+// A pinned host buffer per calling thread, grown on demand and kept for the
+// thread's life: host tables go to the device and build summaries come back
+// through it with asynchronous copies, so a build waits for its stream once.
+// nullptr if pinned memory cannot be had (callers then copy from pageable
+// memory, which waits at each copy).
+static char *pinned_staging(size_t bytes) {
+    thread_local char *buf = nullptr;
+    thread_local size_t cap = 0;
+    if (bytes > cap) {
+        if (buf) (void)hipHostFree(buf);
+        buf = nullptr;
+        cap = 0;
+        const size_t want = ((bytes > (64u << 10) ? bytes : (64u << 10)) + 4095u) & ~(size_t)4095u;
+        void *p = nullptr;
+        if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) return nullptr;
+        buf = (char *)p;
+        cap = want;
+    }
+    return buf;
+}
+
 rg_status rg_lbvh_finish(RgLbvhOut *out, bool with_nodes) {
     if (!out->pending) return RG_OK;
     out->pending = false;
     SmallResult res;
     memcpy(&res, out->deferred, sizeof(res));
     if (res.err) return RG_ERR_HIP;  // never: every inner node gets a box
+    out->flag = res.flag;
     out->depth = with_nodes ? (int32_t)res.depth : 0;
     out->n_nodes = with_nodes ? (int64_t)res.n_nodes : 0;
     for (int k = 0; k < 3; ++k) {
@@ -2113,11 +2410,11 @@ uint64_t tlas_out_bytes(int64_t n, int w, uint64_t *nodes_off, uint64_t *inst_of
 
 uint64_t tlas_scratch_bytes(int64_t n, int32_t n_blas, int32_t builder) {
     RgArena a{nullptr, 0, 0};
-    a.take<char>(12 * (size_t)n + sizeof(BlasInfo) * (size_t)(n_blas > 0 ? n_blas : 1));  // host tables
+    const size_t t4 = (4 * (size_t)n + 7) & ~size_t(7);
+    // host tables: matrices, three uint32 tables, bottom-level addresses, flag word
+    a.take<char>(48 * (size_t)n + 3 * t4 + sizeof(BlasInfo) * (size_t)(n_blas > 0 ? n_blas : 1) + 8);
     a.take<float>(6 * n);       // instance boxes
     a.take<RgInst>(n);          // unsorted records
-    a.take<uint32_t>(8);        // flags
-    a.take<uint32_t>(n);        // instance flags
     return a.used + rg_lbvh_scratch_bytes(n, builder);
 }
 
@@ -2196,7 +2493,12 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
     // boxes hold and the input check is read with its summary at the one
     // wait of the call; a larger build checks the input first
     const bool small = o.builder == RG_BUILDER_LBVH && n_tris <= kSmallMax;
-    uint32_t summary[11] = {};  // a one-workgroup build's summary, then the flags word
+    // a one-workgroup build's summary, then the flags word (pinned: the copies
+    // back do not wait)
+    uint32_t local[11] = {};
+    uint32_t *summary = (uint32_t *)pinned_staging(64);
+    if (!summary) summary = local;
+    summary[10] = 0u;
     if (!small) {
         RG_HIP(hipMemcpyAsync(summary + 10, flags, 4, hipMemcpyDeviceToHost, st));
         RG_HIP(hipStreamSynchronize(st));
@@ -2286,6 +2588,7 @@ rg_status rg_refit_blas_many(rg_blas *blas, int32_t n_blas, const float *const *
             J.nodes = base + B.nodes_off;
             J.tris = (RgTri *)(base + B.tris_off);
             J.levels = (const uint32_t *)(base + B.levels_off);
+            J.parents = (const uint32_t *)(base + B.parents_off);
             J.hdr = (RgBlasHdr *)base;
             J.verts = verts[b0 + k];
             J.idx = idx[b0 + k];
@@ -2404,43 +2707,61 @@ rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xfo
     hipStream_t st = (hipStream_t)stream;
     RgArena arena{(char *)scratch, scratch_bytes, 0};
     float *d_xf = (float *)((char *)out_buf + xo);  // kept: the trace calls recompute hits from it
-    // the host tables go over in one copy: blas ids, materials, flags, bottom levels
-    const size_t t_bytes = 4 * (size_t)n_inst * (inst_flags ? 3 : 2) + sizeof(BlasInfo) * (size_t)n_blas;
+    // everything from the host goes over in one copy, in this layout (byte
+    // offsets, 8-aligned): matrices, blas ids, materials, flags, bottom-level
+    // addresses, a zero word (the invalid-bottom-level flag); the summary of
+    // the build comes back behind it
+    const size_t n8 = (size_t)n_inst;
+    const size_t off_bid = 48 * n8, off_mat = off_bid + ((4 * n8 + 7) & ~size_t(7));
+    const size_t off_fl = off_mat + ((4 * n8 + 7) & ~size_t(7));
+    const size_t off_info = off_fl + (inst_flags ? ((4 * n8 + 7) & ~size_t(7)) : 0);
+    const size_t off_flag = off_info + sizeof(BlasInfo) * (size_t)n_blas;
+    const size_t t_bytes = off_flag + 8;
     char *d_tab = arena.take<char>(t_bytes);
     float *d_box = arena.take<float>(6 * n_inst);
     RgInst *d_rec = arena.take<RgInst>(n_inst);
-    uint32_t *d_flags = arena.take<uint32_t>(8);
-    uint32_t *d_bid = (uint32_t *)d_tab, *d_mat = d_bid + n_inst;
-    uint32_t *d_iflags = inst_flags ? d_mat + n_inst : nullptr;
-    BlasInfo *d_info = (BlasInfo *)(d_tab + 4 * (size_t)n_inst * (inst_flags ? 3 : 2));
-    std::vector<char> tab(t_bytes);
-    memcpy(tab.data(), blas_id, 4 * (size_t)n_inst);
-    memcpy(tab.data() + 4 * (size_t)n_inst, inst_material, 4 * (size_t)n_inst);
-    if (inst_flags) memcpy(tab.data() + 8 * (size_t)n_inst, inst_flags, 4 * (size_t)n_inst);
-    memcpy(tab.data() + 4 * (size_t)n_inst * (inst_flags ? 3 : 2), info.data(), sizeof(BlasInfo) * (size_t)n_blas);
-    k_fill_u32<<<1, 64, 0, st>>>(d_flags, 0u, 1);
-    RG_HIP(hipMemcpyAsync(d_xf, xform, 48 * n_inst, hipMemcpyHostToDevice, st));
-    RG_HIP(hipMemcpyAsync(d_tab, tab.data(), t_bytes, hipMemcpyHostToDevice, st));
-    k_inst_setup<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(d_xf, d_bid, d_mat, d_iflags, d_info, n_inst, d_box,
-                                                                    d_rec, d_flags);
+    std::vector<char> fallback;
+    char *tab = pinned_staging(t_bytes + 64);
+    if (!tab) {
+        fallback.resize(t_bytes + 64);
+        tab = fallback.data();
+    }
+    memcpy(tab, xform, 48 * n8);
+    memcpy(tab + off_bid, blas_id, 4 * n8);
+    memcpy(tab + off_mat, inst_material, 4 * n8);
+    if (inst_flags) memcpy(tab + off_fl, inst_flags, 4 * n8);
+    memcpy(tab + off_info, info.data(), sizeof(BlasInfo) * (size_t)n_blas);
+    memset(tab + off_flag, 0, 8);
+    uint32_t *summary = (uint32_t *)(tab + t_bytes);  // a one-workgroup build's summary, or the flag word
+    uint32_t *d_flag = (uint32_t *)(d_tab + off_flag);
+    RG_HIP(hipMemcpyAsync(d_tab, tab, t_bytes, hipMemcpyHostToDevice, st));
+    k_inst_setup<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(
+        (const float *)d_tab, (const uint32_t *)(d_tab + off_bid), (const uint32_t *)(d_tab + off_mat),
+        inst_flags ? (const uint32_t *)(d_tab + off_fl) : nullptr, (const BlasInfo *)(d_tab + off_info), n_inst,
+        d_box, d_rec, d_flag, d_xf);
     RG_LAUNCH_CHECK();
     char *base = (char *)out_buf;
     RgLbvhOut lo;
-    uint32_t summary[11];  // a one-workgroup build's summary, then the flags word
     lo.deferred = summary;
+    lo.flag_in = d_flag;
     rg_status r = rg_lbvh_build(d_box, n_inst, w, 1, o.builder, o.radius, base + no, nullptr, nullptr, arena, st, &lo,
                                 false, nullptr, nullptr, nullptr, nullptr);
-    if (r != RG_OK) return r;
+    if (r != RG_OK) {
+        (void)hipStreamSynchronize(st);  // the staging buffer may still be in use by a copy
+        return r;
+    }
     k_reorder_inst<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(d_rec, lo.ids, n_inst, (RgInst *)(base + io),
                                                                       (uint32_t *)(base + ro));
+    const bool deferred = lo.pending;  // else the flag word comes back on its own
     const hipError_t le = hipGetLastError();
-    const hipError_t ce = le == hipSuccess ? hipMemcpyAsync(summary + 10, d_flags, 4, hipMemcpyDeviceToHost, st)
-                                           : le;
+    const hipError_t ce = (le == hipSuccess && !deferred)
+                              ? hipMemcpyAsync(summary, d_flag, 4, hipMemcpyDeviceToHost, st)
+                              : le;
     RG_HIP(hipStreamSynchronize(st));  // the one wait of the call (also before any error return: the
                                        // summary copy targets this frame)
     RG_HIP(ce);
     if ((r = rg_lbvh_finish(&lo, true)) != RG_OK) return r;
-    if (summary[10]) return RG_ERR_INVALID_ARG;  // a bottom level was refitted to invalid vertex data
+    if (deferred ? lo.flag : summary[0]) return RG_ERR_INVALID_ARG;  // a bottom level was refitted to invalid vertex data
     out->buf = out_buf;
     out->nodes_off = no;
     out->inst_off = io;

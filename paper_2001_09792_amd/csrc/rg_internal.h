@@ -149,6 +149,11 @@ struct RgLbvhOut {
     uint32_t *deferred = nullptr;
     bool pending = false;
     const float *root_dev = nullptr;  // the root box (lo xyz, hi xyz) on the device, once the stream gets there
+    // Optional device word that a one-workgroup build returns with its
+    // summary (read when the build runs, after the caller's earlier steps on
+    // the stream); rg_lbvh_finish stores it in `flag`.
+    const uint32_t *flag_in = nullptr;
+    uint32_t flag = 0;
 };
 // Fills depth, n_nodes and the root box of a pending one-workgroup build
 // from its summary (after the caller's wait); RG_ERR_HIP if it failed.
