@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(256) k_refine(RefineArgs a) {
 // / instance entries before a wave runs that code.  Incoherent ray batches
 // gain from waiting lanes; the coherent rays of frames do not.
 rg_trace_tune g_tune[RG_TUNE_SCOPES] = {
-    {8, 20, 16, 12, 6},  // RG_TUNE_TRACE: rg_trace_closest / any / counts (5 waves per SIMD fit)
+    {16, 20, 16, 12, 6},  // RG_TUNE_TRACE: rg_trace_closest / any / counts (5 waves per SIMD fit)
     {8, 16, 16, 1, 1},   // RG_TUNE_FRAME: rg_render, rg_batch_render
     {8, 16, 16, 8, 1},   // RG_TUNE_ENGINE: rg_engine_step
 };

@@ -36,6 +36,12 @@ constexpr uint32_t kMaxSteps = 1u << 22;
 // u = 2^-24): the subtraction, the hardware reciprocal (1 ulp) and the product
 // each add error to t, and the near distance may err the other way.
 constexpr float kFarWiden = 2.0f * (5.0f * 5.9604645e-8f) / (1.0f - 5.0f * 5.9604645e-8f);
+// Slab distances are computed as fma(plane, inv, -c): one rounding less in
+// the relative error than (plane - o) * inv, but c = o * inv is rounded (by
+// up to u |o inv|) and so is the shifted constant (u |c'|).  Shifting c by
+// 3 u |o| |inv| (slightly more) towards the side that widens the slab keeps
+// the lo-plane and hi-plane distances on the safe side of the exact ones.
+constexpr float kSlabShift = 3.0f * 5.9604645e-8f * 1.01f;
 
 #define RG_GLOBAL __attribute__((address_space(1)))
 #define RG_LDS __attribute__((address_space(3)))
@@ -168,6 +174,14 @@ struct Stack {
     __device__ inline uint32_t pop() {
         --sp;
         return sp < n_lds ? lds[sp * kThreads] : priv[sp - n_lds];
+    }
+    // Whether every active lane of the wave has m free LDS entries.
+    __device__ inline bool room(int m) const { return __ballot(sp + m > n_lds) == 0ull; }
+    // With room(): the entry goes to the top of the LDS part whether or not
+    // it is kept; `keep` decides whether it stays (no branch per entry).
+    __device__ inline void push_if(uint32_t v, bool keep) {
+        lds[sp * kThreads] = v;
+        sp += keep ? 1 : 0;
     }
 };
 
@@ -322,17 +336,33 @@ struct Tracer {
             if (MODE == kCounts) ++h.n_nodes;
             float tn[W];
             uint32_t ch[W];
+            // slab distances as one fused plane * inv - c each.  The constant
+            // c of the lo planes and that of the hi planes sit on either side
+            // of o * inv, kSlabShift |o| |inv| apart from it, on the side that
+            // widens the slab whatever the sign of inv, so the rounding of
+            // o * inv cannot narrow an interval; the far widening covers the
+            // relative error as before
+            float cl[3], chh[3];
+            {
+                const float o_[3] = {ox, oy, oz}, i_[3] = {ix, iy, iz};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float c = o_[a] * i_[a], sh_ = kSlabShift * fabsf(o_[a]);
+                    cl[a] = fmaf(sh_, i_[a], c);
+                    chh[a] = fmaf(-sh_, i_[a], c);
+                }
+            }
 #pragma unroll
             for (int k = 0; k < W; ++k) {
                 const float lx = __uint_as_float(w[k]), ly = __uint_as_float(w[W + k]);
                 const float lz = __uint_as_float(w[2 * W + k]), hx = __uint_as_float(w[3 * W + k]);
                 const float hy = __uint_as_float(w[4 * W + k]), hz = __uint_as_float(w[5 * W + k]);
-                float x0 = (lx - ox) * ix, x1 = (hx - ox) * ix;
-                float y0 = (ly - oy) * iy, y1 = (hy - oy) * iy;
-                float z0 = (lz - oz) * iz, z1 = (hz - oz) * iz;
+                const float x0 = fmaf(lx, ix, -cl[0]), x1 = fmaf(hx, ix, -chh[0]);
+                const float y0 = fmaf(ly, iy, -cl[1]), y1 = fmaf(hy, iy, -chh[1]);
+                const float z0 = fmaf(lz, iz, -cl[2]), z1 = fmaf(hz, iz, -chh[2]);
                 float n_ = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), tlo));
                 float f_ = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fmaxf(z0, z1));
-                f_ = f_ + fabsf(f_) * kFarWiden;
+                f_ = fmaf(fabsf(f_), kFarWiden, f_);
                 f_ = fminf(f_, thi);
                 ch[k] = w[6 * W + k];
                 bool hit = (n_ <= f_) && (ch[k] != RG_EMPTY);
@@ -340,8 +370,23 @@ struct Tracer {
             }
             if (!ANY) sort_children<W>(tn, ch);
             // the nearest hit child continues; the others are pushed far first
+            // (when the wave's LDS stacks have room for all of them: without
+            // a branch per child)
             uint32_t next = RG_EMPTY;
-            if (ANY) {
+            if (st.room(W - 1)) {  // wave-uniform
+                if (ANY) {
+#pragma unroll
+                    for (int k = 0; k < W; ++k) {
+                        const bool hk = tn[k] != INFINITY;
+                        if (k > 0) st.push_if(ch[k], hk && next != RG_EMPTY);
+                        next = (hk && next == RG_EMPTY) ? ch[k] : next;
+                    }
+                } else {
+#pragma unroll
+                    for (int k = W - 1; k >= 1; --k) st.push_if(ch[k], tn[k] != INFINITY);
+                    next = tn[0] != INFINITY ? ch[0] : RG_EMPTY;
+                }
+            } else if (ANY) {
 #pragma unroll
                 for (int k = 0; k < W; ++k) {
                     if (tn[k] != INFINITY) {
@@ -444,7 +489,10 @@ struct Tracer {
                     const bool front = (det > 0.0f) != ((cull & kFlip) != 0u);
                     if (cull & (front ? RG_RAY_CULL_FRONT : RG_RAY_CULL_BACK)) continue;
                 }
-                float tl = T / det;
+                // t by the hardware reciprocal (1 ulp) and one product: up to
+                // 1.5 ulp from T / det, inside the float32 band the parity
+                // checks allow around t; the reported t is recomputed in double
+                float tl = T * __builtin_amdgcn_rcpf(det);
                 float tw = t0 + tl;
                 if (!(tw >= R.tmin) || !(tw <= best)) continue;
                 if (OPT && alpha && !alpha_open(alpha[tri.prim], alpha_level, V / det, Wv / det)) continue;

@@ -10,7 +10,7 @@ world->object matrix stored in float32 (its inverse computed in double and
 rounded), the object-space origin is slid to where the ray enters the mesh's
 box, and the triangle is tested in the ray-space shear of Woop, Benthin &
 Wald (JCGT 2013): three 2-D edge functions U, V, W of the sheared vertices,
-their sum det, and T with t = T / det measured from the slid origin.
+their sum det, and T with t = T * (1 / det) measured from the slid origin.
 """
 import numpy as np
 
@@ -85,7 +85,7 @@ def trace_tri(xform, box_lo, box_hi, o, d, tmin, tmax, tri):
     poss = (U > 0) | (V > 0) | (W > 0)
     hit = ~(negs & poss) & (det != 0)
     with np.errstate(divide="ignore", invalid="ignore"):
-        tl = T / det
+        tl = T * (f32(1.0) / det)            # the GPU's reciprocal, then a product
         u = V / det
         v = W / det
     return dict(hit=hit, t=t0 + tl, u=u, v=v, det=det)
