@@ -183,17 +183,22 @@ __device__ inline uint64_t morton_key(const float *__restrict__ b, const uint32_
     return (spread21(q[0]) << 2) | (spread21(q[1]) << 1) | spread21(q[2]);
 }
 
+// Also clears the sort's digit totals (2 x 256 words) for its first pass.
 __global__ void k_morton(const float *__restrict__ box, int64_t n, const uint32_t *__restrict__ bounds,
-                         uint64_t *__restrict__ keys, uint32_t *__restrict__ ids) {
+                         uint64_t *__restrict__ keys, uint32_t *__restrict__ ids, uint32_t *__restrict__ totals) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < 512) totals[i] = 0u;
     if (i >= n) return;
     keys[i] = morton_key(box + 6 * i, bounds);
     ids[i] = (uint32_t)i;
 }
 
 // -------------------------------------------------- 3. LSD radix sort
+// Per pass: digit counts per block (ghist, digit-major) and per digit over
+// all blocks (totals), then k_sort_offsets turns ghist into each block's
+// first position per digit, then the stable scatter.
 __global__ void k_sort_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
-                            uint32_t *__restrict__ ghist, int nblocks) {
+                            uint32_t *__restrict__ ghist, int nblocks, uint32_t *__restrict__ totals) {
     __shared__ uint32_t h[256];
     int t = threadIdx.x;
     h[t] = 0;
@@ -206,57 +211,88 @@ __global__ void k_sort_hist(const uint64_t *__restrict__ keys, int64_t n, int sh
     }
     __syncthreads();
     ghist[(int64_t)t * nblocks + blockIdx.x] = h[t];
+    if (h[t]) atomicAdd(&totals[t], h[t]);
 }
 
-// Exclusive scan in place by one block.  Each thread takes kScanPer
-// consecutive elements per pass (their loads in flight together), scans them
-// serially, and the block scans the per-thread totals.
+// Exclusive scan in place.  A block scans a chunk of kScanChunk elements at
+// a time: each thread takes kScanPer consecutive elements (their loads in
+// flight together), scans them serially, and the block scans the per-thread
+// totals.
 constexpr int kScanPer = 4;
+constexpr int kScanChunk = kScanThreads * kScanPer;
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_excl(uint32_t *data, int64_t m) {
-    __shared__ uint32_t wsum[kScanThreads / 64];
-    __shared__ uint32_t carry;
+// Scans data[base, base + kScanChunk) (clipped to m), adding `carry`;
+// returns the chunk's total (every thread of the block).
+__device__ inline uint32_t scan_chunk(uint32_t *data, int64_t m, int64_t base, uint32_t carry, uint32_t *wsum) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    if (t == 0) carry = 0;
+    const int64_t i0 = base + (int64_t)t * kScanPer;
+    uint32_t v[kScanPer];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) v[k] = (i0 + k < m) ? data[i0 + k] : 0u;
+    uint32_t tot = 0u;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) tot += v[k];
+    uint32_t x = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
     __syncthreads();
-    for (int64_t base = 0; base < m; base += (int64_t)kScanThreads * kScanPer) {
-        const int64_t i0 = base + (int64_t)t * kScanPer;
-        uint32_t v[kScanPer];
-#pragma unroll
-        for (int k = 0; k < kScanPer; ++k) v[k] = (i0 + k < m) ? data[i0 + k] : 0u;
-        uint32_t tot = 0u;
-#pragma unroll
-        for (int k = 0; k < kScanPer; ++k) tot += v[k];
-        uint32_t x = tot;
+    if (w == 0) {
+        uint32_t s = lane < kScanThreads / 64 ? wsum[lane] : 0u;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
+            const uint32_t y = __shfl_up(s, o, 64);
+            if (lane >= o) s += y;
         }
-        if (lane == 63) wsum[w] = x;
-        __syncthreads();
-        if (w == 0) {
-            uint32_t s = lane < kScanThreads / 64 ? wsum[lane] : 0u;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t y = __shfl_up(s, o, 64);
-                if (lane >= o) s += y;
-            }
-            if (lane < kScanThreads / 64) wsum[lane] = s;  // inclusive wave totals
-        }
-        __syncthreads();
-        const uint32_t c = carry;
-        uint32_t run = c + (w > 0 ? wsum[w - 1] : 0u) + x - tot;
-#pragma unroll
-        for (int k = 0; k < kScanPer; ++k) {
-            if (i0 + k < m) data[i0 + k] = run;
-            run += v[k];
-        }
-        __syncthreads();
-        if (t == kScanThreads - 1) carry = c + wsum[kScanThreads / 64 - 1];
-        __syncthreads();
+        if (lane < kScanThreads / 64) wsum[lane] = s;  // inclusive wave totals
     }
+    __syncthreads();
+    uint32_t run = carry + (w > 0 ? wsum[w - 1] : 0u) + x - tot;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (i0 + k < m) data[i0 + k] = run;
+        run += v[k];
+    }
+    const uint32_t total = wsum[kScanThreads / 64 - 1];
+    __syncthreads();
+    return total;
 }
+
+// The whole array by one block, chunk after chunk.
+__global__ void __launch_bounds__(kScanThreads) k_scan_excl(uint32_t *data, int64_t m) {
+    __shared__ uint32_t wsum[kScanThreads / 64];
+    uint32_t carry = 0u;
+    for (int64_t base = 0; base < m; base += kScanChunk) carry += scan_chunk(data, m, base, carry, wsum);
+}
+
+// One block per digit d: ghist[d][*] becomes the exclusive scan over the
+// blocks plus the count of all smaller digits.  Clears next_totals[d] for the
+// following pass.
+__global__ void __launch_bounds__(kScanThreads) k_sort_offsets(uint32_t *ghist, int nblocks,
+                                                               const uint32_t *__restrict__ totals,
+                                                               uint32_t *__restrict__ next_totals) {
+    __shared__ uint32_t wsum[kScanThreads / 64];
+    __shared__ uint32_t below;
+    const int d = blockIdx.x, t = threadIdx.x;
+    if (t < 64) {
+        uint32_t x = 0u;
+        for (int k = t; k < d; k += 64) x += totals[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if (t == 0) {
+            below = x;
+            next_totals[d] = 0u;
+        }
+    }
+    __syncthreads();
+    uint32_t carry = below;
+    uint32_t *col = ghist + (int64_t)d * nblocks;
+    for (int64_t b0 = 0; b0 < nblocks; b0 += kScanChunk) carry += scan_chunk(col, nblocks, b0, carry, wsum);
+}
+
 
 // Stable scatter: within each 256-element chunk, lanes with equal digits are
 // matched with 8 ballots, ranked by lane order, and offset by the counts of
@@ -374,8 +410,8 @@ __global__ void k_karras(const uint64_t *__restrict__ keys, int64_t n, int32_t *
 }
 
 // -------------------------------------------------------- 5. box refit
-// Inner boxes are computed level by level from the root's depth order
-// (k_boxes_at below), after k_leaf_boxes has gathered the leaf boxes.
+// Inner boxes come from the leaf ranges (k_range_* below), after
+// k_leaf_boxes has gathered the leaf boxes in leaf order.
 
 // --------------------------------------------------- 6. wide collapse
 __device__ inline float surface_area(const float *b) {
@@ -384,7 +420,7 @@ __device__ inline float surface_area(const float *b) {
 }
 
 constexpr int kCollapseRing = 16;   // per-level bookkeeping slots on the device
-constexpr int kCollapseBatch = 4;   // levels launched between host reads (< kCollapseRing - 2)
+constexpr int kCollapseBatch = 8;   // levels launched between host reads (< kCollapseRing - 2)
 
 // The children of the wide node that stands for binary inner node b: b's
 // two children, then repeatedly the inner one of largest surface area opened
@@ -488,17 +524,40 @@ __device__ inline void write_wide_node(RgNode<W> *nd, const int32_t C[W], int m,
     for (int q = 0; q < 2 * W; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
 }
 
+// The children every inner node of the binary hierarchy would get as the
+// root of a wide node (the opening order depends on that node alone), for
+// all m inner nodes at once: binary ids (wch), the links of the children
+// that end as leaves (wlink, RG_EMPTY past the last child) and the mask of
+// those that stay inner nodes (winner).  The level-by-level collapse then
+// waits on one load round for them instead of the whole opening sequence.
+template <int W>
+__global__ void k_wide_plan(const int32_t *__restrict__ left, const int32_t *__restrict__ right,
+                            const int32_t *__restrict__ first, const int32_t *__restrict__ last,
+                            const float *__restrict__ int_box, int leaf_max, int64_t m, int32_t *__restrict__ wch,
+                            uint32_t *__restrict__ wlink, uint8_t *__restrict__ winner) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int32_t C[W];
+    uint32_t link[W];
+    const int n_ch = collapse_children<W>((int32_t)i, left, right, int_box, C);
+    winner[i] = (uint8_t)collapse_links<W>(C, n_ch, first, last, leaf_max, link);
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        wch[W * i + k] = k < n_ch ? C[k] : 0;
+        wlink[W * i + k] = link[k];
+    }
+}
+
 // One thread per node of the level (queue items: node index, binary node it
 // stands for).  Children that stay inner nodes join the next level's queue:
 // one counter add per wave, and a child's node index is the next level's
 // first index plus its queue slot.
 template <int W>
-__global__ void k_collapse(const int32_t *__restrict__ left, const int32_t *__restrict__ right,
-                           const int32_t *__restrict__ first, const int32_t *__restrict__ last,
-                           const float *__restrict__ int_box, const float *__restrict__ leaf_box,
-                           int leaf_max, const uint2 *__restrict__ q_in, uint2 *__restrict__ q_out,
-                           uint32_t *ring, int level, RgNode<W> *__restrict__ nodes,
-                           uint32_t *__restrict__ parents, uint32_t cap) {
+__global__ void k_collapse(const int32_t *__restrict__ wch, const uint32_t *__restrict__ wlink,
+                           const uint8_t *__restrict__ winner, const float *__restrict__ int_box,
+                           const float *__restrict__ leaf_box, const uint2 *__restrict__ q_in,
+                           uint2 *__restrict__ q_out, uint32_t *ring, int level, RgNode<W> *__restrict__ nodes,
+                           uint32_t *__restrict__ parents, uint32_t *__restrict__ levels, uint32_t cap) {
     // ring: [0, R) node count of level l at l % R, [R, 2R) first node index of
     // level l at R + l % R, [2R] error flags.  A level's kernel sets up the
     // next level's first index and clears the count two levels ahead, so
@@ -510,6 +569,9 @@ __global__ void k_collapse(const int32_t *__restrict__ left, const int32_t *__re
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ring[kCollapseRing + (level + 1) % kCollapseRing] = next_base;
         ring[(level + 2) % kCollapseRing] = 0u;
+        // the level table (first node of each level, then the node count):
+        // launches past the last level write the node count again
+        if (levels && level + 1 <= RG_LEVELS_CAP) levels[level + 1] = next_base;
     }
     uint32_t *err = ring + 2 * kCollapseRing;
     const int lane = threadIdx.x & 63;
@@ -519,14 +581,21 @@ __global__ void k_collapse(const int32_t *__restrict__ left, const int32_t *__re
         const uint32_t qi = base + threadIdx.x;
         const bool active = qi < cnt;
         int32_t C[W];
+        uint32_t link[W];
         uint2 item = make_uint2(0u, 0u);
         int m = 0;
+        uint32_t inner = 0u;
         if (active) {
             item = q_in[qi];
-            m = collapse_children<W>((int32_t)item.y, left, right, int_box, C);
+            const int64_t b = item.y;
+            inner = winner[b];
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                C[k] = wch[W * b + k];
+                link[k] = wlink[W * b + k];
+                if (((inner >> k) & 1u) || link[k] != RG_EMPTY) m = k + 1;
+            }
         }
-        uint32_t link[W];
-        const uint32_t inner = active ? collapse_links<W>(C, m, first, last, leaf_max, link) : 0u;
         // queue slots: an exclusive scan of the inner-child counts over the wave
         const uint32_t nc = __popc(inner);
         uint32_t incl = nc;
@@ -576,11 +645,12 @@ __global__ void k_single_root(const float *__restrict__ leaf_box, RgNode<W> *nod
     nd->pad[k] = 0u;
 }
 
-__global__ void k_collapse_init(uint2 *q, uint32_t *ring, uint32_t *parents) {
+__global__ void k_collapse_init(uint2 *q, uint32_t *ring, uint32_t *parents, uint32_t *levels) {
     q[0] = make_uint2(0u, 0u);
     for (int k = 0; k <= 2 * kCollapseRing; ++k) ring[k] = 0u;
     ring[0] = 1u;  // level 0: the root, node 0
     if (parents) parents[0] = RG_MISS;  // the root
+    if (levels) levels[0] = 0u;
 }
 
 // ------------------------------------- whole build in one workgroup
@@ -1321,28 +1391,8 @@ __global__ void __launch_bounds__(kThreads) k_depth_scatter(int64_t m, const int
     order[hstart[d] + at] = (int32_t)x;
 }
 
-// Per-depth passes over the nodes of one depth (order[0 .. count)), run
-// deepest first: the children of a node are deeper, so their values are final.
-__global__ void k_boxes_at(const int32_t *__restrict__ order, int64_t count, const int32_t *__restrict__ left,
-                           const int32_t *__restrict__ right, float *int_box, const float *__restrict__ leaf_box) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    const int32_t x = order[i];
-    const int32_t c[2] = {left[x], right[x]};
-    float b[12];
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const float *src = c[k] < 0 ? leaf_box + 6 * (int64_t)(-c[k] - 1) : int_box + 6 * (int64_t)c[k];
-#pragma unroll
-        for (int q = 0; q < 6; ++q) b[6 * k + q] = src[q];
-    }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        int_box[6 * (int64_t)x + q] = fminf(b[q], b[6 + q]);
-        int_box[6 * (int64_t)x + 3 + q] = fmaxf(b[3 + q], b[9 + q]);
-    }
-}
-
+// Per-depth pass over the nodes of one depth (order[0 .. count)), run
+// deepest first: the children of a node are deeper, so their sizes are final.
 __global__ void k_sizes_at(const int32_t *__restrict__ order, int64_t count, const int32_t *__restrict__ left,
                            const int32_t *__restrict__ right, int32_t *size) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1359,6 +1409,103 @@ __global__ void k_leaf_boxes(const float *__restrict__ prim_box, const uint32_t 
     const uint32_t src = ids[i];
 #pragma unroll
     for (int k = 0; k < 6; ++k) leaf_box[6 * i + k] = prim_box[6 * (int64_t)src + k];
+}
+
+// ---------------------------------------------- inner boxes from ranges
+// Every inner node of the radix tree covers a contiguous range of leaves
+// (first .. last, leaf order), and its box is the union of their boxes.  The
+// unions come from three tables, so the boxes are computed in three kinds of
+// launches with no dependence on the tree's depth: per block of
+// kRangeLeaves leaves, the prefix and the suffix unions inside the block;
+// a sparse table over the blocks (level j: the union of 2^j consecutive
+// blocks); then one thread per inner node combines at most four entries (or
+// loops over the at most kRangeLeaves leaves of a range inside one block).
+// min / max are exact, so the boxes are the same as any order of unions.
+constexpr int kRangeLeaves = 16;
+
+__device__ inline void box_union(float u[6], const float *__restrict__ b) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        u[k] = fminf(u[k], b[k]);
+        u[3 + k] = fmaxf(u[3 + k], b[3 + k]);
+    }
+}
+
+__global__ void __launch_bounds__(kThreads) k_range_blocks(const float *__restrict__ leaf_box, int64_t n,
+                                                           float *__restrict__ pre, float *__restrict__ suf,
+                                                           float *__restrict__ table) {
+    __shared__ float b[kThreads * 6];
+    const int t = threadIdx.x;
+    const int64_t i = blockIdx.x * (int64_t)kThreads + t;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) b[6 * t + k] = i < n ? leaf_box[6 * i + k] : (k < 3 ? INFINITY : -INFINITY);
+    __syncthreads();
+    if (i >= n) return;
+    const int g0 = t & ~(kRangeLeaves - 1), r = t & (kRangeLeaves - 1);
+    float p[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    float q[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int k = 0; k <= r; ++k) box_union(p, b + 6 * (g0 + k));
+    for (int k = r; k < kRangeLeaves; ++k) box_union(q, b + 6 * (g0 + k));  // past n: empty boxes
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        pre[6 * i + k] = p[k];
+        suf[6 * i + k] = q[k];
+    }
+    if (r == 0) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) table[6 * (i / kRangeLeaves) + k] = q[k];  // the whole block
+    }
+}
+
+// Levels j0 + 1 .. j0 + kRangeStride of the sparse table over nb blocks
+// from level j0 (one launch): entry b of level j0 + r (b + 2^(j0 + r) <= nb)
+// is the union of level j0's entries b + k 2^j0, k < 2^r.  Thread
+// (r - 1, b).
+constexpr int kRangeStride = 4;
+__global__ void k_range_levels(float *table, int64_t nb, int j0, int top) {
+    const int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int r = (int)(x / nb) + 1;
+    const int64_t b = x % nb;
+    const int j = j0 + r;
+    if (r > kRangeStride || j > top || b + (1ll << j) > nb) return;
+    const int64_t step = 1ll << j0;
+    const float *src = table + 6 * ((int64_t)j0 * nb + b);
+    float u[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int k = 0; k < (1 << r); ++k) box_union(u, src + 6 * step * k);
+    float *y = table + 6 * ((int64_t)j * nb + b);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) y[k] = u[k];
+}
+
+__global__ void k_range_boxes(const int32_t *__restrict__ first, const int32_t *__restrict__ last, int64_t m,
+                              const float *__restrict__ leaf_box, const float *__restrict__ pre,
+                              const float *__restrict__ suf, const float *__restrict__ table, int64_t nb,
+                              float *__restrict__ int_box) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int32_t f = first[i], l = last[i];
+    const int32_t bf = f / kRangeLeaves, bl = l / kRangeLeaves;
+    float u[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    if (bf == bl) {
+        for (int32_t k = f; k <= l; ++k) box_union(u, leaf_box + 6 * (int64_t)k);
+    } else {
+        box_union(u, suf + 6 * (int64_t)f);
+        box_union(u, pre + 6 * (int64_t)l);
+        if (bl - bf >= 2) {  // whole blocks bf + 1 .. bl - 1: two overlapping table entries
+            const int32_t a = bf + 1, len = bl - 1 - a + 1;
+            const int j = 31 - __clz(len);
+            box_union(u, table + 6 * ((int64_t)j * nb + a));
+            box_union(u, table + 6 * ((int64_t)j * nb + (a + len - (1 << j))));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) int_box[6 * i + k] = u[k];
+}
+
+int64_t range_levels(int64_t nb) {
+    int64_t L = 1;
+    while ((1ll << L) <= nb) ++L;
+    return L;  // levels 0 .. L - 1: 2^(L-1) <= nb
 }
 
 __global__ void __launch_bounds__(64) k_treelet(const int32_t *__restrict__ order, int32_t *left, int32_t *right,
@@ -1927,9 +2074,12 @@ uint64_t align256(uint64_t x) { return (x + 255u) & ~uint64_t(255); }
 struct LbvhScratch {
     float *leaf_box, *int_box;
     uint64_t *keys, *keys2;
-    uint32_t *ids, *ids2, *hist, *bounds, *qcount, *flags;
+    uint32_t *ids, *ids2, *hist, *totals, *bounds, *qcount, *flags;
     int32_t *left, *right, *pint, *pleaf, *first, *last;
     uint2 *q0, *q1;
+    int32_t *wch;       // wide-node plan: W children, W links per inner node (W up to 8), inner masks
+    uint32_t *wlink;
+    uint8_t *winner;
     // clustering only
     int32_t *cid[2], *nearest, *rank, *size;
     float *cbox[2];
@@ -1938,6 +2088,9 @@ struct LbvhScratch {
     // restructuring also takes rank, size and cbox[0]
     int32_t *height, *order;
     uint32_t *hcount, *hcursor, *hstart, *hmax;
+    // inner boxes from leaf ranges (radix tree): prefix / suffix unions,
+    // sparse table over blocks of kRangeLeaves leaves
+    float *pre, *suf, *rtab;
     SmallResult *small;  // summary of a one-workgroup build
 };
 
@@ -1951,6 +2104,7 @@ bool carve(RgArena &a, int64_t n, int32_t builder, LbvhScratch &s) {
     s.ids = a.take<uint32_t>(n);
     s.ids2 = a.take<uint32_t>(n);
     s.hist = a.take<uint32_t>(256 * nb);
+    s.totals = a.take<uint32_t>(512);
     s.bounds = a.take<uint32_t>(8);
     s.qcount = a.take<uint32_t>(2 * kCollapseRing + 8);
     s.flags = a.take<uint32_t>(8);
@@ -1962,6 +2116,9 @@ bool carve(RgArena &a, int64_t n, int32_t builder, LbvhScratch &s) {
     s.last = a.take<int32_t>(ni);
     s.q0 = a.take<uint2>(ni);
     s.q1 = a.take<uint2>(ni);
+    s.wch = a.take<int32_t>(8 * ni);
+    s.wlink = a.take<uint32_t>(8 * ni);
+    s.winner = a.take<uint8_t>(ni);
     if (builder == RG_BUILDER_PLOC) {
         int64_t pb = (n + kPlocT - 1) / kPlocT + 1;
         for (int k = 0; k < 2; ++k) {
@@ -1985,6 +2142,12 @@ bool carve(RgArena &a, int64_t n, int32_t builder, LbvhScratch &s) {
     s.hcursor = a.take<uint32_t>(n + 1);
     s.hstart = a.take<uint32_t>(n + 1);
     s.hmax = a.take<uint32_t>(8);
+    if (builder != RG_BUILDER_PLOC) {
+        const int64_t nbr = (n + kRangeLeaves - 1) / kRangeLeaves;
+        s.pre = a.take<float>(6 * n);
+        s.suf = a.take<float>(6 * n);
+        s.rtab = a.take<float>(6 * nbr * range_levels(nbr));
+    }
     s.small = a.take<SmallResult>(1);
     return !a.overflow();
 }
@@ -2125,7 +2288,9 @@ rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes_v,
     }
     uint32_t *ring = s.qcount;
     const uint32_t cap = (uint32_t)(n - 1);
-    k_collapse_init<<<1, 1, 0, st>>>(s.q0, ring, parents);
+    k_wide_plan<W><<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>(s.left, s.right, s.first, s.last, s.int_box,
+                                                                     leaf_max, n - 1, s.wch, s.wlink, s.winner);
+    k_collapse_init<<<1, 1, 0, st>>>(s.q0, ring, parents, levels);
     RG_LAUNCH_CHECK();
     uint2 *q[2] = {s.q0, s.q1};
     // levels go in batches; the host learns their sizes after each batch.  A
@@ -2140,9 +2305,9 @@ rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes_v,
             unsigned blocks = rg_blocks((int64_t)(bound ? bound : 1), kThreads);
             if (blocks > 1024) blocks = 1024;
             const int level = d + j;
-            k_collapse<W><<<blocks, kThreads, 0, st>>>(s.left, s.right, s.first, s.last, s.int_box, s.leaf_box,
-                                                        leaf_max, q[level & 1], q[(level + 1) & 1], ring, level,
-                                                        nodes, parents, cap);
+            k_collapse<W><<<blocks, kThreads, 0, st>>>(s.wch, s.wlink, s.winner, s.int_box, s.leaf_box,
+                                                        q[level & 1], q[(level + 1) & 1], ring, level, nodes,
+                                                        parents, levels, cap);
             bound = std::min<uint64_t>((uint64_t)cap, bound * (uint64_t)W);
         }
         RG_LAUNCH_CHECK();
@@ -2163,10 +2328,7 @@ rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes_v,
         if (d > 4096) return RG_ERR_HIP;  // never expected
     }
     d = levels_n;
-    const uint32_t nn = starts.back();  // levels are numbered contiguously
-    if (levels && starts.size() <= (size_t)RG_LEVELS_CAP + 1)
-        RG_HIP(hipMemcpyAsync(levels, starts.data(), 4 * starts.size(), hipMemcpyHostToDevice, st));
-    RG_HIP(hipStreamSynchronize(st));
+    const uint32_t nn = starts.back();  // levels are numbered contiguously (the kernels wrote the level table)
     if (starts.size() != (size_t)d + 1) return RG_ERR_HIP;  // never expected
     *depth = d;
     *n_nodes = nn;
@@ -2251,14 +2413,16 @@ rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t
     if (bb > 256) bb = 256;
     k_centre_bounds<<<bb, kThreads, 0, st>>>(prim_box, n, s.bounds);
     RG_LAUNCH_CHECK();
-    k_morton<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(prim_box, n, s.bounds, s.keys, s.ids);
+    k_morton<<<rg_blocks(n < 512 ? 512 : n, kThreads), kThreads, 0, st>>>(prim_box, n, s.bounds, s.keys, s.ids,
+                                                                           s.totals);
     RG_LAUNCH_CHECK();
     // 8 passes of 8 bits; the result lands back in keys/ids
     uint64_t *ka = s.keys, *kb = s.keys2;
     uint32_t *ia = s.ids, *ib = s.ids2;
     for (int shift = 0; shift < 64; shift += 8) {
-        k_sort_hist<<<nblocks, kThreads, 0, st>>>(ka, n, shift, s.hist, nblocks);
-        k_scan_excl<<<1, kScanThreads, 0, st>>>(s.hist, (int64_t)256 * nblocks);
+        uint32_t *tot = s.totals + 256 * ((shift >> 3) & 1), *tot_next = s.totals + 256 * (((shift >> 3) + 1) & 1);
+        k_sort_hist<<<nblocks, kThreads, 0, st>>>(ka, n, shift, s.hist, nblocks, tot);
+        k_sort_offsets<<<256, kScanThreads, 0, st>>>(s.hist, nblocks, tot, tot_next);
         k_sort_scatter<<<nblocks, kThreads, 0, st>>>(ka, ia, kb, ib, n, shift, s.hist, nblocks);
         RG_LAUNCH_CHECK();
         uint64_t *tk = ka; ka = kb; kb = tk;
@@ -2276,16 +2440,15 @@ rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t
         }
         k_leaf_boxes<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(prim_box, ia, n, s.leaf_box);
         RG_LAUNCH_CHECK();
-        if (n > 1) {  // inner boxes level by level, deepest first
-            DepthOrder o;
-            rg_status r = depth_order(s, n - 1, st, o);
-            if (r != RG_OK) return r;
-            for (int64_t d = o.dmax; d >= 0; --d)
-                k_boxes_at<<<rg_blocks(o.cnt[d], kThreads), kThreads, 0, st>>>(s.order + o.start[d], o.cnt[d],
-                                                                                s.left, s.right, s.int_box,
-                                                                                s.leaf_box);
+        if (n > 1) {  // inner boxes from the leaf ranges: no host step
+            const int64_t nbr = (n + kRangeLeaves - 1) / kRangeLeaves;
+            k_range_blocks<<<rg_blocks(n, kThreads), kThreads, 0, st>>>(s.leaf_box, n, s.pre, s.suf, s.rtab);
+            const int top = (int)range_levels(nbr) - 1;
+            for (int j0 = 0; j0 < top; j0 += kRangeStride)
+                k_range_levels<<<rg_blocks(kRangeStride * nbr, kThreads), kThreads, 0, st>>>(s.rtab, nbr, j0, top);
+            k_range_boxes<<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>(s.first, s.last, n - 1, s.leaf_box,
+                                                                            s.pre, s.suf, s.rtab, nbr, s.int_box);
             RG_LAUNCH_CHECK();
-            RG_HIP(hipStreamSynchronize(st));  // the host vectors of `o` go away here
         }
         if (builder == RG_BUILDER_TREELET && n > 1) {
             rg_status r = treelet_build(n, radius, ia, ib, s, st);
@@ -2311,8 +2474,14 @@ rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t
         if (r != RG_OK) return r;
     }
     out->root_dev = n > 1 ? s.int_box : s.leaf_box;
+    if (out->deferred) {  // the root box comes back with the caller's wait, into the summary's box words
+        static_assert(offsetof(SmallResult, lo) == 16, "summary layout");
+        RG_HIP(hipMemcpyAsync(out->deferred + 4, out->root_dev, 24, hipMemcpyDeviceToHost, st));
+        out->pending_box = true;
+        return RG_OK;
+    }
     float rb[6];
-    RG_HIP(hipMemcpyAsync(rb, n > 1 ? s.int_box : s.leaf_box, 24, hipMemcpyDeviceToHost, st));
+    RG_HIP(hipMemcpyAsync(rb, out->root_dev, 24, hipMemcpyDeviceToHost, st));
     RG_HIP(hipStreamSynchronize(st));
     for (int k = 0; k < 3; ++k) {
         out->lo[k] = rb[k];
@@ -2343,6 +2512,15 @@ static char *pinned_staging(size_t bytes) {
 }
 
 rg_status rg_lbvh_finish(RgLbvhOut *out, bool with_nodes) {
+    if (out->pending_box) {
+        out->pending_box = false;
+        float rb[6];
+        memcpy(rb, out->deferred + 4, sizeof(rb));
+        for (int k = 0; k < 3; ++k) {
+            out->lo[k] = rb[k];
+            out->hi[k] = rb[3 + k];
+        }
+    }
     if (!out->pending) return RG_OK;
     out->pending = false;
     SmallResult res;
@@ -2489,17 +2667,17 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
     k_fill_u32<<<1, 64, 0, st>>>(flags, 0u, 1);
     k_tri_boxes<<<rg_blocks(n_tris, kThreads), kThreads, 0, st>>>(verts, n_verts, idx, n_tris, pbox, flags);
     RG_LAUNCH_CHECK();
-    // a build in one workgroup (small meshes, linear BVH) runs on whatever the
-    // boxes hold and the input check is read with its summary at the one
-    // wait of the call; a larger build checks the input first
-    const bool small = o.builder == RG_BUILDER_LBVH && n_tris <= kSmallMax;
-    // a one-workgroup build's summary, then the flags word (pinned: the copies
-    // back do not wait)
+    // the build's summary (one-workgroup builds) or root box, then the flags
+    // word: pinned, so the copies back do not wait
     uint32_t local[11] = {};
     uint32_t *summary = (uint32_t *)pinned_staging(64);
     if (!summary) summary = local;
     summary[10] = 0u;
-    if (!small) {
+    // the linear build runs on whatever the boxes hold (out-of-range indices
+    // were clamped, and its steps stay in bounds for any key values): the
+    // input check comes back with the call's last wait.  The clustering and
+    // restructuring builders take only checked input.
+    if (o.builder != RG_BUILDER_LBVH) {
         RG_HIP(hipMemcpyAsync(summary + 10, flags, 4, hipMemcpyDeviceToHost, st));
         RG_HIP(hipStreamSynchronize(st));
         if (summary[10]) return RG_ERR_INVALID_ARG;
@@ -2510,7 +2688,10 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
     rg_status r = rg_lbvh_build(pbox, n_tris, w, l, o.builder, o.radius, base + no, (uint32_t *)(base + po),
                                 (uint32_t *)(base + lvo), arena, st, &lo, false, nullptr, nullptr, nullptr, nullptr);
     if (r != RG_OK) {
-        if (lo.pending) hipStreamSynchronize(st);  // the summary copy targets this frame
+        // an invalid input is reported as such, also when it upset the build
+        const hipError_t fe = hipMemcpyAsync(summary + 10, flags, 4, hipMemcpyDeviceToHost, st);
+        (void)hipStreamSynchronize(st);  // the summary copies target this frame
+        if (fe == hipSuccess && summary[10]) return RG_ERR_INVALID_ARG;
         return r;
     }
     k_reorder_tris<<<rg_blocks(n_tris, kThreads), kThreads, 0, st>>>(
@@ -2519,8 +2700,7 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
     k_blas_header<<<1, 1, 0, st>>>((RgBlasHdr *)base, (uint64_t)(base + no), (uint64_t)(base + to),
                                    (uint64_t)(base + mo), (uint64_t)(base + so), lo.root_dev);
     const hipError_t le = hipGetLastError();
-    const hipError_t ce = (le == hipSuccess && small) ?
-                          hipMemcpyAsync(summary + 10, flags, 4, hipMemcpyDeviceToHost, st) : le;
+    const hipError_t ce = le == hipSuccess ? hipMemcpyAsync(summary + 10, flags, 4, hipMemcpyDeviceToHost, st) : le;
     RG_HIP(hipStreamSynchronize(st));
     RG_HIP(ce);
     if ((r = rg_lbvh_finish(&lo, true)) != RG_OK) return r;

@@ -154,6 +154,9 @@ struct RgLbvhOut {
     // the stream); rg_lbvh_finish stores it in `flag`.
     const uint32_t *flag_in = nullptr;
     uint32_t flag = 0;
+    // Set by a larger build given `deferred`: the root box is on its way to
+    // deferred[4..9]; rg_lbvh_finish (after the caller's wait) reads it.
+    bool pending_box = false;
 };
 // Fills depth, n_nodes and the root box of a pending one-workgroup build
 // from its summary (after the caller's wait); RG_ERR_HIP if it failed.

@@ -196,6 +196,29 @@ def test_bad_inputs_are_rejected():
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("builder", ["lbvh", "treelet"])
+def test_bad_inputs_are_rejected_large(builder):
+    """Above the one-workgroup size the linear build runs before its input
+    check comes back (the clustering and restructuring builders check
+    first): a non-finite coordinate or an index out of range is still an
+    error of the call, and the device stays usable."""
+    import torch
+    import paper_2001_09792_amd as rg
+    mesh = sg.random_soup(6000, 31)
+    v, i = _dev(mesh)
+    bad = v.clone()
+    bad[40, 2] = float("inf")
+    with pytest.raises(rg.RgError):
+        rg.build_blas(bad, i, builder=builder)
+    bad_i = i.clone()
+    bad_i[300, 0] = 10 ** 7
+    with pytest.raises(rg.RgError):
+        rg.build_blas(v, bad_i, builder=builder)
+    b = rg.build_blas(v, i, builder=builder)
+    assert b.n_tris == 6000
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("name,rounds", [("soup1500", 1), ("soup1500", 3), ("small", 2), ("torus_small", 2),
                                          ("two", 3), ("dupes", 2), ("three", 1)])
 def test_treelet_stages_match_definition(name, rounds):
