@@ -210,16 +210,27 @@ const char *rg_last_error(void);
  * Errors: RG_ERR_INVALID_ARG for n_tris < 1 or > 2^28, bad opts, NULL out. */
 rg_status rg_blas_sizes(int64_t n_tris, const rg_build_opts *opts, rg_sizes *out /*host*/);
 
-/* Builds a binary BVH (Morton codes of triangle-box centres, LSD radix sort
- * with LDS ranking, then opts' builder: Karras's radix tree with a bottom-up
- * box refit, or locally-ordered clustering) and collapses it into
- * `width`-wide nodes with leaves of at most leaf_max
- * triangles; writes nodes, triangles in leaf order and per-triangle
- * materials into out_buf.  verts: float[n_verts][3]; idx: uint32[n_tris][3];
- * prim_material: uint16[n_tris] or NULL.  Synchronous (waits for `stream`).
+/* The bottom level of the two-level structure, built from a mesh's vertex
+ * data (section 1: the first of the two steps, an acceleration structure per
+ * mesh).  Builds a binary BVH (Morton codes of triangle-box centres, LSD
+ * radix sort with LDS ranking, then opts' builder: Karras's radix tree with
+ * inner boxes from the leaf ranges, locally-ordered clustering, or the radix
+ * tree restructured by treelets) and collapses it into `width`-wide nodes
+ * with leaves of at most leaf_max triangles; writes a header, nodes,
+ * triangles in leaf order, per-triangle materials, per-node parents and the
+ * level table into out_buf (offsets in *out).  verts: device
+ * float[n_verts][3]; idx: device uint32[n_tris][3]; prim_material: device
+ * uint16[n_tris] or NULL.  out_buf (rg_blas_sizes bytes) belongs to the
+ * caller and must outlive every top level, trace and render over it;
+ * scratch (rg_blas_sizes' scratch_bytes) is free again when the call
+ * returns.  Synchronous (returns after `stream` has finished the build);
+ * meshes of up to 4,096 triangles build in one workgroup.
  * Errors: RG_ERR_INVALID_ARG for NULL pointers, sizes out of range, an index
- * >= n_verts or a non-finite vertex (checked on the device, reported after the
- * sync); RG_ERR_OUT_OF_MEMORY if out_bytes / scratch_bytes are too small. */
+ * >= n_verts or a non-finite vertex (checked on the device: the clustering
+ * and treelet builders wait for the check before building; the linear build
+ * runs on the clamped input and reports it at its one final wait, leaving
+ * out_buf unusable); RG_ERR_OUT_OF_MEMORY if out_bytes / scratch_bytes are
+ * too small. */
 rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx, int64_t n_tris,
                         const uint16_t *prim_material, const rg_build_opts *opts,
                         void *out_buf, uint64_t out_bytes, void *scratch, uint64_t scratch_bytes,
@@ -289,13 +300,19 @@ rg_status rg_blas_state(const rg_blas *blas /*host*/, float *lo /*host [3]*/, fl
 /* --------------------------------------------------------- top level */
 rg_status rg_tlas_sizes(int64_t n_inst, const rg_build_opts *opts, rg_sizes *out /*host*/);
 
-/* Builds the top level over n_inst instances.  blas: host array of n_blas
- * descriptors (all of the same width as opts); xform: host float[n_inst][3][4]
- * object->world; blas_id, inst_material: host uint32[n_inst].  Instance boxes
- * are the 8 transformed corners of the bottom level's root box, computed in
- * double and rounded outward to float; the world->object inverse is computed
- * in double and stored as float.  The bottom levels' root boxes are read
- * from their headers on the device.  Synchronous.
+/* The top level of the two-level structure, built from the instances'
+ * transformation matrices (section 1: the second step, over the bottom
+ * levels).  Builds the top level over n_inst instances.  blas: host array of
+ * n_blas descriptors (all of the same width as opts); xform: host
+ * float[n_inst][3][4] object->world, row-major; blas_id, inst_material: host
+ * uint32[n_inst].  Instance boxes are the 8 transformed corners of the bottom
+ * level's root box, computed in double and rounded outward to float; the
+ * world->object inverse is computed in double and stored as float; a copy of
+ * the matrices stays in out_buf (the trace calls recompute hits from it).
+ * The bottom levels' root boxes are read from their headers on the device.
+ * out_buf belongs to the caller and must outlive every trace and render over
+ * it; the bottom levels must outlive it.  Synchronous: one upload of the host
+ * tables and one wait (up to 4,096 instances build in one workgroup).
  * Errors: RG_ERR_INVALID_ARG for NULL pointers, blas_id out of range, a
  * non-finite or singular matrix, mixed widths, or a bottom level whose last
  * refit found invalid input (its header's status word is set). */
@@ -403,21 +420,28 @@ rg_status rg_trace_tuning(int32_t scope, const rg_trace_tune *set /*host, nullab
                           rg_trace_tune *get /*host, nullable*/);
 
 /* ---------------------------------------------------- ray generation */
-/* Pinhole camera rays, one per pixel centre, y = 0 the top row, vertical
- * field of view: f = normalize(target-eye), r = normalize(f x up), u = r x f,
- * d = normalize(f + sx r + sy u), tmin = 0, tmax = +inf.  Ray i is pixel i
- * (row-major).  `rays` points to 8 float arrays of width*height entries.
- * Asynchronous. */
+/* The ray-generation step of a dispatch (section 1: a ray-generation shader
+ * starts the rays of the frame): pinhole camera rays, one per pixel centre,
+ * y = 0 the top row, vertical field of view: f = normalize(target-eye),
+ * r = normalize(f x up), u = r x f, d = normalize(f + sx r + sy u), tmin = 0,
+ * tmax = +inf.  Ray i is pixel i (row-major).  `rays` points to 8 device
+ * float arrays (ox oy oz dx dy dz tmin tmax) of width*height entries, owned
+ * by the caller.  Asynchronous.  Errors: RG_ERR_INVALID_ARG for a NULL
+ * camera or array, width or height < 1, or more than 2^31 pixels. */
 rg_status rg_camera_rays(const rg_camera *cam /*host*/, int32_t width, int32_t height,
                          float *const rays[8], void *stream);
 
-/* Ambient-occlusion rays: for each input ray i (n of them) whose hit is not a
- * miss, 8 cosine-weighted directions around the faced normal (Malley's
+/* Rays spawned at the hits of a first pass (section 1: a closest-hit
+ * shader may spawn further rays), here the incoherent ambient-occlusion rays
+ * of the measured workload: for each input ray i (n of them) whose hit is not
+ * a miss, 8 cosine-weighted directions around the faced normal (Malley's
  * method in the Duff et al. 2017 basis), uniforms from SplitMix64 keyed by
  * (seed, i*8+k), origin offset 1e-4*max(1,|p|inf) along the faced normal,
  * tmin 0, tmax `ao_tmax`.  Output is compacted in input order: out_rays
- * (8 float arrays of capacity 8n), out_src uint32[8n] = (i*8 + k), and the
- * count in *out_count (device uint32).  Asynchronous. */
+ * (8 device float arrays of capacity 8n), out_src uint32[8n] = (i*8 + k), and
+ * the count in *out_count (device uint32).  Asynchronous.  Errors:
+ * RG_ERR_INVALID_ARG for NULL pointers or n < 0; RG_ERR_OUT_OF_MEMORY for
+ * scratch shorter than rg_ao_rays_scratch. */
 rg_status rg_ao_rays(const rg_tlas *tlas, rg_rays rays, int64_t n, const uint32_t *hit_inst,
                      const uint32_t *hit_prim, const float *hit_t, uint64_t seed, float ao_tmax,
                      float *const out_rays[8], uint32_t *out_src, uint32_t *out_count,
