@@ -377,6 +377,44 @@ def build_tlas(blas: Sequence[Blas], xform, blas_id, inst_mat, width: int = 4, s
     return Tlas(buf, d, blas)
 
 
+class TlasBuilder:
+    """Rebuilds one top level over the same bottom levels, instance table and
+    materials with new matrices, frame after frame, into one output buffer:
+    the per-frame top-level update of a dynamic scene without a new buffer or
+    new descriptor tables per call.  Every Tlas it returns shares that buffer,
+    so the next build replaces the previous one (the caller orders it after
+    the traces that still read it, e.g. on the same stream)."""
+
+    def __init__(self, blas: Sequence[Blas], blas_id, inst_mat, width: int = 4, builder: str = "lbvh",
+                 radius: int = 0, inst_flags=None, stream=None):
+        self.blas = list(blas)
+        self.blas_id = np.ascontiguousarray(blas_id, np.uint32)
+        self.inst_mat = np.ascontiguousarray(inst_mat, np.uint32)
+        self.n = int(self.blas_id.shape[0])
+        self.flags = np.ascontiguousarray(inst_flags, np.uint32).reshape(self.n) if inst_flags is not None else None
+        self.opts = _opts(width, 1, builder, radius)
+        s = Sizes()
+        _check("rg_tlas_sizes", _lib.rg_tlas_sizes(self.n, ctypes.byref(self.opts), ctypes.byref(s)))
+        dev = self.blas[0].buf.device
+        self.buf = _bytes(s.bytes, dev)
+        self.scratch = _bytes(s.scratch_bytes, dev)
+        self.descs = (BlasDesc * len(self.blas))(*[b.desc for b in self.blas])
+        self.stream = stream
+
+    def build(self, xform) -> Tlas:
+        """xform: host float32 [I,3,4] object->world."""
+        xf = np.ascontiguousarray(xform, np.float32).reshape(-1, 12)
+        if xf.shape[0] != self.n:
+            raise ValueError(f"{xf.shape[0]} matrices for {self.n} instances")
+        d = TlasDesc()
+        _check("rg_build_tlas", _lib.rg_build_tlas_ex(
+            self.descs, len(self.blas), xf.ctypes.data, self.blas_id.ctypes.data, self.inst_mat.ctypes.data,
+            self.flags.ctypes.data if self.flags is not None else None, self.n, ctypes.byref(self.opts),
+            _ptr(self.buf), self.buf.numel(), _ptr(self.scratch), self.scratch.numel(), _stream(self.stream),
+            ctypes.byref(d)))
+        return Tlas(self.buf, d, self.blas)
+
+
 def upload_scene(scene, width: int = 4, leaf_max: int = 4, device="cuda", builder: str = "lbvh",
                  radius: int = 0, tlas_builder: Optional[str] = None, inst_flags=None) -> Tlas:
     """Builds every mesh and the instance level of a scene object with

@@ -653,6 +653,106 @@ __global__ void k_collapse_init(uint2 *q, uint32_t *ring, uint32_t *parents, uin
     if (levels) levels[0] = 0u;
 }
 
+// ------------------------------------------------ top-level instances
+struct BlasInfo {
+    uint64_t nodes, tris, hdr;
+};
+
+__device__ inline float round_down(double x) {
+    float f = (float)x;
+    if ((double)f > x) f = nextafterf(f, -INFINITY);
+    return f;
+}
+__device__ inline float round_up(double x) {
+    float f = (float)x;
+    if ((double)f < x) f = nextafterf(f, INFINITY);
+    return f;
+}
+
+// Instance i: its world box (the 8 transformed corners of the bottom level's
+// root box, in double, rounded outward), its record (the world->object
+// inverse in double, stored as float) and a copy of its matrix.  The bottom
+// level's root box and the status of its last refit come from its header on
+// the device (a refit updates them without a host round trip).
+struct InstTables {
+    const float *xform;
+    const uint32_t *blas_id, *inst_mat, *inst_flags;  // inst_flags nullable
+    const BlasInfo *blas;
+    uint32_t *flags;   // bit 0: a bottom level's last refit saw invalid input
+    float *xf_keep;
+};
+
+// A top level of up to kResidentMax instances built in one launch with its
+// instance step (RgLbvhOut::tlas_fuse points to one).
+struct TlasFuse {
+    InstTables T;
+    RgInst *rec_tmp, *recs_out;
+    uint32_t *rec_of;
+};
+
+__device__ inline void inst_setup_one(const InstTables &T, int64_t i, float box[6], RgInst &r) {
+    double m[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        m[k] = (double)T.xform[12 * i + k];
+        T.xf_keep[12 * i + k] = T.xform[12 * i + k];
+    }
+    const BlasInfo &BI = T.blas[T.blas_id[i]];
+    const RgBlasHdr &B = *reinterpret_cast<const RgBlasHdr *>(BI.hdr);
+    if (B.status != 0u) atomicOr(T.flags, 1u);
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int c = 0; c < 8; ++c) {
+        double p[3] = {(double)((c & 1) ? B.hi[0] : B.lo[0]), (double)((c & 2) ? B.hi[1] : B.lo[1]),
+                       (double)((c & 4) ? B.hi[2] : B.lo[2])};
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            double w = m[4 * q] * p[0] + m[4 * q + 1] * p[1] + m[4 * q + 2] * p[2] + m[4 * q + 3];
+            mn[q] = fmin(mn[q], w);
+            mx[q] = fmax(mx[q], w);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        box[q] = round_down(mn[q]);
+        box[3 + q] = round_up(mx[q]);
+    }
+    // inverse of the linear part (adjugate over determinant), in double
+    double a = m[0], b = m[1], c = m[2], d = m[4], e = m[5], f = m[6], g = m[8], h = m[9], k = m[10];
+    double A = e * k - f * h, Bc = -(d * k - f * g), Cc = d * h - e * g;
+    double det = a * A + b * Bc + c * Cc;
+    double inv[9] = {A / det, -(b * k - c * h) / det, (b * f - c * e) / det,
+                     Bc / det, (a * k - c * g) / det, -(a * f - c * d) / det,
+                     Cc / det, -(a * h - b * g) / det, (a * e - b * d) / det};
+#pragma unroll
+    for (int q = 0; q < 9; ++q) r.inv[q] = (float)inv[q];
+    r.p[0] = T.xform[12 * i + 3];
+    r.p[1] = T.xform[12 * i + 7];
+    r.p[2] = T.xform[12 * i + 11];
+    r.nodes = BI.nodes;
+    r.tris = BI.tris;
+    r.hdr = BI.hdr;
+    r.mat = T.inst_mat[i];
+    r.inst = (uint32_t)i;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        r.blo[q] = B.lo[q];
+        r.bhi[q] = B.hi[q];
+    }
+    r.flags = (T.inst_flags ? T.inst_flags[i] : RG_INST_MASK_ALL) | (B.alpha ? RG_INST_ALPHA : 0u);
+    r.pad = 0u;
+}
+
+__global__ void k_inst_setup(InstTables T, int64_t n, float *__restrict__ box, RgInst *__restrict__ recs) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float b[6];
+    RgInst r;
+    inst_setup_one(T, i, b, r);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) box[6 * i + q] = b[q];
+    recs[i] = r;
+}
+
 // ------------------------------------- whole build in one workgroup
 // For up to kSmallMax primitives (top levels, small meshes) the steps above
 // run in one workgroup of one launch, the keys in LDS: the same centre
@@ -678,8 +778,15 @@ struct SmallArgs {
     uint2 *q[2];
     void *nodes;                    // nullable: binary hierarchy only
     uint32_t *parents, *levels;     // nullable
-    const uint32_t *flag_in;        // nullable: a word of an earlier step returned with the summary
+    const uint32_t *flag_in;        // nullable: a word of an earlier step (or of this kernel) returned with the summary
     SmallResult *res;
+    // a top level built in the same launch (TLAS): each primitive is an
+    // instance whose box and record the kernel computes from the tables; the
+    // records land in rec_tmp (input order), then recs_out (leaf order) with
+    // rec_of (each instance's record)
+    InstTables inst;
+    RgInst *rec_tmp, *recs_out;
+    uint32_t *rec_of;
 };
 
 // LDS of the one-workgroup build (dynamic).  Up to kResidentMax primitives
@@ -692,8 +799,9 @@ constexpr size_t kSmallLdsGlobal = (size_t)kSmallMax * (8 + 4);
 size_t small_lds_bytes(int64_t n) { return n <= kResidentMax ? kSmallLdsResident : kSmallLdsGlobal; }
 static_assert(8 * 2 + 1 <= 24, "the wide-children table fits the primitive-box area (W <= 8)");
 
-template <int W, bool RESIDENT>
+template <int W, bool RESIDENT, bool TLAS = false>
 __global__ void __launch_bounds__(kSmallThreads) k_small_build(SmallArgs a) {
+    static_assert(RESIDENT || !TLAS, "a fused top level is built resident");
     extern __shared__ uint64_t small_lds[];
     __shared__ uint32_t bnd[6];
     __shared__ uint32_t done[2][kSmallMax / 32];
@@ -731,8 +839,14 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_build(SmallArgs a) {
         float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
         for (int i = t; i < n; i += kSmallThreads) {
             float b[6];
+            if (TLAS) {
+                RgInst r;
+                inst_setup_one(a.inst, i, b, r);
+                a.rec_tmp[i] = r;
+            } else {
 #pragma unroll
-            for (int q = 0; q < 6; ++q) b[q] = a.prim_box[6 * i + q];
+                for (int q = 0; q < 6; ++q) b[q] = a.prim_box[6 * i + q];
+            }
             if (RESIDENT) {
 #pragma unroll
                 for (int q = 0; q < 6; ++q) pbox[6 * i + q] = b[q];
@@ -796,6 +910,10 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_build(SmallArgs a) {
         if (t < n) {
             a.ids[t] = v0;
             if (a.keys_out) a.keys_out[t] = k0;
+            if (TLAS) {  // the record of the instance at leaf position t (written above, before the barriers)
+                a.recs_out[t] = a.rec_tmp[v0];
+                a.rec_of[v0] = (uint32_t)t;
+            }
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
                 const float b = pbox[6 * v0 + q];
@@ -919,7 +1037,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_build(SmallArgs a) {
             a.res->hi[z] = root[3 + z];
         }
         a.res->err = (n > 1 && !(done[0][0] & 1u)) ? 1u : 0u;
-        a.res->flag = a.flag_in ? *a.flag_in : 0u;
+        a.res->flag = a.flag_in ? __hip_atomic_load(a.flag_in, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
     }
     if (!a.nodes) return;
     RgNode<W> *nodes = reinterpret_cast<RgNode<W> *>(a.nodes);
@@ -1962,82 +2080,6 @@ void refit_deep(const rg_blas &b, uint32_t *need, uint32_t *arrived, hipStream_t
 }
 
 // ----------------------------------------------------------- top level
-struct BlasInfo {
-    uint64_t nodes, tris, hdr;
-};
-
-__device__ inline float round_down(double x) {
-    float f = (float)x;
-    if ((double)f > x) f = nextafterf(f, -INFINITY);
-    return f;
-}
-__device__ inline float round_up(double x) {
-    float f = (float)x;
-    if ((double)f < x) f = nextafterf(f, INFINITY);
-    return f;
-}
-
-// The bottom level's root box and the status of its last refit come from its
-// header on the device (a refit updates them without a host round trip).
-__global__ void k_inst_setup(const float *__restrict__ xform, const uint32_t *__restrict__ blas_id,
-                             const uint32_t *__restrict__ inst_mat, const uint32_t *__restrict__ inst_flags,
-                             const BlasInfo *__restrict__ blas, int64_t n, float *__restrict__ box,
-                             RgInst *__restrict__ recs, uint32_t *__restrict__ flags, float *__restrict__ xf_keep) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double m[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-        m[k] = (double)xform[12 * i + k];
-        xf_keep[12 * i + k] = xform[12 * i + k];
-    }
-    const BlasInfo &BI = blas[blas_id[i]];
-    const RgBlasHdr &B = *reinterpret_cast<const RgBlasHdr *>(BI.hdr);
-    if (B.status != 0u) atomicOr(flags, 1u);
-    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int c = 0; c < 8; ++c) {
-        double p[3] = {(double)((c & 1) ? B.hi[0] : B.lo[0]), (double)((c & 2) ? B.hi[1] : B.lo[1]),
-                       (double)((c & 4) ? B.hi[2] : B.lo[2])};
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            double w = m[4 * r] * p[0] + m[4 * r + 1] * p[1] + m[4 * r + 2] * p[2] + m[4 * r + 3];
-            mn[r] = fmin(mn[r], w);
-            mx[r] = fmax(mx[r], w);
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        box[6 * i + r] = round_down(mn[r]);
-        box[6 * i + 3 + r] = round_up(mx[r]);
-    }
-    // inverse of the linear part (adjugate over determinant), in double
-    double a = m[0], b = m[1], c = m[2], d = m[4], e = m[5], f = m[6], g = m[8], h = m[9], k = m[10];
-    double A = e * k - f * h, Bc = -(d * k - f * g), Cc = d * h - e * g;
-    double det = a * A + b * Bc + c * Cc;
-    double inv[9] = {A / det, -(b * k - c * h) / det, (b * f - c * e) / det,
-                     Bc / det, (a * k - c * g) / det, -(a * f - c * d) / det,
-                     Cc / det, -(a * h - b * g) / det, (a * e - b * d) / det};
-    RgInst r;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) r.inv[q] = (float)inv[q];
-    r.p[0] = xform[12 * i + 3];
-    r.p[1] = xform[12 * i + 7];
-    r.p[2] = xform[12 * i + 11];
-    r.nodes = BI.nodes;
-    r.tris = BI.tris;
-    r.hdr = BI.hdr;
-    r.mat = inst_mat[i];
-    r.inst = (uint32_t)i;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        r.blo[q] = B.lo[q];
-        r.bhi[q] = B.hi[q];
-    }
-    r.flags = (inst_flags ? inst_flags[i] : RG_INST_MASK_ALL) | (B.alpha ? RG_INST_ALPHA : 0u);
-    r.pad = 0u;
-    recs[i] = r;
-}
-
 __global__ void k_reorder_inst(const RgInst *__restrict__ in, const uint32_t *__restrict__ ids, int64_t n,
                                RgInst *__restrict__ out, uint32_t *__restrict__ rec_of) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -2370,7 +2412,18 @@ rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t
         sa.flag_in = out->flag_in;
         sa.res = s.small;
         const size_t lds = small_lds_bytes(n);
-        if (n <= kResidentMax) {
+        const TlasFuse *fuse = reinterpret_cast<const TlasFuse *>(out->tlas_fuse);
+        if (fuse && n <= kResidentMax) {
+            sa.inst = fuse->T;
+            sa.rec_tmp = fuse->rec_tmp;
+            sa.recs_out = fuse->recs_out;
+            sa.rec_of = fuse->rec_of;
+            if (width == 2) k_small_build<2, true, true><<<1, kSmallThreads, lds, st>>>(sa);
+            else if (width == 4) k_small_build<4, true, true><<<1, kSmallThreads, lds, st>>>(sa);
+            else k_small_build<8, true, true><<<1, kSmallThreads, lds, st>>>(sa);
+        } else if (fuse) {
+            return RG_ERR_HIP;  // never: the top level fuses only up to kResidentMax instances
+        } else if (n <= kResidentMax) {
             if (width == 2) k_small_build<2, true><<<1, kSmallThreads, lds, st>>>(sa);
             else if (width == 4) k_small_build<4, true><<<1, kSmallThreads, lds, st>>>(sa);
             else k_small_build<8, true><<<1, kSmallThreads, lds, st>>>(sa);
@@ -2915,23 +2968,37 @@ rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xfo
     uint32_t *summary = (uint32_t *)(tab + t_bytes);  // a one-workgroup build's summary, or the flag word
     uint32_t *d_flag = (uint32_t *)(d_tab + off_flag);
     RG_HIP(hipMemcpyAsync(d_tab, tab, t_bytes, hipMemcpyHostToDevice, st));
-    k_inst_setup<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(
-        (const float *)d_tab, (const uint32_t *)(d_tab + off_bid), (const uint32_t *)(d_tab + off_mat),
-        inst_flags ? (const uint32_t *)(d_tab + off_fl) : nullptr, (const BlasInfo *)(d_tab + off_info), n_inst,
-        d_box, d_rec, d_flag, d_xf);
-    RG_LAUNCH_CHECK();
+    InstTables T;
+    T.xform = (const float *)d_tab;
+    T.blas_id = (const uint32_t *)(d_tab + off_bid);
+    T.inst_mat = (const uint32_t *)(d_tab + off_mat);
+    T.inst_flags = inst_flags ? (const uint32_t *)(d_tab + off_fl) : nullptr;
+    T.blas = (const BlasInfo *)(d_tab + off_info);
+    T.flags = d_flag;
+    T.xf_keep = d_xf;
     char *base = (char *)out_buf;
+    // up to kResidentMax instances (linear BVH): the instance step, the
+    // build and the record reordering in one launch
+    const bool fused = o.builder == RG_BUILDER_LBVH && n_inst <= kResidentMax;
+    const TlasFuse F{T, d_rec, (RgInst *)(base + io), (uint32_t *)(base + ro)};
+    if (!fused) {
+        k_inst_setup<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(T, n_inst, d_box, d_rec);
+        RG_LAUNCH_CHECK();
+    }
     RgLbvhOut lo;
     lo.deferred = summary;
     lo.flag_in = d_flag;
+    lo.tlas_fuse = fused ? &F : nullptr;
     rg_status r = rg_lbvh_build(d_box, n_inst, w, 1, o.builder, o.radius, base + no, nullptr, nullptr, arena, st, &lo,
                                 false, nullptr, nullptr, nullptr, nullptr);
     if (r != RG_OK) {
         (void)hipStreamSynchronize(st);  // the staging buffer may still be in use by a copy
         return r;
     }
-    k_reorder_inst<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(d_rec, lo.ids, n_inst, (RgInst *)(base + io),
-                                                                      (uint32_t *)(base + ro));
+    if (!fused)
+        k_reorder_inst<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(d_rec, lo.ids, n_inst,
+                                                                          (RgInst *)(base + io),
+                                                                          (uint32_t *)(base + ro));
     const bool deferred = lo.pending;  // else the flag word comes back on its own
     const hipError_t le = hipGetLastError();
     const hipError_t ce = (le == hipSuccess && !deferred)

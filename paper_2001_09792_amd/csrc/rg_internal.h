@@ -157,6 +157,10 @@ struct RgLbvhOut {
     // Set by a larger build given `deferred`: the root box is on its way to
     // deferred[4..9]; rg_lbvh_finish (after the caller's wait) reads it.
     bool pending_box = false;
+    // Set by the top-level build (nullable): a one-workgroup linear build of
+    // up to 1,024 instances then also computes the instances' boxes and
+    // records from the uploaded tables and writes the records in leaf order.
+    const void *tlas_fuse = nullptr;
 };
 // Fills depth, n_nodes and the root box of a pending one-workgroup build
 // from its summary (after the caller's wait); RG_ERR_HIP if it failed.
