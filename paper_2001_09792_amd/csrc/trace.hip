@@ -365,19 +365,41 @@ unsigned persistent_blocks(int64_t n, int waves_per_cu) {
     return (unsigned)(need < want ? need : want);
 }
 
+// A persistent launch takes no more blocks than the kernel variant can keep
+// resident (its registers and LDS decide how many fit on a CU): blocks
+// beyond that would wait for a resident one to finish and start its share
+// of the sequence late.
+template <class Kernel>
+unsigned resident_cap(Kernel kernel, unsigned blocks, size_t shm) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, rgt::kThreads, shm) != hipSuccess ||
+        per_cu < 1) {
+        (void)hipGetLastError();
+        return blocks;
+    }
+    const unsigned cap = (unsigned)per_cu * (unsigned)rg_cu_count();
+    return blocks < cap ? blocks : cap;
+}
+
+template <int W, bool ANY, int MODE, bool OPT>
+void launch_one(const RgTraceArgs &a, hipStream_t st, unsigned blocks, size_t shm, const rg_trace_tune &t) {
+    auto kernel = k_trace<W, ANY, MODE, OPT>;
+    blocks = resident_cap(kernel, blocks, shm);
+    kernel<<<blocks, rgt::kThreads, shm, st>>>(a, t.refill, t.lds_depth, t.leaf_batch, t.inst_batch);
+}
+
 template <int W, bool OPT>
 void launch_mode(bool any, int mode, const RgTraceArgs &a, hipStream_t st, unsigned blocks, size_t shm,
                  const rg_trace_tune &t) {
-    const int refill = t.refill, lds = t.lds_depth, lb = t.leaf_batch, ib = t.inst_batch;
     if (mode == rgt::kCounts) {
-        if (any) k_trace<W, true, rgt::kCounts, OPT><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
-        else k_trace<W, false, rgt::kCounts, OPT><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
+        if (any) launch_one<W, true, rgt::kCounts, OPT>(a, st, blocks, shm, t);
+        else launch_one<W, false, rgt::kCounts, OPT>(a, st, blocks, shm, t);
     } else if (mode == rgt::kRender) {
-        if (any) k_trace<W, true, rgt::kRender, OPT><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
-        else k_trace<W, false, rgt::kRender, OPT><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
+        if (any) launch_one<W, true, rgt::kRender, OPT>(a, st, blocks, shm, t);
+        else launch_one<W, false, rgt::kRender, OPT>(a, st, blocks, shm, t);
     } else {
-        if (any) k_trace<W, true, rgt::kClosest, OPT><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
-        else k_trace<W, false, rgt::kClosest, OPT><<<blocks, rgt::kThreads, shm, st>>>(a, refill, lds, lb, ib);
+        if (any) launch_one<W, true, rgt::kClosest, OPT>(a, st, blocks, shm, t);
+        else launch_one<W, false, rgt::kClosest, OPT>(a, st, blocks, shm, t);
     }
 }
 
