@@ -720,9 +720,10 @@ __device__ inline void inst_setup_one(const InstTables &T, int64_t i, float box[
     double a = m[0], b = m[1], c = m[2], d = m[4], e = m[5], f = m[6], g = m[8], h = m[9], k = m[10];
     double A = e * k - f * h, Bc = -(d * k - f * g), Cc = d * h - e * g;
     double det = a * A + b * Bc + c * Cc;
-    double inv[9] = {A / det, -(b * k - c * h) / det, (b * f - c * e) / det,
-                     Bc / det, (a * k - c * g) / det, -(a * f - c * d) / det,
-                     Cc / det, -(a * h - b * g) / det, (a * e - b * d) / det};
+    const double rdet = 1.0 / det;  // one division; the entries differ from x / det by an ulp of double at most
+    double inv[9] = {A * rdet, -(b * k - c * h) * rdet, (b * f - c * e) * rdet,
+                     Bc * rdet, (a * k - c * g) * rdet, -(a * f - c * d) * rdet,
+                     Cc * rdet, -(a * h - b * g) * rdet, (a * e - b * d) * rdet};
 #pragma unroll
     for (int q = 0; q < 9; ++q) r.inv[q] = (float)inv[q];
     r.p[0] = T.xform[12 * i + 3];

@@ -634,6 +634,25 @@ rg_status run_batch(const rg_batch *B, hipStream_t st) {
     return RG_OK;
 }
 
+// The two timing events of a call that reports stats, destroyed however the
+// call ends.
+struct StatEvents {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    StatEvents() = default;
+    StatEvents(const StatEvents &) = delete;
+    StatEvents &operator=(const StatEvents &) = delete;
+    ~StatEvents() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+    rg_status start(hipStream_t st) {
+        RG_HIP(hipEventCreate(&e0));
+        RG_HIP(hipEventCreate(&e1));
+        RG_HIP(hipEventRecord(e0, st));
+        return RG_OK;
+    }
+};
+
 rg_status finish_stats(hipStream_t st, hipEvent_t e0, hipEvent_t e1, const unsigned long long *dstat,
                        rg_render_stats *stats) {
     RG_HIP(hipEventRecord(e1, st));
@@ -645,8 +664,6 @@ rg_status finish_stats(hipStream_t st, hipEvent_t e0, hipEvent_t e1, const unsig
     stats->rays_traced = hs[0];
     stats->shadow_rays = hs[1];
     stats->ms_total = ms;
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
     return RG_OK;
 }
 
@@ -953,11 +970,10 @@ rg_status rg_batch_render(const rg_batch *batch, void *stream, rg_render_stats *
 static rg_status batch_impl(const rg_batch *batch, void *stream, rg_render_stats *stats) {
     if (!batch || !batch->scratch || batch->n_jobs < 1) return RG_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    StatEvents ev;
     if (stats) {
-        RG_HIP(hipEventCreate(&e0));
-        RG_HIP(hipEventCreate(&e1));
-        RG_HIP(hipEventRecord(e0, st));
+        const rg_status re = ev.start(st);
+        if (re != RG_OK) return re;
     }
     rg_status r = run_batch(batch, st);
     if (r != RG_OK) return r;
@@ -965,7 +981,7 @@ static rg_status batch_impl(const rg_batch *batch, void *stream, rg_render_stats
         RgArena A{(char *)batch->scratch, batch->scratch_bytes, 0};
         RgWaveBufs b;
         rg_wave_carve(A, batch->total_pixels, batch->capacity, batch->n_jobs, batch->n_mats, b);
-        return finish_stats(st, e0, e1, b.stat, stats);
+        return finish_stats(st, ev.e0, ev.e1, b.stat, stats);
     }
     return RG_OK;
 }
@@ -1044,11 +1060,10 @@ static rg_status render_impl(const rg_tlas *tlas, const rg_material *mats, int32
         RgArena A{(char *)scratch, scratch_bytes, 0};
         RgWaveBufs b;
         if (!rg_wave_carve(A, n, n << max_depth, 1, 256, b)) return RG_ERR_OUT_OF_MEMORY;
-        hipEvent_t e0 = nullptr, e1 = nullptr;
+        StatEvents ev;
         if (stats) {
-            RG_HIP(hipEventCreate(&e0));
-            RG_HIP(hipEventCreate(&e1));
-            RG_HIP(hipEventRecord(e0, st));
+            const rg_status re = ev.start(st);
+            if (re != RG_OK) return re;
         }
         RgJobDev J = {};
         J.cam = *cam;
@@ -1087,18 +1102,17 @@ static rg_status render_impl(const rg_tlas *tlas, const rg_material *mats, int32
             }
         }
         if ((r = rg_wave_resolve(b, J, st)) != RG_OK) return r;
-        if (stats) return finish_stats(st, e0, e1, b.stat, stats);
+        if (stats) return finish_stats(st, ev.e0, ev.e1, b.stat, stats);
         return RG_OK;
     }
     const int64_t n = (int64_t)width * height;
     RgArena A{(char *)scratch, scratch_bytes, 0};
     AoBufs b;
     if (!carve_ao(A, n, b)) return RG_ERR_OUT_OF_MEMORY;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    StatEvents ev;
     if (stats) {
-        RG_HIP(hipEventCreate(&e0));
-        RG_HIP(hipEventCreate(&e1));
-        RG_HIP(hipEventRecord(e0, st));
+        const rg_status re = ev.start(st);
+        if (re != RG_OK) return re;
     }
     k_zero_u64<<<rg_blocks(3 * n, kT), kT, 0, st>>>(b.acc, 3 * n);
     k_zero_u64<<<1, kT, 0, st>>>(b.stat, 4);
@@ -1142,7 +1156,7 @@ static rg_status render_impl(const rg_tlas *tlas, const rg_material *mats, int32
     RG_LAUNCH_CHECK();
     k_stat_add<<<1, 1, 0, st>>>(b.stat, b.counts + 0);
     k_stat_add<<<1, 1, 0, st>>>(b.stat + 1, b.counts + 2);
-    if (stats) return finish_stats(st, e0, e1, b.stat, stats);
+    if (stats) return finish_stats(st, ev.e0, ev.e1, b.stat, stats);
     return RG_OK;
 }
 

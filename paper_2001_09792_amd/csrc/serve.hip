@@ -156,10 +156,10 @@ namespace {
 // Frees the host object and whatever HIP objects it holds (null ones skipped).
 void engine_free(rg_engine *E) {
     for (int k = 0; k < kEventRing; ++k)
-        if (E->ev[k]) hipEventDestroy(E->ev[k]);
-    if (E->side.shaded) hipEventDestroy(E->side.shaded);
-    if (E->side.shadowed) hipEventDestroy(E->side.shadowed);
-    if (E->side.st) hipStreamDestroy(E->side.st);
+        if (E->ev[k]) (void)hipEventDestroy(E->ev[k]);
+    if (E->side.shaded) (void)hipEventDestroy(E->side.shaded);
+    if (E->side.shadowed) (void)hipEventDestroy(E->side.shadowed);
+    if (E->side.st) (void)hipStreamDestroy(E->side.st);
     delete E;
 }
 

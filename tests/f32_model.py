@@ -27,7 +27,7 @@ def _inv3(m):
     rows = [[A, -(b * k - c * h), b * f - c * e],
             [B, a * k - c * g, -(a * f - c * d)],
             [C, -(a * h - b * g), a * e - b * d]]
-    return np.stack([np.stack(r, -1) for r in rows], -2) / det[..., None, None]
+    return np.stack([np.stack(r, -1) for r in rows], -2) * (1.0 / det)[..., None, None]  # as the GPU: one division
 
 
 def trace_tri(xform, box_lo, box_hi, o, d, tmin, tmax, tri):

@@ -27,6 +27,8 @@ MESHES = {
     # the largest build done by one workgroup, and the smallest done by the
     # multi-launch path
     "soup4096": lambda: sg.random_soup(4096, 23),
+    # the largest build whose arrays all stay in LDS (keys, tree, boxes)
+    "soup1024": lambda: sg.random_soup(1024, 26),
     "soup4097": lambda: sg.random_soup(4097, 24),
     "one": lambda: sg.random_soup(1, 25),
 }
