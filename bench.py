@@ -620,18 +620,26 @@ def bench_build(args, torch, rg, sg):
     dev = [(torch.from_numpy(m.verts).cuda(), torch.from_numpy(m.idx.view(np.int32)).cuda()) for m in scene.blas]
     n_tris = sum(m.n_tris for m in scene.blas)
     res = {}
-    for builder in ("lbvh", "ploc", "treelet"):
+    # the three builders with 63-bit keys, and the linear one with the
+    # compact 30-bit keys (four sort passes instead of eight); the mean SAH
+    # cost of the 16 trees shows what the coarser keys cost in quality
+    for name, builder, bits in (("lbvh", "lbvh", 0), ("ploc", "ploc", 0), ("treelet", "treelet", 0),
+                                ("lbvh_keys30", "lbvh", 10)):
         for _ in range(args.warmup):
             for v, i in dev:
-                rg.build_blas(v, i, None, args.width, args.leaf, builder=builder)
+                rg.build_blas(v, i, None, args.width, args.leaf, builder=builder, morton_bits=bits)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
             for v, i in dev:
-                rg.build_blas(v, i, None, args.width, args.leaf, builder=builder)
+                b = rg.build_blas(v, i, None, args.width, args.leaf, builder=builder, morton_bits=bits)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        res[builder] = {"ms_per_scene": ms, "mtris_s": n_tris / (ms * 1e-3) / 1e6}
+        sah = []
+        for v, i in dev[:4]:
+            b = rg.build_blas(v, i, None, args.width, args.leaf, builder=builder, morton_bits=bits)
+            sah.append(sah_cost(b.buf.cpu().numpy(), b.desc.nodes_off, b.desc.n_nodes, args.width))
+        res[name] = {"ms_per_scene": ms, "mtris_s": n_tris / (ms * 1e-3) / 1e6, "sah_cost_mean_4": float(np.mean(sah))}
     width, leaf, builder = SHAPES["incoherent"]
     out = {
         "metric": "Mtris/s bottom-level build", "value": res[builder]["mtris_s"], "unit": "Mtris/s",

@@ -93,12 +93,18 @@ typedef int32_t rg_status;
  * most triangles per leaf (1..8); builder = RG_BUILDER_*; radius = search
  * radius of RG_BUILDER_PLOC (1..32, 0 = RG_PLOC_RADIUS_DEFAULT), rounds of
  * RG_BUILDER_TREELET (1..8, 0 = RG_TREELET_ROUNDS_DEFAULT), ignored by
- * RG_BUILDER_LBVH.  NULL means {4, 4, RG_BUILDER_LBVH, 0}. */
+ * RG_BUILDER_LBVH; morton_bits = bits per axis of the Morton codes: 21 (0
+ * means 21: 63-bit keys, eight radix-sort passes) or 10 (30-bit keys, four
+ * passes, for builds of at most 2^20 primitives: the key is the 21-bit key's
+ * top 30 bits, a coarser grid that costs some hierarchy quality).  NULL
+ * means {4, 4, RG_BUILDER_LBVH, 0, 0}. */
+#define RG_MORTON_BITS_COMPACT_MAX_PRIMS (1 << 20)
 typedef struct {
     int32_t width;
     int32_t leaf_max;
     int32_t builder;
     int32_t radius;
+    int32_t morton_bits;
 } rg_build_opts;
 
 typedef struct {
@@ -207,7 +213,8 @@ const char *rg_last_error(void);
 
 /* ------------------------------------------------------- bottom level */
 /* Sizes for a bottom level of n_tris triangles (host call, no GPU work).
- * Errors: RG_ERR_INVALID_ARG for n_tris < 1 or > 2^28, bad opts, NULL out. */
+ * Errors: RG_ERR_INVALID_ARG for n_tris < 1 or > 2^28, bad opts (also
+ * morton_bits 10 with more than 2^20 triangles), NULL out. */
 rg_status rg_blas_sizes(int64_t n_tris, const rg_build_opts *opts, rg_sizes *out /*host*/);
 
 /* The bottom level of the two-level structure, built from a mesh's vertex

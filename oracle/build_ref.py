@@ -10,11 +10,12 @@ choice, so these definitions are its specification:
 
   centroid  c = 0.5 * (lo + hi) of each triangle's box, float32
   bounds    lo_c, hi_c = exact min / max of the centroids
-  quantise  q_k = min(floor((c_k - lo_k) * s_k), 2^21 - 1) with
-            s_k = 2^21 / (hi_k - lo_k) (0 when hi_k == lo_k), every step
-            float32 and rounded to nearest (no fused multiply-add)
-  key       63-bit interleave: bit 3i+2 <- x bit i, 3i+1 <- y bit i,
-            3i <- z bit i
+  quantise  q_k = min(floor((c_k - lo_k) * s_k), 2^B - 1) with
+            s_k = 2^B / (hi_k - lo_k) (0 when hi_k == lo_k), every step
+            float32 and rounded to nearest (no fused multiply-add); B = 21
+            bits per axis, or B = 10 for the compact option
+  key       3B-bit interleave (63 or 30 bits): bit 3i+2 <- x bit i,
+            3i+1 <- y bit i, 3i <- z bit i
   sort      stable ascending by key
   hierarchy for the sorted keys, the unique binary radix tree: a range
             [first, last] splits after the last index whose key shares more
@@ -26,8 +27,8 @@ from __future__ import annotations
 
 import numpy as np
 
-BITS = 21
-Q = np.float32(2 ** BITS)
+BITS = 21          # bits per axis of the default keys
+BITS_COMPACT = 10  # the compact option (30-bit keys)
 
 
 def tri_boxes(verts: np.ndarray, idx: np.ndarray):
@@ -40,29 +41,30 @@ def centroids(verts, idx) -> np.ndarray:
     return (np.float32(0.5) * (lo + hi)).astype(np.float32)
 
 
-def quantise(c: np.ndarray, lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
+def quantise(c: np.ndarray, lo: np.ndarray, hi: np.ndarray, bits: int = BITS) -> np.ndarray:
     c = c.astype(np.float32)
     ext = (hi.astype(np.float32) - lo.astype(np.float32)).astype(np.float32)
     with np.errstate(divide="ignore"):
-        s = np.where(ext > 0, Q / np.where(ext > 0, ext, np.float32(1)), np.float32(0)).astype(np.float32)
+        s = np.where(ext > 0, np.float32(2 ** bits) / np.where(ext > 0, ext, np.float32(1)),
+                     np.float32(0)).astype(np.float32)
     x = ((c - lo.astype(np.float32)).astype(np.float32) * s).astype(np.float32)
     q = np.floor(x).astype(np.int64)
-    return np.clip(q, 0, 2 ** BITS - 1).astype(np.uint64)
+    return np.clip(q, 0, 2 ** bits - 1).astype(np.uint64)
 
 
-def interleave(q: np.ndarray) -> np.ndarray:
-    """Bit-by-bit interleave of three 21-bit integers (x highest)."""
+def interleave(q: np.ndarray, bits: int = BITS) -> np.ndarray:
+    """Bit-by-bit interleave of three `bits`-bit integers (x highest)."""
     key = np.zeros(q.shape[0], np.uint64)
-    for i in range(BITS):
+    for i in range(bits):
         for axis, shift in ((0, 2), (1, 1), (2, 0)):
             bit = (q[:, axis] >> np.uint64(i)) & np.uint64(1)
             key |= bit << np.uint64(3 * i + shift)
     return key
 
 
-def morton_keys(verts, idx) -> np.ndarray:
+def morton_keys(verts, idx, bits: int = BITS) -> np.ndarray:
     c = centroids(verts, idx)
-    return interleave(quantise(c, c.min(axis=0), c.max(axis=0)))
+    return interleave(quantise(c, c.min(axis=0), c.max(axis=0), bits), bits)
 
 
 def morton_keys_for_centroids(c: np.ndarray) -> np.ndarray:

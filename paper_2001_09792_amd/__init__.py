@@ -41,7 +41,8 @@ c_p = ctypes.c_void_p
 
 
 class BuildOpts(ctypes.Structure):
-    _fields_ = [("width", c_i32), ("leaf_max", c_i32), ("builder", c_i32), ("radius", c_i32)]
+    _fields_ = [("width", c_i32), ("leaf_max", c_i32), ("builder", c_i32), ("radius", c_i32),
+                ("morton_bits", c_i32)]
 
 
 class Sizes(ctypes.Structure):
@@ -241,10 +242,10 @@ BUILDERS = {"lbvh": 0, "ploc": 1, "treelet": 2}
 PLOC_RADIUS_DEFAULT = 16
 
 
-def _opts(width: int, leaf_max: int, builder: str = "lbvh", radius: int = 0) -> BuildOpts:
+def _opts(width: int, leaf_max: int, builder: str = "lbvh", radius: int = 0, morton_bits: int = 0) -> BuildOpts:
     if builder not in BUILDERS:
         raise ValueError(f"builder must be one of {sorted(BUILDERS)}")
-    return BuildOpts(width, leaf_max, BUILDERS[builder], radius)
+    return BuildOpts(width, leaf_max, BUILDERS[builder], radius, morton_bits)
 
 
 # -------------------------------------------------------------- bottom level
@@ -265,24 +266,27 @@ class Blas:
         return int(self.desc.depth)
 
 
-def blas_sizes(n_tris: int, width: int = 4, leaf_max: int = 4, builder: str = "lbvh", radius: int = 0):
+def blas_sizes(n_tris: int, width: int = 4, leaf_max: int = 4, builder: str = "lbvh", radius: int = 0,
+               morton_bits: int = 0):
     s = Sizes()
-    o = _opts(width, leaf_max, builder, radius)
+    o = _opts(width, leaf_max, builder, radius, morton_bits)
     _check("rg_blas_sizes", _lib.rg_blas_sizes(n_tris, ctypes.byref(o), ctypes.byref(s)))
     return int(s.bytes), int(s.scratch_bytes)
 
 
 def build_blas(verts, idx, prim_mat=None, width: int = 4, leaf_max: int = 4, scratch=None,
-               stream=None, builder: str = "lbvh", radius: int = 0) -> Blas:
+               stream=None, builder: str = "lbvh", radius: int = 0, morton_bits: int = 0) -> Blas:
     """verts: CUDA float32 [V,3]; idx: CUDA int32/uint32 [T,3]; prim_mat: CUDA
-    int16 [T] or None; builder: "lbvh" or "ploc" (radius 0: the default)."""
+    int16 [T] or None; builder: "lbvh", "ploc" or "treelet" (radius 0: the
+    default); morton_bits: 21 (0: the default) or 10 (30-bit keys, four sort
+    passes, up to 2^20 triangles)."""
     n_tris = int(idx.shape[0])
-    nb, ns = blas_sizes(n_tris, width, leaf_max, builder, radius)
+    nb, ns = blas_sizes(n_tris, width, leaf_max, builder, radius, morton_bits)
     buf = _bytes(nb, verts.device)
     if scratch is None or scratch.numel() < ns:
         scratch = _bytes(ns, verts.device)
     d = BlasDesc()
-    o = _opts(width, leaf_max, builder, radius)
+    o = _opts(width, leaf_max, builder, radius, morton_bits)
     _check("rg_build_blas", _lib.rg_build_blas(
         _ptr(verts), int(verts.shape[0]), _ptr(idx), n_tris, _ptr(prim_mat), ctypes.byref(o),
         _ptr(buf), buf.numel(), _ptr(scratch), scratch.numel(), _stream(stream), ctypes.byref(d)))
@@ -349,17 +353,19 @@ class Tlas:
 
 
 def build_tlas(blas: Sequence[Blas], xform, blas_id, inst_mat, width: int = 4, stream=None,
-               scratch=None, builder: str = "lbvh", radius: int = 0, inst_flags=None) -> Tlas:
+               scratch=None, builder: str = "lbvh", radius: int = 0, inst_flags=None,
+               morton_bits: int = 0) -> Tlas:
     """xform: host float32 [I,3,4]; blas_id, inst_mat: host uint32 [I];
     inst_flags: host uint32 [I] (visibility mask in bits 0-7,
-    INST_CULL_DISABLE, INST_FLIP_FACING) or None (all visible)."""
+    INST_CULL_DISABLE, INST_FLIP_FACING) or None (all visible);
+    morton_bits as for build_blas."""
     torch = _torch()
     xform = np.ascontiguousarray(xform, np.float32).reshape(-1, 12)
     blas_id = np.ascontiguousarray(blas_id, np.uint32)
     inst_mat = np.ascontiguousarray(inst_mat, np.uint32)
     n = xform.shape[0]
     s = Sizes()
-    o = _opts(width, 1, builder, radius)
+    o = _opts(width, 1, builder, radius, morton_bits)
     _check("rg_tlas_sizes", _lib.rg_tlas_sizes(n, ctypes.byref(o), ctypes.byref(s)))
     dev = blas[0].buf.device
     buf = _bytes(s.bytes, dev)
@@ -973,13 +979,13 @@ class Engine:
             pass
 
 
-def lbvh_stages(verts, idx, stream=None, builder: str = "lbvh", radius: int = 0) -> dict:
+def lbvh_stages(verts, idx, stream=None, builder: str = "lbvh", radius: int = 0, morton_bits: int = 0) -> dict:
     """Intermediate results of the bottom-level build (keys, ids, binary
-    tree, boxes) for the given builder."""
+    tree, boxes) for the given builder and key width."""
     torch = _torch()
     n = int(idx.shape[0])
-    _, ns = blas_sizes(n, builder=builder, radius=radius)
-    o = _opts(4, 4, builder, radius)
+    _, ns = blas_sizes(n, builder=builder, radius=radius, morton_bits=morton_bits)
+    o = _opts(4, 4, builder, radius, morton_bits)
     scratch = _bytes(ns, verts.device)
     dev = verts.device
     keys = torch.empty(n, dtype=torch.int64, device=dev)

@@ -32,8 +32,13 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kSortItems = 8;
-constexpr int kSortTile = kThreads * kSortItems;
+// radix sort tiles: kSortThreads threads of kSortItems keys.  A compute
+// unit keeps only so many loads in flight, so the tiles have to be spread
+// over all of them (2,048 keys: 307 tiles for a mesh of 627,200 triangles).
+constexpr int kSortThreads = 512;
+constexpr int kSortItems = 4;
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kCountCopies = 8;  // copies of the digit counts, spread over the tiles (fewer atomics per word)
 constexpr int kScanThreads = 1024;
 
 // --------------------------------------------------------------- helpers
@@ -114,12 +119,20 @@ __global__ void k_tri_boxes(const float *__restrict__ verts, int64_t n_verts,
     if (bad) atomicOr(flags, bad);
 }
 
-// Bounds of the box centres c = 0.5 (lo + hi) as order-preserving uints:
-// bounds[0..2] = min, bounds[3..5] = max.
-__global__ void k_centre_bounds(const float *__restrict__ box, int64_t n, uint32_t *__restrict__ bounds) {
+// Bounds of the box centres c = 0.5 (lo + hi): one partial per block,
+// part[6 b .. 6 b + 5] = min xyz, max xyz (k_morton reduces them, so no
+// atomics and no initialised bounds are needed).  Also clears zero[0, nz):
+// the sort's digit counts, tickets and tile status words.
+constexpr int kBoundParts = 512;  // largest grid of k_centre_bounds
+__global__ void __launch_bounds__(kThreads) k_centre_bounds(const float *__restrict__ box, int64_t n,
+                                                            float *__restrict__ part, uint32_t *__restrict__ zero,
+                                                            int64_t nz) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (int64_t j = i0; j < nz; j += stride) zero[j] = 0u;
     float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll 4
+    for (int64_t i = i0; i < n; i += stride) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             float c = (box[6 * i + k] + box[6 * i + 3 + k]) * 0.5f;
@@ -127,9 +140,7 @@ __global__ void k_centre_bounds(const float *__restrict__ box, int64_t n, uint32
             mx[k] = fmaxf(mx[k], c);
         }
     }
-    // waves, then the block through LDS, then one atomic per value and block
-    // (atomics on one address serialise: one per wave made this kernel slow)
-    __shared__ float part[6][kThreads / 64];
+    __shared__ float red[6][kThreads / 64];
     const int wv = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -139,17 +150,16 @@ __global__ void k_centre_bounds(const float *__restrict__ box, int64_t n, uint32
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            part[k][wv] = mn[k];
-            part[3 + k][wv] = mx[k];
+            red[k][wv] = mn[k];
+            red[3 + k][wv] = mx[k];
         }
     }
     __syncthreads();
     if (threadIdx.x < 6) {
         const int k = threadIdx.x;
-        float v = part[k][0];
-        for (int q = 1; q < kThreads / 64; ++q) v = k < 3 ? fminf(v, part[k][q]) : fmaxf(v, part[k][q]);
-        if (k < 3) atomicMin(&bounds[k], rg_f2ord(v));
-        else atomicMax(&bounds[k], rg_f2ord(v));
+        float v = red[k][0];
+        for (int q = 1; q < kThreads / 64; ++q) v = k < 3 ? fminf(v, red[k][q]) : fmaxf(v, red[k][q]);
+        part[6 * blockIdx.x + k] = v;
     }
 }
 
@@ -164,14 +174,13 @@ __device__ inline uint64_t spread21(uint64_t x) {
     return x;
 }
 
-// The key of one primitive box from the centre bounds (order-preserving
-// uints: lo[0..2], hi[3..5]).
-__device__ inline uint64_t morton_key(const float *__restrict__ b, const uint32_t *bounds) {
+// The key of one primitive box from the centre bounds lo[3], hi[3].
+__device__ inline uint64_t morton_key(const float *__restrict__ b, const float *lo3, const float *hi3) {
 #pragma clang fp contract(off)
     uint64_t q[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        float lo = rg_ord2f(bounds[k]), hi = rg_ord2f(bounds[3 + k]);
+        float lo = lo3[k], hi = hi3[k];
         float ext = hi - lo;
         float s = ext > 0.0f ? 2097152.0f / ext : 0.0f;
         float c = (b[k] + b[3 + k]) * 0.5f;
@@ -182,36 +191,177 @@ __device__ inline uint64_t morton_key(const float *__restrict__ b, const uint32_
     }
     return (spread21(q[0]) << 2) | (spread21(q[1]) << 1) | spread21(q[2]);
 }
+// The same from bounds held as order-preserving uints (lo[0..2], hi[3..5]).
+__device__ inline uint64_t morton_key(const float *__restrict__ b, const uint32_t *bounds) {
+    float lo[3], hi[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = rg_ord2f(bounds[k]);
+        hi[k] = rg_ord2f(bounds[3 + k]);
+    }
+    return morton_key(b, lo, hi);
+}
 
-// Also clears the sort's digit totals (2 x 256 words) for its first pass.
-__global__ void k_morton(const float *__restrict__ box, int64_t n, const uint32_t *__restrict__ bounds,
-                         uint64_t *__restrict__ keys, uint32_t *__restrict__ ids, uint32_t *__restrict__ totals) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < 512) totals[i] = 0u;
-    if (i >= n) return;
-    keys[i] = morton_key(box + 6 * i, bounds);
-    ids[i] = (uint32_t)i;
+// Keys and ids of one tile of kSortTile boxes per block, and the counts of
+// every 8-bit digit of the keys for all eight sort passes, added into
+// count[copy][pass][digit] (copy = block mod kCountCopies; cleared by
+// k_centre_bounds).  The centre bounds are the reduction of
+// k_centre_bounds' nparts partials.
+__global__ void __launch_bounds__(kSortThreads) k_morton(const float *__restrict__ box, int64_t n,
+                                                         const float *__restrict__ part, int nparts, int key_shift,
+                                                         uint64_t *__restrict__ keys, uint32_t *__restrict__ ids,
+                                                         uint32_t *__restrict__ count) {
+    constexpr int kWaves = kSortThreads / 64;
+    __shared__ uint32_t h[8 * 256];
+    __shared__ float red[6][kWaves];
+    __shared__ float bnd[6];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    for (int j = t; j < 8 * 256; j += kSortThreads) h[j] = 0u;
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int j = t; j < nparts; j += kSortThreads) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            mn[k] = fminf(mn[k], part[6 * j + k]);
+            mx[k] = fmaxf(mx[k], part[6 * j + 3 + k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        mn[k] = wave_min(mn[k]);
+        mx[k] = wave_max(mx[k]);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            red[k][w] = mn[k];
+            red[3 + k][w] = mx[k];
+        }
+    }
+    __syncthreads();
+    if (t < 6) {
+        float v = red[t][0];
+        for (int q = 1; q < kWaves; ++q) v = t < 3 ? fminf(v, red[t][q]) : fmaxf(v, red[t][q]);
+        bnd[t] = v;
+    }
+    __syncthreads();
+    const float lo[3] = {bnd[0], bnd[1], bnd[2]}, hi[3] = {bnd[3], bnd[4], bnd[5]};
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    float b[kSortItems][6];  // every box load in flight before the first is used
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t i = base + it * kSortThreads + t;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) b[it][k] = i < n ? box[6 * i + k] : 0.0f;
+    }
+#pragma unroll
+    for (int it = 0; it < kSortItems; ++it) {
+        const int64_t i = base + it * kSortThreads + t;
+        const bool valid = i < n;
+        uint64_t key = 0ull;
+        if (valid) {
+            key = morton_key(b[it], lo, hi) >> key_shift;
+            keys[i] = key;
+            ids[i] = (uint32_t)i;
+        }
+        const uint64_t vm = __ballot(valid);
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+            const uint32_t d = (uint32_t)(key >> (8 * p)) & 255u;
+            const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);  // lane 0: valid whenever vm != 0
+            if (__ballot(valid && d != d0) == 0ull) {  // one digit across the wave (the high digits)
+                if (lane == 0) atomicAdd(&h[256 * p + d0], (uint32_t)__popcll(vm));
+            } else if (valid) {
+                atomicAdd(&h[256 * p + d], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t *cc = count + 2048 * (blockIdx.x % kCountCopies);
+    for (int j = t; j < 8 * 256; j += kSortThreads) {
+        const uint32_t c = h[j];
+        if (c) atomicAdd(&cc[j], c);
+    }
 }
 
 // -------------------------------------------------- 3. LSD radix sort
-// Per pass: digit counts per block (ghist, digit-major) and per digit over
-// all blocks (totals), then k_sort_offsets turns ghist into each block's
-// first position per digit, then the stable scatter.
-__global__ void k_sort_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
-                            uint32_t *__restrict__ ghist, int nblocks, uint32_t *__restrict__ totals) {
-    __shared__ uint32_t h[256];
-    int t = threadIdx.x;
-    h[t] = 0;
-    __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * kSortTile;
+// Three launches per pass of 8 bits, each spread over every compute unit
+// (a unit keeps only so many loads in flight, so a tile of 2,048 keys per
+// workgroup): the digit counts of every tile (k_sort_count, digit-major),
+// their exclusive scan per digit plus the pass's count of all smaller
+// digits (k_sort_scan, one workgroup per digit; the totals of every pass
+// were counted with the keys), and the stable scatter (k_sort_scatter).  A
+// single launch per pass with a look-back over earlier tiles' counts was
+// slower here: with ~300 tiles finishing at once its chain of cross-die
+// reads outlasts the two extra launches.
+
+// Ranks a tile's items by digit, tile order = (wave, item, lane): rk[k] =
+// count of equal digits before item k within its wave; wcnt[w][d] (zero on
+// entry) ends as wave w's count of digit d.  Lanes with equal digits are
+// matched with 8 ballots (one when the wave shares one digit).
+template <typename K>
+__device__ inline void rank_items(const K (&key)[kSortItems], int in_tile, int shift, uint32_t (&rk)[kSortItems],
+                                  uint32_t (*wcnt)[256]) {
+    constexpr int kPerWave = kSortTile / (kSortThreads / 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
 #pragma unroll
-    for (int it = 0; it < kSortItems; ++it) {
-        int64_t i = base + it * kThreads + t;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    for (int k = 0; k < kSortItems; ++k) {
+        const bool valid = w * kPerWave + k * 64 + lane < in_tile;
+        const uint32_t dg = (uint32_t)(key[k] >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+        const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
+        if (__ballot(valid && dg != d0) != 0ull) {  // uniform; else every valid lane shares one digit
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (dg >> b) & 1u;
+                const uint64_t m = __ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+        }
+        const uint32_t before = (uint32_t)__popcll(peers & lt);
+        const uint32_t c = wcnt[w][dg];  // LDS accesses of one wave complete in order
+        rk[k] = c + before;
+        if (valid && before == 0u) wcnt[w][dg] = c + (uint32_t)__popcll(peers);
     }
+}
+
+// Loads tile blockIdx.x: wave w holds elements [w kPerWave, (w + 1)
+// kPerWave), item k at k * 64 + lane; every load issued before any is used.
+template <typename K>
+__device__ inline int load_tile(const K *__restrict__ keys, int64_t n, K (&key)[kSortItems]) {
+    constexpr int kPerWave = kSortTile / (kSortThreads / 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int in_tile = (int)(n - base < kSortTile ? n - base : kSortTile);
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const int e = w * kPerWave + k * 64 + lane;
+        key[k] = e < in_tile ? keys[base + e] : (K)0;
+    }
+    return in_tile;
+}
+
+// cnt[d * nb + tile] = the tile's count of digit d.
+template <typename K>
+__global__ void __launch_bounds__(kSortThreads) k_sort_count(const K *__restrict__ keys, int64_t n, int shift,
+                                                             uint32_t *__restrict__ cnt, int nb) {
+    constexpr int kWaves = kSortThreads / 64;
+    static_assert(kSortThreads >= 256, "a thread per digit");
+    __shared__ uint32_t wcnt[kWaves][256];
+    const int t = threadIdx.x;
+    for (int j = t; j < kWaves * 256; j += kSortThreads) (&wcnt[0][0])[j] = 0u;
+    K key[kSortItems];
+    uint32_t rk[kSortItems];
+    const int in_tile = load_tile(keys, n, key);
     __syncthreads();
-    ghist[(int64_t)t * nblocks + blockIdx.x] = h[t];
-    if (h[t]) atomicAdd(&totals[t], h[t]);
+    rank_items(key, in_tile, shift, rk, wcnt);
+    __syncthreads();
+    if (t < 256) {
+        uint32_t tot = 0u;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) tot += wcnt[q][t];
+        cnt[(int64_t)t * nb + blockIdx.x] = tot;
+    }
 }
 
 // Exclusive scan in place.  A block scans a chunk of kScanChunk elements at
@@ -268,81 +418,100 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_excl(uint32_t *data, int6
     for (int64_t base = 0; base < m; base += kScanChunk) carry += scan_chunk(data, m, base, carry, wsum);
 }
 
-// One block per digit d: ghist[d][*] becomes the exclusive scan over the
-// blocks plus the count of all smaller digits.  Clears next_totals[d] for the
-// following pass.
-__global__ void __launch_bounds__(kScanThreads) k_sort_offsets(uint32_t *ghist, int nblocks,
-                                                               const uint32_t *__restrict__ totals,
-                                                               uint32_t *__restrict__ next_totals) {
+
+// One workgroup per digit d: cnt[d][*] becomes the exclusive scan over the
+// tiles plus the pass's count of all smaller digits (total: the pass's
+// digit counts, kCountCopies copies 2,048 words apart).
+__global__ void __launch_bounds__(kScanThreads) k_sort_scan(uint32_t *cnt, int nb, const uint32_t *__restrict__ total) {
     __shared__ uint32_t wsum[kScanThreads / 64];
     __shared__ uint32_t below;
     const int d = blockIdx.x, t = threadIdx.x;
-    if (t < 64) {
+    if (t < 256) {
         uint32_t x = 0u;
-        for (int k = t; k < d; k += 64) x += totals[k];
+        if (t < d) {
+#pragma unroll
+            for (int c = 0; c < kCountCopies; ++c) x += total[2048 * c + t];
+        }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-        if (t == 0) {
-            below = x;
-            next_totals[d] = 0u;
+        if ((t & 63) == 0) wsum[t >> 6] = x;
+    }
+    __syncthreads();
+    if (t == 0) below = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    uint32_t carry = below;
+    __syncthreads();  // wsum is reused by the scan
+    uint32_t *col = cnt + (int64_t)d * nb;
+    for (int64_t b0 = 0; b0 < nb; b0 += kScanChunk) carry += scan_chunk(col, nb, b0, carry, wsum);
+}
+
+// Stable scatter of tile blockIdx.x: its keys ranked by digit, put in digit
+// order in LDS, then written out with consecutive threads on consecutive
+// positions of each digit's run, from the tile's first position per digit
+// in goff[d * nb + tile].
+template <typename K>
+__global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const K *__restrict__ keys_in,
+                                                               const uint32_t *__restrict__ ids_in,
+                                                               K *__restrict__ keys_out,
+                                                               uint32_t *__restrict__ ids_out, int64_t n, int shift,
+                                                               const uint32_t *__restrict__ goff, int nb) {
+    constexpr int kWaves = kSortThreads / 64, kPerWave = kSortTile / kWaves;
+    __shared__ K skey[kSortTile];
+    __shared__ uint32_t sid[kSortTile];
+    __shared__ uint32_t wcnt[kWaves][256];  // per wave: digit counts, then offsets within the tile's digit
+    __shared__ uint32_t dstart[256], gpos[256];
+    __shared__ uint32_t wsum[kWaves];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    for (int j = t; j < kWaves * 256; j += kSortThreads) (&wcnt[0][0])[j] = 0u;
+    if (t < 256) gpos[t] = goff[(int64_t)t * nb + blockIdx.x];
+    K key[kSortItems];
+    uint32_t id[kSortItems], rk[kSortItems];
+    const int in_tile = load_tile(keys_in, n, key);
+    load_tile(ids_in, n, id);
+    __syncthreads();
+    rank_items(key, in_tile, shift, rk, wcnt);
+    __syncthreads();
+    // thread t < 256 = digit t: offsets of the waves within the tile's digit,
+    // then the digit's first position in the tile
+    uint32_t tot = 0u;
+    if (t < 256) {
+        for (int q = 0; q < kWaves; ++q) {
+            const uint32_t c = wcnt[q][t];
+            wcnt[q][t] = tot;
+            tot += c;
+        }
+    }
+    uint32_t x = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    uint32_t pre = 0u;
+    for (int q = 0; q < w; ++q) pre += wsum[q];
+    if (t < 256) dstart[t] = pre + x - tot;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const int e = w * kPerWave + k * 64 + lane;
+        if (e < in_tile) {
+            const uint32_t dg = (uint32_t)(key[k] >> shift) & 255u;
+            const uint32_t p = dstart[dg] + wcnt[w][dg] + rk[k];
+            skey[p] = key[k];
+            sid[p] = id[k];
         }
     }
     __syncthreads();
-    uint32_t carry = below;
-    uint32_t *col = ghist + (int64_t)d * nblocks;
-    for (int64_t b0 = 0; b0 < nblocks; b0 += kScanChunk) carry += scan_chunk(col, nblocks, b0, carry, wsum);
-}
-
-
-// Stable scatter: within each 256-element chunk, lanes with equal digits are
-// matched with 8 ballots, ranked by lane order, and offset by the counts of
-// earlier waves (LDS) and of earlier chunks and blocks.
-__global__ void __launch_bounds__(kThreads) k_sort_scatter(
-    const uint64_t *__restrict__ keys_in, const uint32_t *__restrict__ ids_in,
-    uint64_t *__restrict__ keys_out, uint32_t *__restrict__ ids_out, int64_t n, int shift,
-    const uint32_t *__restrict__ goff, int nblocks) {
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t wcount[kThreads / 64][256];
-    int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    run[t] = goff[(int64_t)t * nblocks + blockIdx.x];
-    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    for (int it = 0; it < kSortItems; ++it) {
-        int64_t i = (int64_t)blockIdx.x * kSortTile + it * kThreads + t;
-        bool valid = i < n;
-        uint64_t key = valid ? keys_in[i] : 0ull;
-        uint32_t id = valid ? ids_in[i] : 0u;
-        uint32_t digit = (uint32_t)(key >> shift) & 255u;
-#pragma unroll
-        for (int q = 0; q < kThreads / 64; ++q) wcount[q][t] = 0u;
-        __syncthreads();
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            bool bit = (digit >> b) & 1u;
-            uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
+    for (int j = t; j < in_tile; j += kSortThreads) {
+        const K kk = skey[j];
+        const uint32_t dg = (uint32_t)(kk >> shift) & 255u;
+        const uint32_t o = gpos[dg] + ((uint32_t)j - dstart[dg]);
+        if (o < (uint64_t)n) {  // always true for consistent counts
+            keys_out[o] = kk;
+            ids_out[o] = sid[j];
         }
-        uint32_t rank = (uint32_t)__popcll(peers & lt);
-        if (valid && rank == 0) wcount[w][digit] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        uint32_t total = 0;
-#pragma unroll
-        for (int q = 0; q < kThreads / 64; ++q) {
-            uint32_t c = wcount[q][t];
-            wcount[q][t] = total;
-            total += c;
-        }
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = run[digit] + wcount[w][digit] + rank;
-            if (pos < (uint64_t)n) {  // always true for a consistent histogram
-                keys_out[pos] = key;
-                ids_out[pos] = id;
-            }
-        }
-        __syncthreads();
-        run[t] += total;
-        __syncthreads();
     }
 }
 
@@ -780,6 +949,7 @@ struct SmallArgs {
     void *nodes;                    // nullable: binary hierarchy only
     uint32_t *parents, *levels;     // nullable
     const uint32_t *flag_in;        // nullable: a word of an earlier step (or of this kernel) returned with the summary
+    int32_t key_shift;              // 0 (63-bit keys) or 33 (their top 30 bits)
     SmallResult *res;
     // a top level built in the same launch (TLAS): each primitive is an
     // instance whose box and record the kernel computes from the tables; the
@@ -877,7 +1047,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_build(SmallArgs a) {
         // one element per thread (padding past n sorts last): bitonic sort by
         // (key, index) in registers, partners within a wave by shuffles,
         // across waves through LDS
-        uint64_t k0 = t < n ? morton_key(pbox + 6 * t, bnd) : ~0ull;
+        uint64_t k0 = t < n ? morton_key(pbox + 6 * t, bnd) >> a.key_shift : ~0ull;
         uint32_t v0 = (uint32_t)t;
 #pragma unroll
         for (int kk = 2; kk <= kResidentMax; kk <<= 1) {
@@ -927,7 +1097,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_build(SmallArgs a) {
         int P = 1;
         while (P < n) P <<= 1;
         for (int i = t; i < P; i += kSmallThreads) {
-            key[i] = i < n ? morton_key(a.prim_box + 6 * i, bnd) : ~0ull;  // padding sorts last
+            key[i] = i < n ? morton_key(a.prim_box + 6 * i, bnd) >> a.key_shift : ~0ull;  // padding sorts last
             id[i] = (uint32_t)i;
         }
         // bitonic sort by (key, index)
@@ -2092,12 +2262,15 @@ __global__ void k_reorder_inst(const RgInst *__restrict__ in, const uint32_t *__
 int node_bytes(int w) { return 32 * w; }
 
 struct Opts {
-    int32_t w, leaf, builder, radius;
+    int32_t w, leaf, builder, radius, bits;
+    int32_t key_shift() const { return bits == 10 ? 33 : 0; }  // the 30-bit key: top bits of the 63-bit one
+    bool fits(int64_t n) const { return bits != 10 || n <= RG_MORTON_BITS_COMPACT_MAX_PRIMS; }
 };
 
 bool opts_ok(const rg_build_opts *o, Opts *out) {
-    Opts r{4, 4, RG_BUILDER_LBVH, 0};
-    if (o) r = Opts{o->width, o->leaf_max, o->builder, o->radius};
+    Opts r{4, 4, RG_BUILDER_LBVH, 0, 21};
+    if (o) r = Opts{o->width, o->leaf_max, o->builder, o->radius, o->morton_bits == 0 ? 21 : o->morton_bits};
+    if (!(r.bits == 21 || r.bits == 10)) return false;
     if (!(r.w == 2 || r.w == 4 || r.w == 8)) return false;
     if (r.leaf < 1 || r.leaf > 8) return false;
     if (r.builder == RG_BUILDER_TREELET) {
@@ -2117,7 +2290,12 @@ uint64_t align256(uint64_t x) { return (x + 255u) & ~uint64_t(255); }
 struct LbvhScratch {
     float *leaf_box, *int_box;
     uint64_t *keys, *keys2;
-    uint32_t *ids, *ids2, *hist, *totals, *bounds, *qcount, *flags;
+    uint32_t *ids, *ids2, *qcount, *flags;
+    // sort: the digit counts of the eight passes (kCountCopies x 2048,
+    // cleared by k_centre_bounds), per-tile digit counts of one pass
+    uint32_t *sortz, *count, *cnt;
+    int64_t sortz_words;
+    float *part;  // centre-bound partials, 6 per block of k_centre_bounds
     int32_t *left, *right, *pint, *pleaf, *first, *last;
     uint2 *q0, *q1;
     int32_t *wch;       // wide-node plan: W children, W links per inner node (W up to 8), inner masks
@@ -2146,9 +2324,11 @@ bool carve(RgArena &a, int64_t n, int32_t builder, LbvhScratch &s) {
     s.keys2 = a.take<uint64_t>(n);
     s.ids = a.take<uint32_t>(n);
     s.ids2 = a.take<uint32_t>(n);
-    s.hist = a.take<uint32_t>(256 * nb);
-    s.totals = a.take<uint32_t>(512);
-    s.bounds = a.take<uint32_t>(8);
+    s.sortz_words = 2048 * kCountCopies;
+    s.sortz = a.take<uint32_t>(s.sortz_words);
+    s.count = s.sortz;
+    s.cnt = a.take<uint32_t>(256 * nb);
+    s.part = a.take<float>(6 * kBoundParts);
     s.qcount = a.take<uint32_t>(2 * kCollapseRing + 8);
     s.flags = a.take<uint32_t>(8);
     s.left = a.take<int32_t>(ni);
@@ -2411,6 +2591,7 @@ rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t
         sa.parents = parents;
         sa.levels = levels;
         sa.flag_in = out->flag_in;
+        sa.key_shift = out->key_shift;
         sa.res = s.small;
         const size_t lds = small_lds_bytes(n);
         const TlasFuse *fuse = reinterpret_cast<const TlasFuse *>(out->tlas_fuse);
@@ -2459,25 +2640,24 @@ rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t
         out->deferred = nullptr;
         return r;
     }
-    int nblocks = (int)((n + kSortTile - 1) / kSortTile);
-    // bounds of the centres
-    k_fill_u32<<<1, 64, 0, st>>>(s.bounds, 0xFFFFFFFFu, 3);
-    k_fill_u32<<<1, 64, 0, st>>>(s.bounds + 3, 0u, 3);
-    unsigned bb = rg_blocks(n, kThreads);
-    if (bb > 256) bb = 256;
-    k_centre_bounds<<<bb, kThreads, 0, st>>>(prim_box, n, s.bounds);
+    const int nblocks = (int)((n + kSortTile - 1) / kSortTile);
+    // centre bounds (partials; the sort's counters cleared), keys with the
+    // digit counts of every pass, then one launch per pass
+    int64_t bparts = (n + kThreads - 1) / kThreads;
+    if (bparts > kBoundParts) bparts = kBoundParts;
+    k_centre_bounds<<<(unsigned)bparts, kThreads, 0, st>>>(prim_box, n, s.part, s.sortz, s.sortz_words);
     RG_LAUNCH_CHECK();
-    k_morton<<<rg_blocks(n < 512 ? 512 : n, kThreads), kThreads, 0, st>>>(prim_box, n, s.bounds, s.keys, s.ids,
-                                                                           s.totals);
+    k_morton<<<nblocks, kSortThreads, 0, st>>>(prim_box, n, s.part, (int)bparts, out->key_shift, s.keys, s.ids,
+                                               s.count);
     RG_LAUNCH_CHECK();
-    // 8 passes of 8 bits; the result lands back in keys/ids
+    // 8 passes of 8 bits (4 for 30-bit keys); the result lands in ka / ia
     uint64_t *ka = s.keys, *kb = s.keys2;
     uint32_t *ia = s.ids, *ib = s.ids2;
-    for (int shift = 0; shift < 64; shift += 8) {
-        uint32_t *tot = s.totals + 256 * ((shift >> 3) & 1), *tot_next = s.totals + 256 * (((shift >> 3) + 1) & 1);
-        k_sort_hist<<<nblocks, kThreads, 0, st>>>(ka, n, shift, s.hist, nblocks, tot);
-        k_sort_offsets<<<256, kScanThreads, 0, st>>>(s.hist, nblocks, tot, tot_next);
-        k_sort_scatter<<<nblocks, kThreads, 0, st>>>(ka, ia, kb, ib, n, shift, s.hist, nblocks);
+    const int passes = out->key_shift ? 4 : 8;
+    for (int p = 0; p < passes; ++p) {
+        k_sort_count<uint64_t><<<nblocks, kSortThreads, 0, st>>>(ka, n, 8 * p, s.cnt, nblocks);
+        k_sort_scan<<<256, kScanThreads, 0, st>>>(s.cnt, nblocks, s.count + 256 * p);
+        k_sort_scatter<uint64_t><<<nblocks, kSortThreads, 0, st>>>(ka, ia, kb, ib, n, 8 * p, s.cnt, nblocks);
         RG_LAUNCH_CHECK();
         uint64_t *tk = ka; ka = kb; kb = tk;
         uint32_t *ti = ia; ia = ib; ib = ti;
@@ -2696,7 +2876,7 @@ const char *rg_status_string(rg_status s) {
 
 rg_status rg_blas_sizes(int64_t n_tris, const rg_build_opts *opts, rg_sizes *out) {
     Opts o;
-    if (!out || n_tris < 1 || n_tris > RG_MAX_TRIS || !opts_ok(opts, &o)) return RG_ERR_INVALID_ARG;
+    if (!out || n_tris < 1 || n_tris > RG_MAX_TRIS || !opts_ok(opts, &o) || !o.fits(n_tris)) return RG_ERR_INVALID_ARG;
     uint64_t a, b, c, d, e, f;
     out->bytes = blas_out_bytes(n_tris, o.w, &a, &b, &c, &d, &e, &f);
     out->scratch_bytes = blas_scratch_bytes(n_tris, o.builder);
@@ -2709,7 +2889,7 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
     Opts o;
     if (!verts || !idx || !out_buf || !scratch || !out) return RG_ERR_INVALID_ARG;
     if (n_verts < 1 || n_verts > (1ll << 32) || n_tris < 1 || n_tris > RG_MAX_TRIS) return RG_ERR_INVALID_ARG;
-    if (!opts_ok(opts, &o)) return RG_ERR_INVALID_ARG;
+    if (!opts_ok(opts, &o) || !o.fits(n_tris)) return RG_ERR_INVALID_ARG;
     const int32_t w = o.w, l = o.leaf;
     uint64_t no, to, mo, so, po, lvo;
     uint64_t need = blas_out_bytes(n_tris, w, &no, &to, &mo, &so, &po, &lvo);
@@ -2739,6 +2919,7 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
     char *base = (char *)out_buf;
     RgLbvhOut lo;
     lo.deferred = summary;
+    lo.key_shift = o.key_shift();
     rg_status r = rg_lbvh_build(pbox, n_tris, w, l, o.builder, o.radius, base + no, (uint32_t *)(base + po),
                                 (uint32_t *)(base + lvo), arena, st, &lo, false, nullptr, nullptr, nullptr, nullptr);
     if (r != RG_OK) {
@@ -2896,7 +3077,7 @@ rg_status rg_blas_set_alpha(rg_blas *blas, const uint64_t *alpha, int32_t level,
 
 rg_status rg_tlas_sizes(int64_t n_inst, const rg_build_opts *opts, rg_sizes *out) {
     Opts o;
-    if (!out || n_inst < 1 || n_inst > RG_MAX_TRIS || !opts_ok(opts, &o)) return RG_ERR_INVALID_ARG;
+    if (!out || n_inst < 1 || n_inst > RG_MAX_TRIS || !opts_ok(opts, &o) || !o.fits(n_inst)) return RG_ERR_INVALID_ARG;
     uint64_t a, b, c, d;
     out->bytes = tlas_out_bytes(n_inst, o.w, &a, &b, &c, &d);
     out->scratch_bytes = tlas_scratch_bytes(n_inst, 4096, o.builder);
@@ -2910,7 +3091,7 @@ rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xfo
     Opts o;
     if (!blas || !xform || !blas_id || !inst_material || !out_buf || !scratch || !out) return RG_ERR_INVALID_ARG;
     if (n_blas < 1 || n_blas > 4096 || n_inst < 1 || n_inst > RG_MAX_TRIS) return RG_ERR_INVALID_ARG;
-    if (!opts_ok(opts, &o)) return RG_ERR_INVALID_ARG;
+    if (!opts_ok(opts, &o) || !o.fits(n_inst)) return RG_ERR_INVALID_ARG;
     const int32_t w = o.w;
     int32_t max_depth = 0;
     std::vector<BlasInfo> info((size_t)n_blas);
@@ -2989,6 +3170,7 @@ rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xfo
     RgLbvhOut lo;
     lo.deferred = summary;
     lo.flag_in = d_flag;
+    lo.key_shift = o.key_shift();
     lo.tlas_fuse = fused ? &F : nullptr;
     rg_status r = rg_lbvh_build(d_box, n_inst, w, 1, o.builder, o.radius, base + no, nullptr, nullptr, arena, st, &lo,
                                 false, nullptr, nullptr, nullptr, nullptr);
@@ -3046,7 +3228,8 @@ rg_status rg_lbvh_stages(const float *verts, int64_t n_verts, const uint32_t *id
     Opts o;
     if (!verts || !idx || !keys || !ids || !boxes || !scratch) return RG_ERR_INVALID_ARG;
     if (n_tris > 1 && (!left || !right)) return RG_ERR_INVALID_ARG;
-    if (n_verts < 1 || n_tris < 1 || n_tris > RG_MAX_TRIS || !opts_ok(opts, &o)) return RG_ERR_INVALID_ARG;
+    if (n_verts < 1 || n_tris < 1 || n_tris > RG_MAX_TRIS || !opts_ok(opts, &o) || !o.fits(n_tris))
+        return RG_ERR_INVALID_ARG;
     if (scratch_bytes < blas_scratch_bytes(n_tris, o.builder)) return RG_ERR_OUT_OF_MEMORY;
     hipStream_t st = (hipStream_t)stream;
     RgArena arena{(char *)scratch, scratch_bytes, 0};
@@ -3060,6 +3243,7 @@ rg_status rg_lbvh_stages(const float *verts, int64_t n_verts, const uint32_t *id
     RG_HIP(hipStreamSynchronize(st));
     if (hflags) return RG_ERR_INVALID_ARG;
     RgLbvhOut lo;
+    lo.key_shift = o.key_shift();
     rg_status r = rg_lbvh_build(pbox, n_tris, o.w, o.leaf, o.builder, o.radius, nullptr, nullptr, nullptr, arena,
                                 st, &lo, true, keys, left, right, boxes);
     if (r != RG_OK) return r;

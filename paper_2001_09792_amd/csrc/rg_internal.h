@@ -157,6 +157,9 @@ struct RgLbvhOut {
     // Set by a larger build given `deferred`: the root box is on its way to
     // deferred[4..9]; rg_lbvh_finish (after the caller's wait) reads it.
     bool pending_box = false;
+    // Set by the caller: 0 for 63-bit Morton keys, 33 for their top 30 bits
+    // (ten per axis; four sort passes).
+    int32_t key_shift = 0;
     // Set by the top-level build (nullable): a one-workgroup linear build of
     // up to 1,024 instances then also computes the instances' boxes and
     // records from the uploaded tables and writes the records in leaf order.

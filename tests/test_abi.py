@@ -251,3 +251,17 @@ def test_treelet_builder_options():
     assert lib.rg_blas_sizes(1000, ctypes.byref(o), ctypes.byref(s)) == -1       # unknown builder
     lbvh, tr = rg.blas_sizes(5000, builder="lbvh"), rg.blas_sizes(5000, builder="treelet")
     assert tr[0] == lbvh[0] and tr[1] > lbvh[1]          # same output, more scratch
+
+
+def test_morton_bits_option():
+    """Key width: 0 / 21 (63-bit keys) or 10 (30-bit keys, at most 2^20
+    primitives); anything else is rejected before any GPU work."""
+    import paper_2001_09792_amd as rg
+    lib, s = rg._lib, rg.Sizes()
+    assert rg.blas_sizes(1000, morton_bits=10) == rg.blas_sizes(1000)
+    assert rg.blas_sizes(1000, morton_bits=21) == rg.blas_sizes(1000)
+    assert rg.blas_sizes(1 << 20, morton_bits=10)[0] > 0
+    for bits, n in ((11, 1000), (32, 1000), (-1, 1000), (10, (1 << 20) + 1)):
+        o = rg.BuildOpts(4, 4, 0, 0, bits)
+        assert lib.rg_blas_sizes(n, ctypes.byref(o), ctypes.byref(s)) == -1, (bits, n)
+        assert lib.rg_tlas_sizes(n, ctypes.byref(o), ctypes.byref(s)) == -1, (bits, n)

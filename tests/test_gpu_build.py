@@ -19,7 +19,7 @@ def _dev(mesh):
 
 
 MESHES = {
-    "soup5000": lambda: sg.random_soup(5000, 21),          # 3 sort tiles and a ragged tail
+    "soup5000": lambda: sg.random_soup(5000, 21),          # one ragged sort tile
     "small": lambda: sg.config_small().blas[0],
     "torus": lambda: sg.torus(48, 40, 1.0, 0.35, 0.08, 6.0, 3001),
     "two": lambda: sg.random_soup(2, 5),
@@ -57,6 +57,58 @@ def test_lbvh_stages_match_definitions(name):
         boxes = st["boxes"].cpu().numpy()
         assert np.array_equal(boxes[: n - 1, :3], blo) and np.array_equal(boxes[: n - 1, 3:], bhi)
         assert np.array_equal(boxes[n - 1:, :3], lo[ref_ids]) and np.array_equal(boxes[n - 1:, 3:], hi[ref_ids])
+
+
+@pytest.mark.parametrize("name", ["soup1024", "soup4096", "torus", "dupes", "soup5000", "soup700001"])
+def test_compact_keys_match_definitions(name):
+    """30-bit keys (10 bits per axis, four sort passes): keys, stable order,
+    radix tree and boxes equal the oracle's definitions for that width, in
+    the one-workgroup builds (resident and not) and the multi-launch one."""
+    import paper_2001_09792_amd as rg
+    mesh = sg.random_soup(700001, 27) if name == "soup700001" else MESHES[name]()
+    print(f"[compact keys] {name}: {mesh.n_tris} tris", flush=True)
+    v, i = _dev(mesh)
+    st = rg.lbvh_stages(v, i, morton_bits=10)
+    ref_sorted, ref_ids = br.sort_pairs(br.morton_keys(mesh.verts, mesh.idx, br.BITS_COMPACT))
+    assert np.array_equal(st["keys"].cpu().numpy().view(np.uint64), ref_sorted), "keys differ"
+    assert np.array_equal(st["ids"].cpu().numpy().view(np.uint32), ref_ids), "the sort must be stable"
+    n = mesh.n_tris
+    if n <= 5000:  # the plain radix tree of the oracle is a Python loop
+        left, right, first, last = br.radix_tree(ref_sorted)
+        assert np.array_equal(st["left"].cpu().numpy(), left.astype(np.int32))
+        assert np.array_equal(st["right"].cpu().numpy(), right.astype(np.int32))
+        lo, hi = br.tri_boxes(mesh.verts, mesh.idx)
+        blo, bhi = br.refit(lo[ref_ids], hi[ref_ids], first, last)
+        boxes = st["boxes"].cpu().numpy()
+        assert np.array_equal(boxes[: n - 1, :3], blo) and np.array_equal(boxes[: n - 1, 3:], bhi)
+    b = rg.build_blas(v, i, None, 4, 4, morton_bits=10)
+    info = bvh_check.check_blas(b.buf.cpu().numpy(), b.desc)
+    assert np.array_equal(info["verts"], mesh.verts[mesh.idx[info["prim"]]])
+
+
+def _soup_with_repeats(n_tris, n_distinct, seed):
+    """n_tris triangles drawn (seeded) from n_distinct ones: long runs of equal
+    keys whose stable order spans many sort tiles."""
+    base = sg.random_soup(n_distinct, seed)
+    tris = base.verts[base.idx.astype(np.int64)]
+    pick = np.random.default_rng(seed).integers(0, n_distinct, n_tris)
+    return sg.triangles_mesh(tris[pick])
+
+
+@pytest.mark.parametrize("name", ["soup700001", "repeats200000"])
+def test_sort_across_many_tiles(name):
+    """The radix sort over many tiles (each pass a single launch whose tiles
+    add up the counts of the tiles before them): keys and ids equal a stable
+    argsort of the oracle's Morton keys, also where equal keys run through
+    many tiles."""
+    import paper_2001_09792_amd as rg
+    mesh = sg.random_soup(700001, 27) if name == "soup700001" else _soup_with_repeats(200000, 37, 28)
+    print(f"[sort tiles] {name}: {mesh.n_tris} tris", flush=True)
+    v, i = _dev(mesh)
+    st = rg.lbvh_stages(v, i)
+    ref_sorted, ref_ids = br.sort_pairs(br.morton_keys(mesh.verts, mesh.idx))
+    assert np.array_equal(st["keys"].cpu().numpy().view(np.uint64), ref_sorted), "keys differ"
+    assert np.array_equal(st["ids"].cpu().numpy().view(np.uint32), ref_ids), "the sort must be stable"
 
 
 @pytest.mark.parametrize("name,radius", [("soup5000", 16), ("soup5000", 1), ("small", 32), ("torus", 8),

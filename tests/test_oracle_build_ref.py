@@ -25,6 +25,28 @@ def test_quantise_extremes():
     assert (q[:, 1] == 0).all() and (q[:, 2] == 0).all()
 
 
+def test_compact_keys():
+    """30-bit keys (10 bits per axis): hand values of the quantisation and the
+    interleave, and the relation to the 63-bit keys: scaling by 2^21 is
+    scaling by 2^10 times 2^11 exactly in float32, so each 10-bit coordinate
+    is its 21-bit one shifted right by 11 and the 30-bit key is the 63-bit
+    key's top 30 bits."""
+    B = br.BITS_COMPACT
+    q = np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1], [2, 0, 0], [2 ** B - 1] * 3], np.uint64)
+    k = br.interleave(q, B)
+    assert list(k[:4]) == [4, 2, 1, 32]
+    assert int(k[4]) == 2 ** 30 - 1
+    c = np.array([[0, 0, 0], [1, 2, 3], [0.5, 1, 1.5], [0.25, 0.5, 0.75]], np.float32)
+    qq = br.quantise(c, c.min(0), c.max(0), B)
+    assert (qq[0] == 0).all() and (qq[1] == 1023).all() and (qq[2] == 512).all() and (qq[3] == 256).all()
+    for seed, mesh in enumerate([sg.random_soup(3000, 61), sg.torus(40, 30, 1.0, 0.3, 0.05, 6.0, 62),
+                                 sg.random_soup(500, 63, extent=1e-3, size=1e-4)]):
+        k63 = br.morton_keys(mesh.verts, mesh.idx)
+        k30 = br.morton_keys(mesh.verts, mesh.idx, B)
+        assert k30.max() < 2 ** 30
+        assert np.array_equal(k30, k63 >> np.uint64(33)), seed
+
+
 def test_karras_figure_tree():
     """The 8-key example tree (5-bit keys 00001 00010 00100 00101 10011 11000
     11001 11110), split by hand at the highest differing bit."""
