@@ -588,8 +588,9 @@ __device__ inline float surface_area(const float *b) {
     return 2.0f * (dx * dy + dy * dz + dz * dx);
 }
 
-constexpr int kCollapseRing = 16;   // per-level bookkeeping slots on the device
-constexpr int kCollapseBatch = 8;   // levels launched between host reads (< kCollapseRing - 2)
+constexpr int kCollapseRing = 24;   // per-level bookkeeping slots on the device
+constexpr int kCollapseBatch = 8;   // levels launched between host reads after the first batch
+constexpr int kCollapseFirstMax = kCollapseRing - 3;  // the first batch (sized from n) at most
 
 // The children of the wide node that stands for binary inner node b: b's
 // two children, then repeatedly the inner one of largest surface area opened
@@ -2522,9 +2523,14 @@ rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes_v,
     // after the last one find an empty queue and return.
     uint32_t known = 1;  // size of level `d`, the first of the next batch
     int32_t d = 0, levels_n = 0;
+    // the first batch covers the depth a tree of n leaves usually reaches
+    // (1.6 log_W n + 2 levels: a host read, and so a wait, less than with
+    // fixed batches for most trees); later ones kCollapseBatch levels
+    int batch = (int)std::ceil(1.6 * std::log((double)n) / std::log((double)W)) + 2;
+    batch = std::max(kCollapseBatch, std::min(kCollapseFirstMax, batch));
     while (levels_n == 0) {
         uint64_t bound = known;
-        for (int j = 0; j < kCollapseBatch; ++j) {
+        for (int j = 0; j < batch; ++j) {
             unsigned blocks = rg_blocks((int64_t)(bound ? bound : 1), kThreads);
             if (blocks > 1024) blocks = 1024;
             const int level = d + j;
@@ -2538,7 +2544,7 @@ rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes_v,
         RG_HIP(hipMemcpyAsync(hr, ring, sizeof(hr), hipMemcpyDeviceToHost, st));
         RG_HIP(hipStreamSynchronize(st));
         if (hr[2 * kCollapseRing] != 0u) return RG_ERR_HIP;  // inconsistent hierarchy: never expected
-        for (int j = 0; j < kCollapseBatch; ++j) {
+        for (int j = 0; j < batch; ++j) {
             const uint32_t c = hr[(d + j + 1) % kCollapseRing];  // nodes of level d + j + 1
             if (c == 0u) {
                 levels_n = d + j + 1;
@@ -2547,7 +2553,8 @@ rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes_v,
             starts.push_back(starts.back() + c);
             known = c;
         }
-        d += kCollapseBatch;
+        d += batch;
+        batch = kCollapseBatch;
         if (d > 4096) return RG_ERR_HIP;  // never expected
     }
     d = levels_n;
