@@ -9,7 +9,9 @@
  * a small payload.  Section 2.1 adds multiple objects, reflection, refraction
  * and shadow casting.  This header turns those steps into calls:
  *
- *   bottom level from vertex data            rg_build_blas   (+ rg_blas_sizes)
+ *   bottom level from vertex data            rg_build_blas   (+ rg_blas_sizes;
+ *                                            enqueued: rg_build_blas_async /
+ *                                            rg_build_blas_finish)
  *   top level from instances and matrices    rg_build_tlas   (+ rg_tlas_sizes)
  *   ray generation                           rg_camera_rays, rg_ao_rays
  *   closest hit / miss per ray               rg_trace_closest
@@ -242,6 +244,32 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
                         const uint16_t *prim_material, const rg_build_opts *opts,
                         void *out_buf, uint64_t out_bytes, void *scratch, uint64_t scratch_bytes,
                         void *stream, rg_blas *out /*host*/);
+
+/* rg_build_blas without the wait (section 1's first step, enqueued): the
+ * whole build of the linear builder (RG_BUILDER_LBVH; others:
+ * RG_ERR_UNSUPPORTED) goes onto `stream` and the call returns; the
+ * descriptor comes from rg_build_blas_finish.  ticket: RG_BUILD_TICKET_BYTES
+ * of pinned host memory (hipHostMalloc or a pinned tensor), 16-byte
+ * aligned, owned by the caller: the build's summary lands there by
+ * asynchronous copies.  verts, idx, prim_material, out_buf, scratch and the
+ * ticket must stay untouched until rg_build_blas_finish returns (so builds
+ * that overlap need scratch buffers of their own).  Arguments, sizes and
+ * errors detected on the host as rg_build_blas, returned at once. */
+#define RG_BUILD_TICKET_BYTES 1024
+rg_status rg_build_blas_async(const float *verts, int64_t n_verts, const uint32_t *idx, int64_t n_tris,
+                              const uint16_t *prim_material, const rg_build_opts *opts, void *out_buf,
+                              uint64_t out_bytes, void *scratch, uint64_t scratch_bytes, void *stream,
+                              void *ticket /*pinned host*/);
+
+/* Completes an rg_build_blas_async: waits until its stream has finished that
+ * build (not the work queued after it), fills *out (as rg_build_blas does)
+ * and returns the build's error: RG_ERR_INVALID_ARG for an index >= n_verts
+ * or a non-finite vertex (found on the device), or for a ticket that holds
+ * no pending build (each completes once).  A hierarchy deeper than the
+ * levels the asynchronous call launched (rare: more than about 1.6 log_W
+ * n_tris + 2) gets its remaining levels here, on the build's stream, with a
+ * wait for them. */
+rg_status rg_build_blas_finish(void *ticket /*pinned host*/, rg_blas *out /*host*/);
 
 /* Scratch for rg_refit_blas on `blas` (host call, no GPU work). */
 rg_status rg_refit_sizes(const rg_blas *blas /*host*/, uint64_t *scratch_bytes /*host*/);

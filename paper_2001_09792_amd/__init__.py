@@ -134,6 +134,8 @@ SIGNATURES = {
     "rg_last_error": (ctypes.c_char_p, []),
     "rg_blas_sizes": (c_i32, [c_i64, c_p, c_p]),
     "rg_build_blas": (c_i32, [c_p, c_i64, c_p, c_i64, c_p, c_p, c_p, c_u64, c_p, c_u64, c_p, c_p]),
+    "rg_build_blas_async": (c_i32, [c_p, c_i64, c_p, c_i64, c_p, c_p, c_p, c_u64, c_p, c_u64, c_p, c_p]),
+    "rg_build_blas_finish": (c_i32, [c_p, c_p]),
     "rg_tlas_sizes": (c_i32, [c_i64, c_p, c_p]),
     "rg_build_tlas": (c_i32, [c_p, c_i32, c_p, c_p, c_p, c_i64, c_p, c_p, c_u64, c_p, c_u64, c_p, c_p]),
     "rg_trace_closest": (c_i32, [c_p, Rays, c_i64, Hits, c_p]),
@@ -291,6 +293,46 @@ def build_blas(verts, idx, prim_mat=None, width: int = 4, leaf_max: int = 4, scr
         _ptr(verts), int(verts.shape[0]), _ptr(idx), n_tris, _ptr(prim_mat), ctypes.byref(o),
         _ptr(buf), buf.numel(), _ptr(scratch), scratch.numel(), _stream(stream), ctypes.byref(d)))
     return Blas(buf, d)
+
+
+BUILD_TICKET_BYTES = 1024
+
+
+class PendingBlas:
+    """A bottom-level build enqueued by build_blas_async: the inputs, the
+    output and scratch buffers and the pinned ticket stay referenced here
+    until finish() returns the Blas."""
+
+    def __init__(self, keep, buf, ticket):
+        self._keep = keep
+        self.buf = buf
+        self.ticket = ticket
+
+    def finish(self) -> Blas:
+        d = BlasDesc()
+        _check("rg_build_blas_finish", _lib.rg_build_blas_finish(self.ticket.data_ptr(), ctypes.byref(d)))
+        self._keep = None
+        return Blas(self.buf, d)
+
+
+def build_blas_async(verts, idx, prim_mat=None, width: int = 4, leaf_max: int = 4, scratch=None,
+                     stream=None, morton_bits: int = 0) -> PendingBlas:
+    """build_blas for the linear builder without the wait: the build is
+    enqueued on `stream` and finish() on the result waits for it.  Builds
+    in flight together need scratch buffers of their own (pass none to get
+    a new one)."""
+    torch = _torch()
+    n_tris = int(idx.shape[0])
+    nb, ns = blas_sizes(n_tris, width, leaf_max, "lbvh", 0, morton_bits)
+    buf = _bytes(nb, verts.device)
+    if scratch is None or scratch.numel() < ns:
+        scratch = _bytes(ns, verts.device)
+    ticket = torch.empty(BUILD_TICKET_BYTES, dtype=torch.uint8, pin_memory=True)
+    o = _opts(width, leaf_max, "lbvh", 0, morton_bits)
+    _check("rg_build_blas_async", _lib.rg_build_blas_async(
+        _ptr(verts), int(verts.shape[0]), _ptr(idx), n_tris, _ptr(prim_mat), ctypes.byref(o),
+        _ptr(buf), buf.numel(), _ptr(scratch), scratch.numel(), _stream(stream), ticket.data_ptr()))
+    return PendingBlas((verts, idx, prim_mat, scratch), buf, ticket)
 
 
 def refit_blas(blas: Blas, verts, idx, scratch=None, stream=None) -> Blas:

@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <vector>
 
 #include "rg_internal.h"
@@ -2492,76 +2493,135 @@ rg_status treelet_build(int64_t n, int rounds, const uint32_t *ids, uint32_t *id
     return relabel_leaves(s, n, ids, ids_out, s.cbox[0], st);
 }
 
+// A level-by-level collapse between host reads.  Levels go in batches; the
+// host learns their sizes after each batch (the counts in the device ring).
+// A level's size is at most W times the one before, which bounds the grids
+// of the levels launched before their sizes are known; levels launched after
+// the last one find an empty queue and return.
+struct CollapseState {
+    int32_t width = 4;
+    int32_t d = 0;         // first level of the next batch
+    int32_t batch = 0;     // levels in the batch last launched
+    int32_t depth = 0;     // the number of levels, once known
+    uint32_t known = 1;    // size of level d
+    uint32_t cap = 0;
+    uint64_t n_nodes = 1;  // nodes of the levels known so far
+    const int32_t *wch;
+    const uint32_t *wlink;
+    const uint8_t *winner;
+    const float *int_box, *leaf_box;
+    uint2 *q[2];
+    uint32_t *ring;
+    void *nodes;
+    uint32_t *parents, *levels;
+};
+constexpr int kRingWords = 2 * kCollapseRing + 1;  // what the host reads after a batch
+
 template <int W>
-rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes_v, uint32_t *parents,
-                   uint32_t *levels, hipStream_t st, int32_t *depth, int64_t *n_nodes) {
-    RgNode<W> *nodes = reinterpret_cast<RgNode<W> *>(nodes_v);
-    // nodes are allocated level by level: starts[l] .. starts[l+1] is level l
-    std::vector<uint32_t> starts{0u, 1u};
+void collapse_batch(const CollapseState &c, hipStream_t st) {
+    uint64_t bound = c.known;
+    for (int j = 0; j < c.batch; ++j) {
+        unsigned blocks = rg_blocks((int64_t)(bound ? bound : 1), kThreads);
+        if (blocks > 1024) blocks = 1024;
+        const int level = c.d + j;
+        k_collapse<W><<<blocks, kThreads, 0, st>>>(c.wch, c.wlink, c.winner, c.int_box, c.leaf_box, c.q[level & 1],
+                                                    c.q[(level + 1) & 1], c.ring, level,
+                                                    reinterpret_cast<RgNode<W> *>(c.nodes), c.parents, c.levels,
+                                                    c.cap);
+        bound = std::min<uint64_t>((uint64_t)c.cap, bound * (uint64_t)W);
+    }
+}
+
+rg_status collapse_launch(const CollapseState &c, hipStream_t st) {
+    if (c.width == 2) collapse_batch<2>(c, st);
+    else if (c.width == 4) collapse_batch<4>(c, st);
+    else collapse_batch<8>(c, st);
+    RG_LAUNCH_CHECK();
+    return RG_OK;
+}
+
+// Takes in the counts read after a batch: the depth once a level comes out
+// empty, else the next batch (kCollapseBatch levels) to launch.
+rg_status collapse_absorb(CollapseState &c, const uint32_t *hr) {
+    if (hr[2 * kCollapseRing] != 0u) return RG_ERR_HIP;  // inconsistent hierarchy: never expected
+    for (int j = 0; j < c.batch; ++j) {
+        const uint32_t cnt = hr[(c.d + j + 1) % kCollapseRing];  // nodes of level d + j + 1
+        if (cnt == 0u) {
+            c.depth = c.d + j + 1;
+            return RG_OK;
+        }
+        c.n_nodes += cnt;
+        c.known = cnt;
+    }
+    c.d += c.batch;
+    c.batch = kCollapseBatch;
+    if (c.d > 4096 || c.n_nodes > c.cap) return RG_ERR_HIP;  // never expected
+    return RG_OK;
+}
+
+// Launches the plan and the first batch (sized to cover the depth a tree of
+// n leaves usually reaches, 1.6 log_W n + 2 levels, so that most builds read
+// the counts once).  n == 1: the single root, depth known at once.
+template <int W>
+rg_status collapse_begin(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes, uint32_t *parents,
+                         uint32_t *levels, hipStream_t st, CollapseState &c) {
+    c = CollapseState{};
+    c.width = W;
     if (n == 1) {
-        k_single_root<W><<<1, 64, 0, st>>>(s.leaf_box, nodes);
+        k_single_root<W><<<1, 64, 0, st>>>(s.leaf_box, reinterpret_cast<RgNode<W> *>(nodes));
         if (parents) k_fill_u32<<<1, 64, 0, st>>>(parents, RG_MISS, 1);
         if (levels) {
             k_fill_u32<<<1, 64, 0, st>>>(levels, 0u, 1);
             k_fill_u32<<<1, 64, 0, st>>>(levels + 1, 1u, 1);
         }
         RG_LAUNCH_CHECK();
-        *depth = 1;
-        *n_nodes = 1;
+        c.depth = 1;
         return RG_OK;
     }
-    uint32_t *ring = s.qcount;
-    const uint32_t cap = (uint32_t)(n - 1);
+    c.cap = (uint32_t)(n - 1);
+    c.wch = s.wch;
+    c.wlink = s.wlink;
+    c.winner = s.winner;
+    c.int_box = s.int_box;
+    c.leaf_box = s.leaf_box;
+    c.q[0] = s.q0;
+    c.q[1] = s.q1;
+    c.ring = s.qcount;
+    c.nodes = nodes;
+    c.parents = parents;
+    c.levels = levels;
     k_wide_plan<W><<<rg_blocks(n - 1, kThreads), kThreads, 0, st>>>(s.left, s.right, s.first, s.last, s.int_box,
                                                                      leaf_max, n - 1, s.wch, s.wlink, s.winner);
-    k_collapse_init<<<1, 1, 0, st>>>(s.q0, ring, parents, levels);
+    k_collapse_init<<<1, 1, 0, st>>>(s.q0, c.ring, parents, levels);
     RG_LAUNCH_CHECK();
-    uint2 *q[2] = {s.q0, s.q1};
-    // levels go in batches; the host learns their sizes after each batch.  A
-    // level's size is at most W times the one before, which bounds the grids
-    // of the levels launched before their sizes are known.  Levels launched
-    // after the last one find an empty queue and return.
-    uint32_t known = 1;  // size of level `d`, the first of the next batch
-    int32_t d = 0, levels_n = 0;
-    // the first batch covers the depth a tree of n leaves usually reaches
-    // (1.6 log_W n + 2 levels: a host read, and so a wait, less than with
-    // fixed batches for most trees); later ones kCollapseBatch levels
-    int batch = (int)std::ceil(1.6 * std::log((double)n) / std::log((double)W)) + 2;
-    batch = std::max(kCollapseBatch, std::min(kCollapseFirstMax, batch));
-    while (levels_n == 0) {
-        uint64_t bound = known;
-        for (int j = 0; j < batch; ++j) {
-            unsigned blocks = rg_blocks((int64_t)(bound ? bound : 1), kThreads);
-            if (blocks > 1024) blocks = 1024;
-            const int level = d + j;
-            k_collapse<W><<<blocks, kThreads, 0, st>>>(s.wch, s.wlink, s.winner, s.int_box, s.leaf_box,
-                                                        q[level & 1], q[(level + 1) & 1], ring, level, nodes,
-                                                        parents, levels, cap);
-            bound = std::min<uint64_t>((uint64_t)cap, bound * (uint64_t)W);
-        }
-        RG_LAUNCH_CHECK();
-        uint32_t hr[2 * kCollapseRing + 1];
-        RG_HIP(hipMemcpyAsync(hr, ring, sizeof(hr), hipMemcpyDeviceToHost, st));
+    const int b = (int)std::ceil(1.6 * std::log((double)n) / std::log((double)W)) + 2;
+    c.batch = std::max(kCollapseBatch, std::min(kCollapseFirstMax, b));
+    return collapse_launch(c, st);
+}
+
+// Reads the counts of the batch in flight (into hr, pinned or not) and goes
+// on until the depth is known; waits for `st` at each read.
+rg_status collapse_finish(CollapseState &c, hipStream_t st, uint32_t *hr) {
+    while (c.depth == 0) {
+        RG_HIP(hipMemcpyAsync(hr, c.ring, kRingWords * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         RG_HIP(hipStreamSynchronize(st));
-        if (hr[2 * kCollapseRing] != 0u) return RG_ERR_HIP;  // inconsistent hierarchy: never expected
-        for (int j = 0; j < batch; ++j) {
-            const uint32_t c = hr[(d + j + 1) % kCollapseRing];  // nodes of level d + j + 1
-            if (c == 0u) {
-                levels_n = d + j + 1;
-                break;
-            }
-            starts.push_back(starts.back() + c);
-            known = c;
-        }
-        d += batch;
-        batch = kCollapseBatch;
-        if (d > 4096) return RG_ERR_HIP;  // never expected
+        rg_status r = collapse_absorb(c, hr);
+        if (r != RG_OK) return r;
+        if (c.depth == 0 && (r = collapse_launch(c, st)) != RG_OK) return r;
     }
-    d = levels_n;
-    const uint32_t nn = starts.back();  // levels are numbered contiguously (the kernels wrote the level table)
-    if (starts.size() != (size_t)d + 1) return RG_ERR_HIP;  // never expected
-    *depth = d;
-    *n_nodes = nn;
+    return RG_OK;
+}
+
+template <int W>
+rg_status collapse(const LbvhScratch &s, int64_t n, int leaf_max, void *nodes, uint32_t *parents,
+                   uint32_t *levels, hipStream_t st, int32_t *depth, int64_t *n_nodes) {
+    CollapseState c;
+    rg_status r = collapse_begin<W>(s, n, leaf_max, nodes, parents, levels, st, c);
+    if (r != RG_OK) return r;
+    uint32_t hr[kRingWords];
+    if ((r = collapse_finish(c, st, hr)) != RG_OK) return r;
+    *depth = c.depth;
+    *n_nodes = (int64_t)c.n_nodes;
     return RG_OK;
 }
 
@@ -2708,7 +2768,15 @@ rg_status rg_lbvh_build(const float *prim_box, int64_t n, int32_t width, int32_t
     }
     out->ids = ia;
     rg_status r = RG_OK;
-    if (nodes) {
+    if (nodes && out->coll_async) {  // the first batch only; the caller completes the collapse
+        CollapseState &c = *static_cast<CollapseState *>(out->coll_async);
+        if (width == 2) r = collapse_begin<2>(s, n, leaf_max, nodes, parents, levels, st, c);
+        else if (width == 4) r = collapse_begin<4>(s, n, leaf_max, nodes, parents, levels, st, c);
+        else r = collapse_begin<8>(s, n, leaf_max, nodes, parents, levels, st, c);
+        if (r != RG_OK) return r;
+        if (c.depth == 0)
+            RG_HIP(hipMemcpyAsync(out->coll_hr, c.ring, kRingWords * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    } else if (nodes) {
         if (width == 2) r = collapse<2>(s, n, leaf_max, nodes, parents, levels, st, &out->depth, &out->n_nodes);
         else if (width == 4) r = collapse<4>(s, n, leaf_max, nodes, parents, levels, st, &out->depth, &out->n_nodes);
         else r = collapse<8>(s, n, leaf_max, nodes, parents, levels, st, &out->depth, &out->n_nodes);
@@ -2966,6 +3034,121 @@ rg_status rg_build_blas(const float *verts, int64_t n_verts, const uint32_t *idx
     }
     out->has_alpha = 0;
     out->alpha_level = 0;
+    return RG_OK;
+}
+
+// The state of an asynchronous bottom-level build, kept in the caller's
+// pinned ticket: the device summaries land in it by asynchronous copies.
+struct BlasTicket {
+    uint64_t magic;
+    hipStream_t st;
+    hipEvent_t done;
+    uint32_t summary[12];    // one-workgroup summary (10 words) or the root box at 4..9; input flags at 10
+    uint32_t hr[kRingWords];  // the collapse's level counts after its first batch
+    RgLbvhOut lo;
+    CollapseState coll;
+    rg_blas desc;            // what is known at enqueue time
+};
+constexpr uint64_t kTicketMagic = 0x7267424c41534174ull;
+static_assert(sizeof(BlasTicket) <= RG_BUILD_TICKET_BYTES, "ticket size");
+
+rg_status rg_build_blas_async(const float *verts, int64_t n_verts, const uint32_t *idx, int64_t n_tris,
+                              const uint16_t *prim_material, const rg_build_opts *opts, void *out_buf,
+                              uint64_t out_bytes, void *scratch, uint64_t scratch_bytes, void *stream, void *ticket) {
+    Opts o;
+    if (!verts || !idx || !out_buf || !scratch || !ticket || ((uintptr_t)ticket & 15u)) return RG_ERR_INVALID_ARG;
+    if (n_verts < 1 || n_verts > (1ll << 32) || n_tris < 1 || n_tris > RG_MAX_TRIS) return RG_ERR_INVALID_ARG;
+    if (!opts_ok(opts, &o) || !o.fits(n_tris)) return RG_ERR_INVALID_ARG;
+    if (o.builder != RG_BUILDER_LBVH) return RG_ERR_UNSUPPORTED;  // the others step their rounds from the host
+    const int32_t w = o.w, l = o.leaf;
+    uint64_t no, to, mo, so, po, lvo;
+    const uint64_t need = blas_out_bytes(n_tris, w, &no, &to, &mo, &so, &po, &lvo);
+    if (out_bytes < need || scratch_bytes < blas_scratch_bytes(n_tris, o.builder)) return RG_ERR_OUT_OF_MEMORY;
+    hipStream_t st = (hipStream_t)stream;
+    BlasTicket *T = new (ticket) BlasTicket();
+    T->st = st;
+    RG_HIP(hipEventCreateWithFlags(&T->done, hipEventDisableTiming));  // before anything is enqueued
+    RgArena arena{(char *)scratch, scratch_bytes, 0};
+    float *pbox = arena.take<float>(6 * n_tris);
+    uint32_t *flags = arena.take<uint32_t>(8);
+    k_fill_u32<<<1, 64, 0, st>>>(flags, 0u, 1);
+    k_tri_boxes<<<rg_blocks(n_tris, kThreads), kThreads, 0, st>>>(verts, n_verts, idx, n_tris, pbox, flags);
+    RG_LAUNCH_CHECK();
+    char *base = (char *)out_buf;
+    T->lo.deferred = T->summary;
+    T->lo.key_shift = o.key_shift();
+    T->lo.coll_async = &T->coll;
+    T->lo.coll_hr = T->hr;
+    rg_status r = rg_lbvh_build(pbox, n_tris, w, l, o.builder, o.radius, base + no, (uint32_t *)(base + po),
+                                (uint32_t *)(base + lvo), arena, st, &T->lo, false, nullptr, nullptr, nullptr,
+                                nullptr);
+    hipError_t e = hipSuccess;
+    if (r == RG_OK) {
+        k_reorder_tris<<<rg_blocks(n_tris, kThreads), kThreads, 0, st>>>(
+            verts, n_verts, idx, T->lo.ids, n_tris, prim_material, (RgTri *)(base + to), (uint16_t *)(base + mo),
+            (uint32_t *)(base + so));
+        k_blas_header<<<1, 1, 0, st>>>((RgBlasHdr *)base, (uint64_t)(base + no), (uint64_t)(base + to),
+                                       (uint64_t)(base + mo), (uint64_t)(base + so), T->lo.root_dev);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(T->summary + 10, flags, 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipEventRecord(T->done, st);
+    }
+    if (r != RG_OK || e != hipSuccess) {
+        (void)hipStreamSynchronize(st);  // copies into the ticket may be in flight
+        (void)hipEventDestroy(T->done);
+        T->magic = 0;
+        if (r != RG_OK) return r;
+        RG_HIP(e);
+    }
+    rg_blas &d = T->desc;
+    d = rg_blas{};
+    d.buf = out_buf;
+    d.nodes_off = no;
+    d.tris_off = to;
+    d.mats_off = mo;
+    d.slots_off = so;
+    d.parents_off = po;
+    d.levels_off = lvo;
+    d.n_tris = n_tris;
+    d.width = w;
+    d.leaf_max = l;
+    d.has_mats = prim_material ? 1 : 0;
+    T->magic = kTicketMagic;
+    return RG_OK;
+}
+
+rg_status rg_build_blas_finish(void *ticket, rg_blas *out) {
+    if (!ticket || !out || ((uintptr_t)ticket & 15u)) return RG_ERR_INVALID_ARG;
+    BlasTicket *T = static_cast<BlasTicket *>(ticket);
+    if (T->magic != kTicketMagic) return RG_ERR_INVALID_ARG;
+    T->magic = 0;  // a ticket completes once
+    const hipError_t we = hipEventSynchronize(T->done);
+    (void)hipEventDestroy(T->done);
+    RG_HIP(we);
+    rg_status r = RG_OK;
+    if (T->lo.pending) {  // one-workgroup build: everything is in the summary
+        r = rg_lbvh_finish(&T->lo, true);
+    } else {
+        r = rg_lbvh_finish(&T->lo, true);  // the root box
+        if (r == RG_OK && T->coll.depth == 0) {
+            r = collapse_absorb(T->coll, T->hr);
+            if (r == RG_OK && T->coll.depth == 0) {  // deeper than the first batch: the rest, waiting here
+                if ((r = collapse_launch(T->coll, T->st)) == RG_OK) r = collapse_finish(T->coll, T->st, T->hr);
+            }
+        }
+        T->lo.depth = T->coll.depth;
+        T->lo.n_nodes = (int64_t)T->coll.n_nodes;
+    }
+    if (r != RG_OK) return r;
+    if (T->summary[10]) return RG_ERR_INVALID_ARG;
+    rg_blas d = T->desc;
+    d.n_nodes = T->lo.n_nodes;
+    d.depth = T->lo.depth;
+    for (int k = 0; k < 3; ++k) {
+        d.lo[k] = T->lo.lo[k];
+        d.hi[k] = T->lo.hi[k];
+    }
+    *out = d;
     return RG_OK;
 }
 

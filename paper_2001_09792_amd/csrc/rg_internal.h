@@ -160,6 +160,12 @@ struct RgLbvhOut {
     // Set by the caller: 0 for 63-bit Morton keys, 33 for their top 30 bits
     // (ten per axis; four sort passes).
     int32_t key_shift = 0;
+    // Set by an asynchronous caller (nullable): the multi-launch collapse
+    // then launches its first batch of levels, records its state in
+    // *coll_async and copies the level counts to coll_hr (pinned host) with
+    // no wait; the caller completes it after the stream gets there.
+    void *coll_async = nullptr;
+    uint32_t *coll_hr = nullptr;
     // Set by the top-level build (nullable): a one-workgroup linear build of
     // up to 1,024 instances then also computes the instances' boxes and
     // records from the uploaded tables and writes the records in leaf order.

@@ -265,3 +265,25 @@ def test_morton_bits_option():
         o = rg.BuildOpts(4, 4, 0, 0, bits)
         assert lib.rg_blas_sizes(n, ctypes.byref(o), ctypes.byref(s)) == -1, (bits, n)
         assert lib.rg_tlas_sizes(n, ctypes.byref(o), ctypes.byref(s)) == -1, (bits, n)
+
+
+def test_async_build_arguments_are_checked_on_the_host():
+    """rg_build_blas_async / rg_build_blas_finish reject what the host can
+    see before enqueueing anything: a missing or misaligned ticket, a builder
+    other than the linear one, a ticket holding no pending build."""
+    import paper_2001_09792_amd as rg
+    lib = rg._lib
+    raw = ctypes.create_string_buffer(rg.BUILD_TICKET_BYTES + 32)
+    t = (ctypes.addressof(raw) + 15) & ~15
+    d = rg.BlasDesc()
+    assert lib.rg_build_blas_finish(t, ctypes.byref(d)) == -1          # nothing pending
+    assert lib.rg_build_blas_finish(None, ctypes.byref(d)) == -1
+    assert lib.rg_build_blas_finish(t + 4, ctypes.byref(d)) == -1      # misaligned
+    fake = 1 << 20  # never dereferenced: every call below fails its host checks
+    nb, ns = rg.blas_sizes(1000)
+    args = lambda o, ticket: (fake, 3000, fake, 1000, None, ctypes.byref(o), fake, nb, fake, ns, None, ticket)  # noqa: E731
+    assert lib.rg_build_blas_async(*args(rg.BuildOpts(4, 4, 0, 0), None)) == -1
+    assert lib.rg_build_blas_async(*args(rg.BuildOpts(4, 4, 0, 0), t + 8)) == -1
+    assert lib.rg_build_blas_async(*args(rg.BuildOpts(4, 4, 1, 0), t)) == -4   # clustering: unsupported
+    assert lib.rg_build_blas_async(*args(rg.BuildOpts(4, 4, 2, 0), t)) == -4   # treelets: unsupported
+    assert lib.rg_build_blas_async(*args(rg.BuildOpts(3, 4, 0, 0), t)) == -1

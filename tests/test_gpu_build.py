@@ -329,3 +329,115 @@ def test_treelet_blas_and_tlas_invariants(width, leaf_max):
     bvh_check.check_tlas(tl.buf.cpu().numpy(), tl.desc, [b.desc for b in tl.blas], sc.xform)
     for bb in tl.blas:
         bvh_check.check_blas(bb.buf.cpu().numpy(), bb.desc)
+
+
+def _comb(n_tris, seed):
+    """A mesh whose linear hierarchy is deep: 40 triangles at x = 2^-k (one
+    Morton level each) and the rest inside [0, 2^-40] (equal keys, split by
+    index), so a binary tree of about 34 levels."""
+    rng = np.random.default_rng(seed)
+    c = np.zeros((n_tris, 1, 3))
+    c[:40, 0, 0] = 2.0 ** -np.arange(40)
+    c[40:, 0, 0] = rng.uniform(0, 2.0 ** -40, n_tris - 40)
+    c[:, 0, 1] = 0.5
+    shape = np.array([[0, 0, 0], [1e-3, 0, 0], [0, 1e-3, 0]])  # one shape: the centres differ in x only
+    return sg.triangles_mesh(c + shape)
+
+
+def _canonical(b):
+    """A bottom level in a form that does not depend on how nodes of one
+    level are numbered (the level queues fill in the order waves claim their
+    slots): the nodes in depth-first order from the root, children in slot
+    order, each as its boxes and its leaf links (inner children marked), plus
+    the parts written in a fixed order (triangles, materials and slots in
+    leaf order, the level table)."""
+    d, buf = b.desc, b.buf.cpu().numpy()
+    W = d.width
+    words = buf[d.nodes_off: d.nodes_off + d.n_nodes * 32 * W].view(np.uint32).reshape(d.n_nodes, 8 * W)
+    nodes, stack = [], [0]
+    while stack:
+        w = words[stack.pop()]
+        rec, kids = [w[:6 * W].tobytes()], []
+        for c in w[6 * W:7 * W].tolist():
+            inner = c != 0xFFFFFFFF and not (c & 0x80000000)
+            rec.append(b"I" if inner else int(c).to_bytes(4, "little"))
+            if inner:
+                kids.append(c)
+        nodes.append(b"".join(rec))
+        stack.extend(reversed(kids))
+    parts = [buf[d.tris_off: d.tris_off + 40 * d.n_tris], buf[d.mats_off: d.mats_off + 2 * d.n_tris],
+             buf[d.slots_off: d.slots_off + 4 * d.n_tris]]
+    if d.depth <= 64:
+        parts.append(buf[d.levels_off: d.levels_off + 4 * (d.depth + 1)])
+    return nodes, parts
+
+
+def _same_blas(a, b):
+    for f in ("n_tris", "n_nodes", "width", "leaf_max", "depth", "has_mats"):
+        assert getattr(a.desc, f) == getattr(b.desc, f), f
+    assert list(a.desc.lo) == list(b.desc.lo) and list(a.desc.hi) == list(b.desc.hi)
+    na, pa = _canonical(a)
+    nb, pb = _canonical(b)
+    assert len(na) == a.desc.n_nodes and na == nb, "hierarchies differ"
+    for x, y in zip(pa, pb):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("name,width", [("soup1024", 4), ("soup4096", 8), ("soup5000", 4), ("soup5000", 2),
+                                        ("soup700001", 4), ("comb", 2), ("comb", 4)])
+def test_async_build_equals_sync(name, width):
+    """rg_build_blas_async + rg_build_blas_finish give the synchronous build's
+    structure byte for byte: one-workgroup builds, the multi-launch build,
+    and a hierarchy deeper than the levels the asynchronous call launches
+    (the comb: finish launches the rest)."""
+    import paper_2001_09792_amd as rg
+    mesh = {"soup700001": lambda: sg.random_soup(700001, 27), "comb": lambda: _comb(5000, 71)}.get(
+        name, MESHES.get(name))()
+    print(f"[async build] {name} W={width}: {mesh.n_tris} tris", flush=True)
+    v, i = _dev(mesh)
+    ref = rg.build_blas(v, i, None, width, 1)
+    p = rg.build_blas_async(v, i, None, width, 1)
+    got = p.finish()
+    _same_blas(got, ref)
+    bvh_check.check_blas(got.buf.cpu().numpy(), got.desc)
+    if name == "comb":
+        assert ref.desc.depth > (21 if width == 2 else 12), ref.desc.depth  # deeper than the first batch
+
+
+def test_async_builds_in_flight_together():
+    """Four builds on four streams, each with its own scratch, finished after
+    all were enqueued: each equals its synchronous build; the ticket of a
+    finished build is rejected."""
+    import torch
+    import paper_2001_09792_amd as rg
+    meshes = [sg.random_soup(60000 + 1000 * k, 80 + k) for k in range(4)]
+    devs = [_dev(m) for m in meshes]
+    refs = [rg.build_blas(v, i, None, 4, 1) for v, i in devs]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    pend = [rg.build_blas_async(v, i, None, 4, 1, stream=s) for (v, i), s in zip(devs, streams)]
+    got = [p.finish() for p in pend]
+    for g, r in zip(got, refs):
+        _same_blas(g, r)
+    with pytest.raises(rg.RgError):
+        pend[0].finish()
+
+
+def test_async_build_reports_bad_input():
+    import torch
+    import paper_2001_09792_amd as rg
+    mesh = sg.random_soup(6000, 91)
+    v, i = _dev(mesh)
+    i2 = i.clone()
+    i2[77, 1] = 10 ** 7
+    with pytest.raises(rg.RgError) as e:
+        rg.build_blas_async(v, i2, None, 4, 1).finish()
+    assert e.value.status == -1
+    v2 = v.clone()
+    v2[5, 0] = float("nan")
+    with pytest.raises(rg.RgError) as e:
+        rg.build_blas_async(v2, i, None, 4, 1).finish()
+    assert e.value.status == -1
+    # the stream and the library are fine afterwards
+    _same_blas(rg.build_blas_async(v, i, None, 4, 1).finish(), rg.build_blas(v, i, None, 4, 1))
+    del torch
