@@ -12,7 +12,9 @@
  *   bottom level from vertex data            rg_build_blas   (+ rg_blas_sizes;
  *                                            enqueued: rg_build_blas_async /
  *                                            rg_build_blas_finish)
- *   top level from instances and matrices    rg_build_tlas   (+ rg_tlas_sizes)
+ *   top level from instances and matrices    rg_build_tlas   (+ rg_tlas_sizes;
+ *                                            enqueued: rg_build_tlas_async /
+ *                                            rg_build_tlas_finish)
  *   ray generation                           rg_camera_rays, rg_ao_rays
  *   closest hit / miss per ray               rg_trace_closest
  *   any hit per ray                          rg_trace_any
@@ -371,6 +373,30 @@ rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xfo
                            const uint32_t *inst_flags /*host, nullable*/, int64_t n_inst,
                            const rg_build_opts *opts, void *out_buf, uint64_t out_bytes,
                            void *scratch, uint64_t scratch_bytes, void *stream, rg_tlas *out /*host*/);
+
+/* rg_build_tlas_ex without the wait (section 1's second step, enqueued), for
+ * the linear builder (others: RG_ERR_UNSUPPORTED): everything the host
+ * checks (as rg_build_tlas_ex) is checked and returned at once; the host
+ * tables go to the device through the ticket, the build is enqueued on
+ * `stream`, and rg_build_tlas_finish fills the descriptor.  ticket:
+ * rg_tlas_ticket_bytes of pinned host memory (hipHostMalloc or a pinned
+ * tensor), 256-byte aligned, owned by the caller; the bottom levels,
+ * out_buf, scratch and the ticket must stay untouched until
+ * rg_build_tlas_finish returns (the host arrays may be released when this
+ * call returns). */
+rg_status rg_tlas_ticket_bytes(int64_t n_inst, int32_t n_blas, int32_t with_flags, uint64_t *bytes /*host*/);
+rg_status rg_build_tlas_async(const rg_blas *blas, int32_t n_blas, const float *xform,
+                              const uint32_t *blas_id, const uint32_t *inst_material,
+                              const uint32_t *inst_flags, int64_t n_inst, const rg_build_opts *opts,
+                              void *out_buf, uint64_t out_bytes, void *scratch, uint64_t scratch_bytes,
+                              void *stream, void *ticket /*pinned host*/, uint64_t ticket_bytes);
+
+/* Completes an rg_build_tlas_async: waits until its stream has finished that
+ * build, fills *out and returns its error (RG_ERR_INVALID_ARG for a bottom
+ * level whose last refit found invalid input, or for a ticket that holds no
+ * pending build: each completes once); a hierarchy deeper than the levels
+ * the asynchronous call launched gets the rest here, with a wait. */
+rg_status rg_build_tlas_finish(void *ticket /*pinned host*/, rg_tlas *out /*host*/);
 
 /* ---------------------------------------------------------- tracing */
 /* Closest hit for n rays (section 1: the closest-hit / miss outcome of each

@@ -136,6 +136,10 @@ SIGNATURES = {
     "rg_build_blas": (c_i32, [c_p, c_i64, c_p, c_i64, c_p, c_p, c_p, c_u64, c_p, c_u64, c_p, c_p]),
     "rg_build_blas_async": (c_i32, [c_p, c_i64, c_p, c_i64, c_p, c_p, c_p, c_u64, c_p, c_u64, c_p, c_p]),
     "rg_build_blas_finish": (c_i32, [c_p, c_p]),
+    "rg_tlas_ticket_bytes": (c_i32, [c_i64, c_i32, c_i32, c_p]),
+    "rg_build_tlas_async": (c_i32, [c_p, c_i32, c_p, c_p, c_p, c_p, c_i64, c_p, c_p, c_u64, c_p, c_u64, c_p, c_p,
+                                    c_u64]),
+    "rg_build_tlas_finish": (c_i32, [c_p, c_p]),
     "rg_tlas_sizes": (c_i32, [c_i64, c_p, c_p]),
     "rg_build_tlas": (c_i32, [c_p, c_i32, c_p, c_p, c_p, c_i64, c_p, c_p, c_u64, c_p, c_u64, c_p, c_p]),
     "rg_trace_closest": (c_i32, [c_p, Rays, c_i64, Hits, c_p]),
@@ -423,6 +427,53 @@ def build_tlas(blas: Sequence[Blas], xform, blas_id, inst_mat, width: int = 4, s
         ctypes.byref(d)))
     del torch
     return Tlas(buf, d, blas)
+
+
+class PendingTlas:
+    """A top-level build enqueued by build_tlas_async; finish() returns it."""
+
+    def __init__(self, buf, blas, keep, ticket):
+        self.buf = buf
+        self.blas = list(blas)
+        self._keep = keep
+        self.ticket = ticket
+
+    def finish(self) -> Tlas:
+        d = TlasDesc()
+        _check("rg_build_tlas_finish", _lib.rg_build_tlas_finish(self.ticket.data_ptr(), ctypes.byref(d)))
+        self._keep = None
+        return Tlas(self.buf, d, self.blas)
+
+
+def build_tlas_async(blas: Sequence[Blas], xform, blas_id, inst_mat, width: int = 4, stream=None,
+                     scratch=None, inst_flags=None, morton_bits: int = 0) -> PendingTlas:
+    """build_tlas for the linear builder without the wait: the host tables go
+    through a pinned ticket, the build is enqueued on `stream`, finish()
+    waits for it."""
+    torch = _torch()
+    xform = np.ascontiguousarray(xform, np.float32).reshape(-1, 12)
+    blas_id = np.ascontiguousarray(blas_id, np.uint32)
+    inst_mat = np.ascontiguousarray(inst_mat, np.uint32)
+    n = xform.shape[0]
+    s = Sizes()
+    o = _opts(width, 1, "lbvh", 0, morton_bits)
+    _check("rg_tlas_sizes", _lib.rg_tlas_sizes(n, ctypes.byref(o), ctypes.byref(s)))
+    dev = blas[0].buf.device
+    buf = _bytes(s.bytes, dev)
+    if scratch is None or scratch.numel() < s.scratch_bytes:
+        scratch = _bytes(s.scratch_bytes, dev)
+    fl = np.ascontiguousarray(inst_flags, np.uint32).reshape(n) if inst_flags is not None else None
+    tb = ctypes.c_uint64()
+    _check("rg_tlas_ticket_bytes", _lib.rg_tlas_ticket_bytes(n, len(blas), int(fl is not None), ctypes.byref(tb)))
+    raw = torch.empty(tb.value + 256, dtype=torch.uint8, pin_memory=True)
+    off = (-raw.data_ptr()) % 256
+    ticket = raw[off: off + tb.value]
+    arr = (BlasDesc * len(blas))(*[b.desc for b in blas])
+    _check("rg_build_tlas_async", _lib.rg_build_tlas_async(
+        arr, len(blas), xform.ctypes.data, blas_id.ctypes.data, inst_mat.ctypes.data,
+        fl.ctypes.data if fl is not None else None, n, ctypes.byref(o), _ptr(buf), buf.numel(), _ptr(scratch),
+        scratch.numel(), _stream(stream), ticket.data_ptr(), tb.value))
+    return PendingTlas(buf, blas, (scratch, raw), ticket)
 
 
 class TlasBuilder:

@@ -3274,14 +3274,61 @@ rg_status rg_tlas_sizes(int64_t n_inst, const rg_build_opts *opts, rg_sizes *out
     return RG_OK;
 }
 
-rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xform, const uint32_t *blas_id,
-                           const uint32_t *inst_material, const uint32_t *inst_flags, int64_t n_inst,
-                           const rg_build_opts *opts, void *out_buf, uint64_t out_bytes, void *scratch,
-                           uint64_t scratch_bytes, void *stream, rg_tlas *out) {
+}  // extern "C"
+
+namespace {
+
+// Host tables of a top-level build, copied to the device in one piece
+// (byte offsets, 8-aligned): matrices, blas ids, materials, flags,
+// bottom-level addresses, a zero word (the invalid-bottom-level flag); the
+// build's summary comes back behind them (stage = the whole staging area).
+struct TlasLayout {
+    size_t off_bid, off_mat, off_fl, off_info, off_flag, t_bytes, stage;
+};
+TlasLayout tlas_layout(int64_t n_inst, int32_t n_blas, bool with_flags) {
+    const size_t n8 = (size_t)n_inst, t4 = (4 * n8 + 7) & ~size_t(7);
+    TlasLayout L;
+    L.off_bid = 48 * n8;
+    L.off_mat = L.off_bid + t4;
+    L.off_fl = L.off_mat + t4;
+    L.off_info = L.off_fl + (with_flags ? t4 : 0);
+    L.off_flag = L.off_info + sizeof(BlasInfo) * (size_t)n_blas;
+    L.t_bytes = L.off_flag + 8;
+    L.stage = L.t_bytes + 64;
+    return L;
+}
+
+// A top-level build between enqueue and completion (the caller's pinned
+// ticket for rg_build_tlas_async, a local for the synchronous call).
+struct TlasTicket {
+    uint64_t magic = 0;
+    hipStream_t st = nullptr;
+    hipEvent_t done = nullptr;   // nullptr: complete by waiting for the stream
+    uint32_t *summary = nullptr;  // in the staging area: a one-workgroup summary, or the flag word
+    bool deferred = false;
+    RgLbvhOut lo;
+    CollapseState coll;
+    uint32_t hr[kRingWords];
+    rg_tlas desc;
+};
+constexpr size_t kTlasTicketHead = (sizeof(TlasTicket) + 255) & ~size_t(255);
+constexpr uint64_t kTlasTicketMagic = 0x7267544c41534174ull;
+
+// Validates and enqueues a top-level build; T holds what completing it
+// needs.  stage: host staging of tlas_stage_bytes (pinned for an
+// asynchronous build), reused only after completion; async: the collapse
+// goes no further than its first batch and nothing waits (the clustering and
+// treelet builders, which step their rounds from the host, are refused).
+rg_status tlas_enqueue(const rg_blas *blas, int32_t n_blas, const float *xform, const uint32_t *blas_id,
+                       const uint32_t *inst_material, const uint32_t *inst_flags, int64_t n_inst,
+                       const rg_build_opts *opts, void *out_buf, uint64_t out_bytes, void *scratch,
+                       uint64_t scratch_bytes, hipStream_t st, char *stage, uint64_t stage_bytes, bool async,
+                       TlasTicket *Tk) {
     Opts o;
-    if (!blas || !xform || !blas_id || !inst_material || !out_buf || !scratch || !out) return RG_ERR_INVALID_ARG;
+    if (!blas || !xform || !blas_id || !inst_material || !out_buf || !scratch) return RG_ERR_INVALID_ARG;
     if (n_blas < 1 || n_blas > 4096 || n_inst < 1 || n_inst > RG_MAX_TRIS) return RG_ERR_INVALID_ARG;
     if (!opts_ok(opts, &o) || !o.fits(n_inst)) return RG_ERR_INVALID_ARG;
+    if (async && o.builder != RG_BUILDER_LBVH) return RG_ERR_UNSUPPORTED;
     const int32_t w = o.w;
     int32_t max_depth = 0;
     std::vector<BlasInfo> info((size_t)n_blas);
@@ -3309,7 +3356,8 @@ rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xfo
     uint64_t need = tlas_out_bytes(n_inst, w, &no, &io, &ro, &xo);
     if (out_bytes < need || scratch_bytes < tlas_scratch_bytes(n_inst, n_blas, o.builder))
         return RG_ERR_OUT_OF_MEMORY;
-    hipStream_t st = (hipStream_t)stream;
+    const TlasLayout L = tlas_layout(n_inst, n_blas, inst_flags != nullptr);
+    if (stage && stage_bytes < L.stage) return RG_ERR_OUT_OF_MEMORY;
     RgArena arena{(char *)scratch, scratch_bytes, 0};
     float *d_xf = (float *)((char *)out_buf + xo);  // kept: the trace calls recompute hits from it
     // everything from the host goes over in one copy, in this layout (byte
@@ -3317,20 +3365,12 @@ rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xfo
     // addresses, a zero word (the invalid-bottom-level flag); the summary of
     // the build comes back behind it
     const size_t n8 = (size_t)n_inst;
-    const size_t off_bid = 48 * n8, off_mat = off_bid + ((4 * n8 + 7) & ~size_t(7));
-    const size_t off_fl = off_mat + ((4 * n8 + 7) & ~size_t(7));
-    const size_t off_info = off_fl + (inst_flags ? ((4 * n8 + 7) & ~size_t(7)) : 0);
-    const size_t off_flag = off_info + sizeof(BlasInfo) * (size_t)n_blas;
-    const size_t t_bytes = off_flag + 8;
+    const size_t off_bid = L.off_bid, off_mat = L.off_mat, off_fl = L.off_fl, off_info = L.off_info;
+    const size_t off_flag = L.off_flag, t_bytes = L.t_bytes;
     char *d_tab = arena.take<char>(t_bytes);
     float *d_box = arena.take<float>(6 * n_inst);
     RgInst *d_rec = arena.take<RgInst>(n_inst);
-    std::vector<char> fallback;
-    char *tab = pinned_staging(t_bytes + 64);
-    if (!tab) {
-        fallback.resize(t_bytes + 64);
-        tab = fallback.data();
-    }
+    char *tab = stage;
     memcpy(tab, xform, 48 * n8);
     memcpy(tab + off_bid, blas_id, 4 * n8);
     memcpy(tab + off_mat, inst_material, 4 * n8);
@@ -3339,6 +3379,7 @@ rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xfo
     memset(tab + off_flag, 0, 8);
     uint32_t *summary = (uint32_t *)(tab + t_bytes);  // a one-workgroup build's summary, or the flag word
     uint32_t *d_flag = (uint32_t *)(d_tab + off_flag);
+    if (async) RG_HIP(hipEventCreateWithFlags(&Tk->done, hipEventDisableTiming));  // before anything is enqueued
     RG_HIP(hipMemcpyAsync(d_tab, tab, t_bytes, hipMemcpyHostToDevice, st));
     InstTables T;
     T.xform = (const float *)d_tab;
@@ -3357,13 +3398,20 @@ rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xfo
         k_inst_setup<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(T, n_inst, d_box, d_rec);
         RG_LAUNCH_CHECK();
     }
-    RgLbvhOut lo;
+    Tk->st = st;
+    Tk->summary = summary;
+    RgLbvhOut &lo = Tk->lo;
     lo.deferred = summary;
     lo.flag_in = d_flag;
     lo.key_shift = o.key_shift();
     lo.tlas_fuse = fused ? &F : nullptr;
+    if (async) {
+        lo.coll_async = &Tk->coll;
+        lo.coll_hr = Tk->hr;
+    }
     rg_status r = rg_lbvh_build(d_box, n_inst, w, 1, o.builder, o.radius, base + no, nullptr, nullptr, arena, st, &lo,
                                 false, nullptr, nullptr, nullptr, nullptr);
+    lo.tlas_fuse = nullptr;  // it pointed at this frame
     if (r != RG_OK) {
         (void)hipStreamSynchronize(st);  // the staging buffer may still be in use by a copy
         return r;
@@ -3372,37 +3420,120 @@ rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xfo
         k_reorder_inst<<<rg_blocks(n_inst, kThreads), kThreads, 0, st>>>(d_rec, lo.ids, n_inst,
                                                                           (RgInst *)(base + io),
                                                                           (uint32_t *)(base + ro));
-    const bool deferred = lo.pending;  // else the flag word comes back on its own
-    const hipError_t le = hipGetLastError();
-    const hipError_t ce = (le == hipSuccess && !deferred)
-                              ? hipMemcpyAsync(summary, d_flag, 4, hipMemcpyDeviceToHost, st)
-                              : le;
-    RG_HIP(hipStreamSynchronize(st));  // the one wait of the call (also before any error return: the
-                                       // summary copy targets this frame)
-    RG_HIP(ce);
-    if ((r = rg_lbvh_finish(&lo, true)) != RG_OK) return r;
-    if (deferred ? lo.flag : summary[0]) return RG_ERR_INVALID_ARG;  // a bottom level was refitted to invalid vertex data
-    out->buf = out_buf;
-    out->nodes_off = no;
-    out->inst_off = io;
-    out->rec_off = ro;
-    out->xf_off = xo;
-    out->n_inst = n_inst;
-    out->n_nodes = lo.n_nodes;
-    out->width = w;
-    out->depth = lo.depth;
-    out->max_blas_depth = max_depth;
-    out->has_inst_flags = 0;
+    Tk->deferred = lo.pending;  // else the flag word comes back on its own
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess && !Tk->deferred) e = hipMemcpyAsync(summary, d_flag, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && async) e = hipEventRecord(Tk->done, st);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(st);
+        RG_HIP(e);
+    }
+    rg_tlas &d = Tk->desc;
+    d = rg_tlas{};
+    d.buf = out_buf;
+    d.nodes_off = no;
+    d.inst_off = io;
+    d.rec_off = ro;
+    d.xf_off = xo;
+    d.n_inst = n_inst;
+    d.width = w;
+    d.max_blas_depth = max_depth;
     for (int32_t b = 0; b < n_blas; ++b)
-        if (blas[b].has_alpha) out->has_inst_flags = 1;
+        if (blas[b].has_alpha) d.has_inst_flags = 1;
     if (inst_flags)
         for (int64_t i = 0; i < n_inst; ++i)
-            if (inst_flags[i] != RG_INST_MASK_ALL) out->has_inst_flags = 1;
-    for (int k = 0; k < 3; ++k) {
-        out->lo[k] = lo.lo[k];
-        out->hi[k] = lo.hi[k];
-    }
+            if (inst_flags[i] != RG_INST_MASK_ALL) d.has_inst_flags = 1;
     return RG_OK;
+}
+
+// Completes an enqueued top-level build: waits (for its event, else its
+// stream), finishes a collapse left after its first batch, fills *out.
+rg_status tlas_complete(TlasTicket *Tk, rg_tlas *out) {
+    if (Tk->done) {
+        const hipError_t we = hipEventSynchronize(Tk->done);
+        (void)hipEventDestroy(Tk->done);
+        Tk->done = nullptr;
+        RG_HIP(we);
+    } else {
+        RG_HIP(hipStreamSynchronize(Tk->st));
+    }
+    RgLbvhOut &lo = Tk->lo;
+    rg_status r = rg_lbvh_finish(&lo, true);
+    if (r == RG_OK && !Tk->deferred && lo.coll_async) {
+        if (Tk->coll.depth == 0) {
+            r = collapse_absorb(Tk->coll, Tk->hr);
+            if (r == RG_OK && Tk->coll.depth == 0 && (r = collapse_launch(Tk->coll, Tk->st)) == RG_OK)
+                r = collapse_finish(Tk->coll, Tk->st, Tk->hr);
+        }
+        lo.depth = Tk->coll.depth;
+        lo.n_nodes = (int64_t)Tk->coll.n_nodes;
+    }
+    if (r != RG_OK) return r;
+    if (Tk->deferred ? lo.flag : Tk->summary[0]) return RG_ERR_INVALID_ARG;  // a bottom level was refitted to invalid vertex data
+    rg_tlas d = Tk->desc;
+    d.n_nodes = lo.n_nodes;
+    d.depth = lo.depth;
+    for (int k = 0; k < 3; ++k) {
+        d.lo[k] = lo.lo[k];
+        d.hi[k] = lo.hi[k];
+    }
+    *out = d;
+    return RG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xform, const uint32_t *blas_id,
+                           const uint32_t *inst_material, const uint32_t *inst_flags, int64_t n_inst,
+                           const rg_build_opts *opts, void *out_buf, uint64_t out_bytes, void *scratch,
+                           uint64_t scratch_bytes, void *stream, rg_tlas *out) {
+    if (!out || n_inst < 1 || n_inst > RG_MAX_TRIS || n_blas < 1 || n_blas > 4096) return RG_ERR_INVALID_ARG;
+    const TlasLayout L = tlas_layout(n_inst, n_blas, inst_flags != nullptr);
+    std::vector<char> fallback;
+    char *tab = pinned_staging(L.stage);
+    if (!tab) {
+        fallback.resize(L.stage);
+        tab = fallback.data();
+    }
+    TlasTicket T;
+    rg_status r = tlas_enqueue(blas, n_blas, xform, blas_id, inst_material, inst_flags, n_inst, opts, out_buf,
+                               out_bytes, scratch, scratch_bytes, (hipStream_t)stream, tab, L.stage, false, &T);
+    if (r != RG_OK) return r;
+    return tlas_complete(&T, out);
+}
+
+rg_status rg_tlas_ticket_bytes(int64_t n_inst, int32_t n_blas, int32_t with_flags, uint64_t *bytes) {
+    if (!bytes || n_inst < 1 || n_inst > RG_MAX_TRIS || n_blas < 1 || n_blas > 4096) return RG_ERR_INVALID_ARG;
+    *bytes = kTlasTicketHead + tlas_layout(n_inst, n_blas, with_flags != 0).stage;
+    return RG_OK;
+}
+
+rg_status rg_build_tlas_async(const rg_blas *blas, int32_t n_blas, const float *xform, const uint32_t *blas_id,
+                              const uint32_t *inst_material, const uint32_t *inst_flags, int64_t n_inst,
+                              const rg_build_opts *opts, void *out_buf, uint64_t out_bytes, void *scratch,
+                              uint64_t scratch_bytes, void *stream, void *ticket, uint64_t ticket_bytes) {
+    if (!ticket || ((uintptr_t)ticket & 255u) || ticket_bytes < kTlasTicketHead) return RG_ERR_INVALID_ARG;
+    TlasTicket *T = new (ticket) TlasTicket();
+    rg_status r = tlas_enqueue(blas, n_blas, xform, blas_id, inst_material, inst_flags, n_inst, opts, out_buf,
+                               out_bytes, scratch, scratch_bytes, (hipStream_t)stream,
+                               (char *)ticket + kTlasTicketHead, ticket_bytes - kTlasTicketHead, true, T);
+    if (r != RG_OK) {
+        if (T->done) (void)hipEventDestroy(T->done);
+        T->magic = 0;
+        return r;
+    }
+    T->magic = kTlasTicketMagic;
+    return RG_OK;
+}
+
+rg_status rg_build_tlas_finish(void *ticket, rg_tlas *out) {
+    if (!ticket || !out || ((uintptr_t)ticket & 255u)) return RG_ERR_INVALID_ARG;
+    TlasTicket *T = static_cast<TlasTicket *>(ticket);
+    if (T->magic != kTlasTicketMagic) return RG_ERR_INVALID_ARG;
+    T->magic = 0;  // a ticket completes once
+    return tlas_complete(T, out);
 }
 
 rg_status rg_build_tlas(const rg_blas *blas, int32_t n_blas, const float *xform, const uint32_t *blas_id,

@@ -287,3 +287,27 @@ def test_async_build_arguments_are_checked_on_the_host():
     assert lib.rg_build_blas_async(*args(rg.BuildOpts(4, 4, 1, 0), t)) == -4   # clustering: unsupported
     assert lib.rg_build_blas_async(*args(rg.BuildOpts(4, 4, 2, 0), t)) == -4   # treelets: unsupported
     assert lib.rg_build_blas_async(*args(rg.BuildOpts(3, 4, 0, 0), t)) == -1
+
+
+def test_async_tlas_arguments_are_checked_on_the_host():
+    import paper_2001_09792_amd as rg
+    lib = rg._lib
+    nb = ctypes.c_uint64()
+    assert lib.rg_tlas_ticket_bytes(100, 4, 0, ctypes.byref(nb)) == 0 and nb.value > 100 * 48
+    n1 = ctypes.c_uint64()
+    assert lib.rg_tlas_ticket_bytes(100, 4, 1, ctypes.byref(n1)) == 0 and n1.value > nb.value
+    assert lib.rg_tlas_ticket_bytes(0, 4, 0, ctypes.byref(nb)) == -1
+    raw = ctypes.create_string_buffer(1 << 16)
+    t = (ctypes.addressof(raw) + 255) & ~255
+    d = rg.TlasDesc()
+    assert lib.rg_build_tlas_finish(t, ctypes.byref(d)) == -1        # nothing pending
+    assert lib.rg_build_tlas_finish(t + 16, ctypes.byref(d)) == -1   # misaligned
+    blas = (rg.BlasDesc * 1)()
+    xf = (ctypes.c_float * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
+    ids = (ctypes.c_uint32 * 1)(0)
+    o = rg.BuildOpts(4, 1, 1, 0)  # clustering: unsupported asynchronously
+    fake = 1 << 20
+    assert lib.rg_build_tlas_async(blas, 1, xf, ids, ids, None, 1, ctypes.byref(o), fake, 1 << 20, fake, 1 << 20,
+                                   None, t, 1 << 15) in (-1, -4)
+    assert lib.rg_build_tlas_async(blas, 1, xf, ids, ids, None, 1, None, fake, 1 << 20, fake, 1 << 20, None,
+                                   t + 8, 1 << 15) == -1

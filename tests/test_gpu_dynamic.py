@@ -227,3 +227,50 @@ def test_refit_errors():
     bvh_check.check_blas(b.buf.cpu().numpy(), b.desc)
     rg.build_tlas([b], sg.identity_xform(1), [0], [0])
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n_inst", [64, 1500, 6000])
+def test_async_tlas_equals_sync(n_inst):
+    """rg_build_tlas_async + rg_build_tlas_finish give rg_build_tlas's top
+    level (node count, depth, box, records, record map, matrices, hits) for
+    the fused one-workgroup build, the unfused one and the multi-launch one;
+    an invalid refit of a bottom level is reported by finish; a finished
+    ticket is rejected."""
+    import torch
+    import paper_2001_09792_amd as rg
+    sc = sg.config_two_level(width=64, height=48)
+    tl = rg.upload_scene(sc, 4, 1, builder="lbvh")
+    rng = np.random.default_rng(n_inst + 5)
+    blas_id = rng.integers(0, len(tl.blas), n_inst).astype(np.uint32)
+    mat = rng.integers(0, len(sc.materials), n_inst).astype(np.uint32)
+    xf = sg.animate_instances(np.tile(sc.xform, (n_inst // len(sc.xform) + 1, 1, 1))[:n_inst], 0.3, seed=11)
+    print(f"[async tlas] {n_inst}", flush=True)
+    ref = rg.build_tlas(tl.blas, xf, blas_id, mat, 4)
+    s = torch.cuda.Stream()
+    p = rg.build_tlas_async(tl.blas, xf, blas_id, mat, 4, stream=s)
+    got = p.finish()
+    torch.cuda.synchronize()
+    for f in ("n_inst", "n_nodes", "width", "depth", "max_blas_depth", "has_inst_flags"):
+        assert getattr(got.desc, f) == getattr(ref.desc, f), f
+    assert list(got.desc.lo) == list(ref.desc.lo) and list(got.desc.hi) == list(ref.desc.hi)
+    a, b, d = got.buf.cpu().numpy(), ref.buf.cpu().numpy(), ref.desc
+    for off, size in ((d.inst_off, 112 * n_inst), (d.rec_off, 4 * n_inst), (d.xf_off, 48 * n_inst)):
+        assert np.array_equal(a[off: off + size], b[off: off + size])
+    bvh_check.check_tlas(a, got.desc, [x.desc for x in tl.blas], xf)
+    rays = rg.rays_to_device(sg.random_rays(4000, 41, extent=22.0))
+    h1 = parity.hits_to_numpy(rg.trace_closest(got, rays))
+    h2 = parity.hits_to_numpy(rg.trace_closest(ref, rays))
+    for key in h1:
+        assert np.array_equal(h1[key].view(np.uint32), h2[key].view(np.uint32)), key
+    with pytest.raises(rg.RgError):
+        p.finish()
+    v, i = _dev(sc.blas[0].verts, sc.blas[0].idx)
+    bad = v.clone()
+    bad[0, 0] = float("nan")
+    rg.refit_blas(tl.blas[0], bad, i)
+    with pytest.raises(rg.RgError) as e:
+        rg.build_tlas_async(tl.blas, xf, blas_id, mat, 4).finish()
+    assert e.value.status == -1
+    rg.refit_blas(tl.blas[0], v, i)
+    rg.build_tlas_async(tl.blas, xf, blas_id, mat, 4).finish()
+    torch.cuda.synchronize()
