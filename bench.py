@@ -640,6 +640,24 @@ def bench_build(args, torch, rg, sg):
             b = rg.build_blas(v, i, None, args.width, args.leaf, builder=builder, morton_bits=bits)
             sah.append(sah_cost(b.buf.cpu().numpy(), b.desc.nodes_off, b.desc.n_nodes, args.width))
         res[name] = {"ms_per_scene": ms, "mtris_s": n_tris / (ms * 1e-3) / 1e6, "sah_cost_mean_4": float(np.mean(sah))}
+    # the 16 tori as one mesh of 10,035,200 triangles, linear builder: the
+    # sort's passes at a size where bandwidth, not launches, bounds them
+    offs = np.cumsum([0] + [m.verts.shape[0] for m in scene.blas])
+    big_v = torch.from_numpy(np.concatenate([m.verts for m in scene.blas])).cuda()
+    big_i = torch.from_numpy(np.concatenate([m.idx + np.uint32(o) for m, o in zip(scene.blas, offs)])
+                             .view(np.int32)).cuda()
+    _, ns_big = rg.blas_sizes(n_tris, args.width, args.leaf)
+    scr_big = torch.empty(ns_big, dtype=torch.uint8, device="cuda")
+    for _ in range(args.warmup):
+        rg.build_blas(big_v, big_i, None, args.width, args.leaf, scratch=scr_big)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rg.build_blas(big_v, big_i, None, args.width, args.leaf, scratch=scr_big)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    res["lbvh_one_mesh_10M"] = {"ms_per_scene": ms, "mtris_s": n_tris / (ms * 1e-3) / 1e6}
+    del scr_big
     # the linear builder enqueued without waits: the 16 builds spread over 4
     # streams (each build with a scratch buffer of its own), then finished
     streams = [torch.cuda.Stream() for _ in range(4)]
