@@ -967,7 +967,8 @@ def main():
     ap.add_argument("--post-radius", type=int, default=8, help="post: roughness blur window radius")
     ap.add_argument("--requests", type=int, default=1000, help="serving: measured requests per rate")
     ap.add_argument("--warm", type=int, default=100, help="serving: warm-up requests per rate")
-    ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: engine memory budget")
+    ap.add_argument("--budget-gb", type=float, default=160.0,
+                    help="serving: engine memory budget (the queue space for frames in flight)")
     ap.add_argument("--max-jobs", type=int, default=128, help="serving: frames in flight")
     ap.add_argument("--rate-factors", type=float, nargs="+", default=[0.25, 0.5, 0.75, 0.9, 1.0, 1.25])
     ap.add_argument("--plain-factors", type=float, nargs="*", default=[0.5, 0.9])
