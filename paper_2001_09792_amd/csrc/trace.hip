@@ -1,6 +1,9 @@
 // trace.hip -- closest-hit / any-hit traversal kernels and their entry points
 // (the per-ray closest hit, any hit and miss outcomes of the paper's
 // section 1).  The traversal itself is in trace_core.h.
+#include <atomic>
+#include <mutex>
+
 #include "trace_core.h"
 
 namespace {
@@ -14,6 +17,7 @@ namespace {
 // flight when its slot is needed again (a straggler) is written out as far as
 // it got; its late rays then store their results directly.
 constexpr int kStageSlots = 4;
+constexpr uint32_t kClaimMin = 16;  // packets per wave from which a launch claims its last quarter
 template <bool ANY, int MODE>
 struct StageShape {
     // words per ray: closest hit (inst, prim); any hit (occluded, inst, prim);
@@ -25,7 +29,7 @@ struct StageShape {
 // LDS bytes per wave of the staging ring
 template <int K>
 constexpr size_t stage_wave_bytes() {
-    return K == 0 ? 0 : (size_t)kStageSlots * (K * 64 * 4 + 16);
+    return (size_t)kStageSlots * (K * 64 * 4 + 16);  // words, then mask, owner and packet per slot
 }
 // Orders one wave's LDS accesses across lanes: a compiler fence at
 // wavefront scope and a wave barrier (the LDS serves a wave's accesses in
@@ -35,11 +39,23 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Persistent traversal: each wave walks its own sequence of 64-ray packets
-// (packets wave, wave + waves, wave + 2 waves, ... so that every wave samples
-// the whole batch), and lanes whose ray has finished take the next rays of
-// that sequence together, once at least `refill` lanes are idle.  Rays of a
-// packet stay neighbours, and no lane idles while its wave has work left.
+// Persistent traversal: each wave walks its own sequence of 64-ray packets,
+// and lanes whose ray has finished take the next rays of that sequence
+// together, once at least `refill` lanes are idle.  Rays of a packet stay
+// neighbours, and no lane idles while work is left.  The sequence: first the
+// wave's share of about three quarters of the packets, interleaved (packets
+// wave, wave + waves, ...: the waves of a workgroup run neighbouring packets
+// at the same time and share their nodes in the caches), then packets
+// claimed one at a time from the launch's counter (a.work), so that waves
+// that drew cheap packets take more and all run out of work together (Aila &
+// Laine 2009).  Each claim is issued one packet ahead, so its latency
+// overlaps traversal; the first is issued at the start.  a.work[0] counts
+// the claims, a.work[1] the waves that have left; the last wave to leave
+// clears both for the next launch that uses them (every wave waits for its
+// memory operations first, so no claim of this launch can land after that).
+// Only long launches claim: in a short one the counter's traffic at the
+// start and at the end costs more than the imbalance it removes, and every
+// packet goes out interleaved.
 template <int W, bool ANY, int MODE, bool OPT>
 __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refill, int lds_depth, int leaf_batch,
                                                          int inst_batch) {
@@ -54,6 +70,12 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
     const uint32_t wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave in the block
     const uint32_t wave = blockIdx.x * (rgt::kThreads / 64) + wib;
     const uint32_t n_waves = gridDim.x * (rgt::kThreads / 64);
+    // long launches (kClaimMin packets per wave or more): interleaved packets
+    // per wave, the packets they cover, the rest claimed; shorter ones take
+    // every packet interleaved and touch no counter
+    const bool claims = n_packets >= kClaimMin * n_waves;
+    const uint32_t n_fixed = claims ? (3u * n_packets) / (4u * n_waves) : ~0u;
+    const uint32_t n_static = claims ? n_fixed * n_waves : n_packets;
     rgt::Tracer<W, ANY, MODE, OPT> tr;
     tr.tlas_nodes = reinterpret_cast<const RgNode<W> *>(a.nodes);
     tr.recs = a.recs;
@@ -65,27 +87,32 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
         tr.call_cull = a.ray_flags & (RG_RAY_CULL_BACK | RG_RAY_CULL_FRONT);
         tr.rmask = a.mask;
     }
-    // this wave's staging ring: words [slot][K][64], owner [slot] (packet
-    // number in the wave's sequence, ~0u: free), mask [slot]
+    // this wave's staging ring: words [slot][K][64], mask [slot], owner
+    // [slot] (packet number q in the wave's sequence, ~0u: free), packet
+    // [slot] (the launch's packet that q stands for)
     char RG_LDS *ring = (char RG_LDS *)&lds_stack[lds_depth * rgt::kThreads] + wib * stage_wave_bytes<K>();
     uint32_t RG_LDS *sw = (uint32_t RG_LDS *)ring;
     uint64_t RG_LDS *smask = (uint64_t RG_LDS *)(ring + kStageSlots * K * 64 * 4);
     uint32_t RG_LDS *sown = (uint32_t RG_LDS *)(ring + kStageSlots * (K * 64 * 4 + 8));
-    if (K > 0) {
-        if (lane < kStageSlots) {
-            sown[lane] = ~0u;
-            smask[lane] = 0ull;
-        }
-        wave_sync();
+    uint32_t RG_LDS *spkt = (uint32_t RG_LDS *)(ring + kStageSlots * (K * 64 * 4 + 12));
+    if (lane < kStageSlots) {
+        sown[lane] = ~0u;
+        smask[lane] = 0ull;
+        spkt[lane] = ~0u;
     }
+    wave_sync();
+    uint32_t ahead = 0u;  // lane 0: the claimed packet for the wave's next claimed packet number
+    if (lane == 0 && n_static < n_packets) ahead = atomicAdd(a.work, 1u);
+    uint32_t q_end = 0u;   // packet numbers below this one have their packet (uniform)
+    bool out_of_work = false;  // a claim came back past the last packet (uniform)
     uint32_t next = 0;   // position in this wave's ray sequence (the same in all lanes)
     uint32_t ray_j = 0;  // position of this lane's ray in the sequence
+    uint32_t ray_i = 0;  // index of this lane's ray in the launch
     bool has = false;
     // A finished ray's result stays in its lane until the next refill round
     // (or the wave's end), where all finished lanes place theirs together.
     bool pend = false;
     uint32_t stalled = 0u;  // rounds since a ray of this wave last finished or was taken
-    auto ray_index = [&](uint32_t j) -> uint32_t { return (wave + (j >> 6) * n_waves) * 64 + (j & 63); };
     auto word = [&](int w) -> uint32_t {
         if (MODE == rgt::kRender && !ANY) {
             // the render's closest hits carry their float32 t to shading
@@ -111,23 +138,23 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
         }
     };
     auto write_result = [&]() {  // the visit counts: stored directly
-        const uint64_t i = ray_index(ray_j);
+        const uint64_t i = ray_i;
         a.counts[3 * i] = tr.h.n_nodes;
         a.counts[3 * i + 1] = tr.h.n_tris;
         a.counts[3 * i + 2] = tr.h.n_inst;
     };
-    // Writes slot s's staged rays (all lanes together; uniform arguments).
-    auto flush_slot = [&](int s, uint32_t q, uint64_t m) {
+    // Writes slot s's staged rays, those of launch packet pkt (all lanes
+    // together; uniform arguments).
+    auto flush_slot = [&](int s, uint32_t pkt, uint64_t m) {
         if ((m >> lane) & 1ull) {
-            const uint32_t i = ray_index(q * 64 + lane);
+            const uint32_t i = pkt * 64 + lane;
 #pragma unroll
             for (int w = 0; w < K; ++w) store(w, i, sw[(s * K + w) * 64 + lane]);
         }
     };
-    // Rays of packet q (its first ray in the sequence at 64 q): 64, fewer
-    // for the batch's last packet.
-    auto full_mask = [&](uint32_t q) -> uint64_t {
-        const uint32_t first = (wave + q * n_waves) * 64;
+    // Rays of launch packet pkt: 64, fewer for the batch's last packet.
+    auto full_mask = [&](uint32_t pkt) -> uint64_t {
+        const uint32_t first = pkt * 64;
         const uint32_t cnt = n - first < 64u ? n - first : 64u;
         return cnt >= 64u ? ~0ull : ((1ull << cnt) - 1ull);
     };
@@ -143,7 +170,7 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
                 __hip_atomic_fetch_or(&smask[s], 1ull << (ray_j & 63), __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_WAVEFRONT);
             } else {
-                const uint32_t i = ray_index(ray_j);  // a straggler's packet left the ring
+                const uint32_t i = ray_i;  // a straggler's packet left the ring
 #pragma unroll
                 for (int w = 0; w < K; ++w) store(w, i, word(w));
             }
@@ -157,8 +184,9 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
             const uint64_t m = smask[k];
             const uint64_t mu = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(m >> 32)) << 32) |
                                 __builtin_amdgcn_readfirstlane((uint32_t)m);
-            if (all || mu == full_mask(o)) {
-                flush_slot(k, o, mu);
+            const uint32_t pkt = __builtin_amdgcn_readfirstlane(spkt[k]);
+            if (all || mu == full_mask(pkt)) {
+                flush_slot(k, pkt, mu);
                 wave_sync();
                 if (lane == 0) {
                     sown[k] = ~0u;
@@ -168,25 +196,42 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
             }
         }
     };
-    // Claims the slots of the packets whose first ray is among the positions
-    // [p0, p0 + cnt) of the sequence (all lanes together).
+    // Gives the packet numbers whose first position is among [p0, p0 + cnt)
+    // of the sequence their launch packets (an interleaved one, else the
+    // claimed one ahead, then the next claim issued) and their slots (all
+    // lanes together).
     auto claim = [&](uint32_t p0, uint32_t cnt) {
         for (uint32_t q = (p0 + 63) >> 6; q * 64 < p0 + cnt; ++q) {
-            if (wave + q * n_waves >= n_packets) break;
+            if (out_of_work) break;
+            uint32_t pkt = q < n_fixed ? wave + q * n_waves : n_static;
+            if (pkt >= n_static) {
+                if (n_static >= n_packets) {
+                    out_of_work = true;
+                    break;
+                }
+                pkt = n_static + __builtin_amdgcn_readfirstlane(ahead);
+                if (pkt >= n_packets) {
+                    out_of_work = true;
+                    break;
+                }
+                if (lane == 0) ahead = atomicAdd(a.work, 1u);
+            }
             const int k = (int)(q & (kStageSlots - 1));
             const uint32_t o = __builtin_amdgcn_readfirstlane(sown[k]);
-            if (o != ~0u) {  // a straggler: write out what it has
+            if (K > 0 && o != ~0u) {  // a straggler: write out what it has
                 const uint64_t m = smask[k];
                 const uint64_t mu = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(m >> 32)) << 32) |
                                     __builtin_amdgcn_readfirstlane((uint32_t)m);
-                flush_slot(k, o, mu);
+                flush_slot(k, __builtin_amdgcn_readfirstlane(spkt[k]), mu);
                 wave_sync();
             }
             if (lane == 0) {
                 sown[k] = (uint32_t)q;
                 smask[k] = 0ull;
+                spkt[k] = pkt;
             }
             wave_sync();
+            q_end = q + 1;
         }
     };
     while (true) {
@@ -196,15 +241,13 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
         const int n_need = __popcll(need);
         bool took = false;
         if (n_need >= refill) {
-            if (K > 0) {
-                place(false);
-                claim(next, (uint32_t)n_need);
-            }
+            if (K > 0) place(false);
+            claim(next, (uint32_t)n_need);
             if (!has) {
                 // this lane's rank among the idle lanes
                 const uint32_t j = next + __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
-                const uint32_t pkt = wave + (j >> 6) * n_waves;
+                const uint32_t pkt = (j >> 6) < q_end ? spkt[(j >> 6) & (kStageSlots - 1)] : ~0u;
                 const uint32_t idx = pkt * 64 + (j & 63);
                 if (pkt < n_packets && idx < n) {
                     if (K == 0 && pend) write_result();
@@ -214,6 +257,7 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
                     R.tmin = a.ray[6][idx];
                     R.tmax = a.ray[7][idx];
                     ray_j = j;
+                    ray_i = idx;
                     if (MODE == rgt::kRender && a.ray_job) {  // only frames carry per-ray top levels
                         const RgTlasRef J = a.jobs[a.ray_job[idx]];
                         tr.tlas_nodes = reinterpret_cast<const RgNode<W> *>(J.nodes);
@@ -229,8 +273,8 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
         }
         if (__ballot(has) == 0) {
             // no lane holds a ray after a refill attempt of all 64 lanes: the
-            // sequence is exhausted once its next packet is past the end
-            if (wave + (next >> 6) * n_waves >= n_packets) break;
+            // wave is done once its claims have run past the last packet
+            if (out_of_work) break;
             continue;
         }
         // Which kinds of unit run this round: inner nodes whenever a lane
@@ -261,6 +305,13 @@ __global__ void __launch_bounds__(rgt::kThreads) k_trace(RgTraceArgs a, int refi
     }
     if (K > 0) place(true);
     else if (pend) write_result();
+    if (claims && lane == 0) {
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's claims have come back
+        if (atomicAdd(a.work + 1, 1u) == n_waves - 1u) {
+            atomicExch(a.work, 0u);
+            atomicExch(a.work + 1, 0u);
+        }
+    }
 }
 
 // The reported hit in double precision.  The traversal decides in float32
@@ -403,13 +454,60 @@ void launch_mode(bool any, int mode, const RgTraceArgs &a, hipStream_t st, unsig
     }
 }
 
+// Packet counters of the persistent traversal: each launch takes the next
+// of kWorkSlots pairs of device words (so launches in flight on different
+// streams count apart; a launch captured into a graph keeps a pair of its
+// own); the launch leaves its pair cleared (zero from the module's load on),
+// so a graph that captured a launch can replay it.  The
+// array lives in the library's code object, one copy per device; its device
+// address comes from hipGetSymbolAddress, taken once per device with that
+// device current.
+constexpr uint32_t kWorkSlots = 4096;     // handed out in turn to launches
+constexpr uint32_t kCaptureSlots = 1024;  // each launch captured into a graph keeps one of its own
+constexpr int kMaxDevices = 64;
+std::mutex g_work_mu;
+uint32_t *g_work_ptr[kMaxDevices] = {};
+std::atomic<uint32_t> g_work_seq{0}, g_capture_seq{0};
+
+}  // namespace
+
+static __device__ __align__(256) uint32_t work_counters[2 * (kWorkSlots + kCaptureSlots)];
+
+namespace {
+
+rg_status work_counter(hipStream_t st, uint32_t **out) {
+    int dev = 0;
+    RG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return RG_ERR_UNSUPPORTED;
+    uint32_t *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_work_mu);
+        if (!g_work_ptr[dev]) {
+            void *p = nullptr;
+            RG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(work_counters)));
+            if (!p) return RG_ERR_HIP;
+            g_work_ptr[dev] = static_cast<uint32_t *>(p);
+        }
+        base = g_work_ptr[dev];
+    }
+    // a launch being captured gets a pair no other launch uses (the graph
+    // replays it again and again); others take the next pair of the ring
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    RG_HIP(hipStreamIsCapturing(st, &cs));
+    const uint32_t slot = cs == hipStreamCaptureStatusActive
+                              ? kWorkSlots + g_capture_seq.fetch_add(1u, std::memory_order_relaxed) % kCaptureSlots
+                              : g_work_seq.fetch_add(1u, std::memory_order_relaxed) % kWorkSlots;
+    *out = base + 2 * slot;
+    return RG_OK;
+}
+
 template <int W>
 rg_status launch_w(bool any, int mode, const RgTraceArgs &a, hipStream_t st, const rg_trace_tune &t) {
     unsigned blocks = persistent_blocks(a.n, t.waves_per_cu);
     // the traversal stacks, then one staging ring per wave
     const int K = mode == rgt::kCounts ? 0 : (mode == rgt::kRender ? (any ? 1 : 3) : (any ? 3 : 2));
     size_t shm = (size_t)t.lds_depth * rgt::kThreads * sizeof(uint32_t) +
-                 (rgt::kThreads / 64) * (K == 0 ? 0 : (size_t)kStageSlots * (K * 64 * 4 + 16));
+                 (rgt::kThreads / 64) * (size_t)kStageSlots * (K * 64 * 4 + 16);
     if (a.opt) launch_mode<W, true>(any, mode, a, st, blocks, shm, t);
     else launch_mode<W, false>(any, mode, a, st, blocks, shm, t);
     RG_LAUNCH_CHECK();
@@ -473,14 +571,17 @@ bool rg_trace_depth_ok(const rg_tlas *t) {
     return need <= rgt::kStackCap;
 }
 
-rg_status rg_trace_launch(int width, bool any, int mode, const RgTraceArgs &a, hipStream_t st, int scope) {
-    if (a.n <= 0) return RG_OK;
+rg_status rg_trace_launch(int width, bool any, int mode, const RgTraceArgs &a_in, hipStream_t st, int scope) {
+    if (a_in.n <= 0) return RG_OK;
     if (scope < 0 || scope >= RG_TUNE_SCOPES) return RG_ERR_INVALID_ARG;
+    if (width != 2 && width != 4 && width != 8) return RG_ERR_INVALID_ARG;
     const rg_trace_tune t = g_tune[scope];
+    RgTraceArgs a = a_in;
+    rg_status r = work_counter(st, &a.work);
+    if (r != RG_OK) return r;
     if (width == 2) return rg_debug_done(launch_w<2>(any, mode, a, st, t), st);
     if (width == 4) return rg_debug_done(launch_w<4>(any, mode, a, st, t), st);
-    if (width == 8) return rg_debug_done(launch_w<8>(any, mode, a, st, t), st);
-    return RG_ERR_INVALID_ARG;
+    return rg_debug_done(launch_w<8>(any, mode, a, st, t), st);
 }
 
 extern "C" {

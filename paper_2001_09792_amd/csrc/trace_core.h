@@ -557,6 +557,7 @@ struct RgTraceArgs {
     uint32_t *inst, *prim;
     uint8_t *occluded;             // any hit
     uint32_t *counts;              // visit counts [n][3]
+    uint32_t *work;                // the launch's packet counters, two words (set by rg_trace_launch)
 };
 
 // Launches the traversal over a.n rays (or *a.count if set) on `stream`.
