@@ -456,7 +456,8 @@ rg_status rg_trace_counts(const rg_tlas *tlas, rg_rays rays, int64_t n, int32_t 
  *   RG_TUNE_TRACE  rg_trace_closest, rg_trace_any, rg_trace_counts
  *   RG_TUNE_FRAME  rg_render, rg_batch_render
  *   RG_TUNE_ENGINE rg_engine_step
- * The kernels are persistent: the grid holds waves_per_cu waves per compute unit, each
+ * The kernels are persistent: the grid holds waves_per_cu waves per compute unit (at most
+ * as many as the kernel variant keeps resident; defaults 20, 16 and 20), each
  * wave walks its own interleaved sequence of 64-ray packets, and its lanes
  * take new rays together once `refill` of them (1..64) are idle.  The first
  * lds_depth (8..32) entries of each lane's traversal stack live in LDS, the

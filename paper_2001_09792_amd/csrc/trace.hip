@@ -387,11 +387,16 @@ __global__ void __launch_bounds__(256) k_refine(RefineArgs a) {
 // Launch parameters per family of calls (RG_TUNE_*): refill threshold,
 // resident waves per CU, LDS stack entries per lane, lanes waiting at leaves
 // / instance entries before a wave runs that code.  Incoherent ray batches
-// gain from waiting lanes; the coherent rays of frames do not.
+// gain from waiting lanes; the coherent rays of frames do not.  Every launch
+// takes at most the waves its variant keeps resident: the closest-hit
+// variant of frames fits 4 per SIMD, the any-hit one 5 at widths 2 and 4.
+// The engine runs a pass's any-hit launch beside the next pass's
+// closest-hit launch, and there the any-hit launch's fifth wave per SIMD
+// pays; single frames and batches gain nothing from it.
 rg_trace_tune g_tune[RG_TUNE_SCOPES] = {
     {16, 20, 16, 12, 6},  // RG_TUNE_TRACE: rg_trace_closest / any / counts (5 waves per SIMD fit)
     {8, 16, 16, 1, 1},   // RG_TUNE_FRAME: rg_render, rg_batch_render
-    {8, 16, 16, 8, 1},   // RG_TUNE_ENGINE: rg_engine_step
+    {8, 20, 16, 8, 1},   // RG_TUNE_ENGINE: rg_engine_step
 };
 
 }  // namespace
