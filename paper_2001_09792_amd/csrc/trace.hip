@@ -392,11 +392,14 @@ __global__ void __launch_bounds__(256) k_refine(RefineArgs a) {
 // variant of frames fits 4 per SIMD, the any-hit one 5 at widths 2 and 4.
 // The engine runs a pass's any-hit launch beside the next pass's
 // closest-hit launch, and there the any-hit launch's fifth wave per SIMD
-// pays; single frames and batches gain nothing from it.
+// pays; single frames and batches gain nothing from it.  The engine's
+// passes mix the rays of many frames and depths: like incoherent batches
+// they gain from lanes waiting at leaves and instance entries, and from
+// refilling later (a measured sweep: refill 20..28 with leaf batch 12 best).
 rg_trace_tune g_tune[RG_TUNE_SCOPES] = {
     {16, 20, 16, 12, 6},  // RG_TUNE_TRACE: rg_trace_closest / any / counts (5 waves per SIMD fit)
-    {8, 16, 16, 1, 1},   // RG_TUNE_FRAME: rg_render, rg_batch_render
-    {8, 20, 16, 8, 1},   // RG_TUNE_ENGINE: rg_engine_step
+    {8, 16, 16, 1, 1},    // RG_TUNE_FRAME: rg_render, rg_batch_render
+    {24, 20, 16, 12, 6},  // RG_TUNE_ENGINE: rg_engine_step
 };
 
 }  // namespace
