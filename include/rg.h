@@ -515,8 +515,10 @@ rg_status rg_ao_rays_scratch(int64_t n, uint64_t *scratch_bytes /*host*/);
 rg_status rg_render_sizes(int32_t width, int32_t height, int32_t max_depth, int32_t mode,
                           uint64_t *scratch_bytes /*host*/);
 
-/* Renders one frame: camera rays, then for depth 0..max_depth a closest-hit
- * pass, shading (sky on a miss; ambient term, a shadow ray towards the point
+/* Renders one frame (section 1: rays spawned again by the shader a hit
+ * invokes, each with its payload, to a bounded depth; section 2.1: shadow
+ * casting, reflection and refraction on top of it): camera rays, then for
+ * depth 0..max_depth a closest-hit pass, shading (sky on a miss; ambient term, a shadow ray towards the point
  * light for diffuse hits; a mirror child; reflection and refraction children
  * for glass with Schlick's Fresnel term, both spawned, none past max_depth),
  * an any-hit pass for the shadow rays and the direct term for unoccluded
@@ -537,7 +539,7 @@ rg_status rg_render(const rg_tlas *tlas, const rg_material *mats /*host*/, int32
 /* rg_render that also writes, per pixel, the material its primary ray shaded
  * (the clamped material index; RG_MISS where the primary ray saw the sky)
  * to primary_mat (device uint32[height][width], nullable): the input of the
- * roughness blur below.  primary_mat needs mode 0 (RG_ERR_UNSUPPORTED
+ * roughness blur below (section 2.1's screen-space roughness approximation).  primary_mat needs mode 0 (RG_ERR_UNSUPPORTED
  * otherwise). */
 rg_status rg_render_ex(const rg_tlas *tlas, const rg_material *mats /*host*/, int32_t n_mats,
                        const rg_camera *cam /*host*/, const rg_light *light /*host*/, int32_t width,
@@ -607,10 +609,10 @@ rg_status rg_fxaa(const float *in, int32_t width, int32_t height, float *out, vo
                   uint64_t scratch_bytes, void *stream);
 
 /* ------------------------------------------------------------ batches */
-/* Many frames of different scenes and sizes rendered together: every pass of
- * the Whitted recursion (closest hit, shading, shadow any hit, shadow
- * resolve) is one launch over the rays of all frames, each ray carrying its
- * frame.  Each image is bitwise the one rg_render gives for the same frame.
+/* Many frames of different scenes and sizes rendered together, each the
+ * render of rg_render (sections 1 and 2.1): every pass of the Whitted
+ * recursion (closest hit, shading, shadow any hit, shadow resolve) is one
+ * launch over the rays of all frames, each ray carrying its frame.  Each image is bitwise the one rg_render gives for the same frame.
  * All frames must use top levels of one width; mode must be 0. */
 typedef struct {
     const rg_tlas *tlas;      /* host pointer to the frame's top level */
