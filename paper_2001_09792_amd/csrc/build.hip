@@ -2093,12 +2093,8 @@ __device__ inline void store_row(float *dst, const float *v) {
 // only its own nodes, not its children's.  The root's union goes to the
 // header.  Boxes are min / max of coordinates, exact in any order.
 template <int W>
-__global__ void k_refit_level(RefitJobs jobs, int level) {
-    const RefitJob &J = jobs.j[blockIdx.y];
-    if (level >= J.depth) return;
-    RgNode<W> *nodes = reinterpret_cast<RgNode<W> *>(J.nodes);
-    const uint32_t lo = J.levels[level], hi = J.levels[level + 1];
-    for (uint32_t x = lo + blockIdx.x * blockDim.x + threadIdx.x; x < hi; x += gridDim.x * blockDim.x) {
+__device__ inline void refit_node(const RefitJob &J, RgNode<W> *nodes, uint32_t x) {
+    {
         RgNode<W> &nd = nodes[x];
         float bx[6][W];
         uint32_t ch[W];
@@ -2158,6 +2154,37 @@ __global__ void k_refit_level(RefitJobs jobs, int level) {
             pd.lo_x[ps] = u[0]; pd.lo_y[ps] = u[1]; pd.lo_z[ps] = u[2];
             pd.hi_x[ps] = u[3]; pd.hi_y[ps] = u[4]; pd.hi_z[ps] = u[5];
         }
+    }
+}
+
+template <int W>
+__global__ void k_refit_level(RefitJobs jobs, int level) {
+    const RefitJob &J = jobs.j[blockIdx.y];
+    if (level >= J.depth) return;
+    RgNode<W> *nodes = reinterpret_cast<RgNode<W> *>(J.nodes);
+    const uint32_t lo = J.levels[level], hi = J.levels[level + 1];
+    for (uint32_t x = lo + blockIdx.x * blockDim.x + threadIdx.x; x < hi; x += gridDim.x * blockDim.x)
+        refit_node<W>(J, nodes, x);
+}
+
+// The levels near the root hold few nodes (at most W^l at level l), too few
+// to fill the GPU, yet a launch per level costs its start and end: levels
+// top - 1 .. 0 of every bottom level are refitted in one launch, one
+// workgroup per bottom level stepping up to the root with a workgroup
+// barrier between levels.  A level's writes into its parents' rows are read
+// by the next level's threads of the same workgroup after the barrier.
+constexpr int kRefitTopThreads = 1024;
+constexpr uint32_t kRefitTopNodes = 4096;  // the widest level the one-workgroup launch takes (W^l)
+template <int W>
+__global__ void __launch_bounds__(kRefitTopThreads) k_refit_top(RefitJobs jobs, int top) {
+    const RefitJob &J = jobs.j[blockIdx.x];
+    RgNode<W> *nodes = reinterpret_cast<RgNode<W> *>(J.nodes);
+    for (int level = top - 1; level >= 0; --level) {
+        if (level < J.depth) {  // the same for the whole workgroup
+            const uint32_t lo = J.levels[level], hi = J.levels[level + 1];
+            for (uint32_t x = lo + threadIdx.x; x < hi; x += blockDim.x) refit_node<W>(J, nodes, x);
+        }
+        __syncthreads();
     }
 }
 
@@ -2237,8 +2264,12 @@ __global__ void k_refit_up(RgNode<W> *nodes, int64_t n_nodes, const uint32_t *__
 
 template <int W>
 void refit_levels(const RefitJobs &jobs, int n, int max_depth, unsigned blocks, hipStream_t st) {
-    for (int l = max_depth - 1; l >= 0; --l)
+    // levels 0 .. top - 1 hold at most W^(top - 1) <= kRefitTopNodes nodes
+    int top = 1;
+    for (uint64_t c = W; c <= kRefitTopNodes && top < max_depth; c *= W) ++top;
+    for (int l = max_depth - 1; l >= top; --l)
         k_refit_level<W><<<dim3(blocks, (unsigned)n), kThreads, 0, st>>>(jobs, l);
+    k_refit_top<W><<<(unsigned)n, kRefitTopThreads, 0, st>>>(jobs, top);
 }
 
 template <int W>
