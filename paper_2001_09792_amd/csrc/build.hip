@@ -3350,11 +3350,61 @@ constexpr uint64_t kTlasTicketMagic = 0x7267544c41534174ull;
 // asynchronous build), reused only after completion; async: the collapse
 // goes no further than its first batch and nothing waits (the clustering and
 // treelet builders, which step their rounds from the host, are refused).
+// The synchronous top-level build's upload of its host tables: into a device
+// buffer of the library's own (one per thread and device: the call waits for
+// its summary before it returns, so the buffer is free again by then), on a
+// stream of its own (default priority, not ordered with the null stream).
+// The caller's stream waits for the copy's event just before the build reads
+// the tables, so the copy overlaps whatever that stream still runs, such as
+// the refit of the bottom levels the instances refer to, instead of queueing
+// behind it (used only when that stream has work queued).  nullptr: no such
+// buffer (the copy then goes on the caller's stream, into its scratch).
+struct TableUpload {
+    hipStream_t st = nullptr;
+    hipEvent_t done = nullptr;
+    char *buf = nullptr;
+    size_t cap = 0;
+};
+constexpr int kUploadDevices = 16;
+TableUpload *table_upload(size_t bytes) {
+    thread_local TableUpload per_dev[kUploadDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kUploadDevices) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    TableUpload &U = per_dev[dev];
+    if (!U.st && hipStreamCreateWithFlags(&U.st, hipStreamNonBlocking) != hipSuccess) {
+        U.st = nullptr;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (!U.done && hipEventCreateWithFlags(&U.done, hipEventDisableTiming) != hipSuccess) {
+        U.done = nullptr;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (bytes > U.cap) {
+        if (U.buf) (void)hipFree(U.buf);
+        U.buf = nullptr;
+        U.cap = 0;
+        const size_t want = ((bytes > (64u << 10) ? bytes : (64u << 10)) + 4095u) & ~(size_t)4095u;
+        void *p = nullptr;
+        if (hipMalloc(&p, want) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        U.buf = (char *)p;
+        U.cap = want;
+    }
+    return &U;
+}
+
 rg_status tlas_enqueue(const rg_blas *blas, int32_t n_blas, const float *xform, const uint32_t *blas_id,
                        const uint32_t *inst_material, const uint32_t *inst_flags, int64_t n_inst,
                        const rg_build_opts *opts, void *out_buf, uint64_t out_bytes, void *scratch,
                        uint64_t scratch_bytes, hipStream_t st, char *stage, uint64_t stage_bytes, bool async,
-                       TlasTicket *Tk) {
+                       TlasTicket *Tk, bool side_upload) {
     Opts o;
     if (!blas || !xform || !blas_id || !inst_material || !out_buf || !scratch) return RG_ERR_INVALID_ARG;
     if (n_blas < 1 || n_blas > 4096 || n_inst < 1 || n_inst > RG_MAX_TRIS) return RG_ERR_INVALID_ARG;
@@ -3399,6 +3449,15 @@ rg_status tlas_enqueue(const rg_blas *blas, int32_t n_blas, const float *xform, 
     const size_t off_bid = L.off_bid, off_mat = L.off_mat, off_fl = L.off_fl, off_info = L.off_info;
     const size_t off_flag = L.off_flag, t_bytes = L.t_bytes;
     char *d_tab = arena.take<char>(t_bytes);
+    // only worth it while the caller's stream still has work queued: on an
+    // idle stream the cross-stream wait costs more than the copy it hides
+    bool busy = false;
+    if (side_upload && !async) {
+        busy = hipStreamQuery(st) == hipErrorNotReady;
+        (void)hipGetLastError();  // "not ready" is an answer, not an error
+    }
+    TableUpload *up = busy ? table_upload(t_bytes) : nullptr;
+    if (up) d_tab = up->buf;
     float *d_box = arena.take<float>(6 * n_inst);
     RgInst *d_rec = arena.take<RgInst>(n_inst);
     char *tab = stage;
@@ -3411,7 +3470,15 @@ rg_status tlas_enqueue(const rg_blas *blas, int32_t n_blas, const float *xform, 
     uint32_t *summary = (uint32_t *)(tab + t_bytes);  // a one-workgroup build's summary, or the flag word
     uint32_t *d_flag = (uint32_t *)(d_tab + off_flag);
     if (async) RG_HIP(hipEventCreateWithFlags(&Tk->done, hipEventDisableTiming));  // before anything is enqueued
-    RG_HIP(hipMemcpyAsync(d_tab, tab, t_bytes, hipMemcpyHostToDevice, st));
+    if (up) {
+        hipError_t e = hipMemcpyAsync(d_tab, tab, t_bytes, hipMemcpyHostToDevice, up->st);
+        if (e == hipSuccess) e = hipEventRecord(up->done, up->st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, up->done, 0);
+        if (e != hipSuccess) (void)hipStreamSynchronize(up->st);  // the staging buffer may still be read
+        RG_HIP(e);
+    } else {
+        RG_HIP(hipMemcpyAsync(d_tab, tab, t_bytes, hipMemcpyHostToDevice, st));
+    }
     InstTables T;
     T.xform = (const float *)d_tab;
     T.blas_id = (const uint32_t *)(d_tab + off_bid);
@@ -3530,7 +3597,8 @@ rg_status rg_build_tlas_ex(const rg_blas *blas, int32_t n_blas, const float *xfo
     }
     TlasTicket T;
     rg_status r = tlas_enqueue(blas, n_blas, xform, blas_id, inst_material, inst_flags, n_inst, opts, out_buf,
-                               out_bytes, scratch, scratch_bytes, (hipStream_t)stream, tab, L.stage, false, &T);
+                               out_bytes, scratch, scratch_bytes, (hipStream_t)stream, tab, L.stage, false, &T,
+                               fallback.empty());
     if (r != RG_OK) return r;
     return tlas_complete(&T, out);
 }
@@ -3549,7 +3617,7 @@ rg_status rg_build_tlas_async(const rg_blas *blas, int32_t n_blas, const float *
     TlasTicket *T = new (ticket) TlasTicket();
     rg_status r = tlas_enqueue(blas, n_blas, xform, blas_id, inst_material, inst_flags, n_inst, opts, out_buf,
                                out_bytes, scratch, scratch_bytes, (hipStream_t)stream,
-                               (char *)ticket + kTlasTicketHead, ticket_bytes - kTlasTicketHead, true, T);
+                               (char *)ticket + kTlasTicketHead, ticket_bytes - kTlasTicketHead, true, T, false);
     if (r != RG_OK) {
         if (T->done) (void)hipEventDestroy(T->done);
         T->magic = 0;
