@@ -2065,8 +2065,12 @@ __global__ void k_refit_tris(RefitJobs jobs) {
             atomicOr(&J.hdr->status, bad);
             continue;
         }
+        // the 40-byte record (nine coordinates, then prim unchanged) as five
+        // 8-byte stores: records are 8-byte aligned
+        uint2 *dst = reinterpret_cast<uint2 *>(&J.tris[s]);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) J.tris[s].v[k] = v[k];
+        for (int k = 0; k < 4; ++k) dst[k] = make_uint2(__float_as_uint(v[2 * k]), __float_as_uint(v[2 * k + 1]));
+        dst[4] = make_uint2(__float_as_uint(v[8]), prim);
     }
 }
 
