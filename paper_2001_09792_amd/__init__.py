@@ -482,16 +482,18 @@ class TlasBuilder:
     the per-frame top-level update of a dynamic scene without a new buffer or
     new descriptor tables per call.  Every Tlas it returns shares that buffer,
     so the next build replaces the previous one (the caller orders it after
-    the traces that still read it, e.g. on the same stream)."""
+    the traces that still read it, e.g. on the same stream).  morton_bits:
+    as for build_tlas (10: 30-bit keys, four sort passes, up to 2^20
+    instances)."""
 
     def __init__(self, blas: Sequence[Blas], blas_id, inst_mat, width: int = 4, builder: str = "lbvh",
-                 radius: int = 0, inst_flags=None, stream=None):
+                 radius: int = 0, inst_flags=None, stream=None, morton_bits: int = 0):
         self.blas = list(blas)
         self.blas_id = np.ascontiguousarray(blas_id, np.uint32)
         self.inst_mat = np.ascontiguousarray(inst_mat, np.uint32)
         self.n = int(self.blas_id.shape[0])
         self.flags = np.ascontiguousarray(inst_flags, np.uint32).reshape(self.n) if inst_flags is not None else None
-        self.opts = _opts(width, 1, builder, radius)
+        self.opts = _opts(width, 1, builder, radius, morton_bits)
         s = Sizes()
         _check("rg_tlas_sizes", _lib.rg_tlas_sizes(self.n, ctypes.byref(self.opts), ctypes.byref(s)))
         dev = self.blas[0].buf.device
