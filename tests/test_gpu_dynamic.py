@@ -274,3 +274,42 @@ def test_async_tlas_equals_sync(n_inst):
     rg.refit_blas(tl.blas[0], v, i)
     rg.build_tlas_async(tl.blas, xf, blas_id, mat, 4).finish()
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n_inst", [300, 3000])
+def test_tlas_built_behind_queued_work_equals_idle_build(n_inst):
+    """The synchronous top-level build uploads its host tables on a stream of
+    its own while the caller's stream still has work queued (here a trace of
+    4M rays), then makes that stream wait for the copy: the result is the
+    top level built on an idle stream (records, record map, matrices, hits)."""
+    import torch
+    import paper_2001_09792_amd as rg
+    sc = sg.config_two_level(width=64, height=48)
+    tl = rg.upload_scene(sc, 4, 1, builder="lbvh")
+    rng = np.random.default_rng(n_inst + 9)
+    blas_id = rng.integers(0, len(tl.blas), n_inst).astype(np.uint32)
+    mat = rng.integers(0, len(sc.materials), n_inst).astype(np.uint32)
+    xf = sg.animate_instances(np.tile(sc.xform, (n_inst // len(sc.xform) + 1, 1, 1))[:n_inst], 0.3, seed=13)
+    print(f"[tlas behind work] {n_inst}", flush=True)
+    torch.cuda.synchronize()
+    ref = rg.build_tlas(tl.blas, xf, blas_id, mat, 4)
+    ref_buf = ref.buf.clone()
+    torch.cuda.synchronize()
+    rays = rg.rays_to_device(sg.random_rays(4_000_000, 43, extent=22.0))
+    torch.cuda.synchronize()
+    rg.trace_closest(tl, rays)  # queued: the stream is busy when the build is called
+    got = rg.build_tlas(tl.blas, xf, blas_id, mat, 4)
+    torch.cuda.synchronize()
+    for f in ("n_inst", "n_nodes", "width", "depth", "max_blas_depth", "has_inst_flags"):
+        assert getattr(got.desc, f) == getattr(ref.desc, f), f
+    assert list(got.desc.lo) == list(ref.desc.lo) and list(got.desc.hi) == list(ref.desc.hi)
+    a, b, d = got.buf.cpu().numpy(), ref_buf.cpu().numpy(), ref.desc
+    for off, size in ((d.inst_off, 112 * n_inst), (d.rec_off, 4 * n_inst), (d.xf_off, 48 * n_inst)):
+        assert np.array_equal(a[off: off + size], b[off: off + size])
+    bvh_check.check_tlas(a, got.desc, [x.desc for x in tl.blas], xf)
+    sample = rg.rays_to_device(sg.random_rays(4000, 47, extent=22.0))
+    h1 = parity.hits_to_numpy(rg.trace_closest(got, sample))
+    ref2 = rg.build_tlas(tl.blas, xf, blas_id, mat, 4)
+    h2 = parity.hits_to_numpy(rg.trace_closest(ref2, sample))
+    for key in h1:
+        assert np.array_equal(h1[key].view(np.uint32), h2[key].view(np.uint32)), key
