@@ -349,7 +349,12 @@ rg_status rg_tlas_sizes(int64_t n_inst, const rg_build_opts *opts, rg_sizes *out
  * The bottom levels' root boxes are read from their headers on the device.
  * out_buf belongs to the caller and must outlive every trace and render over
  * it; the bottom levels must outlive it.  Synchronous: one upload of the host
- * tables and one wait (up to 4,096 instances build in one workgroup).
+ * tables and one wait (up to 4,096 instances build in one workgroup).  When
+ * `stream` still has work queued, the upload goes on a stream of the
+ * library's own (created with the first such call, per thread and device,
+ * with an event and a device buffer of the tables' size that the library
+ * keeps until the process ends) and `stream` waits for it just before the
+ * build, so the copy overlaps the queued work.
  * Errors: RG_ERR_INVALID_ARG for NULL pointers, blas_id out of range, a
  * non-finite or singular matrix, mixed widths, or a bottom level whose last
  * refit found invalid input (its header's status word is set). */
