@@ -369,6 +369,16 @@ __global__ void k_zero_u64(unsigned long long *p, int64_t n) {
 
 __global__ void k_stat_add(unsigned long long *stat, const uint32_t *count) { *stat += *count; }
 
+// Between a pass's closest-hit launch and its shading: the rays it traced
+// go into the statistics, and the next pass's queue count and the shadow
+// queue count start at zero (one launch instead of three).
+__global__ void k_pass_counts(unsigned long long *stat, const uint32_t *count_in, uint32_t *count_out,
+                              uint32_t *count_shadow) {
+    *stat += *count_in;
+    *count_out = 0u;
+    *count_shadow = 0u;
+}
+
 // Frame record and materials written through kernel arguments: nothing
 // for the host to keep alive, nothing to wait for, capturable.
 __global__ void k_put_job(RgJobDev *jobs, RgTlasRef *tlas, uint32_t slot, RgJobDev J, RgTlasRef T) {
@@ -790,9 +800,7 @@ rg_status rg_wave_pass(const RgWaveBufs &b, int32_t width, int64_t pass, int64_t
     // the shadow queue and its count are reused below: the previous pass's
     // shadow work must be done with them
     if (side && side->pending) RG_HIP(hipStreamWaitEvent(st, side->shadowed, 0));
-    k_stat_add<<<1, 1, 0, st>>>(b.stat, cin);
-    k_fill_u32<<<1, 64, 0, st>>>(cout, 0u, 1);
-    k_fill_u32<<<1, 64, 0, st>>>(csq, 0u, 1);
+    k_pass_counts<<<1, 1, 0, st>>>(b.stat, cin, cout, csq);
     ShadeArgs sa;
     sa.in = qin;
     sa.count_in = cin;
